@@ -1,0 +1,86 @@
+"""Pins of the oracle's reverse-mode V-cycle: the dot-product test against
+the forward cycle, symmetry of the cycle's right-hand-side map, complex-step
+derivatives of the k-cycle loss through the Kronecker-matrix cycle, and
+central finite differences through the loop cycle."""
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import dense
+
+C9 = np.array([0.28891272760249742, 0.065661983546022137, 0.019698595063806643])
+C7 = np.array([16 / 73, 2 / 73])
+
+
+@pytest.mark.parametrize("d,N,c", [(2, 16, C9), (2, 32, C9), (3, 8, C7), (3, 16, C7)])
+def test_dot_product(d, N, c):
+    # the cycle is affine in (u, b): V(u + du, b + db) - V(u, b) = E du + B db,
+    # so <ubar_out, E du + B db> = <ubar_in, du> + <bbar, db>
+    rng = np.random.default_rng(1)
+    s = (N - 1,) * d
+    u, b = rng.uniform(-1, 1, s), rng.standard_normal(s)
+    du, db, ub = rng.standard_normal(s), rng.standard_normal(s), rng.standard_normal(s)
+    dout = O.vcycle(d, N, c, u + du, b + db) - O.vcycle(d, N, c, u, b)
+    ubar, bbar, _ = O.vcycle_adjoint(d, N, c, u, b, ub)
+    lhs = np.vdot(ub, dout)
+    rhs = np.vdot(ubar, du) + np.vdot(bbar, db)
+    assert abs(lhs - rhs) <= 1e-11 * (abs(lhs) + np.linalg.norm(ub) * np.linalg.norm(dout))
+
+
+@pytest.mark.parametrize("d,N,c", [(2, 32, C9), (3, 8, C7)])
+def test_rhs_adjoint_is_forward_cycle(d, N, c):
+    # with u = 0 the cycle is b -> B b with B symmetric, so the b-adjoint of
+    # one cycle is one forward cycle from zero
+    rng = np.random.default_rng(2)
+    s = (N - 1,) * d
+    g = rng.standard_normal(s)
+    _, bbar, _ = O.vcycle_adjoint(d, N, c, np.zeros(s), rng.standard_normal(s), g)
+    assert np.allclose(bbar, O.vcycle(d, N, c, np.zeros(s), g), rtol=0,
+                       atol=1e-12 * np.max(np.abs(bbar)))
+
+
+@pytest.mark.parametrize("d,N,c,K", [(2, 16, C9, 3), (2, 8, np.array([0.3, 0.05, 0.02]), 2),
+                                     (3, 8, C7, 2)])
+def test_coefficient_gradient_vs_complex_step(d, N, c, K):
+    rng = np.random.default_rng(3)
+    e0 = rng.uniform(-1, 1, (2,) + (N - 1,) * d)
+    L, cbar, _, _ = O.grad_kcycles(d, N, c, e0, np.zeros((N - 1,) * d), K)
+    Ld = dense.loss_kcycles(d, N, c, e0, K)
+    assert abs(L - Ld) <= 1e-12 * abs(L)
+    g = dense.complex_step_grad(d, N, c, e0, K)
+    assert np.max(np.abs(cbar - g)) <= 1e-9 * np.max(np.abs(g))
+
+
+@pytest.mark.parametrize("d,N,c,K", [(2, 32, C9, 3), (3, 16, C7, 2)])
+def test_coefficient_gradient_vs_central_differences(d, N, c, K):
+    rng = np.random.default_rng(4)
+    s = (N - 1,) * d
+    e0 = rng.uniform(-1, 1, (2,) + s)
+    b = np.zeros(s)
+    _, cbar, _, _ = O.grad_kcycles(d, N, c, e0, b, K)
+    step = 1e-6
+    for j in range(len(c)):
+        cp, cm = c.copy(), c.copy()
+        cp[j] += step
+        cm[j] -= step
+        fd = (O.loss_kcycles(d, N, cp, e0, b, K) - O.loss_kcycles(d, N, cm, e0, b, K)) / (2 * step)
+        assert abs(fd - cbar[j]) <= 1e-6 * np.max(np.abs(cbar))
+
+
+def test_rhs_gradient_vs_central_differences():
+    d, N, c, K = 2, 16, C9, 3
+    rng = np.random.default_rng(5)
+    s = (N - 1,) * d
+    e0 = rng.uniform(-1, 1, (2,) + s)
+    b = np.zeros(s)
+    _, _, bbar, e0bar = O.grad_kcycles(d, N, c, e0, b, K)
+    for _ in range(3):
+        v = rng.standard_normal(s)
+        t = 1e-4     # the loss is quadratic in b: central differences are exact
+        fd = (O.loss_kcycles(d, N, c, e0, b + t * v, K)
+              - O.loss_kcycles(d, N, c, e0, b - t * v, K)) / (2 * t)
+        assert abs(fd - np.vdot(bbar, v)) <= 1e-7 * abs(fd) + 1e-12
+        # the same perturbation of every initial error of the batch
+        fd = (O.loss_kcycles(d, N, c, e0 + t * v, b, K)
+              - O.loss_kcycles(d, N, c, e0 - t * v, b, K)) / (2 * t)
+        assert abs(fd - np.vdot(e0bar.sum(0), v)) <= 1e-7 * abs(fd) + 1e-12
