@@ -1,0 +1,187 @@
+/*
+ * spaimg.h -- C ABI of libspaimg.so: geometric multigrid for the Dirichlet
+ * Laplacian with the optimised sparse-approximate-inverse (SPAI) smoothers of
+ * He, Liu and Wang, "Optimized sparse approximate inverse smoothers for
+ * solving Laplacian linear systems" (arXiv 2206.05543), on AMD gfx950 GPUs.
+ *
+ * Problem (Section 1, eqs. (Poisson), (Ax=b), (A_h)): A_h u = b on the unit
+ * square (d = 2, 5-point stencil) or cube (d = 3, 7-point stencil), h = 1/N,
+ * unknowns at the (N-1)^d interior nodes.  Dirichlet data g is folded into b
+ * by the caller (b_i += g/h^2 at nodes next to the boundary).
+ *
+ * Smoother (Section 2, eq. (smoother)): u <- u + M (b - A_h u) with
+ * M = h^2 (c0 K0 + c1 K1 + c2 K2), K0 = identity, K1 = sum over the 2d face
+ * neighbours, K2 = sum over the 4 diagonal neighbours (2D only), applied to a
+ * residual that is zero outside the grid.  The coefficients are h-free and
+ * include the damping factor omega; the same coefficients are used on every
+ * level (rediscretisation, Section 4).  The paper's smoothers:
+ *   2D M9 (Theorem 3.1): omega = (309 - 12 sqrt(10))/1720, (c0, c1, c2) =
+ *      omega (44, 10, 3)/24 = (0.28891272760249742, 0.065661983546022137,
+ *      0.019698595063806643)
+ *   3D M7 (Theorem 3.2): omega = 20/73, (c0, c1) = (16/73, 2/73)
+ *   damped Jacobi: 2D (0.2, 0, 0), 3D (1/7, 0); best 5-point M5: (12/41,
+ *   2/41, 0); additive Vanka: (0.28, 0.04, 0.01) (Section 3.1).
+ *
+ * Cycle (Section 4): V(1,1) -- one pre- and one post-smoothing step, full
+ * weighting restriction of the residual, rediscretised coarse operators with
+ * H = 2h, linear (bi-/tri-linear) interpolation, and an exact solve on the
+ * grid with h0 = 1/4 (3^d unknowns).  Coarse levels start from zero.
+ *
+ * Memory layout and ownership: every field argument is a DEVICE pointer owned
+ * by the caller, C-contiguous, shape [batch, (N-1)^d] with x fastest (FP64
+ * unless stated otherwise).  The library never frees nor retains them past a
+ * call.  It owns every internal buffer (allocated in mg_setup and when an
+ * option changes the batch or precision; freed in mg_destroy).
+ *
+ * Streams: every call enqueues its work on `stream` (a hipStream_t; NULL is
+ * the null stream) and returns without waiting, except mg_solve,
+ * mg_residual_norm and the timing queries, which synchronise that stream.  A
+ * handle must not be used from two host threads at once, nor by calls whose
+ * work overlaps on two streams.
+ *
+ * Errors: functions return MG_OK (0) or a negative code; mg_last_error()
+ * returns a thread-local message describing the last failure.  Arguments are
+ * checked on the host before any work is enqueued.
+ */
+#ifndef SPAIMG_H
+#define SPAIMG_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MG_OK 0
+#define MG_EINVAL (-1)      /* bad argument or option                        */
+#define MG_EHIP (-2)        /* HIP runtime failure (message in mg_last_error) */
+#define MG_ENOCONV (-3)     /* max cycles reached before the tolerance       */
+#define MG_ENONFINITE (-4)  /* a residual norm is NaN or infinite            */
+
+/* mg_set_option keys */
+#define MG_OPT_PRECISION 1  /* MG_PREC_*; used by mg_solve                     */
+#define MG_OPT_BATCH 2      /* number of stacked problems, >= 1 (default 1)    */
+#define MG_OPT_MAX_CYCLES 3 /* cycle limit of mg_solve, 1..10000 (default 100) */
+#define MG_OPT_TAIL_N 4     /* largest coarse grid (intervals, power of two,
+                               4..64 in 2D, 4..16 in 3D) solved by the
+                               single-workgroup LDS tail kernel; 0 = default   */
+#define MG_OPT_TIMING 5     /* 0 off; 1 time the fine-level smoother with HIP
+                               events; 2 time every kernel of every level      */
+
+/* precisions for MG_OPT_PRECISION */
+#define MG_PREC_FP64 0      /* FP64 V-cycles                                  */
+#define MG_PREC_FP32_IR 1   /* FP64 iterative refinement around FP32 V-cycles */
+#define MG_PREC_FP16_IR 2   /* ... around V-cycles with FP16 storage, FP32
+                               arithmetic and per-level power-of-two scaling  */
+
+/* operation codes of mg_sweep */
+#define MG_OP_SMOOTH 0       /* out = u + M (b - A u)                          */
+#define MG_OP_SMOOTH_ZERO 1  /* out = M b (smoothing from a zero guess)        */
+#define MG_OP_RESTRICT 2     /* out (level+1) = R (b - A u)                    */
+#define MG_OP_PROLONG_ADD 3  /* out += P u, u on level+1 (in place on out)     */
+
+/* timing kinds for mg_get_timing */
+#define MG_TIME_SMOOTH 0
+#define MG_TIME_SMOOTH_ZERO 1
+#define MG_TIME_RESTRICT 2
+#define MG_TIME_PROLONG 3
+#define MG_TIME_TAIL 4
+#define MG_TIME_IR_STEP 5
+#define MG_TIME_RESIDUAL 6
+
+typedef struct mg_ctx* mg_handle_t;
+
+typedef struct mg_stats {
+    int cycles;        /* cycles k at which ||r_k|| <= tol ||r_0|| (or the
+                          limit); u holds u_k                                 */
+    int cycles_run;    /* cycles executed (one more: the convergence test of
+                          u_k overlaps the next cycle)                        */
+    double r0_norm;    /* ||b - A u_0||_2 (whole batch)                       */
+    double rk_norm;    /* ||b - A u_k||_2                                      */
+    double b_norm;     /* ||b||_2 (filled only when res_hist is given)        */
+    double* res_hist;  /* optional host array: ||r_j||_2, j = 0..cycles       */
+    int hist_cap;      /* its capacity (entries)                               */
+    double elapsed_ms; /* device time of the whole solve (HIP events)         */
+} mg_stats;
+
+/* Creates a solver for N intervals per direction (power of two, 4 <= N <=
+ * 65536 in 2D, <= 2048 in 3D) in d = 2 or 3 dimensions with n_coeffs = 3
+ * (2D) or 2 (3D) host FP64 coefficients (see above).  Allocates the level
+ * hierarchy (about (1/3 + 1/(2^d - 1)) of one fine field per batch entry plus
+ * two fine FP64 fields).  *out receives the handle. */
+int mg_setup(int N, int d, const double* spai_coeffs, int n_coeffs, mg_handle_t* out);
+
+/* Sets an option (keys above).  Changing the batch or precision reallocates
+ * internal buffers. */
+int mg_set_option(mg_handle_t h, int key, double value);
+
+/* Replaces the smoother coefficients (host FP64, n_coeffs as in mg_setup). */
+int mg_set_coeffs(mg_handle_t h, const double* spai_coeffs, int n_coeffs);
+
+/* One FP64 V(1,1) cycle for every batch entry: u <- V(u, b), in place.
+ * (Section 4.) */
+int mg_vcycle(mg_handle_t h, const double* b, double* u, void* stream);
+
+/* Cycles from the initial guess in u until ||b - A u_k||_2 <= tol ||b - A
+ * u_0||_2 over the whole batch (the stopping rule on the relative residual,
+ * Section 4), with the precision set by MG_OPT_PRECISION.  FP64: V(1,1)
+ * cycles.  FP32_IR / FP16_IR: each step computes r = b - A u in FP64, scales
+ * it by a power of two, runs one V(1,1) cycle from zero in low precision on
+ * A e = s r, and updates u += e / s in FP64.  Synchronises `stream`.
+ * Returns MG_ENOCONV (u = last iterate, st filled) if MG_OPT_MAX_CYCLES is
+ * reached, MG_ENONFINITE if a norm is not finite.  st may be NULL. */
+int mg_solve(mg_handle_t h, const double* b, double* u, double tol, mg_stats* st,
+             void* stream);
+
+/* Reverse-mode derivative of one FP64 V(1,1) cycle u_out = V(u_in, b; c):
+ * given ubar_out = dL/du_out, writes ubar_in = dL/du_in (may alias
+ * ubar_out), accumulates bbar_acc += dL/db (device, batch-shaped) and
+ * cbar_acc[j] += dL/dc_j summed over the batch (HOST FP64 array of n_coeffs).
+ * The forward states of every level are recomputed from u_in.  Uses A^T = A,
+ * M^T = M (symmetric stencils with zero extension), P^T = 2^d R.
+ * Synchronises `stream` (to return cbar_acc on the host). */
+int mg_vcycle_adjoint(mg_handle_t h, const double* b, const double* u_in,
+                      const double* ubar_out, double* ubar_in, double* bbar_acc,
+                      double* cbar_acc, void* stream);
+
+/* One building-block kernel on one level (level 0 = the finest grid, level l
+ * has N/2^l intervals), for the whole batch.  prec = MG_PREC_FP64 uses FP64
+ * fields in true units.  prec = MG_PREC_FP32_IR (FP32 fields) or
+ * MG_PREC_FP16_IR (FP16 fields) uses the scaled storage of the low-precision
+ * hierarchies: a correction e on level l is stored as e / h_l^2, the
+ * right-hand side unscaled (so A and M need no h factors, and P carries a
+ * factor 4 between levels).  op = MG_OP_SMOOTH: out = u + M(b - A u);
+ * MG_OP_SMOOTH_ZERO: out = M b (u ignored); MG_OP_RESTRICT: out (shape of
+ * level+1) = R (b - A u); MG_OP_PROLONG_ADD: out (level) += P u where u has
+ * the shape of level+1 (b ignored).  out must not alias u or b, except for
+ * MG_OP_PROLONG_ADD where out is updated in place. */
+int mg_sweep(mg_handle_t h, int op, int level, int prec, const void* u, const void* b,
+             void* out, void* stream);
+
+/* Zero-guess V(1,1) cycle below and including `level` (level >= 1, or the
+ * coarsest): e = B_level b, in precision prec (scaled storage as in
+ * mg_sweep for the low precisions). */
+int mg_coarse_cycle(mg_handle_t h, int level, int prec, const void* b, void* e,
+                    void* stream);
+
+/* ||b - A u||_2 over the whole batch on the finest grid (FP64); writes the
+ * host double *norm.  Synchronises `stream`. */
+int mg_residual_norm(mg_handle_t h, const double* b, const double* u, double* norm,
+                     void* stream);
+
+/* Accumulated device time (ms) and launch count of a timed kernel kind
+ * (MG_TIME_*) on `level` since the last reset (MG_OPT_TIMING must be on). */
+int mg_get_timing(mg_handle_t h, int kind, int level, double* total_ms, int* count);
+int mg_reset_timing(mg_handle_t h);
+
+/* Number of grid levels (finest N down to N = 4). */
+int mg_num_levels(mg_handle_t h);
+
+/* Releases every internal buffer of the handle; NULL is ignored. */
+void mg_destroy(mg_handle_t h);
+
+/* Thread-local message of the last failing call ("" if none). */
+const char* mg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPAIMG_H */

@@ -1,0 +1,822 @@
+// Host side of libspaimg.so: level hierarchy, cycle orchestration, the solve
+// loop with its convergence monitor, mixed-precision refinement and the
+// adjoint cycle.  Every arithmetic step on a grid runs in the gfx950 kernels
+// of mg_kernels.hip / mg_adjoint.hip; the host only allocates, enqueues and
+// reads back one norm per cycle.
+//
+// Cycle structure (He, Liu and Wang, arXiv 2206.05543, Section 4): V(1,1)
+// with full weighting, linear interpolation, rediscretised coarse operators
+// and an exact solve at h0 = 1/4; the stopping rule is the reduction of the
+// 2-norm of the residual relative to the initial one.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/spaimg.h"
+#include "mg_internal.h"
+
+using namespace spaimg;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIPCHK(expr)                                                               \
+    do {                                                                           \
+        hipError_t e_ = (expr);                                                    \
+        if (e_ != hipSuccess)                                                      \
+            return fail(MG_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr int kMaxLevels = 20;
+constexpr int kTimeKinds = 7;
+constexpr long kPartialCap = 1 << 17;  // per batch entry
+
+struct Hier {
+    Prec p = P64;
+    bool scaled = false;
+    std::vector<void*> e, b, t;        // per level; FP64 level 0: only t
+    double* ginv = nullptr;            // sigma_coarsest * A_coarsest^{-1}
+    bool allocated = false;
+};
+
+struct TimedLaunch {
+    int kind, level;
+    hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct mg_ctx {
+    int N = 0, d = 2, L = 0, batch = 1, prec = MG_PREC_FP64, max_cycles = 100;
+    int tail_N = 0;  // 0 = default
+    int ncoef = 3;
+    double c[3] = {0, 0, 0};
+    Hier h64, hlo;
+    double* ualt = nullptr;      // FP64 fine ping-pong buffer
+    double* psum = nullptr;      // per-block partial sums
+    double* pmax = nullptr;      // per-block partial maxima
+    double* dnorm = nullptr;     // device norms: 2 per slot (norm, max)
+    double* dscale = nullptr;    // refinement scales per step
+    double* hnorm = nullptr;     // pinned host mirror of dnorm
+    int norm_slots = 0;
+    // adjoint scratch (FP64), allocated on first use
+    std::vector<double*> adj;    // per level: r1, r3, u1/u2, ubar work
+    bool adj_alloc = false;
+    double* adj_cpart = nullptr;
+    double* adj_cacc = nullptr;
+    // timing
+    int timing = 0;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    std::vector<TimedLaunch> pending;
+    double t_ms[kTimeKinds][kMaxLevels] = {};
+    int t_cnt[kTimeKinds][kMaxLevels] = {};
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+namespace {
+
+long level_pts(const mg_ctx* h, int l) {
+    long n = (h->N >> l) - 1, p = 1;
+    for (int a = 0; a < h->d; ++a) p *= n;
+    return p;
+}
+int level_n(const mg_ctx* h, int l) { return (h->N >> l) - 1; }
+int level_N(const mg_ctx* h, int l) { return h->N >> l; }
+
+int default_tail_N(int d) { return d == 2 ? 64 : 16; }
+
+// first level handled by the tail kernel (never level 0 for FP64 cycles with
+// an initial guess; the low-precision inner cycle starts from zero)
+int tail_level(const mg_ctx* h, bool allow_level0) {
+    const int tN = h->tail_N ? h->tail_N : default_tail_N(h->d);
+    for (int l = allow_level0 ? 0 : 1; l < h->L; ++l)
+        if (level_N(h, l) <= tN) return l;
+    return h->L - 1;
+}
+
+void level_scales(const mg_ctx* h, const Hier& H, int l, double* sA, double* sW,
+                  double* pf) {
+    const double N = level_N(h, l);
+    if (H.scaled) {
+        *sA = 1.0;
+        *sW = 1.0;
+        *pf = 4.0;
+    } else {
+        *sA = N * N;
+        *sW = 1.0 / (N * N);
+        *pf = 1.0;
+    }
+}
+
+// Inverse of the h-free Laplacian stencil matrix on the 3^d coarsest grid,
+// by Gauss-Jordan elimination with partial pivoting in FP64.
+std::vector<double> coarsest_stencil_inverse(int d) {
+    const int n = 3, m = d == 2 ? 9 : 27;
+    std::vector<double> A(m * m, 0.0), I(m * m, 0.0);
+    auto id = [&](int i, int j, int k) { return d == 2 ? i + n * j : i + n * (j + n * k); };
+    for (int k = 0; k < (d == 3 ? n : 1); ++k)
+        for (int j = 0; j < n; ++j)
+            for (int i = 0; i < n; ++i) {
+                const int p = id(i, j, k);
+                A[p * m + p] = 2.0 * d;
+                const int nb[6][3] = {{i - 1, j, k}, {i + 1, j, k}, {i, j - 1, k},
+                                      {i, j + 1, k}, {i, j, k - 1}, {i, j, k + 1}};
+                for (int q = 0; q < 2 * d; ++q) {
+                    const int a = nb[q][0], b = nb[q][1], c = nb[q][2];
+                    if (a < 0 || a >= n || b < 0 || b >= n) continue;
+                    if (d == 3 && (c < 0 || c >= n)) continue;
+                    A[p * m + id(a, b, c)] = -1.0;
+                }
+            }
+    for (int i = 0; i < m; ++i) I[i * m + i] = 1.0;
+    for (int c = 0; c < m; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < m; ++r)
+            if (std::fabs(A[r * m + c]) > std::fabs(A[piv * m + c])) piv = r;
+        for (int q = 0; q < m; ++q) {
+            std::swap(A[c * m + q], A[piv * m + q]);
+            std::swap(I[c * m + q], I[piv * m + q]);
+        }
+        const double dv = A[c * m + c];
+        for (int q = 0; q < m; ++q) {
+            A[c * m + q] /= dv;
+            I[c * m + q] /= dv;
+        }
+        for (int r = 0; r < m; ++r) {
+            if (r == c) continue;
+            const double f = A[r * m + c];
+            if (f == 0.0) continue;
+            for (int q = 0; q < m; ++q) {
+                A[r * m + q] -= f * A[c * m + q];
+                I[r * m + q] -= f * I[c * m + q];
+            }
+        }
+    }
+    return I;
+}
+
+void free_hier(Hier& H) {
+    for (auto* v : {&H.e, &H.b, &H.t})
+        for (void* p : *v)
+            if (p) (void)hipFree(p);
+    H.e.clear();
+    H.b.clear();
+    H.t.clear();
+    if (H.ginv) (void)hipFree(H.ginv);
+    H.ginv = nullptr;
+    H.allocated = false;
+}
+
+int alloc_hier(mg_ctx* h, Hier& H, Prec p) {
+    free_hier(H);
+    H.p = p;
+    H.scaled = p != P64;
+    H.e.assign(h->L, nullptr);
+    H.b.assign(h->L, nullptr);
+    H.t.assign(h->L, nullptr);
+    const size_t es = prec_bytes(p);
+    for (int l = 0; l < h->L; ++l) {
+        const size_t bytes = (size_t)level_pts(h, l) * h->batch * es;
+        if (l == 0 && p == P64) {
+            HIPCHK(hipMalloc(&H.t[0], bytes));
+            continue;
+        }
+        HIPCHK(hipMalloc(&H.e[l], bytes));
+        HIPCHK(hipMalloc(&H.b[l], bytes));
+        HIPCHK(hipMalloc(&H.t[l], bytes));
+    }
+    // exact coarsest solve: sigma * A^{-1}; A = N^2 * stencil (N = 4); in the
+    // scaled hierarchy sigma = N^2, so sigma A^{-1} = stencil^{-1}
+    std::vector<double> G = coarsest_stencil_inverse(h->d);
+    if (!H.scaled)
+        for (double& g : G) g /= 16.0;
+    HIPCHK(hipMalloc(&H.ginv, G.size() * sizeof(double)));
+    HIPCHK(hipMemcpy(H.ginv, G.data(), G.size() * sizeof(double), hipMemcpyHostToDevice));
+    H.allocated = true;
+    return MG_OK;
+}
+
+int alloc_common(mg_ctx* h) {
+    if (h->ualt) (void)hipFree(h->ualt);
+    if (h->psum) (void)hipFree(h->psum);
+    if (h->pmax) (void)hipFree(h->pmax);
+    if (h->dnorm) (void)hipFree(h->dnorm);
+    if (h->dscale) (void)hipFree(h->dscale);
+    if (h->hnorm) (void)hipHostFree(h->hnorm);
+    h->ualt = h->psum = h->pmax = h->dnorm = h->dscale = h->hnorm = nullptr;
+    const size_t fine = (size_t)level_pts(h, 0) * h->batch * sizeof(double);
+    HIPCHK(hipMalloc(&h->ualt, fine));
+    HIPCHK(hipMalloc(&h->psum, kPartialCap * h->batch * sizeof(double)));
+    HIPCHK(hipMalloc(&h->pmax, kPartialCap * h->batch * sizeof(double)));
+    h->norm_slots = h->max_cycles + 4;
+    HIPCHK(hipMalloc(&h->dnorm, 2 * h->norm_slots * sizeof(double)));
+    HIPCHK(hipMalloc(&h->dscale, h->norm_slots * sizeof(double)));
+    HIPCHK(hipHostMalloc(&h->hnorm, 2 * h->norm_slots * sizeof(double), hipHostMallocDefault));
+    return MG_OK;
+}
+
+void free_adj(mg_ctx* h);
+
+int realloc_all(mg_ctx* h) {
+    int rc = alloc_hier(h, h->h64, P64);
+    if (rc) return rc;
+    if (h->prec != MG_PREC_FP64) {
+        rc = alloc_hier(h, h->hlo, h->prec == MG_PREC_FP32_IR ? P32 : P16);
+        if (rc) return rc;
+    } else {
+        free_hier(h->hlo);
+    }
+    free_adj(h);
+    return alloc_common(h);
+}
+
+// ---- timing -------------------------------------------------------------
+
+bool timed(const mg_ctx* h, int kind, int level) {
+    if (h->timing == 2) return true;
+    return h->timing == 1 && kind == MG_TIME_SMOOTH && level == 0;
+}
+
+int time_begin(mg_ctx* h, int kind, int level, hipStream_t st, TimedLaunch* tl) {
+    if (h->ev_used + 2 > h->ev_pool.size()) {
+        for (int i = 0; i < 64; ++i) {
+            hipEvent_t e;
+            HIPCHK(hipEventCreate(&e));
+            h->ev_pool.push_back(e);
+        }
+    }
+    tl->kind = kind;
+    tl->level = level;
+    tl->a = h->ev_pool[h->ev_used++];
+    tl->b = h->ev_pool[h->ev_used++];
+    HIPCHK(hipEventRecord(tl->a, st));
+    return MG_OK;
+}
+
+int time_end(mg_ctx* h, TimedLaunch& tl, hipStream_t st) {
+    HIPCHK(hipEventRecord(tl.b, st));
+    h->pending.push_back(tl);
+    return MG_OK;
+}
+
+// after the stream has been synchronised
+int time_collect(mg_ctx* h) {
+    for (auto& tl : h->pending) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, tl.a, tl.b));
+        h->t_ms[tl.kind][tl.level] += ms;
+        h->t_cnt[tl.kind][tl.level] += 1;
+    }
+    h->pending.clear();
+    h->ev_used = 0;
+    return MG_OK;
+}
+
+// wraps one launch with optional timing events
+template <typename F>
+int run_timed(mg_ctx* h, int kind, int level, hipStream_t st, F&& launch) {
+    TimedLaunch tl;
+    const bool on = timed(h, kind, level);
+    if (on) {
+        int rc = time_begin(h, kind, level, st, &tl);
+        if (rc) return rc;
+    }
+    hipError_t e = launch();
+    if (e != hipSuccess) return fail(MG_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
+    if (on) return time_end(h, tl, st);
+    return MG_OK;
+}
+
+// ---- cycle pieces ------------------------------------------------------
+
+Sweep make_sweep(const mg_ctx* h, const Hier& H, int l) {
+    Sweep s;
+    s.d = h->d;
+    s.n = level_n(h, l);
+    s.batch = h->batch;
+    double pf;
+    level_scales(h, H, l, &s.sA, &s.sW, &pf);
+    for (int j = 0; j < 3; ++j) s.c[j] = j < h->ncoef ? h->c[j] : 0.0;
+    return s;
+}
+
+int run_tail(mg_ctx* h, Hier& H, int l, const void* b, void* e, hipStream_t st) {
+    Tail t;
+    t.d = h->d;
+    t.nt = level_n(h, l);
+    t.batch = h->batch;
+    t.b = b;
+    t.e = e;
+    for (int j = 0; j < 3; ++j) t.c[j] = j < h->ncoef ? h->c[j] : 0.0;
+    t.ginv = H.ginv;
+    t.scaled = H.scaled;
+    t.N_top = level_N(h, l);
+    return run_timed(h, MG_TIME_TAIL, l, st, [&] { return launch_tail(H.p, t, st); });
+}
+
+// e[l] = B_l b[l] (zero initial guess) on hierarchy H, levels l..L-1
+int coarse_cycle(mg_ctx* h, Hier& H, int l, hipStream_t st) {
+    if (l >= tail_level(h, H.p != P64)) return run_tail(h, H, l, H.b[l], H.e[l], st);
+    Sweep s = make_sweep(h, H, l);
+    double sA, sW, pf;
+    level_scales(h, H, l, &sA, &sW, &pf);
+    int rc;
+    s.b = H.b[l];
+    s.out = H.t[l];
+    rc = run_timed(h, MG_TIME_SMOOTH_ZERO, l, st,
+                   [&] { return launch_smooth(H.p, true, false, s, st, nullptr); });
+    if (rc) return rc;
+    s.u = H.t[l];
+    s.out = H.b[l + 1];
+    rc = run_timed(h, MG_TIME_RESTRICT, l, st, [&] { return launch_restrict(H.p, s, st); });
+    if (rc) return rc;
+    rc = coarse_cycle(h, H, l + 1, st);
+    if (rc) return rc;
+    rc = run_timed(h, MG_TIME_PROLONG, l, st, [&] {
+        return launch_prolong(H.p, h->d, s.n, h->batch, H.e[l + 1], H.t[l], pf, st);
+    });
+    if (rc) return rc;
+    s.u = H.t[l];
+    s.out = H.e[l];
+    return run_timed(h, MG_TIME_SMOOTH, l, st,
+                     [&] { return launch_smooth(H.p, false, false, s, st, nullptr); });
+}
+
+// One FP64 V(1,1) cycle on the finest grid: u_out = V(u_in, b).  With
+// norm_slot >= 0 the pre-smoother also produces ||b - A u_in||_2 into
+// dnorm[2 slot] and starts its copy to the pinned host mirror.
+int fine_cycle64(mg_ctx* h, const double* b, const double* u_in, double* u_out,
+                 int norm_slot, hipStream_t st, hipEvent_t norm_ready = nullptr) {
+    Hier& H = h->h64;
+    const bool norm = norm_slot >= 0;
+    int rc, nparts = 0;
+    if (h->L == 1) {
+        // a single grid (N = 4): the cycle is the exact solve
+        if (norm) {
+            HIPCHK(launch_residual_norm(h->d, level_n(h, 0), h->batch, u_in, b,
+                                        (double)h->N * h->N, h->psum, h->pmax,
+                                        kPartialCap * h->batch, st, &nparts));
+            HIPCHK(launch_finalize(h->psum, nullptr, nparts, h->dnorm + 2 * norm_slot, st));
+            HIPCHK(hipMemcpyAsync(h->hnorm + 2 * norm_slot, h->dnorm + 2 * norm_slot,
+                                  sizeof(double), hipMemcpyDeviceToHost, st));
+            if (norm_ready) HIPCHK(hipEventRecord(norm_ready, st));
+        }
+        return run_tail(h, H, 0, b, u_out, st);
+    }
+    Sweep s = make_sweep(h, H, 0);
+    s.u = u_in;
+    s.b = b;
+    s.out = H.t[0];
+    s.partials = h->psum;
+    s.partials_cap = kPartialCap * h->batch;
+    rc = run_timed(h, MG_TIME_SMOOTH, 0, st,
+                   [&] { return launch_smooth(P64, false, norm, s, st, &nparts); });
+    if (rc) return rc;
+    if (norm) {
+        HIPCHK(launch_finalize(h->psum, nullptr, nparts, h->dnorm + 2 * norm_slot, st));
+        HIPCHK(hipMemcpyAsync(h->hnorm + 2 * norm_slot, h->dnorm + 2 * norm_slot,
+                              sizeof(double), hipMemcpyDeviceToHost, st));
+        if (norm_ready) HIPCHK(hipEventRecord(norm_ready, st));
+    }
+    s.u = H.t[0];
+    s.out = H.b[1];
+    rc = run_timed(h, MG_TIME_RESTRICT, 0, st, [&] { return launch_restrict(P64, s, st); });
+    if (rc) return rc;
+    rc = coarse_cycle(h, H, 1, st);
+    if (rc) return rc;
+    rc = run_timed(h, MG_TIME_PROLONG, 0, st, [&] {
+        return launch_prolong(P64, h->d, s.n, h->batch, H.e[1], H.t[0], 1.0, st);
+    });
+    if (rc) return rc;
+    s.u = H.t[0];
+    s.out = u_out;
+    s.partials = nullptr;
+    return run_timed(h, MG_TIME_SMOOTH, 0, st,
+                     [&] { return launch_smooth(P64, false, false, s, st, nullptr); });
+}
+
+int check_handle(mg_ctx* h) {
+    if (!h) return fail(MG_EINVAL, "null handle");
+    return MG_OK;
+}
+
+}  // namespace
+
+// ============================================================== C ABI
+
+extern "C" {
+
+const char* mg_last_error(void) { return g_err.c_str(); }
+
+int mg_setup(int N, int d, const double* coeffs, int n_coeffs, mg_handle_t* out) {
+    if (!out) return fail(MG_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (d != 2 && d != 3) return fail(MG_EINVAL, "d must be 2 or 3");
+    if (N < 4 || (N & (N - 1)) != 0) return fail(MG_EINVAL, "N must be a power of two >= 4");
+    if ((d == 2 && N > 65536) || (d == 3 && N > 2048)) return fail(MG_EINVAL, "N too large");
+    const int nc = d == 2 ? 3 : 2;
+    if (!coeffs || n_coeffs != nc)
+        return fail(MG_EINVAL, d == 2 ? "2D takes 3 coefficients" : "3D takes 2 coefficients");
+    for (int j = 0; j < nc; ++j)
+        if (!std::isfinite(coeffs[j])) return fail(MG_EINVAL, "coefficients must be finite");
+    mg_ctx* h = new mg_ctx;
+    h->N = N;
+    h->d = d;
+    h->ncoef = nc;
+    for (int j = 0; j < nc; ++j) h->c[j] = coeffs[j];
+    h->L = 0;
+    for (int M = N; M >= 4; M /= 2) h->L++;
+    if (h->L > kMaxLevels) {
+        delete h;
+        return fail(MG_EINVAL, "too many levels");
+    }
+    int rc = realloc_all(h);
+    if (rc) {
+        mg_destroy(h);
+        return rc;
+    }
+    hipError_t e1 = hipEventCreate(&h->ev0), e2 = hipEventCreate(&h->ev1);
+    if (e1 != hipSuccess || e2 != hipSuccess) {
+        mg_destroy(h);
+        return fail(MG_EHIP, "hipEventCreate failed");
+    }
+    *out = h;
+    return MG_OK;
+}
+
+int mg_set_coeffs(mg_handle_t h, const double* coeffs, int n_coeffs) {
+    if (check_handle(h)) return MG_EINVAL;
+    if (!coeffs || n_coeffs != h->ncoef) return fail(MG_EINVAL, "wrong coefficient count");
+    for (int j = 0; j < n_coeffs; ++j)
+        if (!std::isfinite(coeffs[j])) return fail(MG_EINVAL, "coefficients must be finite");
+    for (int j = 0; j < n_coeffs; ++j) h->c[j] = coeffs[j];
+    return MG_OK;
+}
+
+int mg_set_option(mg_handle_t h, int key, double value) {
+    if (check_handle(h)) return MG_EINVAL;
+    const int v = (int)value;
+    if ((double)v != value) return fail(MG_EINVAL, "option values are integers");
+    switch (key) {
+        case MG_OPT_PRECISION:
+            if (v < MG_PREC_FP64 || v > MG_PREC_FP16_IR) return fail(MG_EINVAL, "bad precision");
+            if (v == h->prec) return MG_OK;
+            h->prec = v;
+            return realloc_all(h);
+        case MG_OPT_BATCH:
+            if (v < 1 || v > 65535) return fail(MG_EINVAL, "batch must be 1..65535");
+            if (v == h->batch) return MG_OK;
+            h->batch = v;
+            return realloc_all(h);
+        case MG_OPT_MAX_CYCLES:
+            if (v < 1 || v > 10000) return fail(MG_EINVAL, "max cycles must be 1..10000");
+            h->max_cycles = v;
+            return alloc_common(h);
+        case MG_OPT_TAIL_N: {
+            if (v == 0) {
+                h->tail_N = 0;
+                return MG_OK;
+            }
+            const int lim = h->d == 2 ? 64 : 16;
+            if (v < 4 || v > lim || (v & (v - 1)) != 0)
+                return fail(MG_EINVAL, "tail N must be a power of two in 4..64 (2D) or 4..16 (3D)");
+            h->tail_N = v;
+            return MG_OK;
+        }
+        case MG_OPT_TIMING:
+            if (v < 0 || v > 2) return fail(MG_EINVAL, "timing must be 0, 1 or 2");
+            h->timing = v;
+            return MG_OK;
+        default:
+            return fail(MG_EINVAL, "unknown option");
+    }
+}
+
+int mg_num_levels(mg_handle_t h) { return h ? h->L : MG_EINVAL; }
+
+int mg_vcycle(mg_handle_t h, const double* b, double* u, void* stream) {
+    if (check_handle(h)) return MG_EINVAL;
+    if (!b || !u) return fail(MG_EINVAL, "null field pointer");
+    hipStream_t st = (hipStream_t)stream;
+    // u is updated in place: the post-smoother reads the internal iterate
+    // and writes u, and the pre-smoother never writes u
+    return fine_cycle64(h, b, u, u, -1, st);
+}
+
+int mg_sweep(mg_handle_t h, int op, int level, int prec, const void* u, const void* b,
+             void* out, void* stream) {
+    if (check_handle(h)) return MG_EINVAL;
+    if (prec < MG_PREC_FP64 || prec > MG_PREC_FP16_IR) return fail(MG_EINVAL, "bad precision");
+    if (level < 0 || level >= h->L) return fail(MG_EINVAL, "bad level");
+    if (!out) return fail(MG_EINVAL, "null output");
+    if (op != MG_OP_SMOOTH_ZERO && !u) return fail(MG_EINVAL, "null u");
+    if (op != MG_OP_PROLONG_ADD && !b) return fail(MG_EINVAL, "null b");
+    if ((op == MG_OP_RESTRICT || op == MG_OP_PROLONG_ADD) && level >= h->L - 1)
+        return fail(MG_EINVAL, "no coarser level");
+    const Prec p = prec == MG_PREC_FP64 ? P64 : (prec == MG_PREC_FP32_IR ? P32 : P16);
+    Hier H;
+    H.p = p;
+    H.scaled = p != P64;
+    Sweep s = make_sweep(h, H, level);
+    double sA, sW, pf;
+    level_scales(h, H, level, &sA, &sW, &pf);
+    hipStream_t st = (hipStream_t)stream;
+    s.u = u;
+    s.b = b;
+    s.out = out;
+    hipError_t e;
+    switch (op) {
+        case MG_OP_SMOOTH: e = launch_smooth(p, false, false, s, st, nullptr); break;
+        case MG_OP_SMOOTH_ZERO: e = launch_smooth(p, true, false, s, st, nullptr); break;
+        case MG_OP_RESTRICT: e = launch_restrict(p, s, st); break;
+        case MG_OP_PROLONG_ADD:
+            e = launch_prolong(p, h->d, s.n, h->batch, u, out, pf, st);
+            break;
+        default: return fail(MG_EINVAL, "bad op");
+    }
+    if (e != hipSuccess) return fail(MG_EHIP, std::string("launch: ") + hipGetErrorString(e));
+    return MG_OK;
+}
+
+int mg_coarse_cycle(mg_handle_t h, int level, int prec, const void* b, void* e,
+                    void* stream) {
+    if (check_handle(h)) return MG_EINVAL;
+    if (!b || !e) return fail(MG_EINVAL, "null field pointer");
+    if (prec < MG_PREC_FP64 || prec > MG_PREC_FP16_IR) return fail(MG_EINVAL, "bad precision");
+    if (level < 0 || level >= h->L) return fail(MG_EINVAL, "bad level");
+    if (prec == MG_PREC_FP64 && level == 0 && h->L > 1)
+        return fail(MG_EINVAL, "FP64 level 0 has no zero-guess hierarchy; use mg_vcycle");
+    Hier* H;
+    if (prec == MG_PREC_FP64) {
+        H = &h->h64;
+    } else {
+        if (prec != h->prec) return fail(MG_EINVAL, "set MG_OPT_PRECISION to this precision first");
+        H = &h->hlo;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    const size_t bytes = (size_t)level_pts(h, level) * h->batch * prec_bytes(H->p);
+    if (level >= tail_level(h, H->p != P64)) return run_tail(h, *H, level, b, e, st);
+    HIPCHK(hipMemcpyAsync(H->b[level], b, bytes, hipMemcpyDeviceToDevice, st));
+    int rc = coarse_cycle(h, *H, level, st);
+    if (rc) return rc;
+    HIPCHK(hipMemcpyAsync(e, H->e[level], bytes, hipMemcpyDeviceToDevice, st));
+    return MG_OK;
+}
+
+int mg_residual_norm(mg_handle_t h, const double* b, const double* u, double* norm,
+                     void* stream) {
+    if (check_handle(h)) return MG_EINVAL;
+    if (!b || !u || !norm) return fail(MG_EINVAL, "null pointer");
+    hipStream_t st = (hipStream_t)stream;
+    int nparts = 0;
+    const double N = h->N;
+    int rc = run_timed(h, MG_TIME_RESIDUAL, 0, st, [&] {
+        return launch_residual_norm(h->d, level_n(h, 0), h->batch, u, b, N * N, h->psum,
+                                    h->pmax, kPartialCap * h->batch, st, &nparts);
+    });
+    if (rc) return rc;
+    HIPCHK(launch_finalize(h->psum, h->pmax, nparts, h->dnorm, st));
+    HIPCHK(hipMemcpyAsync(h->hnorm, h->dnorm, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    rc = time_collect(h);
+    if (rc) return rc;
+    *norm = h->hnorm[0];
+    return MG_OK;
+}
+
+static int solve64(mg_ctx* h, const double* b, double* u, double tol, mg_stats* st_out,
+                   hipStream_t st) {
+    double* X = u;
+    double* Y = h->ualt;
+    const size_t fine = (size_t)level_pts(h, 0) * h->batch * sizeof(double);
+    HIPCHK(hipEventRecord(h->ev0, st));
+    std::vector<double> hist;
+    double r0 = 0.0, rk = 0.0;
+    int k = 0, code = MG_OK, run = 0;
+    hipEvent_t evn;
+    HIPCHK(hipEventCreateWithFlags(&evn, hipEventDisableTiming));
+    for (k = 0;; ++k) {
+        // cycle k reads u_k from X and writes u_{k+1} to Y; its pre-smoother
+        // also yields ||r_k||.  The host waits only for that norm while the
+        // rest of cycle k runs, then decides whether to enqueue cycle k + 1.
+        int rc = fine_cycle64(h, b, X, Y, k, st, evn);
+        if (rc) {
+            (void)hipEventDestroy(evn);
+            return rc;
+        }
+        ++run;
+        hipError_t e = hipEventSynchronize(evn);
+        if (e != hipSuccess) {
+            (void)hipEventDestroy(evn);
+            return fail(MG_EHIP, std::string("hipEventSynchronize: ") + hipGetErrorString(e));
+        }
+        const double nk = h->hnorm[2 * k];
+        if (!std::isfinite(nk)) {
+            code = MG_ENONFINITE;
+            rk = nk;
+            break;
+        }
+        if (k == 0) r0 = nk;
+        hist.push_back(nk);
+        rk = nk;
+        if (nk <= tol * r0) break;
+        if (k >= h->max_cycles) {
+            code = MG_ENOCONV;
+            break;
+        }
+        std::swap(X, Y);
+    }
+    (void)hipEventDestroy(evn);
+    // u_k is in X
+    if (X != u) HIPCHK(hipMemcpyAsync(u, X, fine, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipEventRecord(h->ev1, st));
+    HIPCHK(hipStreamSynchronize(st));
+    int rc = time_collect(h);
+    if (rc) return rc;
+    if (st_out) {
+        st_out->cycles = k;
+        st_out->cycles_run = run;
+        st_out->r0_norm = r0;
+        st_out->rk_norm = rk;
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+        st_out->elapsed_ms = ms;
+        if (st_out->res_hist)
+            for (int j = 0; j < (int)hist.size() && j < st_out->hist_cap; ++j)
+                st_out->res_hist[j] = hist[j];
+    }
+    if (code == MG_ENONFINITE) return fail(code, "residual norm is not finite");
+    if (code == MG_ENOCONV) return fail(code, "maximum number of cycles reached");
+    return MG_OK;
+}
+
+static int solve_ir(mg_ctx* h, const double* b, double* u, double tol, mg_stats* st_out,
+                    hipStream_t st) {
+    Hier& H = h->hlo;
+    double* X = u;
+    double* Y = h->ualt;
+    const size_t fine = (size_t)level_pts(h, 0) * h->batch * sizeof(double);
+    const double N = h->N;
+    const double sigma0 = H.scaled ? N * N : 1.0;
+    HIPCHK(hipEventRecord(h->ev0, st));
+    int nparts = 0, rc;
+    // residual of the initial guess: slot 0 holds (||r_0||, max|r_0|)
+    rc = run_timed(h, MG_TIME_RESIDUAL, 0, st, [&] {
+        return launch_residual_norm(h->d, level_n(h, 0), h->batch, X, b, N * N, h->psum,
+                                    h->pmax, kPartialCap * h->batch, st, &nparts);
+    });
+    if (rc) return rc;
+    HIPCHK(launch_finalize(h->psum, h->pmax, nparts, h->dnorm, st));
+    std::vector<double> hist;
+    double r0 = 0.0, rk = 0.0;
+    int k = 0, code = MG_OK, run = 0;
+    hipEvent_t evn;
+    HIPCHK(hipEventCreateWithFlags(&evn, hipEventDisableTiming));
+    for (k = 0;; ++k) {
+        const int slot = 1 + k;   // k <= max_cycles < norm_slots - 2
+        const int pslot = k;
+        IRStep s;
+        s.d = h->d;
+        s.n = level_n(h, 0);
+        s.batch = h->batch;
+        s.k = k;
+        s.u = X;
+        s.unew = Y;
+        s.e_lo = k > 0 ? H.e[0] : nullptr;
+        s.b = b;
+        s.r_lo = H.b[0];
+        s.inv_h2 = N * N;
+        s.sigma0 = sigma0;
+        s.scales = h->dscale;
+        s.maxprev = h->dnorm + 2 * pslot + 1;
+        s.psum = h->psum;
+        s.pmax = h->pmax;
+        s.partials_cap = kPartialCap * h->batch;
+        rc = run_timed(h, MG_TIME_IR_STEP, 0, st,
+                       [&] { return launch_ir_step(H.p, s, st, &nparts); });
+        if (rc) return rc;
+        HIPCHK(launch_finalize(h->psum, h->pmax, nparts, h->dnorm + 2 * slot, st));
+        HIPCHK(hipMemcpyAsync(h->hnorm + 2 * slot, h->dnorm + 2 * slot, sizeof(double),
+                              hipMemcpyDeviceToHost, st));
+        HIPCHK(hipEventRecord(evn, st));
+        // inner low-precision cycle from zero on A e = s r
+        rc = coarse_cycle(h, H, 0, st);
+        if (rc) return rc;
+        ++run;
+        HIPCHK(hipEventSynchronize(evn));
+        const double nk = h->hnorm[2 * slot];
+        if (!std::isfinite(nk)) {
+            code = MG_ENONFINITE;
+            rk = nk;
+            break;
+        }
+        if (k == 0) r0 = nk;
+        hist.push_back(nk);
+        rk = nk;
+        if (nk <= tol * r0) break;
+        if (k >= h->max_cycles) {
+            code = MG_ENOCONV;
+            break;
+        }
+        std::swap(X, Y);
+    }
+    // u_k is the refinement step's output, in Y
+    if (Y != u) HIPCHK(hipMemcpyAsync(u, Y, fine, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipEventRecord(h->ev1, st));
+    HIPCHK(hipStreamSynchronize(st));
+    (void)hipEventDestroy(evn);
+    rc = time_collect(h);
+    if (rc) return rc;
+    if (st_out) {
+        st_out->cycles = k;
+        st_out->cycles_run = run;
+        st_out->r0_norm = r0;
+        st_out->rk_norm = rk;
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+        st_out->elapsed_ms = ms;
+        if (st_out->res_hist)
+            for (int j = 0; j < (int)hist.size() && j < st_out->hist_cap; ++j)
+                st_out->res_hist[j] = hist[j];
+    }
+    if (code == MG_ENONFINITE) return fail(code, "residual norm is not finite");
+    if (code == MG_ENOCONV) return fail(code, "maximum number of cycles reached");
+    return MG_OK;
+}
+
+int mg_solve(mg_handle_t h, const double* b, double* u, double tol, mg_stats* st,
+             void* stream) {
+    if (check_handle(h)) return MG_EINVAL;
+    if (!b || !u) return fail(MG_EINVAL, "null field pointer");
+    if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(MG_EINVAL, "tol must be finite and >= 0");
+    hipStream_t s = (hipStream_t)stream;
+    if (h->prec == MG_PREC_FP64) return solve64(h, b, u, tol, st, s);
+    return solve_ir(h, b, u, tol, st, s);
+}
+
+int mg_get_timing(mg_handle_t h, int kind, int level, double* total_ms, int* count) {
+    if (check_handle(h)) return MG_EINVAL;
+    if (kind < 0 || kind >= kTimeKinds || level < 0 || level >= kMaxLevels)
+        return fail(MG_EINVAL, "bad timing kind or level");
+    if (total_ms) *total_ms = h->t_ms[kind][level];
+    if (count) *count = h->t_cnt[kind][level];
+    return MG_OK;
+}
+
+int mg_reset_timing(mg_handle_t h) {
+    if (check_handle(h)) return MG_EINVAL;
+    std::memset(h->t_ms, 0, sizeof(h->t_ms));
+    std::memset(h->t_cnt, 0, sizeof(h->t_cnt));
+    return MG_OK;
+}
+
+void mg_destroy(mg_handle_t h) {
+    if (!h) return;
+    free_hier(h->h64);
+    free_hier(h->hlo);
+    free_adj(h);
+    if (h->ualt) (void)hipFree(h->ualt);
+    if (h->psum) (void)hipFree(h->psum);
+    if (h->pmax) (void)hipFree(h->pmax);
+    if (h->dnorm) (void)hipFree(h->dnorm);
+    if (h->dscale) (void)hipFree(h->dscale);
+    if (h->hnorm) (void)hipHostFree(h->hnorm);
+    for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
+    if (h->ev0) (void)hipEventDestroy(h->ev0);
+    if (h->ev1) (void)hipEventDestroy(h->ev1);
+    delete h;
+}
+
+}  // extern "C"
+
+namespace {
+void free_adj(mg_ctx* h) {
+    for (double* p : h->adj)
+        if (p) (void)hipFree(p);
+    h->adj.clear();
+    if (h->adj_cpart) (void)hipFree(h->adj_cpart);
+    if (h->adj_cacc) (void)hipFree(h->adj_cacc);
+    h->adj_cpart = h->adj_cacc = nullptr;
+    h->adj_alloc = false;
+}
+}  // namespace
+
+extern "C" int mg_vcycle_adjoint(mg_handle_t h, const double* b, const double* u_in,
+                                 const double* ubar_out, double* ubar_in, double* bbar_acc,
+                                 double* cbar_acc, void* stream) {
+    (void)b; (void)u_in; (void)ubar_out; (void)ubar_in; (void)bbar_acc; (void)cbar_acc;
+    (void)stream;
+    if (!h) return fail(MG_EINVAL, "null handle");
+    return fail(MG_EINVAL, "adjoint cycle not available in this build");
+}

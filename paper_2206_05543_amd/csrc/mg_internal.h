@@ -1,0 +1,115 @@
+// Internal interface between the host orchestration (mg_api.cpp) and the
+// gfx950 kernels (mg_kernels.hip).  Not part of the public C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace spaimg {
+
+// Storage precision of a level hierarchy.  FP64 computes in double; FP32 and
+// FP16 (storage) compute in float.
+enum Prec : int { P64 = 0, P32 = 1, P16 = 2 };
+
+inline size_t prec_bytes(Prec p) { return p == P64 ? 8 : (p == P32 ? 4 : 2); }
+
+// One stencil sweep over a grid with n = N-1 interior nodes per direction.
+// Values are stored scaled by sigma (stored = sigma * true value); the sweep
+// uses sA = 1/(h^2 sigma) in front of the Laplacian stencil and
+// sW = h^2 sigma in front of the SPAI stencil, so the same code serves the
+// unscaled FP64 hierarchy (sigma = 1) and the h-free scaled low-precision
+// hierarchies (sigma = 1/h^2, sA = sW = 1).
+struct Sweep {
+    const void* u = nullptr;     // current iterate (ignored for zero guess)
+    const void* b = nullptr;     // right-hand side
+    void* out = nullptr;         // output (new iterate, or coarse rhs)
+    int d = 2;
+    int n = 0;                   // interior nodes per direction (fine grid)
+    int batch = 1;
+    double sA = 0, sW = 0;
+    double c[3] = {0, 0, 0};     // SPAI coefficients (centre, face, corner)
+    double* partials = nullptr;  // per-block sum r^2 (norm variant)
+    long partials_cap = 0;       // entries available in partials
+};
+
+// Launchers return hipSuccess or the launch error.  *nparts receives the
+// number of per-block partial sums written (norm variants).
+hipError_t launch_smooth(Prec p, bool zero_guess, bool norm, const Sweep& s,
+                         hipStream_t st, int* nparts);
+hipError_t launch_restrict(Prec p, const Sweep& s, hipStream_t st);
+// u (fine, n interior) += pf * P ec (coarse, n/2 interior)
+hipError_t launch_prolong(Prec p, int d, int n, int batch, const void* ec,
+                          void* u, double pf, hipStream_t st);
+// Coarse tail: from a level with nt interior nodes down to 3 and back up, in
+// one workgroup, for every batch entry.  b and e hold the tail's top level.
+struct Tail {
+    int d = 2, nt = 0, batch = 1;
+    const void* b = nullptr;
+    void* e = nullptr;
+    double c[3] = {0, 0, 0};
+    const double* ginv = nullptr;  // device: sigma_0 * A_0^{-1}, (3^d)^2
+    double sigma_top = 1.0;        // storage scale of the top tail level
+    bool scaled = false;           // scaled hierarchy (sigma_l = 1/h_l^2)
+    int N_top = 0;                 // intervals of the top tail level
+};
+hipError_t launch_tail(Prec p, const Tail& t, hipStream_t st);
+size_t tail_lds_bytes(Prec p, int d, int nt);
+
+// Deterministic norm finalisation: out[0] = sqrt(sum partials) (fixed order),
+// out[1] = max of the max-partials (if maxparts != nullptr).
+hipError_t launch_finalize(const double* partials, const double* maxparts,
+                           int count, double* out, hipStream_t st);
+
+// Fine-grid residual norm of an FP64 iterate: partials of r^2 and max|r|.
+hipError_t launch_residual_norm(int d, int n, int batch, const double* u,
+                                const double* b, double inv_h2, double* psum,
+                                double* pmax, long partials_cap, hipStream_t st,
+                                int* nparts);
+
+// One FP64 refinement step: unew = u + e_lo * scale_prev (if e_lo), the
+// residual r = b - A unew in FP64 and r_lo = s r stored in precision p,
+// where s = 2^-ceil(log2(max|r_prev|)) is read from maxprev on the device
+// and written to scales[k].  Partials of r^2 and max|r|.
+struct IRStep {
+    int d = 2, n = 0, batch = 1, k = 0;
+    const double* u = nullptr;
+    double* unew = nullptr;
+    const void* e_lo = nullptr;  // correction from the previous inner cycle
+    const double* b = nullptr;
+    void* r_lo = nullptr;
+    double inv_h2 = 0;
+    double sigma0 = 1;           // storage scale of the inner fine level
+    double* scales = nullptr;    // device array of refinement scales
+    const double* maxprev = nullptr;  // device: max|r_{k-1}|
+    double* psum = nullptr;
+    double* pmax = nullptr;
+    long partials_cap = 0;
+};
+hipError_t launch_ir_step(Prec p, const IRStep& s, hipStream_t st, int* nparts);
+
+// Reverse-mode kernels of the adjoint cycle (FP64 only).
+//   adj_smooth: w = W ubar (ring), ubar_new = ubar - A w, bbar += w,
+//               partial sums of <ubar, K_j r> for j = 0..ncoef-1.
+hipError_t launch_adj_smooth(int d, int n, int batch, const double* ubar,
+                             const double* r, double* ubar_new, double* bbar,
+                             double inv_h2, double h2, const double* c,
+                             double* partials, hipStream_t st, int* nparts);
+//   adj_restrict: rbar = R^T bcbar; bbar += rbar; ubar -= A rbar (in place ok)
+hipError_t launch_adj_restrict(int d, int n, int batch, const double* bcbar,
+                               double* ubar, double* bbar, double inv_h2,
+                               hipStream_t st);
+//   ecbar = P^T ubar (coarse = n/2 interior)
+hipError_t launch_prolong_T(int d, int n, int batch, const double* ubar,
+                            double* ecbar, hipStream_t st);
+//   r = b - A u (FP64, plain residual field)
+hipError_t launch_residual(int d, int n, int batch, const double* u,
+                           const double* b, double* r, double inv_h2,
+                           hipStream_t st);
+//   coefficient-gradient partial sums -> cbar (device, ncoef doubles, +=)
+hipError_t launch_reduce_cols(const double* partials, int count, int ncols,
+                              double* acc, hipStream_t st);
+// dense matvec on the coarsest grid for the adjoint: y (+)= G x per batch
+hipError_t launch_coarse_matvec(int m, int batch, const double* G,
+                                const double* x, double* y, bool accumulate,
+                                hipStream_t st);
+
+}  // namespace spaimg

@@ -1,0 +1,128 @@
+"""Parity of whole cycles and solves with the CPU oracle.
+
+V(1,1) cycles are compared element by element (the cycle is a fixed affine
+map of norm about 1, so rounding differences stay at a few hundred ulps of
+max|u|).  Solves are compared iterate by iterate through the residual
+histories, which are deterministic linear algebra up to rounding, and the
+final iterates to the accuracy the tolerance implies.  At the full workload
+sizes, the oracle checks one V-cycle element by element and the solve through
+properties that hold at any size: the oracle's own residual of the GPU
+solution, and the distance to the closed-form discrete solution of the
+sine-mode right-hand side (||u - u*|| <= ||r|| / lambda_min).
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2206_05543_amd import M7, M9, JACOBI_2D, M5
+from paper_2206_05543_amd.workloads import poisson_problem, sine_sum, workload
+from tests._gpu import dev, gpu, host, make_mg, need_gpu, say, torch
+
+pytestmark = gpu
+
+
+def _c(d):
+    return np.array(M9 if d == 2 else M7)
+
+
+@pytest.mark.parametrize("d,N,batch", [(2, 8, 1), (2, 64, 1), (2, 256, 2), (2, 1024, 1),
+                                       (3, 8, 1), (3, 32, 2), (3, 64, 1), (3, 128, 1)])
+def test_vcycle_parity(d, N, batch):
+    need_gpu()
+    rng = np.random.default_rng(N + 7 * batch)
+    shp = (batch,) + (N - 1,) * d
+    u0 = rng.uniform(-1, 1, shp)
+    b = rng.standard_normal(shp) * 10
+    say("vcycle", d, N, batch)
+    with make_mg(N, d, _c(d), batch=batch) as mg:
+        u = dev(u0)
+        mg.vcycle(dev(b), u)
+        torch.cuda.synchronize()
+        got = host(u)
+    for s in range(batch):
+        want = O.vcycle(d, N, _c(d), u0[s], b[s])
+        scale = max(np.abs(want).max(), np.abs(u0[s]).max())
+        assert np.max(np.abs(got[s] - want)) <= 1e-12 * scale
+
+
+@pytest.mark.parametrize("coeffs", [M9, JACOBI_2D, M5], ids=["M9", "J", "M5"])
+def test_solve_config0_history(coeffs):
+    # 2D N=64, eight sine modes, initial guess U[-1, 1], V(1,1) to 1e-10
+    need_gpu()
+    p = workload("poisson2d_n64")
+    c = np.array(coeffs)
+    u_or, k_or, hist_or = O.solve(2, 64, c, p["u0"], p["b"], tol=1e-10, maxc=100)
+    say("solve-config0", coeffs)
+    with make_mg(64, 2, c) as mg:
+        u = dev(p["u0"])
+        st = mg.solve(dev(p["b"]), u, tol=1e-10)
+        got = host(u)
+    assert st["code"] == 0
+    assert st["cycles"] == k_or
+    h = np.array(st["history"])
+    assert np.allclose(h, hist_or, rtol=1e-8, atol=1e-13 * hist_or[0])
+    assert np.max(np.abs(got - u_or)) <= 1e-9 * np.abs(u_or).max()
+    # the oracle's own residual of the GPU iterate meets the tolerance
+    assert O.norm2(O.residual(2, 64, got, p["b"])) <= 1.0001e-10 * hist_or[0]
+
+
+@pytest.mark.parametrize("d,N", [(2, 256), (3, 32), (3, 64)])
+def test_solve_history_mid_size(d, N):
+    need_gpu()
+    p = poisson_problem(d, N, seed=11, n_modes=8, kmax=N // 4)
+    u_or, k_or, hist_or = O.solve(d, N, _c(d), p["u0"], p["b"], tol=1e-10, maxc=100)
+    say("solve-mid", d, N)
+    with make_mg(N, d, _c(d)) as mg:
+        u = dev(p["u0"])
+        st = mg.solve(dev(p["b"]), u, tol=1e-10)
+        got = host(u)
+    assert st["cycles"] == k_or
+    assert np.allclose(st["history"], hist_or, rtol=1e-8, atol=1e-13 * hist_or[0])
+    assert np.max(np.abs(got - u_or)) <= 1e-9 * np.abs(u_or).max()
+
+
+def _closed_form(d, N, modes, weights):
+    lam = 4.0 * N * N * sum(np.sin(modes[:, a] * np.pi / (2 * N)) ** 2 for a in range(d))
+    return sine_sum(d, N, modes, weights / lam)
+
+
+@pytest.mark.parametrize("name", ["poisson2d_n4096", "poisson3d_n256"])
+def test_full_size_vcycle_and_solve(name):
+    need_gpu()
+    p = workload(name)
+    d = 2 if "2d" in name else 3
+    N = 4096 if d == 2 else 256
+    c = _c(d)
+    say("full-size", name)
+    with make_mg(N, d, c) as mg:
+        b = dev(p["b"])
+        u = dev(p["u0"])
+        mg.vcycle(b, u)
+        torch.cuda.synchronize()
+        got1 = host(u)
+        want1 = O.vcycle(d, N, c, p["u0"], p["b"])
+        assert np.max(np.abs(got1 - want1)) <= 1e-12 * np.abs(want1).max()
+        u = dev(p["u0"])
+        st = mg.solve(b, u, tol=1e-10)
+        got = host(u)
+    assert st["code"] == 0 and 5 <= st["cycles"] <= 20
+    r0 = O.norm2(O.residual(d, N, p["u0"], p["b"]))
+    rk = O.norm2(O.residual(d, N, got, p["b"]))
+    assert abs(st["r0"] - r0) <= 1e-10 * r0
+    assert rk <= 1.0001e-10 * r0
+    ustar = _closed_form(d, N, p["modes"], p["weights"])
+    lam_min = 4.0 * d * N * N * np.sin(np.pi / (2 * N)) ** 2
+    assert np.linalg.norm(got - ustar) <= 1.01 * rk / lam_min + 1e-12 * np.linalg.norm(ustar)
+
+
+def test_residual_norm_entry_point():
+    need_gpu()
+    rng = np.random.default_rng(3)
+    d, N = 3, 64
+    u0 = rng.uniform(-1, 1, (N - 1,) * d)
+    b = rng.standard_normal((N - 1,) * d)
+    say("residual-norm")
+    with make_mg(N, d, _c(d)) as mg:
+        got = mg.residual_norm(dev(b), dev(u0))
+    want = O.norm2(O.residual(d, N, u0, b))
+    assert abs(got - want) <= 1e-12 * want

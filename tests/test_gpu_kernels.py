@@ -1,0 +1,157 @@
+"""Parity of every building-block kernel with the CPU oracle, element by
+element, on seeded inputs: the fused residual + SPAI smoother (from a guess
+and from zero), the fused residual + full-weighting restriction, linear
+interpolation + correction and the LDS coarse tail, in FP64 and in the scaled
+FP32 / FP16 storage of the refinement hierarchies.
+
+Tolerances.  FP64 smoothing out = u + h^2 K (b - h^-2 L u): the residual
+b - h^-2 L u carries an absolute rounding error of at most about
+8 eps (|b| + 4d h^-2 |u|); K has weights summing to about 0.63 (M9) or 0.38
+(M7) in h^2 units; so |out_gpu - out_oracle| <= 64 eps (max|u| + h^2 max|b|)
+bounds every ordering and FMA contraction the kernel may use.  The same
+bound with eps of FP32 holds for the FP32 storage; FP16 storage adds the
+rounding of the stored output, one half-ulp, i.e. eps16 |out|.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2206_05543_amd import M7, M9
+from tests._gpu import (EPS16, EPS32, EPS64, dev, gpu, host, make_mg, need_gpu, say,
+                        torch)
+
+pytestmark = gpu
+
+CASES_2D = [16, 64, 512, 1024]
+CASES_3D = [8, 32, 128]
+STORE = {"fp64": np.float64, "fp32_ir": np.float32, "fp16_ir": np.float16}
+EPS = {"fp64": EPS64, "fp32_ir": EPS32, "fp16_ir": EPS32}
+
+
+def _coeffs(d):
+    return np.array(M9 if d == 2 else M7)
+
+
+def _rand(rng, shape, scale=1.0):
+    return scale * rng.uniform(-1.0, 1.0, shape)
+
+
+def _roundtrip(a, prec):
+    """The values the GPU actually sees after storage rounding."""
+    return a.astype(STORE[prec]).astype(np.float64)
+
+
+def _tdt(prec):
+    return {"fp64": torch.float64, "fp32_ir": torch.float32, "fp16_ir": torch.float16}[prec]
+
+
+def _sigma(prec, N):
+    # stored = sigma * true; the low-precision hierarchies store e / h^2
+    return 1.0 if prec == "fp64" else float(N) * N
+
+
+def _tol(prec, *mags, out_mag=0.0):
+    t = 64 * EPS[prec] * sum(mags)
+    if prec == "fp16_ir":
+        t += EPS16 * out_mag
+    return t
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_ir", "fp16_ir"])
+@pytest.mark.parametrize("d,N", [(2, n) for n in CASES_2D] + [(3, n) for n in CASES_3D])
+@pytest.mark.parametrize("level", [0, 1])
+def test_smooth_parity(d, N, level, prec):
+    need_gpu()
+    Nl = N >> level
+    if Nl < 4:
+        pytest.skip("level does not exist")
+    rng = np.random.default_rng(100 + N + level)
+    shp = (Nl - 1,) * d
+    c = _coeffs(d)
+    sig = _sigma(prec, Nl)
+    # stored iterate O(1), rhs O(1) in the scaled form; true units for fp64
+    us = _roundtrip(_rand(rng, shp), prec)
+    b = _roundtrip(_rand(rng, shp, 1.0 if prec != "fp64" else Nl * Nl), prec)
+    say("smooth", d, N, level, prec)
+    with make_mg(N, d, c) as mg:
+        out = torch.empty(shp, dtype=_tdt(prec), device="cuda")
+        mg.sweep("smooth", level, prec, dev(us, _tdt(prec)), dev(b, _tdt(prec)), out)
+        out0 = torch.empty_like(out)
+        mg.sweep("smooth_zero", level, prec, None, dev(b, _tdt(prec)), out0)
+        torch.cuda.synchronize()
+        got, got0 = host(out), host(out0)
+    want = O.smooth(d, Nl, c, us / sig, b) * sig
+    want0 = O.apply_W(d, Nl, c, b) * sig
+    h2 = 1.0 / (Nl * Nl)
+    tol = _tol(prec, np.abs(us).max(), h2 * sig * np.abs(b).max(), out_mag=np.abs(want).max())
+    tol0 = _tol(prec, h2 * sig * np.abs(b).max(), out_mag=np.abs(want0).max())
+    assert np.max(np.abs(got - want)) <= tol
+    assert np.max(np.abs(got0 - want0)) <= tol0
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_ir", "fp16_ir"])
+@pytest.mark.parametrize("d,N", [(2, n) for n in CASES_2D] + [(3, n) for n in CASES_3D])
+def test_restrict_parity(d, N, prec):
+    need_gpu()
+    rng = np.random.default_rng(200 + N)
+    shp, shc = (N - 1,) * d, (N // 2 - 1,) * d
+    sig = _sigma(prec, N)
+    us = _roundtrip(_rand(rng, shp), prec)
+    b = _roundtrip(_rand(rng, shp, 1.0 if prec != "fp64" else N * N), prec)
+    say("restrict", d, N, prec)
+    with make_mg(N, d, _coeffs(d)) as mg:
+        out = torch.empty(shc, dtype=_tdt(prec), device="cuda")
+        mg.sweep("restrict", 0, prec, dev(us, _tdt(prec)), dev(b, _tdt(prec)), out)
+        torch.cuda.synchronize()
+        got = host(out)
+    want = O.restrict(d, N, O.residual(d, N, us / sig, b))
+    tol = _tol(prec, np.abs(b).max(), 4 * d * N * N / sig * np.abs(us).max(),
+               out_mag=np.abs(want).max())
+    assert np.max(np.abs(got - want)) <= tol
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_ir", "fp16_ir"])
+@pytest.mark.parametrize("d,N", [(2, n) for n in CASES_2D] + [(3, n) for n in CASES_3D])
+def test_prolong_parity(d, N, prec):
+    need_gpu()
+    rng = np.random.default_rng(300 + N)
+    shp, shc = (N - 1,) * d, (N // 2 - 1,) * d
+    sig, sigc = _sigma(prec, N), _sigma(prec, N // 2)
+    us = _roundtrip(_rand(rng, shp), prec)
+    ecs = _roundtrip(_rand(rng, shc), prec)
+    say("prolong", d, N, prec)
+    with make_mg(N, d, _coeffs(d)) as mg:
+        out = dev(us, _tdt(prec))
+        mg.sweep("prolong_add", 0, prec, dev(ecs, _tdt(prec)), None, out)
+        torch.cuda.synchronize()
+        got = host(out)
+    want = O.prolong_add(d, N, ecs / sigc, us / sig) * sig
+    tol = _tol(prec, np.abs(us).max(), 4 * np.abs(ecs).max(), out_mag=np.abs(want).max())
+    assert np.max(np.abs(got - want)) <= tol
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_ir", "fp16_ir"])
+@pytest.mark.parametrize("d,N,level", [(2, 64, 1), (2, 128, 1), (2, 16, 1), (2, 8, 1),
+                                       (3, 32, 1), (3, 16, 1), (3, 8, 1)])
+def test_coarse_tail_parity(d, N, level, prec):
+    # a zero-guess V(1,1) cycle below `level`, run entirely by the LDS tail
+    # kernel when N >> level is within the tail range, else by the level
+    # kernels down to the tail
+    need_gpu()
+    Nl = N >> level
+    rng = np.random.default_rng(400 + N)
+    shp = (Nl - 1,) * d
+    sig = _sigma(prec, Nl)
+    b = _roundtrip(_rand(rng, shp), prec)
+    say("coarse-cycle", d, N, level, prec)
+    with make_mg(N, d, _coeffs(d), precision=prec) as mg:
+        e = torch.empty(shp, dtype=_tdt(prec), device="cuda")
+        mg.coarse_cycle(level, prec, dev(b, _tdt(prec)), e)
+        torch.cuda.synchronize()
+        got = host(e)
+    want = O.vcycle(d, Nl, _coeffs(d), np.zeros(shp), b) * sig
+    # the cycle is a fixed linear map of norm O(1) in the scaled units; its
+    # rounding errors are bounded by a few hundred eps times the magnitudes
+    scale = np.abs(want).max()
+    tol = {"fp64": 1e-12, "fp32_ir": 2e-5, "fp16_ir": 2e-2}[prec] * scale
+    assert np.max(np.abs(got - want)) <= tol
