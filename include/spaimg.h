@@ -65,6 +65,9 @@ extern "C" {
                                single-workgroup LDS tail kernel; 0 = default   */
 #define MG_OPT_TIMING 5     /* 0 off; 1 time the fine-level smoother with HIP
                                events; 2 time every kernel of every level      */
+#define MG_OPT_INNER_CYCLES 6 /* low-precision V-cycles per FP64 refinement
+                               step, 1..16; 0 = default (3 for FP32, 2 for
+                               FP16)                                          */
 
 /* precisions for MG_OPT_PRECISION */
 #define MG_PREC_FP64 0      /* FP64 V-cycles                                  */
@@ -123,11 +126,13 @@ int mg_vcycle(mg_handle_t h, const double* b, double* u, void* stream);
 /* Cycles from the initial guess in u until ||b - A u_k||_2 <= tol ||b - A
  * u_0||_2 over the whole batch (the stopping rule on the relative residual,
  * Section 4), with the precision set by MG_OPT_PRECISION.  FP64: V(1,1)
- * cycles.  FP32_IR / FP16_IR: each step computes r = b - A u in FP64, scales
- * it by a power of two, runs one V(1,1) cycle from zero in low precision on
- * A e = s r, and updates u += e / s in FP64.  Synchronises `stream`.
- * Returns MG_ENOCONV (u = last iterate, st filled) if MG_OPT_MAX_CYCLES is
- * reached, MG_ENONFINITE if a norm is not finite.  st may be NULL. */
+ * cycles; st->cycles counts them.  FP32_IR / FP16_IR: each refinement step
+ * computes r = b - A u in FP64, scales it by a power of two s (so that
+ * max |s r| < 1), runs MG_OPT_INNER_CYCLES low-precision V(1,1) cycles on
+ * A e = s r (the first from zero) and updates u += e / s in FP64;
+ * st->cycles counts refinement steps.  Synchronises `stream`.  Returns
+ * MG_ENOCONV (u = last iterate, st filled) if MG_OPT_MAX_CYCLES is reached,
+ * MG_ENONFINITE if a norm is not finite.  st may be NULL. */
 int mg_solve(mg_handle_t h, const double* b, double* u, double tol, mg_stats* st,
              void* stream);
 
@@ -156,9 +161,17 @@ int mg_vcycle_adjoint(mg_handle_t h, const double* b, const double* u_in,
 int mg_sweep(mg_handle_t h, int op, int level, int prec, const void* u, const void* b,
              void* out, void* stream);
 
-/* Zero-guess V(1,1) cycle below and including `level` (level >= 1, or the
- * coarsest): e = B_level b, in precision prec (scaled storage as in
- * mg_sweep for the low precisions). */
+/* Fused post-smoothing sweep with the coarse-grid correction: with
+ * v = u + P ec (ec on level + 1; in the scaled low-precision storage the
+ * correction carries the factor 4 between levels), out = v + M (b - A v).
+ * out must not alias u, ec or b. */
+int mg_sweep_correct(mg_handle_t h, int level, int prec, const void* u, const void* ec,
+                     const void* b, void* out, void* stream);
+
+/* Zero-guess V(1,1) cycle from `level` down: e = B_level b, in precision
+ * prec (scaled storage as in mg_sweep for the low precisions; for those,
+ * MG_OPT_PRECISION must be set to prec first).  Levels at or below the tail
+ * size run in the single-workgroup LDS tail kernel. */
 int mg_coarse_cycle(mg_handle_t h, int level, int prec, const void* b, void* e,
                     void* stream);
 

@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(HERE, "libspaimg.so")
 
 MG_OK, MG_EINVAL, MG_EHIP, MG_ENOCONV, MG_ENONFINITE = 0, -1, -2, -3, -4
 OPT_PRECISION, OPT_BATCH, OPT_MAX_CYCLES, OPT_TAIL_N, OPT_TIMING = 1, 2, 3, 4, 5
+OPT_INNER_CYCLES = 6
 PREC = {"fp64": 0, "fp32_ir": 1, "fp16_ir": 2}
 OP = {"smooth": 0, "smooth_zero": 1, "restrict": 2, "prolong_add": 3}
 TIME = {"smooth": 0, "smooth_zero": 1, "restrict": 2, "prolong": 3, "tail": 4,
@@ -54,6 +55,7 @@ def lib():
         L.mg_vcycle_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, dp, vp]
         L.mg_sweep.argtypes = [vp, i, i, i, vp, vp, vp, vp]
         L.mg_coarse_cycle.argtypes = [vp, i, i, vp, vp, vp]
+        L.mg_sweep_correct.argtypes = [vp, i, i, vp, vp, vp, vp, vp]
         L.mg_residual_norm.argtypes = [vp, vp, vp, dp, vp]
         L.mg_get_timing.argtypes = [vp, i, i, dp, ctypes.POINTER(i)]
         L.mg_reset_timing.argtypes = [vp]
@@ -181,6 +183,17 @@ class Multigrid:
         po = self._field(out, lo, dt, "out")
         _check(lib().mg_sweep(self._h, o, level, code, pu, pb, po, _stream()))
         return out
+
+    def sweep_correct(self, level, prec, u, ec, b, out):
+        dt = STORAGE[PREC[prec]]
+        _check(lib().mg_sweep_correct(
+            self._h, level, PREC[prec], self._field(u, level, dt, "u"),
+            self._field(ec, level + 1, dt, "ec"), self._field(b, level, dt, "b"),
+            self._field(out, level, dt, "out"), _stream()))
+        return out
+
+    def set_inner_cycles(self, m):
+        self.set_option(OPT_INNER_CYCLES, m)
 
     def coarse_cycle(self, level, prec, b, e):
         code = PREC[prec]

@@ -59,6 +59,7 @@ struct TimedLaunch {
 struct mg_ctx {
     int N = 0, d = 2, L = 0, batch = 1, prec = MG_PREC_FP64, max_cycles = 100;
     int tail_N = 0;  // 0 = default
+    int inner = 0;   // inner cycles per refinement step, 0 = default
     int ncoef = 3;
     double c[3] = {0, 0, 0};
     Hier h64, hlo;
@@ -96,8 +97,13 @@ int level_N(const mg_ctx* h, int l) { return h->N >> l; }
 
 int default_tail_N(int d) { return d == 2 ? 64 : 16; }
 
-// first level handled by the tail kernel (never level 0 for FP64 cycles with
-// an initial guess; the low-precision inner cycle starts from zero)
+// low-precision V-cycles per FP64 refinement step
+int inner_cycles(const mg_ctx* h) {
+    if (h->inner) return h->inner;
+    return h->prec == MG_PREC_FP16_IR ? 2 : 3;
+}
+
+// first level whose zero-guess cycles run in the tail kernel
 int tail_level(const mg_ctx* h, bool allow_level0) {
     const int tN = h->tail_N ? h->tail_N : default_tail_N(h->d);
     for (int l = allow_level0 ? 0 : 1; l < h->L; ++l)
@@ -325,30 +331,66 @@ int run_tail(mg_ctx* h, Hier& H, int l, const void* b, void* e, hipStream_t st) 
     return run_timed(h, MG_TIME_TAIL, l, st, [&] { return launch_tail(H.p, t, st); });
 }
 
-// e[l] = B_l b[l] (zero initial guess) on hierarchy H, levels l..L-1
-int coarse_cycle(mg_ctx* h, Hier& H, int l, hipStream_t st) {
-    if (l >= tail_level(h, H.p != P64)) return run_tail(h, H, l, H.b[l], H.e[l], st);
+// Where the pre-smoother's residual norm goes (fine FP64 level only).
+struct NormReq {
+    int slot = -1;                  // dnorm slot, -1 = none
+    hipEvent_t ready = nullptr;     // recorded after the copy to the host
+};
+
+// One V(1,1) cycle on hierarchy H at level l: out = V(u_in, b), or from a
+// zero guess when u_in is null.  tmp receives the pre-smoothed iterate
+// (must differ from u_in, b and out; out may alias u_in).  Coarser levels
+// use H.b / H.e / H.t.  Zero-guess cycles at or below the tail size run in
+// the single-workgroup LDS tail kernel; the coarsest grid is always solved
+// exactly there.
+int cycle(mg_ctx* h, Hier& H, int l, const void* u_in, const void* b, void* out, void* tmp,
+          const NormReq& nr, hipStream_t st) {
+    const bool zero = u_in == nullptr;
+    int rc, nparts = 0;
+    if (l == h->L - 1 || (zero && l >= tail_level(h, true))) {
+        if (nr.slot >= 0) {
+            // only a single-grid FP64 problem (N = 4) gets here with a norm
+            HIPCHK(launch_residual_norm(h->d, level_n(h, l), h->batch,
+                                        static_cast<const double*>(u_in),
+                                        static_cast<const double*>(b), (double)h->N * h->N,
+                                        h->psum, h->pmax, kPartialCap * h->batch, st, &nparts));
+            HIPCHK(launch_finalize(h->psum, nullptr, nparts, h->dnorm + 2 * nr.slot, st));
+            HIPCHK(hipMemcpyAsync(h->hnorm + 2 * nr.slot, h->dnorm + 2 * nr.slot,
+                                  sizeof(double), hipMemcpyDeviceToHost, st));
+            if (nr.ready) HIPCHK(hipEventRecord(nr.ready, st));
+        }
+        return run_tail(h, H, l, b, out, st);
+    }
     Sweep s = make_sweep(h, H, l);
     double sA, sW, pf;
     level_scales(h, H, l, &sA, &sW, &pf);
-    int rc;
-    s.b = H.b[l];
-    s.out = H.t[l];
-    rc = run_timed(h, MG_TIME_SMOOTH_ZERO, l, st,
-                   [&] { return launch_smooth(H.p, true, false, s, st, nullptr); });
+    s.u = u_in;
+    s.b = b;
+    s.out = tmp;
+    const bool norm = nr.slot >= 0 && !zero && H.p == P64;
+    s.partials = h->psum;
+    s.partials_cap = kPartialCap * h->batch;
+    rc = run_timed(h, zero ? MG_TIME_SMOOTH_ZERO : MG_TIME_SMOOTH, l, st,
+                   [&] { return launch_smooth(H.p, zero, norm, s, st, &nparts); });
     if (rc) return rc;
-    s.u = H.t[l];
+    if (norm) {
+        HIPCHK(launch_finalize(h->psum, nullptr, nparts, h->dnorm + 2 * nr.slot, st));
+        HIPCHK(hipMemcpyAsync(h->hnorm + 2 * nr.slot, h->dnorm + 2 * nr.slot, sizeof(double),
+                              hipMemcpyDeviceToHost, st));
+        if (nr.ready) HIPCHK(hipEventRecord(nr.ready, st));
+    }
+    s.u = tmp;
     s.out = H.b[l + 1];
+    s.partials = nullptr;
     rc = run_timed(h, MG_TIME_RESTRICT, l, st, [&] { return launch_restrict(H.p, s, st); });
     if (rc) return rc;
-    rc = coarse_cycle(h, H, l + 1, st);
+    rc = cycle(h, H, l + 1, nullptr, H.b[l + 1], H.e[l + 1], H.t[l + 1], NormReq(), st);
     if (rc) return rc;
-    rc = run_timed(h, MG_TIME_PROLONG, l, st, [&] {
-        return launch_prolong(H.p, h->d, s.n, h->batch, H.e[l + 1], H.t[l], pf, st);
-    });
-    if (rc) return rc;
-    s.u = H.t[l];
-    s.out = H.e[l];
+    // post-smoothing of tmp + pf P e_{l+1} (correction fused into the sweep)
+    s.u = tmp;
+    s.out = out;
+    s.ec = H.e[l + 1];
+    s.pf = pf;
     return run_timed(h, MG_TIME_SMOOTH, l, st,
                      [&] { return launch_smooth(H.p, false, false, s, st, nullptr); });
 }
@@ -358,52 +400,10 @@ int coarse_cycle(mg_ctx* h, Hier& H, int l, hipStream_t st) {
 // dnorm[2 slot] and starts its copy to the pinned host mirror.
 int fine_cycle64(mg_ctx* h, const double* b, const double* u_in, double* u_out,
                  int norm_slot, hipStream_t st, hipEvent_t norm_ready = nullptr) {
-    Hier& H = h->h64;
-    const bool norm = norm_slot >= 0;
-    int rc, nparts = 0;
-    if (h->L == 1) {
-        // a single grid (N = 4): the cycle is the exact solve
-        if (norm) {
-            HIPCHK(launch_residual_norm(h->d, level_n(h, 0), h->batch, u_in, b,
-                                        (double)h->N * h->N, h->psum, h->pmax,
-                                        kPartialCap * h->batch, st, &nparts));
-            HIPCHK(launch_finalize(h->psum, nullptr, nparts, h->dnorm + 2 * norm_slot, st));
-            HIPCHK(hipMemcpyAsync(h->hnorm + 2 * norm_slot, h->dnorm + 2 * norm_slot,
-                                  sizeof(double), hipMemcpyDeviceToHost, st));
-            if (norm_ready) HIPCHK(hipEventRecord(norm_ready, st));
-        }
-        return run_tail(h, H, 0, b, u_out, st);
-    }
-    Sweep s = make_sweep(h, H, 0);
-    s.u = u_in;
-    s.b = b;
-    s.out = H.t[0];
-    s.partials = h->psum;
-    s.partials_cap = kPartialCap * h->batch;
-    rc = run_timed(h, MG_TIME_SMOOTH, 0, st,
-                   [&] { return launch_smooth(P64, false, norm, s, st, &nparts); });
-    if (rc) return rc;
-    if (norm) {
-        HIPCHK(launch_finalize(h->psum, nullptr, nparts, h->dnorm + 2 * norm_slot, st));
-        HIPCHK(hipMemcpyAsync(h->hnorm + 2 * norm_slot, h->dnorm + 2 * norm_slot,
-                              sizeof(double), hipMemcpyDeviceToHost, st));
-        if (norm_ready) HIPCHK(hipEventRecord(norm_ready, st));
-    }
-    s.u = H.t[0];
-    s.out = H.b[1];
-    rc = run_timed(h, MG_TIME_RESTRICT, 0, st, [&] { return launch_restrict(P64, s, st); });
-    if (rc) return rc;
-    rc = coarse_cycle(h, H, 1, st);
-    if (rc) return rc;
-    rc = run_timed(h, MG_TIME_PROLONG, 0, st, [&] {
-        return launch_prolong(P64, h->d, s.n, h->batch, H.e[1], H.t[0], 1.0, st);
-    });
-    if (rc) return rc;
-    s.u = H.t[0];
-    s.out = u_out;
-    s.partials = nullptr;
-    return run_timed(h, MG_TIME_SMOOTH, 0, st,
-                     [&] { return launch_smooth(P64, false, false, s, st, nullptr); });
+    NormReq nr;
+    nr.slot = norm_slot;
+    nr.ready = norm_ready;
+    return cycle(h, h->h64, 0, u_in, b, u_out, h->h64.t[0], nr, st);
 }
 
 int check_handle(mg_ctx* h) {
@@ -498,6 +498,10 @@ int mg_set_option(mg_handle_t h, int key, double value) {
             if (v < 0 || v > 2) return fail(MG_EINVAL, "timing must be 0, 1 or 2");
             h->timing = v;
             return MG_OK;
+        case MG_OPT_INNER_CYCLES:
+            if (v < 0 || v > 16) return fail(MG_EINVAL, "inner cycles must be 0..16");
+            h->inner = v;
+            return MG_OK;
         default:
             return fail(MG_EINVAL, "unknown option");
     }
@@ -549,14 +553,35 @@ int mg_sweep(mg_handle_t h, int op, int level, int prec, const void* u, const vo
     return MG_OK;
 }
 
+int mg_sweep_correct(mg_handle_t h, int level, int prec, const void* u, const void* ec,
+                     const void* b, void* out, void* stream) {
+    if (check_handle(h)) return MG_EINVAL;
+    if (prec < MG_PREC_FP64 || prec > MG_PREC_FP16_IR) return fail(MG_EINVAL, "bad precision");
+    if (level < 0 || level >= h->L - 1) return fail(MG_EINVAL, "bad level (needs a coarser one)");
+    if (!u || !ec || !b || !out) return fail(MG_EINVAL, "null field pointer");
+    const Prec p = prec == MG_PREC_FP64 ? P64 : (prec == MG_PREC_FP32_IR ? P32 : P16);
+    Hier H;
+    H.p = p;
+    H.scaled = p != P64;
+    Sweep s = make_sweep(h, H, level);
+    double sA, sW, pf;
+    level_scales(h, H, level, &sA, &sW, &pf);
+    s.u = u;
+    s.b = b;
+    s.out = out;
+    s.ec = ec;
+    s.pf = pf;
+    hipError_t e = launch_smooth(p, false, false, s, (hipStream_t)stream, nullptr);
+    if (e != hipSuccess) return fail(MG_EHIP, std::string("launch: ") + hipGetErrorString(e));
+    return MG_OK;
+}
+
 int mg_coarse_cycle(mg_handle_t h, int level, int prec, const void* b, void* e,
                     void* stream) {
     if (check_handle(h)) return MG_EINVAL;
     if (!b || !e) return fail(MG_EINVAL, "null field pointer");
     if (prec < MG_PREC_FP64 || prec > MG_PREC_FP16_IR) return fail(MG_EINVAL, "bad precision");
     if (level < 0 || level >= h->L) return fail(MG_EINVAL, "bad level");
-    if (prec == MG_PREC_FP64 && level == 0 && h->L > 1)
-        return fail(MG_EINVAL, "FP64 level 0 has no zero-guess hierarchy; use mg_vcycle");
     Hier* H;
     if (prec == MG_PREC_FP64) {
         H = &h->h64;
@@ -565,12 +590,9 @@ int mg_coarse_cycle(mg_handle_t h, int level, int prec, const void* b, void* e,
         H = &h->hlo;
     }
     hipStream_t st = (hipStream_t)stream;
-    const size_t bytes = (size_t)level_pts(h, level) * h->batch * prec_bytes(H->p);
-    if (level >= tail_level(h, H->p != P64)) return run_tail(h, *H, level, b, e, st);
-    HIPCHK(hipMemcpyAsync(H->b[level], b, bytes, hipMemcpyDeviceToDevice, st));
-    int rc = coarse_cycle(h, *H, level, st);
+    void* tmp = H->t[level];
+    int rc = cycle(h, *H, level, nullptr, b, e, tmp, NormReq(), st);
     if (rc) return rc;
-    HIPCHK(hipMemcpyAsync(e, H->e[level], bytes, hipMemcpyDeviceToDevice, st));
     return MG_OK;
 }
 
@@ -710,9 +732,14 @@ static int solve_ir(mg_ctx* h, const double* b, double* u, double tol, mg_stats*
         HIPCHK(hipMemcpyAsync(h->hnorm + 2 * slot, h->dnorm + 2 * slot, sizeof(double),
                               hipMemcpyDeviceToHost, st));
         HIPCHK(hipEventRecord(evn, st));
-        // inner low-precision cycle from zero on A e = s r
-        rc = coarse_cycle(h, H, 0, st);
+        // inner low-precision cycles on A e = s r: the first from zero, the
+        // others continue from the current e
+        rc = cycle(h, H, 0, nullptr, H.b[0], H.e[0], H.t[0], NormReq(), st);
         if (rc) return rc;
+        for (int j = 1; j < inner_cycles(h); ++j) {
+            rc = cycle(h, H, 0, H.e[0], H.b[0], H.e[0], H.t[0], NormReq(), st);
+            if (rc) return rc;
+        }
         ++run;
         HIPCHK(hipEventSynchronize(evn));
         const double nk = h->hnorm[2 * slot];

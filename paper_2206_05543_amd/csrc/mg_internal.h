@@ -29,6 +29,10 @@ struct Sweep {
     double c[3] = {0, 0, 0};     // SPAI coefficients (centre, face, corner)
     double* partials = nullptr;  // per-block sum r^2 (norm variant)
     long partials_cap = 0;       // entries available in partials
+    // optional fused correction: the sweep reads u + pf * P ec, where ec is a
+    // coarse-grid field ((n+1)/2 - 1 interior nodes) of the same storage type
+    const void* ec = nullptr;
+    double pf = 1.0;
 };
 
 // Launchers return hipSuccess or the launch error.  *nparts receives the

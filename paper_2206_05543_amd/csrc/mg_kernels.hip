@@ -40,6 +40,23 @@ __device__ __forceinline__ int xcd_remap(int bid, int total) {
 template <typename C, typename S>
 __device__ __forceinline__ C cvt(S v) { return static_cast<C>(v); }
 
+__device__ __forceinline__ int interp_idx(int i, int nc, int* j0, int* j1) {
+    // fine index i (grid coordinate i+1): even coordinate -> one coarse node,
+    // odd -> two; returns the count, indices clipped to the coarse interior
+    // (-1 marks a boundary node, value 0).
+    const int g = i + 1;
+    if ((g & 1) == 0) {
+        *j0 = g / 2 - 1;
+        *j1 = -1;
+        return 1;
+    }
+    const int a = (g - 1) / 2 - 1, c = (g + 1) / 2 - 1;
+    *j0 = (a >= 0 && a < nc) ? a : -1;
+    *j1 = (c >= 0 && c < nc) ? c : -1;
+    return 2;
+}
+
+
 // Deterministic workgroup sum (fixed shuffle tree, then waves in order).
 template <int NT>
 __device__ __forceinline__ double block_sum(double v, double* red) {
@@ -68,24 +85,42 @@ __device__ __forceinline__ double block_max(double v, double* red) {
 }
 
 // ---------------------------------------------------------------------------
-// 3D fused residual + SPAI smoother:  out = u + sW * K_c (b - sA * L u)
-// K_c = c0 I + c1 (6 face neighbours); residual zero outside the grid.
-// Tile TX x TY outputs per plane; the residual is computed on the tile plus a
-// ring of 1, which needs u on the tile plus a ring of 2 (without corners).
-// Output lags the residual by one plane.
+// Software pipeline of the marching kernels.  Global loads of the plane that
+// will be needed PD + 1 steps later are issued at the top of each step into
+// raw storage-typed registers; they are converted (and combined with the
+// fused coarse correction) only when the plane is consumed, so no arithmetic
+// waits on a load in flight.
 // ---------------------------------------------------------------------------
-template <typename S, typename C, int TX, int TY, int NT, bool ZG, bool NORM>
+
+// ---------------------------------------------------------------------------
+// 3D fused residual + SPAI smoother:  out = v + sW * K_c (b - sA * L v)
+// with v = u (PRO = false), v = 0 (ZG), or v = u + pf * P ec (PRO: the
+// coarse-grid correction fused into the post-smoother).  K_c = c0 I +
+// c1 (6 face neighbours); the residual is zero outside the grid.  Tile
+// TX x TY outputs per plane; the residual is computed on the tile plus a
+// ring of 1, which needs v on the tile plus a ring of 2 (without corners).
+// Output lags the residual by one plane.  For PRO, the coarse plane under
+// each even fine plane is staged once into an LDS tile, and every column
+// keeps the bilinear value of the last coarse plane in a register, so the
+// trilinear correction costs one coarse read per coarse node.
+// ---------------------------------------------------------------------------
+template <typename S, typename C, int TX, int TY, int NT, int PD, bool ZG, bool NORM, bool PRO>
 __global__ void __launch_bounds__(NT)
 k_smooth3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out,
            int n, int tiles_x, int tiles_y, int zchunk, int nchunks, C sA,
-           C sW, C c0, C c1, double* __restrict__ partials) {
+           C sW, C c0, C c1, double* __restrict__ partials,
+           const S* __restrict__ ec, int nc, C pf) {
     constexpr int RX = TX + 2, RY = TY + 2, NR = RX * RY;
     constexpr int UX = TX + 4, UY = TY + 4, NU = UX * UY;
     constexpr int M = (NR + NT - 1) / NT;
     constexpr int NR2 = 2 * RX + 2 * RY;
+    constexpr int CX = TX / 2 + 3, CY = TY / 2 + 3, NC = CX * CY;
+    constexpr int MC = (NC + NT - 1) / NT;
     static_assert(NR2 <= NT, "one thread per ring-2 point");
+    static_assert(TX % 2 == 0 && TY % 2 == 0, "even tiles");
     __shared__ C uL[2][ZG ? 1 : NU];
     __shared__ C rL[2][NR];
+    __shared__ C cL[PRO ? NC : 1];
     __shared__ double red[NT / 64];
 
     const int total = tiles_x * tiles_y * nchunks;
@@ -115,7 +150,7 @@ k_smooth3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out
         ul[m] = inr[m] ? (ly + 1) * UX + lx + 1 : 0;
         go[m] = val[m] ? gy * n + gx : 0;
     }
-    int r2l = 0, r2g = 0;
+    int r2l = 0, r2g = 0, r2x = 0, r2y = 0;
     bool r2v = false;
     if (!ZG && t < NR2) {
         int ux, uy;
@@ -123,36 +158,166 @@ k_smooth3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out
         else if (t < 2 * RX) { ux = 1 + t - RX; uy = UY - 1; }
         else if (t < 2 * RX + RY) { ux = 0; uy = 1 + t - 2 * RX; }
         else { ux = UX - 1; uy = 1 + t - 2 * RX - RY; }
-        const int gx = x0 - 2 + ux, gy = y0 - 2 + uy;
+        r2x = x0 - 2 + ux;
+        r2y = y0 - 2 + uy;
         r2l = uy * UX + ux;
-        r2v = gx >= 0 && gx < n && gy >= 0 && gy < n;
-        r2g = r2v ? gy * n + gx : 0;
+        r2v = r2x >= 0 && r2x < n && r2y >= 0 && r2y < n;
+        r2g = r2v ? r2y * n + r2x : 0;
     }
-    auto ldu = [&](int p, int m) -> C {
-        return (!ZG && val[m] && p >= 0 && p < n) ? cvt<C>(u[p * plane + go[m]]) : C(0);
+
+    // ---- fused coarse correction (PRO)
+    const long cplane = (long)nc * nc;
+    const int cx0 = x0 / 2 - 2, cy0 = y0 / 2 - 2;  // coarse tile origin
+    int cidx[M + 1][4];
+    C cw[M + 1], qprev[M + 1];
+    int cgo[MC];
+    bool cval[MC];
+    S rc[MC];
+    if (PRO) {
+        ec += (long)blockIdx.y * cplane * nc;
+        auto setup = [&](int k, bool ok, int gx, int gy) {
+            int xa, xb, ya, yb;
+            const int nx = interp_idx(gx, nc, &xa, &xb), ny = interp_idx(gy, nc, &ya, &yb);
+            cw[k] = (nx == 1 ? C(1) : C(0.5)) * (ny == 1 ? C(1) : C(0.5));
+            const int lxa = xa - cx0, lxb = xb - cx0, lya = ya - cy0, lyb = yb - cy0;
+            cidx[k][0] = (ok && xa >= 0 && ya >= 0) ? lya * CX + lxa : -1;
+            cidx[k][1] = (ok && nx == 2 && xb >= 0 && ya >= 0) ? lya * CX + lxb : -1;
+            cidx[k][2] = (ok && ny == 2 && xa >= 0 && yb >= 0) ? lyb * CX + lxa : -1;
+            cidx[k][3] = (ok && nx == 2 && ny == 2 && xb >= 0 && yb >= 0) ? lyb * CX + lxb : -1;
+            qprev[k] = C(0);
+        };
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const int i = t + m * NT;
+            setup(m, val[m], x0 - 1 + i % RX, y0 - 1 + i / RX);
+        }
+        setup(M, r2v, r2x, r2y);
+#pragma unroll
+        for (int j = 0; j < MC; ++j) {
+            const int i = t + j * NT;
+            const int gx = cx0 + i % CX, gy = cy0 + i / CX;
+            cval[j] = i < NC && gx >= 0 && gx < nc && gy >= 0 && gy < nc;
+            cgo[j] = cval[j] ? gy * nc + gx : 0;
+        }
+    }
+    auto c_issue = [&](int Z) {
+#pragma unroll
+        for (int j = 0; j < MC; ++j)
+            rc[j] = (cval[j] && Z >= 0 && Z < nc) ? ec[Z * cplane + cgo[j]] : S(0);
     };
-    auto ldb = [&](int p, int m) -> C {
-        return (val[m] && p >= 0 && p < n) ? cvt<C>(b[p * plane + go[m]]) : C(0);
+    auto c_write = [&]() {
+#pragma unroll
+        for (int j = 0; j < MC; ++j)
+            if (t + j * NT < NC) cL[t + j * NT] = cvt<C>(rc[j]);
     };
-    auto ldr2 = [&](int p) -> C {
-        return (!ZG && r2v && p >= 0 && p < n) ? cvt<C>(u[p * plane + r2g]) : C(0);
+    auto q_lds = [&](int k) -> C {
+        C q = C(0);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (cidx[k][j] >= 0) q += cL[cidx[k][j]];
+        return cw[k] * q;
+    };
+    auto q_direct = [&](int k, int Z) -> C {
+        if (Z < 0 || Z >= nc) return C(0);
+        C q = C(0);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (cidx[k][j] >= 0) {
+                const int c = cidx[k][j];
+                q += cvt<C>(ec[Z * cplane + (cy0 + c / CX) * nc + cx0 + c % CX]);
+            }
+        return cw[k] * q;
     };
 
-    C um1[M], u0[M], up1[M], nu[M], b0[M], nb[M], rm2[M], rm1[M], r0[M];
-    C urp1 = 0, nur = 0;
+    // ---- raw prefetch registers: ru[k] = plane s+2+k, rb[k] = b plane s+1+k
+    S ru[PD + 1][M], rb[PD + 1][M], rr2[PD + 1];
+    auto issue_u = [&](int p, int k) {
+#pragma unroll
+        for (int m = 0; m < M; ++m)
+            ru[k][m] = (!ZG && val[m] && p >= 0 && p < n) ? u[p * plane + go[m]] : S(0);
+        rr2[k] = (!ZG && r2v && p >= 0 && p < n) ? u[p * plane + r2g] : S(0);
+    };
+    auto issue_b = [&](int p, int k) {
+#pragma unroll
+        for (int m = 0; m < M; ++m)
+            rb[k][m] = (val[m] && p >= 0 && p < n) ? b[p * plane + go[m]] : S(0);
+    };
+    // consume raw plane p from slot 0: v = u + pf * P ec (zero off the grid);
+    // qh holds the bilinear coarse values of plane p/2 when p is even
+    auto take_u = [&](int p, const C* qh, C* dst, C& rdst) {
+#pragma unroll
+        for (int m = 0; m < M + 1; ++m) {
+            C v = cvt<C>(m < M ? ru[0][m] : rr2[0]);
+            if (PRO) {
+                C pe;
+                if ((p & 1) == 0) {
+                    pe = C(0.5) * (qprev[m] + qh[m]);
+                    qprev[m] = qh[m];
+                } else {
+                    pe = qprev[m];
+                }
+                v += pf * pe;
+            }
+            if (m < M) dst[m] = v; else rdst = v;
+        }
+    };
+    auto shift = [&]() {
+#pragma unroll
+        for (int k = 0; k < PD; ++k) {
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                ru[k][m] = ru[k + 1][m];
+                rb[k][m] = rb[k + 1][m];
+            }
+            rr2[k] = rr2[k + 1];
+        }
+    };
+
+    C um1[M], u0[M], up1[M], b0[M], rm2[M], rm1[M], r0[M];
+    C ur0 = 0, urp1 = 0;
     double nacc = 0.0;
     const int s0 = z0 - 1;
+    // prologue: planes s0-1, s0, s0+1 of v (synchronous), b of plane s0
+    {
+        C qh[M + 1];
+        if (PRO) {
+            const int pf0 = s0 - 1;
+            const int zp = (pf0 & 1) == 0 ? pf0 / 2 - 1 : (pf0 - 1) / 2;
 #pragma unroll
-    for (int m = 0; m < M; ++m) {
-        um1[m] = ldu(s0 - 1, m);
-        u0[m] = ldu(s0, m);
-        up1[m] = ldu(s0 + 1, m);
-        b0[m] = ldb(s0, m);
-        rm2[m] = rm1[m] = C(0);
+            for (int k = 0; k < M + 1; ++k) qprev[k] = q_direct(k, zp);
+        }
+        C dummy;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const int p = s0 - 1 + q;
+            issue_u(p, 0);
+            if (PRO && (p & 1) == 0) {
+#pragma unroll
+                for (int k = 0; k < M + 1; ++k) qh[k] = q_direct(k, p / 2);
+            }
+            C* dst = q == 0 ? um1 : (q == 1 ? u0 : up1);
+            take_u(p, qh, dst, q == 1 ? ur0 : (q == 2 ? urp1 : dummy));
+        }
+        issue_b(s0, 0);
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            b0[m] = cvt<C>(rb[0][m]);
+            rm2[m] = rm1[m] = C(0);
+        }
+        for (int k = 0; k < PD; ++k) {
+            issue_u(s0 + 2 + k, k);
+            issue_b(s0 + 1 + k, k);
+        }
+        if (PRO) {
+            if ((s0 & 1) == 0) {
+                c_issue((s0 + 2) / 2);
+                c_write();
+            } else {
+                c_issue((s0 + 3) / 2);
+            }
+        }
     }
     if (!ZG) {
-        const C ur0 = ldr2(s0);
-        urp1 = ldr2(s0 + 1);
         const int sl = (s0 + 2) & 1;
 #pragma unroll
         for (int m = 0; m < M; ++m)
@@ -163,13 +328,10 @@ k_smooth3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out
     for (int s = s0; s <= z1; ++s) {
         __syncthreads();
         const int cur = (s + 2) & 1;
-        // prefetch the planes needed by the next step
-#pragma unroll
-        for (int m = 0; m < M; ++m) {
-            nu[m] = ldu(s + 2, m);
-            nb[m] = ldb(s + 1, m);
-        }
-        if (!ZG && t < NR2) nur = ldr2(s + 2);
+        // prefetch: v plane s+2+PD and b plane s+1+PD; coarse plane for PRO
+        issue_u(s + 2 + PD, PD);
+        issue_b(s + 1 + PD, PD);
+        if (PRO && (s & 1) == 0) c_issue((s + 4) / 2);
         // residual of plane s on the tile plus ring 1
         const bool pin = s >= 0 && s < n;
 #pragma unroll
@@ -197,52 +359,64 @@ k_smooth3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out
             for (int m = 0; m < M; ++m) {
                 if (!inn[m]) continue;
                 const int q = rl[m];
-                const C rc = rm1[m];
+                const C rc0 = rm1[m];
                 const C nbs = R[q - 1] + R[q + 1] + R[q - RX] + R[q + RX] + rm2[m] + r0[m];
-                const C v = (ZG ? C(0) : um1[m]) + sW * (c0 * rc + c1 * nbs);
+                const C v = (ZG ? C(0) : um1[m]) + sW * (c0 * rc0 + c1 * nbs);
                 out[p * plane + go[m]] = static_cast<S>(v);
-                if (NORM) nacc += (double)rc * (double)rc;
+                if (NORM) nacc += (double)rc0 * (double)rc0;
             }
         }
-        // u of plane s + 1 into the other LDS slot
+        // v of plane s + 1 into the other LDS slot
         if (!ZG) {
 #pragma unroll
             for (int m = 0; m < M; ++m)
                 if (inr[m]) uL[cur ^ 1][ul[m]] = up1[m];
             if (t < NR2) uL[cur ^ 1][r2l] = urp1;
         }
+        // rotate: consume plane s+2 of v and plane s+1 of b
+        C qh[M + 1];
+        if (PRO && (s & 1) == 0) {
+#pragma unroll
+            for (int k = 0; k < M + 1; ++k) qh[k] = q_lds(k);
+        }
 #pragma unroll
         for (int m = 0; m < M; ++m) {
             um1[m] = u0[m];
             u0[m] = up1[m];
-            up1[m] = nu[m];
-            b0[m] = nb[m];
             rm2[m] = rm1[m];
             rm1[m] = r0[m];
+            b0[m] = cvt<C>(rb[0][m]);
         }
-        urp1 = nur;
+        if (!ZG) take_u(s + 2, qh, up1, urp1);
+        shift();
+        if (PRO && (s & 1) == 1) c_write();
     }
     if (NORM) {
-        const double s = block_sum<NT>(nacc, red);
-        if (t == 0) partials[(long)blockIdx.y * gridDim.x + blockIdx.x] = s;
+        const double sm = block_sum<NT>(nacc, red);
+        if (t == 0) partials[(long)blockIdx.y * gridDim.x + blockIdx.x] = sm;
     }
 }
 
 // ---------------------------------------------------------------------------
-// 2D fused residual + SPAI smoother (9-point M): x strips of TX outputs,
-// marching over rows.  The residual of row s is computed on the strip plus a
-// ring of 1; output lags by two rows because the 9-point stencil needs the
-// residual of rows p-1..p+1 at x-1..x+1 from LDS (4 row slots).
+// 2D fused residual + SPAI smoother (9-point M), same scheme: x strips of TX
+// outputs marching over rows.  The residual of row s is computed on the
+// strip plus a ring of 1; output lags by two rows because the 9-point
+// stencil needs the residual of rows p-1..p+1 at x-1..x+1 from LDS (4 row
+// slots).  PRO stages the coarse row under each even fine row in LDS.
 // ---------------------------------------------------------------------------
-template <typename S, typename C, int TX, int NT, bool ZG, bool NORM>
+template <typename S, typename C, int TX, int NT, int PD, bool ZG, bool NORM, bool PRO>
 __global__ void __launch_bounds__(NT)
 k_smooth2d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out,
            int n, int tiles_x, int ychunk, int nchunks, C sA, C sW, C c0, C c1,
-           C c2, double* __restrict__ partials) {
+           C c2, double* __restrict__ partials, const S* __restrict__ ec, int nc, C pf) {
     constexpr int RX = TX + 2, UX = TX + 4;
     constexpr int M = (RX + NT - 1) / NT;
+    constexpr int CX = TX / 2 + 3;
+    constexpr int MC = (CX + NT - 1) / NT;
+    static_assert(TX % 2 == 0, "even strips");
     __shared__ C uL[2][ZG ? 1 : UX];
     __shared__ C rL[4][RX];
+    __shared__ C cL[PRO ? CX : 1];
     __shared__ double red[NT / 64];
 
     const int total = tiles_x * nchunks;
@@ -273,31 +447,142 @@ k_smooth2d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out
     const int r2l = (t == 0) ? 0 : UX - 1;
     const bool r2v = !ZG && t < 2 && r2x >= 0 && r2x < n;
 
-    auto ldu = [&](int p, int m) -> C {
-        return (!ZG && val[m] && p >= 0 && p < n) ? cvt<C>(u[(long)p * n + go[m]]) : C(0);
+    const int cx0 = x0 / 2 - 2;
+    int cidx[M + 1][2];
+    C cw[M + 1], qprev[M + 1];
+    int cgo[MC];
+    bool cval[MC];
+    S rc[MC];
+    if (PRO) {
+        ec += (long)blockIdx.y * nc * nc;
+        auto setup = [&](int k, bool ok, int gx) {
+            int xa, xb;
+            const int nx = interp_idx(gx, nc, &xa, &xb);
+            cw[k] = nx == 1 ? C(1) : C(0.5);
+            cidx[k][0] = (ok && xa >= 0) ? xa - cx0 : -1;
+            cidx[k][1] = (ok && nx == 2 && xb >= 0) ? xb - cx0 : -1;
+            qprev[k] = C(0);
+        };
+#pragma unroll
+        for (int m = 0; m < M; ++m) setup(m, val[m], x0 - 1 + t + m * NT);
+        setup(M, r2v, r2x);
+#pragma unroll
+        for (int j = 0; j < MC; ++j) {
+            const int i = t + j * NT;
+            const int gx = cx0 + i;
+            cval[j] = i < CX && gx >= 0 && gx < nc;
+            cgo[j] = cval[j] ? gx : 0;
+        }
+    }
+    auto c_issue = [&](int Y) {
+#pragma unroll
+        for (int j = 0; j < MC; ++j)
+            rc[j] = (cval[j] && Y >= 0 && Y < nc) ? ec[(long)Y * nc + cgo[j]] : S(0);
     };
-    auto ldb = [&](int p, int m) -> C {
-        return (val[m] && p >= 0 && p < n) ? cvt<C>(b[(long)p * n + go[m]]) : C(0);
+    auto c_write = [&]() {
+#pragma unroll
+        for (int j = 0; j < MC; ++j)
+            if (t + j * NT < CX) cL[t + j * NT] = cvt<C>(rc[j]);
     };
-    auto ldr2 = [&](int p) -> C {
-        return (r2v && p >= 0 && p < n) ? cvt<C>(u[(long)p * n + r2x]) : C(0);
+    auto q_lds = [&](int k) -> C {
+        C q = C(0);
+        if (cidx[k][0] >= 0) q += cL[cidx[k][0]];
+        if (cidx[k][1] >= 0) q += cL[cidx[k][1]];
+        return cw[k] * q;
+    };
+    auto q_direct = [&](int k, int Y) -> C {
+        if (Y < 0 || Y >= nc) return C(0);
+        C q = C(0);
+        if (cidx[k][0] >= 0) q += cvt<C>(ec[(long)Y * nc + cx0 + cidx[k][0]]);
+        if (cidx[k][1] >= 0) q += cvt<C>(ec[(long)Y * nc + cx0 + cidx[k][1]]);
+        return cw[k] * q;
     };
 
-    C um2[M], um1[M], u0[M], up1[M], nu[M], b0[M], nb[M];
-    C urp1 = 0, nur = 0;
+    S ru[PD + 1][M], rb[PD + 1][M], rr2[PD + 1];
+    auto issue_u = [&](int p, int k) {
+#pragma unroll
+        for (int m = 0; m < M; ++m)
+            ru[k][m] = (!ZG && val[m] && p >= 0 && p < n) ? u[(long)p * n + go[m]] : S(0);
+        rr2[k] = (r2v && p >= 0 && p < n) ? u[(long)p * n + r2x] : S(0);
+    };
+    auto issue_b = [&](int p, int k) {
+#pragma unroll
+        for (int m = 0; m < M; ++m)
+            rb[k][m] = (val[m] && p >= 0 && p < n) ? b[(long)p * n + go[m]] : S(0);
+    };
+    auto take_u = [&](int p, const C* qh, C* dst, C& rdst) {
+#pragma unroll
+        for (int m = 0; m < M + 1; ++m) {
+            C v = cvt<C>(m < M ? ru[0][m] : rr2[0]);
+            if (PRO) {
+                C pe;
+                if ((p & 1) == 0) {
+                    pe = C(0.5) * (qprev[m] + qh[m]);
+                    qprev[m] = qh[m];
+                } else {
+                    pe = qprev[m];
+                }
+                v += pf * pe;
+            }
+            if (m < M) dst[m] = v; else rdst = v;
+        }
+    };
+    auto shift = [&]() {
+#pragma unroll
+        for (int k = 0; k < PD; ++k) {
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                ru[k][m] = ru[k + 1][m];
+                rb[k][m] = rb[k + 1][m];
+            }
+            rr2[k] = rr2[k + 1];
+        }
+    };
+
+    C um2[M], um1[M], u0[M], up1[M], b0[M];
+    C ur0 = 0, urp1 = 0;
     double nacc = 0.0;
     const int s0 = y0 - 1;
+    {
+        C qh[M + 1];
+        if (PRO) {
+            const int pf0 = s0 - 1;
+            const int yp = (pf0 & 1) == 0 ? pf0 / 2 - 1 : (pf0 - 1) / 2;
 #pragma unroll
-    for (int m = 0; m < M; ++m) {
-        um2[m] = C(0);
-        um1[m] = ldu(s0 - 1, m);
-        u0[m] = ldu(s0, m);
-        up1[m] = ldu(s0 + 1, m);
-        b0[m] = ldb(s0, m);
+            for (int k = 0; k < M + 1; ++k) qprev[k] = q_direct(k, yp);
+        }
+        C dummy;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const int p = s0 - 1 + q;
+            issue_u(p, 0);
+            if (PRO && (p & 1) == 0) {
+#pragma unroll
+                for (int k = 0; k < M + 1; ++k) qh[k] = q_direct(k, p / 2);
+            }
+            C* dst = q == 0 ? um1 : (q == 1 ? u0 : up1);
+            take_u(p, qh, dst, q == 1 ? ur0 : (q == 2 ? urp1 : dummy));
+        }
+        issue_b(s0, 0);
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            um2[m] = C(0);
+            b0[m] = cvt<C>(rb[0][m]);
+        }
+        for (int k = 0; k < PD; ++k) {
+            issue_u(s0 + 2 + k, k);
+            issue_b(s0 + 1 + k, k);
+        }
+        if (PRO) {
+            if ((s0 & 1) == 0) {
+                c_issue((s0 + 2) / 2);
+                c_write();
+            } else {
+                c_issue((s0 + 3) / 2);
+            }
+        }
     }
     if (!ZG) {
-        const C ur0 = ldr2(s0);
-        urp1 = ldr2(s0 + 1);
         const int sl = (s0 + 2) & 1;
 #pragma unroll
         for (int m = 0; m < M; ++m)
@@ -309,12 +594,9 @@ k_smooth2d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out
         __syncthreads();
         const int cur = (s + 2) & 1;
         const int rs = (s + 4) & 3;
-#pragma unroll
-        for (int m = 0; m < M; ++m) {
-            nu[m] = ldu(s + 2, m);
-            nb[m] = ldb(s + 1, m);
-        }
-        if (!ZG && t < 2) nur = ldr2(s + 2);
+        issue_u(s + 2 + PD, PD);
+        issue_b(s + 1 + PD, PD);
+        if (PRO && (s & 1) == 0) c_issue((s + 4) / 2);
         const bool pin = s >= 0 && s < n;
 #pragma unroll
         for (int m = 0; m < M; ++m) {
@@ -340,12 +622,12 @@ k_smooth2d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out
             for (int m = 0; m < M; ++m) {
                 if (!inn[m]) continue;
                 const int i = t + m * NT;
-                const C rc = R1[i];
+                const C rcc = R1[i];
                 const C fc = R1[i - 1] + R1[i + 1] + R0[i] + R2[i];
                 const C cn = R0[i - 1] + R0[i + 1] + R2[i - 1] + R2[i + 1];
-                const C v = (ZG ? C(0) : um2[m]) + sW * (c0 * rc + c1 * fc + c2 * cn);
+                const C v = (ZG ? C(0) : um2[m]) + sW * (c0 * rcc + c1 * fc + c2 * cn);
                 out[(long)p * n + go[m]] = static_cast<S>(v);
-                if (NORM) nacc += (double)rc * (double)rc;
+                if (NORM) nacc += (double)rcc * (double)rcc;
             }
         }
         if (!ZG) {
@@ -354,19 +636,25 @@ k_smooth2d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out
                 if (inr[m]) uL[cur ^ 1][t + m * NT + 1] = up1[m];
             if (t < 2) uL[cur ^ 1][r2l] = urp1;
         }
+        C qh[M + 1];
+        if (PRO && (s & 1) == 0) {
+#pragma unroll
+            for (int k = 0; k < M + 1; ++k) qh[k] = q_lds(k);
+        }
 #pragma unroll
         for (int m = 0; m < M; ++m) {
             um2[m] = um1[m];
             um1[m] = u0[m];
             u0[m] = up1[m];
-            up1[m] = nu[m];
-            b0[m] = nb[m];
+            b0[m] = cvt<C>(rb[0][m]);
         }
-        urp1 = nur;
+        if (!ZG) take_u(s + 2, qh, up1, urp1);
+        shift();
+        if (PRO && (s & 1) == 1) c_write();
     }
     if (NORM) {
-        const double sum = block_sum<NT>(nacc, red);
-        if (t == 0) partials[(long)blockIdx.y * gridDim.x + blockIdx.x] = sum;
+        const double sm = block_sum<NT>(nacc, red);
+        if (t == 0) partials[(long)blockIdx.y * gridDim.x + blockIdx.x] = sm;
     }
 }
 
@@ -376,7 +664,7 @@ k_smooth2d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out
 // computed plane by plane on the (2TXc+1) x (2TYc+1) fine window and reduced
 // in xy; the z weights (1/4, 1/2, 1/4) are accumulated in registers.
 // ---------------------------------------------------------------------------
-template <typename S, typename C, int TXc, int TYc>
+template <typename S, typename C, int TXc, int TYc, int RPD>
 __global__ void __launch_bounds__(TXc * TYc)
 k_restrict3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ bc,
              int n, int nc, int tiles_x, int tiles_y, int zchunk, int nchunks, C sA) {
@@ -427,32 +715,53 @@ k_restrict3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ b
         r2v = gx >= 0 && gx < n && gy >= 0 && gy < n;
         r2g = r2v ? gy * n + gx : 0;
     }
-    auto ldu = [&](int p, int m) -> C {
-        return (val[m] && p >= 0 && p < n) ? cvt<C>(u[p * plane + go[m]]) : C(0);
+    S ru[RPD + 1][M], rb[RPD + 1][M], rr2[RPD + 1];
+    auto issue_u = [&](int p, int k) {
+#pragma unroll
+        for (int m = 0; m < M; ++m)
+            ru[k][m] = (val[m] && p >= 0 && p < n) ? u[p * plane + go[m]] : S(0);
+        rr2[k] = (r2v && p >= 0 && p < n) ? u[p * plane + r2g] : S(0);
     };
-    auto ldb = [&](int p, int m) -> C {
-        return (val[m] && p >= 0 && p < n) ? cvt<C>(b[p * plane + go[m]]) : C(0);
+    auto issue_b = [&](int p, int k) {
+#pragma unroll
+        for (int m = 0; m < M; ++m)
+            rb[k][m] = (val[m] && p >= 0 && p < n) ? b[p * plane + go[m]] : S(0);
     };
-    auto ldr2 = [&](int p) -> C {
-        return (r2v && p >= 0 && p < n) ? cvt<C>(u[p * plane + r2g]) : C(0);
+    auto shift = [&]() {
+#pragma unroll
+        for (int k = 0; k < RPD; ++k) {
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                ru[k][m] = ru[k + 1][m];
+                rb[k][m] = rb[k + 1][m];
+            }
+            rr2[k] = rr2[k + 1];
+        }
     };
     const int cx = t % TXc, cy = t / TXc;
     const bool cval = (cx0 + cx) < nc && (cy0 + cy) < nc;
     const int cgo = (cy0 + cy) * nc + cx0 + cx;
 
-    C um1[M], u0[M], up1[M], nu[M], b0[M], nb[M];
-    C urp1 = 0, nur = 0, acc = 0;
+    C um1[M], u0[M], up1[M], b0[M];
+    C ur0 = 0, urp1 = 0, acc = 0;
     const int f0 = 2 * Z0, f1 = 2 * Z1;  // fine planes f0..f1 contribute
-#pragma unroll
-    for (int m = 0; m < M; ++m) {
-        um1[m] = ldu(f0 - 1, m);
-        u0[m] = ldu(f0, m);
-        up1[m] = ldu(f0 + 1, m);
-        b0[m] = ldb(f0, m);
-    }
     {
-        const C ur0 = ldr2(f0);
-        urp1 = ldr2(f0 + 1);
+        C dummy;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            issue_u(f0 - 1 + q, 0);
+            C* dst = q == 0 ? um1 : (q == 1 ? u0 : up1);
+#pragma unroll
+            for (int m = 0; m < M; ++m) dst[m] = cvt<C>(ru[0][m]);
+            (q == 1 ? ur0 : (q == 2 ? urp1 : dummy)) = cvt<C>(rr2[0]);
+        }
+        issue_b(f0, 0);
+#pragma unroll
+        for (int m = 0; m < M; ++m) b0[m] = cvt<C>(rb[0][m]);
+        for (int k = 0; k < RPD; ++k) {
+            issue_u(f0 + 2 + k, k);
+            issue_b(f0 + 1 + k, k);
+        }
         const int sl = f0 & 1;
 #pragma unroll
         for (int m = 0; m < M; ++m)
@@ -462,12 +771,8 @@ k_restrict3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ b
     for (int s = f0; s <= f1 + 1; ++s) {
         __syncthreads();
         const int cur = s & 1;
-#pragma unroll
-        for (int m = 0; m < M; ++m) {
-            nu[m] = ldu(s + 2, m);
-            nb[m] = ldb(s + 1, m);
-        }
-        if (t < NR2) nur = ldr2(s + 2);
+        issue_u(s + 2 + RPD, RPD);
+        issue_b(s + 1 + RPD, RPD);
         if (s <= f1) {
 #pragma unroll
             for (int m = 0; m < M; ++m) {
@@ -500,20 +805,19 @@ k_restrict3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ b
                 acc += C(0.5) * xs;
             }
         }
-        if (s + 1 <= f1 + 1) {
 #pragma unroll
-            for (int m = 0; m < M; ++m)
-                if (inr[m]) uL[cur ^ 1][ul[m]] = up1[m];
-            if (t < NR2) uL[cur ^ 1][r2l] = urp1;
-        }
+        for (int m = 0; m < M; ++m)
+            if (inr[m]) uL[cur ^ 1][ul[m]] = up1[m];
+        if (t < NR2) uL[cur ^ 1][r2l] = urp1;
 #pragma unroll
         for (int m = 0; m < M; ++m) {
             um1[m] = u0[m];
             u0[m] = up1[m];
-            up1[m] = nu[m];
-            b0[m] = nb[m];
+            up1[m] = cvt<C>(ru[0][m]);
+            b0[m] = cvt<C>(rb[0][m]);
         }
-        urp1 = nur;
+        urp1 = cvt<C>(rr2[0]);
+        shift();
     }
 }
 
@@ -521,7 +825,7 @@ k_restrict3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ b
 // 2D fused residual + full-weighting restriction: a strip of TXc coarse
 // columns (one per thread), marching over fine rows.
 // ---------------------------------------------------------------------------
-template <typename S, typename C, int TXc>
+template <typename S, typename C, int TXc, int RPD>
 __global__ void __launch_bounds__(TXc)
 k_restrict2d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ bc,
              int n, int nc, int tiles_x, int ychunk, int nchunks, C sA) {
@@ -554,30 +858,51 @@ k_restrict2d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ b
     const int r2x = (t == 0) ? fx0 - 1 : fx0 + FX;
     const int r2l = (t == 0) ? 0 : UX - 1;
     const bool r2v = t < 2 && r2x >= 0 && r2x < n;
-    auto ldu = [&](int p, int m) -> C {
-        return (val[m] && p >= 0 && p < n) ? cvt<C>(u[(long)p * n + go[m]]) : C(0);
+    S ru[RPD + 1][M], rb[RPD + 1][M], rr2[RPD + 1];
+    auto issue_u = [&](int p, int k) {
+#pragma unroll
+        for (int m = 0; m < M; ++m)
+            ru[k][m] = (val[m] && p >= 0 && p < n) ? u[(long)p * n + go[m]] : S(0);
+        rr2[k] = (r2v && p >= 0 && p < n) ? u[(long)p * n + r2x] : S(0);
     };
-    auto ldb = [&](int p, int m) -> C {
-        return (val[m] && p >= 0 && p < n) ? cvt<C>(b[(long)p * n + go[m]]) : C(0);
+    auto issue_b = [&](int p, int k) {
+#pragma unroll
+        for (int m = 0; m < M; ++m)
+            rb[k][m] = (val[m] && p >= 0 && p < n) ? b[(long)p * n + go[m]] : S(0);
     };
-    auto ldr2 = [&](int p) -> C {
-        return (r2v && p >= 0 && p < n) ? cvt<C>(u[(long)p * n + r2x]) : C(0);
+    auto shift = [&]() {
+#pragma unroll
+        for (int k = 0; k < RPD; ++k) {
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                ru[k][m] = ru[k + 1][m];
+                rb[k][m] = rb[k + 1][m];
+            }
+            rr2[k] = rr2[k + 1];
+        }
     };
     const bool cval = (cx0 + t) < nc;
 
-    C um1[M], u0[M], up1[M], nu[M], b0[M], nb[M];
-    C urp1 = 0, nur = 0, acc = 0;
+    C um1[M], u0[M], up1[M], b0[M];
+    C ur0 = 0, urp1 = 0, acc = 0;
     const int f0 = 2 * Y0, f1 = 2 * Y1;
-#pragma unroll
-    for (int m = 0; m < M; ++m) {
-        um1[m] = ldu(f0 - 1, m);
-        u0[m] = ldu(f0, m);
-        up1[m] = ldu(f0 + 1, m);
-        b0[m] = ldb(f0, m);
-    }
     {
-        const C ur0 = ldr2(f0);
-        urp1 = ldr2(f0 + 1);
+        C dummy;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            issue_u(f0 - 1 + q, 0);
+            C* dst = q == 0 ? um1 : (q == 1 ? u0 : up1);
+#pragma unroll
+            for (int m = 0; m < M; ++m) dst[m] = cvt<C>(ru[0][m]);
+            (q == 1 ? ur0 : (q == 2 ? urp1 : dummy)) = cvt<C>(rr2[0]);
+        }
+        issue_b(f0, 0);
+#pragma unroll
+        for (int m = 0; m < M; ++m) b0[m] = cvt<C>(rb[0][m]);
+        for (int k = 0; k < RPD; ++k) {
+            issue_u(f0 + 2 + k, k);
+            issue_b(f0 + 1 + k, k);
+        }
         const int sl = f0 & 1;
 #pragma unroll
         for (int m = 0; m < M; ++m)
@@ -587,12 +912,8 @@ k_restrict2d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ b
     for (int s = f0; s <= f1 + 1; ++s) {
         __syncthreads();
         const int cur = s & 1;
-#pragma unroll
-        for (int m = 0; m < M; ++m) {
-            nu[m] = ldu(s + 2, m);
-            nb[m] = ldb(s + 1, m);
-        }
-        if (t < 2) nur = ldr2(s + 2);
+        issue_u(s + 2 + RPD, RPD);
+        issue_b(s + 1 + RPD, RPD);
         if (s <= f1) {
 #pragma unroll
             for (int m = 0; m < M; ++m) {
@@ -622,20 +943,19 @@ k_restrict2d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ b
                 acc += C(0.5) * xs;
             }
         }
-        if (s + 1 <= f1 + 1) {
 #pragma unroll
-            for (int m = 0; m < M; ++m)
-                if (inr[m]) uL[cur ^ 1][t + m * NT + 1] = up1[m];
-            if (t < 2) uL[cur ^ 1][r2l] = urp1;
-        }
+        for (int m = 0; m < M; ++m)
+            if (inr[m]) uL[cur ^ 1][t + m * NT + 1] = up1[m];
+        if (t < 2) uL[cur ^ 1][r2l] = urp1;
 #pragma unroll
         for (int m = 0; m < M; ++m) {
             um1[m] = u0[m];
             u0[m] = up1[m];
-            up1[m] = nu[m];
-            b0[m] = nb[m];
+            up1[m] = cvt<C>(ru[0][m]);
+            b0[m] = cvt<C>(rb[0][m]);
         }
-        urp1 = nur;
+        urp1 = cvt<C>(rr2[0]);
+        shift();
     }
 }
 
@@ -643,22 +963,6 @@ k_restrict2d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ b
 // Linear interpolation + correction: u += pf * P ec.  One fine node per
 // thread; the coarse values (1/2^d of the traffic) come through L2.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int interp_idx(int i, int nc, int* j0, int* j1) {
-    // fine index i (grid coordinate i+1): even coordinate -> one coarse node,
-    // odd -> two; returns the count, indices clipped to the coarse interior
-    // (-1 marks a boundary node, value 0).
-    const int g = i + 1;
-    if ((g & 1) == 0) {
-        *j0 = g / 2 - 1;
-        *j1 = -1;
-        return 1;
-    }
-    const int a = (g - 1) / 2 - 1, c = (g + 1) / 2 - 1;
-    *j0 = (a >= 0 && a < nc) ? a : -1;
-    *j1 = (c >= 0 && c < nc) ? c : -1;
-    return 2;
-}
-
 template <typename S, typename C>
 __global__ void __launch_bounds__(256)
 k_prolong2d(const S* __restrict__ ec, S* __restrict__ u, int n, int nc, C pf) {
@@ -710,184 +1014,222 @@ k_prolong3d(const S* __restrict__ ec, S* __restrict__ u, int n, int nc, C pf) {
 
 // ---------------------------------------------------------------------------
 // Coarse tail: every level from nt interior nodes per direction down to 3,
-// the exact solve on the 3^d grid and back up, in one workgroup with all
-// level arrays in LDS.  Coarse levels start from a zero guess (pre-smoothing
-// is e = sW K b).
+// the exact solve on the 3^d grid and back up, in one workgroup of 1024
+// threads with all level arrays in LDS.  Coarse levels start from a zero
+// guess (pre-smoothing is e = sW K b).  Every LDS array carries a ring of
+// zeros, so stencils need no bounds checks; threads map to nodes through
+// power-of-two boxes (2D: 64 x 16 per pass, 3D: 16 x 16 x 4), so no
+// divisions are needed.
 // ---------------------------------------------------------------------------
-template <typename C>
-struct TailLevel {
-    C* e;
-    C* b;
-    C* r;
-    int n;
-    C sA, sW;
+__host__ __device__ inline int tail_levels(int nt) {
+    int L = 1;
+    for (int n = nt; n > 3; n = (n + 1) / 2 - 1) ++L;
+    return L;
+}
+
+__host__ __device__ inline long tail_padded(int d, int n) {
+    const long p = n + 2;
+    return d == 3 ? p * p * p : p * p;
+}
+
+template <int D>
+struct TailMap;
+template <>
+struct TailMap<2> {
+    // lane -> x, wave -> row
+    static __device__ __forceinline__ int x0() { return threadIdx.x & 63; }
+    static __device__ __forceinline__ int y0() { return threadIdx.x >> 6; }
+    static constexpr int YS = 16;
+};
+template <>
+struct TailMap<3> {
+    static __device__ __forceinline__ int x0() { return threadIdx.x & 15; }
+    static __device__ __forceinline__ int y0() { return (threadIdx.x >> 4) & 15; }
+    static __device__ __forceinline__ int z0() { return threadIdx.x >> 8; }
+    static constexpr int ZS = 4;
 };
 
-template <typename C>
-__device__ __forceinline__ C tget(const C* a, int d, int n, int i, int j, int k) {
-    if (i < 0 || i >= n || j < 0 || j >= n) return C(0);
-    if (d == 3) {
-        if (k < 0 || k >= n) return C(0);
-        return a[(k * n + j) * n + i];
+// calls f(i, j, k) for every node of an n-grid owned by this thread
+template <int D, typename F>
+__device__ __forceinline__ void tail_for(int n, F&& f) {
+    if (D == 2) {
+        const int i = TailMap<2>::x0();
+        if (i >= n) return;
+        for (int j = TailMap<2>::y0(); j < n; j += TailMap<2>::YS) f(i, j, 0);
+    } else {
+        const int i = TailMap<3>::x0(), j = TailMap<3>::y0();
+        if (i >= n || j >= n) return;
+        for (int k = TailMap<3>::z0(); k < n; k += TailMap<3>::ZS) f(i, j, k);
     }
-    return a[j * n + i];
 }
 
-template <typename C>
-__device__ __forceinline__ void tdecode(int p, int d, int n, int* i, int* j, int* k) {
-    *i = p % n;
-    *j = (p / n) % n;
-    *k = d == 3 ? p / (n * n) : 0;
-}
-
-template <typename C>
-__device__ __forceinline__ C tlap(const C* a, int d, int n, int i, int j, int k) {
-    C s = C(2 * d) * tget(a, d, n, i, j, k) - tget(a, d, n, i - 1, j, k) -
-          tget(a, d, n, i + 1, j, k) - tget(a, d, n, i, j - 1, k) - tget(a, d, n, i, j + 1, k);
-    if (d == 3) s -= tget(a, d, n, i, j, k - 1) + tget(a, d, n, i, j, k + 1);
-    return s;
-}
-
-template <typename C>
-__device__ __forceinline__ C tspai(const C* a, int d, int n, int i, int j, int k, C c0,
-                                   C c1, C c2) {
-    C f = tget(a, d, n, i - 1, j, k) + tget(a, d, n, i + 1, j, k) +
-          tget(a, d, n, i, j - 1, k) + tget(a, d, n, i, j + 1, k);
-    C v = c0 * tget(a, d, n, i, j, k);
-    if (d == 3) {
-        f += tget(a, d, n, i, j, k - 1) + tget(a, d, n, i, j, k + 1);
-        return v + c1 * f;
-    }
-    const C cn = tget(a, d, n, i - 1, j - 1, k) + tget(a, d, n, i + 1, j - 1, k) +
-                 tget(a, d, n, i - 1, j + 1, k) + tget(a, d, n, i + 1, j + 1, k);
-    return v + c1 * f + c2 * cn;
-}
-
-template <typename S, typename C>
+template <typename S, typename C, int D>
 __global__ void __launch_bounds__(1024)
-k_tail(const S* __restrict__ bt, S* __restrict__ et, int d, int nt, C c0, C c1, C c2,
+k_tail(const S* __restrict__ bt, S* __restrict__ et, int nt, C c0, C c1, C c2,
        const double* __restrict__ ginv, int scaled, int Ntop) {
     extern __shared__ unsigned char smem_raw[];
     C* sm = reinterpret_cast<C*>(smem_raw);
-    constexpr int NT = 1024;
     const int t = threadIdx.x;
-    TailLevel<C> lv[8];
-    int L = 0;
-    {
-        int n = nt, N = Ntop;
+    const int L = tail_levels(nt);
+    // level l: n_l, pitch P_l = n_l + 2, arrays e, b, r of (P_l)^D each
+    long tot = 0;
+    for (int l = 0, n = nt; l < L; ++l, n = (n + 1) / 2 - 1) tot += 3 * tail_padded(D, n);
+    for (long q = t; q < tot; q += 1024) sm[q] = C(0);
+    auto base = [&](int l) -> C* {
         C* p = sm;
-        while (true) {
-            long pts = 1;
-            for (int a = 0; a < d; ++a) pts *= n;
-            lv[L].e = p;
-            lv[L].b = p + pts;
-            lv[L].r = p + 2 * pts;
-            lv[L].n = n;
-            if (scaled) {
-                lv[L].sA = C(1);
-                lv[L].sW = C(1);
-            } else {
-                lv[L].sA = C((double)N * (double)N);
-                lv[L].sW = C(1.0 / ((double)N * (double)N));
-            }
-            p += 3 * pts;
-            ++L;
-            if (n == 3) break;
-            n = (n + 1) / 2 - 1;
-            N /= 2;
-        }
-    }
-    const C pf = scaled ? C(4) : C(1);
-    auto npts = [&](int n) { return d == 3 ? n * n * n : n * n; };
+        for (int k = 0, n = nt; k < l; ++k, n = (n + 1) / 2 - 1) p += 3 * tail_padded(D, n);
+        return p;
+    };
+    auto nl = [&](int l) {
+        int n = nt;
+        for (int k = 0; k < l; ++k) n = (n + 1) / 2 - 1;
+        return n;
+    };
+    __syncthreads();
     {
-        const long off = (long)blockIdx.x * npts(nt);
-        for (int p = t; p < npts(nt); p += NT) lv[0].b[p] = cvt<C>(bt[off + p]);
+        const long off = (long)blockIdx.x * (D == 3 ? (long)nt * nt * nt : (long)nt * nt);
+        C* B = base(0) + tail_padded(D, nt);
+        const int P = nt + 2;
+        tail_for<D>(nt, [&](int i, int j, int k) {
+            const long g = D == 3 ? ((long)k * nt + j) * nt + i : (long)j * nt + i;
+            B[D == 3 ? ((k + 1) * P + j + 1) * P + i + 1 : (j + 1) * P + i + 1] = cvt<C>(bt[off + g]);
+        });
     }
     __syncthreads();
+    auto level_consts = [&](int l, C* sA, C* sW) {
+        if (scaled) {
+            *sA = C(1);
+            *sW = C(1);
+        } else {
+            const double N = (double)(Ntop >> l);
+            *sA = C(N * N);
+            *sW = C(1.0 / (N * N));
+        }
+    };
+    const C pf = scaled ? C(4) : C(1);
+    // stencils on a padded array at flat index q with pitches 1, P, P^2
+    auto lap = [&](const C* a, long q, int P) -> C {
+        C s = C(2 * D) * a[q] - a[q - 1] - a[q + 1] - a[q - P] - a[q + P];
+        if (D == 3) s -= a[q - (long)P * P] + a[q + (long)P * P];
+        return s;
+    };
+    auto spai = [&](const C* a, long q, int P) -> C {
+        C f = a[q - 1] + a[q + 1] + a[q - P] + a[q + P];
+        if (D == 3) {
+            f += a[q - (long)P * P] + a[q + (long)P * P];
+            return c0 * a[q] + c1 * f;
+        }
+        const C cn = a[q - P - 1] + a[q - P + 1] + a[q + P - 1] + a[q + P + 1];
+        return c0 * a[q] + c1 * f + c2 * cn;
+    };
+    auto pidx = [&](int i, int j, int k, int P) -> long {
+        return D == 3 ? ((long)(k + 1) * P + j + 1) * P + i + 1 : (long)(j + 1) * P + i + 1;
+    };
     for (int l = 0; l + 1 < L; ++l) {
-        TailLevel<C>& A = lv[l];
-        TailLevel<C>& B = lv[l + 1];
-        const int n = A.n, m = npts(n);
-        for (int p = t; p < m; p += NT) {
-            int i, j, k;
-            tdecode<C>(p, d, n, &i, &j, &k);
-            A.e[p] = A.sW * tspai(A.b, d, n, i, j, k, c0, c1, c2);
-        }
+        const int n = nl(l), P = n + 2, nc = nl(l + 1), Pc = nc + 2;
+        C* E = base(l);
+        C* B = E + tail_padded(D, n);
+        C* R = B + tail_padded(D, n);
+        C* Bc = base(l + 1) + tail_padded(D, nc);
+        C sA, sW;
+        level_consts(l, &sA, &sW);
+        tail_for<D>(n, [&](int i, int j, int k) {
+            const long q = pidx(i, j, k, P);
+            E[q] = sW * spai(B, q, P);
+        });
         __syncthreads();
-        for (int p = t; p < m; p += NT) {
-            int i, j, k;
-            tdecode<C>(p, d, n, &i, &j, &k);
-            A.r[p] = A.b[p] - A.sA * tlap(A.e, d, n, i, j, k);
-        }
+        tail_for<D>(n, [&](int i, int j, int k) {
+            const long q = pidx(i, j, k, P);
+            R[q] = B[q] - sA * lap(E, q, P);
+        });
         __syncthreads();
-        const int nc = B.n, mc = npts(nc);
-        for (int p = t; p < mc; p += NT) {
-            int i, j, k;
-            tdecode<C>(p, d, nc, &i, &j, &k);
-            const int fi = 2 * i + 1, fj = 2 * j + 1, fk = 2 * k + 1;
-            C s = C(0);
-            const int kl = d == 3 ? -1 : 0, kh = d == 3 ? 1 : 0;
-            for (int oz = kl; oz <= kh; ++oz)
-                for (int oy = -1; oy <= 1; ++oy)
-                    for (int ox = -1; ox <= 1; ++ox) {
-                        C w = (ox == 0 ? C(0.5) : C(0.25)) * (oy == 0 ? C(0.5) : C(0.25));
-                        if (d == 3) w *= (oz == 0 ? C(0.5) : C(0.25));
-                        s += w * tget(A.r, d, n, fi + ox, fj + oy, d == 3 ? fk + oz : 0);
-                    }
-            B.b[p] = s;
-        }
+        tail_for<D>(nc, [&](int i, int j, int k) {
+            const long q = pidx(2 * i + 1, 2 * j + 1, D == 3 ? 2 * k + 1 : 0, P);
+            C s;
+            if (D == 2) {
+                s = C(0.25) * R[q] + C(0.125) * (R[q - 1] + R[q + 1] + R[q - P] + R[q + P]) +
+                    C(0.0625) * (R[q - P - 1] + R[q - P + 1] + R[q + P - 1] + R[q + P + 1]);
+            } else {
+                const long P2 = (long)P * P;
+                s = C(0);
+                for (int oz = -1; oz <= 1; ++oz) {
+                    const long qz = q + oz * P2;
+                    const C pl = C(0.25) * R[qz] +
+                                 C(0.125) * (R[qz - 1] + R[qz + 1] + R[qz - P] + R[qz + P]) +
+                                 C(0.0625) * (R[qz - P - 1] + R[qz - P + 1] + R[qz + P - 1] +
+                                              R[qz + P + 1]);
+                    s += (oz == 0 ? C(0.5) : C(0.25)) * pl;
+                }
+            }
+            Bc[pidx(i, j, k, Pc)] = s;
+        });
         __syncthreads();
     }
     {
-        TailLevel<C>& Z = lv[L - 1];
-        const int m = npts(3);
-        for (int p = t; p < m; p += NT) {
+        const int m = D == 2 ? 9 : 27, P = 5;
+        C* E = base(L - 1);
+        C* B = E + tail_padded(D, 3);
+        if (t < m) {
+            const int i = t % 3, j = (t / 3) % 3, k = t / 9;
             double s = 0.0;
-            for (int q = 0; q < m; ++q) s += ginv[p * m + q] * (double)Z.b[q];
-            Z.e[p] = C(s);
+            for (int q = 0; q < m; ++q) {
+                const int qi = q % 3, qj = (q / 3) % 3, qk = q / 9;
+                s += ginv[t * m + q] * (double)B[pidx(qi, qj, qk, P)];
+            }
+            E[pidx(i, j, k, P)] = C(s);
         }
         __syncthreads();
     }
     for (int l = L - 2; l >= 0; --l) {
-        TailLevel<C>& A = lv[l];
-        TailLevel<C>& B = lv[l + 1];
-        const int n = A.n, m = npts(n), nc = B.n;
-        for (int p = t; p < m; p += NT) {
-            int i, j, k;
-            tdecode<C>(p, d, n, &i, &j, &k);
-            int xi[2], yj[2], zk[2] = {0, -1};
-            const int ni = interp_idx(i, nc, &xi[0], &xi[1]);
-            const int nj = interp_idx(j, nc, &yj[0], &yj[1]);
-            int nk = 1;
-            if (d == 3) nk = interp_idx(k, nc, &zk[0], &zk[1]);
-            C w = (ni == 1 ? C(1) : C(0.5)) * (nj == 1 ? C(1) : C(0.5));
-            if (d == 3) w *= (nk == 1 ? C(1) : C(0.5));
-            C s = C(0);
-            for (int c = 0; c < nk; ++c)
-                for (int bq = 0; bq < nj; ++bq)
-                    for (int a = 0; a < ni; ++a)
-                        if (xi[a] >= 0 && yj[bq] >= 0 && zk[c] >= 0)
-                            s += B.e[d == 3 ? (zk[c] * nc + yj[bq]) * nc + xi[a]
-                                            : yj[bq] * nc + xi[a]];
-            A.e[p] += pf * w * s;
-        }
+        const int n = nl(l), P = n + 2, nc = nl(l + 1), Pc = nc + 2;
+        C* E = base(l);
+        C* B = E + tail_padded(D, n);
+        C* R = B + tail_padded(D, n);
+        const C* Ec = base(l + 1);
+        C sA, sW;
+        level_consts(l, &sA, &sW);
+        // linear interpolation: fine node i (grid coordinate i+1) takes the
+        // coarse node (i+1)/2 if even, the mean of (i/2, i/2+1) if odd; in
+        // padded coarse coordinates the coarse node G sits at index G, and
+        // the ring supplies the zero boundary values
+        tail_for<D>(n, [&](int i, int j, int k) {
+            const int gi = i + 1, gj = j + 1, gk = k + 1;
+            const int ia = gi >> 1, ib = (gi + 1) >> 1;
+            const int ja = gj >> 1, jb = (gj + 1) >> 1;
+            C v;
+            if (D == 2) {
+                v = C(0.25) * (Ec[ja * Pc + ia] + Ec[ja * Pc + ib] + Ec[jb * Pc + ia] +
+                               Ec[jb * Pc + ib]);
+            } else {
+                const int ka = gk >> 1, kb = (gk + 1) >> 1;
+                const long P2 = (long)Pc * Pc;
+                v = C(0.125) * (Ec[ka * P2 + ja * Pc + ia] + Ec[ka * P2 + ja * Pc + ib] +
+                                Ec[ka * P2 + jb * Pc + ia] + Ec[ka * P2 + jb * Pc + ib] +
+                                Ec[kb * P2 + ja * Pc + ia] + Ec[kb * P2 + ja * Pc + ib] +
+                                Ec[kb * P2 + jb * Pc + ia] + Ec[kb * P2 + jb * Pc + ib]);
+            }
+            E[pidx(i, j, k, P)] += pf * v;
+        });
         __syncthreads();
-        for (int p = t; p < m; p += NT) {
-            int i, j, k;
-            tdecode<C>(p, d, n, &i, &j, &k);
-            A.r[p] = A.b[p] - A.sA * tlap(A.e, d, n, i, j, k);
-        }
+        tail_for<D>(n, [&](int i, int j, int k) {
+            const long q = pidx(i, j, k, P);
+            R[q] = B[q] - sA * lap(E, q, P);
+        });
         __syncthreads();
-        for (int p = t; p < m; p += NT) {
-            int i, j, k;
-            tdecode<C>(p, d, n, &i, &j, &k);
-            A.e[p] += A.sW * tspai(A.r, d, n, i, j, k, c0, c1, c2);
-        }
+        tail_for<D>(n, [&](int i, int j, int k) {
+            const long q = pidx(i, j, k, P);
+            E[q] += sW * spai(R, q, P);
+        });
         __syncthreads();
     }
     {
-        const long off = (long)blockIdx.x * npts(nt);
-        for (int p = t; p < npts(nt); p += NT) et[off + p] = static_cast<S>(lv[0].e[p]);
+        const long off = (long)blockIdx.x * (D == 3 ? (long)nt * nt * nt : (long)nt * nt);
+        const C* E = base(0);
+        const int P = nt + 2;
+        tail_for<D>(nt, [&](int i, int j, int k) {
+            const long g = D == 3 ? ((long)k * nt + j) * nt + i : (long)j * nt + i;
+            et[off + g] = static_cast<S>(E[pidx(i, j, k, P)]);
+        });
     }
 }
 
@@ -924,14 +1266,13 @@ __device__ __forceinline__ double ir_scale(const double* maxprev) {
     return ldexp(1.0, -e);  // s m in [0.5, 1)
 }
 
-template <typename S, int TX, int TY>
-__global__ void __launch_bounds__(TX * TY)
+template <typename S, int TX, int TY, int NT, int IPD>
+__global__ void __launch_bounds__(NT)
 k_ir3d(const double* __restrict__ u, double* __restrict__ unew, const S* __restrict__ e,
        const double* __restrict__ b, S* __restrict__ rlo, int n, int tiles_x, int tiles_y,
        int zchunk, int nchunks, double inv_h2, double sigma0, int k,
        double* __restrict__ scales, const double* __restrict__ maxprev,
        double* __restrict__ psum, double* __restrict__ pmax) {
-    constexpr int NT = TX * TY;
     constexpr int RX = TX + 2, RY = TY + 2, NR = RX * RY;
     constexpr int M = (NR + NT - 1) / NT;
     __shared__ double uL[2][NR];
@@ -965,27 +1306,61 @@ k_ir3d(const double* __restrict__ u, double* __restrict__ unew, const S* __restr
         inn[m] = val[m] && lx >= 1 && lx <= TX && ly >= 1 && ly <= TY;
         go[m] = val[m] ? gy * n + gx : 0;
     }
-    auto ldU = [&](int p, int m) -> double {
-        if (!val[m] || p < 0 || p >= n) return 0.0;
-        const long g = p * plane + go[m];
-        double v = u[g];
-        if (e && k > 0) v += escale * (double)e[g];
-        return v;
-    };
-    double um1[M], u0[M], up1[M], nu[M];
-    double acc = 0.0, mx = 0.0;
+    // raw prefetch: ru/re[k] = plane s+2+k of u and e, rb[k] = b plane s+1+k
+    const bool hase = e != nullptr && k > 0;
+    double ru[IPD + 1][M], rb[IPD + 1][M];
+    S re[IPD + 1][M];
+    auto issue = [&](int p, int q) {
 #pragma unroll
-    for (int m = 0; m < M; ++m) {
-        um1[m] = ldU(z0 - 1, m);
-        u0[m] = ldU(z0, m);
-        up1[m] = ldU(z0 + 1, m);
-        if (inr[m]) uL[z0 & 1][t + m * NT] = u0[m];
+        for (int m = 0; m < M; ++m) {
+            const bool ok = val[m] && p >= 0 && p < n;
+            const long g = p * plane + go[m];
+            ru[q][m] = ok ? u[g] : 0.0;
+            re[q][m] = (ok && hase) ? e[g] : S(0);
+        }
+    };
+    auto issue_b = [&](int p, int q) {
+#pragma unroll
+        for (int m = 0; m < M; ++m)
+            rb[q][m] = (inn[m] && p >= 0 && p < n) ? b[p * plane + go[m]] : 0.0;
+    };
+    auto take = [&](double* dst) {
+#pragma unroll
+        for (int m = 0; m < M; ++m) dst[m] = ru[0][m] + escale * (double)re[0][m];
+    };
+    auto shift = [&]() {
+#pragma unroll
+        for (int q = 0; q < IPD; ++q)
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                ru[q][m] = ru[q + 1][m];
+                re[q][m] = re[q + 1][m];
+                rb[q][m] = rb[q + 1][m];
+            }
+    };
+    double um1[M], u0[M], up1[M], b0[M];
+    double acc = 0.0, mx = 0.0;
+    issue(z0 - 1, 0);
+    take(um1);
+    issue(z0, 0);
+    take(u0);
+    issue(z0 + 1, 0);
+    take(up1);
+    issue_b(z0, 0);
+#pragma unroll
+    for (int m = 0; m < M; ++m) b0[m] = rb[0][m];
+    for (int q = 0; q < IPD; ++q) {
+        issue(z0 + 2 + q, q);
+        issue_b(z0 + 1 + q, q);
     }
+#pragma unroll
+    for (int m = 0; m < M; ++m)
+        if (inr[m]) uL[z0 & 1][t + m * NT] = u0[m];
     for (int s = z0; s < z1; ++s) {
         __syncthreads();
         const int cur = s & 1;
-#pragma unroll
-        for (int m = 0; m < M; ++m) nu[m] = ldU(s + 2, m);
+        issue(s + 2 + IPD, IPD);
+        issue_b(s + 1 + IPD, IPD);
         const double* U = uL[cur];
 #pragma unroll
         for (int m = 0; m < M; ++m) {
@@ -994,7 +1369,7 @@ k_ir3d(const double* __restrict__ u, double* __restrict__ unew, const S* __restr
             const long g = s * plane + go[m];
             const double lap = 6.0 * u0[m] - U[q - 1] - U[q + 1] - U[q - RX] - U[q + RX] -
                                um1[m] - up1[m];
-            const double r = b[g] - inv_h2 * lap;
+            const double r = b0[m] - inv_h2 * lap;
             unew[g] = u0[m];
             rlo[g] = static_cast<S>(s_new * r);
             acc += r * r;
@@ -1007,8 +1382,10 @@ k_ir3d(const double* __restrict__ u, double* __restrict__ unew, const S* __restr
         for (int m = 0; m < M; ++m) {
             um1[m] = u0[m];
             u0[m] = up1[m];
-            up1[m] = nu[m];
+            b0[m] = rb[0][m];
         }
+        take(up1);
+        shift();
     }
     const double ts = block_sum<NT>(acc, red);
     __syncthreads();
@@ -1020,7 +1397,7 @@ k_ir3d(const double* __restrict__ u, double* __restrict__ unew, const S* __restr
     }
 }
 
-template <typename S, int TX>
+template <typename S, int TX, int IPD>
 __global__ void __launch_bounds__(TX)
 k_ir2d(const double* __restrict__ u, double* __restrict__ unew, const S* __restrict__ e,
        const double* __restrict__ b, S* __restrict__ rlo, int n, int tiles_x, int ychunk,
@@ -1057,27 +1434,60 @@ k_ir2d(const double* __restrict__ u, double* __restrict__ unew, const S* __restr
         inn[m] = val[m] && i >= 1 && i <= TX;
         go[m] = val[m] ? gx : 0;
     }
-    auto ldU = [&](int p, int m) -> double {
-        if (!val[m] || p < 0 || p >= n) return 0.0;
-        const long g = (long)p * n + go[m];
-        double v = u[g];
-        if (e && k > 0) v += escale * (double)e[g];
-        return v;
-    };
-    double um1[M], u0[M], up1[M], nu[M];
-    double acc = 0.0, mx = 0.0;
+    const bool hase = e != nullptr && k > 0;
+    double ru[IPD + 1][M], rb[IPD + 1][M];
+    S re[IPD + 1][M];
+    auto issue = [&](int p, int q) {
 #pragma unroll
-    for (int m = 0; m < M; ++m) {
-        um1[m] = ldU(y0 - 1, m);
-        u0[m] = ldU(y0, m);
-        up1[m] = ldU(y0 + 1, m);
-        if (inr[m]) uL[y0 & 1][t + m * NT] = u0[m];
+        for (int m = 0; m < M; ++m) {
+            const bool ok = val[m] && p >= 0 && p < n;
+            const long g = (long)p * n + go[m];
+            ru[q][m] = ok ? u[g] : 0.0;
+            re[q][m] = (ok && hase) ? e[g] : S(0);
+        }
+    };
+    auto issue_b = [&](int p, int q) {
+#pragma unroll
+        for (int m = 0; m < M; ++m)
+            rb[q][m] = (inn[m] && p >= 0 && p < n) ? b[(long)p * n + go[m]] : 0.0;
+    };
+    auto take = [&](double* dst) {
+#pragma unroll
+        for (int m = 0; m < M; ++m) dst[m] = ru[0][m] + escale * (double)re[0][m];
+    };
+    auto shift = [&]() {
+#pragma unroll
+        for (int q = 0; q < IPD; ++q)
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                ru[q][m] = ru[q + 1][m];
+                re[q][m] = re[q + 1][m];
+                rb[q][m] = rb[q + 1][m];
+            }
+    };
+    double um1[M], u0[M], up1[M], b0[M];
+    double acc = 0.0, mx = 0.0;
+    issue(y0 - 1, 0);
+    take(um1);
+    issue(y0, 0);
+    take(u0);
+    issue(y0 + 1, 0);
+    take(up1);
+    issue_b(y0, 0);
+#pragma unroll
+    for (int m = 0; m < M; ++m) b0[m] = rb[0][m];
+    for (int q = 0; q < IPD; ++q) {
+        issue(y0 + 2 + q, q);
+        issue_b(y0 + 1 + q, q);
     }
+#pragma unroll
+    for (int m = 0; m < M; ++m)
+        if (inr[m]) uL[y0 & 1][t + m * NT] = u0[m];
     for (int s = y0; s < y1; ++s) {
         __syncthreads();
         const int cur = s & 1;
-#pragma unroll
-        for (int m = 0; m < M; ++m) nu[m] = ldU(s + 2, m);
+        issue(s + 2 + IPD, IPD);
+        issue_b(s + 1 + IPD, IPD);
         const double* U = uL[cur];
 #pragma unroll
         for (int m = 0; m < M; ++m) {
@@ -1085,7 +1495,7 @@ k_ir2d(const double* __restrict__ u, double* __restrict__ unew, const S* __restr
             const int q = t + m * NT;
             const long g = (long)s * n + go[m];
             const double lap = 4.0 * u0[m] - U[q - 1] - U[q + 1] - um1[m] - up1[m];
-            const double r = b[g] - inv_h2 * lap;
+            const double r = b0[m] - inv_h2 * lap;
             unew[g] = u0[m];
             rlo[g] = static_cast<S>(s_new * r);
             acc += r * r;
@@ -1098,8 +1508,10 @@ k_ir2d(const double* __restrict__ u, double* __restrict__ unew, const S* __restr
         for (int m = 0; m < M; ++m) {
             um1[m] = u0[m];
             u0[m] = up1[m];
-            up1[m] = nu[m];
+            b0[m] = rb[0][m];
         }
+        take(up1);
+        shift();
     }
     const double ts = block_sum<NT>(acc, red);
     __syncthreads();
@@ -1170,11 +1582,20 @@ inline int pick_chunk(int n, int tiles, int want, int minc) {
 
 constexpr int S3_TX = 64, S3_TY = 16, S3_NT = 256;
 constexpr int S2_TX = 256, S2_NT = 256;
+constexpr int S_PD = 1;
 constexpr int R3_TX = 32, R3_TY = 8;
 constexpr int R2_TX = 256;
-constexpr int I3_TX = 64, I3_TY = 4;
+constexpr int I3_TX = 64, I3_TY = 16, I3_NT = 256;
 constexpr int I2_TX = 256;
 constexpr int kWantBlocks = 1024;
+
+// chunk length along the marching direction: long chunks on large grids
+// (fewer halo planes re-read), one plane per workgroup on small grids, where
+// the sweep is latency bound
+inline int march_chunk(int n, int tiles, long pts, int want, int minc_large) {
+    const int minc = pts >= (1L << 22) ? minc_large : 1;
+    return pick_chunk(n, tiles, want, minc);
+}
 
 template <typename S, typename C>
 hipError_t smooth_impl(bool zg, bool norm, const Sweep& s, hipStream_t st, int* nparts) {
@@ -1182,35 +1603,44 @@ hipError_t smooth_impl(bool zg, bool norm, const Sweep& s, hipStream_t st, int* 
     const S* u = static_cast<const S*>(s.u);
     const S* b = static_cast<const S*>(s.b);
     S* out = static_cast<S*>(s.out);
+    const S* ec = static_cast<const S*>(s.ec);
+    const bool pro = ec != nullptr;
+    const int nc = (n + 1) / 2 - 1;
     const C sA = C(s.sA), sW = C(s.sW), c0 = C(s.c[0]), c1 = C(s.c[1]), c2 = C(s.c[2]);
+    const C pf = C(s.pf);
+    if (zg && (norm || pro)) return hipErrorInvalidValue;
+    if (norm && pro) return hipErrorInvalidValue;
     if (s.d == 3) {
         const int tx = cdiv(n, S3_TX), ty = cdiv(n, S3_TY);
-        const int zc = pick_chunk(n, tx * ty, kWantBlocks, 8);
+        const int zc = march_chunk(n, tx * ty, (long)n * n * n, kWantBlocks, 8);
         const int nch = cdiv(n, zc);
         dim3 grid(tx * ty * nch, s.batch);
         if (nparts) *nparts = grid.x * grid.y;
         if (norm && (long)grid.x * grid.y > s.partials_cap) return hipErrorInvalidValue;
-#define L3(ZG, NM)                                                                  \
-    hipLaunchKernelGGL((k_smooth3d<S, C, S3_TX, S3_TY, S3_NT, ZG, NM>), grid,      \
-                       dim3(S3_NT), 0, st, u, b, out, n, tx, ty, zc, nch, sA, sW, c0, \
-                       c1, s.partials)
-        if (zg) L3(true, false);
-        else if (norm) L3(false, true);
-        else L3(false, false);
+#define L3(ZG, NM, PR)                                                                  \
+    hipLaunchKernelGGL((k_smooth3d<S, C, S3_TX, S3_TY, S3_NT, S_PD, ZG, NM, PR>), grid,\
+                       dim3(S3_NT), 0, st, u, b, out, n, tx, ty, zc, nch, sA, sW, c0,   \
+                       c1, s.partials, ec, nc, pf)
+        if (zg) L3(true, false, false);
+        else if (norm) L3(false, true, false);
+        else if (pro) L3(false, false, true);
+        else L3(false, false, false);
 #undef L3
     } else {
         const int tx = cdiv(n, S2_TX);
-        const int yc = pick_chunk(n, tx, kWantBlocks, 16);
+        const int yc = march_chunk(n, tx, (long)n * n, kWantBlocks, 16);
         const int nch = cdiv(n, yc);
         dim3 grid(tx * nch, s.batch);
         if (nparts) *nparts = grid.x * grid.y;
         if (norm && (long)grid.x * grid.y > s.partials_cap) return hipErrorInvalidValue;
-#define L2(ZG, NM)                                                                  \
-    hipLaunchKernelGGL((k_smooth2d<S, C, S2_TX, S2_NT, ZG, NM>), grid, dim3(S2_NT), \
-                       0, st, u, b, out, n, tx, yc, nch, sA, sW, c0, c1, c2, s.partials)
-        if (zg) L2(true, false);
-        else if (norm) L2(false, true);
-        else L2(false, false);
+#define L2(ZG, NM, PR)                                                                  \
+    hipLaunchKernelGGL((k_smooth2d<S, C, S2_TX, S2_NT, S_PD, ZG, NM, PR>), grid, dim3(S2_NT),\
+                       0, st, u, b, out, n, tx, yc, nch, sA, sW, c0, c1, c2, s.partials, \
+                       ec, nc, pf)
+        if (zg) L2(true, false, false);
+        else if (norm) L2(false, true, false);
+        else if (pro) L2(false, false, true);
+        else L2(false, false, false);
 #undef L2
     }
     return hipGetLastError();
@@ -1225,17 +1655,17 @@ hipError_t restrict_impl(const Sweep& s, hipStream_t st) {
     const C sA = C(s.sA);
     if (s.d == 3) {
         const int tx = cdiv(nc, R3_TX), ty = cdiv(nc, R3_TY);
-        const int zc = pick_chunk(nc, tx * ty, kWantBlocks, 4);
+        const int zc = march_chunk(nc, tx * ty, (long)n * n * n, kWantBlocks, 4);
         const int nch = cdiv(nc, zc);
         dim3 grid(tx * ty * nch, s.batch);
-        hipLaunchKernelGGL((k_restrict3d<S, C, R3_TX, R3_TY>), grid, dim3(R3_TX * R3_TY), 0,
+        hipLaunchKernelGGL((k_restrict3d<S, C, R3_TX, R3_TY, S_PD>), grid, dim3(R3_TX * R3_TY), 0,
                            st, u, b, bc, n, nc, tx, ty, zc, nch, sA);
     } else {
         const int tx = cdiv(nc, R2_TX);
-        const int yc = pick_chunk(nc, tx, kWantBlocks, 8);
+        const int yc = march_chunk(nc, tx, (long)n * n, kWantBlocks, 8);
         const int nch = cdiv(nc, yc);
         dim3 grid(tx * nch, s.batch);
-        hipLaunchKernelGGL((k_restrict2d<S, C, R2_TX>), grid, dim3(R2_TX), 0, st, u, b, bc,
+        hipLaunchKernelGGL((k_restrict2d<S, C, R2_TX, S_PD>), grid, dim3(R2_TX), 0, st, u, b, bc,
                            n, nc, tx, yc, nch, sA);
     }
     return hipGetLastError();
@@ -1256,21 +1686,29 @@ hipError_t prolong_impl(int d, int n, int batch, const void* ec, void* u, double
     return hipGetLastError();
 }
 
-template <typename S, typename C>
-hipError_t tail_impl(const Tail& t, hipStream_t st) {
-    const size_t lds = tail_lds_bytes(sizeof(C) == 8 ? P64 : P32, t.d, t.nt);
+template <typename S, typename C, int D>
+hipError_t tail_impl_d(const Tail& t, size_t lds, hipStream_t st) {
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_tail<S, C>,
+        hipError_t e = hipFuncSetAttribute((const void*)k_tail<S, C, D>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize,
                                            160 * 1024);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    hipLaunchKernelGGL((k_tail<S, C>), dim3(t.batch), dim3(1024), lds, st,
-                       static_cast<const S*>(t.b), static_cast<S*>(t.e), t.d, t.nt,
-                       C(t.c[0]), C(t.c[1]), C(t.c[2]), t.ginv, t.scaled ? 1 : 0, t.N_top);
+    hipLaunchKernelGGL((k_tail<S, C, D>), dim3(t.batch), dim3(1024), lds, st,
+                       static_cast<const S*>(t.b), static_cast<S*>(t.e), t.nt, C(t.c[0]),
+                       C(t.c[1]), C(t.c[2]), t.ginv, t.scaled ? 1 : 0, t.N_top);
     return hipGetLastError();
+}
+
+template <typename S, typename C>
+hipError_t tail_impl(const Tail& t, hipStream_t st) {
+    const size_t lds = tail_lds_bytes(sizeof(C) == 8 ? P64 : P32, t.d, t.nt);
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    // the thread boxes cover at most 64 (2D) or 16 (3D) nodes per direction
+    if ((t.d == 2 && t.nt > 63) || (t.d == 3 && t.nt > 15)) return hipErrorInvalidValue;
+    return t.d == 3 ? tail_impl_d<S, C, 3>(t, lds, st) : tail_impl_d<S, C, 2>(t, lds, st);
 }
 
 template <typename S>
@@ -1280,22 +1718,22 @@ hipError_t ir_impl(const IRStep& s, hipStream_t st, int* nparts) {
     S* rlo = static_cast<S*>(s.r_lo);
     if (s.d == 3) {
         const int tx = cdiv(n, I3_TX), ty = cdiv(n, I3_TY);
-        const int zc = pick_chunk(n, tx * ty, kWantBlocks, 8);
+        const int zc = march_chunk(n, tx * ty, (long)n * n * n, kWantBlocks, 8);
         const int nch = cdiv(n, zc);
         dim3 grid(tx * ty * nch, s.batch);
         if (nparts) *nparts = grid.x * grid.y;
         if ((long)grid.x * grid.y > s.partials_cap) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((k_ir3d<S, I3_TX, I3_TY>), grid, dim3(I3_TX * I3_TY), 0, st, s.u,
+        hipLaunchKernelGGL((k_ir3d<S, I3_TX, I3_TY, I3_NT, S_PD>), grid, dim3(I3_NT), 0, st, s.u,
                            s.unew, e, s.b, rlo, n, tx, ty, zc, nch, s.inv_h2, s.sigma0, s.k,
                            s.scales, s.maxprev, s.psum, s.pmax);
     } else {
         const int tx = cdiv(n, I2_TX);
-        const int yc = pick_chunk(n, tx, kWantBlocks, 16);
+        const int yc = march_chunk(n, tx, (long)n * n, kWantBlocks, 16);
         const int nch = cdiv(n, yc);
         dim3 grid(tx * nch, s.batch);
         if (nparts) *nparts = grid.x * grid.y;
         if ((long)grid.x * grid.y > s.partials_cap) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((k_ir2d<S, I2_TX>), grid, dim3(I2_TX), 0, st, s.u, s.unew, e, s.b,
+        hipLaunchKernelGGL((k_ir2d<S, I2_TX, S_PD>), grid, dim3(I2_TX), 0, st, s.u, s.unew, e, s.b,
                            rlo, n, tx, yc, nch, s.inv_h2, s.sigma0, s.k, s.scales, s.maxprev,
                            s.psum, s.pmax);
     }
@@ -1305,14 +1743,12 @@ hipError_t ir_impl(const IRStep& s, hipStream_t st, int* nparts) {
 }  // namespace
 
 size_t tail_lds_bytes(Prec p, int d, int nt) {
-    long pts = 0;
+    long tot = 0;
     for (int n = nt;; n = (n + 1) / 2 - 1) {
-        long q = 1;
-        for (int a = 0; a < d; ++a) q *= n;
-        pts += q;
+        tot += 3 * tail_padded(d, n);
         if (n <= 3) break;
     }
-    return (size_t)(3 * pts) * (p == P64 ? 8 : 4);
+    return (size_t)tot * (p == P64 ? 8 : 4);
 }
 
 hipError_t launch_smooth(Prec p, bool zg, bool norm, const Sweep& s, hipStream_t st,

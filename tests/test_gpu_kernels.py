@@ -131,7 +131,38 @@ def test_prolong_parity(d, N, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32_ir", "fp16_ir"])
-@pytest.mark.parametrize("d,N,level", [(2, 64, 1), (2, 128, 1), (2, 16, 1), (2, 8, 1),
+@pytest.mark.parametrize("d,N", [(2, n) for n in CASES_2D] + [(3, n) for n in CASES_3D])
+@pytest.mark.parametrize("level", [0, 1])
+def test_smooth_correct_parity(d, N, level, prec):
+    # post-smoothing with the coarse-grid correction fused into the sweep
+    need_gpu()
+    Nl = N >> level
+    if Nl < 8:
+        pytest.skip("needs a coarser level")
+    rng = np.random.default_rng(500 + N + level)
+    shp, shc = (Nl - 1,) * d, (Nl // 2 - 1,) * d
+    c = _coeffs(d)
+    sig, sigc = _sigma(prec, Nl), _sigma(prec, Nl // 2)
+    us = _roundtrip(_rand(rng, shp), prec)
+    ecs = _roundtrip(_rand(rng, shc), prec)
+    b = _roundtrip(_rand(rng, shp, 1.0 if prec != "fp64" else Nl * Nl), prec)
+    say("smooth-correct", d, N, level, prec)
+    with make_mg(N, d, c) as mg:
+        out = torch.empty(shp, dtype=_tdt(prec), device="cuda")
+        mg.sweep_correct(level, prec, dev(us, _tdt(prec)), dev(ecs, _tdt(prec)),
+                         dev(b, _tdt(prec)), out)
+        torch.cuda.synchronize()
+        got = host(out)
+    v = O.prolong_add(d, Nl, ecs / sigc, us / sig)
+    want = O.smooth(d, Nl, c, v, b) * sig
+    h2 = 1.0 / (Nl * Nl)
+    tol = _tol(prec, np.abs(us).max() + 4 * np.abs(ecs).max(), h2 * sig * np.abs(b).max(),
+               out_mag=np.abs(want).max())
+    assert np.max(np.abs(got - want)) <= tol
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_ir", "fp16_ir"])
+@pytest.mark.parametrize("d,N,level", [(2, 64, 0), (2, 64, 1), (2, 128, 1), (2, 16, 1), (2, 8, 1),
                                        (3, 32, 1), (3, 16, 1), (3, 8, 1)])
 def test_coarse_tail_parity(d, N, level, prec):
     # a zero-guess V(1,1) cycle below `level`, run entirely by the LDS tail

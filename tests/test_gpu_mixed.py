@@ -1,0 +1,55 @@
+"""Mixed-precision solves: FP32 (and FP16-storage) V-cycles inside FP64
+iterative refinement reach the same FP64 stopping rule as the plain FP64
+solve, and their solutions agree with the oracle's FP64 solution to what that
+residual implies: ||u - u_oracle|| <= (||r_gpu|| + ||r_oracle||) / lambda_min,
+with both residuals measured by the oracle's own FP64 operator."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2206_05543_amd import M7, M9
+from paper_2206_05543_amd.workloads import poisson_problem
+from tests._gpu import dev, gpu, host, make_mg, need_gpu, say
+
+pytestmark = gpu
+
+
+@pytest.mark.parametrize("prec", ["fp32_ir", "fp16_ir"])
+@pytest.mark.parametrize("d,N,inner", [(2, 256, 0), (3, 64, 0), (3, 64, 1), (2, 64, 3)])
+def test_mixed_solve_matches_fp64_oracle(d, N, prec, inner):
+    need_gpu()
+    c = np.array(M9 if d == 2 else M7)
+    p = poisson_problem(d, N, seed=21, n_modes=8, kmax=N // 4, noise=1e-3)
+    u_or, k_or, hist_or = O.solve(d, N, c, p["u0"], p["b"], tol=1e-10, maxc=100)
+    say("mixed", d, N, prec, inner)
+    with make_mg(N, d, c, precision=prec) as mg:
+        if inner:
+            mg.set_inner_cycles(inner)
+        u = dev(p["u0"])
+        st = mg.solve(dev(p["b"]), u, tol=1e-10)
+        got = host(u)
+    assert st["code"] == 0
+    r0 = O.norm2(O.residual(d, N, p["u0"], p["b"]))
+    rk = O.norm2(O.residual(d, N, got, p["b"]))
+    assert abs(st["r0"] - r0) <= 1e-10 * r0
+    assert rk <= 1.0001e-10 * r0
+    lam_min = 4.0 * d * N * N * np.sin(np.pi / (2 * N)) ** 2
+    bound = (rk + hist_or[-1]) / lam_min
+    assert np.linalg.norm(got - u_or) <= 1.01 * bound + 1e-13 * np.linalg.norm(u_or)
+
+
+@pytest.mark.parametrize("d,N", [(2, 256), (3, 64)])
+def test_fp32_ir_reaches_strict_tolerance(d, N):
+    # ||r|| <= 1e-10 ||b|| with a zero initial guess (so r_0 = b): FP32 inner
+    # cycles inside FP64 refinement still reach the FP64-level residual
+    need_gpu()
+    c = np.array(M9 if d == 2 else M7)
+    p = poisson_problem(d, N, seed=22, n_modes=8, kmax=N // 4, noise=1e-3)
+    say("mixed-strict", d, N)
+    with make_mg(N, d, c, precision="fp32_ir") as mg:
+        u = dev(np.zeros_like(p["b"]))
+        st = mg.solve(dev(p["b"]), u, tol=1e-10)
+        got = host(u)
+    assert st["code"] == 0
+    rk = O.norm2(O.residual(d, N, got, p["b"]))
+    assert rk <= 1.0001e-10 * O.norm2(p["b"])
