@@ -82,13 +82,15 @@ extern "C" {
 #define MG_OP_PROLONG_ADD 3  /* out += P u, u on level+1 (in place on out)     */
 
 /* timing kinds for mg_get_timing */
-#define MG_TIME_SMOOTH 0
+#define MG_TIME_SMOOTH 0      /* smoothing from a guess (pre-smoothing, and
+                                 post-smoothing on small grids)            */
 #define MG_TIME_SMOOTH_ZERO 1
 #define MG_TIME_RESTRICT 2
 #define MG_TIME_PROLONG 3
 #define MG_TIME_TAIL 4
 #define MG_TIME_IR_STEP 5
 #define MG_TIME_RESIDUAL 6
+#define MG_TIME_SMOOTH_CORRECT 7  /* post-smoothing with the fused correction */
 
 typedef struct mg_ctx* mg_handle_t;
 

@@ -1,0 +1,272 @@
+// gfx950 kernels of the reverse-mode (adjoint) V(1,1) cycle, FP64.
+//
+// The forward cycle (He, Liu and Wang, arXiv 2206.05543, Section 4, with the
+// smoother of Section 2, eq. (smoother)) is linear in (u, b) and polynomial
+// in the smoother coefficients c.  Its reverse sweep uses A^T = A and
+// M^T = M (both stencils are symmetric under zero extension), P^T = 2^d R and
+// R^T = 2^-d P for full weighting and linear interpolation.  With
+// M = h^2 sum_j c_j K_j, the coefficient gradient of a smoothing step
+// u_out = u + M r is dL/dc_j = h^2 <ubar_out, K_j r> = h^2 <K_j ubar_out, r>.
+//
+// These are one-node-per-thread kernels (neighbours through L1/L2): the
+// adjoint is a measured path, not a bandwidth-tuned one.  Reductions are
+// per-block partial sums in a fixed order, so gradients are deterministic.
+#include <hip/hip_runtime.h>
+
+#include "mg_internal.h"
+
+namespace spaimg {
+namespace {
+
+struct Grid {
+    int d, n;
+    long pts;
+    __device__ __forceinline__ void coords(long p, int* i, int* j, int* k) const {
+        *i = p % n;
+        *j = (p / n) % n;
+        *k = d == 3 ? (int)(p / ((long)n * n)) : 0;
+    }
+    __device__ __forceinline__ double at(const double* a, int i, int j, int k) const {
+        if (i < 0 || i >= n || j < 0 || j >= n) return 0.0;
+        if (d == 3) {
+            if (k < 0 || k >= n) return 0.0;
+            return a[((long)k * n + j) * n + i];
+        }
+        return a[(long)j * n + i];
+    }
+    __device__ __forceinline__ double lap(const double* a, int i, int j, int k) const {
+        double s = 2.0 * d * at(a, i, j, k) - at(a, i - 1, j, k) - at(a, i + 1, j, k) -
+                   at(a, i, j - 1, k) - at(a, i, j + 1, k);
+        if (d == 3) s -= at(a, i, j, k - 1) + at(a, i, j, k + 1);
+        return s;
+    }
+    __device__ __forceinline__ double faces(const double* a, int i, int j, int k) const {
+        double s = at(a, i - 1, j, k) + at(a, i + 1, j, k) + at(a, i, j - 1, k) +
+                   at(a, i, j + 1, k);
+        if (d == 3) s += at(a, i, j, k - 1) + at(a, i, j, k + 1);
+        return s;
+    }
+    __device__ __forceinline__ double corners(const double* a, int i, int j, int k) const {
+        return at(a, i - 1, j - 1, k) + at(a, i + 1, j - 1, k) + at(a, i - 1, j + 1, k) +
+               at(a, i + 1, j + 1, k);
+    }
+};
+
+__device__ __forceinline__ double block_sum256(double v, double* red) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    __syncthreads();
+    if (l == 0) red[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < 4; ++i) s += red[i];
+    __syncthreads();
+    return s;
+}
+
+// r = b - inv_h2 * L u
+__global__ void __launch_bounds__(256)
+k_residual(const double* __restrict__ u, const double* __restrict__ b, double* __restrict__ r,
+           Grid g, double inv_h2) {
+    const long off = (long)blockIdx.y * g.pts;
+    for (long p = (long)blockIdx.x * 256 + threadIdx.x; p < g.pts; p += (long)gridDim.x * 256) {
+        int i, j, k;
+        g.coords(p, &i, &j, &k);
+        r[off + p] = b[off + p] - inv_h2 * g.lap(u + off, i, j, k);
+    }
+}
+
+// w = sW (c0 K0 + c1 K1 + c2 K2) ubar and per-block partial sums of
+// (K_j ubar)(p) r(p), j = 0..2, into partials[3 * block + j]
+__global__ void __launch_bounds__(256)
+k_adj_applyK(const double* __restrict__ ub, const double* __restrict__ r, double* __restrict__ w,
+             double* __restrict__ partials, Grid g, double sW, double c0, double c1, double c2) {
+    __shared__ double red[4];
+    const long off = (long)blockIdx.y * g.pts;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    for (long p = (long)blockIdx.x * 256 + threadIdx.x; p < g.pts; p += (long)gridDim.x * 256) {
+        int i, j, k;
+        g.coords(p, &i, &j, &k);
+        const double k0 = ub[off + p];
+        const double k1 = g.faces(ub + off, i, j, k);
+        const double k2 = g.d == 2 ? g.corners(ub + off, i, j, k) : 0.0;
+        w[off + p] = sW * (c0 * k0 + c1 * k1 + c2 * k2);
+        const double rv = r[off + p];
+        s0 += k0 * rv;
+        s1 += k1 * rv;
+        s2 += k2 * rv;
+    }
+    const double t0 = block_sum256(s0, red);
+    const double t1 = block_sum256(s1, red);
+    const double t2 = block_sum256(s2, red);
+    if (threadIdx.x == 0) {
+        const long bi = (long)blockIdx.y * gridDim.x + blockIdx.x;
+        partials[3 * bi + 0] = t0;
+        partials[3 * bi + 1] = t1;
+        partials[3 * bi + 2] = t2;
+    }
+}
+
+// ubar_new = ubar - sA L w ;  bbar += w
+__global__ void __launch_bounds__(256)
+k_adj_update(const double* __restrict__ ub, const double* __restrict__ w,
+             double* __restrict__ ub_new, double* __restrict__ bbar, Grid g, double sA) {
+    const long off = (long)blockIdx.y * g.pts;
+    for (long p = (long)blockIdx.x * 256 + threadIdx.x; p < g.pts; p += (long)gridDim.x * 256) {
+        int i, j, k;
+        g.coords(p, &i, &j, &k);
+        const double wl = w[off + p];
+        ub_new[off + p] = ub[off + p] - sA * g.lap(w + off, i, j, k);
+        bbar[off + p] += wl;
+    }
+}
+
+// coarse = scale * R fine (full weighting; scale 2^d gives P^T)
+__global__ void __launch_bounds__(256)
+k_fw(const double* __restrict__ f, double* __restrict__ c, Grid gf, Grid gc, double scale) {
+    const long offf = (long)blockIdx.y * gf.pts, offc = (long)blockIdx.y * gc.pts;
+    for (long p = (long)blockIdx.x * 256 + threadIdx.x; p < gc.pts; p += (long)gridDim.x * 256) {
+        int i, j, k;
+        gc.coords(p, &i, &j, &k);
+        const int fi = 2 * i + 1, fj = 2 * j + 1, fk = 2 * k + 1;
+        double s = 0.0;
+        const int kl = gf.d == 3 ? -1 : 0, kh = gf.d == 3 ? 1 : 0;
+        for (int oz = kl; oz <= kh; ++oz)
+            for (int oy = -1; oy <= 1; ++oy)
+                for (int ox = -1; ox <= 1; ++ox) {
+                    double wt = (ox ? 0.25 : 0.5) * (oy ? 0.25 : 0.5);
+                    if (gf.d == 3) wt *= oz ? 0.25 : 0.5;
+                    s += wt * gf.at(f + offf, fi + ox, fj + oy, gf.d == 3 ? fk + oz : 0);
+                }
+        c[offc + p] = scale * s;
+    }
+}
+
+// fine = scale * P coarse (linear interpolation; scale 2^-d gives R^T)
+__global__ void __launch_bounds__(256)
+k_interp(const double* __restrict__ c, double* __restrict__ f, Grid gf, Grid gc, double scale) {
+    const long offf = (long)blockIdx.y * gf.pts, offc = (long)blockIdx.y * gc.pts;
+    for (long p = (long)blockIdx.x * 256 + threadIdx.x; p < gf.pts; p += (long)gridDim.x * 256) {
+        int i, j, k;
+        gf.coords(p, &i, &j, &k);
+        // grid coordinate g = i + 1: even -> coarse node g/2, odd -> mean of
+        // (g-1)/2 and (g+1)/2; coarse node G has interior index G - 1
+        const int gi = i + 1, gj = j + 1, gk = k + 1;
+        const int ia = gi / 2, ib = (gi + 1) / 2, ja = gj / 2, jb = (gj + 1) / 2;
+        double s;
+        if (gf.d == 2) {
+            s = 0.25 * (gc.at(c + offc, ia - 1, ja - 1, 0) + gc.at(c + offc, ib - 1, ja - 1, 0) +
+                        gc.at(c + offc, ia - 1, jb - 1, 0) + gc.at(c + offc, ib - 1, jb - 1, 0));
+        } else {
+            const int ka = gk / 2, kb = (gk + 1) / 2;
+            s = 0.125 * (gc.at(c + offc, ia - 1, ja - 1, ka - 1) + gc.at(c + offc, ib - 1, ja - 1, ka - 1) +
+                         gc.at(c + offc, ia - 1, jb - 1, ka - 1) + gc.at(c + offc, ib - 1, jb - 1, ka - 1) +
+                         gc.at(c + offc, ia - 1, ja - 1, kb - 1) + gc.at(c + offc, ib - 1, ja - 1, kb - 1) +
+                         gc.at(c + offc, ia - 1, jb - 1, kb - 1) + gc.at(c + offc, ib - 1, jb - 1, kb - 1));
+        }
+        f[offf + p] = scale * s;
+    }
+}
+
+// acc[j] += scale * sum_i partials[ncols * i + j], fixed order
+__global__ void __launch_bounds__(256)
+k_reduce_cols(const double* __restrict__ partials, int count, int ncols, double* __restrict__ acc,
+              double scale) {
+    __shared__ double red[4];
+    for (int jc = 0; jc < ncols; ++jc) {
+        double s = 0.0;
+        for (int i = threadIdx.x; i < count; i += 256) s += partials[(long)ncols * i + jc];
+        const double t = block_sum256(s, red);
+        if (threadIdx.x == 0) acc[jc] += scale * t;
+    }
+}
+
+// y (+)= G x for every batch entry (G: m x m, the exact coarsest solve)
+__global__ void __launch_bounds__(64)
+k_coarse_matvec(int m, const double* __restrict__ G, const double* __restrict__ x,
+                double* __restrict__ y, int accumulate) {
+    const long off = (long)blockIdx.x * m;
+    const int r = threadIdx.x;
+    if (r >= m) return;
+    double s = 0.0;
+    for (int q = 0; q < m; ++q) s += G[r * m + q] * x[off + q];
+    if (accumulate) y[off + r] += s;
+    else y[off + r] = s;
+}
+
+inline Grid make_grid(int d, int n) {
+    Grid g;
+    g.d = d;
+    g.n = n;
+    g.pts = d == 3 ? (long)n * n * n : (long)n * n;
+    return g;
+}
+
+inline dim3 point_grid(long pts, int batch) {
+    long blocks = (pts + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    return dim3((unsigned)blocks, batch);
+}
+
+}  // namespace
+
+hipError_t launch_residual(int d, int n, int batch, const double* u, const double* b, double* r,
+                           double inv_h2, hipStream_t st) {
+    const Grid g = make_grid(d, n);
+    hipLaunchKernelGGL(k_residual, point_grid(g.pts, batch), dim3(256), 0, st, u, b, r, g, inv_h2);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_applyK(int d, int n, int batch, const double* ubar, const double* r,
+                             double* w, double* partials, long partials_cap, double sW,
+                             const double* c, hipStream_t st, int* nparts) {
+    const Grid g = make_grid(d, n);
+    const dim3 grid = point_grid(g.pts, batch);
+    const long nb = (long)grid.x * grid.y;
+    if (3 * nb > partials_cap) return hipErrorInvalidValue;
+    if (nparts) *nparts = (int)nb;
+    hipLaunchKernelGGL(k_adj_applyK, grid, dim3(256), 0, st, ubar, r, w, partials, g, sW, c[0],
+                       c[1], d == 2 ? c[2] : 0.0);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_update(int d, int n, int batch, const double* ubar, const double* w,
+                             double* ubar_new, double* bbar, double sA, hipStream_t st) {
+    const Grid g = make_grid(d, n);
+    hipLaunchKernelGGL(k_adj_update, point_grid(g.pts, batch), dim3(256), 0, st, ubar, w, ubar_new,
+                       bbar, g, sA);
+    return hipGetLastError();
+}
+
+hipError_t launch_fw(int d, int n, int batch, const double* fine, double* coarse, double scale,
+                     hipStream_t st) {
+    const int nc = (n + 1) / 2 - 1;
+    const Grid gf = make_grid(d, n), gc = make_grid(d, nc);
+    hipLaunchKernelGGL(k_fw, point_grid(gc.pts, batch), dim3(256), 0, st, fine, coarse, gf, gc, scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_interp(int d, int n, int batch, const double* coarse, double* fine, double scale,
+                         hipStream_t st) {
+    const int nc = (n + 1) / 2 - 1;
+    const Grid gf = make_grid(d, n), gc = make_grid(d, nc);
+    hipLaunchKernelGGL(k_interp, point_grid(gf.pts, batch), dim3(256), 0, st, coarse, fine, gf, gc,
+                       scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_cols(const double* partials, int count, int ncols, double* acc,
+                              double scale, hipStream_t st) {
+    hipLaunchKernelGGL(k_reduce_cols, dim3(1), dim3(256), 0, st, partials, count, ncols, acc, scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_coarse_matvec(int m, int batch, const double* G, const double* x, double* y,
+                                bool accumulate, hipStream_t st) {
+    if (m > 64) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_coarse_matvec, dim3(batch), dim3(64), 0, st, m, G, x, y, accumulate ? 1 : 0);
+    return hipGetLastError();
+}
+
+}  // namespace spaimg

@@ -38,7 +38,9 @@ int fail(int code, const std::string& msg) {
     } while (0)
 
 constexpr int kMaxLevels = 20;
-constexpr int kTimeKinds = 7;
+constexpr int kTimeKinds = 8;
+// grids with fewer nodes use a separate correction pass (see cycle())
+constexpr long kFusedCorrectionMinPts = 1L << 19;
 constexpr long kPartialCap = 1 << 17;  // per batch entry
 
 struct Hier {
@@ -70,11 +72,10 @@ struct mg_ctx {
     double* dscale = nullptr;    // refinement scales per step
     double* hnorm = nullptr;     // pinned host mirror of dnorm
     int norm_slots = 0;
-    // adjoint scratch (FP64), allocated on first use
-    std::vector<double*> adj;    // per level: r1, r3, u1/u2, ubar work
+    // adjoint scratch (FP64), allocated on first use; per level
+    std::vector<double*> adj_r1, adj_r3, adj_w, adj_ua, adj_ub, adj_uo, adj_bb;
     bool adj_alloc = false;
-    double* adj_cpart = nullptr;
-    double* adj_cacc = nullptr;
+    double* adj_cacc = nullptr;  // device accumulator of dL/dc (3 doubles)
     // timing
     int timing = 0;
     std::vector<hipEvent_t> ev_pool;
@@ -386,11 +387,21 @@ int cycle(mg_ctx* h, Hier& H, int l, const void* u_in, const void* b, void* out,
     if (rc) return rc;
     rc = cycle(h, H, l + 1, nullptr, H.b[l + 1], H.e[l + 1], H.t[l + 1], NormReq(), st);
     if (rc) return rc;
-    // post-smoothing of tmp + pf P e_{l+1} (correction fused into the sweep)
     s.u = tmp;
     s.out = out;
-    s.ec = H.e[l + 1];
-    s.pf = pf;
+    if (level_pts(h, l) >= kFusedCorrectionMinPts) {
+        // post-smoothing of tmp + pf P e_{l+1} (correction fused into the sweep)
+        s.ec = H.e[l + 1];
+        s.pf = pf;
+        return run_timed(h, MG_TIME_SMOOTH_CORRECT, l, st,
+                         [&] { return launch_smooth(H.p, false, false, s, st, nullptr); });
+    }
+    // small grids are latency bound: a plain correction pass and a plain
+    // sweep start faster than the fused sweep's deeper prologue
+    rc = run_timed(h, MG_TIME_PROLONG, l, st, [&] {
+        return launch_prolong(H.p, h->d, s.n, h->batch, H.e[l + 1], tmp, pf, st);
+    });
+    if (rc) return rc;
     return run_timed(h, MG_TIME_SMOOTH, l, st,
                      [&] { return launch_smooth(H.p, false, false, s, st, nullptr); });
 }
@@ -829,21 +840,139 @@ void mg_destroy(mg_handle_t h) {
 
 namespace {
 void free_adj(mg_ctx* h) {
-    for (double* p : h->adj)
-        if (p) (void)hipFree(p);
-    h->adj.clear();
-    if (h->adj_cpart) (void)hipFree(h->adj_cpart);
+    for (auto* v : {&h->adj_r1, &h->adj_r3, &h->adj_w, &h->adj_ua, &h->adj_ub, &h->adj_uo,
+                    &h->adj_bb}) {
+        for (double* p : *v)
+            if (p) (void)hipFree(p);
+        v->clear();
+    }
     if (h->adj_cacc) (void)hipFree(h->adj_cacc);
-    h->adj_cpart = h->adj_cacc = nullptr;
+    h->adj_cacc = nullptr;
     h->adj_alloc = false;
+}
+
+int alloc_adj(mg_ctx* h) {
+    if (h->adj_alloc) return MG_OK;
+    free_adj(h);
+    for (auto* v : {&h->adj_r1, &h->adj_r3, &h->adj_w, &h->adj_ua, &h->adj_ub, &h->adj_uo,
+                    &h->adj_bb})
+        v->assign(h->L, nullptr);
+    for (int l = 0; l < h->L; ++l) {
+        const size_t bytes = (size_t)level_pts(h, l) * h->batch * sizeof(double);
+        if (l == 0) HIPCHK(hipMalloc(&h->adj_r1[l], bytes));
+        if (l > 0) {
+            HIPCHK(hipMalloc(&h->adj_uo[l], bytes));
+            HIPCHK(hipMalloc(&h->adj_bb[l], bytes));
+        }
+        if (l < h->L - 1) {
+            HIPCHK(hipMalloc(&h->adj_r3[l], bytes));
+            HIPCHK(hipMalloc(&h->adj_w[l], bytes));
+            HIPCHK(hipMalloc(&h->adj_ua[l], bytes));
+            HIPCHK(hipMalloc(&h->adj_ub[l], bytes));
+        }
+    }
+    HIPCHK(hipMalloc(&h->adj_cacc, 3 * sizeof(double)));
+    h->adj_alloc = true;
+    return MG_OK;
+}
+
+// Forward recomputation of one V(1,1) cycle at level l from u_in (null: zero
+// guess), keeping what the reverse sweep needs: r1 = b - A u_in (fine
+// level; on coarse levels r1 = b), r3 = b - A u2 with u2 = u1 + P e_{l+1},
+// and the level output e_l (for the level above).
+int adj_forward(mg_ctx* h, int l, const double* u_in, const double* bl, hipStream_t st) {
+    Hier& H = h->h64;
+    const int d = h->d, n = level_n(h, l);
+    const double N = level_N(h, l);
+    if (l == h->L - 1) return run_tail(h, H, l, bl, H.e[l], st);
+    Sweep s = make_sweep(h, H, l);
+    double* t = static_cast<double*>(H.t[l]);
+    s.u = u_in;
+    s.b = bl;
+    s.out = t;
+    HIPCHK(launch_smooth(P64, u_in == nullptr, false, s, st, nullptr));
+    if (u_in) HIPCHK(launch_residual(d, n, h->batch, u_in, bl, h->adj_r1[l], N * N, st));
+    s.u = t;
+    s.out = H.b[l + 1];
+    HIPCHK(launch_restrict(P64, s, st));
+    int rc = adj_forward(h, l + 1, nullptr, static_cast<const double*>(H.b[l + 1]), st);
+    if (rc) return rc;
+    HIPCHK(launch_prolong(P64, d, n, h->batch, H.e[l + 1], t, 1.0, st));
+    HIPCHK(launch_residual(d, n, h->batch, t, bl, h->adj_r3[l], N * N, st));
+    if (l > 0) {
+        s.u = t;
+        s.out = H.e[l];
+        HIPCHK(launch_smooth(P64, false, false, s, st, nullptr));
+    }
+    return MG_OK;
+}
+
+// Reverse sweep of the cycle at level l: given uo = dL/du_out, accumulates
+// bb += dL/db_l and the coefficient gradient, and writes ui = dL/du_in.
+int adj_reverse(mg_ctx* h, int l, const double* uo, double* ui, double* bb, const double* r1,
+                hipStream_t st) {
+    Hier& H = h->h64;
+    const int d = h->d, n = level_n(h, l), b = h->batch;
+    const double N = level_N(h, l), h2 = 1.0 / (N * N);
+    if (l == h->L - 1) {
+        // e = A^{-1} b: bbar += A^{-1} ubar_out; the output ignores u_in
+        HIPCHK(launch_coarse_matvec(d == 2 ? 9 : 27, b, H.ginv, uo, bb, true, st));
+        if (ui) HIPCHK(hipMemsetAsync(ui, 0, (size_t)level_pts(h, l) * b * sizeof(double), st));
+        return MG_OK;
+    }
+    double c[3] = {h->c[0], h->c[1], h->ncoef == 3 ? h->c[2] : 0.0};
+    double* w = h->adj_w[l];
+    double* ua = h->adj_ua[l];
+    double* ub = h->adj_ub[l];
+    const long cap = kPartialCap * b;
+    int np = 0;
+    // post-smoothing  u_out = u2 + M r3, r3 = b - A u2
+    HIPCHK(launch_adj_applyK(d, n, b, uo, h->adj_r3[l], w, h->psum, cap, h2, c, st, &np));
+    HIPCHK(launch_reduce_cols(h->psum, np, 3, h->adj_cacc, h2, st));
+    HIPCHK(launch_adj_update(d, n, b, uo, w, ua, bb, N * N, st));
+    // correction u2 = u1 + P e_c: ecbar = P^T ubar2 = 2^d R ubar2
+    HIPCHK(launch_fw(d, n, b, ua, h->adj_uo[l + 1], d == 2 ? 4.0 : 8.0, st));
+    const size_t cbytes = (size_t)level_pts(h, l + 1) * b * sizeof(double);
+    HIPCHK(hipMemsetAsync(h->adj_bb[l + 1], 0, cbytes, st));
+    int rc = adj_reverse(h, l + 1, h->adj_uo[l + 1], nullptr, h->adj_bb[l + 1],
+                         static_cast<const double*>(H.b[l + 1]), st);
+    if (rc) return rc;
+    // restriction b_c = R (b - A u1): rbar = R^T bcbar = 2^-d P bcbar
+    HIPCHK(launch_interp(d, n, b, h->adj_bb[l + 1], w, d == 2 ? 0.25 : 0.125, st));
+    HIPCHK(launch_adj_update(d, n, b, ua, w, ub, bb, N * N, st));
+    // pre-smoothing  u1 = u + M r1, r1 = b - A u
+    HIPCHK(launch_adj_applyK(d, n, b, ub, r1, w, h->psum, cap, h2, c, st, &np));
+    HIPCHK(launch_reduce_cols(h->psum, np, 3, h->adj_cacc, h2, st));
+    if (ui) HIPCHK(launch_adj_update(d, n, b, ub, w, ui, bb, N * N, st));
+    else HIPCHK(launch_adj_update(d, n, b, ub, w, ua, bb, N * N, st));
+    return MG_OK;
 }
 }  // namespace
 
 extern "C" int mg_vcycle_adjoint(mg_handle_t h, const double* b, const double* u_in,
                                  const double* ubar_out, double* ubar_in, double* bbar_acc,
                                  double* cbar_acc, void* stream) {
-    (void)b; (void)u_in; (void)ubar_out; (void)ubar_in; (void)bbar_acc; (void)cbar_acc;
-    (void)stream;
-    if (!h) return fail(MG_EINVAL, "null handle");
-    return fail(MG_EINVAL, "adjoint cycle not available in this build");
+    if (check_handle(h)) return MG_EINVAL;
+    if (!b || !u_in || !ubar_out || !ubar_in || !bbar_acc || !cbar_acc)
+        return fail(MG_EINVAL, "null pointer");
+    hipStream_t st = (hipStream_t)stream;
+    int rc = alloc_adj(h);
+    if (rc) return rc;
+    HIPCHK(hipMemsetAsync(h->adj_cacc, 0, 3 * sizeof(double), st));
+    if (h->L == 1) {
+        // single grid: u_out = A^{-1} b
+        HIPCHK(launch_coarse_matvec(h->d == 2 ? 9 : 27, h->batch, h->h64.ginv, ubar_out, bbar_acc,
+                                    true, st));
+        HIPCHK(hipMemsetAsync(ubar_in, 0, (size_t)level_pts(h, 0) * h->batch * sizeof(double), st));
+    } else {
+        rc = adj_forward(h, 0, u_in, b, st);
+        if (rc) return rc;
+        rc = adj_reverse(h, 0, ubar_out, ubar_in, bbar_acc, h->adj_r1[0], st);
+        if (rc) return rc;
+    }
+    double hc[3];
+    HIPCHK(hipMemcpyAsync(hc, h->adj_cacc, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int j = 0; j < h->ncoef; ++j) cbar_acc[j] += hc[j];
+    return MG_OK;
 }

@@ -90,30 +90,29 @@ struct IRStep {
 };
 hipError_t launch_ir_step(Prec p, const IRStep& s, hipStream_t st, int* nparts);
 
-// Reverse-mode kernels of the adjoint cycle (FP64 only).
-//   adj_smooth: w = W ubar (ring), ubar_new = ubar - A w, bbar += w,
-//               partial sums of <ubar, K_j r> for j = 0..ncoef-1.
-hipError_t launch_adj_smooth(int d, int n, int batch, const double* ubar,
-                             const double* r, double* ubar_new, double* bbar,
-                             double inv_h2, double h2, const double* c,
-                             double* partials, hipStream_t st, int* nparts);
-//   adj_restrict: rbar = R^T bcbar; bbar += rbar; ubar -= A rbar (in place ok)
-hipError_t launch_adj_restrict(int d, int n, int batch, const double* bcbar,
-                               double* ubar, double* bbar, double inv_h2,
-                               hipStream_t st);
-//   ecbar = P^T ubar (coarse = n/2 interior)
-hipError_t launch_prolong_T(int d, int n, int batch, const double* ubar,
-                            double* ecbar, hipStream_t st);
-//   r = b - A u (FP64, plain residual field)
-hipError_t launch_residual(int d, int n, int batch, const double* u,
-                           const double* b, double* r, double inv_h2,
-                           hipStream_t st);
-//   coefficient-gradient partial sums -> cbar (device, ncoef doubles, +=)
-hipError_t launch_reduce_cols(const double* partials, int count, int ncols,
-                              double* acc, hipStream_t st);
-// dense matvec on the coarsest grid for the adjoint: y (+)= G x per batch
-hipError_t launch_coarse_matvec(int m, int batch, const double* G,
-                                const double* x, double* y, bool accumulate,
-                                hipStream_t st);
+// Kernels of the reverse-mode (adjoint) cycle, FP64, whole batch.
+//   r = b - inv_h2 L u
+hipError_t launch_residual(int d, int n, int batch, const double* u, const double* b,
+                           double* r, double inv_h2, hipStream_t st);
+//   w = sW (c0 K0 + c1 K1 + c2 K2) ubar; partials[3 i + j] = block sums of
+//   (K_j ubar) r
+hipError_t launch_adj_applyK(int d, int n, int batch, const double* ubar, const double* r,
+                             double* w, double* partials, long partials_cap, double sW,
+                             const double* c, hipStream_t st, int* nparts);
+//   ubar_new = ubar - sA L w; bbar += w
+hipError_t launch_adj_update(int d, int n, int batch, const double* ubar, const double* w,
+                             double* ubar_new, double* bbar, double sA, hipStream_t st);
+//   coarse = scale * R fine (full weighting)
+hipError_t launch_fw(int d, int n, int batch, const double* fine, double* coarse,
+                     double scale, hipStream_t st);
+//   fine = scale * P coarse (linear interpolation, overwrite)
+hipError_t launch_interp(int d, int n, int batch, const double* coarse, double* fine,
+                         double scale, hipStream_t st);
+//   acc[j] += scale * sum_i partials[ncols i + j] (fixed order)
+hipError_t launch_reduce_cols(const double* partials, int count, int ncols, double* acc,
+                              double scale, hipStream_t st);
+//   y (+)= G x per batch entry, G m x m (m <= 64)
+hipError_t launch_coarse_matvec(int m, int batch, const double* G, const double* x,
+                                double* y, bool accumulate, hipStream_t st);
 
 }  // namespace spaimg

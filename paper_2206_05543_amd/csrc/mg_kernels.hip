@@ -1580,14 +1580,17 @@ inline int pick_chunk(int n, int tiles, int want, int minc) {
     return ch;
 }
 
-constexpr int S3_TX = 64, S3_TY = 16, S3_NT = 256;
-constexpr int S2_TX = 256, S2_NT = 256;
+constexpr int S3_TX = 64, S3_TY = 32, S3_NT = 512;
+constexpr int S3S_TX = 64, S3S_TY = 16, S3S_NT = 256;
+constexpr int S2_TX = 1024, S2_NT = 512;
+constexpr int S2S_TX = 256, S2S_NT = 256;
 constexpr int S_PD = 1;
 constexpr int R3_TX = 32, R3_TY = 8;
 constexpr int R2_TX = 256;
 constexpr int I3_TX = 64, I3_TY = 16, I3_NT = 256;
 constexpr int I2_TX = 256;
 constexpr int kWantBlocks = 1024;
+constexpr int kWantBlocks3D = 256;
 
 // chunk length along the marching direction: long chunks on large grids
 // (fewer halo planes re-read), one plane per workgroup on small grids, where
@@ -1610,9 +1613,9 @@ hipError_t smooth_impl(bool zg, bool norm, const Sweep& s, hipStream_t st, int* 
     const C pf = C(s.pf);
     if (zg && (norm || pro)) return hipErrorInvalidValue;
     if (norm && pro) return hipErrorInvalidValue;
-    if (s.d == 3) {
+    if (s.d == 3 && n >= 200) {
         const int tx = cdiv(n, S3_TX), ty = cdiv(n, S3_TY);
-        const int zc = march_chunk(n, tx * ty, (long)n * n * n, kWantBlocks, 8);
+        const int zc = march_chunk(n, tx * ty, (long)n * n * n, kWantBlocks3D, 32);
         const int nch = cdiv(n, zc);
         dim3 grid(tx * ty * nch, s.batch);
         if (nparts) *nparts = grid.x * grid.y;
@@ -1626,9 +1629,26 @@ hipError_t smooth_impl(bool zg, bool norm, const Sweep& s, hipStream_t st, int* 
         else if (pro) L3(false, false, true);
         else L3(false, false, false);
 #undef L3
-    } else {
+    } else if (s.d == 3) {
+        const int tx = cdiv(n, S3S_TX), ty = cdiv(n, S3S_TY);
+        const int zc = march_chunk(n, tx * ty, (long)n * n * n, kWantBlocks, 8);
+        const int nch = cdiv(n, zc);
+        dim3 grid(tx * ty * nch, s.batch);
+        if (nparts) *nparts = grid.x * grid.y;
+        if (norm && (long)grid.x * grid.y > s.partials_cap) return hipErrorInvalidValue;
+#define L3(ZG, NM, PR)                                                                     \
+    hipLaunchKernelGGL((k_smooth3d<S, C, S3S_TX, S3S_TY, S3S_NT, S_PD, ZG, NM, PR>), grid, \
+                       dim3(S3S_NT), 0, st, u, b, out, n, tx, ty, zc, nch, sA, sW, c0,     \
+                       c1, s.partials, ec, nc, pf)
+        if (zg) L3(true, false, false);
+        else if (norm) L3(false, true, false);
+        else if (pro) L3(false, false, true);
+        else L3(false, false, false);
+#undef L3
+    } else if (n >= 3000) {
+        // large grids: wide strips, chunk length per variant (measured)
         const int tx = cdiv(n, S2_TX);
-        const int yc = march_chunk(n, tx, (long)n * n, kWantBlocks, 16);
+        const int yc = march_chunk(n, tx, (long)n * n, kWantBlocks, pro ? 64 : 16);
         const int nch = cdiv(n, yc);
         dim3 grid(tx * nch, s.batch);
         if (nparts) *nparts = grid.x * grid.y;
@@ -1637,6 +1657,22 @@ hipError_t smooth_impl(bool zg, bool norm, const Sweep& s, hipStream_t st, int* 
     hipLaunchKernelGGL((k_smooth2d<S, C, S2_TX, S2_NT, S_PD, ZG, NM, PR>), grid, dim3(S2_NT),\
                        0, st, u, b, out, n, tx, yc, nch, sA, sW, c0, c1, c2, s.partials, \
                        ec, nc, pf)
+        if (zg) L2(true, false, false);
+        else if (norm) L2(false, true, false);
+        else if (pro) L2(false, false, true);
+        else L2(false, false, false);
+#undef L2
+    } else {
+        const int tx = cdiv(n, S2S_TX);
+        const int yc = march_chunk(n, tx, (long)n * n, kWantBlocks, pro ? 64 : 16);
+        const int nch = cdiv(n, yc);
+        dim3 grid(tx * nch, s.batch);
+        if (nparts) *nparts = grid.x * grid.y;
+        if (norm && (long)grid.x * grid.y > s.partials_cap) return hipErrorInvalidValue;
+#define L2(ZG, NM, PR)                                                                     \
+    hipLaunchKernelGGL((k_smooth2d<S, C, S2S_TX, S2S_NT, S_PD, ZG, NM, PR>), grid,         \
+                       dim3(S2S_NT), 0, st, u, b, out, n, tx, yc, nch, sA, sW, c0, c1, c2, \
+                       s.partials, ec, nc, pf)
         if (zg) L2(true, false, false);
         else if (norm) L2(false, true, false);
         else if (pro) L2(false, false, true);
@@ -1655,7 +1691,7 @@ hipError_t restrict_impl(const Sweep& s, hipStream_t st) {
     const C sA = C(s.sA);
     if (s.d == 3) {
         const int tx = cdiv(nc, R3_TX), ty = cdiv(nc, R3_TY);
-        const int zc = march_chunk(nc, tx * ty, (long)n * n * n, kWantBlocks, 4);
+        const int zc = march_chunk(nc, tx * ty, (long)n * n * n, kWantBlocks, 16);
         const int nch = cdiv(nc, zc);
         dim3 grid(tx * ty * nch, s.batch);
         hipLaunchKernelGGL((k_restrict3d<S, C, R3_TX, R3_TY, S_PD>), grid, dim3(R3_TX * R3_TY), 0,
