@@ -29,6 +29,30 @@ namespace {
 
 constexpr int kXCD = 8;
 
+// compile-time position of a step within the unrolled marching loops
+template <int K>
+struct Par {
+    static constexpr int k = K;
+};
+
+// Runs f(s, Par<0>), f(s+1, Par<1>), ..., f(s+R-1, Par<R-1>) for s = first,
+// first+R, ... while s <= last: the body of a marching loop unrolled R times,
+// so that every prefetch slot index is a compile-time constant.  Groups are
+// always run whole (the step function ignores steps past `last`): a loop
+// with a single latch keeps the prefetch registers in place, where an exit
+// in the middle of a group makes the compiler copy loads still in flight.
+template <int R, int K = 0, typename F>
+__device__ __forceinline__ void unroll_step(int s, F&& f) {
+    if constexpr (K < R) {
+        f(s + K, Par<K>());
+        unroll_step<R, K + 1>(s, f);
+    }
+}
+template <int R, typename F>
+__device__ __forceinline__ void march(int first, int last, F&& f) {
+    for (int s = first; s <= last; s += R) unroll_step<R>(s, f);
+}
+
 // Bijection from hardware workgroup order (round-robin over XCDs) to a
 // logical tile order in which every XCD owns one contiguous range.
 __device__ __forceinline__ int xcd_remap(int bid, int total) {
@@ -39,6 +63,69 @@ __device__ __forceinline__ int xcd_remap(int bid, int total) {
 
 template <typename C, typename S>
 __device__ __forceinline__ C cvt(S v) { return static_cast<C>(v); }
+
+// Output stores of large grids are non-temporal: the field is consumed by a
+// later kernel from HBM anyway, and keeping the write stream out of the
+// caches lets the two read streams run at full rate (measured on MI355X: a
+// 2-read/1-write stream goes from ~5.4 to ~7.0 TB/s).  Small grids, which
+// the next kernel reads back from L2, use ordinary stores.
+constexpr long kNtMinPts = 1L << 22;
+
+template <typename S>
+__device__ __forceinline__ void st_out(S* p, S v, bool nt) {
+    if (nt) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
+// ---------------------------------------------------------------------------
+// Raw buffer access.  The marching kernels read and write through buffer
+// resources that cover one plane (3D) or one row (2D) of one field: a plane
+// outside the grid gets num_records = 0 and a lane outside the grid uses the
+// byte offset kOob, so both read as zero and their stores are dropped by the
+// hardware range check.  This replaces per-lane index clamps, 64-bit
+// address arithmetic and exec-mask branches by one 32-bit offset per point.
+// ---------------------------------------------------------------------------
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+constexpr unsigned kOob = 0x80000000u;
+constexpr int kRsrcWord3 = 0x00020000;  // raw (untyped) buffer, gfx9-family layout
+typedef int int2v __attribute__((ext_vector_type(2)));
+
+template <typename S>
+__device__ __forceinline__ rsrc_t line_rsrc(const S* base, long first, long len, bool in) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<S*>(in ? base + first : base), 0,
+                                             in ? (int)(len * (long)sizeof(S)) : 0, kRsrcWord3);
+}
+template <typename S>
+__device__ __forceinline__ S bload(rsrc_t r, unsigned off);
+template <>
+__device__ __forceinline__ double bload<double>(rsrc_t r, unsigned off) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+template <>
+__device__ __forceinline__ float bload<float>(rsrc_t r, unsigned off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+template <>
+__device__ __forceinline__ _Float16 bload<_Float16>(rsrc_t r, unsigned off) {
+    return __builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0));
+}
+// NTS selects the non-temporal store (cache policy bit 1)
+template <bool NTS>
+__device__ __forceinline__ void bstore(double v, rsrc_t r, unsigned off) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(int2v, v), r, off, 0, NTS ? 2 : 0);
+}
+template <bool NTS>
+__device__ __forceinline__ void bstore(float v, rsrc_t r, unsigned off) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, v), r, off, 0, NTS ? 2 : 0);
+}
+template <bool NTS>
+__device__ __forceinline__ void bstore(_Float16 v, rsrc_t r, unsigned off) {
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(short, v), r, off, 0, NTS ? 2 : 0);
+}
+template <bool B>
+struct Bool {
+    static constexpr bool value = B;
+};
 
 __device__ __forceinline__ int interp_idx(int i, int nc, int* j0, int* j1) {
     // fine index i (grid coordinate i+1): even coordinate -> one coarse node,
@@ -86,7 +173,7 @@ __device__ __forceinline__ double block_max(double v, double* red) {
 
 // ---------------------------------------------------------------------------
 // Software pipeline of the marching kernels.  Global loads of the plane that
-// will be needed PD + 1 steps later are issued at the top of each step into
+// will be consumed PD steps later are issued at the top of each step into
 // raw storage-typed registers; they are converted (and combined with the
 // fused coarse correction) only when the plane is consumed, so no arithmetic
 // waits on a load in flight.
@@ -103,8 +190,14 @@ __device__ __forceinline__ double block_max(double v, double* red) {
 // each even fine plane is staged once into an LDS tile, and every column
 // keeps the bilinear value of the last coarse plane in a register, so the
 // trilinear correction costs one coarse read per coarse node.
+//
+// Every lane executes the same instruction stream: global accesses go
+// through plane buffer resources (off-grid reads are zero, off-tile stores
+// are dropped), LDS writes of lanes past the tile land in a scratch area,
+// and the residual outside the grid is cleared with a select.
 // ---------------------------------------------------------------------------
-template <typename S, typename C, int TX, int TY, int NT, int PD, bool ZG, bool NORM, bool PRO>
+template <typename S, typename C, int TX, int TY, int NT, int PD, int UN, bool ZG, bool NORM,
+          bool PRO, bool NTS>
 __global__ void __launch_bounds__(NT)
 k_smooth3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out,
            int n, int tiles_x, int tiles_y, int zchunk, int nchunks, C sA,
@@ -114,13 +207,18 @@ k_smooth3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out
     constexpr int UX = TX + 4, UY = TY + 4, NU = UX * UY;
     constexpr int M = (NR + NT - 1) / NT;
     constexpr int NR2 = 2 * RX + 2 * RY;
-    constexpr int CX = TX / 2 + 3, CY = TY / 2 + 3, NC = CX * CY;
+    constexpr int CX = TX / 2 + 4, CY = TY / 2 + 4, NC = CX * CY;
     constexpr int MC = (NC + NT - 1) / NT;
+    // residual planes: slot t + m * NT at offset RP, padded by RX + 1 on
+    // both sides so that neighbour reads of every lane stay in bounds
+    constexpr int RP = RX + 1, RSZ = RP + M * NT + RX + 1;
+    // u planes: lanes past the tile write (and read around) UD + lane
+    constexpr int UD = NU + UX, USZ = NU + 2 * UX + 65;
     static_assert(NR2 <= NT, "one thread per ring-2 point");
     static_assert(TX % 2 == 0 && TY % 2 == 0, "even tiles");
-    __shared__ C uL[2][ZG ? 1 : NU];
-    __shared__ C rL[2][NR];
-    __shared__ C cL[PRO ? NC : 1];
+    __shared__ C uL[2][ZG ? 1 : USZ];
+    __shared__ C rL[2][RSZ];
+    __shared__ C cL[PRO ? MC * NT : 1];
     __shared__ double red[NT / 64];
 
     const int total = tiles_x * tiles_y * nchunks;
@@ -135,24 +233,26 @@ k_smooth3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out
     const int x0 = tx * TX, y0 = ty * TY;
     const int z0 = ch * zchunk, z1 = min(z0 + zchunk, n);
     const int t = threadIdx.x;
+    const int lane = t & 63;
 
-    int rl[M], ul[M], go[M];
-    bool inr[M], val[M], inn[M];
+    int ul[M];
+    unsigned gb[M];  // byte offset in the plane, kOob off the grid
+    bool val[M], inn[M];
 #pragma unroll
     for (int m = 0; m < M; ++m) {
         const int i = t + m * NT;
-        inr[m] = i < NR;
+        const bool inr = i < NR;
         const int lx = i % RX, ly = i / RX;
         const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
-        val[m] = inr[m] && gx >= 0 && gx < n && gy >= 0 && gy < n;
+        val[m] = inr && gx >= 0 && gx < n && gy >= 0 && gy < n;
         inn[m] = val[m] && lx >= 1 && lx <= TX && ly >= 1 && ly <= TY;
-        rl[m] = inr[m] ? i : 0;
-        ul[m] = inr[m] ? (ly + 1) * UX + lx + 1 : 0;
-        go[m] = val[m] ? gy * n + gx : 0;
+        ul[m] = inr ? (ly + 1) * UX + lx + 1 : UD + lane;
+        gb[m] = val[m] ? (unsigned)((gy * n + gx) * (int)sizeof(S)) : kOob;
     }
-    int r2l = 0, r2g = 0, r2x = 0, r2y = 0;
-    bool r2v = false;
-    if (!ZG && t < NR2) {
+    int r2l = UD + lane, r2x = 0, r2y = 0;
+    unsigned r2b = kOob;
+    const bool r2in = !ZG && t < NR2;
+    if (r2in) {
         int ux, uy;
         if (t < RX) { ux = 1 + t; uy = 0; }
         else if (t < 2 * RX) { ux = 1 + t - RX; uy = UY - 1; }
@@ -161,93 +261,105 @@ k_smooth3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out
         r2x = x0 - 2 + ux;
         r2y = y0 - 2 + uy;
         r2l = uy * UX + ux;
-        r2v = r2x >= 0 && r2x < n && r2y >= 0 && r2y < n;
-        r2g = r2v ? r2y * n + r2x : 0;
+        if (r2x >= 0 && r2x < n && r2y >= 0 && r2y < n)
+            r2b = (unsigned)((r2y * n + r2x) * (int)sizeof(S));
     }
 
-    // ---- fused coarse correction (PRO)
+    // ---- fused coarse correction (PRO): per lane, the LDS index of the
+    // lower coarse neighbour plus two flags (second node in x, in y)
     const long cplane = (long)nc * nc;
     const int cx0 = x0 / 2 - 2, cy0 = y0 / 2 - 2;  // coarse tile origin
-    int cidx[M + 1][4];
-    C cw[M + 1], qprev[M + 1];
-    int cgo[MC];
-    bool cval[MC];
-    S rc[MC];
+    int cc[M + 1];
+    C qprev[M + 1];
+    unsigned cgb[MC];
+    // coarse planes are loaded CD even steps ahead into RCS register slots
+    constexpr int RCS = UN / 2, CD = RCS >= 2 ? 2 : 1;
+    S rc[RCS][MC];
     if (PRO) {
         ec += (long)blockIdx.y * cplane * nc;
         auto setup = [&](int k, bool ok, int gx, int gy) {
-            int xa, xb, ya, yb;
-            const int nx = interp_idx(gx, nc, &xa, &xb), ny = interp_idx(gy, nc, &ya, &yb);
-            cw[k] = (nx == 1 ? C(1) : C(0.5)) * (ny == 1 ? C(1) : C(0.5));
-            const int lxa = xa - cx0, lxb = xb - cx0, lya = ya - cy0, lyb = yb - cy0;
-            cidx[k][0] = (ok && xa >= 0 && ya >= 0) ? lya * CX + lxa : -1;
-            cidx[k][1] = (ok && nx == 2 && xb >= 0 && ya >= 0) ? lya * CX + lxb : -1;
-            cidx[k][2] = (ok && ny == 2 && xa >= 0 && yb >= 0) ? lyb * CX + lxa : -1;
-            cidx[k][3] = (ok && nx == 2 && ny == 2 && xb >= 0 && yb >= 0) ? lyb * CX + lxb : -1;
+            const int g = gx + 1, h = gy + 1;  // grid coordinates
+            const int lx = (g >> 1) - 1 - cx0, ly = (h >> 1) - 1 - cy0;
+            cc[k] = ok ? (ly * CX + lx) | ((g & 1) << 16) | ((h & 1) << 17) : 0;
             qprev[k] = C(0);
         };
 #pragma unroll
         for (int m = 0; m < M; ++m) {
             const int i = t + m * NT;
-            setup(m, val[m], x0 - 1 + i % RX, y0 - 1 + i / RX);
+            setup(m, i < NR, x0 - 1 + i % RX, y0 - 1 + i / RX);
         }
-        setup(M, r2v, r2x, r2y);
+        setup(M, r2in, r2x, r2y);
 #pragma unroll
         for (int j = 0; j < MC; ++j) {
             const int i = t + j * NT;
             const int gx = cx0 + i % CX, gy = cy0 + i / CX;
-            cval[j] = i < NC && gx >= 0 && gx < nc && gy >= 0 && gy < nc;
-            cgo[j] = cval[j] ? gy * nc + gx : 0;
+            const bool ok = i < NC && gx >= 0 && gx < nc && gy >= 0 && gy < nc;
+            cgb[j] = ok ? (unsigned)((gy * nc + gx) * (int)sizeof(S)) : kOob;
         }
     }
-    auto c_issue = [&](int Z) {
+    auto c_issue = [&](int Z, int sl) {
+        const rsrc_t r = line_rsrc(ec, (long)Z * cplane, cplane, Z >= 0 && Z < nc);
 #pragma unroll
-        for (int j = 0; j < MC; ++j)
-            rc[j] = (cval[j] && Z >= 0 && Z < nc) ? ec[Z * cplane + cgo[j]] : S(0);
+        for (int j = 0; j < MC; ++j) rc[sl][j] = bload<S>(r, cgb[j]);
     };
-    auto c_write = [&]() {
+    auto c_write = [&](int sl) {
 #pragma unroll
-        for (int j = 0; j < MC; ++j)
-            if (t + j * NT < NC) cL[t + j * NT] = cvt<C>(rc[j]);
+        for (int j = 0; j < MC; ++j) cL[t + j * NT] = cvt<C>(rc[sl][j]);
     };
+    // bilinear value of the staged coarse plane at lane k: the same sum
+    // order and weights as the explicit interpolation operator
     auto q_lds = [&](int k) -> C {
-        C q = C(0);
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-            if (cidx[k][j] >= 0) q += cL[cidx[k][j]];
-        return cw[k] * q;
+        const int i = cc[k] & 0xffff;
+        const bool hx = cc[k] & 0x10000, hy = cc[k] & 0x20000;
+        C q = cL[i];
+        q += hx ? cL[i + 1] : C(0);
+        q += hy ? cL[i + CX] : C(0);
+        q += (hx && hy) ? cL[i + CX + 1] : C(0);
+        return (hx ? C(0.5) : C(1)) * (hy ? C(0.5) : C(1)) * q;
     };
     auto q_direct = [&](int k, int Z) -> C {
         if (Z < 0 || Z >= nc) return C(0);
-        C q = C(0);
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-            if (cidx[k][j] >= 0) {
-                const int c = cidx[k][j];
-                q += cvt<C>(ec[Z * cplane + (cy0 + c / CX) * nc + cx0 + c % CX]);
-            }
-        return cw[k] * q;
+        const int i = cc[k] & 0xffff;
+        const bool hx = cc[k] & 0x10000, hy = cc[k] & 0x20000;
+        const int gx = cx0 + i % CX, gy = cy0 + i / CX;
+        auto at = [&](int X, int Y) -> C {
+            return (X >= 0 && X < nc && Y >= 0 && Y < nc) ? cvt<C>(ec[Z * cplane + Y * nc + X])
+                                                          : C(0);
+        };
+        C q = at(gx, gy);
+        q += hx ? at(gx + 1, gy) : C(0);
+        q += hy ? at(gx, gy + 1) : C(0);
+        q += (hx && hy) ? at(gx + 1, gy + 1) : C(0);
+        return (hx ? C(0.5) : C(1)) * (hy ? C(0.5) : C(1)) * q;
     };
 
-    // ---- raw prefetch registers: ru[k] = plane s+2+k, rb[k] = b plane s+1+k
-    S ru[PD + 1][M], rb[PD + 1][M], rr2[PD + 1];
+    // ---- prefetch ring: raw u (and ring-2 value) of plane p and raw b of
+    // plane p live in slot (p - s0) % (PD + 1); written by the loads, read
+    // once when consumed.  b is consumed PD steps after its load, u PD + 1.
+    // The marching loop is unrolled UN times: a multiple of the ring length
+    // and of the PRO parity keeps every slot index static, and a multiple of
+    // 3 (the u/r plane rotation) leaves no register copies at the latch.
+    constexpr int RS = PD + 1;
+    constexpr int UR = UN;
+    static_assert(UN % RS == 0 && UN % 2 == 0, "unroll covers the prefetch ring and parity");
+    S ru[RS][M], rb[RS][M], rr2[RS];
     auto issue_u = [&](int p, int k) {
+        const rsrc_t r = line_rsrc(u, (long)p * plane, plane, p >= 0 && p < n);
 #pragma unroll
-        for (int m = 0; m < M; ++m)
-            ru[k][m] = (!ZG && val[m] && p >= 0 && p < n) ? u[p * plane + go[m]] : S(0);
-        rr2[k] = (!ZG && r2v && p >= 0 && p < n) ? u[p * plane + r2g] : S(0);
+        for (int m = 0; m < M; ++m) ru[k][m] = bload<S>(r, gb[m]);
+        rr2[k] = bload<S>(r, r2b);
     };
     auto issue_b = [&](int p, int k) {
+        const rsrc_t r = line_rsrc(b, (long)p * plane, plane, p >= 0 && p < n);
 #pragma unroll
-        for (int m = 0; m < M; ++m)
-            rb[k][m] = (val[m] && p >= 0 && p < n) ? b[p * plane + go[m]] : S(0);
+        for (int m = 0; m < M; ++m) rb[k][m] = bload<S>(r, gb[m]);
     };
-    // consume raw plane p from slot 0: v = u + pf * P ec (zero off the grid);
-    // qh holds the bilinear coarse values of plane p/2 when p is even
-    auto take_u = [&](int p, const C* qh, C* dst, C& rdst) {
+    // consume raw plane p from slot sl: v = u + pf * P ec; qh holds the
+    // bilinear coarse values of plane p/2 when p is even
+    auto take_u = [&](int p, int sl, const C* qh, C* dst, C& rdst) {
 #pragma unroll
         for (int m = 0; m < M + 1; ++m) {
-            C v = cvt<C>(m < M ? ru[0][m] : rr2[0]);
+            C v = cvt<C>(m < M ? ru[sl][m] : rr2[sl]);
             if (PRO) {
                 C pe;
                 if ((p & 1) == 0) {
@@ -261,19 +373,8 @@ k_smooth3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out
             if (m < M) dst[m] = v; else rdst = v;
         }
     };
-    auto shift = [&]() {
-#pragma unroll
-        for (int k = 0; k < PD; ++k) {
-#pragma unroll
-            for (int m = 0; m < M; ++m) {
-                ru[k][m] = ru[k + 1][m];
-                rb[k][m] = rb[k + 1][m];
-            }
-            rr2[k] = rr2[k + 1];
-        }
-    };
 
-    C um1[M], u0[M], up1[M], b0[M], rm2[M], rm1[M], r0[M];
+    C um1[M], u0[M], up1[M], rm2[M], rm1[M], r0[M];
     C ur0 = 0, urp1 = 0;
     double nacc = 0.0;
     const int s0 = z0 - 1;
@@ -287,97 +388,94 @@ k_smooth3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out
             for (int k = 0; k < M + 1; ++k) qprev[k] = q_direct(k, zp);
         }
         C dummy;
+        if (!ZG) {
 #pragma unroll
-        for (int q = 0; q < 3; ++q) {
-            const int p = s0 - 1 + q;
-            issue_u(p, 0);
-            if (PRO && (p & 1) == 0) {
+            for (int q = 0; q < 3; ++q) {
+                const int p = s0 - 1 + q;
+                issue_u(p, 0);
+                if (PRO && (p & 1) == 0) {
 #pragma unroll
-                for (int k = 0; k < M + 1; ++k) qh[k] = q_direct(k, p / 2);
+                    for (int k = 0; k < M + 1; ++k) qh[k] = q_direct(k, p / 2);
+                }
+                C* dst = q == 0 ? um1 : (q == 1 ? u0 : up1);
+                take_u(p, 0, qh, dst, q == 1 ? ur0 : (q == 2 ? urp1 : dummy));
             }
-            C* dst = q == 0 ? um1 : (q == 1 ? u0 : up1);
-            take_u(p, qh, dst, q == 1 ? ur0 : (q == 2 ? urp1 : dummy));
         }
+#pragma unroll
+        for (int m = 0; m < M; ++m) rm2[m] = rm1[m] = C(0);
         issue_b(s0, 0);
 #pragma unroll
-        for (int m = 0; m < M; ++m) {
-            b0[m] = cvt<C>(rb[0][m]);
-            rm2[m] = rm1[m] = C(0);
+        for (int q = 1; q < PD; ++q) issue_b(s0 + q, q);
+        if (!ZG) {
+#pragma unroll
+            for (int q = 0; q < PD; ++q) issue_u(s0 + 2 + q, (2 + q) % RS);
         }
-        for (int k = 0; k < PD; ++k) {
-            issue_u(s0 + 2 + k, k);
-            issue_b(s0 + 1 + k, k);
-        }
+        // s0 is odd (the launch uses even chunks); coarse plane (s0+3)/2 + j
+        // goes to the slot of the even step that would have issued it
         if (PRO) {
-            if ((s0 & 1) == 0) {
-                c_issue((s0 + 2) / 2);
-                c_write();
-            } else {
-                c_issue((s0 + 3) / 2);
-            }
+#pragma unroll
+            for (int j = 0; j < CD; ++j)
+                c_issue((s0 + 3) / 2 + j, (((1 + 2 * j - 2 * CD + 2 * UN) % UN) >> 1) % RCS);
         }
     }
     if (!ZG) {
         const int sl = (s0 + 2) & 1;
 #pragma unroll
-        for (int m = 0; m < M; ++m)
-            if (inr[m]) uL[sl][ul[m]] = u0[m];
-        if (t < NR2) uL[sl][r2l] = ur0;
+        for (int m = 0; m < M; ++m) uL[sl][ul[m]] = u0[m];
+        uL[sl][r2l] = ur0;
     }
 
-    for (int s = s0; s <= z1; ++s) {
+    auto step = [&](int s, auto kc) {
+        constexpr int k = decltype(kc)::k;  // (s - s0) % UR
         __syncthreads();
         const int cur = (s + 2) & 1;
-        // prefetch: v plane s+2+PD and b plane s+1+PD; coarse plane for PRO
-        issue_u(s + 2 + PD, PD);
-        issue_b(s + 1 + PD, PD);
-        if (PRO && (s & 1) == 0) c_issue((s + 4) / 2);
+        // prefetch: v plane s+2+PD and b plane s+PD into the slots consumed
+        // last step; coarse plane for PRO
+        if (!ZG) issue_u(s + 2 + PD, (k + 1) % RS);
+        issue_b(s + PD, (k + PD) % RS);
+        // s even (s0 odd): coarse plane needed 2 CD steps later
+        if (PRO && (k & 1) == 1) c_issue((s + 2 + 2 * CD) / 2, (k >> 1) % RCS);
         // residual of plane s on the tile plus ring 1
         const bool pin = s >= 0 && s < n;
 #pragma unroll
         for (int m = 0; m < M; ++m) {
-            C r = C(0);
-            if (val[m] && pin) {
-                if (ZG) {
-                    r = b0[m];
-                } else {
-                    const C* U = uL[cur];
-                    const int q = ul[m];
-                    const C lap = C(6) * u0[m] - U[q - 1] - U[q + 1] - U[q - UX] -
-                                  U[q + UX] - um1[m] - up1[m];
-                    r = b0[m] - sA * lap;
-                }
+            C r = cvt<C>(rb[k % RS][m]);
+            if (!ZG) {
+                const C* U = uL[cur];
+                const int q = ul[m];
+                const C lap = C(6) * u0[m] - U[q - 1] - U[q + 1] - U[q - UX] - U[q + UX] -
+                              um1[m] - up1[m];
+                r = (pin && val[m]) ? r - sA * lap : C(0);
             }
             r0[m] = r;
-            if (inr[m]) rL[cur][rl[m]] = r;
+            rL[cur][RP + t + m * NT] = r;
         }
         // smoothed plane s - 1
         const int p = s - 1;
-        if (p >= z0) {
+        if (p >= z0 && p < z1) {
             const C* R = rL[cur ^ 1];
+            const rsrc_t ro = line_rsrc(out, (long)p * plane, plane, true);
 #pragma unroll
             for (int m = 0; m < M; ++m) {
-                if (!inn[m]) continue;
-                const int q = rl[m];
+                const int q = RP + t + m * NT;
                 const C rc0 = rm1[m];
                 const C nbs = R[q - 1] + R[q + 1] + R[q - RX] + R[q + RX] + rm2[m] + r0[m];
                 const C v = (ZG ? C(0) : um1[m]) + sW * (c0 * rc0 + c1 * nbs);
-                out[p * plane + go[m]] = static_cast<S>(v);
-                if (NORM) nacc += (double)rc0 * (double)rc0;
+                bstore<NTS>(static_cast<S>(v), ro, inn[m] ? gb[m] : kOob);
+                if (NORM) nacc += inn[m] ? (double)rc0 * (double)rc0 : 0.0;
             }
         }
         // v of plane s + 1 into the other LDS slot
         if (!ZG) {
 #pragma unroll
-            for (int m = 0; m < M; ++m)
-                if (inr[m]) uL[cur ^ 1][ul[m]] = up1[m];
-            if (t < NR2) uL[cur ^ 1][r2l] = urp1;
+            for (int m = 0; m < M; ++m) uL[cur ^ 1][ul[m]] = up1[m];
+            uL[cur ^ 1][r2l] = urp1;
         }
-        // rotate: consume plane s+2 of v and plane s+1 of b
+        // rotate: consume plane s+2 of v
         C qh[M + 1];
-        if (PRO && (s & 1) == 0) {
+        if (PRO && (k & 1) == 1) {  // s even
 #pragma unroll
-            for (int k = 0; k < M + 1; ++k) qh[k] = q_lds(k);
+            for (int j = 0; j < M + 1; ++j) qh[j] = q_lds(j);
         }
 #pragma unroll
         for (int m = 0; m < M; ++m) {
@@ -385,12 +483,12 @@ k_smooth3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out
             u0[m] = up1[m];
             rm2[m] = rm1[m];
             rm1[m] = r0[m];
-            b0[m] = cvt<C>(rb[0][m]);
         }
-        if (!ZG) take_u(s + 2, qh, up1, urp1);
-        shift();
-        if (PRO && (s & 1) == 1) c_write();
-    }
+        if (!ZG) take_u(s + 2, (k + 2) % RS, qh, up1, urp1);
+        // s odd: stage coarse plane (s+3)/2, loaded 2 CD - 1 steps ago
+        if (PRO && (k & 1) == 0) c_write((((k - 2 * CD + 1 + UN) % UN) >> 1) % RCS);
+    };
+    march<UR>(s0, z1, step);
     if (NORM) {
         const double sm = block_sum<NT>(nacc, red);
         if (t == 0) partials[(long)blockIdx.y * gridDim.x + blockIdx.x] = sm;
@@ -402,21 +500,28 @@ k_smooth3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out
 // outputs marching over rows.  The residual of row s is computed on the
 // strip plus a ring of 1; output lags by two rows because the 9-point
 // stencil needs the residual of rows p-1..p+1 at x-1..x+1 from LDS (4 row
-// slots).  PRO stages the coarse row under each even fine row in LDS.
+// slots).  PRO stages the coarse row under each even fine row in LDS.  As in
+// 3D, every lane runs the same instruction stream (row buffer resources,
+// LDS scratch slots for lanes past the strip, selects for off-grid points).
 // ---------------------------------------------------------------------------
-template <typename S, typename C, int TX, int NT, int PD, bool ZG, bool NORM, bool PRO>
+template <typename S, typename C, int TX, int NT, int PD, int UN, bool ZG, bool NORM, bool PRO,
+          bool NTS>
 __global__ void __launch_bounds__(NT)
 k_smooth2d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out,
            int n, int tiles_x, int ychunk, int nchunks, C sA, C sW, C c0, C c1,
            C c2, double* __restrict__ partials, const S* __restrict__ ec, int nc, C pf) {
     constexpr int RX = TX + 2, UX = TX + 4;
     constexpr int M = (RX + NT - 1) / NT;
-    constexpr int CX = TX / 2 + 3;
+    constexpr int CX = TX / 2 + 4;
     constexpr int MC = (CX + NT - 1) / NT;
+    // residual rows: slot t + m * NT at offset 1, one guard entry each side;
+    // u rows: column x0 - 2 + j at j, lanes past the strip use UD + lane
+    constexpr int RSZ = M * NT + 2;
+    constexpr int UD = UX + 1, USZ = UD + 65;
     static_assert(TX % 2 == 0, "even strips");
-    __shared__ C uL[2][ZG ? 1 : UX];
-    __shared__ C rL[4][RX];
-    __shared__ C cL[PRO ? CX : 1];
+    __shared__ C uL[2][ZG ? 1 : USZ];
+    __shared__ C rL[4][RSZ];
+    __shared__ C cL[PRO ? MC * NT : 1];
     __shared__ double red[NT / 64];
 
     const int total = tiles_x * nchunks;
@@ -430,90 +535,105 @@ k_smooth2d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out
     const int x0 = tx * TX;
     const int y0 = ch * ychunk, y1 = min(y0 + ychunk, n);
     const int t = threadIdx.x;
+    const int lane = t & 63;
 
-    int go[M];
-    bool inr[M], val[M], inn[M];
+    int ul[M];
+    unsigned gb[M];
+    bool val[M], inn[M];
 #pragma unroll
     for (int m = 0; m < M; ++m) {
         const int i = t + m * NT;
-        inr[m] = i < RX;
+        const bool inr = i < RX;
         const int gx = x0 - 1 + i;
-        val[m] = inr[m] && gx >= 0 && gx < n;
+        val[m] = inr && gx >= 0 && gx < n;
         inn[m] = val[m] && i >= 1 && i <= TX;
-        go[m] = val[m] ? gx : 0;
+        ul[m] = inr ? i + 1 : UD + lane;
+        gb[m] = val[m] ? (unsigned)(gx * (int)sizeof(S)) : kOob;
     }
     // ring-2 columns x0-2 (thread 0) and x0+TX+1 (thread 1)
+    const bool r2in = !ZG && t < 2;
     const int r2x = (t == 0) ? x0 - 2 : x0 + TX + 1;
-    const int r2l = (t == 0) ? 0 : UX - 1;
-    const bool r2v = !ZG && t < 2 && r2x >= 0 && r2x < n;
+    const int r2l = r2in ? (t == 0 ? 0 : UX - 1) : UD + lane;
+    const unsigned r2b =
+        (r2in && r2x >= 0 && r2x < n) ? (unsigned)(r2x * (int)sizeof(S)) : kOob;
 
+    // fused coarse correction: LDS index of the left coarse neighbour and a
+    // flag for the second node
     const int cx0 = x0 / 2 - 2;
-    int cidx[M + 1][2];
-    C cw[M + 1], qprev[M + 1];
-    int cgo[MC];
-    bool cval[MC];
-    S rc[MC];
+    int cc[M + 1];
+    C qprev[M + 1];
+    unsigned cgb[MC];
+    // coarse planes are loaded CD even steps ahead into RCS register slots
+    constexpr int RCS = UN / 2, CD = RCS >= 2 ? 2 : 1;
+    S rc[RCS][MC];
     if (PRO) {
         ec += (long)blockIdx.y * nc * nc;
         auto setup = [&](int k, bool ok, int gx) {
-            int xa, xb;
-            const int nx = interp_idx(gx, nc, &xa, &xb);
-            cw[k] = nx == 1 ? C(1) : C(0.5);
-            cidx[k][0] = (ok && xa >= 0) ? xa - cx0 : -1;
-            cidx[k][1] = (ok && nx == 2 && xb >= 0) ? xb - cx0 : -1;
+            const int g = gx + 1;
+            cc[k] = ok ? ((g >> 1) - 1 - cx0) | ((g & 1) << 16) : 0;
             qprev[k] = C(0);
         };
 #pragma unroll
-        for (int m = 0; m < M; ++m) setup(m, val[m], x0 - 1 + t + m * NT);
-        setup(M, r2v, r2x);
+        for (int m = 0; m < M; ++m) setup(m, t + m * NT < RX, x0 - 1 + t + m * NT);
+        setup(M, r2in, r2x);
 #pragma unroll
         for (int j = 0; j < MC; ++j) {
             const int i = t + j * NT;
             const int gx = cx0 + i;
-            cval[j] = i < CX && gx >= 0 && gx < nc;
-            cgo[j] = cval[j] ? gx : 0;
+            cgb[j] = (i < CX && gx >= 0 && gx < nc) ? (unsigned)(gx * (int)sizeof(S)) : kOob;
         }
     }
-    auto c_issue = [&](int Y) {
+    auto c_issue = [&](int Y, int sl) {
+        const rsrc_t r = line_rsrc(ec, (long)Y * nc, nc, Y >= 0 && Y < nc);
 #pragma unroll
-        for (int j = 0; j < MC; ++j)
-            rc[j] = (cval[j] && Y >= 0 && Y < nc) ? ec[(long)Y * nc + cgo[j]] : S(0);
+        for (int j = 0; j < MC; ++j) rc[sl][j] = bload<S>(r, cgb[j]);
     };
-    auto c_write = [&]() {
+    auto c_write = [&](int sl) {
 #pragma unroll
-        for (int j = 0; j < MC; ++j)
-            if (t + j * NT < CX) cL[t + j * NT] = cvt<C>(rc[j]);
+        for (int j = 0; j < MC; ++j) cL[t + j * NT] = cvt<C>(rc[sl][j]);
     };
     auto q_lds = [&](int k) -> C {
-        C q = C(0);
-        if (cidx[k][0] >= 0) q += cL[cidx[k][0]];
-        if (cidx[k][1] >= 0) q += cL[cidx[k][1]];
-        return cw[k] * q;
+        const int i = cc[k] & 0xffff;
+        const bool hx = cc[k] & 0x10000;
+        C q = cL[i];
+        q += hx ? cL[i + 1] : C(0);
+        return (hx ? C(0.5) : C(1)) * q;
     };
     auto q_direct = [&](int k, int Y) -> C {
         if (Y < 0 || Y >= nc) return C(0);
-        C q = C(0);
-        if (cidx[k][0] >= 0) q += cvt<C>(ec[(long)Y * nc + cx0 + cidx[k][0]]);
-        if (cidx[k][1] >= 0) q += cvt<C>(ec[(long)Y * nc + cx0 + cidx[k][1]]);
-        return cw[k] * q;
+        const int i = cc[k] & 0xffff;
+        const bool hx = cc[k] & 0x10000;
+        const int gx = cx0 + i;
+        auto at = [&](int X) -> C {
+            return (X >= 0 && X < nc) ? cvt<C>(ec[(long)Y * nc + X]) : C(0);
+        };
+        C q = at(gx);
+        q += hx ? at(gx + 1) : C(0);
+        return (hx ? C(0.5) : C(1)) * q;
     };
 
-    S ru[PD + 1][M], rb[PD + 1][M], rr2[PD + 1];
+    // prefetch ring, as in 3D: u of row p and b of row p in slot
+    // (p - s0) % (PD + 1); b is consumed PD steps after its load.  Unrolled
+    // UN times (a multiple of 4 matches the four-row rotation)
+    constexpr int RS = PD + 1;
+    constexpr int UR = UN;
+    static_assert(UN % RS == 0 && UN % 2 == 0, "unroll covers the prefetch ring and parity");
+    S ru[RS][M], rb[RS][M], rr2[RS];
     auto issue_u = [&](int p, int k) {
+        const rsrc_t r = line_rsrc(u, (long)p * n, n, p >= 0 && p < n);
 #pragma unroll
-        for (int m = 0; m < M; ++m)
-            ru[k][m] = (!ZG && val[m] && p >= 0 && p < n) ? u[(long)p * n + go[m]] : S(0);
-        rr2[k] = (r2v && p >= 0 && p < n) ? u[(long)p * n + r2x] : S(0);
+        for (int m = 0; m < M; ++m) ru[k][m] = bload<S>(r, gb[m]);
+        rr2[k] = bload<S>(r, r2b);
     };
     auto issue_b = [&](int p, int k) {
+        const rsrc_t r = line_rsrc(b, (long)p * n, n, p >= 0 && p < n);
 #pragma unroll
-        for (int m = 0; m < M; ++m)
-            rb[k][m] = (val[m] && p >= 0 && p < n) ? b[(long)p * n + go[m]] : S(0);
+        for (int m = 0; m < M; ++m) rb[k][m] = bload<S>(r, gb[m]);
     };
-    auto take_u = [&](int p, const C* qh, C* dst, C& rdst) {
+    auto take_u = [&](int p, int sl, const C* qh, C* dst, C& rdst) {
 #pragma unroll
         for (int m = 0; m < M + 1; ++m) {
-            C v = cvt<C>(m < M ? ru[0][m] : rr2[0]);
+            C v = cvt<C>(m < M ? ru[sl][m] : rr2[sl]);
             if (PRO) {
                 C pe;
                 if ((p & 1) == 0) {
@@ -527,19 +647,8 @@ k_smooth2d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out
             if (m < M) dst[m] = v; else rdst = v;
         }
     };
-    auto shift = [&]() {
-#pragma unroll
-        for (int k = 0; k < PD; ++k) {
-#pragma unroll
-            for (int m = 0; m < M; ++m) {
-                ru[k][m] = ru[k + 1][m];
-                rb[k][m] = rb[k + 1][m];
-            }
-            rr2[k] = rr2[k + 1];
-        }
-    };
 
-    C um2[M], um1[M], u0[M], up1[M], b0[M];
+    C um2[M], um1[M], u0[M], up1[M];
     C ur0 = 0, urp1 = 0;
     double nacc = 0.0;
     const int s0 = y0 - 1;
@@ -552,106 +661,102 @@ k_smooth2d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out
             for (int k = 0; k < M + 1; ++k) qprev[k] = q_direct(k, yp);
         }
         C dummy;
+        if (!ZG) {
 #pragma unroll
-        for (int q = 0; q < 3; ++q) {
-            const int p = s0 - 1 + q;
-            issue_u(p, 0);
-            if (PRO && (p & 1) == 0) {
+            for (int q = 0; q < 3; ++q) {
+                const int p = s0 - 1 + q;
+                issue_u(p, 0);
+                if (PRO && (p & 1) == 0) {
 #pragma unroll
-                for (int k = 0; k < M + 1; ++k) qh[k] = q_direct(k, p / 2);
+                    for (int k = 0; k < M + 1; ++k) qh[k] = q_direct(k, p / 2);
+                }
+                C* dst = q == 0 ? um1 : (q == 1 ? u0 : up1);
+                take_u(p, 0, qh, dst, q == 1 ? ur0 : (q == 2 ? urp1 : dummy));
             }
-            C* dst = q == 0 ? um1 : (q == 1 ? u0 : up1);
-            take_u(p, qh, dst, q == 1 ? ur0 : (q == 2 ? urp1 : dummy));
         }
+#pragma unroll
+        for (int m = 0; m < M; ++m) um2[m] = C(0);
         issue_b(s0, 0);
 #pragma unroll
-        for (int m = 0; m < M; ++m) {
-            um2[m] = C(0);
-            b0[m] = cvt<C>(rb[0][m]);
+        for (int q = 1; q < PD; ++q) issue_b(s0 + q, q);
+        if (!ZG) {
+#pragma unroll
+            for (int q = 0; q < PD; ++q) issue_u(s0 + 2 + q, (2 + q) % RS);
         }
-        for (int k = 0; k < PD; ++k) {
-            issue_u(s0 + 2 + k, k);
-            issue_b(s0 + 1 + k, k);
-        }
+        // s0 is odd (the launch uses even chunks); coarse plane (s0+3)/2 + j
+        // goes to the slot of the even step that would have issued it
         if (PRO) {
-            if ((s0 & 1) == 0) {
-                c_issue((s0 + 2) / 2);
-                c_write();
-            } else {
-                c_issue((s0 + 3) / 2);
-            }
+#pragma unroll
+            for (int j = 0; j < CD; ++j)
+                c_issue((s0 + 3) / 2 + j, (((1 + 2 * j - 2 * CD + 2 * UN) % UN) >> 1) % RCS);
         }
     }
     if (!ZG) {
         const int sl = (s0 + 2) & 1;
 #pragma unroll
-        for (int m = 0; m < M; ++m)
-            if (inr[m]) uL[sl][t + m * NT + 1] = u0[m];
-        if (t < 2) uL[sl][r2l] = ur0;
+        for (int m = 0; m < M; ++m) uL[sl][ul[m]] = u0[m];
+        uL[sl][r2l] = ur0;
     }
 
-    for (int s = s0; s <= y1 + 1; ++s) {
+    auto step = [&](int s, auto kc) {
+        constexpr int k = decltype(kc)::k;  // (s - s0) % UR
         __syncthreads();
         const int cur = (s + 2) & 1;
         const int rs = (s + 4) & 3;
-        issue_u(s + 2 + PD, PD);
-        issue_b(s + 1 + PD, PD);
-        if (PRO && (s & 1) == 0) c_issue((s + 4) / 2);
+        if (!ZG) issue_u(s + 2 + PD, (k + 1) % RS);
+        issue_b(s + PD, (k + PD) % RS);
+        // s even (s0 odd): coarse plane needed 2 CD steps later
+        if (PRO && (k & 1) == 1) c_issue((s + 2 + 2 * CD) / 2, (k >> 1) % RCS);
         const bool pin = s >= 0 && s < n;
 #pragma unroll
         for (int m = 0; m < M; ++m) {
-            C r = C(0);
-            const int i = t + m * NT;
-            if (val[m] && pin) {
-                if (ZG) {
-                    r = b0[m];
-                } else {
-                    const C* U = uL[cur];
-                    const C lap = C(4) * u0[m] - U[i] - U[i + 2] - um1[m] - up1[m];
-                    r = b0[m] - sA * lap;
-                }
+            C r = cvt<C>(rb[k % RS][m]);
+            if (!ZG) {
+                const C* U = uL[cur];
+                const int q = ul[m];
+                const C lap = C(4) * u0[m] - U[q - 1] - U[q + 1] - um1[m] - up1[m];
+                r = (pin && val[m]) ? r - sA * lap : C(0);
             }
-            if (inr[m]) rL[rs][i] = r;
+            rL[rs][1 + t + m * NT] = r;
         }
         const int p = s - 2;
-        if (p >= y0) {
+        if (p >= y0 && p < y1) {
             const C* R0 = rL[(p + 3) & 3];  // row p - 1
             const C* R1 = rL[(p + 4) & 3];  // row p
             const C* R2 = rL[(p + 5) & 3];  // row p + 1
+            const rsrc_t ro = line_rsrc(out, (long)p * n, n, true);
 #pragma unroll
             for (int m = 0; m < M; ++m) {
-                if (!inn[m]) continue;
-                const int i = t + m * NT;
-                const C rcc = R1[i];
-                const C fc = R1[i - 1] + R1[i + 1] + R0[i] + R2[i];
-                const C cn = R0[i - 1] + R0[i + 1] + R2[i - 1] + R2[i + 1];
+                const int q = 1 + t + m * NT;
+                const C rcc = R1[q];
+                const C fc = R1[q - 1] + R1[q + 1] + R0[q] + R2[q];
+                const C cn = R0[q - 1] + R0[q + 1] + R2[q - 1] + R2[q + 1];
                 const C v = (ZG ? C(0) : um2[m]) + sW * (c0 * rcc + c1 * fc + c2 * cn);
-                out[(long)p * n + go[m]] = static_cast<S>(v);
-                if (NORM) nacc += (double)rcc * (double)rcc;
+                bstore<NTS>(static_cast<S>(v), ro, inn[m] ? gb[m] : kOob);
+                if (NORM) nacc += inn[m] ? (double)rcc * (double)rcc : 0.0;
             }
         }
         if (!ZG) {
 #pragma unroll
-            for (int m = 0; m < M; ++m)
-                if (inr[m]) uL[cur ^ 1][t + m * NT + 1] = up1[m];
-            if (t < 2) uL[cur ^ 1][r2l] = urp1;
+            for (int m = 0; m < M; ++m) uL[cur ^ 1][ul[m]] = up1[m];
+            uL[cur ^ 1][r2l] = urp1;
         }
         C qh[M + 1];
-        if (PRO && (s & 1) == 0) {
+        if (PRO && (k & 1) == 1) {  // s even
 #pragma unroll
-            for (int k = 0; k < M + 1; ++k) qh[k] = q_lds(k);
+            for (int j = 0; j < M + 1; ++j) qh[j] = q_lds(j);
         }
 #pragma unroll
         for (int m = 0; m < M; ++m) {
             um2[m] = um1[m];
             um1[m] = u0[m];
             u0[m] = up1[m];
-            b0[m] = cvt<C>(rb[0][m]);
         }
-        if (!ZG) take_u(s + 2, qh, up1, urp1);
-        shift();
-        if (PRO && (s & 1) == 1) c_write();
-    }
+        if (!ZG) take_u(s + 2, (k + 2) % RS, qh, up1, urp1);
+        // s odd: stage coarse plane (s+3)/2, loaded 2 CD - 1 steps ago
+        if (PRO && (k & 1) == 0) c_write((((k - 2 * CD + 1 + UN) % UN) >> 1) % RCS);
+    };
+    march<UR>(s0, y1 + 1, step);
     if (NORM) {
         const double sm = block_sum<NT>(nacc, red);
         if (t == 0) partials[(long)blockIdx.y * gridDim.x + blockIdx.x] = sm;
@@ -682,6 +787,7 @@ k_restrict3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ b
     const int tx = lg % tiles_x, ty = (lg / tiles_x) % tiles_y,
               ch = lg / (tiles_x * tiles_y);
     const long plane = (long)n * n, cplane = (long)nc * nc;
+    const bool nt = plane * n >= kNtMinPts;
     u += (long)blockIdx.y * plane * n;
     b += (long)blockIdx.y * plane * n;
     bc += (long)blockIdx.y * cplane * nc;
@@ -715,28 +821,17 @@ k_restrict3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ b
         r2v = gx >= 0 && gx < n && gy >= 0 && gy < n;
         r2g = r2v ? gy * n + gx : 0;
     }
-    S ru[RPD + 1][M], rb[RPD + 1][M], rr2[RPD + 1];
+    S ru[2][M], rb[2][M], rr2[2];  // prefetch slots by plane parity
     auto issue_u = [&](int p, int k) {
 #pragma unroll
         for (int m = 0; m < M; ++m)
-            ru[k][m] = (val[m] && p >= 0 && p < n) ? u[p * plane + go[m]] : S(0);
-        rr2[k] = (r2v && p >= 0 && p < n) ? u[p * plane + r2g] : S(0);
+            ru[k][m] = u[(val[m] && p >= 0 && p < n) ? p * plane + go[m] : 0];
+        rr2[k] = u[(r2v && p >= 0 && p < n) ? p * plane + r2g : 0];
     };
     auto issue_b = [&](int p, int k) {
 #pragma unroll
         for (int m = 0; m < M; ++m)
-            rb[k][m] = (val[m] && p >= 0 && p < n) ? b[p * plane + go[m]] : S(0);
-    };
-    auto shift = [&]() {
-#pragma unroll
-        for (int k = 0; k < RPD; ++k) {
-#pragma unroll
-            for (int m = 0; m < M; ++m) {
-                ru[k][m] = ru[k + 1][m];
-                rb[k][m] = rb[k + 1][m];
-            }
-            rr2[k] = rr2[k + 1];
-        }
+            rb[k][m] = b[(val[m] && p >= 0 && p < n) ? p * plane + go[m] : 0];
     };
     const int cx = t % TXc, cy = t / TXc;
     const bool cval = (cx0 + cx) < nc && (cy0 + cy) < nc;
@@ -749,30 +844,31 @@ k_restrict3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ b
         C dummy;
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
-            issue_u(f0 - 1 + q, 0);
+            const int p = f0 - 1 + q;
+            const bool pin = p >= 0 && p < n;
+            issue_u(p, 0);
             C* dst = q == 0 ? um1 : (q == 1 ? u0 : up1);
 #pragma unroll
-            for (int m = 0; m < M; ++m) dst[m] = cvt<C>(ru[0][m]);
-            (q == 1 ? ur0 : (q == 2 ? urp1 : dummy)) = cvt<C>(rr2[0]);
+            for (int m = 0; m < M; ++m) dst[m] = (pin && val[m]) ? cvt<C>(ru[0][m]) : C(0);
+            (q == 1 ? ur0 : (q == 2 ? urp1 : dummy)) = (pin && r2v) ? cvt<C>(rr2[0]) : C(0);
         }
         issue_b(f0, 0);
 #pragma unroll
         for (int m = 0; m < M; ++m) b0[m] = cvt<C>(rb[0][m]);
-        for (int k = 0; k < RPD; ++k) {
-            issue_u(f0 + 2 + k, k);
-            issue_b(f0 + 1 + k, k);
-        }
+        issue_u(f0 + 2, 0);
+        issue_b(f0 + 1, 1);
         const int sl = f0 & 1;
 #pragma unroll
         for (int m = 0; m < M; ++m)
             if (inr[m]) uL[sl][ul[m]] = u0[m];
         if (t < NR2) uL[sl][r2l] = ur0;
     }
-    for (int s = f0; s <= f1 + 1; ++s) {
+    auto step = [&](int s, auto kc) {
+        constexpr int k = decltype(kc)::k;  // (s - f0) & 1
         __syncthreads();
         const int cur = s & 1;
-        issue_u(s + 2 + RPD, RPD);
-        issue_b(s + 1 + RPD, RPD);
+        issue_u(s + 3, k ^ 1);
+        issue_b(s + 2, k);
         if (s <= f1) {
 #pragma unroll
             for (int m = 0; m < M; ++m) {
@@ -798,7 +894,7 @@ k_restrict3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ b
                 if (f > f0) {
                     acc += C(0.25) * xs;
                     const int Zc = f / 2 - 1;
-                    if (cval) bc[Zc * cplane + cgo] = static_cast<S>(acc);
+                    if (cval) st_out(&bc[Zc * cplane + cgo], static_cast<S>(acc), nt);
                 }
                 acc = C(0.25) * xs;
             } else {
@@ -809,15 +905,20 @@ k_restrict3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ b
         for (int m = 0; m < M; ++m)
             if (inr[m]) uL[cur ^ 1][ul[m]] = up1[m];
         if (t < NR2) uL[cur ^ 1][r2l] = urp1;
+        const bool pin2 = s + 2 >= 0 && s + 2 < n;
 #pragma unroll
         for (int m = 0; m < M; ++m) {
             um1[m] = u0[m];
             u0[m] = up1[m];
-            up1[m] = cvt<C>(ru[0][m]);
-            b0[m] = cvt<C>(rb[0][m]);
+            up1[m] = (pin2 && val[m]) ? cvt<C>(ru[k][m]) : C(0);
+            b0[m] = cvt<C>(rb[k ^ 1][m]);
         }
-        urp1 = cvt<C>(rr2[0]);
-        shift();
+        urp1 = (pin2 && r2v) ? cvt<C>(rr2[k]) : C(0);
+    };
+    for (int s = f0; s <= f1 + 1; s += 2) {
+        step(s, Par<0>());
+        if (s + 1 > f1 + 1) break;
+        step(s + 1, Par<1>());
     }
 }
 
@@ -838,6 +939,7 @@ k_restrict2d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ b
     const int total = tiles_x * nchunks;
     const int lg = xcd_remap(blockIdx.x, total);
     const int tx = lg % tiles_x, ch = lg / tiles_x;
+    const bool nt = (long)n * n >= kNtMinPts;
     u += (long)blockIdx.y * n * n;
     b += (long)blockIdx.y * n * n;
     bc += (long)blockIdx.y * nc * nc;
@@ -858,28 +960,17 @@ k_restrict2d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ b
     const int r2x = (t == 0) ? fx0 - 1 : fx0 + FX;
     const int r2l = (t == 0) ? 0 : UX - 1;
     const bool r2v = t < 2 && r2x >= 0 && r2x < n;
-    S ru[RPD + 1][M], rb[RPD + 1][M], rr2[RPD + 1];
+    S ru[2][M], rb[2][M], rr2[2];  // prefetch slots by plane parity
     auto issue_u = [&](int p, int k) {
 #pragma unroll
         for (int m = 0; m < M; ++m)
-            ru[k][m] = (val[m] && p >= 0 && p < n) ? u[(long)p * n + go[m]] : S(0);
-        rr2[k] = (r2v && p >= 0 && p < n) ? u[(long)p * n + r2x] : S(0);
+            ru[k][m] = u[(val[m] && p >= 0 && p < n) ? (long)p * n + go[m] : 0];
+        rr2[k] = u[(r2v && p >= 0 && p < n) ? (long)p * n + r2x : 0];
     };
     auto issue_b = [&](int p, int k) {
 #pragma unroll
         for (int m = 0; m < M; ++m)
-            rb[k][m] = (val[m] && p >= 0 && p < n) ? b[(long)p * n + go[m]] : S(0);
-    };
-    auto shift = [&]() {
-#pragma unroll
-        for (int k = 0; k < RPD; ++k) {
-#pragma unroll
-            for (int m = 0; m < M; ++m) {
-                ru[k][m] = ru[k + 1][m];
-                rb[k][m] = rb[k + 1][m];
-            }
-            rr2[k] = rr2[k + 1];
-        }
+            rb[k][m] = b[(val[m] && p >= 0 && p < n) ? (long)p * n + go[m] : 0];
     };
     const bool cval = (cx0 + t) < nc;
 
@@ -890,30 +981,31 @@ k_restrict2d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ b
         C dummy;
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
-            issue_u(f0 - 1 + q, 0);
+            const int p = f0 - 1 + q;
+            const bool pin = p >= 0 && p < n;
+            issue_u(p, 0);
             C* dst = q == 0 ? um1 : (q == 1 ? u0 : up1);
 #pragma unroll
-            for (int m = 0; m < M; ++m) dst[m] = cvt<C>(ru[0][m]);
-            (q == 1 ? ur0 : (q == 2 ? urp1 : dummy)) = cvt<C>(rr2[0]);
+            for (int m = 0; m < M; ++m) dst[m] = (pin && val[m]) ? cvt<C>(ru[0][m]) : C(0);
+            (q == 1 ? ur0 : (q == 2 ? urp1 : dummy)) = (pin && r2v) ? cvt<C>(rr2[0]) : C(0);
         }
         issue_b(f0, 0);
 #pragma unroll
         for (int m = 0; m < M; ++m) b0[m] = cvt<C>(rb[0][m]);
-        for (int k = 0; k < RPD; ++k) {
-            issue_u(f0 + 2 + k, k);
-            issue_b(f0 + 1 + k, k);
-        }
+        issue_u(f0 + 2, 0);
+        issue_b(f0 + 1, 1);
         const int sl = f0 & 1;
 #pragma unroll
         for (int m = 0; m < M; ++m)
             if (inr[m]) uL[sl][t + m * NT + 1] = u0[m];
         if (t < 2) uL[sl][r2l] = ur0;
     }
-    for (int s = f0; s <= f1 + 1; ++s) {
+    auto step = [&](int s, auto kc) {
+        constexpr int k = decltype(kc)::k;  // (s - f0) & 1
         __syncthreads();
         const int cur = s & 1;
-        issue_u(s + 2 + RPD, RPD);
-        issue_b(s + 1 + RPD, RPD);
+        issue_u(s + 3, k ^ 1);
+        issue_b(s + 2, k);
         if (s <= f1) {
 #pragma unroll
             for (int m = 0; m < M; ++m) {
@@ -936,7 +1028,7 @@ k_restrict2d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ b
                 if (f > f0) {
                     acc += C(0.25) * xs;
                     const int Yc = f / 2 - 1;
-                    if (cval) bc[(long)Yc * nc + cx0 + t] = static_cast<S>(acc);
+                    if (cval) st_out(&bc[(long)Yc * nc + cx0 + t], static_cast<S>(acc), nt);
                 }
                 acc = C(0.25) * xs;
             } else {
@@ -947,15 +1039,20 @@ k_restrict2d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ b
         for (int m = 0; m < M; ++m)
             if (inr[m]) uL[cur ^ 1][t + m * NT + 1] = up1[m];
         if (t < 2) uL[cur ^ 1][r2l] = urp1;
+        const bool pin2 = s + 2 >= 0 && s + 2 < n;
 #pragma unroll
         for (int m = 0; m < M; ++m) {
             um1[m] = u0[m];
             u0[m] = up1[m];
-            up1[m] = cvt<C>(ru[0][m]);
-            b0[m] = cvt<C>(rb[0][m]);
+            up1[m] = (pin2 && val[m]) ? cvt<C>(ru[k][m]) : C(0);
+            b0[m] = cvt<C>(rb[k ^ 1][m]);
         }
-        urp1 = cvt<C>(rr2[0]);
-        shift();
+        urp1 = (pin2 && r2v) ? cvt<C>(rr2[k]) : C(0);
+    };
+    for (int s = f0; s <= f1 + 1; s += 2) {
+        step(s, Par<0>());
+        if (s + 1 > f1 + 1) break;
+        step(s + 1, Par<1>());
     }
 }
 
@@ -985,7 +1082,7 @@ k_prolong2d(const S* __restrict__ ec, S* __restrict__ u, int n, int nc, C pf) {
         s += e(ia, jb);
         if (ni == 2) s += e(ib, jb);
     }
-    u[idx] = static_cast<S>(cvt<C>(u[idx]) + pf * (wi * wj) * s);
+    st_out(&u[idx], static_cast<S>(cvt<C>(u[idx]) + pf * (wi * wj) * s), area >= kNtMinPts);
 }
 
 template <typename S, typename C>
@@ -1009,7 +1106,7 @@ k_prolong3d(const S* __restrict__ ec, S* __restrict__ u, int n, int nc, C pf) {
             for (int a = 0; a < ni; ++a)
                 if (xi[a] >= 0 && yj[bq] >= 0 && zk[c] >= 0)
                     s += cvt<C>(ec[((long)zk[c] * nc + yj[bq]) * nc + xi[a]]);
-    u[idx] = static_cast<S>(cvt<C>(u[idx]) + pf * w * s);
+    st_out(&u[idx], static_cast<S>(cvt<C>(u[idx]) + pf * w * s), vol >= kNtMinPts);
 }
 
 // ---------------------------------------------------------------------------
@@ -1282,6 +1379,7 @@ k_ir3d(const double* __restrict__ u, double* __restrict__ unew, const S* __restr
     const int tx = lg % tiles_x, ty = (lg / tiles_x) % tiles_y,
               ch = lg / (tiles_x * tiles_y);
     const long plane = (long)n * n, boff = (long)blockIdx.y * plane * n;
+    const bool nt = plane * n >= kNtMinPts;
     u += boff;
     unew += boff;
     b += boff;
@@ -1308,59 +1406,55 @@ k_ir3d(const double* __restrict__ u, double* __restrict__ unew, const S* __restr
     }
     // raw prefetch: ru/re[k] = plane s+2+k of u and e, rb[k] = b plane s+1+k
     const bool hase = e != nullptr && k > 0;
-    double ru[IPD + 1][M], rb[IPD + 1][M];
-    S re[IPD + 1][M];
+    // e is read unconditionally (no branch around the loads, so the wait
+    // counters stay exact); without a correction the values come from b,
+    // which is as large, and are discarded by the select in take()
+    const S* esrc = hase ? e : reinterpret_cast<const S*>(b);
+    double ru[2][M], rb[2][M];  // prefetch slots by plane parity
+    S re[2][M];
+    bool okq[2][M];
     auto issue = [&](int p, int q) {
 #pragma unroll
         for (int m = 0; m < M; ++m) {
             const bool ok = val[m] && p >= 0 && p < n;
-            const long g = p * plane + go[m];
-            ru[q][m] = ok ? u[g] : 0.0;
-            re[q][m] = (ok && hase) ? e[g] : S(0);
+            const long g = ok ? p * plane + go[m] : 0;
+            ru[q][m] = u[g];
+            re[q][m] = esrc[g];
+            okq[q][m] = ok;
         }
     };
     auto issue_b = [&](int p, int q) {
 #pragma unroll
         for (int m = 0; m < M; ++m)
-            rb[q][m] = (inn[m] && p >= 0 && p < n) ? b[p * plane + go[m]] : 0.0;
+            rb[q][m] = b[(inn[m] && p >= 0 && p < n) ? p * plane + go[m] : 0];
     };
-    auto take = [&](double* dst) {
+    auto take = [&](double* dst, int sl) {
 #pragma unroll
-        for (int m = 0; m < M; ++m) dst[m] = ru[0][m] + escale * (double)re[0][m];
-    };
-    auto shift = [&]() {
-#pragma unroll
-        for (int q = 0; q < IPD; ++q)
-#pragma unroll
-            for (int m = 0; m < M; ++m) {
-                ru[q][m] = ru[q + 1][m];
-                re[q][m] = re[q + 1][m];
-                rb[q][m] = rb[q + 1][m];
-            }
+        for (int m = 0; m < M; ++m)
+            dst[m] = okq[sl][m] ? (hase ? ru[sl][m] + escale * (double)re[sl][m] : ru[sl][m]) : 0.0;
     };
     double um1[M], u0[M], up1[M], b0[M];
     double acc = 0.0, mx = 0.0;
     issue(z0 - 1, 0);
-    take(um1);
+    take(um1, 0);
     issue(z0, 0);
-    take(u0);
+    take(u0, 0);
     issue(z0 + 1, 0);
-    take(up1);
+    take(up1, 0);
     issue_b(z0, 0);
 #pragma unroll
     for (int m = 0; m < M; ++m) b0[m] = rb[0][m];
-    for (int q = 0; q < IPD; ++q) {
-        issue(z0 + 2 + q, q);
-        issue_b(z0 + 1 + q, q);
-    }
+    issue(z0 + 2, 0);
+    issue_b(z0 + 1, 1);
 #pragma unroll
     for (int m = 0; m < M; ++m)
         if (inr[m]) uL[z0 & 1][t + m * NT] = u0[m];
-    for (int s = z0; s < z1; ++s) {
+    auto step = [&](int s, auto kc) {
+        constexpr int k = decltype(kc)::k;  // (s - z0) & 1
         __syncthreads();
         const int cur = s & 1;
-        issue(s + 2 + IPD, IPD);
-        issue_b(s + 1 + IPD, IPD);
+        issue(s + 3, k ^ 1);
+        issue_b(s + 2, k);
         const double* U = uL[cur];
 #pragma unroll
         for (int m = 0; m < M; ++m) {
@@ -1370,8 +1464,8 @@ k_ir3d(const double* __restrict__ u, double* __restrict__ unew, const S* __restr
             const double lap = 6.0 * u0[m] - U[q - 1] - U[q + 1] - U[q - RX] - U[q + RX] -
                                um1[m] - up1[m];
             const double r = b0[m] - inv_h2 * lap;
-            unew[g] = u0[m];
-            rlo[g] = static_cast<S>(s_new * r);
+            st_out(&unew[g], u0[m], nt);
+            st_out(&rlo[g], static_cast<S>(s_new * r), nt);
             acc += r * r;
             mx = fmax(mx, fabs(r));
         }
@@ -1382,10 +1476,14 @@ k_ir3d(const double* __restrict__ u, double* __restrict__ unew, const S* __restr
         for (int m = 0; m < M; ++m) {
             um1[m] = u0[m];
             u0[m] = up1[m];
-            b0[m] = rb[0][m];
+            b0[m] = rb[k ^ 1][m];
         }
-        take(up1);
-        shift();
+        take(up1, k);
+    };
+    for (int s = z0; s < z1; s += 2) {
+        step(s, Par<0>());
+        if (s + 1 >= z1) break;
+        step(s + 1, Par<1>());
     }
     const double ts = block_sum<NT>(acc, red);
     __syncthreads();
@@ -1412,6 +1510,7 @@ k_ir2d(const double* __restrict__ u, double* __restrict__ unew, const S* __restr
     const int lg = xcd_remap(blockIdx.x, total);
     const int tx = lg % tiles_x, ch = lg / tiles_x;
     const long area = (long)n * n, boff = (long)blockIdx.y * area;
+    const bool nt = area >= kNtMinPts;
     u += boff;
     unew += boff;
     b += boff;
@@ -1435,59 +1534,55 @@ k_ir2d(const double* __restrict__ u, double* __restrict__ unew, const S* __restr
         go[m] = val[m] ? gx : 0;
     }
     const bool hase = e != nullptr && k > 0;
-    double ru[IPD + 1][M], rb[IPD + 1][M];
-    S re[IPD + 1][M];
+    // e is read unconditionally (no branch around the loads, so the wait
+    // counters stay exact); without a correction the values come from b,
+    // which is as large, and are discarded by the select in take()
+    const S* esrc = hase ? e : reinterpret_cast<const S*>(b);
+    double ru[2][M], rb[2][M];  // prefetch slots by plane parity
+    S re[2][M];
+    bool okq[2][M];
     auto issue = [&](int p, int q) {
 #pragma unroll
         for (int m = 0; m < M; ++m) {
             const bool ok = val[m] && p >= 0 && p < n;
-            const long g = (long)p * n + go[m];
-            ru[q][m] = ok ? u[g] : 0.0;
-            re[q][m] = (ok && hase) ? e[g] : S(0);
+            const long g = ok ? (long)p * n + go[m] : 0;
+            ru[q][m] = u[g];
+            re[q][m] = esrc[g];
+            okq[q][m] = ok;
         }
     };
     auto issue_b = [&](int p, int q) {
 #pragma unroll
         for (int m = 0; m < M; ++m)
-            rb[q][m] = (inn[m] && p >= 0 && p < n) ? b[(long)p * n + go[m]] : 0.0;
+            rb[q][m] = b[(inn[m] && p >= 0 && p < n) ? (long)p * n + go[m] : 0];
     };
-    auto take = [&](double* dst) {
+    auto take = [&](double* dst, int sl) {
 #pragma unroll
-        for (int m = 0; m < M; ++m) dst[m] = ru[0][m] + escale * (double)re[0][m];
-    };
-    auto shift = [&]() {
-#pragma unroll
-        for (int q = 0; q < IPD; ++q)
-#pragma unroll
-            for (int m = 0; m < M; ++m) {
-                ru[q][m] = ru[q + 1][m];
-                re[q][m] = re[q + 1][m];
-                rb[q][m] = rb[q + 1][m];
-            }
+        for (int m = 0; m < M; ++m)
+            dst[m] = okq[sl][m] ? (hase ? ru[sl][m] + escale * (double)re[sl][m] : ru[sl][m]) : 0.0;
     };
     double um1[M], u0[M], up1[M], b0[M];
     double acc = 0.0, mx = 0.0;
     issue(y0 - 1, 0);
-    take(um1);
+    take(um1, 0);
     issue(y0, 0);
-    take(u0);
+    take(u0, 0);
     issue(y0 + 1, 0);
-    take(up1);
+    take(up1, 0);
     issue_b(y0, 0);
 #pragma unroll
     for (int m = 0; m < M; ++m) b0[m] = rb[0][m];
-    for (int q = 0; q < IPD; ++q) {
-        issue(y0 + 2 + q, q);
-        issue_b(y0 + 1 + q, q);
-    }
+    issue(y0 + 2, 0);
+    issue_b(y0 + 1, 1);
 #pragma unroll
     for (int m = 0; m < M; ++m)
         if (inr[m]) uL[y0 & 1][t + m * NT] = u0[m];
-    for (int s = y0; s < y1; ++s) {
+    auto step = [&](int s, auto kc) {
+        constexpr int k = decltype(kc)::k;  // (s - y0) & 1
         __syncthreads();
         const int cur = s & 1;
-        issue(s + 2 + IPD, IPD);
-        issue_b(s + 1 + IPD, IPD);
+        issue(s + 3, k ^ 1);
+        issue_b(s + 2, k);
         const double* U = uL[cur];
 #pragma unroll
         for (int m = 0; m < M; ++m) {
@@ -1496,8 +1591,8 @@ k_ir2d(const double* __restrict__ u, double* __restrict__ unew, const S* __restr
             const long g = (long)s * n + go[m];
             const double lap = 4.0 * u0[m] - U[q - 1] - U[q + 1] - um1[m] - up1[m];
             const double r = b0[m] - inv_h2 * lap;
-            unew[g] = u0[m];
-            rlo[g] = static_cast<S>(s_new * r);
+            st_out(&unew[g], u0[m], nt);
+            st_out(&rlo[g], static_cast<S>(s_new * r), nt);
             acc += r * r;
             mx = fmax(mx, fabs(r));
         }
@@ -1508,10 +1603,14 @@ k_ir2d(const double* __restrict__ u, double* __restrict__ unew, const S* __restr
         for (int m = 0; m < M; ++m) {
             um1[m] = u0[m];
             u0[m] = up1[m];
-            b0[m] = rb[0][m];
+            b0[m] = rb[k ^ 1][m];
         }
-        take(up1);
-        shift();
+        take(up1, k);
+    };
+    for (int s = y0; s < y1; s += 2) {
+        step(s, Par<0>());
+        if (s + 1 >= y1) break;
+        step(s + 1, Par<1>());
     }
     const double ts = block_sum<NT>(acc, red);
     __syncthreads();
@@ -1580,9 +1679,9 @@ inline int pick_chunk(int n, int tiles, int want, int minc) {
     return ch;
 }
 
-constexpr int S3_TX = 64, S3_TY = 32, S3_NT = 512;
+constexpr int S3_TX = 64, S3_TY = 16, S3_NT = 640;
 constexpr int S3S_TX = 64, S3S_TY = 16, S3S_NT = 256;
-constexpr int S2_TX = 1024, S2_NT = 512;
+constexpr int S2_TX = 1024, S2_NT = 576;
 constexpr int S2S_TX = 256, S2S_NT = 256;
 constexpr int S_PD = 1;
 constexpr int R3_TX = 32, R3_TY = 8;
@@ -1590,7 +1689,7 @@ constexpr int R2_TX = 256;
 constexpr int I3_TX = 64, I3_TY = 16, I3_NT = 256;
 constexpr int I2_TX = 256;
 constexpr int kWantBlocks = 1024;
-constexpr int kWantBlocks3D = 256;
+constexpr int kWantBlocksLarge = 256;  // one long march per CU on large grids
 
 // chunk length along the marching direction: long chunks on large grids
 // (fewer halo planes re-read), one plane per workgroup on small grids, where
@@ -1599,6 +1698,9 @@ inline int march_chunk(int n, int tiles, long pts, int want, int minc_large) {
     const int minc = pts >= (1L << 22) ? minc_large : 1;
     return pick_chunk(n, tiles, want, minc);
 }
+
+// the fused-correction sweep assumes every chunk starts on an even plane
+inline int even_chunk(int c) { return c + (c & 1); }
 
 template <typename S, typename C>
 hipError_t smooth_impl(bool zg, bool norm, const Sweep& s, hipStream_t st, int* nparts) {
@@ -1613,15 +1715,18 @@ hipError_t smooth_impl(bool zg, bool norm, const Sweep& s, hipStream_t st, int* 
     const C pf = C(s.pf);
     if (zg && (norm || pro)) return hipErrorInvalidValue;
     if (norm && pro) return hipErrorInvalidValue;
+    // buffer offsets are 32-bit byte offsets within one plane
+    if (s.d == 3 && (long)n * n * (long)sizeof(S) > 0x7fffffffL) return hipErrorInvalidValue;
+    // large 3D grids (at least 200^3 > 2^22 nodes) store non-temporally
     if (s.d == 3 && n >= 200) {
         const int tx = cdiv(n, S3_TX), ty = cdiv(n, S3_TY);
-        const int zc = march_chunk(n, tx * ty, (long)n * n * n, kWantBlocks3D, 32);
+        const int zc = even_chunk(march_chunk(n, tx * ty, (long)n * n * n, kWantBlocksLarge, 32));
         const int nch = cdiv(n, zc);
         dim3 grid(tx * ty * nch, s.batch);
         if (nparts) *nparts = grid.x * grid.y;
         if (norm && (long)grid.x * grid.y > s.partials_cap) return hipErrorInvalidValue;
 #define L3(ZG, NM, PR)                                                                  \
-    hipLaunchKernelGGL((k_smooth3d<S, C, S3_TX, S3_TY, S3_NT, S_PD, ZG, NM, PR>), grid,\
+    hipLaunchKernelGGL((k_smooth3d<S, C, S3_TX, S3_TY, S3_NT, (PR ? 2 : S_PD), 6, ZG, NM, PR, true>), grid,\
                        dim3(S3_NT), 0, st, u, b, out, n, tx, ty, zc, nch, sA, sW, c0,   \
                        c1, s.partials, ec, nc, pf)
         if (zg) L3(true, false, false);
@@ -1631,13 +1736,13 @@ hipError_t smooth_impl(bool zg, bool norm, const Sweep& s, hipStream_t st, int* 
 #undef L3
     } else if (s.d == 3) {
         const int tx = cdiv(n, S3S_TX), ty = cdiv(n, S3S_TY);
-        const int zc = march_chunk(n, tx * ty, (long)n * n * n, kWantBlocks, 8);
+        const int zc = even_chunk(march_chunk(n, tx * ty, (long)n * n * n, kWantBlocks, 8));
         const int nch = cdiv(n, zc);
         dim3 grid(tx * ty * nch, s.batch);
         if (nparts) *nparts = grid.x * grid.y;
         if (norm && (long)grid.x * grid.y > s.partials_cap) return hipErrorInvalidValue;
 #define L3(ZG, NM, PR)                                                                     \
-    hipLaunchKernelGGL((k_smooth3d<S, C, S3S_TX, S3S_TY, S3S_NT, S_PD, ZG, NM, PR>), grid, \
+    hipLaunchKernelGGL((k_smooth3d<S, C, S3S_TX, S3S_TY, S3S_NT, S_PD, 2, ZG, NM, PR, false>), grid, \
                        dim3(S3S_NT), 0, st, u, b, out, n, tx, ty, zc, nch, sA, sW, c0,     \
                        c1, s.partials, ec, nc, pf)
         if (zg) L3(true, false, false);
@@ -1646,15 +1751,16 @@ hipError_t smooth_impl(bool zg, bool norm, const Sweep& s, hipStream_t st, int* 
         else L3(false, false, false);
 #undef L3
     } else if (n >= 3000) {
-        // large grids: wide strips, chunk length per variant (measured)
+        // large grids (at least 3000^2 > 2^22 nodes, non-temporal stores):
+        // wide strips, chunk length per variant (measured)
         const int tx = cdiv(n, S2_TX);
-        const int yc = march_chunk(n, tx, (long)n * n, kWantBlocks, pro ? 64 : 16);
+        const int yc = even_chunk(march_chunk(n, tx, (long)n * n, kWantBlocksLarge, 32));
         const int nch = cdiv(n, yc);
         dim3 grid(tx * nch, s.batch);
         if (nparts) *nparts = grid.x * grid.y;
         if (norm && (long)grid.x * grid.y > s.partials_cap) return hipErrorInvalidValue;
 #define L2(ZG, NM, PR)                                                                  \
-    hipLaunchKernelGGL((k_smooth2d<S, C, S2_TX, S2_NT, S_PD, ZG, NM, PR>), grid, dim3(S2_NT),\
+    hipLaunchKernelGGL((k_smooth2d<S, C, S2_TX, S2_NT, S_PD, 4, ZG, NM, PR, true>), grid, dim3(S2_NT),\
                        0, st, u, b, out, n, tx, yc, nch, sA, sW, c0, c1, c2, s.partials, \
                        ec, nc, pf)
         if (zg) L2(true, false, false);
@@ -1664,13 +1770,13 @@ hipError_t smooth_impl(bool zg, bool norm, const Sweep& s, hipStream_t st, int* 
 #undef L2
     } else {
         const int tx = cdiv(n, S2S_TX);
-        const int yc = march_chunk(n, tx, (long)n * n, kWantBlocks, pro ? 64 : 16);
+        const int yc = even_chunk(march_chunk(n, tx, (long)n * n, kWantBlocks, pro ? 64 : 16));
         const int nch = cdiv(n, yc);
         dim3 grid(tx * nch, s.batch);
         if (nparts) *nparts = grid.x * grid.y;
         if (norm && (long)grid.x * grid.y > s.partials_cap) return hipErrorInvalidValue;
 #define L2(ZG, NM, PR)                                                                     \
-    hipLaunchKernelGGL((k_smooth2d<S, C, S2S_TX, S2S_NT, S_PD, ZG, NM, PR>), grid,         \
+    hipLaunchKernelGGL((k_smooth2d<S, C, S2S_TX, S2S_NT, S_PD, 2, ZG, NM, PR, false>), grid,  \
                        dim3(S2S_NT), 0, st, u, b, out, n, tx, yc, nch, sA, sW, c0, c1, c2, \
                        s.partials, ec, nc, pf)
         if (zg) L2(true, false, false);
