@@ -765,29 +765,34 @@ k_smooth2d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out
 
 // ---------------------------------------------------------------------------
 // 3D fused residual + full-weighting restriction: bc = R (b - sA L u).
-// Coarse tile TXc x TYc (one coarse column per thread); the fine residual is
-// computed plane by plane on the (2TXc+1) x (2TYc+1) fine window and reduced
-// in xy; the z weights (1/4, 1/2, 1/4) are accumulated in registers.
+// Coarse tile TXc x TYc; the fine residual is computed plane by plane on the
+// (2TXc+1) x (2TYc+1) fine window (lanes own window points, NT chosen so
+// that about two points per lane cover it) and reduced in xy by one thread
+// per coarse column; the z weights (1/4, 1/2, 1/4) are accumulated in
+// registers.  Same branch-free buffer addressing and prefetch ring as the
+// smoothers.
 // ---------------------------------------------------------------------------
-template <typename S, typename C, int TXc, int TYc, int RPD>
-__global__ void __launch_bounds__(TXc * TYc)
+template <typename S, typename C, int TXc, int TYc, int NT, int UN>
+__global__ void __launch_bounds__(NT)
 k_restrict3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ bc,
              int n, int nc, int tiles_x, int tiles_y, int zchunk, int nchunks, C sA) {
-    constexpr int NT = TXc * TYc;
     constexpr int FX = 2 * TXc + 1, FY = 2 * TYc + 1, NF = FX * FY;
     constexpr int UX = FX + 2, UY = FY + 2, NU = UX * UY;
     constexpr int M = (NF + NT - 1) / NT;
     constexpr int NR2 = 2 * FX + 2 * FY;
-    static_assert(NR2 <= NT, "one thread per ring point");
-    __shared__ C uL[2][NU];
-    __shared__ C rL[2][NF];
+    constexpr int RP = FX + 1, RSZ = RP + M * NT + FX + 1;
+    constexpr int UD = NU + UX, USZ = NU + 2 * UX + 65;
+    constexpr int RS = 2;  // prefetch ring: one plane ahead
+    static_assert(NR2 <= NT && TXc * TYc <= NT, "ring and coarse columns fit the workgroup");
+    static_assert(UN % 2 == 0, "unroll covers the prefetch ring and the plane parity");
+    __shared__ C uL[2][USZ];
+    __shared__ C rL[2][RSZ];
 
     const int total = tiles_x * tiles_y * nchunks;
     const int lg = xcd_remap(blockIdx.x, total);
     const int tx = lg % tiles_x, ty = (lg / tiles_x) % tiles_y,
               ch = lg / (tiles_x * tiles_y);
     const long plane = (long)n * n, cplane = (long)nc * nc;
-    const bool nt = plane * n >= kNtMinPts;
     u += (long)blockIdx.y * plane * n;
     b += (long)blockIdx.y * plane * n;
     bc += (long)blockIdx.y * cplane * nc;
@@ -795,21 +800,23 @@ k_restrict3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ b
     const int Z0 = ch * zchunk, Z1 = min(Z0 + zchunk, nc);
     const int fx0 = 2 * cx0, fy0 = 2 * cy0;  // fine index of window origin
     const int t = threadIdx.x;
+    const int lane = t & 63;
 
-    int ul[M], go[M];
-    bool inr[M], val[M];
+    int ul[M];
+    unsigned gb[M];
+    bool val[M];
 #pragma unroll
     for (int m = 0; m < M; ++m) {
         const int i = t + m * NT;
-        inr[m] = i < NF;
+        const bool inr = i < NF;
         const int lx = i % FX, ly = i / FX;
         const int gx = fx0 + lx, gy = fy0 + ly;
-        val[m] = inr[m] && gx < n && gy < n;
-        ul[m] = inr[m] ? (ly + 1) * UX + lx + 1 : 0;
-        go[m] = val[m] ? gy * n + gx : 0;
+        val[m] = inr && gx < n && gy < n;
+        ul[m] = inr ? (ly + 1) * UX + lx + 1 : UD + lane;
+        gb[m] = val[m] ? (unsigned)((gy * n + gx) * (int)sizeof(S)) : kOob;
     }
-    int r2l = 0, r2g = 0;
-    bool r2v = false;
+    int r2l = UD + lane;
+    unsigned r2b = kOob;
     if (t < NR2) {
         int ux, uy;
         if (t < FX) { ux = 1 + t; uy = 0; }
@@ -818,83 +825,76 @@ k_restrict3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ b
         else { ux = UX - 1; uy = 1 + t - 2 * FX - FY; }
         const int gx = fx0 - 1 + ux, gy = fy0 - 1 + uy;
         r2l = uy * UX + ux;
-        r2v = gx >= 0 && gx < n && gy >= 0 && gy < n;
-        r2g = r2v ? gy * n + gx : 0;
+        if (gx >= 0 && gx < n && gy >= 0 && gy < n) r2b = (unsigned)((gy * n + gx) * (int)sizeof(S));
     }
-    S ru[2][M], rb[2][M], rr2[2];  // prefetch slots by plane parity
+    S ru[RS][M], rb[RS][M], rr2[RS];
     auto issue_u = [&](int p, int k) {
+        const rsrc_t r = line_rsrc(u, (long)p * plane, plane, p >= 0 && p < n);
 #pragma unroll
-        for (int m = 0; m < M; ++m)
-            ru[k][m] = u[(val[m] && p >= 0 && p < n) ? p * plane + go[m] : 0];
-        rr2[k] = u[(r2v && p >= 0 && p < n) ? p * plane + r2g : 0];
+        for (int m = 0; m < M; ++m) ru[k][m] = bload<S>(r, gb[m]);
+        rr2[k] = bload<S>(r, r2b);
     };
     auto issue_b = [&](int p, int k) {
+        const rsrc_t r = line_rsrc(b, (long)p * plane, plane, p >= 0 && p < n);
 #pragma unroll
-        for (int m = 0; m < M; ++m)
-            rb[k][m] = b[(val[m] && p >= 0 && p < n) ? p * plane + go[m] : 0];
+        for (int m = 0; m < M; ++m) rb[k][m] = bload<S>(r, gb[m]);
     };
+    // coarse column of this thread and its window centre
     const int cx = t % TXc, cy = t / TXc;
-    const bool cval = (cx0 + cx) < nc && (cy0 + cy) < nc;
-    const int cgo = (cy0 + cy) * nc + cx0 + cx;
+    const bool cin = t < TXc * TYc;
+    const unsigned cgb = (cin && cx0 + cx < nc && cy0 + cy < nc)
+                             ? (unsigned)(((cy0 + cy) * nc + cx0 + cx) * (int)sizeof(S))
+                             : kOob;
+    const int cq = RP + (cin ? (2 * cy + 1) * FX + 2 * cx + 1 : FX + 1);
 
-    C um1[M], u0[M], up1[M], b0[M];
+    C um1[M], u0[M], up1[M];
     C ur0 = 0, urp1 = 0, acc = 0;
     const int f0 = 2 * Z0, f1 = 2 * Z1;  // fine planes f0..f1 contribute
     {
         C dummy;
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
-            const int p = f0 - 1 + q;
-            const bool pin = p >= 0 && p < n;
-            issue_u(p, 0);
+            issue_u(f0 - 1 + q, 0);
             C* dst = q == 0 ? um1 : (q == 1 ? u0 : up1);
 #pragma unroll
-            for (int m = 0; m < M; ++m) dst[m] = (pin && val[m]) ? cvt<C>(ru[0][m]) : C(0);
-            (q == 1 ? ur0 : (q == 2 ? urp1 : dummy)) = (pin && r2v) ? cvt<C>(rr2[0]) : C(0);
+            for (int m = 0; m < M; ++m) dst[m] = cvt<C>(ru[0][m]);
+            (q == 1 ? ur0 : (q == 2 ? urp1 : dummy)) = cvt<C>(rr2[0]);
         }
         issue_b(f0, 0);
-#pragma unroll
-        for (int m = 0; m < M; ++m) b0[m] = cvt<C>(rb[0][m]);
         issue_u(f0 + 2, 0);
-        issue_b(f0 + 1, 1);
         const int sl = f0 & 1;
 #pragma unroll
-        for (int m = 0; m < M; ++m)
-            if (inr[m]) uL[sl][ul[m]] = u0[m];
-        if (t < NR2) uL[sl][r2l] = ur0;
+        for (int m = 0; m < M; ++m) uL[sl][ul[m]] = u0[m];
+        uL[sl][r2l] = ur0;
     }
     auto step = [&](int s, auto kc) {
-        constexpr int k = decltype(kc)::k;  // (s - f0) & 1
+        constexpr int k = decltype(kc)::k;  // (s - f0) % UN
         __syncthreads();
         const int cur = s & 1;
-        issue_u(s + 3, k ^ 1);
-        issue_b(s + 2, k);
-        if (s <= f1) {
+        issue_u(s + 3, (k + 1) % RS);
+        issue_b(s + 1, (k + 1) % RS);
+        // residual of fine plane s on the window
 #pragma unroll
-            for (int m = 0; m < M; ++m) {
-                C r = C(0);
-                if (val[m]) {
-                    const C* U = uL[cur];
-                    const int q = ul[m];
-                    const C lap = C(6) * u0[m] - U[q - 1] - U[q + 1] - U[q - UX] -
-                                  U[q + UX] - um1[m] - up1[m];
-                    r = b0[m] - sA * lap;
-                }
-                if (inr[m]) rL[cur][t + m * NT] = r;
-            }
+        for (int m = 0; m < M; ++m) {
+            const C* U = uL[cur];
+            const int q = ul[m];
+            const C lap = C(6) * u0[m] - U[q - 1] - U[q + 1] - U[q - UX] - U[q + UX] - um1[m] -
+                          up1[m];
+            const C r = cvt<C>(rb[k % RS][m]) - sA * lap;
+            rL[cur][RP + t + m * NT] = val[m] ? r : C(0);
         }
         const int f = s - 1;  // fine plane whose residual is reduced now
-        if (f >= f0) {
+        if (f >= f0 && f <= f1) {
             const C* R = rL[cur ^ 1];
-            const int q = (2 * cy + 1) * FX + 2 * cx + 1;
+            const int q = cq;
             const C xs = C(0.25) * R[q] +
                          C(0.125) * (R[q - 1] + R[q + 1] + R[q - FX] + R[q + FX]) +
                          C(0.0625) * (R[q - FX - 1] + R[q - FX + 1] + R[q + FX - 1] + R[q + FX + 1]);
-            if (((f - f0) & 1) == 0) {
+            if ((k & 1) == 1) {  // f - f0 even
                 if (f > f0) {
                     acc += C(0.25) * xs;
-                    const int Zc = f / 2 - 1;
-                    if (cval) st_out(&bc[Zc * cplane + cgo], static_cast<S>(acc), nt);
+                    const rsrc_t ro = line_rsrc(bc, (long)(f / 2 - 1) * cplane, cplane, true);
+                    bstore<false>(static_cast<S>(acc), ro, cgb);
                 }
                 acc = C(0.25) * xs;
             } else {
@@ -902,133 +902,124 @@ k_restrict3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ b
             }
         }
 #pragma unroll
-        for (int m = 0; m < M; ++m)
-            if (inr[m]) uL[cur ^ 1][ul[m]] = up1[m];
-        if (t < NR2) uL[cur ^ 1][r2l] = urp1;
-        const bool pin2 = s + 2 >= 0 && s + 2 < n;
+        for (int m = 0; m < M; ++m) uL[cur ^ 1][ul[m]] = up1[m];
+        uL[cur ^ 1][r2l] = urp1;
 #pragma unroll
         for (int m = 0; m < M; ++m) {
             um1[m] = u0[m];
             u0[m] = up1[m];
-            up1[m] = (pin2 && val[m]) ? cvt<C>(ru[k][m]) : C(0);
-            b0[m] = cvt<C>(rb[k ^ 1][m]);
+            up1[m] = cvt<C>(ru[k % RS][m]);
         }
-        urp1 = (pin2 && r2v) ? cvt<C>(rr2[k]) : C(0);
+        urp1 = cvt<C>(rr2[k % RS]);
     };
-    for (int s = f0; s <= f1 + 1; s += 2) {
-        step(s, Par<0>());
-        if (s + 1 > f1 + 1) break;
-        step(s + 1, Par<1>());
-    }
+    march<UN>(f0, f1 + 1, step);
 }
 
 // ---------------------------------------------------------------------------
 // 2D fused residual + full-weighting restriction: a strip of TXc coarse
-// columns (one per thread), marching over fine rows.
+// columns (window of 2 TXc + 1 fine columns owned by NT lanes), marching
+// over fine rows.
 // ---------------------------------------------------------------------------
-template <typename S, typename C, int TXc, int RPD>
-__global__ void __launch_bounds__(TXc)
+template <typename S, typename C, int TXc, int NT, int UN>
+__global__ void __launch_bounds__(NT)
 k_restrict2d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ bc,
              int n, int nc, int tiles_x, int ychunk, int nchunks, C sA) {
-    constexpr int NT = TXc;
     constexpr int FX = 2 * TXc + 1, UX = FX + 2;
     constexpr int M = (FX + NT - 1) / NT;
-    __shared__ C uL[2][UX];
-    __shared__ C rL[2][FX];
+    constexpr int RSZ = M * NT + 2;
+    constexpr int UD = UX + 1, USZ = UD + 65;
+    constexpr int RS = 2;
+    static_assert(TXc <= NT, "one thread per coarse column");
+    static_assert(UN % 2 == 0, "unroll covers the prefetch ring and the row parity");
+    __shared__ C uL[2][USZ];
+    __shared__ C rL[2][RSZ];
 
     const int total = tiles_x * nchunks;
     const int lg = xcd_remap(blockIdx.x, total);
     const int tx = lg % tiles_x, ch = lg / tiles_x;
-    const bool nt = (long)n * n >= kNtMinPts;
     u += (long)blockIdx.y * n * n;
     b += (long)blockIdx.y * n * n;
     bc += (long)blockIdx.y * nc * nc;
     const int cx0 = tx * TXc, fx0 = 2 * cx0;
     const int Y0 = ch * ychunk, Y1 = min(Y0 + ychunk, nc);
     const int t = threadIdx.x;
+    const int lane = t & 63;
 
-    int go[M];
-    bool inr[M], val[M];
+    int ul[M];
+    unsigned gb[M];
+    bool val[M];
 #pragma unroll
     for (int m = 0; m < M; ++m) {
         const int i = t + m * NT;
-        inr[m] = i < FX;
+        const bool inr = i < FX;
         const int gx = fx0 + i;
-        val[m] = inr[m] && gx < n;
-        go[m] = val[m] ? gx : 0;
+        val[m] = inr && gx < n;
+        ul[m] = inr ? i + 1 : UD + lane;
+        gb[m] = val[m] ? (unsigned)(gx * (int)sizeof(S)) : kOob;
     }
     const int r2x = (t == 0) ? fx0 - 1 : fx0 + FX;
-    const int r2l = (t == 0) ? 0 : UX - 1;
-    const bool r2v = t < 2 && r2x >= 0 && r2x < n;
-    S ru[2][M], rb[2][M], rr2[2];  // prefetch slots by plane parity
+    const int r2l = t < 2 ? (t == 0 ? 0 : UX - 1) : UD + lane;
+    const unsigned r2b =
+        (t < 2 && r2x >= 0 && r2x < n) ? (unsigned)(r2x * (int)sizeof(S)) : kOob;
+    S ru[RS][M], rb[RS][M], rr2[RS];
     auto issue_u = [&](int p, int k) {
+        const rsrc_t r = line_rsrc(u, (long)p * n, n, p >= 0 && p < n);
 #pragma unroll
-        for (int m = 0; m < M; ++m)
-            ru[k][m] = u[(val[m] && p >= 0 && p < n) ? (long)p * n + go[m] : 0];
-        rr2[k] = u[(r2v && p >= 0 && p < n) ? (long)p * n + r2x : 0];
+        for (int m = 0; m < M; ++m) ru[k][m] = bload<S>(r, gb[m]);
+        rr2[k] = bload<S>(r, r2b);
     };
     auto issue_b = [&](int p, int k) {
+        const rsrc_t r = line_rsrc(b, (long)p * n, n, p >= 0 && p < n);
 #pragma unroll
-        for (int m = 0; m < M; ++m)
-            rb[k][m] = b[(val[m] && p >= 0 && p < n) ? (long)p * n + go[m] : 0];
+        for (int m = 0; m < M; ++m) rb[k][m] = bload<S>(r, gb[m]);
     };
-    const bool cval = (cx0 + t) < nc;
+    const unsigned cgb =
+        (t < TXc && cx0 + t < nc) ? (unsigned)((cx0 + t) * (int)sizeof(S)) : kOob;
+    const int cq = 1 + (t < TXc ? 2 * t + 1 : 1);
 
-    C um1[M], u0[M], up1[M], b0[M];
+    C um1[M], u0[M], up1[M];
     C ur0 = 0, urp1 = 0, acc = 0;
     const int f0 = 2 * Y0, f1 = 2 * Y1;
     {
         C dummy;
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
-            const int p = f0 - 1 + q;
-            const bool pin = p >= 0 && p < n;
-            issue_u(p, 0);
+            issue_u(f0 - 1 + q, 0);
             C* dst = q == 0 ? um1 : (q == 1 ? u0 : up1);
 #pragma unroll
-            for (int m = 0; m < M; ++m) dst[m] = (pin && val[m]) ? cvt<C>(ru[0][m]) : C(0);
-            (q == 1 ? ur0 : (q == 2 ? urp1 : dummy)) = (pin && r2v) ? cvt<C>(rr2[0]) : C(0);
+            for (int m = 0; m < M; ++m) dst[m] = cvt<C>(ru[0][m]);
+            (q == 1 ? ur0 : (q == 2 ? urp1 : dummy)) = cvt<C>(rr2[0]);
         }
         issue_b(f0, 0);
-#pragma unroll
-        for (int m = 0; m < M; ++m) b0[m] = cvt<C>(rb[0][m]);
         issue_u(f0 + 2, 0);
-        issue_b(f0 + 1, 1);
         const int sl = f0 & 1;
 #pragma unroll
-        for (int m = 0; m < M; ++m)
-            if (inr[m]) uL[sl][t + m * NT + 1] = u0[m];
-        if (t < 2) uL[sl][r2l] = ur0;
+        for (int m = 0; m < M; ++m) uL[sl][ul[m]] = u0[m];
+        uL[sl][r2l] = ur0;
     }
     auto step = [&](int s, auto kc) {
-        constexpr int k = decltype(kc)::k;  // (s - f0) & 1
+        constexpr int k = decltype(kc)::k;  // (s - f0) % UN
         __syncthreads();
         const int cur = s & 1;
-        issue_u(s + 3, k ^ 1);
-        issue_b(s + 2, k);
-        if (s <= f1) {
+        issue_u(s + 3, (k + 1) % RS);
+        issue_b(s + 1, (k + 1) % RS);
 #pragma unroll
-            for (int m = 0; m < M; ++m) {
-                const int i = t + m * NT;
-                C r = C(0);
-                if (val[m]) {
-                    const C* U = uL[cur];
-                    const C lap = C(4) * u0[m] - U[i] - U[i + 2] - um1[m] - up1[m];
-                    r = b0[m] - sA * lap;
-                }
-                if (inr[m]) rL[cur][i] = r;
-            }
+        for (int m = 0; m < M; ++m) {
+            const C* U = uL[cur];
+            const int q = ul[m];
+            const C lap = C(4) * u0[m] - U[q - 1] - U[q + 1] - um1[m] - up1[m];
+            const C r = cvt<C>(rb[k % RS][m]) - sA * lap;
+            rL[cur][1 + t + m * NT] = val[m] ? r : C(0);
         }
         const int f = s - 1;
-        if (f >= f0) {
+        if (f >= f0 && f <= f1) {
             const C* R = rL[cur ^ 1];
-            const int q = 2 * t + 1;
-            const C xs = C(0.5) * R[q] + C(0.25) * (R[q - 1] + R[q + 1]);
-            if (((f - f0) & 1) == 0) {
+            const C xs = C(0.5) * R[cq] + C(0.25) * (R[cq - 1] + R[cq + 1]);
+            if ((k & 1) == 1) {  // f - f0 even
                 if (f > f0) {
                     acc += C(0.25) * xs;
-                    const int Yc = f / 2 - 1;
-                    if (cval) st_out(&bc[(long)Yc * nc + cx0 + t], static_cast<S>(acc), nt);
+                    const rsrc_t ro = line_rsrc(bc, (long)(f / 2 - 1) * nc, nc, true);
+                    bstore<false>(static_cast<S>(acc), ro, cgb);
                 }
                 acc = C(0.25) * xs;
             } else {
@@ -1036,24 +1027,17 @@ k_restrict2d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ b
             }
         }
 #pragma unroll
-        for (int m = 0; m < M; ++m)
-            if (inr[m]) uL[cur ^ 1][t + m * NT + 1] = up1[m];
-        if (t < 2) uL[cur ^ 1][r2l] = urp1;
-        const bool pin2 = s + 2 >= 0 && s + 2 < n;
+        for (int m = 0; m < M; ++m) uL[cur ^ 1][ul[m]] = up1[m];
+        uL[cur ^ 1][r2l] = urp1;
 #pragma unroll
         for (int m = 0; m < M; ++m) {
             um1[m] = u0[m];
             u0[m] = up1[m];
-            up1[m] = (pin2 && val[m]) ? cvt<C>(ru[k][m]) : C(0);
-            b0[m] = cvt<C>(rb[k ^ 1][m]);
+            up1[m] = cvt<C>(ru[k % RS][m]);
         }
-        urp1 = (pin2 && r2v) ? cvt<C>(rr2[k]) : C(0);
+        urp1 = cvt<C>(rr2[k % RS]);
     };
-    for (int s = f0; s <= f1 + 1; s += 2) {
-        step(s, Par<0>());
-        if (s + 1 > f1 + 1) break;
-        step(s + 1, Par<1>());
-    }
+    march<UN>(f0, f1 + 1, step);
 }
 
 // ---------------------------------------------------------------------------
@@ -1684,8 +1668,8 @@ constexpr int S3S_TX = 64, S3S_TY = 16, S3S_NT = 256;
 constexpr int S2_TX = 1024, S2_NT = 576;
 constexpr int S2S_TX = 256, S2S_NT = 256;
 constexpr int S_PD = 1;
-constexpr int R3_TX = 32, R3_TY = 8;
-constexpr int R2_TX = 256;
+constexpr int R3_TX = 32, R3_TY = 8, R3_NT = 576;
+constexpr int R2_TX = 512, R2_NT = 576;
 constexpr int I3_TX = 64, I3_TY = 16, I3_NT = 256;
 constexpr int I2_TX = 256;
 constexpr int kWantBlocks = 1024;
@@ -1795,20 +1779,33 @@ hipError_t restrict_impl(const Sweep& s, hipStream_t st) {
     const S* b = static_cast<const S*>(s.b);
     S* bc = static_cast<S*>(s.out);
     const C sA = C(s.sA);
+    const long pts = s.d == 3 ? (long)n * n * n : (long)n * n;
+    if (s.d == 3 && (long)n * n * (long)sizeof(S) > 0x7fffffffL) return hipErrorInvalidValue;
+    // large grids: one long march per CU, unrolled 6 times (2 zc + 2 steps);
+    // small grids: many short marches
+    const bool large = pts >= (1L << 22);
     if (s.d == 3) {
         const int tx = cdiv(nc, R3_TX), ty = cdiv(nc, R3_TY);
-        const int zc = march_chunk(nc, tx * ty, (long)n * n * n, kWantBlocks, 16);
+        const int zc = march_chunk(nc, tx * ty, pts, large ? kWantBlocksLarge : kWantBlocks, 8);
         const int nch = cdiv(nc, zc);
         dim3 grid(tx * ty * nch, s.batch);
-        hipLaunchKernelGGL((k_restrict3d<S, C, R3_TX, R3_TY, S_PD>), grid, dim3(R3_TX * R3_TY), 0,
-                           st, u, b, bc, n, nc, tx, ty, zc, nch, sA);
+        if (large)
+            hipLaunchKernelGGL((k_restrict3d<S, C, R3_TX, R3_TY, R3_NT, 6>), grid, dim3(R3_NT), 0,
+                               st, u, b, bc, n, nc, tx, ty, zc, nch, sA);
+        else
+            hipLaunchKernelGGL((k_restrict3d<S, C, R3_TX, R3_TY, R3_NT, 2>), grid, dim3(R3_NT), 0,
+                               st, u, b, bc, n, nc, tx, ty, zc, nch, sA);
     } else {
         const int tx = cdiv(nc, R2_TX);
-        const int yc = march_chunk(nc, tx, (long)n * n, kWantBlocks, 8);
+        const int yc = march_chunk(nc, tx, pts, large ? kWantBlocksLarge : kWantBlocks, 8);
         const int nch = cdiv(nc, yc);
         dim3 grid(tx * nch, s.batch);
-        hipLaunchKernelGGL((k_restrict2d<S, C, R2_TX, S_PD>), grid, dim3(R2_TX), 0, st, u, b, bc,
-                           n, nc, tx, yc, nch, sA);
+        if (large)
+            hipLaunchKernelGGL((k_restrict2d<S, C, R2_TX, R2_NT, 6>), grid, dim3(R2_NT), 0, st, u,
+                               b, bc, n, nc, tx, yc, nch, sA);
+        else
+            hipLaunchKernelGGL((k_restrict2d<S, C, R2_TX, R2_NT, 2>), grid, dim3(R2_NT), 0, st, u,
+                               b, bc, n, nc, tx, yc, nch, sA);
     }
     return hipGetLastError();
 }
