@@ -39,8 +39,6 @@ int fail(int code, const std::string& msg) {
 
 constexpr int kMaxLevels = 20;
 constexpr int kTimeKinds = 8;
-// grids with fewer nodes use a separate correction pass (see cycle())
-constexpr long kFusedCorrectionMinPts = 1L << 19;
 constexpr long kPartialCap = 1 << 17;  // per batch entry
 
 struct Hier {
@@ -389,20 +387,12 @@ int cycle(mg_ctx* h, Hier& H, int l, const void* u_in, const void* b, void* out,
     if (rc) return rc;
     s.u = tmp;
     s.out = out;
-    if (level_pts(h, l) >= kFusedCorrectionMinPts) {
-        // post-smoothing of tmp + pf P e_{l+1} (correction fused into the sweep)
-        s.ec = H.e[l + 1];
-        s.pf = pf;
-        return run_timed(h, MG_TIME_SMOOTH_CORRECT, l, st,
-                         [&] { return launch_smooth(H.p, false, false, s, st, nullptr); });
-    }
-    // small grids are latency bound: a plain correction pass and a plain
-    // sweep start faster than the fused sweep's deeper prologue
-    rc = run_timed(h, MG_TIME_PROLONG, l, st, [&] {
-        return launch_prolong(H.p, h->d, s.n, h->batch, H.e[l + 1], tmp, pf, st);
-    });
-    if (rc) return rc;
-    return run_timed(h, MG_TIME_SMOOTH, l, st,
+    // post-smoothing of tmp + pf P e_{l+1}: the correction is fused into the
+    // sweep on every level (on small grids it costs no more than a plain
+    // sweep, and saves the separate correction launch)
+    s.ec = H.e[l + 1];
+    s.pf = pf;
+    return run_timed(h, MG_TIME_SMOOTH_CORRECT, l, st,
                      [&] { return launch_smooth(H.p, false, false, s, st, nullptr); });
 }
 

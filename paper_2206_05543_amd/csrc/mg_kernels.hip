@@ -306,30 +306,15 @@ k_smooth3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out
 #pragma unroll
         for (int j = 0; j < MC; ++j) cL[t + j * NT] = cvt<C>(rc[sl][j]);
     };
-    // bilinear value of the staged coarse plane at lane k: the same sum
-    // order and weights as the explicit interpolation operator
-    auto q_lds = [&](int k) -> C {
+    // bilinear value at lane k of a coarse plane staged in LDS at `base`:
+    // the same sum order and weights as the explicit interpolation operator
+    auto q_at = [&](const C* base, int k) -> C {
         const int i = cc[k] & 0xffff;
         const bool hx = cc[k] & 0x10000, hy = cc[k] & 0x20000;
-        C q = cL[i];
-        q += hx ? cL[i + 1] : C(0);
-        q += hy ? cL[i + CX] : C(0);
-        q += (hx && hy) ? cL[i + CX + 1] : C(0);
-        return (hx ? C(0.5) : C(1)) * (hy ? C(0.5) : C(1)) * q;
-    };
-    auto q_direct = [&](int k, int Z) -> C {
-        if (Z < 0 || Z >= nc) return C(0);
-        const int i = cc[k] & 0xffff;
-        const bool hx = cc[k] & 0x10000, hy = cc[k] & 0x20000;
-        const int gx = cx0 + i % CX, gy = cy0 + i / CX;
-        auto at = [&](int X, int Y) -> C {
-            return (X >= 0 && X < nc && Y >= 0 && Y < nc) ? cvt<C>(ec[Z * cplane + Y * nc + X])
-                                                          : C(0);
-        };
-        C q = at(gx, gy);
-        q += hx ? at(gx + 1, gy) : C(0);
-        q += hy ? at(gx, gy + 1) : C(0);
-        q += (hx && hy) ? at(gx + 1, gy + 1) : C(0);
+        C q = base[i];
+        q += hx ? base[i + 1] : C(0);
+        q += hy ? base[i + CX] : C(0);
+        q += (hx && hy) ? base[i + CX + 1] : C(0);
         return (hx ? C(0.5) : C(1)) * (hy ? C(0.5) : C(1)) * q;
     };
 
@@ -354,12 +339,12 @@ k_smooth3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out
 #pragma unroll
         for (int m = 0; m < M; ++m) rb[k][m] = bload<S>(r, gb[m]);
     };
-    // consume raw plane p from slot sl: v = u + pf * P ec; qh holds the
-    // bilinear coarse values of plane p/2 when p is even
-    auto take_u = [&](int p, int sl, const C* qh, C* dst, C& rdst) {
+    // consume raw plane p: v = u + pf * P ec; qh holds the bilinear coarse
+    // values of plane p/2 when p is even
+    auto take_raw = [&](int p, const S* raw, S raw2, const C* qh, C* dst, C& rdst) {
 #pragma unroll
         for (int m = 0; m < M + 1; ++m) {
-            C v = cvt<C>(m < M ? ru[sl][m] : rr2[sl]);
+            C v = cvt<C>(m < M ? raw[m] : raw2);
             if (PRO) {
                 C pe;
                 if ((p & 1) == 0) {
@@ -373,39 +358,65 @@ k_smooth3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out
             if (m < M) dst[m] = v; else rdst = v;
         }
     };
+    auto take_u = [&](int p, int sl, const C* qh, C* dst, C& rdst) {
+        take_raw(p, ru[sl], rr2[sl], qh, dst, rdst);
+    };
 
     C um1[M], u0[M], up1[M], rm2[M], rm1[M], r0[M];
     C ur0 = 0, urp1 = 0;
     double nacc = 0.0;
     const int s0 = z0 - 1;
-    // prologue: planes s0-1, s0, s0+1 of v (synchronous), b of plane s0
+    // prologue: every load is issued before the first wait.  v of planes
+    // s0-1, s0, s0+1, b of plane s0 (and the next PD-1), and for PRO the
+    // coarse planes (s0-1)/2 - 1 .. (s0+1)/2, staged in the residual LDS
+    // (not in use before the loop) to interpolate the first three planes.
+    static_assert(!PRO || 3 * MC * NT <= 2 * RSZ, "coarse staging fits the residual LDS");
     {
-        C qh[M + 1];
-        if (PRO) {
-            const int pf0 = s0 - 1;
-            const int zp = (pf0 & 1) == 0 ? pf0 / 2 - 1 : (pf0 - 1) / 2;
 #pragma unroll
-            for (int k = 0; k < M + 1; ++k) qprev[k] = q_direct(k, zp);
-        }
-        C dummy;
+        for (int q = 0; q < PD; ++q) issue_b(s0 + q, q);
+        S pu[3][M], pr2[3];
         if (!ZG) {
 #pragma unroll
             for (int q = 0; q < 3; ++q) {
                 const int p = s0 - 1 + q;
-                issue_u(p, 0);
-                if (PRO && (p & 1) == 0) {
+                const rsrc_t r = line_rsrc(u, (long)p * plane, plane, p >= 0 && p < n);
 #pragma unroll
-                    for (int k = 0; k < M + 1; ++k) qh[k] = q_direct(k, p / 2);
-                }
-                C* dst = q == 0 ? um1 : (q == 1 ? u0 : up1);
-                take_u(p, 0, qh, dst, q == 1 ? ur0 : (q == 2 ? urp1 : dummy));
+                for (int m = 0; m < M; ++m) pu[q][m] = bload<S>(r, gb[m]);
+                pr2[q] = bload<S>(r, r2b);
             }
+        }
+        C qs[3][M + 1];
+        if (PRO) {
+            const int Zb = (s0 - 1) / 2;  // s0 is odd
+            S pc[3][MC];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                const int Z = Zb - 1 + q;
+                const rsrc_t r = line_rsrc(ec, (long)Z * cplane, cplane, Z >= 0 && Z < nc);
+#pragma unroll
+                for (int j = 0; j < MC; ++j) pc[q][j] = bload<S>(r, cgb[j]);
+            }
+            C* cs = &rL[0][0];
+#pragma unroll
+            for (int q = 0; q < 3; ++q)
+#pragma unroll
+                for (int j = 0; j < MC; ++j) cs[q * MC * NT + t + j * NT] = cvt<C>(pc[q][j]);
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < 3; ++q)
+#pragma unroll
+                for (int k = 0; k < M + 1; ++k) qs[q][k] = q_at(cs + q * MC * NT, k);
+#pragma unroll
+            for (int k = 0; k < M + 1; ++k) qprev[k] = qs[0][k];
+        }
+        if (!ZG) {
+            C dummy;
+            take_raw(s0 - 1, pu[0], pr2[0], qs[1], um1, dummy);
+            take_raw(s0, pu[1], pr2[1], qs[1], u0, ur0);
+            take_raw(s0 + 1, pu[2], pr2[2], qs[2], up1, urp1);
         }
 #pragma unroll
         for (int m = 0; m < M; ++m) rm2[m] = rm1[m] = C(0);
-        issue_b(s0, 0);
-#pragma unroll
-        for (int q = 1; q < PD; ++q) issue_b(s0 + q, q);
         if (!ZG) {
 #pragma unroll
             for (int q = 0; q < PD; ++q) issue_u(s0 + 2 + q, (2 + q) % RS);
@@ -475,7 +486,7 @@ k_smooth3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out
         C qh[M + 1];
         if (PRO && (k & 1) == 1) {  // s even
 #pragma unroll
-            for (int j = 0; j < M + 1; ++j) qh[j] = q_lds(j);
+            for (int j = 0; j < M + 1; ++j) qh[j] = q_at(cL, j);
         }
 #pragma unroll
         for (int m = 0; m < M; ++m) {
@@ -592,23 +603,11 @@ k_smooth2d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out
 #pragma unroll
         for (int j = 0; j < MC; ++j) cL[t + j * NT] = cvt<C>(rc[sl][j]);
     };
-    auto q_lds = [&](int k) -> C {
+    auto q_at = [&](const C* base, int k) -> C {
         const int i = cc[k] & 0xffff;
         const bool hx = cc[k] & 0x10000;
-        C q = cL[i];
-        q += hx ? cL[i + 1] : C(0);
-        return (hx ? C(0.5) : C(1)) * q;
-    };
-    auto q_direct = [&](int k, int Y) -> C {
-        if (Y < 0 || Y >= nc) return C(0);
-        const int i = cc[k] & 0xffff;
-        const bool hx = cc[k] & 0x10000;
-        const int gx = cx0 + i;
-        auto at = [&](int X) -> C {
-            return (X >= 0 && X < nc) ? cvt<C>(ec[(long)Y * nc + X]) : C(0);
-        };
-        C q = at(gx);
-        q += hx ? at(gx + 1) : C(0);
+        C q = base[i];
+        q += hx ? base[i + 1] : C(0);
         return (hx ? C(0.5) : C(1)) * q;
     };
 
@@ -630,10 +629,10 @@ k_smooth2d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out
 #pragma unroll
         for (int m = 0; m < M; ++m) rb[k][m] = bload<S>(r, gb[m]);
     };
-    auto take_u = [&](int p, int sl, const C* qh, C* dst, C& rdst) {
+    auto take_raw = [&](int p, const S* raw, S raw2, const C* qh, C* dst, C& rdst) {
 #pragma unroll
         for (int m = 0; m < M + 1; ++m) {
-            C v = cvt<C>(m < M ? ru[sl][m] : rr2[sl]);
+            C v = cvt<C>(m < M ? raw[m] : raw2);
             if (PRO) {
                 C pe;
                 if ((p & 1) == 0) {
@@ -647,38 +646,62 @@ k_smooth2d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out
             if (m < M) dst[m] = v; else rdst = v;
         }
     };
+    auto take_u = [&](int p, int sl, const C* qh, C* dst, C& rdst) {
+        take_raw(p, ru[sl], rr2[sl], qh, dst, rdst);
+    };
 
     C um2[M], um1[M], u0[M], up1[M];
     C ur0 = 0, urp1 = 0;
     double nacc = 0.0;
     const int s0 = y0 - 1;
+    // prologue: all loads before the first wait (see the 3D kernel)
+    static_assert(!PRO || 3 * MC <= 4 * M, "coarse staging fits the residual LDS");
     {
-        C qh[M + 1];
-        if (PRO) {
-            const int pf0 = s0 - 1;
-            const int yp = (pf0 & 1) == 0 ? pf0 / 2 - 1 : (pf0 - 1) / 2;
 #pragma unroll
-            for (int k = 0; k < M + 1; ++k) qprev[k] = q_direct(k, yp);
-        }
-        C dummy;
+        for (int q = 0; q < PD; ++q) issue_b(s0 + q, q);
+        S pu[3][M], pr2[3];
         if (!ZG) {
 #pragma unroll
             for (int q = 0; q < 3; ++q) {
                 const int p = s0 - 1 + q;
-                issue_u(p, 0);
-                if (PRO && (p & 1) == 0) {
+                const rsrc_t r = line_rsrc(u, (long)p * n, n, p >= 0 && p < n);
 #pragma unroll
-                    for (int k = 0; k < M + 1; ++k) qh[k] = q_direct(k, p / 2);
-                }
-                C* dst = q == 0 ? um1 : (q == 1 ? u0 : up1);
-                take_u(p, 0, qh, dst, q == 1 ? ur0 : (q == 2 ? urp1 : dummy));
+                for (int m = 0; m < M; ++m) pu[q][m] = bload<S>(r, gb[m]);
+                pr2[q] = bload<S>(r, r2b);
             }
+        }
+        C qs[3][M + 1];
+        if (PRO) {
+            const int Yb = (s0 - 1) / 2;  // s0 is odd
+            S pc[3][MC];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                const int Y = Yb - 1 + q;
+                const rsrc_t r = line_rsrc(ec, (long)Y * nc, nc, Y >= 0 && Y < nc);
+#pragma unroll
+                for (int j = 0; j < MC; ++j) pc[q][j] = bload<S>(r, cgb[j]);
+            }
+            C* cs = &rL[0][0];
+#pragma unroll
+            for (int q = 0; q < 3; ++q)
+#pragma unroll
+                for (int j = 0; j < MC; ++j) cs[q * MC * NT + t + j * NT] = cvt<C>(pc[q][j]);
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < 3; ++q)
+#pragma unroll
+                for (int k = 0; k < M + 1; ++k) qs[q][k] = q_at(cs + q * MC * NT, k);
+#pragma unroll
+            for (int k = 0; k < M + 1; ++k) qprev[k] = qs[0][k];
+        }
+        if (!ZG) {
+            C dummy;
+            take_raw(s0 - 1, pu[0], pr2[0], qs[1], um1, dummy);
+            take_raw(s0, pu[1], pr2[1], qs[1], u0, ur0);
+            take_raw(s0 + 1, pu[2], pr2[2], qs[2], up1, urp1);
         }
 #pragma unroll
         for (int m = 0; m < M; ++m) um2[m] = C(0);
-        issue_b(s0, 0);
-#pragma unroll
-        for (int q = 1; q < PD; ++q) issue_b(s0 + q, q);
         if (!ZG) {
 #pragma unroll
             for (int q = 0; q < PD; ++q) issue_u(s0 + 2 + q, (2 + q) % RS);
@@ -744,7 +767,7 @@ k_smooth2d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out
         C qh[M + 1];
         if (PRO && (k & 1) == 1) {  // s even
 #pragma unroll
-            for (int j = 0; j < M + 1; ++j) qh[j] = q_lds(j);
+            for (int j = 0; j < M + 1; ++j) qh[j] = q_at(cL, j);
         }
 #pragma unroll
         for (int m = 0; m < M; ++m) {
@@ -851,16 +874,25 @@ k_restrict3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ b
     C ur0 = 0, urp1 = 0, acc = 0;
     const int f0 = 2 * Z0, f1 = 2 * Z1;  // fine planes f0..f1 contribute
     {
+        // all prologue loads before the first wait
+        issue_b(f0, 0);
+        S pu[3][M], pr2[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const int p = f0 - 1 + q;
+            const rsrc_t r = line_rsrc(u, (long)p * plane, plane, p >= 0 && p < n);
+#pragma unroll
+            for (int m = 0; m < M; ++m) pu[q][m] = bload<S>(r, gb[m]);
+            pr2[q] = bload<S>(r, r2b);
+        }
         C dummy;
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
-            issue_u(f0 - 1 + q, 0);
             C* dst = q == 0 ? um1 : (q == 1 ? u0 : up1);
 #pragma unroll
-            for (int m = 0; m < M; ++m) dst[m] = cvt<C>(ru[0][m]);
-            (q == 1 ? ur0 : (q == 2 ? urp1 : dummy)) = cvt<C>(rr2[0]);
+            for (int m = 0; m < M; ++m) dst[m] = cvt<C>(pu[q][m]);
+            (q == 1 ? ur0 : (q == 2 ? urp1 : dummy)) = cvt<C>(pr2[q]);
         }
-        issue_b(f0, 0);
         issue_u(f0 + 2, 0);
         const int sl = f0 & 1;
 #pragma unroll
@@ -981,16 +1013,25 @@ k_restrict2d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ b
     C ur0 = 0, urp1 = 0, acc = 0;
     const int f0 = 2 * Y0, f1 = 2 * Y1;
     {
+        // all prologue loads before the first wait
+        issue_b(f0, 0);
+        S pu[3][M], pr2[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const int p = f0 - 1 + q;
+            const rsrc_t r = line_rsrc(u, (long)p * n, n, p >= 0 && p < n);
+#pragma unroll
+            for (int m = 0; m < M; ++m) pu[q][m] = bload<S>(r, gb[m]);
+            pr2[q] = bload<S>(r, r2b);
+        }
         C dummy;
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
-            issue_u(f0 - 1 + q, 0);
             C* dst = q == 0 ? um1 : (q == 1 ? u0 : up1);
 #pragma unroll
-            for (int m = 0; m < M; ++m) dst[m] = cvt<C>(ru[0][m]);
-            (q == 1 ? ur0 : (q == 2 ? urp1 : dummy)) = cvt<C>(rr2[0]);
+            for (int m = 0; m < M; ++m) dst[m] = cvt<C>(pu[q][m]);
+            (q == 1 ? ur0 : (q == 2 ? urp1 : dummy)) = cvt<C>(pr2[q]);
         }
-        issue_b(f0, 0);
         issue_u(f0 + 2, 0);
         const int sl = f0 & 1;
 #pragma unroll
@@ -1338,6 +1379,8 @@ k_finalize(const double* __restrict__ ps, const double* __restrict__ pm, int cou
 // ---------------------------------------------------------------------------
 // FP64 refinement step, 3D: unew = u + escale * e (on the fly, halo included),
 // r = b - A unew, r_lo = s * r (stored in S), partials of r^2 and max |r|.
+// Same scheme as the smoothers: plane buffer resources (e reads as zero when
+// there is no correction yet), an unrolled marching loop over planes.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double ir_scale(const double* maxprev) {
     const double m = maxprev[0];
@@ -1347,7 +1390,7 @@ __device__ __forceinline__ double ir_scale(const double* maxprev) {
     return ldexp(1.0, -e);  // s m in [0.5, 1)
 }
 
-template <typename S, int TX, int TY, int NT, int IPD>
+template <typename S, int TX, int TY, int NT, int UN, bool NTS>
 __global__ void __launch_bounds__(NT)
 k_ir3d(const double* __restrict__ u, double* __restrict__ unew, const S* __restrict__ e,
        const double* __restrict__ b, S* __restrict__ rlo, int n, int tiles_x, int tiles_y,
@@ -1356,119 +1399,122 @@ k_ir3d(const double* __restrict__ u, double* __restrict__ unew, const S* __restr
        double* __restrict__ psum, double* __restrict__ pmax) {
     constexpr int RX = TX + 2, RY = TY + 2, NR = RX * RY;
     constexpr int M = (NR + NT - 1) / NT;
-    __shared__ double uL[2][NR];
+    constexpr int RP = RX + 1, RSZ = RP + M * NT + RX + 1;
+    constexpr int RS = 2;
+    static_assert(UN % 2 == 0, "unroll covers the prefetch ring");
+    __shared__ double uL[2][RSZ];
     __shared__ double red[NT / 64];
     const int total = tiles_x * tiles_y * nchunks;
     const int lg = xcd_remap(blockIdx.x, total);
     const int tx = lg % tiles_x, ty = (lg / tiles_x) % tiles_y,
               ch = lg / (tiles_x * tiles_y);
     const long plane = (long)n * n, boff = (long)blockIdx.y * plane * n;
-    const bool nt = plane * n >= kNtMinPts;
     u += boff;
     unew += boff;
     b += boff;
     rlo += boff;
-    if (e) e += boff;
+    const bool hase = e != nullptr && k > 0;
+    if (hase) e += boff;
     const int x0 = tx * TX, y0 = ty * TY;
     const int z0 = ch * zchunk, z1 = min(z0 + zchunk, n);
     const int t = threadIdx.x;
     const double s_new = ir_scale(maxprev);
     if (blockIdx.x == 0 && blockIdx.y == 0 && t == 0) scales[k] = s_new;
-    const double escale = (e && k > 0) ? 1.0 / (sigma0 * scales[k - 1]) : 0.0;
+    const double escale = hase ? 1.0 / (sigma0 * scales[k - 1]) : 0.0;
 
-    int go[M];
-    bool inr[M], val[M], inn[M];
+    unsigned gu[M], ge[M], gi[M];  // byte offsets: u (ring), e (ring), interior
+    bool inn[M];
 #pragma unroll
     for (int m = 0; m < M; ++m) {
         const int i = t + m * NT;
-        inr[m] = i < NR;
         const int lx = i % RX, ly = i / RX;
         const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
-        val[m] = inr[m] && gx >= 0 && gx < n && gy >= 0 && gy < n;
-        inn[m] = val[m] && lx >= 1 && lx <= TX && ly >= 1 && ly <= TY;
-        go[m] = val[m] ? gy * n + gx : 0;
+        const bool val = i < NR && gx >= 0 && gx < n && gy >= 0 && gy < n;
+        inn[m] = val && lx >= 1 && lx <= TX && ly >= 1 && ly <= TY;
+        const int g = gy * n + gx;
+        gu[m] = val ? (unsigned)(g * 8) : kOob;
+        ge[m] = val ? (unsigned)(g * (int)sizeof(S)) : kOob;
+        gi[m] = inn[m] ? (unsigned)(g * 8) : kOob;
     }
-    // raw prefetch: ru/re[k] = plane s+2+k of u and e, rb[k] = b plane s+1+k
-    const bool hase = e != nullptr && k > 0;
-    // e is read unconditionally (no branch around the loads, so the wait
-    // counters stay exact); without a correction the values come from b,
-    // which is as large, and are discarded by the select in take()
-    const S* esrc = hase ? e : reinterpret_cast<const S*>(b);
-    double ru[2][M], rb[2][M];  // prefetch slots by plane parity
-    S re[2][M];
-    bool okq[2][M];
+    double ru[RS][M], rb[RS][M];
+    S re[RS][M];
     auto issue = [&](int p, int q) {
+        const bool pin = p >= 0 && p < n;
+        const rsrc_t a = line_rsrc(u, (long)p * plane, plane, pin);
+        const rsrc_t c = line_rsrc(e, (long)p * plane, plane, pin && hase);
 #pragma unroll
         for (int m = 0; m < M; ++m) {
-            const bool ok = val[m] && p >= 0 && p < n;
-            const long g = ok ? p * plane + go[m] : 0;
-            ru[q][m] = u[g];
-            re[q][m] = esrc[g];
-            okq[q][m] = ok;
+            ru[q][m] = bload<double>(a, gu[m]);
+            re[q][m] = bload<S>(c, ge[m]);
         }
     };
     auto issue_b = [&](int p, int q) {
+        const rsrc_t a = line_rsrc(b, (long)p * plane, plane, p >= 0 && p < n);
 #pragma unroll
-        for (int m = 0; m < M; ++m)
-            rb[q][m] = b[(inn[m] && p >= 0 && p < n) ? p * plane + go[m] : 0];
+        for (int m = 0; m < M; ++m) rb[q][m] = bload<double>(a, gi[m]);
     };
-    auto take = [&](double* dst, int sl) {
+    auto take = [&](double* dst, const double* raw, const S* rawe) {
 #pragma unroll
-        for (int m = 0; m < M; ++m)
-            dst[m] = okq[sl][m] ? (hase ? ru[sl][m] + escale * (double)re[sl][m] : ru[sl][m]) : 0.0;
+        for (int m = 0; m < M; ++m) dst[m] = raw[m] + escale * (double)rawe[m];
     };
-    double um1[M], u0[M], up1[M], b0[M];
+    double um1[M], u0[M], up1[M];
     double acc = 0.0, mx = 0.0;
-    issue(z0 - 1, 0);
-    take(um1, 0);
-    issue(z0, 0);
-    take(u0, 0);
-    issue(z0 + 1, 0);
-    take(up1, 0);
-    issue_b(z0, 0);
+    {
+        // all prologue loads before the first wait
+        issue_b(z0, 0);
+        double pu[3][M];
+        S pe[3][M];
 #pragma unroll
-    for (int m = 0; m < M; ++m) b0[m] = rb[0][m];
-    issue(z0 + 2, 0);
-    issue_b(z0 + 1, 1);
+        for (int q = 0; q < 3; ++q) {
+            const int p = z0 - 1 + q;
+            const bool pin = p >= 0 && p < n;
+            const rsrc_t a = line_rsrc(u, (long)p * plane, plane, pin);
+            const rsrc_t c = line_rsrc(e, (long)p * plane, plane, pin && hase);
 #pragma unroll
-    for (int m = 0; m < M; ++m)
-        if (inr[m]) uL[z0 & 1][t + m * NT] = u0[m];
+            for (int m = 0; m < M; ++m) {
+                pu[q][m] = bload<double>(a, gu[m]);
+                pe[q][m] = bload<S>(c, ge[m]);
+            }
+        }
+        take(um1, pu[0], pe[0]);
+        take(u0, pu[1], pe[1]);
+        take(up1, pu[2], pe[2]);
+        issue(z0 + 2, 0);
+#pragma unroll
+        for (int m = 0; m < M; ++m) uL[z0 & 1][RP + t + m * NT] = u0[m];
+    }
     auto step = [&](int s, auto kc) {
-        constexpr int k = decltype(kc)::k;  // (s - z0) & 1
+        constexpr int k = decltype(kc)::k;  // (s - z0) % UN
         __syncthreads();
         const int cur = s & 1;
-        issue(s + 3, k ^ 1);
-        issue_b(s + 2, k);
-        const double* U = uL[cur];
+        issue(s + 3, (k + 1) % RS);
+        issue_b(s + 1, (k + 1) % RS);
+        if (s < z1) {
+            const double* U = uL[cur];
+            const rsrc_t ow = line_rsrc(unew, (long)s * plane, plane, true);
+            const rsrc_t orl = line_rsrc(rlo, (long)s * plane, plane, true);
 #pragma unroll
-        for (int m = 0; m < M; ++m) {
-            if (!inn[m]) continue;
-            const int q = t + m * NT;
-            const long g = s * plane + go[m];
-            const double lap = 6.0 * u0[m] - U[q - 1] - U[q + 1] - U[q - RX] - U[q + RX] -
-                               um1[m] - up1[m];
-            const double r = b0[m] - inv_h2 * lap;
-            st_out(&unew[g], u0[m], nt);
-            st_out(&rlo[g], static_cast<S>(s_new * r), nt);
-            acc += r * r;
-            mx = fmax(mx, fabs(r));
+            for (int m = 0; m < M; ++m) {
+                const int q = RP + t + m * NT;
+                const double lap = 6.0 * u0[m] - U[q - 1] - U[q + 1] - U[q - RX] - U[q + RX] -
+                                   um1[m] - up1[m];
+                const double r = rb[k % RS][m] - inv_h2 * lap;
+                bstore<NTS>(u0[m], ow, gi[m]);
+                bstore<NTS>(static_cast<S>(s_new * r), orl, inn[m] ? ge[m] : kOob);
+                acc += inn[m] ? r * r : 0.0;
+                mx = fmax(mx, inn[m] ? fabs(r) : 0.0);
+            }
         }
 #pragma unroll
-        for (int m = 0; m < M; ++m)
-            if (inr[m]) uL[cur ^ 1][t + m * NT] = up1[m];
+        for (int m = 0; m < M; ++m) uL[cur ^ 1][RP + t + m * NT] = up1[m];
 #pragma unroll
         for (int m = 0; m < M; ++m) {
             um1[m] = u0[m];
             u0[m] = up1[m];
-            b0[m] = rb[k ^ 1][m];
         }
-        take(up1, k);
+        take(up1, ru[k % RS], re[k % RS]);
     };
-    for (int s = z0; s < z1; s += 2) {
-        step(s, Par<0>());
-        if (s + 1 >= z1) break;
-        step(s + 1, Par<1>());
-    }
+    march<UN>(z0, z1 - 1, step);
     const double ts = block_sum<NT>(acc, red);
     __syncthreads();
     const double tm = block_max<NT>(mx, red);
@@ -1479,123 +1525,125 @@ k_ir3d(const double* __restrict__ u, double* __restrict__ unew, const S* __restr
     }
 }
 
-template <typename S, int TX, int IPD>
-__global__ void __launch_bounds__(TX)
+template <typename S, int TX, int NT, int UN, bool NTS>
+__global__ void __launch_bounds__(NT)
 k_ir2d(const double* __restrict__ u, double* __restrict__ unew, const S* __restrict__ e,
        const double* __restrict__ b, S* __restrict__ rlo, int n, int tiles_x, int ychunk,
        int nchunks, double inv_h2, double sigma0, int k, double* __restrict__ scales,
        const double* __restrict__ maxprev, double* __restrict__ psum,
        double* __restrict__ pmax) {
-    constexpr int NT = TX, RX = TX + 2;
+    constexpr int RX = TX + 2;
     constexpr int M = (RX + NT - 1) / NT;
-    __shared__ double uL[2][RX];
+    constexpr int RSZ = M * NT + 2;
+    constexpr int RS = 2;
+    static_assert(UN % 2 == 0, "unroll covers the prefetch ring");
+    __shared__ double uL[2][RSZ];
     __shared__ double red[NT / 64];
     const int total = tiles_x * nchunks;
     const int lg = xcd_remap(blockIdx.x, total);
     const int tx = lg % tiles_x, ch = lg / tiles_x;
     const long area = (long)n * n, boff = (long)blockIdx.y * area;
-    const bool nt = area >= kNtMinPts;
     u += boff;
     unew += boff;
     b += boff;
     rlo += boff;
-    if (e) e += boff;
+    const bool hase = e != nullptr && k > 0;
+    if (hase) e += boff;
     const int x0 = tx * TX;
     const int y0 = ch * ychunk, y1 = min(y0 + ychunk, n);
     const int t = threadIdx.x;
     const double s_new = ir_scale(maxprev);
     if (blockIdx.x == 0 && blockIdx.y == 0 && t == 0) scales[k] = s_new;
-    const double escale = (e && k > 0) ? 1.0 / (sigma0 * scales[k - 1]) : 0.0;
-    int go[M];
-    bool inr[M], val[M], inn[M];
+    const double escale = hase ? 1.0 / (sigma0 * scales[k - 1]) : 0.0;
+    unsigned gu[M], ge[M], gi[M];
+    bool inn[M];
 #pragma unroll
     for (int m = 0; m < M; ++m) {
         const int i = t + m * NT;
-        inr[m] = i < RX;
         const int gx = x0 - 1 + i;
-        val[m] = inr[m] && gx >= 0 && gx < n;
-        inn[m] = val[m] && i >= 1 && i <= TX;
-        go[m] = val[m] ? gx : 0;
+        const bool val = i < RX && gx >= 0 && gx < n;
+        inn[m] = val && i >= 1 && i <= TX;
+        gu[m] = val ? (unsigned)(gx * 8) : kOob;
+        ge[m] = val ? (unsigned)(gx * (int)sizeof(S)) : kOob;
+        gi[m] = inn[m] ? (unsigned)(gx * 8) : kOob;
     }
-    const bool hase = e != nullptr && k > 0;
-    // e is read unconditionally (no branch around the loads, so the wait
-    // counters stay exact); without a correction the values come from b,
-    // which is as large, and are discarded by the select in take()
-    const S* esrc = hase ? e : reinterpret_cast<const S*>(b);
-    double ru[2][M], rb[2][M];  // prefetch slots by plane parity
-    S re[2][M];
-    bool okq[2][M];
+    double ru[RS][M], rb[RS][M];
+    S re[RS][M];
     auto issue = [&](int p, int q) {
+        const bool pin = p >= 0 && p < n;
+        const rsrc_t a = line_rsrc(u, (long)p * n, n, pin);
+        const rsrc_t c = line_rsrc(e, (long)p * n, n, pin && hase);
 #pragma unroll
         for (int m = 0; m < M; ++m) {
-            const bool ok = val[m] && p >= 0 && p < n;
-            const long g = ok ? (long)p * n + go[m] : 0;
-            ru[q][m] = u[g];
-            re[q][m] = esrc[g];
-            okq[q][m] = ok;
+            ru[q][m] = bload<double>(a, gu[m]);
+            re[q][m] = bload<S>(c, ge[m]);
         }
     };
     auto issue_b = [&](int p, int q) {
+        const rsrc_t a = line_rsrc(b, (long)p * n, n, p >= 0 && p < n);
 #pragma unroll
-        for (int m = 0; m < M; ++m)
-            rb[q][m] = b[(inn[m] && p >= 0 && p < n) ? (long)p * n + go[m] : 0];
+        for (int m = 0; m < M; ++m) rb[q][m] = bload<double>(a, gi[m]);
     };
-    auto take = [&](double* dst, int sl) {
+    auto take = [&](double* dst, const double* raw, const S* rawe) {
 #pragma unroll
-        for (int m = 0; m < M; ++m)
-            dst[m] = okq[sl][m] ? (hase ? ru[sl][m] + escale * (double)re[sl][m] : ru[sl][m]) : 0.0;
+        for (int m = 0; m < M; ++m) dst[m] = raw[m] + escale * (double)rawe[m];
     };
-    double um1[M], u0[M], up1[M], b0[M];
+    double um1[M], u0[M], up1[M];
     double acc = 0.0, mx = 0.0;
-    issue(y0 - 1, 0);
-    take(um1, 0);
-    issue(y0, 0);
-    take(u0, 0);
-    issue(y0 + 1, 0);
-    take(up1, 0);
-    issue_b(y0, 0);
+    {
+        issue_b(y0, 0);
+        double pu[3][M];
+        S pe[3][M];
 #pragma unroll
-    for (int m = 0; m < M; ++m) b0[m] = rb[0][m];
-    issue(y0 + 2, 0);
-    issue_b(y0 + 1, 1);
+        for (int q = 0; q < 3; ++q) {
+            const int p = y0 - 1 + q;
+            const bool pin = p >= 0 && p < n;
+            const rsrc_t a = line_rsrc(u, (long)p * n, n, pin);
+            const rsrc_t c = line_rsrc(e, (long)p * n, n, pin && hase);
 #pragma unroll
-    for (int m = 0; m < M; ++m)
-        if (inr[m]) uL[y0 & 1][t + m * NT] = u0[m];
+            for (int m = 0; m < M; ++m) {
+                pu[q][m] = bload<double>(a, gu[m]);
+                pe[q][m] = bload<S>(c, ge[m]);
+            }
+        }
+        take(um1, pu[0], pe[0]);
+        take(u0, pu[1], pe[1]);
+        take(up1, pu[2], pe[2]);
+        issue(y0 + 2, 0);
+#pragma unroll
+        for (int m = 0; m < M; ++m) uL[y0 & 1][1 + t + m * NT] = u0[m];
+    }
     auto step = [&](int s, auto kc) {
-        constexpr int k = decltype(kc)::k;  // (s - y0) & 1
+        constexpr int k = decltype(kc)::k;  // (s - y0) % UN
         __syncthreads();
         const int cur = s & 1;
-        issue(s + 3, k ^ 1);
-        issue_b(s + 2, k);
-        const double* U = uL[cur];
+        issue(s + 3, (k + 1) % RS);
+        issue_b(s + 1, (k + 1) % RS);
+        if (s < y1) {
+            const double* U = uL[cur];
+            const rsrc_t ow = line_rsrc(unew, (long)s * n, n, true);
+            const rsrc_t orl = line_rsrc(rlo, (long)s * n, n, true);
 #pragma unroll
-        for (int m = 0; m < M; ++m) {
-            if (!inn[m]) continue;
-            const int q = t + m * NT;
-            const long g = (long)s * n + go[m];
-            const double lap = 4.0 * u0[m] - U[q - 1] - U[q + 1] - um1[m] - up1[m];
-            const double r = b0[m] - inv_h2 * lap;
-            st_out(&unew[g], u0[m], nt);
-            st_out(&rlo[g], static_cast<S>(s_new * r), nt);
-            acc += r * r;
-            mx = fmax(mx, fabs(r));
+            for (int m = 0; m < M; ++m) {
+                const int q = 1 + t + m * NT;
+                const double lap = 4.0 * u0[m] - U[q - 1] - U[q + 1] - um1[m] - up1[m];
+                const double r = rb[k % RS][m] - inv_h2 * lap;
+                bstore<NTS>(u0[m], ow, gi[m]);
+                bstore<NTS>(static_cast<S>(s_new * r), orl, inn[m] ? ge[m] : kOob);
+                acc += inn[m] ? r * r : 0.0;
+                mx = fmax(mx, inn[m] ? fabs(r) : 0.0);
+            }
         }
 #pragma unroll
-        for (int m = 0; m < M; ++m)
-            if (inr[m]) uL[cur ^ 1][t + m * NT] = up1[m];
+        for (int m = 0; m < M; ++m) uL[cur ^ 1][1 + t + m * NT] = up1[m];
 #pragma unroll
         for (int m = 0; m < M; ++m) {
             um1[m] = u0[m];
             u0[m] = up1[m];
-            b0[m] = rb[k ^ 1][m];
         }
-        take(up1, k);
+        take(up1, ru[k % RS], re[k % RS]);
     };
-    for (int s = y0; s < y1; s += 2) {
-        step(s, Par<0>());
-        if (s + 1 >= y1) break;
-        step(s + 1, Par<1>());
-    }
+    march<UN>(y0, y1 - 1, step);
     const double ts = block_sum<NT>(acc, red);
     __syncthreads();
     const double tm = block_max<NT>(mx, red);
@@ -1605,7 +1653,6 @@ k_ir2d(const double* __restrict__ u, double* __restrict__ unew, const S* __restr
         pmax[pi] = tm;
     }
 }
-
 
 // ---------------------------------------------------------------------------
 // FP64 residual norm of the fine grid: per-block sum of r^2 and max |r|.
@@ -1663,151 +1710,136 @@ inline int pick_chunk(int n, int tiles, int want, int minc) {
     return ch;
 }
 
-constexpr int S3_TX = 64, S3_TY = 16, S3_NT = 640;
-constexpr int S3S_TX = 64, S3S_TY = 16, S3S_NT = 256;
-constexpr int S2_TX = 1024, S2_NT = 576;
-constexpr int S2S_TX = 256, S2S_NT = 256;
-constexpr int S_PD = 1;
-constexpr int R3_TX = 32, R3_TY = 8, R3_NT = 576;
-constexpr int R2_TX = 512, R2_NT = 576;
-constexpr int I3_TX = 64, I3_TY = 16, I3_NT = 256;
-constexpr int I2_TX = 256;
 constexpr int kWantBlocks = 1024;
-constexpr int kWantBlocksLarge = 256;  // one long march per CU on large grids
-
-// chunk length along the marching direction: long chunks on large grids
-// (fewer halo planes re-read), one plane per workgroup on small grids, where
-// the sweep is latency bound
-inline int march_chunk(int n, int tiles, long pts, int want, int minc_large) {
-    const int minc = pts >= (1L << 22) ? minc_large : 1;
-    return pick_chunk(n, tiles, want, minc);
-}
 
 // the fused-correction sweep assumes every chunk starts on an even plane
 inline int even_chunk(int c) { return c + (c & 1); }
 
-template <typename S, typename C>
-hipError_t smooth_impl(bool zg, bool norm, const Sweep& s, hipStream_t st, int* nparts) {
-    const int n = s.n;
+// Launch configurations of the marching sweeps by grid size, measured on
+// MI355X in FP64 (the same shapes serve FP32/FP16 storage).  `want` is the
+// number of marches (workgroups) per batch entry: one long march per CU on
+// large grids, where halo planes cost bandwidth, more and shorter ones on
+// smaller grids, where latency dominates.
+//   smoother 3D  n >= 200: 64x16 tiles / 640 threads, unrolled 6, 256 marches
+//                n >= 100: 64x16 / 640, 256 marches;  else 32x16 / 320, 256
+//   smoother 2D  n >= 3000: 1024-wide strips / 576 threads, unrolled 4, 256
+//                n >= 700: 512 / 320, 512 marches;  else 128 / 192, 512
+//   restriction  3D n >= 200: 32x8 coarse columns / 576, unrolled 6, 256;
+//                else 32x4 / 320, 512;  2D n >= 3000: 512 / 576, unrolled 6,
+//                256; n >= 700: 256 / 320, 512; else 128 / 192, 512
+template <typename S, typename C, int TX, int TY, int NT, int UN, bool NTS>
+hipError_t launch_smooth3d(bool zg, bool norm, const Sweep& s, int want, int minc,
+                           hipStream_t st, int* nparts) {
+    const int n = s.n, nc = (n + 1) / 2 - 1;
     const S* u = static_cast<const S*>(s.u);
     const S* b = static_cast<const S*>(s.b);
     S* out = static_cast<S*>(s.out);
     const S* ec = static_cast<const S*>(s.ec);
     const bool pro = ec != nullptr;
-    const int nc = (n + 1) / 2 - 1;
+    const C sA = C(s.sA), sW = C(s.sW), c0 = C(s.c[0]), c1 = C(s.c[1]), pf = C(s.pf);
+    const int tx = cdiv(n, TX), ty = cdiv(n, TY);
+    const int zc = even_chunk(pick_chunk(n, tx * ty, want, minc));
+    const int nch = cdiv(n, zc);
+    dim3 grid(tx * ty * nch, s.batch);
+    if (nparts) *nparts = grid.x * grid.y;
+    if (norm && (long)grid.x * grid.y > s.partials_cap) return hipErrorInvalidValue;
+    constexpr int PDC = UN % 3 == 0 ? 2 : 1;  // deeper prefetch for the fused correction
+#define L3(PD, ZG, NM, PR)                                                                     \
+    hipLaunchKernelGGL((k_smooth3d<S, C, TX, TY, NT, PD, UN, ZG, NM, PR, NTS>), grid, dim3(NT), \
+                       0, st, u, b, out, n, tx, ty, zc, nch, sA, sW, c0, c1, s.partials, ec, nc, pf)
+    if (zg) L3(1, true, false, false);
+    else if (norm) L3(1, false, true, false);
+    else if (pro) L3(PDC, false, false, true);
+    else L3(1, false, false, false);
+#undef L3
+    return hipGetLastError();
+}
+
+template <typename S, typename C, int TX, int NT, int UN, bool NTS>
+hipError_t launch_smooth2d(bool zg, bool norm, const Sweep& s, int want, int minc,
+                           hipStream_t st, int* nparts) {
+    const int n = s.n, nc = (n + 1) / 2 - 1;
+    const S* u = static_cast<const S*>(s.u);
+    const S* b = static_cast<const S*>(s.b);
+    S* out = static_cast<S*>(s.out);
+    const S* ec = static_cast<const S*>(s.ec);
+    const bool pro = ec != nullptr;
     const C sA = C(s.sA), sW = C(s.sW), c0 = C(s.c[0]), c1 = C(s.c[1]), c2 = C(s.c[2]);
     const C pf = C(s.pf);
+    const int tx = cdiv(n, TX);
+    const int yc = even_chunk(pick_chunk(n, tx, want, minc));
+    const int nch = cdiv(n, yc);
+    dim3 grid(tx * nch, s.batch);
+    if (nparts) *nparts = grid.x * grid.y;
+    if (norm && (long)grid.x * grid.y > s.partials_cap) return hipErrorInvalidValue;
+#define L2(ZG, NM, PR)                                                                      \
+    hipLaunchKernelGGL((k_smooth2d<S, C, TX, NT, 1, UN, ZG, NM, PR, NTS>), grid, dim3(NT), 0, \
+                       st, u, b, out, n, tx, yc, nch, sA, sW, c0, c1, c2, s.partials, ec, nc, pf)
+    if (zg) L2(true, false, false);
+    else if (norm) L2(false, true, false);
+    else if (pro) L2(false, false, true);
+    else L2(false, false, false);
+#undef L2
+    return hipGetLastError();
+}
+
+template <typename S, typename C>
+hipError_t smooth_impl(bool zg, bool norm, const Sweep& s, hipStream_t st, int* nparts) {
+    const int n = s.n;
+    const bool pro = s.ec != nullptr;
     if (zg && (norm || pro)) return hipErrorInvalidValue;
     if (norm && pro) return hipErrorInvalidValue;
     // buffer offsets are 32-bit byte offsets within one plane
     if (s.d == 3 && (long)n * n * (long)sizeof(S) > 0x7fffffffL) return hipErrorInvalidValue;
-    // large 3D grids (at least 200^3 > 2^22 nodes) store non-temporally
-    if (s.d == 3 && n >= 200) {
-        const int tx = cdiv(n, S3_TX), ty = cdiv(n, S3_TY);
-        const int zc = even_chunk(march_chunk(n, tx * ty, (long)n * n * n, kWantBlocksLarge, 32));
-        const int nch = cdiv(n, zc);
-        dim3 grid(tx * ty * nch, s.batch);
-        if (nparts) *nparts = grid.x * grid.y;
-        if (norm && (long)grid.x * grid.y > s.partials_cap) return hipErrorInvalidValue;
-#define L3(ZG, NM, PR)                                                                  \
-    hipLaunchKernelGGL((k_smooth3d<S, C, S3_TX, S3_TY, S3_NT, (PR ? 2 : S_PD), 6, ZG, NM, PR, true>), grid,\
-                       dim3(S3_NT), 0, st, u, b, out, n, tx, ty, zc, nch, sA, sW, c0,   \
-                       c1, s.partials, ec, nc, pf)
-        if (zg) L3(true, false, false);
-        else if (norm) L3(false, true, false);
-        else if (pro) L3(false, false, true);
-        else L3(false, false, false);
-#undef L3
-    } else if (s.d == 3) {
-        const int tx = cdiv(n, S3S_TX), ty = cdiv(n, S3S_TY);
-        const int zc = even_chunk(march_chunk(n, tx * ty, (long)n * n * n, kWantBlocks, 8));
-        const int nch = cdiv(n, zc);
-        dim3 grid(tx * ty * nch, s.batch);
-        if (nparts) *nparts = grid.x * grid.y;
-        if (norm && (long)grid.x * grid.y > s.partials_cap) return hipErrorInvalidValue;
-#define L3(ZG, NM, PR)                                                                     \
-    hipLaunchKernelGGL((k_smooth3d<S, C, S3S_TX, S3S_TY, S3S_NT, S_PD, 2, ZG, NM, PR, false>), grid, \
-                       dim3(S3S_NT), 0, st, u, b, out, n, tx, ty, zc, nch, sA, sW, c0,     \
-                       c1, s.partials, ec, nc, pf)
-        if (zg) L3(true, false, false);
-        else if (norm) L3(false, true, false);
-        else if (pro) L3(false, false, true);
-        else L3(false, false, false);
-#undef L3
-    } else if (n >= 3000) {
-        // large grids (at least 3000^2 > 2^22 nodes, non-temporal stores):
-        // wide strips, chunk length per variant (measured)
-        const int tx = cdiv(n, S2_TX);
-        const int yc = even_chunk(march_chunk(n, tx, (long)n * n, kWantBlocksLarge, 32));
-        const int nch = cdiv(n, yc);
-        dim3 grid(tx * nch, s.batch);
-        if (nparts) *nparts = grid.x * grid.y;
-        if (norm && (long)grid.x * grid.y > s.partials_cap) return hipErrorInvalidValue;
-#define L2(ZG, NM, PR)                                                                  \
-    hipLaunchKernelGGL((k_smooth2d<S, C, S2_TX, S2_NT, S_PD, 4, ZG, NM, PR, true>), grid, dim3(S2_NT),\
-                       0, st, u, b, out, n, tx, yc, nch, sA, sW, c0, c1, c2, s.partials, \
-                       ec, nc, pf)
-        if (zg) L2(true, false, false);
-        else if (norm) L2(false, true, false);
-        else if (pro) L2(false, false, true);
-        else L2(false, false, false);
-#undef L2
-    } else {
-        const int tx = cdiv(n, S2S_TX);
-        const int yc = even_chunk(march_chunk(n, tx, (long)n * n, kWantBlocks, pro ? 64 : 16));
-        const int nch = cdiv(n, yc);
-        dim3 grid(tx * nch, s.batch);
-        if (nparts) *nparts = grid.x * grid.y;
-        if (norm && (long)grid.x * grid.y > s.partials_cap) return hipErrorInvalidValue;
-#define L2(ZG, NM, PR)                                                                     \
-    hipLaunchKernelGGL((k_smooth2d<S, C, S2S_TX, S2S_NT, S_PD, 2, ZG, NM, PR, false>), grid,  \
-                       dim3(S2S_NT), 0, st, u, b, out, n, tx, yc, nch, sA, sW, c0, c1, c2, \
-                       s.partials, ec, nc, pf)
-        if (zg) L2(true, false, false);
-        else if (norm) L2(false, true, false);
-        else if (pro) L2(false, false, true);
-        else L2(false, false, false);
-#undef L2
+    // the large configurations (at least 200^3 or 3000^2 > 2^22 nodes)
+    // store non-temporally
+    if (s.d == 3) {
+        if (n >= 200) return launch_smooth3d<S, C, 64, 16, 640, 6, true>(zg, norm, s, 256, 32, st, nparts);
+        if (n >= 100) return launch_smooth3d<S, C, 64, 16, 640, 2, false>(zg, norm, s, 256, 2, st, nparts);
+        return launch_smooth3d<S, C, 32, 16, 320, 2, false>(zg, norm, s, 256, 2, st, nparts);
     }
+    if (n >= 3000) return launch_smooth2d<S, C, 1024, 576, 4, true>(zg, norm, s, 256, 32, st, nparts);
+    if (n >= 700) return launch_smooth2d<S, C, 512, 320, 2, false>(zg, norm, s, 512, 2, st, nparts);
+    return launch_smooth2d<S, C, 128, 192, 2, false>(zg, norm, s, 512, 2, st, nparts);
+}
+
+template <typename S, typename C, int TXc, int TYc, int NT, int UN>
+hipError_t launch_restrict3d(const Sweep& s, int want, int minc, hipStream_t st) {
+    const int n = s.n, nc = (n + 1) / 2 - 1;
+    const int tx = cdiv(nc, TXc), ty = cdiv(nc, TYc);
+    const int zc = pick_chunk(nc, tx * ty, want, minc);
+    const int nch = cdiv(nc, zc);
+    dim3 grid(tx * ty * nch, s.batch);
+    hipLaunchKernelGGL((k_restrict3d<S, C, TXc, TYc, NT, UN>), grid, dim3(NT), 0, st,
+                       static_cast<const S*>(s.u), static_cast<const S*>(s.b),
+                       static_cast<S*>(s.out), n, nc, tx, ty, zc, nch, C(s.sA));
+    return hipGetLastError();
+}
+
+template <typename S, typename C, int TXc, int NT, int UN>
+hipError_t launch_restrict2d(const Sweep& s, int want, int minc, hipStream_t st) {
+    const int n = s.n, nc = (n + 1) / 2 - 1;
+    const int tx = cdiv(nc, TXc);
+    const int yc = pick_chunk(nc, tx, want, minc);
+    const int nch = cdiv(nc, yc);
+    dim3 grid(tx * nch, s.batch);
+    hipLaunchKernelGGL((k_restrict2d<S, C, TXc, NT, UN>), grid, dim3(NT), 0, st,
+                       static_cast<const S*>(s.u), static_cast<const S*>(s.b),
+                       static_cast<S*>(s.out), n, nc, tx, yc, nch, C(s.sA));
     return hipGetLastError();
 }
 
 template <typename S, typename C>
 hipError_t restrict_impl(const Sweep& s, hipStream_t st) {
-    const int n = s.n, nc = (n + 1) / 2 - 1;
-    const S* u = static_cast<const S*>(s.u);
-    const S* b = static_cast<const S*>(s.b);
-    S* bc = static_cast<S*>(s.out);
-    const C sA = C(s.sA);
-    const long pts = s.d == 3 ? (long)n * n * n : (long)n * n;
+    const int n = s.n;
     if (s.d == 3 && (long)n * n * (long)sizeof(S) > 0x7fffffffL) return hipErrorInvalidValue;
-    // large grids: one long march per CU, unrolled 6 times (2 zc + 2 steps);
-    // small grids: many short marches
-    const bool large = pts >= (1L << 22);
     if (s.d == 3) {
-        const int tx = cdiv(nc, R3_TX), ty = cdiv(nc, R3_TY);
-        const int zc = march_chunk(nc, tx * ty, pts, large ? kWantBlocksLarge : kWantBlocks, 8);
-        const int nch = cdiv(nc, zc);
-        dim3 grid(tx * ty * nch, s.batch);
-        if (large)
-            hipLaunchKernelGGL((k_restrict3d<S, C, R3_TX, R3_TY, R3_NT, 6>), grid, dim3(R3_NT), 0,
-                               st, u, b, bc, n, nc, tx, ty, zc, nch, sA);
-        else
-            hipLaunchKernelGGL((k_restrict3d<S, C, R3_TX, R3_TY, R3_NT, 2>), grid, dim3(R3_NT), 0,
-                               st, u, b, bc, n, nc, tx, ty, zc, nch, sA);
-    } else {
-        const int tx = cdiv(nc, R2_TX);
-        const int yc = march_chunk(nc, tx, pts, large ? kWantBlocksLarge : kWantBlocks, 8);
-        const int nch = cdiv(nc, yc);
-        dim3 grid(tx * nch, s.batch);
-        if (large)
-            hipLaunchKernelGGL((k_restrict2d<S, C, R2_TX, R2_NT, 6>), grid, dim3(R2_NT), 0, st, u,
-                               b, bc, n, nc, tx, yc, nch, sA);
-        else
-            hipLaunchKernelGGL((k_restrict2d<S, C, R2_TX, R2_NT, 2>), grid, dim3(R2_NT), 0, st, u,
-                               b, bc, n, nc, tx, yc, nch, sA);
+        if (n >= 200) return launch_restrict3d<S, C, 32, 8, 576, 6>(s, 256, 8, st);
+        return launch_restrict3d<S, C, 32, 4, 320, 2>(s, 512, 1, st);
     }
-    return hipGetLastError();
+    if (n >= 3000) return launch_restrict2d<S, C, 512, 576, 6>(s, 256, 8, st);
+    if (n >= 700) return launch_restrict2d<S, C, 256, 320, 2>(s, 512, 1, st);
+    return launch_restrict2d<S, C, 128, 192, 2>(s, 512, 1, st);
 }
 
 template <typename S, typename C>
@@ -1855,27 +1887,43 @@ hipError_t ir_impl(const IRStep& s, hipStream_t st, int* nparts) {
     const int n = s.n;
     const S* e = static_cast<const S*>(s.e_lo);
     S* rlo = static_cast<S*>(s.r_lo);
+    if (s.d == 3 && (long)n * n * 8L > 0x7fffffffL) return hipErrorInvalidValue;
+    const bool large = s.d == 3 ? n >= 200 : n >= 3000;
+    // same shapes as the smoothers; large grids: one long march per CU,
+    // unrolled 6 times, non-temporal stores
+#define IR3(TX, TY, NT, UN, NTS, WANT, MINC)                                                    \
+    do {                                                                                       \
+        const int tx = cdiv(n, TX), ty = cdiv(n, TY);                                          \
+        const int zc = pick_chunk(n, tx * ty, WANT, MINC);                                     \
+        const int nch = cdiv(n, zc);                                                           \
+        dim3 grid(tx * ty * nch, s.batch);                                                     \
+        if (nparts) *nparts = grid.x * grid.y;                                                 \
+        if ((long)grid.x * grid.y > s.partials_cap) return hipErrorInvalidValue;               \
+        hipLaunchKernelGGL((k_ir3d<S, TX, TY, NT, UN, NTS>), grid, dim3(NT), 0, st, s.u, s.unew, \
+                           e, s.b, rlo, n, tx, ty, zc, nch, s.inv_h2, s.sigma0, s.k, s.scales,  \
+                           s.maxprev, s.psum, s.pmax);                                          \
+    } while (0)
+#define IR2(TX, NT, UN, NTS, WANT, MINC)                                                        \
+    do {                                                                                       \
+        const int tx = cdiv(n, TX);                                                            \
+        const int yc = pick_chunk(n, tx, WANT, MINC);                                          \
+        const int nch = cdiv(n, yc);                                                           \
+        dim3 grid(tx * nch, s.batch);                                                          \
+        if (nparts) *nparts = grid.x * grid.y;                                                 \
+        if ((long)grid.x * grid.y > s.partials_cap) return hipErrorInvalidValue;               \
+        hipLaunchKernelGGL((k_ir2d<S, TX, NT, UN, NTS>), grid, dim3(NT), 0, st, s.u, s.unew, e, \
+                           s.b, rlo, n, tx, yc, nch, s.inv_h2, s.sigma0, s.k, s.scales,         \
+                           s.maxprev, s.psum, s.pmax);                                          \
+    } while (0)
     if (s.d == 3) {
-        const int tx = cdiv(n, I3_TX), ty = cdiv(n, I3_TY);
-        const int zc = march_chunk(n, tx * ty, (long)n * n * n, kWantBlocks, 8);
-        const int nch = cdiv(n, zc);
-        dim3 grid(tx * ty * nch, s.batch);
-        if (nparts) *nparts = grid.x * grid.y;
-        if ((long)grid.x * grid.y > s.partials_cap) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((k_ir3d<S, I3_TX, I3_TY, I3_NT, S_PD>), grid, dim3(I3_NT), 0, st, s.u,
-                           s.unew, e, s.b, rlo, n, tx, ty, zc, nch, s.inv_h2, s.sigma0, s.k,
-                           s.scales, s.maxprev, s.psum, s.pmax);
+        if (large) IR3(64, 16, 640, 6, true, 256, 32);
+        else IR3(32, 16, 320, 2, false, 512, 1);
     } else {
-        const int tx = cdiv(n, I2_TX);
-        const int yc = march_chunk(n, tx, (long)n * n, kWantBlocks, 16);
-        const int nch = cdiv(n, yc);
-        dim3 grid(tx * nch, s.batch);
-        if (nparts) *nparts = grid.x * grid.y;
-        if ((long)grid.x * grid.y > s.partials_cap) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((k_ir2d<S, I2_TX, S_PD>), grid, dim3(I2_TX), 0, st, s.u, s.unew, e, s.b,
-                           rlo, n, tx, yc, nch, s.inv_h2, s.sigma0, s.k, s.scales, s.maxprev,
-                           s.psum, s.pmax);
+        if (large) IR2(1024, 576, 6, true, 256, 32);
+        else IR2(128, 192, 2, false, 512, 1);
     }
+#undef IR3
+#undef IR2
     return hipGetLastError();
 }
 
