@@ -69,6 +69,15 @@ struct mg_ctx {
     double* dnorm = nullptr;     // device norms: 2 per slot (norm, max)
     double* dscale = nullptr;    // refinement scales per step
     double* hnorm = nullptr;     // pinned host mirror of dnorm
+    double* hnorm_dev = nullptr; // its device address
+    // partial sums of a finished sweep waiting to be reduced: by the next
+    // restriction of cycle() (block 0 of that launch), else by k_finalize
+    struct PendingNorm {
+        int count = 0;           // partials in psum (0 = nothing pending)
+        bool with_max = false;   // also reduce pmax into dnorm[2 slot + 1]
+        int slot = -1;
+        hipEvent_t ready = nullptr;  // recorded once the host mirror is written
+    } pend;
     int norm_slots = 0;
     // adjoint scratch (FP64), allocated on first use; per level
     std::vector<double*> adj_r1, adj_r3, adj_w, adj_ua, adj_ub, adj_uo, adj_bb;
@@ -219,7 +228,7 @@ int alloc_common(mg_ctx* h) {
     if (h->dnorm) (void)hipFree(h->dnorm);
     if (h->dscale) (void)hipFree(h->dscale);
     if (h->hnorm) (void)hipHostFree(h->hnorm);
-    h->ualt = h->psum = h->pmax = h->dnorm = h->dscale = h->hnorm = nullptr;
+    h->ualt = h->psum = h->pmax = h->dnorm = h->dscale = h->hnorm = h->hnorm_dev = nullptr;
     const size_t fine = (size_t)level_pts(h, 0) * h->batch * sizeof(double);
     HIPCHK(hipMalloc(&h->ualt, fine));
     HIPCHK(hipMalloc(&h->psum, kPartialCap * h->batch * sizeof(double)));
@@ -228,6 +237,7 @@ int alloc_common(mg_ctx* h) {
     HIPCHK(hipMalloc(&h->dnorm, 2 * h->norm_slots * sizeof(double)));
     HIPCHK(hipMalloc(&h->dscale, h->norm_slots * sizeof(double)));
     HIPCHK(hipHostMalloc(&h->hnorm, 2 * h->norm_slots * sizeof(double), hipHostMallocDefault));
+    HIPCHK(hipHostGetDevicePointer(reinterpret_cast<void**>(&h->hnorm_dev), h->hnorm, 0));
     return MG_OK;
 }
 
@@ -373,16 +383,30 @@ int cycle(mg_ctx* h, Hier& H, int l, const void* u_in, const void* b, void* out,
                    [&] { return launch_smooth(H.p, zero, norm, s, st, &nparts); });
     if (rc) return rc;
     if (norm) {
-        HIPCHK(launch_finalize(h->psum, nullptr, nparts, h->dnorm + 2 * nr.slot, st));
-        HIPCHK(hipMemcpyAsync(h->hnorm + 2 * nr.slot, h->dnorm + 2 * nr.slot, sizeof(double),
-                              hipMemcpyDeviceToHost, st));
-        if (nr.ready) HIPCHK(hipEventRecord(nr.ready, st));
+        h->pend.count = nparts;
+        h->pend.with_max = false;
+        h->pend.slot = nr.slot;
+        h->pend.ready = nr.ready;
     }
     s.u = tmp;
     s.out = H.b[l + 1];
     s.partials = nullptr;
+    const mg_ctx::PendingNorm pn = h->pend;
+    if (pn.count > 0) {
+        // the restriction's first workgroup reduces the pending norm
+        s.fin_ps = h->psum;
+        s.fin_pm = pn.with_max ? h->pmax : nullptr;
+        s.fin_count = pn.count;
+        s.fin_dev = h->dnorm + 2 * pn.slot;
+        s.fin_host = h->hnorm_dev + 2 * pn.slot;
+        h->pend = mg_ctx::PendingNorm();
+    }
     rc = run_timed(h, MG_TIME_RESTRICT, l, st, [&] { return launch_restrict(H.p, s, st); });
     if (rc) return rc;
+    if (pn.count > 0 && pn.ready) HIPCHK(hipEventRecord(pn.ready, st));
+    s.fin_ps = s.fin_pm = nullptr;
+    s.fin_count = 0;
+    s.fin_dev = s.fin_host = nullptr;
     rc = cycle(h, H, l + 1, nullptr, H.b[l + 1], H.e[l + 1], H.t[l + 1], NormReq(), st);
     if (rc) return rc;
     s.u = tmp;
@@ -396,6 +420,20 @@ int cycle(mg_ctx* h, Hier& H, int l, const void* u_in, const void* b, void* out,
                      [&] { return launch_smooth(H.p, false, false, s, st, nullptr); });
 }
 
+// Reduces a pending norm that no restriction has picked up (tail-only
+// hierarchies) with the standalone kernel and a copy to the host mirror.
+int flush_pending_norm(mg_ctx* h, hipStream_t st) {
+    const mg_ctx::PendingNorm pn = h->pend;
+    if (pn.count == 0) return MG_OK;
+    h->pend = mg_ctx::PendingNorm();
+    HIPCHK(launch_finalize(h->psum, pn.with_max ? h->pmax : nullptr, pn.count,
+                           h->dnorm + 2 * pn.slot, st));
+    HIPCHK(hipMemcpyAsync(h->hnorm + 2 * pn.slot, h->dnorm + 2 * pn.slot, sizeof(double),
+                          hipMemcpyDeviceToHost, st));
+    if (pn.ready) HIPCHK(hipEventRecord(pn.ready, st));
+    return MG_OK;
+}
+
 // One FP64 V(1,1) cycle on the finest grid: u_out = V(u_in, b).  With
 // norm_slot >= 0 the pre-smoother also produces ||b - A u_in||_2 into
 // dnorm[2 slot] and starts its copy to the pinned host mirror.
@@ -404,7 +442,9 @@ int fine_cycle64(mg_ctx* h, const double* b, const double* u_in, double* u_out,
     NormReq nr;
     nr.slot = norm_slot;
     nr.ready = norm_ready;
-    return cycle(h, h->h64, 0, u_in, b, u_out, h->h64.t[0], nr, st);
+    const int rc = cycle(h, h->h64, 0, u_in, b, u_out, h->h64.t[0], nr, st);
+    if (rc) return rc;
+    return flush_pending_norm(h, st);
 }
 
 int check_handle(mg_ctx* h) {
@@ -516,6 +556,7 @@ int mg_vcycle(mg_handle_t h, const double* b, double* u, void* stream) {
     hipStream_t st = (hipStream_t)stream;
     // u is updated in place: the post-smoother reads the internal iterate
     // and writes u, and the pre-smoother never writes u
+    h->pend = mg_ctx::PendingNorm();
     return fine_cycle64(h, b, u, u, -1, st);
 }
 
@@ -592,6 +633,7 @@ int mg_coarse_cycle(mg_handle_t h, int level, int prec, const void* b, void* e,
     }
     hipStream_t st = (hipStream_t)stream;
     void* tmp = H->t[level];
+    h->pend = mg_ctx::PendingNorm();
     int rc = cycle(h, *H, level, nullptr, b, e, tmp, NormReq(), st);
     if (rc) return rc;
     return MG_OK;
@@ -729,13 +771,17 @@ static int solve_ir(mg_ctx* h, const double* b, double* u, double tol, mg_stats*
         rc = run_timed(h, MG_TIME_IR_STEP, 0, st,
                        [&] { return launch_ir_step(H.p, s, st, &nparts); });
         if (rc) return rc;
-        HIPCHK(launch_finalize(h->psum, h->pmax, nparts, h->dnorm + 2 * slot, st));
-        HIPCHK(hipMemcpyAsync(h->hnorm + 2 * slot, h->dnorm + 2 * slot, sizeof(double),
-                              hipMemcpyDeviceToHost, st));
-        HIPCHK(hipEventRecord(evn, st));
+        // (norm, max) of r_k: reduced by the first restriction of the inner
+        // cycle, which also writes the host mirror
+        h->pend.count = nparts;
+        h->pend.with_max = true;
+        h->pend.slot = slot;
+        h->pend.ready = evn;
         // inner low-precision cycles on A e = s r: the first from zero, the
         // others continue from the current e
         rc = cycle(h, H, 0, nullptr, H.b[0], H.e[0], H.t[0], NormReq(), st);
+        if (rc) return rc;
+        rc = flush_pending_norm(h, st);
         if (rc) return rc;
         for (int j = 1; j < inner_cycles(h); ++j) {
             rc = cycle(h, H, 0, H.e[0], H.b[0], H.e[0], H.t[0], NormReq(), st);
@@ -789,6 +835,7 @@ int mg_solve(mg_handle_t h, const double* b, double* u, double tol, mg_stats* st
     if (!b || !u) return fail(MG_EINVAL, "null field pointer");
     if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(MG_EINVAL, "tol must be finite and >= 0");
     hipStream_t s = (hipStream_t)stream;
+    h->pend = mg_ctx::PendingNorm();  // nothing survives a failed call
     if (h->prec == MG_PREC_FP64) return solve64(h, b, u, tol, st, s);
     return solve_ir(h, b, u, tol, st, s);
 }

@@ -33,6 +33,15 @@ struct Sweep {
     // coarse-grid field ((n+1)/2 - 1 interior nodes) of the same storage type
     const void* ec = nullptr;
     double pf = 1.0;
+    // optional norm finalisation (restriction only): block 0 reduces the
+    // fin_count partial sums (and maxima) of the previous sweep in a fixed
+    // order and writes (sqrt(sum), max) to fin_dev and sqrt(sum) to the
+    // pinned host mirror fin_host (device address)
+    const double* fin_ps = nullptr;
+    const double* fin_pm = nullptr;
+    int fin_count = 0;
+    double* fin_dev = nullptr;
+    double* fin_host = nullptr;
 };
 
 // Launchers return hipSuccess or the launch error.  *nparts receives the

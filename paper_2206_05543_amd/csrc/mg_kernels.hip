@@ -171,6 +171,32 @@ __device__ __forceinline__ double block_max(double v, double* red) {
     return s;
 }
 
+// Norm of a finished sweep from its per-block partials, in a fixed order
+// (deterministic run to run): (sqrt(sum ps), max pm) to dev, sqrt(sum ps)
+// to the pinned host mirror `host`.  Run by one whole workgroup of the
+// kernel that follows the sweep, which saves a reduction launch and a copy.
+template <int NT>
+__device__ void finalize_norm(const double* ps, const double* pm, int count, double* dev,
+                              double* host, double* red) {
+    double s = 0.0, mx = 0.0;
+    for (int i = threadIdx.x; i < count; i += NT) {
+        s += ps[i];
+        if (pm) mx = fmax(mx, pm[i]);
+    }
+    const double tot = block_sum<NT>(s, red);
+    __syncthreads();
+    const double tmx = block_max<NT>(mx, red);
+    if (threadIdx.x == 0) {
+        const double nrm = sqrt(tot);
+        dev[0] = nrm;
+        if (pm) dev[1] = tmx;
+        if (host) {
+            host[0] = nrm;
+            __threadfence_system();
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Software pipeline of the marching kernels.  Global loads of the plane that
 // will be consumed PD steps later are issued at the top of each step into
@@ -798,7 +824,9 @@ k_smooth2d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out
 template <typename S, typename C, int TXc, int TYc, int NT, int UN>
 __global__ void __launch_bounds__(NT)
 k_restrict3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ bc,
-             int n, int nc, int tiles_x, int tiles_y, int zchunk, int nchunks, C sA) {
+             int n, int nc, int tiles_x, int tiles_y, int zchunk, int nchunks, C sA,
+             const double* __restrict__ fin_ps, const double* __restrict__ fin_pm, int fin_count,
+             double* __restrict__ fin_dev, double* __restrict__ fin_host) {
     constexpr int FX = 2 * TXc + 1, FY = 2 * TYc + 1, NF = FX * FY;
     constexpr int UX = FX + 2, UY = FY + 2, NU = UX * UY;
     constexpr int M = (NF + NT - 1) / NT;
@@ -810,6 +838,9 @@ k_restrict3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ b
     static_assert(UN % 2 == 0, "unroll covers the prefetch ring and the plane parity");
     __shared__ C uL[2][USZ];
     __shared__ C rL[2][RSZ];
+    __shared__ double red[NT / 64];
+    if (fin_count > 0 && blockIdx.x == 0 && blockIdx.y == 0)
+        finalize_norm<NT>(fin_ps, fin_pm, fin_count, fin_dev, fin_host, red);
 
     const int total = tiles_x * tiles_y * nchunks;
     const int lg = xcd_remap(blockIdx.x, total);
@@ -955,7 +986,9 @@ k_restrict3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ b
 template <typename S, typename C, int TXc, int NT, int UN>
 __global__ void __launch_bounds__(NT)
 k_restrict2d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ bc,
-             int n, int nc, int tiles_x, int ychunk, int nchunks, C sA) {
+             int n, int nc, int tiles_x, int ychunk, int nchunks, C sA,
+             const double* __restrict__ fin_ps, const double* __restrict__ fin_pm, int fin_count,
+             double* __restrict__ fin_dev, double* __restrict__ fin_host) {
     constexpr int FX = 2 * TXc + 1, UX = FX + 2;
     constexpr int M = (FX + NT - 1) / NT;
     constexpr int RSZ = M * NT + 2;
@@ -965,6 +998,9 @@ k_restrict2d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ b
     static_assert(UN % 2 == 0, "unroll covers the prefetch ring and the row parity");
     __shared__ C uL[2][USZ];
     __shared__ C rL[2][RSZ];
+    __shared__ double red[NT / 64];
+    if (fin_count > 0 && blockIdx.x == 0 && blockIdx.y == 0)
+        finalize_norm<NT>(fin_ps, fin_pm, fin_count, fin_dev, fin_host, red);
 
     const int total = tiles_x * nchunks;
     const int lg = xcd_remap(blockIdx.x, total);
@@ -1812,7 +1848,8 @@ hipError_t launch_restrict3d(const Sweep& s, int want, int minc, hipStream_t st)
     dim3 grid(tx * ty * nch, s.batch);
     hipLaunchKernelGGL((k_restrict3d<S, C, TXc, TYc, NT, UN>), grid, dim3(NT), 0, st,
                        static_cast<const S*>(s.u), static_cast<const S*>(s.b),
-                       static_cast<S*>(s.out), n, nc, tx, ty, zc, nch, C(s.sA));
+                       static_cast<S*>(s.out), n, nc, tx, ty, zc, nch, C(s.sA), s.fin_ps,
+                       s.fin_pm, s.fin_count, s.fin_dev, s.fin_host);
     return hipGetLastError();
 }
 
@@ -1825,7 +1862,8 @@ hipError_t launch_restrict2d(const Sweep& s, int want, int minc, hipStream_t st)
     dim3 grid(tx * nch, s.batch);
     hipLaunchKernelGGL((k_restrict2d<S, C, TXc, NT, UN>), grid, dim3(NT), 0, st,
                        static_cast<const S*>(s.u), static_cast<const S*>(s.b),
-                       static_cast<S*>(s.out), n, nc, tx, yc, nch, C(s.sA));
+                       static_cast<S*>(s.out), n, nc, tx, yc, nch, C(s.sA), s.fin_ps,
+                       s.fin_pm, s.fin_count, s.fin_dev, s.fin_host);
     return hipGetLastError();
 }
 
