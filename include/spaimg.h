@@ -82,8 +82,7 @@ extern "C" {
 #define MG_OP_PROLONG_ADD 3  /* out += P u, u on level+1 (in place on out)     */
 
 /* timing kinds for mg_get_timing */
-#define MG_TIME_SMOOTH 0      /* smoothing from a guess (pre-smoothing, and
-                                 post-smoothing on small grids)            */
+#define MG_TIME_SMOOTH 0      /* smoothing from a guess (pre-smoothing)    */
 #define MG_TIME_SMOOTH_ZERO 1
 #define MG_TIME_RESTRICT 2
 #define MG_TIME_PROLONG 3

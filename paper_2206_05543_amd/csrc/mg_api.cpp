@@ -778,15 +778,13 @@ static int solve_ir(mg_ctx* h, const double* b, double* u, double tol, mg_stats*
         h->pend.slot = slot;
         h->pend.ready = evn;
         // inner low-precision cycles on A e = s r: the first from zero, the
-        // others continue from the current e
+        // others continue from the current e.  The host reads ||r_k|| while
+        // the first inner cycle runs and enqueues the others only if the
+        // solve goes on, so a converged solve discards one inner cycle.
         rc = cycle(h, H, 0, nullptr, H.b[0], H.e[0], H.t[0], NormReq(), st);
         if (rc) return rc;
         rc = flush_pending_norm(h, st);
         if (rc) return rc;
-        for (int j = 1; j < inner_cycles(h); ++j) {
-            rc = cycle(h, H, 0, H.e[0], H.b[0], H.e[0], H.t[0], NormReq(), st);
-            if (rc) return rc;
-        }
         ++run;
         HIPCHK(hipEventSynchronize(evn));
         const double nk = h->hnorm[2 * slot];
@@ -802,6 +800,10 @@ static int solve_ir(mg_ctx* h, const double* b, double* u, double tol, mg_stats*
         if (k >= h->max_cycles) {
             code = MG_ENOCONV;
             break;
+        }
+        for (int j = 1; j < inner_cycles(h); ++j) {
+            rc = cycle(h, H, 0, H.e[0], H.b[0], H.e[0], H.t[0], NormReq(), st);
+            if (rc) return rc;
         }
         std::swap(X, Y);
     }

@@ -1426,7 +1426,9 @@ __device__ __forceinline__ double ir_scale(const double* maxprev) {
     return ldexp(1.0, -e);  // s m in [0.5, 1)
 }
 
-template <typename S, int TX, int TY, int NT, int UN, bool NTS>
+// RES: residual norm only (no e, no stores, no scale): the initial residual
+// pass of a solve and mg_residual_norm
+template <typename S, int TX, int TY, int NT, int UN, bool NTS, bool RES>
 __global__ void __launch_bounds__(NT)
 k_ir3d(const double* __restrict__ u, double* __restrict__ unew, const S* __restrict__ e,
        const double* __restrict__ b, S* __restrict__ rlo, int n, int tiles_x, int tiles_y,
@@ -1449,13 +1451,13 @@ k_ir3d(const double* __restrict__ u, double* __restrict__ unew, const S* __restr
     unew += boff;
     b += boff;
     rlo += boff;
-    const bool hase = e != nullptr && k > 0;
+    const bool hase = !RES && e != nullptr && k > 0;
     if (hase) e += boff;
     const int x0 = tx * TX, y0 = ty * TY;
     const int z0 = ch * zchunk, z1 = min(z0 + zchunk, n);
     const int t = threadIdx.x;
-    const double s_new = ir_scale(maxprev);
-    if (blockIdx.x == 0 && blockIdx.y == 0 && t == 0) scales[k] = s_new;
+    const double s_new = RES ? 1.0 : ir_scale(maxprev);
+    if (!RES && blockIdx.x == 0 && blockIdx.y == 0 && t == 0) scales[k] = s_new;
     const double escale = hase ? 1.0 / (sigma0 * scales[k - 1]) : 0.0;
 
     unsigned gu[M], ge[M], gi[M];  // byte offsets: u (ring), e (ring), interior
@@ -1535,8 +1537,10 @@ k_ir3d(const double* __restrict__ u, double* __restrict__ unew, const S* __restr
                 const double lap = 6.0 * u0[m] - U[q - 1] - U[q + 1] - U[q - RX] - U[q + RX] -
                                    um1[m] - up1[m];
                 const double r = rb[k % RS][m] - inv_h2 * lap;
-                bstore<NTS>(u0[m], ow, gi[m]);
-                bstore<NTS>(static_cast<S>(s_new * r), orl, inn[m] ? ge[m] : kOob);
+                if (!RES) {
+                    bstore<NTS>(u0[m], ow, gi[m]);
+                    bstore<NTS>(static_cast<S>(s_new * r), orl, inn[m] ? ge[m] : kOob);
+                }
                 acc += inn[m] ? r * r : 0.0;
                 mx = fmax(mx, inn[m] ? fabs(r) : 0.0);
             }
@@ -1561,7 +1565,7 @@ k_ir3d(const double* __restrict__ u, double* __restrict__ unew, const S* __restr
     }
 }
 
-template <typename S, int TX, int NT, int UN, bool NTS>
+template <typename S, int TX, int NT, int UN, bool NTS, bool RES>
 __global__ void __launch_bounds__(NT)
 k_ir2d(const double* __restrict__ u, double* __restrict__ unew, const S* __restrict__ e,
        const double* __restrict__ b, S* __restrict__ rlo, int n, int tiles_x, int ychunk,
@@ -1583,13 +1587,13 @@ k_ir2d(const double* __restrict__ u, double* __restrict__ unew, const S* __restr
     unew += boff;
     b += boff;
     rlo += boff;
-    const bool hase = e != nullptr && k > 0;
+    const bool hase = !RES && e != nullptr && k > 0;
     if (hase) e += boff;
     const int x0 = tx * TX;
     const int y0 = ch * ychunk, y1 = min(y0 + ychunk, n);
     const int t = threadIdx.x;
-    const double s_new = ir_scale(maxprev);
-    if (blockIdx.x == 0 && blockIdx.y == 0 && t == 0) scales[k] = s_new;
+    const double s_new = RES ? 1.0 : ir_scale(maxprev);
+    if (!RES && blockIdx.x == 0 && blockIdx.y == 0 && t == 0) scales[k] = s_new;
     const double escale = hase ? 1.0 / (sigma0 * scales[k - 1]) : 0.0;
     unsigned gu[M], ge[M], gi[M];
     bool inn[M];
@@ -1664,8 +1668,10 @@ k_ir2d(const double* __restrict__ u, double* __restrict__ unew, const S* __restr
                 const int q = 1 + t + m * NT;
                 const double lap = 4.0 * u0[m] - U[q - 1] - U[q + 1] - um1[m] - up1[m];
                 const double r = rb[k % RS][m] - inv_h2 * lap;
-                bstore<NTS>(u0[m], ow, gi[m]);
-                bstore<NTS>(static_cast<S>(s_new * r), orl, inn[m] ? ge[m] : kOob);
+                if (!RES) {
+                    bstore<NTS>(u0[m], ow, gi[m]);
+                    bstore<NTS>(static_cast<S>(s_new * r), orl, inn[m] ? ge[m] : kOob);
+                }
                 acc += inn[m] ? r * r : 0.0;
                 mx = fmax(mx, inn[m] ? fabs(r) : 0.0);
             }
@@ -1684,47 +1690,6 @@ k_ir2d(const double* __restrict__ u, double* __restrict__ unew, const S* __restr
     __syncthreads();
     const double tm = block_max<NT>(mx, red);
     if (t == 0) {
-        const long pi = (long)blockIdx.y * gridDim.x + blockIdx.x;
-        psum[pi] = ts;
-        pmax[pi] = tm;
-    }
-}
-
-// ---------------------------------------------------------------------------
-// FP64 residual norm of the fine grid: per-block sum of r^2 and max |r|.
-// One node per thread; neighbours come through L1/L2 (used once per solve).
-// ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256)
-k_residual_norm(const double* __restrict__ u, const double* __restrict__ b, int d, int n,
-                double inv_h2, double* __restrict__ psum, double* __restrict__ pmax) {
-    __shared__ double red[4];
-    const long pts = d == 3 ? (long)n * n * n : (long)n * n;
-    const long off = (long)blockIdx.y * pts;
-    u += off;
-    b += off;
-    double rr = 0.0, mx = 0.0;
-    const long sy = n, sz = (long)n * n;
-    for (long idx = (long)blockIdx.x * 256 + threadIdx.x; idx < pts;
-         idx += (long)gridDim.x * 256) {
-        const int i = idx % n, j = (idx / n) % n;
-        const int k = d == 3 ? (int)(idx / ((long)n * n)) : 0;
-        double lap = 2.0 * d * u[idx];
-        if (i > 0) lap -= u[idx - 1];
-        if (i < n - 1) lap -= u[idx + 1];
-        if (j > 0) lap -= u[idx - sy];
-        if (j < n - 1) lap -= u[idx + sy];
-        if (d == 3) {
-            if (k > 0) lap -= u[idx - sz];
-            if (k < n - 1) lap -= u[idx + sz];
-        }
-        const double r = b[idx] - inv_h2 * lap;
-        rr += r * r;
-        mx = fmax(mx, fabs(r));
-    }
-    const double ts = block_sum<256>(rr, red);
-    __syncthreads();
-    const double tm = block_max<256>(mx, red);
-    if (threadIdx.x == 0) {
         const long pi = (long)blockIdx.y * gridDim.x + blockIdx.x;
         psum[pi] = ts;
         pmax[pi] = tm;
@@ -1752,15 +1717,17 @@ constexpr int kWantBlocks = 1024;
 inline int even_chunk(int c) { return c + (c & 1); }
 
 // Launch configurations of the marching sweeps by grid size, measured on
-// MI355X in FP64 (the same shapes serve FP32/FP16 storage).  `want` is the
+// MI355X in FP64 (the same shapes serve FP32/FP16 storage unless noted).  `want` is the
 // number of marches (workgroups) per batch entry: one long march per CU on
 // large grids, where halo planes cost bandwidth, more and shorter ones on
 // smaller grids, where latency dominates.
 //   smoother 3D  n >= 200: 64x16 tiles / 640 threads, unrolled 6, 256 marches
+//                (FP32/FP16 storage: 128x16 / 768, 1024 marches)
 //                n >= 100: 64x16 / 640, 256 marches;  else 32x16 / 320, 256
 //   smoother 2D  n >= 3000: 1024-wide strips / 576 threads, unrolled 4, 256
 //                n >= 700: 512 / 320, 512 marches;  else 128 / 192, 512
-//   restriction  3D n >= 200: 32x8 coarse columns / 576, unrolled 6, 256;
+//   restriction  3D n >= 200: 32x8 coarse columns / 576, unrolled 6, 256
+//                (FP32/FP16: 64x8 / 768, 512);
 //                else 32x4 / 320, 512;  2D n >= 3000: 512 / 576, unrolled 6,
 //                256; n >= 700: 256 / 320, 512; else 128 / 192, 512
 template <typename S, typename C, int TX, int TY, int NT, int UN, bool NTS>
@@ -1830,6 +1797,10 @@ hipError_t smooth_impl(bool zg, bool norm, const Sweep& s, hipStream_t st, int* 
     // the large configurations (at least 200^3 or 3000^2 > 2^22 nodes)
     // store non-temporally
     if (s.d == 3) {
+        // FP32 / FP16 storage: 128-wide tiles and 1024 marches (4-byte and
+        // 2-byte rows need longer row segments and more waves in flight)
+        if (sizeof(S) < 8 && n >= 200)
+            return launch_smooth3d<S, C, 128, 16, 768, 6, true>(zg, norm, s, 1024, 32, st, nparts);
         if (n >= 200) return launch_smooth3d<S, C, 64, 16, 640, 6, true>(zg, norm, s, 256, 32, st, nparts);
         if (n >= 100) return launch_smooth3d<S, C, 64, 16, 640, 2, false>(zg, norm, s, 256, 2, st, nparts);
         return launch_smooth3d<S, C, 32, 16, 320, 2, false>(zg, norm, s, 256, 2, st, nparts);
@@ -1872,6 +1843,7 @@ hipError_t restrict_impl(const Sweep& s, hipStream_t st) {
     const int n = s.n;
     if (s.d == 3 && (long)n * n * (long)sizeof(S) > 0x7fffffffL) return hipErrorInvalidValue;
     if (s.d == 3) {
+        if (sizeof(S) < 8 && n >= 200) return launch_restrict3d<S, C, 64, 8, 768, 6>(s, 512, 8, st);
         if (n >= 200) return launch_restrict3d<S, C, 32, 8, 576, 6>(s, 256, 8, st);
         return launch_restrict3d<S, C, 32, 4, 320, 2>(s, 512, 1, st);
     }
@@ -1920,7 +1892,7 @@ hipError_t tail_impl(const Tail& t, hipStream_t st) {
     return t.d == 3 ? tail_impl_d<S, C, 3>(t, lds, st) : tail_impl_d<S, C, 2>(t, lds, st);
 }
 
-template <typename S>
+template <typename S, bool RES>
 hipError_t ir_impl(const IRStep& s, hipStream_t st, int* nparts) {
     const int n = s.n;
     const S* e = static_cast<const S*>(s.e_lo);
@@ -1937,7 +1909,7 @@ hipError_t ir_impl(const IRStep& s, hipStream_t st, int* nparts) {
         dim3 grid(tx * ty * nch, s.batch);                                                     \
         if (nparts) *nparts = grid.x * grid.y;                                                 \
         if ((long)grid.x * grid.y > s.partials_cap) return hipErrorInvalidValue;               \
-        hipLaunchKernelGGL((k_ir3d<S, TX, TY, NT, UN, NTS>), grid, dim3(NT), 0, st, s.u, s.unew, \
+        hipLaunchKernelGGL((k_ir3d<S, TX, TY, NT, UN, NTS, RES>), grid, dim3(NT), 0, st, s.u, s.unew, \
                            e, s.b, rlo, n, tx, ty, zc, nch, s.inv_h2, s.sigma0, s.k, s.scales,  \
                            s.maxprev, s.psum, s.pmax);                                          \
     } while (0)
@@ -1949,7 +1921,7 @@ hipError_t ir_impl(const IRStep& s, hipStream_t st, int* nparts) {
         dim3 grid(tx * nch, s.batch);                                                          \
         if (nparts) *nparts = grid.x * grid.y;                                                 \
         if ((long)grid.x * grid.y > s.partials_cap) return hipErrorInvalidValue;               \
-        hipLaunchKernelGGL((k_ir2d<S, TX, NT, UN, NTS>), grid, dim3(NT), 0, st, s.u, s.unew, e, \
+        hipLaunchKernelGGL((k_ir2d<S, TX, NT, UN, NTS, RES>), grid, dim3(NT), 0, st, s.u, s.unew, e, \
                            s.b, rlo, n, tx, yc, nch, s.inv_h2, s.sigma0, s.k, s.scales,         \
                            s.maxprev, s.psum, s.pmax);                                          \
     } while (0)
@@ -2019,19 +1991,25 @@ hipError_t launch_finalize(const double* partials, const double* maxparts, int c
 hipError_t launch_residual_norm(int d, int n, int batch, const double* u, const double* b,
                                 double inv_h2, double* psum, double* pmax, long partials_cap,
                                 hipStream_t st, int* nparts) {
-    const long pts = d == 3 ? (long)n * n * n : (long)n * n;
-    dim3 grid(std::min(cdiv(pts, 256), 4096), batch);
-    if (nparts) *nparts = grid.x * grid.y;
-    if ((long)grid.x * grid.y > partials_cap) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_residual_norm, grid, dim3(256), 0, st, u, b, d, n, inv_h2, psum, pmax);
-    return hipGetLastError();
+    // the marching refinement-step kernel without its stores
+    IRStep s;
+    s.d = d;
+    s.n = n;
+    s.batch = batch;
+    s.u = u;
+    s.b = b;
+    s.inv_h2 = inv_h2;
+    s.psum = psum;
+    s.pmax = pmax;
+    s.partials_cap = partials_cap;
+    return ir_impl<double, true>(s, st, nparts);
 }
 
 hipError_t launch_ir_step(Prec p, const IRStep& s, hipStream_t st, int* nparts) {
     switch (p) {
-        case P32: return ir_impl<float>(s, st, nparts);
-        case P16: return ir_impl<_Float16>(s, st, nparts);
-        default: return ir_impl<double>(s, st, nparts);
+        case P32: return ir_impl<float, false>(s, st, nparts);
+        case P16: return ir_impl<_Float16, false>(s, st, nparts);
+        default: return ir_impl<double, false>(s, st, nparts);
     }
 }
 
