@@ -63,8 +63,9 @@ extern "C" {
 #define MG_OPT_TAIL_N 4     /* largest coarse grid (intervals, power of two,
                                4..64 in 2D, 4..16 in 3D) solved by the
                                single-workgroup LDS tail kernel; 0 = default   */
-#define MG_OPT_TIMING 5     /* 0 off; 1 time the fine-level smoother with HIP
-                               events; 2 time every kernel of every level      */
+#define MG_OPT_TIMING 5     /* 0 off; 1 time the fine-level post-smoother
+                               (with the fused correction) with HIP events;
+                               2 time every kernel of every level              */
 #define MG_OPT_INNER_CYCLES 6 /* low-precision V-cycles per FP64 refinement
                                step, 1..16; 0 = default (3 for FP32, 2 for
                                FP16)                                          */

@@ -260,7 +260,9 @@ int realloc_all(mg_ctx* h) {
 
 bool timed(const mg_ctx* h, int kind, int level) {
     if (h->timing == 2) return true;
-    return h->timing == 1 && kind == MG_TIME_SMOOTH && level == 0;
+    // mode 1: the fine-level post-smoother with the fused correction (the
+    // longest-running kernel of a cycle), one event pair per cycle
+    return h->timing == 1 && level == 0 && kind == MG_TIME_SMOOTH_CORRECT;
 }
 
 int time_begin(mg_ctx* h, int kind, int level, hipStream_t st, TimedLaunch* tl) {
