@@ -234,3 +234,37 @@ def grad_kcycles(d, N, c, e0, b, K):
             cbar += cb
         e0bar[s] = ubar
     return L, cbar, bbar, e0bar
+
+
+def descend(d, N, c0, e0, b, K, max_iter=200, rtol=1e-7, armijo=1e-4):
+    """Coefficient fit by plain gradient descent with Armijo backtracking on
+    loss_kcycles, gradients from grad_kcycles (reading of the unstated
+    procedure for the coefficient-recovery experiment).  First trial step:
+    1% of |c|; the trial step doubles after an accepted step and halves
+    until L(c - a g) <= L(c) - armijo a |g|^2.  Stops when the accepted step
+    is below rtol |c| or after max_iter steps.  Returns (c, L, steps)."""
+    c = np.array(c0, dtype=np.float64)
+    L, g, _, _ = grad_kcycles(d, N, c, e0, b, K)
+    alpha = None
+    it = 0
+    for it in range(1, max_iter + 1):
+        gn = float(np.linalg.norm(g))
+        if gn == 0.0:
+            break
+        alpha = 1e-2 * float(np.linalg.norm(c)) / gn if alpha is None else 2.0 * alpha
+        while True:
+            cn = c - alpha * g
+            Ln = loss_kcycles(d, N, cn, e0, b, K)
+            if Ln <= L - armijo * alpha * gn * gn:
+                break
+            alpha *= 0.5
+            if alpha * gn <= 1e-16 * float(np.linalg.norm(c)):
+                break
+        step = alpha * gn
+        if Ln > L:
+            break
+        c = cn
+        L, g, _, _ = grad_kcycles(d, N, c, e0, b, K)
+        if step <= rtol * float(np.linalg.norm(c)):
+            break
+    return c, L, it

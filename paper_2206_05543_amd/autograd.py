@@ -12,6 +12,8 @@ iterate to FP32, stores it, and continues from the rounded value; the
 recomputation in the backward pass is then bit-identical to the forward pass
 and the gradient is exact for the computed forward map.
 """
+import math
+
 import torch
 
 from ._lib import Multigrid
@@ -57,3 +59,54 @@ def kcycles(mg: Multigrid, coeffs, b, u0, K, checkpoint_dtype=torch.float64):
     (1-D tensor of 3 (2D) or 2 (3D) values), differentiable in coeffs, b and
     u0.  b and u0 are CUDA tensors with mg.batch * (N-1)^d elements."""
     return _KCycles.apply(coeffs, b, u0, mg, int(K), checkpoint_dtype)
+
+
+def descend(mg: Multigrid, coeffs, e0, b, K, max_iter=200, rtol=1e-7,
+            checkpoint_dtype=torch.float32, armijo=1e-4):
+    """Plain gradient descent with Armijo backtracking, in FP64, on the
+    smoother coefficients for the k-cycle loss L(c) = sum over the batch of
+    ||V^K(e0, b; c)||^2, with gradients from the adjoint cycle.
+
+    The first step moves the coefficients by 1% of their norm; after an
+    accepted step the trial step doubles, and it halves until the Armijo
+    condition L(c - a g) <= L(c) - armijo a |g|^2 holds.  Stops when the
+    accepted step is below rtol |c| or after max_iter steps.  Returns a dict
+    with the final coefficients, loss, gradient and the loss history."""
+    c = torch.as_tensor(coeffs, dtype=torch.float64).detach().clone().cpu()
+
+    def loss(cc, grad):
+        cp = cc.clone().requires_grad_(grad)
+        u = kcycles(mg, cp, b, e0, K, checkpoint_dtype)
+        L = (u * u).sum()
+        if not grad:
+            return float(L), None
+        L.backward()
+        return float(L), cp.grad.detach().clone()
+
+    L, g = loss(c, True)
+    hist = [L]
+    alpha = None
+    it = 0
+    for it in range(1, max_iter + 1):
+        gn = float(g.norm())
+        if gn == 0.0:
+            break
+        alpha = 1e-2 * float(c.norm()) / gn if alpha is None else 2.0 * alpha
+        while True:
+            cn = c - alpha * g
+            Ln, _ = loss(cn, False)
+            if Ln <= L - armijo * alpha * gn * gn:
+                break
+            alpha *= 0.5
+            if alpha * gn <= 1e-16 * float(c.norm()):
+                break
+        step = alpha * gn
+        if Ln > L:  # no descent possible at working precision
+            break
+        c = cn
+        L, g = loss(c, True)
+        hist.append(L)
+        if step <= rtol * float(c.norm()):
+            break
+    return {"coeffs": c.tolist(), "loss": L, "grad": g.tolist(), "iterations": it,
+            "history": hist}
