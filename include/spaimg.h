@@ -69,6 +69,16 @@ extern "C" {
 #define MG_OPT_INNER_CYCLES 6 /* low-precision V-cycles per FP64 refinement
                                step, 1..16; 0 = default (3 for FP32, 2 for
                                FP16)                                          */
+#define MG_OPT_CYCLE 7      /* MG_CYCLE_*: the cycle of mg_vcycle, mg_solve
+                               and the inner cycles of refinement (default V) */
+
+/* cycles for MG_OPT_CYCLE (Section 4 tests both) */
+#define MG_CYCLE_V11 0      /* V(1,1): one pre- and one post-smoothing step   */
+#define MG_CYCLE_W10 1      /* W(1,0): one pre-smoothing step, two coarse-grid
+                               visits per level, no post-smoothing; the
+                               coarse levels run one level per launch and
+                               only the 3^d grid is solved in the tail.  Not
+                               available for mg_vcycle_adjoint.               */
 
 /* precisions for MG_OPT_PRECISION */
 #define MG_PREC_FP64 0      /* FP64 V-cycles                                  */

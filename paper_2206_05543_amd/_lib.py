@@ -15,7 +15,8 @@ LIB_PATH = os.path.join(HERE, "libspaimg.so")
 
 MG_OK, MG_EINVAL, MG_EHIP, MG_ENOCONV, MG_ENONFINITE = 0, -1, -2, -3, -4
 OPT_PRECISION, OPT_BATCH, OPT_MAX_CYCLES, OPT_TAIL_N, OPT_TIMING = 1, 2, 3, 4, 5
-OPT_INNER_CYCLES = 6
+OPT_INNER_CYCLES, OPT_CYCLE = 6, 7
+CYCLE = {"V11": 0, "W10": 1}
 PREC = {"fp64": 0, "fp32_ir": 1, "fp16_ir": 2}
 OP = {"smooth": 0, "smooth_zero": 1, "restrict": 2, "prolong_add": 3}
 TIME = {"smooth": 0, "smooth_zero": 1, "restrict": 2, "prolong": 3, "tail": 4,
@@ -86,7 +87,7 @@ class Multigrid:
     """Handle on one solver instance (mg_setup ... mg_destroy)."""
 
     def __init__(self, N, d, coeffs, batch=1, precision="fp64", max_cycles=100,
-                 tail_N=0, timing=0):
+                 tail_N=0, timing=0, cycle="V11"):
         self.N, self.d = int(N), int(d)
         self.n = self.N - 1
         self.ncoef = 3 if d == 2 else 2
@@ -106,6 +107,9 @@ class Multigrid:
             self.set_option(OPT_TAIL_N, tail_N)
         if timing:
             self.set_option(OPT_TIMING, timing)
+        self.cycle = "V11"
+        if cycle != "V11":
+            self.set_cycle(cycle)
 
     # ---- options
     def set_option(self, key, value):
@@ -118,6 +122,11 @@ class Multigrid:
     def set_precision(self, precision):
         self.set_option(OPT_PRECISION, PREC[precision])
         self.precision = precision
+
+    def set_cycle(self, cycle):
+        """"V11" (V(1,1)) or "W10" (W(1,0)) for vcycle, solve and refinement."""
+        self.set_option(OPT_CYCLE, CYCLE[cycle])
+        self.cycle = cycle
 
     def set_coeffs(self, coeffs):
         _check(lib().mg_set_coeffs(self._h, _dbl_array(coeffs), len(coeffs)))

@@ -60,6 +60,7 @@ struct mg_ctx {
     int N = 0, d = 2, L = 0, batch = 1, prec = MG_PREC_FP64, max_cycles = 100;
     int tail_N = 0;  // 0 = default
     int inner = 0;   // inner cycles per refinement step, 0 = default
+    int cycle_kind = MG_CYCLE_V11;
     int ncoef = 3;
     double c[3] = {0, 0, 0};
     Hier h64, hlo;
@@ -348,8 +349,8 @@ struct NormReq {
     hipEvent_t ready = nullptr;     // recorded after the copy to the host
 };
 
-// One V(1,1) cycle on hierarchy H at level l: out = V(u_in, b), or from a
-// zero guess when u_in is null.  tmp receives the pre-smoothed iterate
+// One cycle (V(1,1), or W(1,0) under MG_CYCLE_W10) on hierarchy H at level
+// l: out = V(u_in, b), or from a zero guess when u_in is null.  tmp receives the pre-smoothed iterate
 // (must differ from u_in, b and out; out may alias u_in).  Coarser levels
 // use H.b / H.e / H.t.  Zero-guess cycles at or below the tail size run in
 // the single-workgroup LDS tail kernel; the coarsest grid is always solved
@@ -357,8 +358,11 @@ struct NormReq {
 int cycle(mg_ctx* h, Hier& H, int l, const void* u_in, const void* b, void* out, void* tmp,
           const NormReq& nr, hipStream_t st) {
     const bool zero = u_in == nullptr;
+    const bool wcycle = h->cycle_kind == MG_CYCLE_W10;
     int rc, nparts = 0;
-    if (l == h->L - 1 || (zero && l >= tail_level(h, true))) {
+    // the LDS tail runs V(1,1) on its levels: W cycles use it only for the
+    // exact solve on the coarsest grid
+    if (l == h->L - 1 || (!wcycle && zero && l >= tail_level(h, true))) {
         if (nr.slot >= 0) {
             // only a single-grid FP64 problem (N = 4) gets here with a norm
             HIPCHK(launch_residual_norm(h->d, level_n(h, l), h->batch,
@@ -409,6 +413,17 @@ int cycle(mg_ctx* h, Hier& H, int l, const void* u_in, const void* b, void* out,
     s.fin_ps = s.fin_pm = nullptr;
     s.fin_count = 0;
     s.fin_dev = s.fin_host = nullptr;
+    if (wcycle) {
+        // gamma = 2: the coarse problem twice, the second visit starting from
+        // the first's result; no post-smoothing: out = tmp + pf P e_{l+1}
+        rc = cycle(h, H, l + 1, nullptr, H.b[l + 1], H.e[l + 1], H.t[l + 1], NormReq(), st);
+        if (rc) return rc;
+        rc = cycle(h, H, l + 1, H.e[l + 1], H.b[l + 1], H.e[l + 1], H.t[l + 1], NormReq(), st);
+        if (rc) return rc;
+        return run_timed(h, MG_TIME_PROLONG, l, st, [&] {
+            return launch_prolong_to(H.p, h->d, s.n, h->batch, H.e[l + 1], tmp, out, pf, st);
+        });
+    }
     rc = cycle(h, H, l + 1, nullptr, H.b[l + 1], H.e[l + 1], H.t[l + 1], NormReq(), st);
     if (rc) return rc;
     s.u = tmp;
@@ -544,6 +559,11 @@ int mg_set_option(mg_handle_t h, int key, double value) {
         case MG_OPT_INNER_CYCLES:
             if (v < 0 || v > 16) return fail(MG_EINVAL, "inner cycles must be 0..16");
             h->inner = v;
+            return MG_OK;
+        case MG_OPT_CYCLE:
+            if (v != MG_CYCLE_V11 && v != MG_CYCLE_W10)
+                return fail(MG_EINVAL, "cycle must be MG_CYCLE_V11 or MG_CYCLE_W10");
+            h->cycle_kind = v;
             return MG_OK;
         default:
             return fail(MG_EINVAL, "unknown option");
@@ -996,6 +1016,8 @@ extern "C" int mg_vcycle_adjoint(mg_handle_t h, const double* b, const double* u
     if (check_handle(h)) return MG_EINVAL;
     if (!b || !u_in || !ubar_out || !ubar_in || !bbar_acc || !cbar_acc)
         return fail(MG_EINVAL, "null pointer");
+    if (h->cycle_kind != MG_CYCLE_V11)
+        return fail(MG_EINVAL, "the adjoint is defined for the V(1,1) cycle only");
     hipStream_t st = (hipStream_t)stream;
     int rc = alloc_adj(h);
     if (rc) return rc;

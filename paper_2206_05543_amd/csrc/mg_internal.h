@@ -52,6 +52,9 @@ hipError_t launch_restrict(Prec p, const Sweep& s, hipStream_t st);
 // u (fine, n interior) += pf * P ec (coarse, n/2 interior)
 hipError_t launch_prolong(Prec p, int d, int n, int batch, const void* ec,
                           void* u, double pf, hipStream_t st);
+// out = in + pf * P ec (in may equal out)
+hipError_t launch_prolong_to(Prec p, int d, int n, int batch, const void* ec, const void* in,
+                             void* out, double pf, hipStream_t st);
 // Coarse tail: from a level with nt interior nodes down to 3 and back up, in
 // one workgroup, for every batch entry.  b and e hold the tail's top level.
 struct Tail {

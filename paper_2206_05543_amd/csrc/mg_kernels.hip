@@ -1118,16 +1118,18 @@ k_restrict2d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ b
 }
 
 // ---------------------------------------------------------------------------
-// Linear interpolation + correction: u += pf * P ec.  One fine node per
-// thread; the coarse values (1/2^d of the traffic) come through L2.
+// Linear interpolation + correction: out = in + pf * P ec (in may be out).
+// One fine node per thread; the coarse values (1/2^d of the traffic) come
+// through L2.
 // ---------------------------------------------------------------------------
 template <typename S, typename C>
 __global__ void __launch_bounds__(256)
-k_prolong2d(const S* __restrict__ ec, S* __restrict__ u, int n, int nc, C pf) {
+k_prolong2d(const S* __restrict__ ec, const S* in, S* out, int n, int nc, C pf) {
     const long area = (long)n * n;
     const long idx = (long)blockIdx.x * 256 + threadIdx.x;
     if (idx >= area) return;
-    u += (long)blockIdx.y * area;
+    in += (long)blockIdx.y * area;
+    out += (long)blockIdx.y * area;
     ec += (long)blockIdx.y * nc * nc;
     const int i = idx % n, j = idx / n;
     int ia, ib, ja, jb;
@@ -1143,16 +1145,17 @@ k_prolong2d(const S* __restrict__ ec, S* __restrict__ u, int n, int nc, C pf) {
         s += e(ia, jb);
         if (ni == 2) s += e(ib, jb);
     }
-    st_out(&u[idx], static_cast<S>(cvt<C>(u[idx]) + pf * (wi * wj) * s), area >= kNtMinPts);
+    st_out(&out[idx], static_cast<S>(cvt<C>(in[idx]) + pf * (wi * wj) * s), area >= kNtMinPts);
 }
 
 template <typename S, typename C>
 __global__ void __launch_bounds__(256)
-k_prolong3d(const S* __restrict__ ec, S* __restrict__ u, int n, int nc, C pf) {
+k_prolong3d(const S* __restrict__ ec, const S* in, S* out, int n, int nc, C pf) {
     const long vol = (long)n * n * n;
     const long idx = (long)blockIdx.x * 256 + threadIdx.x;
     if (idx >= vol) return;
-    u += (long)blockIdx.y * vol;
+    in += (long)blockIdx.y * vol;
+    out += (long)blockIdx.y * vol;
     ec += (long)blockIdx.y * nc * nc * nc;
     const int i = idx % n, j = (idx / n) % n, k = idx / ((long)n * n);
     int xi[2], yj[2], zk[2];
@@ -1167,7 +1170,7 @@ k_prolong3d(const S* __restrict__ ec, S* __restrict__ u, int n, int nc, C pf) {
             for (int a = 0; a < ni; ++a)
                 if (xi[a] >= 0 && yj[bq] >= 0 && zk[c] >= 0)
                     s += cvt<C>(ec[((long)zk[c] * nc + yj[bq]) * nc + xi[a]]);
-    st_out(&u[idx], static_cast<S>(cvt<C>(u[idx]) + pf * w * s), vol >= kNtMinPts);
+    st_out(&out[idx], static_cast<S>(cvt<C>(in[idx]) + pf * w * s), vol >= kNtMinPts);
 }
 
 // ---------------------------------------------------------------------------
@@ -1853,17 +1856,19 @@ hipError_t restrict_impl(const Sweep& s, hipStream_t st) {
 }
 
 template <typename S, typename C>
-hipError_t prolong_impl(int d, int n, int batch, const void* ec, void* u, double pf,
-                        hipStream_t st) {
+hipError_t prolong_impl(int d, int n, int batch, const void* ec, const void* in, void* out,
+                        double pf, hipStream_t st) {
     const int nc = (n + 1) / 2 - 1;
     const long pts = d == 3 ? (long)n * n * n : (long)n * n;
     dim3 grid(cdiv(pts, 256), batch);
     if (d == 3)
         hipLaunchKernelGGL((k_prolong3d<S, C>), grid, dim3(256), 0, st,
-                           static_cast<const S*>(ec), static_cast<S*>(u), n, nc, C(pf));
+                           static_cast<const S*>(ec), static_cast<const S*>(in),
+                           static_cast<S*>(out), n, nc, C(pf));
     else
         hipLaunchKernelGGL((k_prolong2d<S, C>), grid, dim3(256), 0, st,
-                           static_cast<const S*>(ec), static_cast<S*>(u), n, nc, C(pf));
+                           static_cast<const S*>(ec), static_cast<const S*>(in),
+                           static_cast<S*>(out), n, nc, C(pf));
     return hipGetLastError();
 }
 
@@ -1967,10 +1972,15 @@ hipError_t launch_restrict(Prec p, const Sweep& s, hipStream_t st) {
 
 hipError_t launch_prolong(Prec p, int d, int n, int batch, const void* ec, void* u,
                           double pf, hipStream_t st) {
+    return launch_prolong_to(p, d, n, batch, ec, u, u, pf, st);
+}
+
+hipError_t launch_prolong_to(Prec p, int d, int n, int batch, const void* ec, const void* in,
+                             void* out, double pf, hipStream_t st) {
     switch (p) {
-        case P64: return prolong_impl<double, double>(d, n, batch, ec, u, pf, st);
-        case P32: return prolong_impl<float, float>(d, n, batch, ec, u, pf, st);
-        default: return prolong_impl<_Float16, float>(d, n, batch, ec, u, pf, st);
+        case P64: return prolong_impl<double, double>(d, n, batch, ec, in, out, pf, st);
+        case P32: return prolong_impl<float, float>(d, n, batch, ec, in, out, pf, st);
+        default: return prolong_impl<_Float16, float>(d, n, batch, ec, in, out, pf, st);
     }
 }
 

@@ -45,7 +45,7 @@ def test_two_grid_spectral_radius_equals_dirichlet_lfa(d, N, c, nu1, nu2):
     assert abs(rho - lfa.dirichlet_two_grid_factor(d, c, nu1 + nu2, N)) < 1e-11
 
 
-def _loop_cycle_maps(d, N, c, gamma=1):
+def _loop_cycle_maps(d, N, c, gamma=1, nu1=1, nu2=1):
     n = (N - 1) ** d
     E = np.zeros((n, n))
     B = np.zeros((n, n))
@@ -53,22 +53,33 @@ def _loop_cycle_maps(d, N, c, gamma=1):
     for i in range(n):
         e = np.zeros(n)
         e[i] = 1.0
-        E[:, i] = O.cycle(d, N, c, e.reshape(z.shape), z, 1, 1, gamma).ravel()
-        B[:, i] = O.cycle(d, N, c, z, e.reshape(z.shape), 1, 1, gamma).ravel()
+        E[:, i] = O.cycle(d, N, c, e.reshape(z.shape), z, nu1, nu2, gamma).ravel()
+        B[:, i] = O.cycle(d, N, c, z, e.reshape(z.shape), nu1, nu2, gamma).ravel()
     return E, B
 
 
-@pytest.mark.parametrize("d,N,c,gamma", [(2, 16, C9, 1), (2, 32, C9, 1), (2, 16, CJ2, 2),
-                                         (3, 8, C7, 1), (3, 8, C7, 2)])
-def test_cycle_operator_matches_matrix_recursion(d, N, c, gamma):
-    E, B = _loop_cycle_maps(d, N, c, gamma)
-    Ed, Bd = dense.vcycle_maps(d, N, c, 1, 1, gamma)
+@pytest.mark.parametrize("d,N,c,gamma,nu1,nu2", [
+    (2, 16, C9, 1, 1, 1), (2, 32, C9, 1, 1, 1), (2, 16, CJ2, 2, 1, 1), (3, 8, C7, 1, 1, 1),
+    (3, 8, C7, 2, 1, 1), (2, 16, C9, 2, 1, 0), (2, 32, CM5, 2, 1, 0), (3, 8, C7, 2, 1, 0)])
+def test_cycle_operator_matches_matrix_recursion(d, N, c, gamma, nu1, nu2):
+    E, B = _loop_cycle_maps(d, N, c, gamma, nu1, nu2)
+    Ed, Bd = dense.vcycle_maps(d, N, c, nu1, nu2, gamma)
     assert np.max(np.abs(E - Ed)) < 1e-12
     assert np.max(np.abs(B - Bd)) < 1e-12 * np.max(np.abs(Bd))
-    # the cycle's approximate inverse is symmetric (nu1 = nu2, symmetric M)
-    assert np.max(np.abs(B - B.T)) < 1e-12 * np.max(np.abs(B))
+    if nu1 == nu2:
+        # the cycle's approximate inverse is symmetric (nu1 = nu2, symmetric M)
+        assert np.max(np.abs(B - B.T)) < 1e-12 * np.max(np.abs(B))
     # consistency: E = I - B A
     assert np.max(np.abs(E - (np.eye(len(E)) - B @ dense.A(d, N)))) < 1e-10
+
+
+def test_w10_two_level_reduces_to_presmoothed_two_grid():
+    # with one coarse level below (N = 8: the 3^d grid is solved exactly) the
+    # W(1,0) error operator is the two-grid operator with one pre-smoothing
+    # step, whatever gamma, since repeating an exact solve changes nothing
+    for d, c in [(2, C9), (3, C7)]:
+        E, _ = _loop_cycle_maps(d, 8, c, 2, 1, 0)
+        assert np.max(np.abs(E - dense.two_grid(d, 8, c, 1, 0))) < 1e-12
 
 
 def test_vcycle_contraction_rates():
