@@ -16,6 +16,14 @@ JACOBI_2D = (0.2, 0.0, 0.0)
 JACOBI_3D = (1.0 / 7.0, 0.0)
 M5 = (12.0 / 41.0, 2.0 / 41.0, 0.0)
 VANKA = (0.28, 0.04, 0.01)
+TW5 = (17.0 / 61.0, 3.0 / 61.0, 0.0)
+
+# The smoothers compared in Section 4 (2D: Jacobi, the 5-point stencils of
+# Tang-Wan and of Section 3.1, additive Vanka, M9; 3D: Jacobi, M7).
+SMOOTHERS = {
+    2: {"J": JACOBI_2D, "TW5": TW5, "M5": M5, "Vanka": VANKA, "M9": M9},
+    3: {"J": JACOBI_3D, "M7": M7},
+}
 
 
 def paper_coeffs(d):

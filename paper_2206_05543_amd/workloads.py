@@ -68,6 +68,42 @@ def random_errors(d, N, seed, batch):
     return {"b": np.zeros((N - 1,) * d), "e0": e0}
 
 
+def example_problem(example, N, seed=0):
+    """The analytic problems of Section 4 (Examples 1-3), g = 0: b = f at the
+    interior nodes, the exact solution u there, and the initial guess drawn
+    uniformly from (0, 1) as in the paper's experiments.
+
+    Example 1 (2D): u = (x^2 - x^4)(y^4 - y^2).
+    Example 2 (2D): u = x ln(x) y ln(y); f is singular as x or y -> 0.
+    Example 3 (3D): u = sin(pi x) sin(pi y) sin(pi z), f = 3 pi^2 u.
+    Arrays are in numpy order (y, x) / (z, y, x).
+    """
+    x = grid_coords(N)
+    if example == 1:
+        X = x[None, :]
+        Y = x[:, None]
+        u = (X ** 2 - X ** 4) * (Y ** 4 - Y ** 2)
+        f = (2.0 * (1.0 - 6.0 * X ** 2) * (Y ** 2 - Y ** 4)
+             + 2.0 * (1.0 - 6.0 * Y ** 2) * (X ** 2 - X ** 4))
+        d = 2
+    elif example == 2:
+        X = x[None, :]
+        Y = x[:, None]
+        u = X * np.log(X) * Y * np.log(Y)
+        f = -X * np.log(X) / Y - Y * np.log(Y) / X
+        d = 2
+    elif example == 3:
+        s = np.sin(np.pi * x)
+        u = s[:, None, None] * s[None, :, None] * s[None, None, :]
+        f = 3.0 * np.pi ** 2 * u
+        d = 3
+    else:
+        raise ValueError("example must be 1, 2 or 3")
+    rng = np.random.default_rng(seed)
+    u0 = rng.uniform(0.0, 1.0, size=(N - 1,) * d)
+    return {"d": d, "b": np.ascontiguousarray(f), "u": np.ascontiguousarray(u), "u0": u0}
+
+
 # The five workloads: (dimension, N, seed, modes, max index, noise, batch).
 WORKLOADS = {
     "poisson2d_n64": dict(d=2, N=64, seed=0, n_modes=8, kmax=16),
