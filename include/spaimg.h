@@ -75,10 +75,10 @@ extern "C" {
 /* cycles for MG_OPT_CYCLE (Section 4 tests both) */
 #define MG_CYCLE_V11 0      /* V(1,1): one pre- and one post-smoothing step   */
 #define MG_CYCLE_W10 1      /* W(1,0): one pre-smoothing step, two coarse-grid
-                               visits per level, no post-smoothing; the
-                               coarse levels run one level per launch and
-                               only the 3^d grid is solved in the tail.  Not
-                               available for mg_vcycle_adjoint.               */
+                               visits per level, no post-smoothing; both
+                               visits of a level at or below the tail size
+                               run in one tail launch.  Not available for
+                               mg_vcycle_adjoint.                             */
 
 /* precisions for MG_OPT_PRECISION */
 #define MG_PREC_FP64 0      /* FP64 V-cycles                                  */

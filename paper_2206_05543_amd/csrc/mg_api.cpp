@@ -329,8 +329,10 @@ Sweep make_sweep(const mg_ctx* h, const Hier& H, int l) {
     return s;
 }
 
-int run_tail(mg_ctx* h, Hier& H, int l, const void* b, void* e, hipStream_t st) {
+int run_tail(mg_ctx* h, Hier& H, int l, const void* b, void* e, hipStream_t st,
+             int wvisits = 0) {
     Tail t;
+    t.wvisits = wvisits;
     t.d = h->d;
     t.nt = level_n(h, l);
     t.batch = h->batch;
@@ -360,9 +362,8 @@ int cycle(mg_ctx* h, Hier& H, int l, const void* u_in, const void* b, void* out,
     const bool zero = u_in == nullptr;
     const bool wcycle = h->cycle_kind == MG_CYCLE_W10;
     int rc, nparts = 0;
-    // the LDS tail runs V(1,1) on its levels: W cycles use it only for the
-    // exact solve on the coarsest grid
-    if (l == h->L - 1 || (!wcycle && zero && l >= tail_level(h, true))) {
+    // zero-guess cycles at or below the tail size run in the LDS tail
+    if (l == h->L - 1 || (zero && l >= tail_level(h, true))) {
         if (nr.slot >= 0) {
             // only a single-grid FP64 problem (N = 4) gets here with a norm
             HIPCHK(launch_residual_norm(h->d, level_n(h, l), h->batch,
@@ -374,7 +375,7 @@ int cycle(mg_ctx* h, Hier& H, int l, const void* u_in, const void* b, void* out,
                                   sizeof(double), hipMemcpyDeviceToHost, st));
             if (nr.ready) HIPCHK(hipEventRecord(nr.ready, st));
         }
-        return run_tail(h, H, l, b, out, st);
+        return run_tail(h, H, l, b, out, st, wcycle ? 1 : 0);
     }
     Sweep s = make_sweep(h, H, l);
     double sA, sW, pf;
@@ -415,10 +416,16 @@ int cycle(mg_ctx* h, Hier& H, int l, const void* u_in, const void* b, void* out,
     s.fin_dev = s.fin_host = nullptr;
     if (wcycle) {
         // gamma = 2: the coarse problem twice, the second visit starting from
-        // the first's result; no post-smoothing: out = tmp + pf P e_{l+1}
-        rc = cycle(h, H, l + 1, nullptr, H.b[l + 1], H.e[l + 1], H.t[l + 1], NormReq(), st);
-        if (rc) return rc;
-        rc = cycle(h, H, l + 1, H.e[l + 1], H.b[l + 1], H.e[l + 1], H.t[l + 1], NormReq(), st);
+        // the first's result (both visits in one tail launch at or below the
+        // tail size); no post-smoothing: out = tmp + pf P e_{l+1}
+        if (l + 1 == h->L - 1 || l + 1 >= tail_level(h, true)) {
+            rc = run_tail(h, H, l + 1, H.b[l + 1], H.e[l + 1], st, 2);
+        } else {
+            rc = cycle(h, H, l + 1, nullptr, H.b[l + 1], H.e[l + 1], H.t[l + 1], NormReq(), st);
+            if (rc) return rc;
+            rc = cycle(h, H, l + 1, H.e[l + 1], H.b[l + 1], H.e[l + 1], H.t[l + 1], NormReq(),
+                       st);
+        }
         if (rc) return rc;
         return run_timed(h, MG_TIME_PROLONG, l, st, [&] {
             return launch_prolong_to(H.p, h->d, s.n, h->batch, H.e[l + 1], tmp, out, pf, st);

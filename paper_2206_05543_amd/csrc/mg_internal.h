@@ -56,7 +56,8 @@ hipError_t launch_prolong(Prec p, int d, int n, int batch, const void* ec,
 hipError_t launch_prolong_to(Prec p, int d, int n, int batch, const void* ec, const void* in,
                              void* out, double pf, hipStream_t st);
 // Coarse tail: from a level with nt interior nodes down to 3 and back up, in
-// one workgroup, for every batch entry.  b and e hold the tail's top level.
+// one workgroup, for every batch entry.  b and e hold the tail's top level;
+// e is written only (every visit sequence starts from a zero guess).
 struct Tail {
     int d = 2, nt = 0, batch = 1;
     const void* b = nullptr;
@@ -66,6 +67,8 @@ struct Tail {
     double sigma_top = 1.0;        // storage scale of the top tail level
     bool scaled = false;           // scaled hierarchy (sigma_l = 1/h_l^2)
     int N_top = 0;                 // intervals of the top tail level
+    int wvisits = 0;               // 0: V(1,1); 1 or 2: W(1,0) visits of the
+                                   // top level, the first from a zero guess
 };
 hipError_t launch_tail(Prec p, const Tail& t, hipStream_t st);
 size_t tail_lds_bytes(Prec p, int d, int nt);

@@ -1176,8 +1176,9 @@ k_prolong3d(const S* __restrict__ ec, const S* in, S* out, int n, int nc, C pf) 
 // ---------------------------------------------------------------------------
 // Coarse tail: every level from nt interior nodes per direction down to 3,
 // the exact solve on the 3^d grid and back up, in one workgroup of 1024
-// threads with all level arrays in LDS.  Coarse levels start from a zero
-// guess (pre-smoothing is e = sW K b).  Every LDS array carries a ring of
+// threads with all level arrays in LDS, as a V(1,1) cycle or (wvisits > 0)
+// W(1,0) visits of the top level.  Each level's first visit starts from a
+// zero guess (pre-smoothing is e = sW K b).  Every LDS array carries a ring of
 // zeros, so stencils need no bounds checks; threads map to nodes through
 // power-of-two boxes (2D: 64 x 16 per pass, 3D: 16 x 16 x 4), so no
 // divisions are needed.
@@ -1224,10 +1225,43 @@ __device__ __forceinline__ void tail_for(int n, F&& f) {
     }
 }
 
+// calls f(i, j, k) for every node of a small n-grid owned by this lane of
+// wave 0 (2D: 8 x 8 lane box, 3D: 4 x 4 x 4)
+template <int D, typename F>
+__device__ __forceinline__ void tail_for_wave(int n, F&& f) {
+    const int lane = threadIdx.x;
+    if (D == 2) {
+        for (int j = lane >> 3; j < n; j += 8)
+            for (int i = lane & 7; i < n; i += 8) f(i, j, 0);
+    } else {
+        for (int k = lane >> 4; k < n; k += 4)
+            for (int j = (lane >> 2) & 3; j < n; j += 4)
+                for (int i = lane & 3; i < n; i += 4) f(i, j, k);
+    }
+}
+
+// orders the LDS accesses of one wave: its lanes exchange data through LDS,
+// and the LDS executes one wave's operations in issue order
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// grids of at most this many interior nodes per direction are processed by
+// wave 0 alone, with wave-level ordering instead of workgroup barriers
+template <int D>
+constexpr int kTailWaveN = D == 2 ? 15 : 7;
+
+// byte offset of the FP64 coarsest-grid inverse behind the level arrays
+__host__ __device__ inline size_t tail_ginv_offset(size_t level_bytes) {
+    return (level_bytes + 7) & ~size_t(7);
+}
+
 template <typename S, typename C, int D>
 __global__ void __launch_bounds__(1024)
 k_tail(const S* __restrict__ bt, S* __restrict__ et, int nt, C c0, C c1, C c2,
-       const double* __restrict__ ginv, int scaled, int Ntop) {
+       const double* __restrict__ ginv, int scaled, int Ntop, int wvisits) {
     extern __shared__ unsigned char smem_raw[];
     C* sm = reinterpret_cast<C*>(smem_raw);
     const int t = threadIdx.x;
@@ -1236,6 +1270,9 @@ k_tail(const S* __restrict__ bt, S* __restrict__ et, int nt, C c0, C c1, C c2,
     long tot = 0;
     for (int l = 0, n = nt; l < L; ++l, n = (n + 1) / 2 - 1) tot += 3 * tail_padded(D, n);
     for (long q = t; q < tot; q += 1024) sm[q] = C(0);
+    constexpr int m3 = D == 2 ? 9 : 27;
+    double* gl = reinterpret_cast<double*>(smem_raw + tail_ginv_offset(tot * sizeof(C)));
+    for (int q = t; q < m3 * m3; q += 1024) gl[q] = ginv[q];
     auto base = [&](int l) -> C* {
         C* p = sm;
         for (int k = 0, n = nt; k < l; ++k, n = (n + 1) / 2 - 1) p += 3 * tail_padded(D, n);
@@ -1286,25 +1323,71 @@ k_tail(const S* __restrict__ bt, S* __restrict__ et, int nt, C c0, C c1, C c2,
     auto pidx = [&](int i, int j, int k, int P) -> long {
         return D == 3 ? ((long)(k + 1) * P + j + 1) * P + i + 1 : (long)(j + 1) * P + i + 1;
     };
-    for (int l = 0; l + 1 < L; ++l) {
-        const int n = nl(l), P = n + 2, nc = nl(l + 1), Pc = nc + 2;
+    // runs f over the nodes of an n-grid and orders the phase: all threads
+    // and a workgroup barrier on large grids, wave 0 and a wave-level fence
+    // on small ones; a large-grid phase after small-grid ones first waits
+    // for wave 0 at a barrier.  Every condition here is uniform.
+    bool after_small = false;
+    auto nodes = [&](int n, auto&& f) {
+        if (n <= kTailWaveN<D>) {
+            if (t < 64) {
+                tail_for_wave<D>(n, f);
+                wave_sync();
+            }
+            after_small = true;
+        } else {
+            if (after_small) {
+                __syncthreads();
+                after_small = false;
+            }
+            tail_for<D>(n, f);
+            __syncthreads();
+        }
+    };
+    // ---- phases (the grid a phase iterates over sets its ordering)
+    // zero-guess pre-smoothing: E = sW K B
+    auto smooth_zero = [&](int l) {
+        const int n = nl(l), P = n + 2;
         C* E = base(l);
-        C* B = E + tail_padded(D, n);
-        C* R = B + tail_padded(D, n);
-        C* Bc = base(l + 1) + tail_padded(D, nc);
+        const C* B = E + tail_padded(D, n);
         C sA, sW;
         level_consts(l, &sA, &sW);
-        tail_for<D>(n, [&](int i, int j, int k) {
+        nodes(n, [&](int i, int j, int k) {
             const long q = pidx(i, j, k, P);
             E[q] = sW * spai(B, q, P);
         });
-        __syncthreads();
-        tail_for<D>(n, [&](int i, int j, int k) {
+    };
+    // R = B - sA A E
+    auto residual = [&](int l) {
+        const int n = nl(l), P = n + 2;
+        const C* E = base(l);
+        const C* B = E + tail_padded(D, n);
+        C* R = const_cast<C*>(B) + tail_padded(D, n);
+        C sA, sW;
+        level_consts(l, &sA, &sW);
+        nodes(n, [&](int i, int j, int k) {
             const long q = pidx(i, j, k, P);
             R[q] = B[q] - sA * lap(E, q, P);
         });
-        __syncthreads();
-        tail_for<D>(nc, [&](int i, int j, int k) {
+    };
+    // E += sW K R (after residual)
+    auto update = [&](int l) {
+        const int n = nl(l), P = n + 2;
+        C* E = base(l);
+        const C* R = E + 2 * tail_padded(D, n);
+        C sA, sW;
+        level_consts(l, &sA, &sW);
+        nodes(n, [&](int i, int j, int k) {
+            const long q = pidx(i, j, k, P);
+            E[q] += sW * spai(R, q, P);
+        });
+    };
+    // B_{l+1} = full weighting of R_l
+    auto restrict_r = [&](int l) {
+        const int n = nl(l), P = n + 2, nc = nl(l + 1), Pc = nc + 2;
+        const C* R = base(l) + 2 * tail_padded(D, n);
+        C* Bc = base(l + 1) + tail_padded(D, nc);
+        nodes(nc, [&](int i, int j, int k) {
             const long q = pidx(2 * i + 1, 2 * j + 1, D == 3 ? 2 * k + 1 : 0, P);
             C s;
             if (D == 2) {
@@ -1324,36 +1407,35 @@ k_tail(const S* __restrict__ bt, S* __restrict__ et, int nt, C c0, C c1, C c2,
             }
             Bc[pidx(i, j, k, Pc)] = s;
         });
-        __syncthreads();
-    }
-    {
+    };
+    // exact solve on the 3^d grid (level L-1) with the FP64 inverse
+    auto exact = [&]() {
         const int m = D == 2 ? 9 : 27, P = 5;
         C* E = base(L - 1);
-        C* B = E + tail_padded(D, 3);
-        if (t < m) {
-            const int i = t % 3, j = (t / 3) % 3, k = t / 9;
-            double s = 0.0;
-            for (int q = 0; q < m; ++q) {
-                const int qi = q % 3, qj = (q / 3) % 3, qk = q / 9;
-                s += ginv[t * m + q] * (double)B[pidx(qi, qj, qk, P)];
+        const C* B = E + tail_padded(D, 3);
+        if (t < 64) {
+            if (t < m) {
+                const int i = t % 3, j = (t / 3) % 3, k = t / 9;
+                double s = 0.0;
+                for (int q = 0; q < m; ++q) {
+                    const int qi = q % 3, qj = (q / 3) % 3, qk = q / 9;
+                    s += gl[t * m + q] * (double)B[pidx(qi, qj, qk, P)];
+                }
+                E[pidx(i, j, k, P)] = C(s);
             }
-            E[pidx(i, j, k, P)] = C(s);
+            wave_sync();
         }
-        __syncthreads();
-    }
-    for (int l = L - 2; l >= 0; --l) {
+        after_small = true;
+    };
+    // E_l += pf P E_{l+1} (linear interpolation: fine node i, at grid
+    // coordinate i+1, takes the coarse node (i+1)/2 if even, the mean of
+    // (i/2, i/2+1) if odd; in padded coarse coordinates the coarse node G
+    // sits at index G, and the ring supplies the zero boundary values)
+    auto correct = [&](int l) {
         const int n = nl(l), P = n + 2, nc = nl(l + 1), Pc = nc + 2;
         C* E = base(l);
-        C* B = E + tail_padded(D, n);
-        C* R = B + tail_padded(D, n);
         const C* Ec = base(l + 1);
-        C sA, sW;
-        level_consts(l, &sA, &sW);
-        // linear interpolation: fine node i (grid coordinate i+1) takes the
-        // coarse node (i+1)/2 if even, the mean of (i/2, i/2+1) if odd; in
-        // padded coarse coordinates the coarse node G sits at index G, and
-        // the ring supplies the zero boundary values
-        tail_for<D>(n, [&](int i, int j, int k) {
+        nodes(n, [&](int i, int j, int k) {
             const int gi = i + 1, gj = j + 1, gk = k + 1;
             const int ia = gi >> 1, ib = (gi + 1) >> 1;
             const int ja = gj >> 1, jb = (gj + 1) >> 1;
@@ -1371,18 +1453,69 @@ k_tail(const S* __restrict__ bt, S* __restrict__ et, int nt, C c0, C c1, C c2,
             }
             E[pidx(i, j, k, P)] += pf * v;
         });
-        __syncthreads();
-        tail_for<D>(n, [&](int i, int j, int k) {
-            const long q = pidx(i, j, k, P);
-            R[q] = B[q] - sA * lap(E, q, P);
-        });
-        __syncthreads();
-        tail_for<D>(n, [&](int i, int j, int k) {
-            const long q = pidx(i, j, k, P);
-            E[q] += sW * spai(R, q, P);
-        });
-        __syncthreads();
+    };
+
+    if (wvisits == 0) {
+        // V(1,1) from a zero guess
+        for (int l = 0; l + 1 < L; ++l) {
+            smooth_zero(l);
+            residual(l);
+            restrict_r(l);
+        }
+        exact();
+        for (int l = L - 2; l >= 0; --l) {
+            correct(l);
+            residual(l);
+            update(l);
+        }
+    } else {
+        // W(1,0): each visit of level l < L-1 pre-smooths (from zero on a
+        // level's first visit, from its current E on the second), restricts,
+        // visits level l+1 twice and adds the interpolated correction.  The
+        // recursion runs as a loop over a level index with one pending-visit
+        // bit per level; all control is uniform across the workgroup.  A
+        // second visit of the 3^d grid repeats an exact solve of unchanged
+        // data and is skipped.  The top level is visited wvisits times.
+        unsigned pending = wvisits > 1 ? 1u : 0u;
+        int l = 0;
+        bool zero = true;
+        for (;;) {
+            while (l + 1 < L) {
+                if (zero) {
+                    smooth_zero(l);
+                } else {
+                    residual(l);
+                    update(l);
+                }
+                residual(l);
+                restrict_r(l);
+                ++l;
+                zero = true;
+                pending |= 1u << l;
+            }
+            exact();
+            // a visit of level l has finished: revisit it, or close the
+            // parent's visit with the correction and go up
+            bool done = false;
+            for (;;) {
+                const unsigned bit = 1u << l;
+                if ((pending & bit) && l + 1 < L) {
+                    pending &= ~bit;
+                    zero = false;
+                    break;
+                }
+                pending &= ~bit;
+                if (l == 0) {
+                    done = true;
+                    break;
+                }
+                correct(l - 1);
+                --l;
+            }
+            if (done) break;
+        }
     }
+    __syncthreads();
     {
         const long off = (long)blockIdx.x * (D == 3 ? (long)nt * nt * nt : (long)nt * nt);
         const C* E = base(0);
@@ -1884,7 +2017,7 @@ hipError_t tail_impl_d(const Tail& t, size_t lds, hipStream_t st) {
     }
     hipLaunchKernelGGL((k_tail<S, C, D>), dim3(t.batch), dim3(1024), lds, st,
                        static_cast<const S*>(t.b), static_cast<S*>(t.e), t.nt, C(t.c[0]),
-                       C(t.c[1]), C(t.c[2]), t.ginv, t.scaled ? 1 : 0, t.N_top);
+                       C(t.c[1]), C(t.c[2]), t.ginv, t.scaled ? 1 : 0, t.N_top, t.wvisits);
     return hipGetLastError();
 }
 
@@ -1950,7 +2083,8 @@ size_t tail_lds_bytes(Prec p, int d, int nt) {
         tot += 3 * tail_padded(d, n);
         if (n <= 3) break;
     }
-    return (size_t)tot * (p == P64 ? 8 : 4);
+    const int m = d == 2 ? 9 : 27;
+    return tail_ginv_offset((size_t)tot * (p == P64 ? 8 : 4)) + (size_t)m * m * 8;
 }
 
 hipError_t launch_smooth(Prec p, bool zg, bool norm, const Sweep& s, hipStream_t st,

@@ -42,6 +42,29 @@ def test_wcycle_parity(d, N, batch):
         assert np.max(np.abs(got[s] - want)) <= 1e-12 * scale
 
 
+@pytest.mark.parametrize("d,N,tail_N", [(2, 256, 4), (2, 256, 8), (2, 256, 16), (2, 256, 32),
+                                        (2, 256, 64), (3, 64, 4), (3, 64, 8), (3, 64, 16)])
+def test_wcycle_tail_depths(d, N, tail_N):
+    # the coarse levels' W(1,0) visits run in the single-workgroup tail from
+    # tail_N down; every split between host levels and tail levels gives the
+    # oracle's cycle
+    need_gpu()
+    rng = np.random.default_rng(N + tail_N)
+    shp = (2,) + (N - 1,) * d
+    u0 = rng.uniform(-1, 1, shp)
+    b = rng.standard_normal(shp) * 10
+    say("wcycle-tail", d, N, tail_N)
+    with make_mg(N, d, _c(d), batch=2, cycle="W10", tail_N=tail_N) as mg:
+        u = dev(u0)
+        mg.vcycle(dev(b), u)
+        torch.cuda.synchronize()
+        got = host(u)
+    for s in range(2):
+        want = O.cycle(d, N, _c(d), u0[s], b[s], nu1=1, nu2=0, gamma=2)
+        scale = max(np.abs(want).max(), np.abs(u0[s]).max())
+        assert np.max(np.abs(got[s] - want)) <= 1e-12 * scale
+
+
 @pytest.mark.parametrize("d,N,coeffs", [(2, 64, M9), (2, 64, JACOBI_2D), (2, 64, M5),
                                         (2, 256, M9), (3, 32, M7), (3, 64, M7)],
                          ids=["2d64-M9", "2d64-J", "2d64-M5", "2d256-M9", "3d32-M7", "3d64-M7"])
