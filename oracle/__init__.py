@@ -4,7 +4,8 @@ TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
 CPU-baseline leg of ``bench.py`` may import this package.  It shares no code
 with the GPU library: ``mg_oracle.c`` holds plain FP64 loops of the method
 (He, Liu and Wang, arXiv 2206.05543; Sections 1-4), ``lfa.py`` the local
-Fourier analysis of Sections 2-4 and ``dense.py`` explicit matrices of every
+Fourier analysis of Sections 2-4, ``search.py`` the minimax search for
+stencil coefficients of Section 3 and ``dense.py`` explicit matrices of every
 operator on tiny grids.
 
 Arrays follow the paper's grid: N intervals per direction, h = 1/N, the

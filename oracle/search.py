@@ -1,0 +1,91 @@
+"""Minimax search for SPAI stencil coefficients (Section 3 of He, Liu and
+Wang, arXiv 2206.05543).
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+Section 3 constructs its smoothers by minimising the optimal smoothing
+factor over a symmetric stencil family: for a fixed stencil shape the best
+damping gives mu_opt = (l1 - l0)/(l1 + l0), with l0, l1 the smallest and
+largest values of the product of the symbols of A_h and M over the high
+frequencies (Section 2, eqs. (mu_opt) and (omega_opt)), so only the ratio
+l1/l0 has to be minimised, and the overall scale of M is free (it moves
+into omega).  Theorems 3.1 and 3.2 solve this min-max problem in closed form
+for the 9-point family in 2D and the 7-point family in 3D; this module
+solves it numerically on the sampled symbol, which also covers families the
+paper does not solve (the 19- and 27-point stencils in 3D).
+
+Families (stencil weights relative to the centre, scale-free):
+  2D "5pt":  c0 I + c1 (face neighbours)
+  2D "9pt":  + c2 (diagonal neighbours)             -- the Upsilon family
+  3D "7pt":  c0 I + c1 (face neighbours)             -- the T family
+  3D "19pt": + c2 (edge neighbours, 12 of them)
+  3D "27pt": + c3 (corner neighbours, 8 of them)
+The symbol of M over cosines x_k = cos(theta_k) is
+  c0 + 2 c1 sum_k x_k + 4 c2 sum_{k<l} x_k x_l [+ 8 c3 x_1 x_2 x_3].
+
+Pins: the 5-, 9- and 7-point optima against the values the paper prints;
+the 19- and 27-point optima have no printed values and are pinned only by
+properties (the symbol against a brute-force Fourier sum, nesting of the
+families, independence of the sampling): their values are otherwise
+parity unpinned.
+"""
+import itertools
+
+import numpy as np
+from scipy.optimize import minimize
+
+from .lfa import high_cos_grid
+
+FAMILIES = {(2, "5pt"): 1, (2, "9pt"): 2, (3, "7pt"): 1, (3, "19pt"): 2, (3, "27pt"): 3}
+
+
+def symbol_product(d, c, x):
+    """A~ M~ (h-free) at the cosine points x, shape (P, d); c = (c0, c1, ...)
+    in the family's order, missing entries zero."""
+    c = list(c) + [0.0] * (4 - len(c))
+    s1 = x.sum(axis=-1)
+    s2 = sum(x[:, a] * x[:, b] for a, b in itertools.combinations(range(d), 2))
+    m = c[0] + 2.0 * c[1] * s1 + 4.0 * c[2] * s2
+    if d == 3:
+        m = m + 8.0 * c[3] * np.prod(x, axis=-1)
+    return 2.0 * (d - s1) * m
+
+
+def mu_opt(d, c, x):
+    """(mu_opt, omega_opt) of the stencil c on the sample x; mu = 1 when the
+    product changes sign on the high frequencies (no damping converges)."""
+    p = symbol_product(d, c, x)
+    l0, l1 = p.min(), p.max()
+    if l0 <= 0.0:
+        return 1.0, 0.0
+    return (l1 - l0) / (l1 + l0), 2.0 / (l0 + l1)
+
+
+def _coeffs(ratios):
+    return np.concatenate([[1.0], ratios])
+
+
+def search(d, family, m=None, starts=None, refine_m=None):
+    """Minimise mu_opt over the family's free ratios c_j / c0 by Nelder-Mead
+    from several starts on a coarse sample of T^H, then polish on a finer
+    one.  Returns dict(mu, omega, ratios, coeffs) where coeffs = omega * c
+    (damping folded in, the library's convention)."""
+    k = FAMILIES[(d, family)]
+    m = m or (200 if d == 2 else 40)
+    refine_m = refine_m or (1000 if d == 2 else 120)
+    x = high_cos_grid(d, m)
+    xf = high_cos_grid(d, refine_m)
+    if starts is None:
+        starts = [np.full(k, 0.1), np.full(k, 0.02), np.linspace(0.2, 0.02, k)]
+    best = None
+    for s in starts:
+        r = minimize(lambda v: mu_opt(d, _coeffs(v), x)[0], np.asarray(s, float),
+                     method="Nelder-Mead",
+                     options=dict(xatol=1e-9, fatol=1e-12, maxiter=4000 * k))
+        if best is None or r.fun < best.fun:
+            best = r
+    r = minimize(lambda v: mu_opt(d, _coeffs(v), xf)[0], best.x, method="Nelder-Mead",
+                 options=dict(xatol=1e-10, fatol=1e-13, maxiter=4000 * k))
+    c = _coeffs(r.x)
+    mu, om = mu_opt(d, c, xf)
+    return {"mu": mu, "omega": om, "ratios": r.x, "coeffs": om * c}
