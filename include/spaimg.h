@@ -107,8 +107,11 @@ typedef struct mg_ctx* mg_handle_t;
 typedef struct mg_stats {
     int cycles;        /* cycles k at which ||r_k|| <= tol ||r_0|| (or the
                           limit); u holds u_k                                 */
-    int cycles_run;    /* cycles executed (one more: the convergence test of
-                          u_k overlaps the next cycle)                        */
+    int cycles_run;    /* cycles (refinement steps) started: one more than
+                          cycles, since u_k is tested by the next cycle's
+                          pre-smoother (refinement step); when the previous
+                          reduction predicts convergence only that part runs
+                          before the host reads the norm                     */
     double r0_norm;    /* ||b - A u_0||_2 (whole batch)                       */
     double rk_norm;    /* ||b - A u_k||_2                                      */
     double b_norm;     /* ||b||_2 (filled only when res_hist is given)        */

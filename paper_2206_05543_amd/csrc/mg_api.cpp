@@ -351,6 +351,10 @@ struct NormReq {
     hipEvent_t ready = nullptr;     // recorded after the copy to the host
 };
 
+// Which part of a cycle to enqueue: all of it, only the pre-smoother (with
+// its norm), or everything after the pre-smoother (tmp holds its output).
+enum CyclePart { kWhole = 0, kPreOnly = 1, kRest = 2 };
+
 // One cycle (V(1,1), or W(1,0) under MG_CYCLE_W10) on hierarchy H at level
 // l: out = V(u_in, b), or from a zero guess when u_in is null.  tmp receives the pre-smoothed iterate
 // (must differ from u_in, b and out; out may alias u_in).  Coarser levels
@@ -358,12 +362,13 @@ struct NormReq {
 // the single-workgroup LDS tail kernel; the coarsest grid is always solved
 // exactly there.
 int cycle(mg_ctx* h, Hier& H, int l, const void* u_in, const void* b, void* out, void* tmp,
-          const NormReq& nr, hipStream_t st) {
+          const NormReq& nr, hipStream_t st, CyclePart part = kWhole) {
     const bool zero = u_in == nullptr;
     const bool wcycle = h->cycle_kind == MG_CYCLE_W10;
     int rc, nparts = 0;
     // zero-guess cycles at or below the tail size run in the LDS tail
     if (l == h->L - 1 || (zero && l >= tail_level(h, true))) {
+        if (part != kWhole) return fail(MG_EINVAL, "split cycle on the tail level");
         if (nr.slot >= 0) {
             // only a single-grid FP64 problem (N = 4) gets here with a norm
             HIPCHK(launch_residual_norm(h->d, level_n(h, l), h->batch,
@@ -386,14 +391,17 @@ int cycle(mg_ctx* h, Hier& H, int l, const void* u_in, const void* b, void* out,
     const bool norm = nr.slot >= 0 && !zero && H.p == P64;
     s.partials = h->psum;
     s.partials_cap = kPartialCap * h->batch;
-    rc = run_timed(h, zero ? MG_TIME_SMOOTH_ZERO : MG_TIME_SMOOTH, l, st,
-                   [&] { return launch_smooth(H.p, zero, norm, s, st, &nparts); });
-    if (rc) return rc;
-    if (norm) {
-        h->pend.count = nparts;
-        h->pend.with_max = false;
-        h->pend.slot = nr.slot;
-        h->pend.ready = nr.ready;
+    if (part != kRest) {
+        rc = run_timed(h, zero ? MG_TIME_SMOOTH_ZERO : MG_TIME_SMOOTH, l, st,
+                       [&] { return launch_smooth(H.p, zero, norm, s, st, &nparts); });
+        if (rc) return rc;
+        if (norm) {
+            h->pend.count = nparts;
+            h->pend.with_max = false;
+            h->pend.slot = nr.slot;
+            h->pend.ready = nr.ready;
+        }
+        if (part == kPreOnly) return MG_OK;
     }
     s.u = tmp;
     s.out = H.b[l + 1];
@@ -462,13 +470,28 @@ int flush_pending_norm(mg_ctx* h, hipStream_t st) {
 // norm_slot >= 0 the pre-smoother also produces ||b - A u_in||_2 into
 // dnorm[2 slot] and starts its copy to the pinned host mirror.
 int fine_cycle64(mg_ctx* h, const double* b, const double* u_in, double* u_out,
-                 int norm_slot, hipStream_t st, hipEvent_t norm_ready = nullptr) {
+                 int norm_slot, hipStream_t st, hipEvent_t norm_ready = nullptr,
+                 CyclePart part = kWhole) {
     NormReq nr;
     nr.slot = norm_slot;
     nr.ready = norm_ready;
-    const int rc = cycle(h, h->h64, 0, u_in, b, u_out, h->h64.t[0], nr, st);
+    const int rc = cycle(h, h->h64, 0, u_in, b, u_out, h->h64.t[0], nr, st, part);
     if (rc) return rc;
     return flush_pending_norm(h, st);
+}
+
+// The solves learn ||r_k|| only while the work that follows it runs, so a
+// converged solve normally discards the rest of one cycle.  When the last
+// reduction factor predicts ||r_k|| <= kGateSlack tol ||r_0||, the loop
+// instead waits for the norm before enqueueing that work (one host round
+// trip, against most of a cycle).
+constexpr double kGateSlack = 4.0;
+
+bool predict_final(const std::vector<double>& hist, double tol, double r0) {
+    const size_t k = hist.size();
+    if (k < 2 || !(hist[k - 2] > 0.0)) return false;
+    const double q = hist[k - 1] / hist[k - 2];
+    return q < 1.0 && hist[k - 1] * q <= kGateSlack * tol * r0;
 }
 
 int check_handle(mg_ctx* h) {
@@ -703,14 +726,27 @@ static int solve64(mg_ctx* h, const double* b, double* u, double tol, mg_stats* 
     for (k = 0;; ++k) {
         // cycle k reads u_k from X and writes u_{k+1} to Y; its pre-smoother
         // also yields ||r_k||.  The host waits only for that norm while the
-        // rest of cycle k runs, then decides whether to enqueue cycle k + 1.
-        int rc = fine_cycle64(h, b, X, Y, k, st, evn);
+        // rest of cycle k runs, then decides whether to enqueue cycle k + 1;
+        // a cycle predicted to find u_k converged runs its pre-smoother alone
+        // first and the rest only if the norm says so.
+        const bool gate = h->L > 1 && predict_final(hist, tol, r0);
+        int rc = fine_cycle64(h, b, X, Y, k, st, evn, gate ? kPreOnly : kWhole);
         if (rc) {
             (void)hipEventDestroy(evn);
             return rc;
         }
         ++run;
         hipError_t e = hipEventSynchronize(evn);
+        if (e == hipSuccess && gate) {
+            const double ng = h->hnorm[2 * k];
+            if (std::isfinite(ng) && ng > tol * r0 && k < h->max_cycles) {
+                rc = fine_cycle64(h, b, X, Y, k, st, nullptr, kRest);
+                if (rc) {
+                    (void)hipEventDestroy(evn);
+                    return rc;
+                }
+            }
+        }
         if (e != hipSuccess) {
             (void)hipEventDestroy(evn);
             return fail(MG_EHIP, std::string("hipEventSynchronize: ") + hipGetErrorString(e));
@@ -765,13 +801,20 @@ static int solve_ir(mg_ctx* h, const double* b, double* u, double tol, mg_stats*
     const double sigma0 = H.scaled ? N * N : 1.0;
     HIPCHK(hipEventRecord(h->ev0, st));
     int nparts = 0, rc;
-    // residual of the initial guess: slot 0 holds (||r_0||, max|r_0|)
-    rc = run_timed(h, MG_TIME_RESIDUAL, 0, st, [&] {
-        return launch_residual_norm(h->d, level_n(h, 0), h->batch, X, b, N * N, h->psum,
-                                    h->pmax, kPartialCap * h->batch, st, &nparts);
-    });
-    if (rc) return rc;
-    HIPCHK(launch_finalize(h->psum, h->pmax, nparts, h->dnorm, st));
+    if (H.p == P16) {
+        // FP16 storage needs r_0 scaled into range: a residual pass of the
+        // initial guess puts (||r_0||, max|r_0|) in slot 0 for the first step
+        rc = run_timed(h, MG_TIME_RESIDUAL, 0, st, [&] {
+            return launch_residual_norm(h->d, level_n(h, 0), h->batch, X, b, N * N, h->psum,
+                                        h->pmax, kPartialCap * h->batch, st, &nparts);
+        });
+        if (rc) return rc;
+        HIPCHK(launch_finalize(h->psum, h->pmax, nparts, h->dnorm, st));
+    } else {
+        // FP32 holds r_0 unscaled: max|r| = 0 in slot 0 gives the first step
+        // the scale 1
+        HIPCHK(hipMemsetAsync(h->dnorm, 0, 2 * sizeof(double), st));
+    }
     std::vector<double> hist;
     double r0 = 0.0, rk = 0.0;
     int k = 0, code = MG_OK, run = 0;
@@ -809,9 +852,14 @@ static int solve_ir(mg_ctx* h, const double* b, double* u, double tol, mg_stats*
         // inner low-precision cycles on A e = s r: the first from zero, the
         // others continue from the current e.  The host reads ||r_k|| while
         // the first inner cycle runs and enqueues the others only if the
-        // solve goes on, so a converged solve discards one inner cycle.
-        rc = cycle(h, H, 0, nullptr, H.b[0], H.e[0], H.t[0], NormReq(), st);
-        if (rc) return rc;
+        // solve goes on, so a converged solve discards one inner cycle --
+        // unless the last reduction predicts convergence: then the norm is
+        // reduced and read before any inner cycle is enqueued.
+        const bool gate = predict_final(hist, tol, r0);
+        if (!gate) {
+            rc = cycle(h, H, 0, nullptr, H.b[0], H.e[0], H.t[0], NormReq(), st);
+            if (rc) return rc;
+        }
         rc = flush_pending_norm(h, st);
         if (rc) return rc;
         ++run;
@@ -830,14 +878,20 @@ static int solve_ir(mg_ctx* h, const double* b, double* u, double tol, mg_stats*
             code = MG_ENOCONV;
             break;
         }
+        if (gate) {
+            rc = cycle(h, H, 0, nullptr, H.b[0], H.e[0], H.t[0], NormReq(), st);
+            if (rc) return rc;
+        }
         for (int j = 1; j < inner_cycles(h); ++j) {
             rc = cycle(h, H, 0, H.e[0], H.b[0], H.e[0], H.t[0], NormReq(), st);
             if (rc) return rc;
         }
-        std::swap(X, Y);
+        // step 0 applies no correction and leaves u_0 in X
+        if (k > 0) std::swap(X, Y);
     }
-    // u_k is the refinement step's output, in Y
-    if (Y != u) HIPCHK(hipMemcpyAsync(u, Y, fine, hipMemcpyDeviceToDevice, st));
+    // u_k is the refinement step's output: in Y, or u_0 in X after step 0
+    double* uk = k > 0 ? Y : X;
+    if (uk != u) HIPCHK(hipMemcpyAsync(u, uk, fine, hipMemcpyDeviceToDevice, st));
     HIPCHK(hipEventRecord(h->ev1, st));
     HIPCHK(hipStreamSynchronize(st));
     (void)hipEventDestroy(evn);

@@ -1551,6 +1551,7 @@ k_finalize(const double* __restrict__ ps, const double* __restrict__ pm, int cou
 // ---------------------------------------------------------------------------
 // FP64 refinement step, 3D: unew = u + escale * e (on the fly, halo included),
 // r = b - A unew, r_lo = s * r (stored in S), partials of r^2 and max |r|.
+// Without a correction (the first step) unew equals u and is not stored.
 // Same scheme as the smoothers: plane buffer resources (e reads as zero when
 // there is no correction yet), an unrolled marching loop over planes.
 // ---------------------------------------------------------------------------
@@ -1665,7 +1666,7 @@ k_ir3d(const double* __restrict__ u, double* __restrict__ unew, const S* __restr
         issue_b(s + 1, (k + 1) % RS);
         if (s < z1) {
             const double* U = uL[cur];
-            const rsrc_t ow = line_rsrc(unew, (long)s * plane, plane, true);
+            const rsrc_t ow = line_rsrc(unew, (long)s * plane, plane, hase);
             const rsrc_t orl = line_rsrc(rlo, (long)s * plane, plane, true);
 #pragma unroll
             for (int m = 0; m < M; ++m) {
@@ -1797,7 +1798,7 @@ k_ir2d(const double* __restrict__ u, double* __restrict__ unew, const S* __restr
         issue_b(s + 1, (k + 1) % RS);
         if (s < y1) {
             const double* U = uL[cur];
-            const rsrc_t ow = line_rsrc(unew, (long)s * n, n, true);
+            const rsrc_t ow = line_rsrc(unew, (long)s * n, n, hase);
             const rsrc_t orl = line_rsrc(rlo, (long)s * n, n, true);
 #pragma unroll
             for (int m = 0; m < M; ++m) {

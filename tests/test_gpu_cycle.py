@@ -126,3 +126,64 @@ def test_residual_norm_entry_point():
         got = mg.residual_norm(dev(b), dev(u0))
     want = O.norm2(O.residual(d, N, u0, b))
     assert abs(got - want) <= 1e-12 * want
+
+
+def _gated_branches(hist, tol):
+    # the solve loop runs the pre-smoother of cycle k alone when the last
+    # reduction factor predicts ||r_k|| <= 4 tol ||r_0||; returns how often
+    # that prediction held with and without convergence at k
+    hit = miss = 0
+    for k in range(2, len(hist)):
+        q = hist[k - 1] / hist[k - 2]
+        if q < 1.0 and hist[k - 1] * q <= 4.0 * tol * hist[0]:
+            if hist[k] <= tol * hist[0]:
+                hit += 1
+            else:
+                miss += 1
+    return hit, miss
+
+
+def test_solve_stops_exactly_across_tolerances():
+    # the tolerance sweep exercises both outcomes of the predicted final
+    # cycle (converged: only its pre-smoother runs; not converged: the rest
+    # of the cycle follows); every solve must stop at the oracle's cycle with
+    # the oracle's iterate
+    need_gpu()
+    p = workload("poisson2d_n64")
+    c = _c(2)
+    hits = misses = 0
+    with make_mg(64, 2, c) as mg:
+        b = dev(p["b"])
+        for tol in np.geomspace(1e-5, 1e-11, 13):
+            u_or, k_or, hist_or = O.solve(2, 64, c, p["u0"], p["b"], tol=tol, maxc=100)
+            say("solve-tol", tol)
+            u = dev(p["u0"])
+            st = mg.solve(b, u, tol=float(tol))
+            got = host(u)
+            assert st["code"] == 0 and st["cycles"] == k_or
+            assert np.max(np.abs(got - u_or)) <= 1e-9 * np.abs(u_or).max()
+            h, m = _gated_branches(hist_or, tol)
+            hits += h
+            misses += m
+    assert hits > 0 and misses > 0
+
+
+@pytest.mark.parametrize("prec", ["fp32_ir", "fp16_ir"])
+def test_refinement_stops_across_tolerances(prec):
+    need_gpu()
+    d, N = 3, 32
+    p = poisson_problem(d, N, seed=21, n_modes=8, kmax=8)
+    r0 = O.norm2(O.residual(d, N, p["u0"], p["b"]))
+    with make_mg(N, d, _c(d), precision=prec) as mg:
+        b = dev(p["b"])
+        for tol in np.geomspace(1e-4, 1e-10, 7):
+            say("ir-tol", prec, tol)
+            u = dev(p["u0"])
+            st = mg.solve(b, u, tol=float(tol))
+            got = host(u)
+            assert st["code"] == 0
+            rk = O.norm2(O.residual(d, N, got, p["b"]))
+            assert rk <= 1.0001 * tol * r0
+            assert abs(st["rk"] - rk) <= 1e-6 * rk + 1e-14 * r0
+            # one step earlier would not have met the tolerance
+            assert st["history"][-2] > tol * r0 if len(st["history"]) > 1 else True
