@@ -487,6 +487,10 @@ int fine_cycle64(mg_ctx* h, const double* b, const double* u_in, double* u_out,
 // trip, against most of a cycle).
 constexpr double kGateSlack = 4.0;
 
+// an in-place cycle (no ping-pong) is taken only when the predicted
+// ||r_k|| exceeds the tolerance by this factor
+constexpr double kFlipMargin = 100.0;
+
 // assumed V-cycle reduction per cycle before any is observed (the optimised
 // SPAI smoothers reach about 0.07-0.12)
 constexpr double kRhoGuess = 0.15;
@@ -725,6 +729,7 @@ static int solve64(mg_ctx* h, const double* b, double* u, double tol, mg_stats* 
     std::vector<double> hist;
     double r0 = 0.0, rk = 0.0;
     int k = 0, code = MG_OK, run = 0;
+    bool flipped = false;
     hipEvent_t evn;
     HIPCHK(hipEventCreateWithFlags(&evn, hipEventDisableTiming));
     for (k = 0;; ++k) {
@@ -734,7 +739,23 @@ static int solve64(mg_ctx* h, const double* b, double* u, double tol, mg_stats* 
         // a cycle predicted to find u_k converged runs its pre-smoother alone
         // first and the rest only if the norm says so.
         const bool gate = h->L > 1 && predict_final(hist, tol, r0);
-        int rc = fine_cycle64(h, b, X, Y, k, st, evn, gate ? kPreOnly : kWhole);
+        // The answer u_K stays where cycle K found it; with ping-pong it
+        // lands in the library's buffer for odd K and needs a final copy.
+        // One cycle run in place (its post-smoother reads only tmp) flips
+        // that parity; it is taken only far from convergence, where u_k
+        // cannot be the answer, once the rate predicts K.
+        bool inplace = false;
+        if (!gate && !flipped && k >= 2 && hist[k - 2] > 0.0) {
+            const double q = hist[k - 1] / hist[k - 2];
+            if (q > 0.0 && q < 0.9 && hist[k - 1] * q >= kFlipMargin * tol * r0) {
+                const int K = k - 1 + (int)std::ceil(std::log(tol * r0 / hist[k - 1]) /
+                                                     std::log(q));
+                const bool lands_in_u = ((K - k) % 2 == 0) == (X == u);
+                inplace = !lands_in_u;
+            }
+        }
+        int rc = fine_cycle64(h, b, X, inplace ? X : Y, k, st, evn,
+                              gate ? kPreOnly : kWhole);
         if (rc) {
             (void)hipEventDestroy(evn);
             return rc;
@@ -764,12 +785,33 @@ static int solve64(mg_ctx* h, const double* b, double* u, double tol, mg_stats* 
         if (k == 0) r0 = nk;
         hist.push_back(nk);
         rk = nk;
+        if (inplace && (nk <= tol * r0 || k >= h->max_cycles)) {
+            // the prediction failed: u_k was overwritten by u_{k+1}, which
+            // is returned with its own residual
+            int np = 0;
+            const double N = h->N;
+            HIPCHK(launch_residual_norm(h->d, level_n(h, 0), h->batch, X, b, N * N, h->psum,
+                                        h->pmax, kPartialCap * h->batch, st, &np));
+            HIPCHK(launch_finalize(h->psum, nullptr, np, h->dnorm, st));
+            HIPCHK(hipMemcpyAsync(h->hnorm, h->dnorm, sizeof(double), hipMemcpyDeviceToHost,
+                                  st));
+            HIPCHK(hipStreamSynchronize(st));
+            rk = h->hnorm[0];
+            ++k;
+            hist.push_back(rk);
+            if (rk <= tol * r0) break;
+            code = MG_ENOCONV;
+            break;
+        }
         if (nk <= tol * r0) break;
         if (k >= h->max_cycles) {
             code = MG_ENOCONV;
             break;
         }
-        std::swap(X, Y);
+        if (inplace)
+            flipped = true;
+        else
+            std::swap(X, Y);
     }
     (void)hipEventDestroy(evn);
     // u_k is in X
