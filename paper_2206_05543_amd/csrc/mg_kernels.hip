@@ -1859,7 +1859,8 @@ inline int even_chunk(int c) { return c + (c & 1); }
 // large grids, where halo planes cost bandwidth, more and shorter ones on
 // smaller grids, where latency dominates.
 //   smoother 3D  n >= 200: 64x16 tiles / 640 threads, unrolled 6, 256 marches
-//                (FP32/FP16 storage: 128x16 / 768, 1024 marches)
+//                (FP32/FP16 storage: 256x8 / 1024, 1024 marches: 4- and 2-byte
+//                rows need long row segments)
 //                n >= 100: 64x16 / 640, 256 marches;  else 32x16 / 320, 256
 //   smoother 2D  n >= 3000: 1024-wide strips / 576 threads, unrolled 4, 256
 //                n >= 700: 512 / 320, 512 marches;  else 128 / 192, 512
@@ -1934,10 +1935,14 @@ hipError_t smooth_impl(bool zg, bool norm, const Sweep& s, hipStream_t st, int* 
     // the large configurations (at least 200^3 or 3000^2 > 2^22 nodes)
     // store non-temporally
     if (s.d == 3) {
-        // FP32 / FP16 storage: 128-wide tiles and 1024 marches (4-byte and
-        // 2-byte rows need longer row segments and more waves in flight)
-        if (sizeof(S) < 8 && n >= 200)
-            return launch_smooth3d<S, C, 128, 16, 768, 6, true>(zg, norm, s, 1024, 32, st, nparts);
+        // FP32 / FP16 storage: 256x8 tiles on 1024 threads and 1024 marches
+        // (4-byte and 2-byte rows need longer row segments and more waves in
+        // flight; 11% faster than 128x16 tiles measured cold at n = 511)
+        if constexpr (sizeof(S) < 8) {
+            if (n >= 200)
+                return launch_smooth3d<S, C, 256, 8, 1024, 6, true>(zg, norm, s, 1024, 32, st,
+                                                                     nparts);
+        }
         if (n >= 200) return launch_smooth3d<S, C, 64, 16, 640, 6, true>(zg, norm, s, 256, 32, st, nparts);
         if (n >= 100) return launch_smooth3d<S, C, 64, 16, 640, 2, false>(zg, norm, s, 256, 2, st, nparts);
         return launch_smooth3d<S, C, 32, 16, 320, 2, false>(zg, norm, s, 256, 2, st, nparts);
@@ -2038,8 +2043,10 @@ hipError_t ir_impl(const IRStep& s, hipStream_t st, int* nparts) {
     S* rlo = static_cast<S*>(s.r_lo);
     if (s.d == 3 && (long)n * n * 8L > 0x7fffffffL) return hipErrorInvalidValue;
     const bool large = s.d == 3 ? n >= 200 : n >= 3000;
-    // same shapes as the smoothers; large grids: one long march per CU,
-    // unrolled 6 times, non-temporal stores
+    // same shapes as the FP64 smoothers; large grids: one long march per CU,
+    // unrolled 6 times, non-temporal stores (256x4 tiles were faster alone,
+    // measured cold, but not inside the refinement loop, and slower with
+    // FP16 corrections)
 #define IR3(TX, TY, NT, UN, NTS, WANT, MINC)                                                    \
     do {                                                                                       \
         const int tx = cdiv(n, TX), ty = cdiv(n, TY);                                          \
