@@ -67,10 +67,8 @@ extern "C" {
                                (with the fused correction) with HIP events;
                                2 time every kernel of every level              */
 #define MG_OPT_INNER_CYCLES 6 /* low-precision V-cycles per FP64 refinement
-                               step, 1..16; 0 = adaptive (default): as many
-                               as the reduction per cycle (0.15 assumed in
-                               the first step, then observed) needs to reach
-                               tol, at most 6 (FP32) or 2 (FP16)              */
+                               step, 1..16; 0 = default (6 for FP32, 2 for
+                               FP16)                                          */
 #define MG_OPT_CYCLE 7      /* MG_CYCLE_*: the cycle of mg_vcycle, mg_solve
                                and the inner cycles of refinement (default V) */
 

@@ -107,9 +107,15 @@ int level_N(const mg_ctx* h, int l) { return h->N >> l; }
 int default_tail_N(int d) { return d == 2 ? 64 : 16; }
 
 // low-precision V-cycles per FP64 refinement step
+// low-precision V-cycles per FP64 refinement step.  FP32: six reach about
+// what FP32 resolves in one step (~1e-6), so 1e-10 takes two steps; fewer
+// per step need more steps, and a last step cut short leaves smooth error
+// components that lie below FP32's resolution of the residual (the residual
+// norm meets tol while the error stays above the FP64 solve's).  FP16: a
+// third cycle gains little.
 int inner_cycles(const mg_ctx* h) {
     if (h->inner) return h->inner;
-    return h->prec == MG_PREC_FP16_IR ? 2 : 3;
+    return h->prec == MG_PREC_FP16_IR ? 2 : 6;
 }
 
 // first level whose zero-guess cycles run in the tail kernel
@@ -490,10 +496,6 @@ constexpr double kGateSlack = 4.0;
 // an in-place cycle (no ping-pong) is taken only when the predicted
 // ||r_k|| exceeds the tolerance by this factor
 constexpr double kFlipMargin = 100.0;
-
-// assumed V-cycle reduction per cycle before any is observed (the optimised
-// SPAI smoothers reach about 0.07-0.12)
-constexpr double kRhoGuess = 0.15;
 
 bool predict_final(const std::vector<double>& hist, double tol, double r0) {
     const size_t k = hist.size();
@@ -926,25 +928,12 @@ static int solve_ir(mg_ctx* h, const double* b, double* u, double tol, mg_stats*
             code = MG_ENOCONV;
             break;
         }
-        // inner cycles of this step: the option's fixed count, else as many
-        // as the per-cycle reduction needs to reach tol (with a factor 2 to
-        // spare) -- assumed kRhoGuess in the first step, observed afterwards
-        // -- at most what the storage precision delivers in one step (FP32
-        // reaches ~1e-6 in six cycles; FP16 gains little beyond two)
-        int m = inner_cycles(h);
+        // inner cycles of this step (fixed: the option's count or the
+        // default), and the per-cycle reduction observed in the last step,
+        // which predicts ||r_{k+1}|| for the gate
+        const int m = inner_cycles(h);
         double rho = 1.0;
         if (k > 0) rho = std::pow(nk / hist[k - 1], 1.0 / m_prev);
-        if (!h->inner) {
-            const int mmax = H.p == P16 ? 2 : 6;
-            const double r = k > 0 ? rho : kRhoGuess;
-            if (r < 0.95) {
-                const double need = 0.5 * tol * r0 / nk;
-                m = (int)std::ceil(std::log(need) / std::log(std::max(r, 0.05)));
-                m = std::min(std::max(m, 1), mmax);
-            } else {
-                m = mmax;
-            }
-        }
         pred = k > 0 && rho < 1.0 ? nk * std::pow(rho, m) : -1.0;
         m_prev = m;
         if (gate) {
