@@ -101,6 +101,8 @@ extern "C" {
 #define MG_TIME_IR_STEP 5
 #define MG_TIME_RESIDUAL 6
 #define MG_TIME_SMOOTH_CORRECT 7  /* post-smoothing with the fused correction */
+#define MG_TIME_ZERO_SMOOTH_RESTRICT 8  /* zero-guess pre-smoothing fused with
+                                           the restriction (2D coarse levels) */
 
 typedef struct mg_ctx* mg_handle_t;
 

@@ -20,7 +20,7 @@ CYCLE = {"V11": 0, "W10": 1}
 PREC = {"fp64": 0, "fp32_ir": 1, "fp16_ir": 2}
 OP = {"smooth": 0, "smooth_zero": 1, "restrict": 2, "prolong_add": 3}
 TIME = {"smooth": 0, "smooth_zero": 1, "restrict": 2, "prolong": 3, "tail": 4,
-        "ir_step": 5, "residual": 6, "smooth_correct": 7}
+        "ir_step": 5, "residual": 6, "smooth_correct": 7, "zero_smooth_restrict": 8}
 STORAGE = {0: torch.float64, 1: torch.float32, 2: torch.float16}
 
 _lib = None

@@ -38,7 +38,7 @@ int fail(int code, const std::string& msg) {
     } while (0)
 
 constexpr int kMaxLevels = 20;
-constexpr int kTimeKinds = 8;
+constexpr int kTimeKinds = 9;
 constexpr long kPartialCap = 1 << 17;  // per batch entry
 
 struct Hier {
@@ -357,18 +357,66 @@ struct NormReq {
     hipEvent_t ready = nullptr;     // recorded after the copy to the host
 };
 
+// Where the zero-guess pre-smoother and the restriction run as one kernel:
+// the 2D coarse levels, where its halo costs 1.3x the reads of b and it
+// saves a launch and a pass over b and e (2.7% per 2D V-cycle).  In 3D the
+// halo of a tile that fits LDS (8x4x4 coarse nodes: 3.5x the reads of b,
+// 2.25x the work on e) made it slower than the two marching sweeps on every
+// grid size, the launch-bound ones included.
+bool fuse_zero_restrict(const mg_ctx* h, int l) { return h->d == 2 && l >= 1; }
+
 // Which part of a cycle to enqueue: all of it, only the pre-smoother (with
 // its norm), or everything after the pre-smoother (tmp holds its output).
 enum CyclePart { kWhole = 0, kPreOnly = 1, kRest = 2 };
 
-// One cycle (V(1,1), or W(1,0) under MG_CYCLE_W10) on hierarchy H at level
-// l: out = V(u_in, b), or from a zero guess when u_in is null.  tmp receives the pre-smoothed iterate
-// (must differ from u_in, b and out; out may alias u_in).  Coarser levels
-// use H.b / H.e / H.t.  Zero-guess cycles at or below the tail size run in
-// the single-workgroup LDS tail kernel; the coarsest grid is always solved
-// exactly there.
 int cycle(mg_ctx* h, Hier& H, int l, const void* u_in, const void* b, void* out, void* tmp,
-          const NormReq& nr, hipStream_t st, CyclePart part = kWhole) {
+          const NormReq& nr, hipStream_t st, CyclePart part = kWhole);
+
+// The part of a cycle after the restriction: the coarse visit(s), then
+// the post-smoother with the fused correction (V) or the correction alone
+// (W).  s holds the level's sweep parameters; tmp the pre-smoothed iterate.
+int coarse_and_post(mg_ctx* h, Hier& H, int l, void* tmp, void* out, Sweep s, double pf,
+                    bool wcycle, hipStream_t st) {
+    int rc;
+    if (wcycle) {
+        // gamma = 2: the coarse problem twice, the second visit starting from
+        // the first's result (both visits in one tail launch at or below the
+        // tail size); no post-smoothing: out = tmp + pf P e_{l+1}
+        if (l + 1 == h->L - 1 || l + 1 >= tail_level(h, true)) {
+            rc = run_tail(h, H, l + 1, H.b[l + 1], H.e[l + 1], st, 2);
+        } else {
+            rc = cycle(h, H, l + 1, nullptr, H.b[l + 1], H.e[l + 1], H.t[l + 1], NormReq(), st);
+            if (rc) return rc;
+            rc = cycle(h, H, l + 1, H.e[l + 1], H.b[l + 1], H.e[l + 1], H.t[l + 1], NormReq(),
+                       st);
+        }
+        if (rc) return rc;
+        return run_timed(h, MG_TIME_PROLONG, l, st, [&] {
+            return launch_prolong_to(H.p, h->d, s.n, h->batch, H.e[l + 1], tmp, out, pf, st);
+        });
+    }
+    rc = cycle(h, H, l + 1, nullptr, H.b[l + 1], H.e[l + 1], H.t[l + 1], NormReq(), st);
+    if (rc) return rc;
+    s.u = tmp;
+    s.out = out;
+    // post-smoothing of tmp + pf P e_{l+1}: the correction is fused into the
+    // sweep on every level (on small grids it costs no more than a plain
+    // sweep, and saves the separate correction launch)
+    s.ec = H.e[l + 1];
+    s.pf = pf;
+    return run_timed(h, MG_TIME_SMOOTH_CORRECT, l, st,
+                     [&] { return launch_smooth(H.p, false, false, s, st, nullptr); });
+}
+
+// One cycle (V(1,1), or W(1,0) under MG_CYCLE_W10) on hierarchy H at level
+// l: out = V(u_in, b), or from a zero guess when u_in is null.  tmp receives
+// the pre-smoothed iterate (must differ from u_in, b and out; out may alias
+// u_in).  Coarser levels use H.b / H.e / H.t.  Zero-guess cycles at or
+// below the tail size run in the single-workgroup LDS tail kernel (the
+// coarsest grid is always solved exactly there); above it their
+// pre-smoother and restriction are one fused kernel.
+int cycle(mg_ctx* h, Hier& H, int l, const void* u_in, const void* b, void* out, void* tmp,
+          const NormReq& nr, hipStream_t st, CyclePart part) {
     const bool zero = u_in == nullptr;
     const bool wcycle = h->cycle_kind == MG_CYCLE_W10;
     int rc, nparts = 0;
@@ -397,6 +445,30 @@ int cycle(mg_ctx* h, Hier& H, int l, const void* u_in, const void* b, void* out,
     const bool norm = nr.slot >= 0 && !zero && H.p == P64;
     s.partials = h->psum;
     s.partials_cap = kPartialCap * h->batch;
+    if (zero && part == kWhole && fuse_zero_restrict(h, l)) {
+        // zero-guess pre-smoothing and the restriction in one kernel (it
+        // also reduces a pending norm in its first workgroup, as the
+        // restriction would)
+        s.out_c = H.b[l + 1];
+        const mg_ctx::PendingNorm pz = h->pend;
+        if (pz.count > 0) {
+            s.fin_ps = h->psum;
+            s.fin_pm = pz.with_max ? h->pmax : nullptr;
+            s.fin_count = pz.count;
+            s.fin_dev = h->dnorm + 2 * pz.slot;
+            s.fin_host = h->hnorm_dev + 2 * pz.slot;
+            h->pend = mg_ctx::PendingNorm();
+        }
+        rc = run_timed(h, MG_TIME_ZERO_SMOOTH_RESTRICT, l, st,
+                       [&] { return launch_zero_smooth_restrict(H.p, s, st); });
+        if (rc) return rc;
+        if (pz.count > 0 && pz.ready) HIPCHK(hipEventRecord(pz.ready, st));
+        s.out_c = nullptr;
+        s.fin_ps = s.fin_pm = nullptr;
+        s.fin_count = 0;
+        s.fin_dev = s.fin_host = nullptr;
+        return coarse_and_post(h, H, l, tmp, out, s, pf, wcycle, st);
+    }
     if (part != kRest) {
         rc = run_timed(h, zero ? MG_TIME_SMOOTH_ZERO : MG_TIME_SMOOTH, l, st,
                        [&] { return launch_smooth(H.p, zero, norm, s, st, &nparts); });
@@ -428,34 +500,7 @@ int cycle(mg_ctx* h, Hier& H, int l, const void* u_in, const void* b, void* out,
     s.fin_ps = s.fin_pm = nullptr;
     s.fin_count = 0;
     s.fin_dev = s.fin_host = nullptr;
-    if (wcycle) {
-        // gamma = 2: the coarse problem twice, the second visit starting from
-        // the first's result (both visits in one tail launch at or below the
-        // tail size); no post-smoothing: out = tmp + pf P e_{l+1}
-        if (l + 1 == h->L - 1 || l + 1 >= tail_level(h, true)) {
-            rc = run_tail(h, H, l + 1, H.b[l + 1], H.e[l + 1], st, 2);
-        } else {
-            rc = cycle(h, H, l + 1, nullptr, H.b[l + 1], H.e[l + 1], H.t[l + 1], NormReq(), st);
-            if (rc) return rc;
-            rc = cycle(h, H, l + 1, H.e[l + 1], H.b[l + 1], H.e[l + 1], H.t[l + 1], NormReq(),
-                       st);
-        }
-        if (rc) return rc;
-        return run_timed(h, MG_TIME_PROLONG, l, st, [&] {
-            return launch_prolong_to(H.p, h->d, s.n, h->batch, H.e[l + 1], tmp, out, pf, st);
-        });
-    }
-    rc = cycle(h, H, l + 1, nullptr, H.b[l + 1], H.e[l + 1], H.t[l + 1], NormReq(), st);
-    if (rc) return rc;
-    s.u = tmp;
-    s.out = out;
-    // post-smoothing of tmp + pf P e_{l+1}: the correction is fused into the
-    // sweep on every level (on small grids it costs no more than a plain
-    // sweep, and saves the separate correction launch)
-    s.ec = H.e[l + 1];
-    s.pf = pf;
-    return run_timed(h, MG_TIME_SMOOTH_CORRECT, l, st,
-                     [&] { return launch_smooth(H.p, false, false, s, st, nullptr); });
+    return coarse_and_post(h, H, l, tmp, out, s, pf, wcycle, st);
 }
 
 // Reduces a pending norm that no restriction has picked up (tail-only

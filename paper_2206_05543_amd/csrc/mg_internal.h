@@ -42,6 +42,9 @@ struct Sweep {
     int fin_count = 0;
     double* fin_dev = nullptr;
     double* fin_host = nullptr;
+    // coarse right-hand side written by the fused zero-guess smoother +
+    // restriction ((n+1)/2 - 1 interior nodes per direction)
+    void* out_c = nullptr;
 };
 
 // Launchers return hipSuccess or the launch error.  *nparts receives the
@@ -49,6 +52,9 @@ struct Sweep {
 hipError_t launch_smooth(Prec p, bool zero_guess, bool norm, const Sweep& s,
                          hipStream_t st, int* nparts);
 hipError_t launch_restrict(Prec p, const Sweep& s, hipStream_t st);
+// zero-guess pre-smoother fused with the restriction (2D): out = sW K b on
+// the fine grid, out_c = R (b - sA L out) on the coarse grid (u, ec ignored)
+hipError_t launch_zero_smooth_restrict(Prec p, const Sweep& s, hipStream_t st);
 // u (fine, n interior) += pf * P ec (coarse, n/2 interior)
 hipError_t launch_prolong(Prec p, int d, int n, int batch, const void* ec,
                           void* u, double pf, hipStream_t st);

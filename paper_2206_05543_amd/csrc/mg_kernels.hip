@@ -1174,6 +1174,85 @@ k_prolong3d(const S* __restrict__ ec, const S* in, S* out, int n, int nc, C pf) 
 }
 
 // ---------------------------------------------------------------------------
+// Zero-guess pre-smoothing fused with the restriction (2D coarse levels):
+// e = sW K_c b, r = b - sA L e, bc = R r.  A workgroup owns a tile of coarse
+// nodes; it stages b on the tile's fine footprint plus a ring of 3 in LDS
+// (zero outside the grid), forms e on the footprint plus a ring of 1 (zero
+// outside the grid), r on the footprint, and writes e on the fine nodes it
+// owns and bc on its coarse nodes.  The halo costs re-reads (mostly L2 hits)
+// and recomputation of e, against a whole launch and one pass over b and e
+// in HBM saved.  Arithmetic in the order of the separate sweeps.  Block 0
+// reduces a pending norm like the restriction does.
+// ---------------------------------------------------------------------------
+template <typename S, typename C, int CX, int CY, int NT>
+__global__ void __launch_bounds__(NT)
+k_zsr2d(const S* __restrict__ b, S* __restrict__ e, S* __restrict__ bc, int n, int nc,
+        int tiles_x, int tiles_y, C sA, C sW, C c0, C c1, C c2,
+        const double* __restrict__ fin_ps, const double* __restrict__ fin_pm, int fin_count,
+        double* __restrict__ fin_dev, double* __restrict__ fin_host) {
+    constexpr int RX = 2 * CX + 1, RY = 2 * CY + 1;  // r: the fine footprint
+    constexpr int EX = RX + 2, EY = RY + 2;          // e: footprint + 1
+    constexpr int BX = RX + 4, BY = RY + 4;          // b: footprint + 2 (+ 1 for e)
+    __shared__ C bL[BX * BY];
+    __shared__ C eL[EX * EY];
+    __shared__ C rL[RX * RY];
+    __shared__ double red[NT / 64];
+    if (fin_count > 0 && blockIdx.x == 0 && blockIdx.y == 0)
+        finalize_norm<NT>(fin_ps, fin_pm, fin_count, fin_dev, fin_host, red);
+    const int lg = xcd_remap(blockIdx.x, tiles_x * tiles_y);
+    const int cx0 = (lg % tiles_x) * CX, cy0 = (lg / tiles_x) * CY;
+    const int fx0 = 2 * cx0, fy0 = 2 * cy0;
+    const long area = (long)n * n;
+    b += (long)blockIdx.y * area;
+    e += (long)blockIdx.y * area;
+    bc += (long)blockIdx.y * nc * nc;
+    // fine nodes owned: [fx0, 2 (cx0 + CX)), the last tile up to n
+    const int ox1 = cx0 + CX >= nc ? n : fx0 + 2 * CX;
+    const int oy1 = cy0 + CY >= nc ? n : fy0 + 2 * CY;
+    const int t = threadIdx.x;
+    for (int i = t; i < BX * BY; i += NT) {
+        const int lx = i % BX, ly = i / BX;
+        const int gx = fx0 - 2 + lx, gy = fy0 - 2 + ly;
+        C v = C(0);
+        if (gx >= 0 && gx < n && gy >= 0 && gy < n) v = cvt<C>(b[(long)gy * n + gx]);
+        bL[i] = v;
+    }
+    __syncthreads();
+    for (int i = t; i < EX * EY; i += NT) {
+        const int lx = i % EX, ly = i / EX;
+        const int gx = fx0 - 1 + lx, gy = fy0 - 1 + ly;
+        const int q = (ly + 1) * BX + lx + 1;
+        const C f = bL[q - 1] + bL[q + 1] + bL[q - BX] + bL[q + BX];
+        const C cn = bL[q - BX - 1] + bL[q - BX + 1] + bL[q + BX - 1] + bL[q + BX + 1];
+        const C v = sW * (c0 * bL[q] + c1 * f + c2 * cn);
+        const bool in = gx >= 0 && gx < n && gy >= 0 && gy < n;
+        eL[i] = in ? v : C(0);
+        if (gx >= fx0 && gx < ox1 && gy >= fy0 && gy < oy1)
+            e[(long)gy * n + gx] = static_cast<S>(v);
+    }
+    __syncthreads();
+    for (int i = t; i < RX * RY; i += NT) {
+        const int lx = i % RX, ly = i / RX;
+        const int qe = (ly + 1) * EX + lx + 1, qb = (ly + 2) * BX + lx + 2;
+        const C lap = C(4) * eL[qe] - eL[qe - 1] - eL[qe + 1] - eL[qe - EX] - eL[qe + EX];
+        const C r = bL[qb] - sA * lap;
+        rL[i] = (fx0 + lx < n && fy0 + ly < n) ? r : C(0);
+    }
+    __syncthreads();
+    for (int i = t; i < CX * CY; i += NT) {
+        const int lx = i % CX, ly = i / CX;
+        const int ci = cx0 + lx, cj = cy0 + ly;
+        if (ci >= nc || cj >= nc) continue;
+        const int q = (2 * ly + 1) * RX + 2 * lx + 1;
+        auto xs = [&](int c) { return C(0.5) * rL[c] + C(0.25) * (rL[c - 1] + rL[c + 1]); };
+        C acc = C(0.25) * xs(q - RX);
+        acc += C(0.5) * xs(q);
+        acc += C(0.25) * xs(q + RX);
+        bc[(long)cj * nc + ci] = static_cast<S>(acc);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Coarse tail: every level from nt interior nodes per direction down to 3,
 // the exact solve on the 3^d grid and back up, in one workgroup of 1024
 // threads with all level arrays in LDS, as a V(1,1) cycle or (wvisits > 0)
@@ -2109,6 +2188,30 @@ hipError_t launch_restrict(Prec p, const Sweep& s, hipStream_t st) {
         case P64: return restrict_impl<double, double>(s, st);
         case P32: return restrict_impl<float, float>(s, st);
         default: return restrict_impl<_Float16, float>(s, st);
+    }
+}
+
+template <typename S, typename C>
+hipError_t zsr_impl(const Sweep& s, hipStream_t st) {
+    const int n = s.n, nc = (n + 1) / 2 - 1;
+    if (s.d != 2 || nc < 1 || !s.out_c) return hipErrorInvalidValue;
+    const S* b = static_cast<const S*>(s.b);
+    S* e = static_cast<S*>(s.out);
+    S* bc = static_cast<S*>(s.out_c);
+    const C sA = C(s.sA), sW = C(s.sW), c0 = C(s.c[0]), c1 = C(s.c[1]), c2 = C(s.c[2]);
+    constexpr int CX = 16, CY = 16;
+    const int tx = cdiv(nc, CX), ty = cdiv(nc, CY);
+    hipLaunchKernelGGL((k_zsr2d<S, C, CX, CY, 256>), dim3(tx * ty, s.batch), dim3(256), 0, st,
+                       b, e, bc, n, nc, tx, ty, sA, sW, c0, c1, c2, s.fin_ps, s.fin_pm,
+                       s.fin_count, s.fin_dev, s.fin_host);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_smooth_restrict(Prec p, const Sweep& s, hipStream_t st) {
+    switch (p) {
+        case P64: return zsr_impl<double, double>(s, st);
+        case P32: return zsr_impl<float, float>(s, st);
+        default: return zsr_impl<_Float16, float>(s, st);
     }
 }
 
