@@ -1255,7 +1255,7 @@ k_zsr2d(const S* __restrict__ b, S* __restrict__ e, S* __restrict__ bc, int n, i
 // ---------------------------------------------------------------------------
 // Coarse tail: every level from nt interior nodes per direction down to 3,
 // the exact solve on the 3^d grid and back up, in one workgroup of 1024
-// threads with all level arrays in LDS, as a V(1,1) cycle or (wvisits > 0)
+// threads with all level arrays in LDS, as a V(1,1) cycle or (WC) wvisits
 // W(1,0) visits of the top level.  Each level's first visit starts from a
 // zero guess (pre-smoothing is e = sW K b).  Every LDS array carries a ring of
 // zeros, so stencils need no bounds checks; threads map to nodes through
@@ -1304,40 +1304,12 @@ __device__ __forceinline__ void tail_for(int n, F&& f) {
     }
 }
 
-// calls f(i, j, k) for every node of a small n-grid owned by this lane of
-// wave 0 (2D: 8 x 8 lane box, 3D: 4 x 4 x 4)
-template <int D, typename F>
-__device__ __forceinline__ void tail_for_wave(int n, F&& f) {
-    const int lane = threadIdx.x;
-    if (D == 2) {
-        for (int j = lane >> 3; j < n; j += 8)
-            for (int i = lane & 7; i < n; i += 8) f(i, j, 0);
-    } else {
-        for (int k = lane >> 4; k < n; k += 4)
-            for (int j = (lane >> 2) & 3; j < n; j += 4)
-                for (int i = lane & 3; i < n; i += 4) f(i, j, k);
-    }
-}
-
-// orders the LDS accesses of one wave: its lanes exchange data through LDS,
-// and the LDS executes one wave's operations in issue order
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// grids of at most this many interior nodes per direction are processed by
-// wave 0 alone, with wave-level ordering instead of workgroup barriers
-template <int D>
-constexpr int kTailWaveN = D == 2 ? 15 : 7;
-
 // byte offset of the FP64 coarsest-grid inverse behind the level arrays
 __host__ __device__ inline size_t tail_ginv_offset(size_t level_bytes) {
     return (level_bytes + 7) & ~size_t(7);
 }
 
-template <typename S, typename C, int D>
+template <typename S, typename C, int D, bool WC>
 __global__ void __launch_bounds__(1024)
 k_tail(const S* __restrict__ bt, S* __restrict__ et, int nt, C c0, C c1, C c2,
        const double* __restrict__ ginv, int scaled, int Ntop, int wvisits) {
@@ -1402,28 +1374,12 @@ k_tail(const S* __restrict__ bt, S* __restrict__ et, int nt, C c0, C c1, C c2,
     auto pidx = [&](int i, int j, int k, int P) -> long {
         return D == 3 ? ((long)(k + 1) * P + j + 1) * P + i + 1 : (long)(j + 1) * P + i + 1;
     };
-    // runs f over the nodes of an n-grid and orders the phase: all threads
-    // and a workgroup barrier on large grids, wave 0 and a wave-level fence
-    // on small ones; a large-grid phase after small-grid ones first waits
-    // for wave 0 at a barrier.  Every condition here is uniform.
-    bool after_small = false;
+    // runs f over the nodes of an n-grid, then a workgroup barrier
     auto nodes = [&](int n, auto&& f) {
-        if (n <= kTailWaveN<D>) {
-            if (t < 64) {
-                tail_for_wave<D>(n, f);
-                wave_sync();
-            }
-            after_small = true;
-        } else {
-            if (after_small) {
-                __syncthreads();
-                after_small = false;
-            }
-            tail_for<D>(n, f);
-            __syncthreads();
-        }
+        tail_for<D>(n, f);
+        __syncthreads();
     };
-    // ---- phases (the grid a phase iterates over sets its ordering)
+    // ---- phases on level l (each ends with a barrier)
     // zero-guess pre-smoothing: E = sW K B
     auto smooth_zero = [&](int l) {
         const int n = nl(l), P = n + 2;
@@ -1492,19 +1448,16 @@ k_tail(const S* __restrict__ bt, S* __restrict__ et, int nt, C c0, C c1, C c2,
         const int m = D == 2 ? 9 : 27, P = 5;
         C* E = base(L - 1);
         const C* B = E + tail_padded(D, 3);
-        if (t < 64) {
-            if (t < m) {
-                const int i = t % 3, j = (t / 3) % 3, k = t / 9;
-                double s = 0.0;
-                for (int q = 0; q < m; ++q) {
-                    const int qi = q % 3, qj = (q / 3) % 3, qk = q / 9;
-                    s += gl[t * m + q] * (double)B[pidx(qi, qj, qk, P)];
-                }
-                E[pidx(i, j, k, P)] = C(s);
+        if (t < m) {
+            const int i = t % 3, j = (t / 3) % 3, k = t / 9;
+            double s = 0.0;
+            for (int q = 0; q < m; ++q) {
+                const int qi = q % 3, qj = (q / 3) % 3, qk = q / 9;
+                s += gl[t * m + q] * (double)B[pidx(qi, qj, qk, P)];
             }
-            wave_sync();
+            E[pidx(i, j, k, P)] = C(s);
         }
-        after_small = true;
+        __syncthreads();
     };
     // E_l += pf P E_{l+1} (linear interpolation: fine node i, at grid
     // coordinate i+1, takes the coarse node (i+1)/2 if even, the mean of
@@ -1534,18 +1487,104 @@ k_tail(const S* __restrict__ bt, S* __restrict__ et, int nt, C c0, C c1, C c2,
         });
     };
 
-    if (wvisits == 0) {
-        // V(1,1) from a zero guess
+    if constexpr (!WC) {
+        // V(1,1) from a zero guess, written out level by level
         for (int l = 0; l + 1 < L; ++l) {
-            smooth_zero(l);
-            residual(l);
-            restrict_r(l);
+            const int n = nl(l), P = n + 2, nc = nl(l + 1), Pc = nc + 2;
+            C* E = base(l);
+            C* B = E + tail_padded(D, n);
+            C* R = B + tail_padded(D, n);
+            C* Bc = base(l + 1) + tail_padded(D, nc);
+            C sA, sW;
+            level_consts(l, &sA, &sW);
+            tail_for<D>(n, [&](int i, int j, int k) {
+                const long q = pidx(i, j, k, P);
+                E[q] = sW * spai(B, q, P);
+            });
+            __syncthreads();
+            tail_for<D>(n, [&](int i, int j, int k) {
+                const long q = pidx(i, j, k, P);
+                R[q] = B[q] - sA * lap(E, q, P);
+            });
+            __syncthreads();
+            tail_for<D>(nc, [&](int i, int j, int k) {
+                const long q = pidx(2 * i + 1, 2 * j + 1, D == 3 ? 2 * k + 1 : 0, P);
+                C s;
+                if (D == 2) {
+                    s = C(0.25) * R[q] + C(0.125) * (R[q - 1] + R[q + 1] + R[q - P] + R[q + P]) +
+                        C(0.0625) * (R[q - P - 1] + R[q - P + 1] + R[q + P - 1] + R[q + P + 1]);
+                } else {
+                    const long P2 = (long)P * P;
+                    s = C(0);
+                    for (int oz = -1; oz <= 1; ++oz) {
+                        const long qz = q + oz * P2;
+                        const C pl = C(0.25) * R[qz] +
+                                     C(0.125) * (R[qz - 1] + R[qz + 1] + R[qz - P] + R[qz + P]) +
+                                     C(0.0625) * (R[qz - P - 1] + R[qz - P + 1] + R[qz + P - 1] +
+                                                  R[qz + P + 1]);
+                        s += (oz == 0 ? C(0.5) : C(0.25)) * pl;
+                    }
+                }
+                Bc[pidx(i, j, k, Pc)] = s;
+            });
+            __syncthreads();
         }
-        exact();
+        {
+            const int m = D == 2 ? 9 : 27, P = 5;
+            C* E = base(L - 1);
+            C* B = E + tail_padded(D, 3);
+            if (t < m) {
+                const int i = t % 3, j = (t / 3) % 3, k = t / 9;
+                double s = 0.0;
+                for (int q = 0; q < m; ++q) {
+                    const int qi = q % 3, qj = (q / 3) % 3, qk = q / 9;
+                    s += gl[t * m + q] * (double)B[pidx(qi, qj, qk, P)];
+                }
+                E[pidx(i, j, k, P)] = C(s);
+            }
+            __syncthreads();
+        }
         for (int l = L - 2; l >= 0; --l) {
-            correct(l);
-            residual(l);
-            update(l);
+            const int n = nl(l), P = n + 2, nc = nl(l + 1), Pc = nc + 2;
+            C* E = base(l);
+            C* B = E + tail_padded(D, n);
+            C* R = B + tail_padded(D, n);
+            const C* Ec = base(l + 1);
+            C sA, sW;
+            level_consts(l, &sA, &sW);
+            // linear interpolation: fine node i (grid coordinate i+1) takes the
+            // coarse node (i+1)/2 if even, the mean of (i/2, i/2+1) if odd; in
+            // padded coarse coordinates the coarse node G sits at index G, and
+            // the ring supplies the zero boundary values
+            tail_for<D>(n, [&](int i, int j, int k) {
+                const int gi = i + 1, gj = j + 1, gk = k + 1;
+                const int ia = gi >> 1, ib = (gi + 1) >> 1;
+                const int ja = gj >> 1, jb = (gj + 1) >> 1;
+                C v;
+                if (D == 2) {
+                    v = C(0.25) * (Ec[ja * Pc + ia] + Ec[ja * Pc + ib] + Ec[jb * Pc + ia] +
+                                   Ec[jb * Pc + ib]);
+                } else {
+                    const int ka = gk >> 1, kb = (gk + 1) >> 1;
+                    const long P2 = (long)Pc * Pc;
+                    v = C(0.125) * (Ec[ka * P2 + ja * Pc + ia] + Ec[ka * P2 + ja * Pc + ib] +
+                                    Ec[ka * P2 + jb * Pc + ia] + Ec[ka * P2 + jb * Pc + ib] +
+                                    Ec[kb * P2 + ja * Pc + ia] + Ec[kb * P2 + ja * Pc + ib] +
+                                    Ec[kb * P2 + jb * Pc + ia] + Ec[kb * P2 + jb * Pc + ib]);
+                }
+                E[pidx(i, j, k, P)] += pf * v;
+            });
+            __syncthreads();
+            tail_for<D>(n, [&](int i, int j, int k) {
+                const long q = pidx(i, j, k, P);
+                R[q] = B[q] - sA * lap(E, q, P);
+            });
+            __syncthreads();
+            tail_for<D>(n, [&](int i, int j, int k) {
+                const long q = pidx(i, j, k, P);
+                E[q] += sW * spai(R, q, P);
+            });
+            __syncthreads();
         }
     } else {
         // W(1,0): each visit of level l < L-1 pre-smooths (from zero on a
@@ -2094,15 +2133,23 @@ template <typename S, typename C, int D>
 hipError_t tail_impl_d(const Tail& t, size_t lds, hipStream_t st) {
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_tail<S, C, D>,
+        hipError_t e = hipFuncSetAttribute((const void*)k_tail<S, C, D, false>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize,
                                            160 * 1024);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void*)k_tail<S, C, D, true>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    hipLaunchKernelGGL((k_tail<S, C, D>), dim3(t.batch), dim3(1024), lds, st,
-                       static_cast<const S*>(t.b), static_cast<S*>(t.e), t.nt, C(t.c[0]),
-                       C(t.c[1]), C(t.c[2]), t.ginv, t.scaled ? 1 : 0, t.N_top, t.wvisits);
+    if (t.wvisits > 0)
+        hipLaunchKernelGGL((k_tail<S, C, D, true>), dim3(t.batch), dim3(1024), lds, st,
+                           static_cast<const S*>(t.b), static_cast<S*>(t.e), t.nt, C(t.c[0]),
+                           C(t.c[1]), C(t.c[2]), t.ginv, t.scaled ? 1 : 0, t.N_top, t.wvisits);
+    else
+        hipLaunchKernelGGL((k_tail<S, C, D, false>), dim3(t.batch), dim3(1024), lds, st,
+                           static_cast<const S*>(t.b), static_cast<S*>(t.e), t.nt, C(t.c[0]),
+                           C(t.c[1]), C(t.c[2]), t.ginv, t.scaled ? 1 : 0, t.N_top, 0);
     return hipGetLastError();
 }
 
