@@ -358,12 +358,13 @@ struct NormReq {
 };
 
 // Where the zero-guess pre-smoother and the restriction run as one kernel:
-// the 2D coarse levels, where its halo costs 1.3x the reads of b and it
-// saves a launch and a pass over b and e (2.7% per 2D V-cycle).  In 3D the
-// halo of a tile that fits LDS (8x4x4 coarse nodes: 3.5x the reads of b,
-// 2.25x the work on e) made it slower than the two marching sweeps on every
-// grid size, the launch-bound ones included.
-bool fuse_zero_restrict(const mg_ctx* h, int l) { return h->d == 2 && l >= 1; }
+// 2D, every level above the tail (a tile kernel; its halo costs 1.3x the
+// reads of b); 3D grids of 200 or more nodes per direction (the
+// restriction's march forming e from b on the fly: 87 against 111 us at
+// n = 255 in FP64, 327 against 478 us at n = 511 with FP32 storage).  On
+// smaller 3D grids its twelve-plane unroll makes short marches slower than
+// the two sweeps (12.5 against 9.6 us at n = 63).
+bool fuse_zero_restrict(const mg_ctx* h, int l) { return h->d == 2 || level_n(h, l) >= 200; }
 
 // Which part of a cycle to enqueue: all of it, only the pre-smoother (with
 // its norm), or everything after the pre-smoother (tmp holds its output).

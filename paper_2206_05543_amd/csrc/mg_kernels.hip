@@ -979,6 +979,275 @@ k_restrict3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ b
 }
 
 // ---------------------------------------------------------------------------
+// 3D zero-guess pre-smoothing fused with the restriction: e = sW K_c b and
+// bc = R (b - sA L e) in one march over fine planes, on the restriction's
+// window (the (2 TXc + 1) x (2 TYc + 1) fine footprint of a coarse column
+// tile).  L e there needs e on the footprint plus a ring of 1 without
+// corners (the "e points"); e at those takes b on a ring of 2 in the plane
+// (LDS, one plane per slot, three slots) and b one plane below and above
+// (registers at the e points, a ring of four planes).  e is formed one plane
+// ahead of the residual, b loaded three planes ahead; e is zero outside the
+// grid and is written on the fine nodes the workgroup owns.  The unroll
+// covers the register rings (4 and 2), the LDS ring (3) and the parity.
+// ---------------------------------------------------------------------------
+template <typename S, typename C, int TXc, int TYc, int NT, int UN>
+__global__ void __launch_bounds__(NT)
+k_zrestrict3d(const S* __restrict__ b, S* __restrict__ e, S* __restrict__ bc, int n, int nc,
+              int tiles_x, int tiles_y, int zchunk, int nchunks, C sA, C sW, C c0, C c1,
+              const double* __restrict__ fin_ps, const double* __restrict__ fin_pm,
+              int fin_count, double* __restrict__ fin_dev, double* __restrict__ fin_host) {
+    constexpr int FX = 2 * TXc + 1, FY = 2 * TYc + 1, NF = FX * FY;
+    constexpr int UX = FX + 2, UY = FY + 2, NU = UX * UY;  // e window
+    constexpr int BX = FX + 4, BY = FY + 4, NB = BX * BY;  // b window
+    constexpr int M = (NF + NT - 1) / NT;
+    constexpr int NR2 = 2 * FX + 2 * FY;  // ring-1 e points (no corners)
+    constexpr int NX = NR2 + 4;           // b beyond the e points: ring 2, ring-1 corners
+    constexpr int RP = FX + 1, RSZ = RP + M * NT + FX + 1;
+    constexpr int UD = NU + UX, USZ = NU + 2 * UX + 65;
+    constexpr int BD = NB + BX, BSZ = NB + 2 * BX + 65;
+    static_assert(NX <= NT && TXc * TYc <= NT, "ring and coarse columns fit the workgroup");
+    static_assert(UN % 12 == 0, "unroll covers the rings of 4, 3 and 2 planes");
+    __shared__ C uL[2][USZ];
+    __shared__ C bL[3][BSZ];
+    __shared__ C rL[2][RSZ];
+    __shared__ double red[NT / 64];
+    if (fin_count > 0 && blockIdx.x == 0 && blockIdx.y == 0)
+        finalize_norm<NT>(fin_ps, fin_pm, fin_count, fin_dev, fin_host, red);
+
+    const int total = tiles_x * tiles_y * nchunks;
+    const int lg = xcd_remap(blockIdx.x, total);
+    const int tx = lg % tiles_x, ty = (lg / tiles_x) % tiles_y,
+              ch = lg / (tiles_x * tiles_y);
+    const long plane = (long)n * n, cplane = (long)nc * nc;
+    b += (long)blockIdx.y * plane * n;
+    e += (long)blockIdx.y * plane * n;
+    bc += (long)blockIdx.y * cplane * nc;
+    const int cx0 = tx * TXc, cy0 = ty * TYc;
+    const int Z0 = ch * zchunk, Z1 = min(Z0 + zchunk, nc);
+    const int fx0 = 2 * cx0, fy0 = 2 * cy0;
+    // fine nodes owned: [f0, 2 (c0 + T)) per direction, the last tile up to n
+    const int ox1 = cx0 + TXc >= nc ? n : fx0 + 2 * TXc;
+    const int oy1 = cy0 + TYc >= nc ? n : fy0 + 2 * TYc;
+    const int t = threadIdx.x;
+    const int lane = t & 63;
+
+    // interior e points: window index, b-window index, global offset, flags
+    int li[M], lbi[M];
+    unsigned gi[M];
+    bool val[M], own[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const int i = t + m * NT;
+        const bool inr = i < NF;
+        const int lx = i % FX, ly = i / FX;
+        const int gx = fx0 + lx, gy = fy0 + ly;
+        val[m] = inr && gx < n && gy < n;
+        own[m] = inr && gx < ox1 && gy < oy1;
+        li[m] = inr ? (ly + 1) * UX + lx + 1 : UD + lane;
+        lbi[m] = inr ? (ly + 2) * BX + lx + 2 : BD + lane;
+        gi[m] = val[m] ? (unsigned)((gy * n + gx) * (int)sizeof(S)) : kOob;
+    }
+    // ring-1 e point (no corners) of threads t < NR2
+    int l1 = UD + lane, lb1 = BD + lane;
+    unsigned g1 = kOob;
+    bool v1 = false;
+    if (t < NR2) {
+        int ux, uy;
+        if (t < FX) { ux = 1 + t; uy = 0; }
+        else if (t < 2 * FX) { ux = 1 + t - FX; uy = UY - 1; }
+        else if (t < 2 * FX + FY) { ux = 0; uy = 1 + t - 2 * FX; }
+        else { ux = UX - 1; uy = 1 + t - 2 * FX - FY; }
+        const int gx = fx0 - 1 + ux, gy = fy0 - 1 + uy;
+        l1 = uy * UX + ux;
+        lb1 = (uy + 1) * BX + ux + 1;
+        v1 = gx >= 0 && gx < n && gy >= 0 && gy < n;
+        if (v1) g1 = (unsigned)((gy * n + gx) * (int)sizeof(S));
+    }
+    // b point beyond the e points of threads t < NX: ring 2 without corners
+    // (where the ring-1 e points reach) and the four ring-1 corners
+    int lbx = BD + lane;
+    unsigned gxo = kOob;
+    if (t < NX) {
+        int bx, by;
+        if (t < FX) { bx = 2 + t; by = 0; }
+        else if (t < 2 * FX) { bx = 2 + t - FX; by = BY - 1; }
+        else if (t < 2 * FX + FY) { bx = 0; by = 2 + t - 2 * FX; }
+        else if (t < NR2) { bx = BX - 1; by = 2 + t - 2 * FX - FY; }
+        else {
+            const int c = t - NR2;
+            bx = (c & 1) ? BX - 2 : 1;
+            by = (c & 2) ? BY - 2 : 1;
+        }
+        const int gx = fx0 - 2 + bx, gy = fy0 - 2 + by;
+        lbx = by * BX + bx;
+        if (gx >= 0 && gx < n && gy >= 0 && gy < n) gxo = (unsigned)((gy * n + gx) * (int)sizeof(S));
+    }
+    S rbi[4][M], rb1[4], rbx[2];
+    auto issue = [&](int p, int q4, int q2) {
+        const rsrc_t r = line_rsrc(b, (long)p * plane, plane, p >= 0 && p < n);
+#pragma unroll
+        for (int m = 0; m < M; ++m) rbi[q4][m] = bload<S>(r, gi[m]);
+        rb1[q4] = bload<S>(r, g1);
+        rbx[q2] = bload<S>(r, gxo);
+    };
+    // e at the e points of plane p from the b window in slot B and b below
+    // (slot dn) and above (slot up) in registers
+    auto form_e = [&](int p, const C* B, int dn, int up, C* ei, C& e1) {
+        const bool pin = p >= 0 && p < n;
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const int q = lbi[m];
+            const C f = B[q - 1] + B[q + 1] + B[q - BX] + B[q + BX] + cvt<C>(rbi[dn][m]) +
+                        cvt<C>(rbi[up][m]);
+            const C v = sW * (c0 * B[q] + c1 * f);
+            ei[m] = (pin && val[m]) ? v : C(0);
+        }
+        const int q = lb1;
+        const C f = B[q - 1] + B[q + 1] + B[q - BX] + B[q + BX] + cvt<C>(rb1[dn]) + cvt<C>(rb1[up]);
+        const C v = sW * (c0 * B[q] + c1 * f);
+        e1 = (pin && v1) ? v : C(0);
+    };
+    auto put_b = [&](C* B, int q4, int q2) {
+#pragma unroll
+        for (int m = 0; m < M; ++m) B[lbi[m]] = cvt<C>(rbi[q4][m]);
+        B[lb1] = cvt<C>(rb1[q4]);
+        B[lbx] = cvt<C>(rbx[q2]);
+    };
+    auto store_e = [&](int p, const C* ei) {
+        const bool pown = p >= 2 * Z0 && p < n && (p < 2 * Z1 || Z1 == nc);
+        const rsrc_t r = line_rsrc(e, (long)p * plane, plane, pown);
+#pragma unroll
+        for (int m = 0; m < M; ++m) bstore<false>(static_cast<S>(ei[m]), r, own[m] ? gi[m] : kOob);
+    };
+    const int cx = t % TXc, cy = t / TXc;
+    const bool cin = t < TXc * TYc;
+    const unsigned cgb = (cin && cx0 + cx < nc && cy0 + cy < nc)
+                             ? (unsigned)(((cy0 + cy) * nc + cx0 + cx) * (int)sizeof(S))
+                             : kOob;
+    const int cq = RP + (cin ? (2 * cy + 1) * FX + 2 * cx + 1 : FX + 1);
+
+    C um1[M], u0[M], up1[M];
+    C ur0 = 0, urp1 = 0, acc = 0;
+    const int f0 = 2 * Z0, f1 = 2 * Z1;
+    {
+        // planes f0-2 .. f0+2; register slot of plane p is (p - f0) mod 4
+        // (mod 2 for the b beyond the e points), LDS slot (p - f0) mod 3
+        S tmi[2][M], tm1[2], tx0, tx1;
+        {
+            const rsrc_t r0 = line_rsrc(b, (long)(f0 - 2) * plane, plane, f0 - 2 >= 0);
+            const rsrc_t r1 = line_rsrc(b, (long)(f0 - 1) * plane, plane, f0 - 1 >= 0);
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                tmi[0][m] = bload<S>(r0, gi[m]);
+                tmi[1][m] = bload<S>(r1, gi[m]);
+            }
+            tm1[0] = bload<S>(r0, g1);
+            tm1[1] = bload<S>(r1, g1);
+        }
+        issue(f0, 0, 0);
+        tx0 = rbx[0];
+        issue(f0 + 1, 1, 1);
+        tx1 = rbx[1];
+        issue(f0 + 2, 2, 0);
+        // LDS: slot 2 <- plane f0-1 (e points only), slot 0 <- f0, slot 1 <- f0+1
+#pragma unroll
+        for (int m = 0; m < M; ++m) bL[2][lbi[m]] = cvt<C>(tmi[1][m]);
+        bL[2][lb1] = cvt<C>(tm1[1]);
+#pragma unroll
+        for (int m = 0; m < M; ++m) bL[0][lbi[m]] = cvt<C>(rbi[0][m]);
+        bL[0][lb1] = cvt<C>(rb1[0]);
+        bL[0][lbx] = cvt<C>(tx0);
+#pragma unroll
+        for (int m = 0; m < M; ++m) bL[1][lbi[m]] = cvt<C>(rbi[1][m]);
+        bL[1][lb1] = cvt<C>(rb1[1]);
+        bL[1][lbx] = cvt<C>(tx1);
+        __syncthreads();
+        // e(f0 - 1) at the interior: b below from the prologue registers,
+        // above = plane f0 (slot 0)
+        {
+            const bool pin = f0 - 1 >= 0;
+            const C* B = bL[2];
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                const int q = lbi[m];
+                const C f = B[q - 1] + B[q + 1] + B[q - BX] + B[q + BX] + cvt<C>(tmi[0][m]) +
+                            cvt<C>(rbi[0][m]);
+                const C v = sW * (c0 * B[q] + c1 * f);
+                um1[m] = (pin && val[m]) ? v : C(0);
+            }
+        }
+        // e(f0) at the e points: below = plane f0-1 (prologue), above = f0+1
+        {
+            const C* B = bL[0];
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                const int q = lbi[m];
+                const C f = B[q - 1] + B[q + 1] + B[q - BX] + B[q + BX] + cvt<C>(tmi[1][m]) +
+                            cvt<C>(rbi[1][m]);
+                const C v = sW * (c0 * B[q] + c1 * f);
+                u0[m] = val[m] ? v : C(0);
+            }
+            const int q = lb1;
+            const C f = B[q - 1] + B[q + 1] + B[q - BX] + B[q + BX] + cvt<C>(tm1[1]) +
+                        cvt<C>(rb1[1]);
+            const C v = sW * (c0 * B[q] + c1 * f);
+            ur0 = v1 ? v : C(0);
+        }
+#pragma unroll
+        for (int m = 0; m < M; ++m) uL[0][li[m]] = u0[m];
+        uL[0][l1] = ur0;
+        store_e(f0, u0);
+    }
+    auto step = [&](int s, auto kc) {
+        constexpr int k = decltype(kc)::k;  // (s - f0) % UN
+        constexpr int cu = k & 1, nx = (k + 1) & 1;
+        __syncthreads();
+        issue(s + 3, (k + 3) % 4, (k + 3) % 2);
+        // e of plane s + 1 (one plane ahead of the residual)
+        form_e(s + 1, bL[(k + 1) % 3], k % 4, (k + 2) % 4, up1, urp1);
+        // residual of fine plane s on the window
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const C* U = uL[cu];
+            const int q = li[m];
+            const C lap = C(6) * u0[m] - U[q - 1] - U[q + 1] - U[q - UX] - U[q + UX] - um1[m] -
+                          up1[m];
+            const C r = cvt<C>(rbi[k % 4][m]) - sA * lap;
+            rL[cu][RP + t + m * NT] = val[m] ? r : C(0);
+        }
+        const int f = s - 1;  // fine plane whose residual is reduced now
+        if (f >= f0 && f <= f1) {
+            const C* R = rL[nx];
+            const int q = cq;
+            const C xs = C(0.25) * R[q] +
+                         C(0.125) * (R[q - 1] + R[q + 1] + R[q - FX] + R[q + FX]) +
+                         C(0.0625) * (R[q - FX - 1] + R[q - FX + 1] + R[q + FX - 1] + R[q + FX + 1]);
+            if ((k & 1) == 1) {  // f - f0 even
+                if (f > f0) {
+                    acc += C(0.25) * xs;
+                    const rsrc_t ro = line_rsrc(bc, (long)(f / 2 - 1) * cplane, cplane, true);
+                    bstore<false>(static_cast<S>(acc), ro, cgb);
+                }
+                acc = C(0.25) * xs;
+            } else {
+                acc += C(0.5) * xs;
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < M; ++m) uL[nx][li[m]] = up1[m];
+        uL[nx][l1] = urp1;
+        store_e(s + 1, up1);
+        put_b(bL[(k + 2) % 3], (k + 2) % 4, k % 2);
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            um1[m] = u0[m];
+            u0[m] = up1[m];
+        }
+    };
+    march<UN>(f0, f1 + 1, step);
+}
+
+// ---------------------------------------------------------------------------
 // 2D fused residual + full-weighting restriction: a strip of TXc coarse
 // columns (window of 2 TXc + 1 fine columns owned by NT lanes), marching
 // over fine rows.
@@ -2238,10 +2507,33 @@ hipError_t launch_restrict(Prec p, const Sweep& s, hipStream_t st) {
     }
 }
 
+template <typename S, typename C, int TXc, int TYc, int NT>
+hipError_t launch_zrestrict3d(const Sweep& s, int want, int minc, hipStream_t st) {
+    const int n = s.n, nc = (n + 1) / 2 - 1;
+    const int tx = cdiv(nc, TXc), ty = cdiv(nc, TYc);
+    const int zc = pick_chunk(nc, tx * ty, want, minc);
+    const int nch = cdiv(nc, zc);
+    hipLaunchKernelGGL((k_zrestrict3d<S, C, TXc, TYc, NT, 12>), dim3(tx * ty * nch, s.batch),
+                       dim3(NT), 0, st, static_cast<const S*>(s.b), static_cast<S*>(s.out),
+                       static_cast<S*>(s.out_c), n, nc, tx, ty, zc, nch, C(s.sA), C(s.sW),
+                       C(s.c[0]), C(s.c[1]), s.fin_ps, s.fin_pm, s.fin_count, s.fin_dev,
+                       s.fin_host);
+    return hipGetLastError();
+}
+
 template <typename S, typename C>
 hipError_t zsr_impl(const Sweep& s, hipStream_t st) {
     const int n = s.n, nc = (n + 1) / 2 - 1;
-    if (s.d != 2 || nc < 1 || !s.out_c) return hipErrorInvalidValue;
+    if (nc < 1 || !s.out_c) return hipErrorInvalidValue;
+    if (s.d == 3) {
+        if ((long)n * n * (long)sizeof(S) > 0x7fffffffL) return hipErrorInvalidValue;
+        // the restriction's shapes
+        if constexpr (sizeof(S) < 8) {
+            if (n >= 200) return launch_zrestrict3d<S, C, 64, 8, 768>(s, 512, 8, st);
+        }
+        if (n >= 200) return launch_zrestrict3d<S, C, 32, 8, 576>(s, 256, 8, st);
+        return launch_zrestrict3d<S, C, 32, 4, 320>(s, 512, 1, st);
+    }
     const S* b = static_cast<const S*>(s.b);
     S* e = static_cast<S*>(s.out);
     S* bc = static_cast<S*>(s.out_c);
