@@ -178,6 +178,16 @@ int mg_vcycle_adjoint(mg_handle_t h, const double* b, const double* u_in,
 int mg_sweep(mg_handle_t h, int op, int level, int prec, const void* u, const void* b,
              void* out, void* stream);
 
+/* Zero-guess pre-smoothing fused with the restriction on level `level` in
+ * storage precision `prec` (as mg_sweep): e = M b on the level and bc = R (b
+ * - A e) on level+1, in one kernel (the kernel mg_solve and mg_vcycle use
+ * for zero-guess cycles; Section 4, V-cycle with a zero initial guess on the
+ * coarse levels).  b, e: the level's shape; bc: level+1's shape.  Errors:
+ * MG_EINVAL for a null handle or pointer, a bad precision, or no coarser
+ * level. */
+int mg_sweep_zero_restrict(mg_handle_t h, int level, int prec, const void* b, void* e, void* bc,
+                           void* stream);
+
 /* Fused post-smoothing sweep with the coarse-grid correction: with
  * v = u + P ec (ec on level + 1; in the scaled low-precision storage the
  * correction carries the factor 4 between levels), out = v + M (b - A v).

@@ -57,6 +57,7 @@ def lib():
         L.mg_sweep.argtypes = [vp, i, i, i, vp, vp, vp, vp]
         L.mg_coarse_cycle.argtypes = [vp, i, i, vp, vp, vp]
         L.mg_sweep_correct.argtypes = [vp, i, i, vp, vp, vp, vp, vp]
+        L.mg_sweep_zero_restrict.argtypes = [vp, i, i, vp, vp, vp, vp]
         L.mg_residual_norm.argtypes = [vp, vp, vp, dp, vp]
         L.mg_get_timing.argtypes = [vp, i, i, dp, ctypes.POINTER(i)]
         L.mg_reset_timing.argtypes = [vp]
@@ -200,6 +201,13 @@ class Multigrid:
             self._field(ec, level + 1, dt, "ec"), self._field(b, level, dt, "b"),
             self._field(out, level, dt, "out"), _stream()))
         return out
+
+    def sweep_zero_restrict(self, level, prec, b, e, bc):
+        dt = STORAGE[PREC[prec]]
+        _check(lib().mg_sweep_zero_restrict(
+            self._h, level, PREC[prec], self._field(b, level, dt, "b"),
+            self._field(e, level, dt, "e"), self._field(bc, level + 1, dt, "bc"), _stream()))
+        return e, bc
 
     def set_inner_cycles(self, m):
         self.set_option(OPT_INNER_CYCLES, m)

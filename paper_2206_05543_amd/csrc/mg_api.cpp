@@ -703,6 +703,25 @@ int mg_sweep(mg_handle_t h, int op, int level, int prec, const void* u, const vo
     return MG_OK;
 }
 
+int mg_sweep_zero_restrict(mg_handle_t h, int level, int prec, const void* b, void* e, void* bc,
+                           void* stream) {
+    if (check_handle(h)) return MG_EINVAL;
+    if (prec < MG_PREC_FP64 || prec > MG_PREC_FP16_IR) return fail(MG_EINVAL, "bad precision");
+    if (level < 0 || level >= h->L - 1) return fail(MG_EINVAL, "bad level (no coarser level)");
+    if (!b || !e || !bc) return fail(MG_EINVAL, "null field pointer");
+    const Prec p = prec == MG_PREC_FP64 ? P64 : (prec == MG_PREC_FP32_IR ? P32 : P16);
+    Hier H;
+    H.p = p;
+    H.scaled = p != P64;
+    Sweep s = make_sweep(h, H, level);
+    s.b = b;
+    s.out = e;
+    s.out_c = bc;
+    const hipError_t err = launch_zero_smooth_restrict(p, s, (hipStream_t)stream);
+    if (err != hipSuccess) return fail(MG_EHIP, std::string("launch: ") + hipGetErrorString(err));
+    return MG_OK;
+}
+
 int mg_sweep_correct(mg_handle_t h, int level, int prec, const void* u, const void* ec,
                      const void* b, void* out, void* stream) {
     if (check_handle(h)) return MG_EINVAL;

@@ -111,6 +111,38 @@ def test_restrict_parity(d, N, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32_ir", "fp16_ir"])
+@pytest.mark.parametrize("d,N,level", [(2, n, 0) for n in CASES_2D] + [(2, 1024, 1)] +
+                         [(3, n, 0) for n in CASES_3D + [256]] + [(3, 256, 1)])
+def test_zero_smooth_restrict_parity(d, N, level, prec):
+    # the fused zero-guess pre-smoother + restriction (2D tile kernel; 3D
+    # march, with the large-grid shapes at N = 256 level 0): e = M b and
+    # bc = R (b - A e), against the oracle's smoother and restriction
+    need_gpu()
+    Nl = N >> level
+    rng = np.random.default_rng(300 + N + level)
+    shp, shc = (Nl - 1,) * d, (Nl // 2 - 1,) * d
+    c = _coeffs(d)
+    sig = _sigma(prec, Nl)
+    b = _roundtrip(_rand(rng, shp, 1.0 if prec != "fp64" else Nl * Nl), prec)
+    say("zero-smooth-restrict", d, N, level, prec)
+    with make_mg(N, d, c) as mg:
+        e = torch.empty(shp, dtype=_tdt(prec), device="cuda")
+        bc = torch.empty(shc, dtype=_tdt(prec), device="cuda")
+        mg.sweep_zero_restrict(level, prec, dev(b, _tdt(prec)), e, bc)
+        torch.cuda.synchronize()
+        got_e, got_c = host(e), host(bc)
+    e_true = O.apply_W(d, Nl, c, b)
+    want_e = e_true * sig
+    want_c = O.restrict(d, Nl, O.residual(d, Nl, e_true, b))
+    h2 = 1.0 / (Nl * Nl)
+    tol_e = _tol(prec, h2 * sig * np.abs(b).max(), out_mag=np.abs(want_e).max())
+    tol_c = _tol(prec, np.abs(b).max(), 4 * d * Nl * Nl / sig * np.abs(want_e).max(),
+                 out_mag=np.abs(want_c).max())
+    assert np.max(np.abs(got_e - want_e)) <= tol_e
+    assert np.max(np.abs(got_c - want_c)) <= tol_c
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_ir", "fp16_ir"])
 @pytest.mark.parametrize("d,N", [(2, n) for n in CASES_2D] + [(3, n) for n in CASES_3D])
 def test_prolong_parity(d, N, prec):
     need_gpu()
