@@ -2235,8 +2235,6 @@ inline int pick_chunk(int n, int tiles, int want, int minc) {
     return ch;
 }
 
-constexpr int kWantBlocks = 1024;
-
 // the fused-correction sweep assumes every chunk starts on an even plane
 inline int even_chunk(int c) { return c + (c & 1); }
 
