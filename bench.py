@@ -8,7 +8,8 @@ second per V-cycle over the pair: sum(unknowns x cycles) / sum(solve time).
 
 Also reported: per-workload rates, the roofline of the dominant kernel (the
 fine-level fused residual + smoother sweep, timed live with HIP events on the
-launch stream), the time to 1e-10 of the 3D N=512 noisy problem in FP64 and
+launch stream), per-level kernel times and GB/s (extra solves after the timed
+region, every launch timed), the time to 1e-10 of the 3D N=512 noisy problem in FP64 and
 with FP32 / FP16 V-cycles inside FP64 refinement, and the CPU oracle timed on
 a bounded sample of the same workloads (single thread).
 
@@ -65,6 +66,53 @@ def hbm_traffic(name, kind):
     return fetch * (cbytes / (cfetch * 1024.0)) * 1024.0 + write * (cbytes / (cwrite * 1024.0)) * 1024.0
 
 WORKLOADS = {"poisson2d_n4096": (2, 4096), "poisson3d_n256": (3, 256)}
+
+# algorithmic FP64 bytes per fine point of a level, per timed kernel kind
+# (the tail is reported by time only)
+LEVEL_KINDS = ("smooth", "smooth_zero", "restrict", "zero_smooth_restrict", "smooth_correct",
+               "prolong", "tail")
+
+
+def level_bytes_per_pt(kind, d):
+    c = 8.0 / 2 ** d  # one coarse value per 2^d fine points
+    return {"smooth": 24.0, "smooth_zero": 16.0, "restrict": 16.0 + c,
+            "zero_smooth_restrict": 16.0 + c, "smooth_correct": 24.0 + c,
+            "prolong": 16.0 + c}.get(kind)
+
+
+def per_level(probs, tol, solves=2):
+    """Per-level kernel times and algorithmic GB/s (fraction of 8 TB/s) from
+    the library's HIP events on every launch (timing mode 2), over extra
+    solves run after the timed region."""
+    from paper_2206_05543_amd._lib import OPT_TIMING
+    out = {}
+    for name, P in probs.items():
+        mg, d, N = P["mg"], P["d"], P["N"]
+        mg.set_option(OPT_TIMING, 2)
+        mg.reset_timing()
+        for _ in range(solves):
+            P["u"].copy_(P["u0"])
+            mg.solve(P["b"], P["u"], tol=tol)
+        rows = []
+        for lev in range(mg.num_levels):
+            n = (N >> lev) - 1
+            pts = n ** d
+            for kind in LEVEL_KINDS:
+                ms, cnt = mg.timing(kind, lev)
+                if not cnt:
+                    continue
+                avg_us = ms / cnt * 1e3
+                r = {"level": lev, "n": n, "kind": kind, "launches_per_solve": cnt / solves,
+                     "avg_us": avg_us}
+                bpp = level_bytes_per_pt(kind, d)
+                if bpp is not None:
+                    gbs = bpp * pts / (avg_us * 1e-6) / 1e9
+                    r["GBps"] = gbs
+                    r["frac_of_peak"] = gbs / HBM_PEAK_GBS
+                rows.append(r)
+        mg.set_option(OPT_TIMING, 1)
+        out[name] = rows
+    return out
 
 
 def parse():
@@ -187,6 +235,7 @@ def main():
                      "algorithmic_bytes_per_launch": byt,
                      "traffic_GBps": traffic / (avg_us * 1e-6) / 1e9 if traffic else None},
     }
+    line["per_level"] = per_level(probs, a.tol)
     for P in probs.values():
         P["mg"].close()
     del probs
