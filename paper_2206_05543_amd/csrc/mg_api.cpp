@@ -812,7 +812,7 @@ static int solve64(mg_ctx* h, const double* b, double* u, double tol, mg_stats* 
         // that parity; it is taken only far from convergence, where u_k
         // cannot be the answer, once the rate predicts K.
         bool inplace = false;
-        if (!gate && !flipped && k >= 2 && hist[k - 2] > 0.0) {
+        if (!gate && !flipped && k >= 2 && k < h->max_cycles && hist[k - 2] > 0.0) {
             const double q = hist[k - 1] / hist[k - 2];
             if (q > 0.0 && q < 0.9 && hist[k - 1] * q >= kFlipMargin * tol * r0) {
                 const int K = k - 1 + (int)std::ceil(std::log(tol * r0 / hist[k - 1]) /
@@ -852,9 +852,10 @@ static int solve64(mg_ctx* h, const double* b, double* u, double tol, mg_stats* 
         if (k == 0) r0 = nk;
         hist.push_back(nk);
         rk = nk;
-        if (inplace && (nk <= tol * r0 || k >= h->max_cycles)) {
+        if (inplace && nk <= tol * r0) {
             // the prediction failed: u_k was overwritten by u_{k+1}, which
-            // is returned with its own residual
+            // is returned with its own residual (an in-place cycle is never
+            // the last one the cycle limit allows)
             int np = 0;
             const double N = h->N;
             HIPCHK(launch_residual_norm(h->d, level_n(h, 0), h->batch, X, b, N * N, h->psum,

@@ -187,3 +187,56 @@ def test_refinement_stops_across_tolerances(prec):
             assert abs(st["rk"] - rk) <= 1e-6 * rk + 1e-14 * r0
             # one step earlier would not have met the tolerance
             assert st["history"][-2] > tol * r0 if len(st["history"]) > 1 else True
+
+
+def _oracle_batched_history(d, N, c, u0, b, kmax):
+    # the library stops a batched solve on the norm over the whole batch:
+    # iterate each entry with the oracle cycle and combine the norms
+    us = [u0[s].copy() for s in range(u0.shape[0])]
+    iters, hist = [], []
+    for k in range(kmax + 1):
+        iters.append([u.copy() for u in us])
+        hist.append(np.sqrt(sum(O.norm2(O.residual(d, N, u, b[s])) ** 2
+                                for s, u in enumerate(us))))
+        us = [O.vcycle(d, N, c, u, b[s]) for s, u in enumerate(us)]
+    return iters, hist
+
+
+@pytest.mark.parametrize("d,N,batch", [(2, 64, 3), (3, 32, 2)])
+@pytest.mark.parametrize("tol", [1e-4, 1e-7, 1e-10])
+def test_batched_solve_stops_on_the_batch_norm(d, N, batch, tol):
+    need_gpu()
+    rng = np.random.default_rng(40 + N + batch)
+    shp = (batch,) + (N - 1,) * d
+    u0 = rng.uniform(-1, 1, shp)
+    b = rng.standard_normal(shp) * N
+    iters, hist = _oracle_batched_history(d, N, _c(d), u0, b, 14)
+    k_or = next(k for k, h in enumerate(hist) if h <= tol * hist[0])
+    say("batched-solve", d, N, batch, tol)
+    with make_mg(N, d, _c(d), batch=batch) as mg:
+        u = dev(u0)
+        st = mg.solve(dev(b), u, tol=tol)
+        got = host(u)
+    assert st["code"] == 0 and st["cycles"] == k_or
+    assert np.allclose(st["history"], hist[:k_or + 1], rtol=1e-8, atol=1e-13 * hist[0])
+    want = np.stack(iters[k_or])
+    assert np.max(np.abs(got - want)) <= 1e-10 * np.abs(want).max()
+
+
+@pytest.mark.parametrize("maxc", [1, 2, 3, 5])
+def test_cycle_limit_returns_the_last_iterate(maxc):
+    # MG_ENOCONV after max_cycles: u holds u_maxc, whatever the solve loop's
+    # gating or in-place cycles did on the way
+    need_gpu()
+    d, N = 2, 64
+    p = workload("poisson2d_n64")
+    iters, hist = _oracle_batched_history(d, N, _c(d), p["u0"][None], p["b"][None], maxc)
+    say("cycle-limit", maxc)
+    with make_mg(N, d, _c(d), max_cycles=maxc) as mg:
+        u = dev(p["u0"])
+        st = mg.solve(dev(p["b"]), u, tol=1e-14)
+        got = host(u)
+    assert st["code"] == -3 and st["cycles"] == maxc
+    assert np.allclose(st["history"], hist, rtol=1e-8, atol=1e-13 * hist[0])
+    want = iters[maxc][0]
+    assert np.max(np.abs(got - want)) <= 1e-10 * np.abs(want).max()
