@@ -75,3 +75,45 @@ def test_mixed_final_error_matches_fp64(d, N, prec):
             assert st["code"] == 0
             err[pr] = np.linalg.norm(host(u) - ref) / np.linalg.norm(ref)
     assert err[prec] <= 2.5 * err["fp64"] + 1e-12, err
+
+
+@pytest.mark.parametrize("prec", ["fp32_ir", "fp16_ir"])
+def test_batched_refinement(prec):
+    # the refinement loop stops on the norm over the whole batch; every
+    # entry's residual, recomputed by the oracle, is within that bound
+    need_gpu()
+    d, N, batch = 3, 32, 3
+    rng = np.random.default_rng(61)
+    shp = (batch,) + (N - 1,) * d
+    u0 = rng.uniform(-1, 1, shp)
+    b = rng.standard_normal(shp) * N
+    say("mixed-batched", prec)
+    with make_mg(N, d, np.array(M7), batch=batch, precision=prec) as mg:
+        u = dev(u0)
+        st = mg.solve(dev(b), u, tol=1e-10)
+        got = host(u)
+    assert st["code"] == 0
+    r0 = np.sqrt(sum(O.norm2(O.residual(d, N, u0[s], b[s])) ** 2 for s in range(batch)))
+    rk = np.sqrt(sum(O.norm2(O.residual(d, N, got[s], b[s])) ** 2 for s in range(batch)))
+    assert abs(st["r0"] - r0) <= 1e-10 * r0
+    assert rk <= 1.0001e-10 * r0
+    assert abs(st["rk"] - rk) <= 1e-6 * rk + 1e-14 * r0
+
+
+@pytest.mark.parametrize("prec", ["fp32_ir", "fp16_ir"])
+@pytest.mark.parametrize("maxc", [1, 2])
+def test_refinement_step_limit(prec, maxc):
+    # MG_ENOCONV after max_cycles refinement steps; u holds that step's
+    # iterate, whose residual the library reports
+    need_gpu()
+    d, N = 2, 256
+    p = poisson_problem(d, N, seed=62, n_modes=8, kmax=N // 4)
+    say("mixed-limit", prec, maxc)
+    with make_mg(N, d, np.array(M9), precision=prec, max_cycles=maxc) as mg:
+        u = dev(p["u0"])
+        st = mg.solve(dev(p["b"]), u, tol=1e-30)
+        got = host(u)
+    assert st["code"] == -3 and st["cycles"] == maxc
+    rk = O.norm2(O.residual(d, N, got, p["b"]))
+    assert abs(st["rk"] - rk) <= 1e-6 * rk
+    assert len(st["history"]) == maxc + 1
