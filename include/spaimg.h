@@ -82,7 +82,10 @@ extern "C" {
 
 /* precisions for MG_OPT_PRECISION */
 #define MG_PREC_FP64 0      /* FP64 V-cycles                                  */
-#define MG_PREC_FP32_IR 1   /* FP64 iterative refinement around FP32 V-cycles */
+#define MG_PREC_FP32_IR 1   /* FP64 iterative refinement around FP32 V-cycles;
+                               the first step stores b - A u_0 unscaled in
+                               FP32, so its entries must stay below ~3e38
+                               (beyond that mg_solve returns MG_ENONFINITE)  */
 #define MG_PREC_FP16_IR 2   /* ... around V-cycles with FP16 storage, FP32
                                arithmetic and per-level power-of-two scaling  */
 

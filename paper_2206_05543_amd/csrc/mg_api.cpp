@@ -814,7 +814,9 @@ static int solve64(mg_ctx* h, const double* b, double* u, double tol, mg_stats* 
         bool inplace = false;
         if (!gate && !flipped && k >= 2 && k < h->max_cycles && hist[k - 2] > 0.0) {
             const double q = hist[k - 1] / hist[k - 2];
-            if (q > 0.0 && q < 0.9 && hist[k - 1] * q >= kFlipMargin * tol * r0) {
+            if (tol * r0 > 0.0 && q > 0.0 && q < 0.9 &&
+                hist[k - 1] * q >= kFlipMargin * tol * r0) {
+                // finite: 0 < tol r0 < hist[k-1] and 0 < q < 0.9
                 const int K = k - 1 + (int)std::ceil(std::log(tol * r0 / hist[k - 1]) /
                                                      std::log(q));
                 const bool lands_in_u = ((K - k) % 2 == 0) == (X == u);

@@ -240,3 +240,18 @@ def test_cycle_limit_returns_the_last_iterate(maxc):
     assert np.allclose(st["history"], hist, rtol=1e-8, atol=1e-13 * hist[0])
     want = iters[maxc][0]
     assert np.max(np.abs(got - want)) <= 1e-10 * np.abs(want).max()
+
+
+def test_zero_tolerance_runs_to_the_cycle_limit():
+    # tol = 0 is a valid request: the solve runs max_cycles cycles and
+    # reports MG_ENOCONV with u = u_maxc
+    need_gpu()
+    p = workload("poisson2d_n64")
+    iters, hist = _oracle_batched_history(2, 64, _c(2), p["u0"][None], p["b"][None], 6)
+    say("zero-tol")
+    with make_mg(64, 2, _c(2), max_cycles=6) as mg:
+        u = dev(p["u0"])
+        st = mg.solve(dev(p["b"]), u, tol=0.0)
+        got = host(u)
+    assert st["code"] == -3 and st["cycles"] == 6
+    assert np.max(np.abs(got - iters[6][0])) <= 1e-10 * np.abs(iters[6][0]).max()
