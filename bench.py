@@ -131,7 +131,7 @@ def parse():
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1 "
                           "(the multi-GPU decomposition is a design, not code)"}))
         sys.exit(2)
     import torch
