@@ -62,7 +62,8 @@ extern "C" {
 #define MG_OPT_MAX_CYCLES 3 /* cycle limit of mg_solve, 1..10000 (default 100) */
 #define MG_OPT_TAIL_N 4     /* largest coarse grid (intervals, power of two,
                                4..64 in 2D, 4..16 in 3D) solved by the
-                               single-workgroup LDS tail kernel; 0 = default   */
+                               single-workgroup LDS tail kernel; 0 = default:
+                               64 in 2D (32 for W(1,0) cycles), 16 in 3D      */
 #define MG_OPT_TIMING 5     /* 0 off; 1 time the fine-level post-smoother
                                (with the fused correction) with HIP events;
                                2 time every kernel of every level              */
