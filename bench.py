@@ -69,14 +69,15 @@ WORKLOADS = {"poisson2d_n4096": (2, 4096), "poisson3d_n256": (3, 256)}
 
 # algorithmic FP64 bytes per fine point of a level, per timed kernel kind
 # (the tail is reported by time only)
-LEVEL_KINDS = ("smooth", "smooth_zero", "restrict", "zero_smooth_restrict", "smooth_correct",
-               "prolong", "tail")
+LEVEL_KINDS = ("smooth", "smooth_zero", "restrict", "smooth_restrict", "zero_smooth_restrict",
+               "smooth_correct", "prolong", "tail")
 
 
 def level_bytes_per_pt(kind, d):
     c = 8.0 / 2 ** d  # one coarse value per 2^d fine points
     return {"smooth": 24.0, "smooth_zero": 16.0, "restrict": 16.0 + c,
-            "zero_smooth_restrict": 16.0 + c, "smooth_correct": 24.0 + c,
+            "smooth_restrict": 24.0 + c, "zero_smooth_restrict": 16.0 + c,
+            "smooth_correct": 24.0 + c,
             "prolong": 16.0 + c}.get(kind)
 
 

@@ -106,7 +106,9 @@ extern "C" {
 #define MG_TIME_RESIDUAL 6
 #define MG_TIME_SMOOTH_CORRECT 7  /* post-smoothing with the fused correction */
 #define MG_TIME_ZERO_SMOOTH_RESTRICT 8  /* zero-guess pre-smoothing fused with
-                                           the restriction (2D coarse levels) */
+                                           the restriction                    */
+#define MG_TIME_SMOOTH_RESTRICT 9  /* pre-smoothing from a nonzero iterate
+                                      fused with the restriction (2D)         */
 
 typedef struct mg_ctx* mg_handle_t;
 
@@ -191,6 +193,17 @@ int mg_sweep(mg_handle_t h, int op, int level, int prec, const void* u, const vo
  * level. */
 int mg_sweep_zero_restrict(mg_handle_t h, int level, int prec, const void* b, void* e, void* bc,
                            void* stream);
+
+/* Pre-smoothing from an iterate u fused with the restriction on level
+ * `level` of a 2D hierarchy, in storage precision `prec` (as mg_sweep): out
+ * = u + M (b - A u) on the level and bc = R (b - A out) on level+1, in one
+ * kernel (the kernel mg_solve and mg_vcycle use for the finest level's
+ * pre-smoothing in 2D; Section 4, V(1,1) cycle).  u, b, out: the level's
+ * shape, out must not alias u or b; bc: level+1's shape.  Errors: MG_EINVAL
+ * for a null handle or pointer, a bad precision, no coarser level or a 3D
+ * hierarchy. */
+int mg_sweep_smooth_restrict(mg_handle_t h, int level, int prec, const void* u, const void* b,
+                             void* out, void* bc, void* stream);
 
 /* Fused post-smoothing sweep with the coarse-grid correction: with
  * v = u + P ec (ec on level + 1; in the scaled low-precision storage the

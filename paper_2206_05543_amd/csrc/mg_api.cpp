@@ -38,7 +38,7 @@ int fail(int code, const std::string& msg) {
     } while (0)
 
 constexpr int kMaxLevels = 20;
-constexpr int kTimeKinds = 9;
+constexpr int kTimeKinds = 10;
 constexpr long kPartialCap = 1 << 17;  // per batch entry
 
 struct Hier {
@@ -373,6 +373,11 @@ struct NormReq {
 // the two sweeps (12.5 against 9.6 us at n = 63).
 bool fuse_zero_restrict(const mg_ctx* h, int l) { return h->d == 2 || level_n(h, l) >= 200; }
 
+// Where the pre-smoother from a nonzero iterate (the finest level of every
+// cycle, the second coarse visit of a W(1,0) cycle) and the restriction run
+// as one kernel: 2D, every level.
+bool fuse_smooth_restrict(const mg_ctx* h, int) { return h->d == 2; }
+
 // Which part of a cycle to enqueue: all of it, only the pre-smoother (with
 // its norm), or everything after the pre-smoother (tmp holds its output).
 enum CyclePart { kWhole = 0, kPreOnly = 1, kRest = 2 };
@@ -475,6 +480,27 @@ int cycle(mg_ctx* h, Hier& H, int l, const void* u_in, const void* b, void* out,
         s.fin_ps = s.fin_pm = nullptr;
         s.fin_count = 0;
         s.fin_dev = s.fin_host = nullptr;
+        return coarse_and_post(h, H, l, tmp, out, s, pf, wcycle, st);
+    }
+    if (!zero && fuse_smooth_restrict(h, l)) {
+        // pre-smoothing and the restriction in one kernel; its norm stays
+        // pending for the next restriction-type kernel (or the flush)
+        if (part != kRest) {
+            s.out_c = H.b[l + 1];
+            rc = run_timed(h, MG_TIME_SMOOTH_RESTRICT, l, st, [&] {
+                return launch_smooth_restrict(H.p, norm, s, st, &nparts);
+            });
+            if (rc) return rc;
+            if (norm) {
+                h->pend.count = nparts;
+                h->pend.with_max = false;
+                h->pend.slot = nr.slot;
+                h->pend.ready = nr.ready;
+            }
+            s.out_c = nullptr;
+            if (part == kPreOnly) return MG_OK;
+        }
+        s.partials = nullptr;
         return coarse_and_post(h, H, l, tmp, out, s, pf, wcycle, st);
     }
     if (part != kRest) {
@@ -725,6 +751,28 @@ int mg_sweep_zero_restrict(mg_handle_t h, int level, int prec, const void* b, vo
     s.out = e;
     s.out_c = bc;
     const hipError_t err = launch_zero_smooth_restrict(p, s, (hipStream_t)stream);
+    if (err != hipSuccess) return fail(MG_EHIP, std::string("launch: ") + hipGetErrorString(err));
+    return MG_OK;
+}
+
+int mg_sweep_smooth_restrict(mg_handle_t h, int level, int prec, const void* u, const void* b,
+                             void* out, void* bc, void* stream) {
+    if (check_handle(h)) return MG_EINVAL;
+    if (prec < MG_PREC_FP64 || prec > MG_PREC_FP16_IR) return fail(MG_EINVAL, "bad precision");
+    if (level < 0 || level >= h->L - 1) return fail(MG_EINVAL, "bad level (no coarser level)");
+    if (!u || !b || !out || !bc) return fail(MG_EINVAL, "null field pointer");
+    if (h->d != 2) return fail(MG_EINVAL, "the fused pre-smoother + restriction is 2D only");
+    const Prec p = prec == MG_PREC_FP64 ? P64 : (prec == MG_PREC_FP32_IR ? P32 : P16);
+    Hier H;
+    H.p = p;
+    H.scaled = p != P64;
+    Sweep s = make_sweep(h, H, level);
+    s.u = u;
+    s.b = b;
+    s.out = out;
+    s.out_c = bc;
+    const hipError_t err =
+        launch_smooth_restrict(p, false, s, (hipStream_t)stream, nullptr);
     if (err != hipSuccess) return fail(MG_EHIP, std::string("launch: ") + hipGetErrorString(err));
     return MG_OK;
 }

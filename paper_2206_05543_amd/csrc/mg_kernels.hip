@@ -1522,6 +1522,227 @@ k_zsr2d(const S* __restrict__ b, S* __restrict__ e, S* __restrict__ bc, int n, i
 }
 
 // ---------------------------------------------------------------------------
+// Pre-smoothing fused with the restriction (2D, any iterate):
+// out = u + sW K_c (b - sA L u) and bc = R (b - sA L out).  x strips of TX
+// fine columns march over rows; a row passes four stages, each one row
+// behind the last, so that one barrier per row suffices: at step s the
+// residual of row s (strip + ring 2, from u on strip + ring 3), the new
+// iterate of row s-2 (strip + ring 1, from residual rows s-3..s-1), the new
+// residual of row s-3 (the strip + the column right of it, where the
+// coarse nodes' full-weighting stencils reach) and its restriction one step
+// later.  Residuals and iterates outside the grid are zero.  The new
+// iterate enters the second residual as stored (rounded to S), as it would
+// from HBM.  The norm variant sums (b - sA L u)^2 over the owned nodes (the
+// residual of the incoming iterate).  Against the separate smoother and
+// restriction, one pass over u and b and one launch are saved for ring-3
+// halo columns (L2 hits) and three extra rows per chunk.
+// ---------------------------------------------------------------------------
+template <typename S, typename C, int TX, int NT, int PD, int UN, bool NTS, bool NORM>
+__global__ void __launch_bounds__(NT)
+k_sr2d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out,
+       S* __restrict__ bc, int n, int nc, int tiles_x, int ychunk, int nchunks, C sA, C sW,
+       C c0, C c1, C c2, double* __restrict__ partials) {
+    constexpr int W = TX + 7;             // columns x0-3 .. x0+TX+3
+    constexpr int M = (W + NT - 1) / NT;
+    constexpr int LW = W + 2 + 65;        // one guard each side, scratch for idle lanes
+    constexpr int HC = TX / 2;            // coarse columns per strip
+    constexpr int MC = (HC + NT - 1) / NT;
+    constexpr int RS = PD + 1;
+    static_assert(TX % 2 == 0, "even strips");
+    static_assert(UN % RS == 0, "unroll covers the prefetch ring");
+    __shared__ C uL[2][LW];
+    __shared__ C rL[4][LW];
+    __shared__ C vL[2][LW];
+    __shared__ C wL[2][LW];
+    __shared__ double red[NT / 64];
+
+    const int total = tiles_x * nchunks;
+    const int lg = xcd_remap(blockIdx.x, total);
+    const int tx = lg % tiles_x, ch = lg / tiles_x;
+    const long area = (long)n * n;
+    u += (long)blockIdx.y * area;
+    b += (long)blockIdx.y * area;
+    out += (long)blockIdx.y * area;
+    bc += (long)blockIdx.y * nc * nc;
+    const int x0 = tx * TX;
+    const int Y0 = ch * ychunk, Y1 = min(Y0 + ychunk, nc);
+    // fine rows owned: [2 Y0, 2 Y1), the last chunk up to n
+    const int o0 = 2 * Y0, o1 = Y1 == nc ? n : 2 * Y1;
+    const int t = threadIdx.x;
+    const int lane = t & 63;
+
+    int li[M];
+    unsigned gb[M];
+    bool col[M], own[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const int j = t + m * NT;
+        const bool inr = j < W;
+        const int gx = x0 - 3 + j;
+        col[m] = inr && gx >= 0 && gx < n;
+        own[m] = col[m] && gx >= x0 && gx < x0 + TX;
+        li[m] = inr ? j + 1 : W + 2 + lane;
+        gb[m] = col[m] ? (unsigned)(gx * (int)sizeof(S)) : kOob;
+    }
+    // coarse column x0/2 + i sits over local column 2 i + 4
+    int cq[MC];
+    unsigned cgb[MC];
+#pragma unroll
+    for (int q = 0; q < MC; ++q) {
+        const int i = t + q * NT;
+        const bool ok = i < HC && x0 / 2 + i < nc;
+        cq[q] = i < HC ? 2 * i + 5 : W + 2 + lane;
+        cgb[q] = ok ? (unsigned)((x0 / 2 + i) * (int)sizeof(S)) : kOob;
+    }
+
+    S ru[RS][M], rb[RS][M];
+    auto issue_u = [&](int p, int k) {
+        const rsrc_t r = line_rsrc(u, (long)p * n, n, p >= 0 && p < n);
+#pragma unroll
+        for (int m = 0; m < M; ++m) ru[k][m] = bload<S>(r, gb[m]);
+    };
+    auto issue_b = [&](int p, int k) {
+        const rsrc_t r = line_rsrc(b, (long)p * n, n, p >= 0 && p < n);
+#pragma unroll
+        for (int m = 0; m < M; ++m) rb[k][m] = bload<S>(r, gb[m]);
+    };
+
+    // u rows s-2..s+1, b rows s-1..s-3, residual rows s-1..s-3 and new
+    // iterate rows s-3, s-4 at this thread's columns (step s, on entry)
+    C um2[M], um1[M], u0[M], up1[M];
+    C b1[M], b2[M], b3[M];
+    C r1[M], r2[M], r3[M];
+    C v1[M], v2[M];
+    C acc[MC];
+    double nacc = 0.0;
+    const int s0 = 2 * Y0 - 2, s1 = 2 * Y1 + 4;
+    {
+        // all prologue loads before the first wait
+        S pu[3][M];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const int p = s0 - 1 + q;
+            const rsrc_t r = line_rsrc(u, (long)p * n, n, p >= 0 && p < n);
+#pragma unroll
+            for (int m = 0; m < M; ++m) pu[q][m] = bload<S>(r, gb[m]);
+        }
+#pragma unroll
+        for (int q = 0; q < PD; ++q) {
+            issue_u(s0 + 2 + q, q);
+            issue_b(s0 + q, q);
+        }
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            um2[m] = C(0);
+            um1[m] = cvt<C>(pu[0][m]);
+            u0[m] = cvt<C>(pu[1][m]);
+            up1[m] = cvt<C>(pu[2][m]);
+            b1[m] = b2[m] = b3[m] = C(0);
+            r1[m] = r2[m] = r3[m] = C(0);
+            v1[m] = v2[m] = C(0);
+            uL[s0 & 1][li[m]] = u0[m];
+        }
+#pragma unroll
+        for (int q = 0; q < MC; ++q) acc[q] = C(0);
+    }
+
+    auto step = [&](int s, auto kc) {
+        constexpr int k = decltype(kc)::k;  // (s - s0) % UN
+        __syncthreads();
+        issue_u(s + 2 + PD, (k + PD) % RS);
+        issue_b(s + PD, (k + PD) % RS);
+        // residual of row s
+        const bool sin = s >= 0 && s < n;
+        const bool sown = s >= o0 && s < o1;
+        C r0[M], b0[M];
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const C* U = uL[s & 1];
+            const int q = li[m];
+            b0[m] = cvt<C>(rb[k % RS][m]);
+            const C lap = C(4) * u0[m] - U[q - 1] - U[q + 1] - um1[m] - up1[m];
+            const C r = (sin && col[m]) ? b0[m] - sA * lap : C(0);
+            r0[m] = r;
+            rL[s & 3][q] = r;
+            if (NORM) nacc += (sown && own[m]) ? (double)r * (double)r : 0.0;
+        }
+        // new iterate of row s-2 (residual rows s-3, s-2, s-1)
+        const int p = s - 2;
+        const bool pin = p >= 0 && p < n;
+        const rsrc_t ro = line_rsrc(out, (long)p * n, n, p >= o0 && p < o1);
+        C v0[M];
+        {
+            const C* R0 = rL[(s + 1) & 3];  // row s - 3
+            const C* R1 = rL[(s + 2) & 3];  // row s - 2
+            const C* R2 = rL[(s + 3) & 3];  // row s - 1
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                const int q = li[m];
+                const C fc = R1[q - 1] + R1[q + 1] + r3[m] + r1[m];
+                const C cn = R0[q - 1] + R0[q + 1] + R2[q - 1] + R2[q + 1];
+                const C v = um2[m] + sW * (c0 * r2[m] + c1 * fc + c2 * cn);
+                const S vs = static_cast<S>(v);
+                bstore<NTS>(vs, ro, own[m] ? gb[m] : kOob);
+                v0[m] = (pin && col[m]) ? cvt<C>(vs) : C(0);
+                vL[p & 1][q] = v0[m];
+            }
+        }
+        // residual of row s-3 at the new iterate (rows s-4, s-3, s-2)
+        {
+            const C* V = vL[(s + 1) & 1];  // row s - 3
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                const int q = li[m];
+                const C lap = C(4) * v1[m] - V[q - 1] - V[q + 1] - v2[m] - v0[m];
+                wL[(s + 1) & 1][q] = b3[m] - sA * lap;
+            }
+        }
+        // restriction of row f = s-4 (written by the previous step)
+        const int f = s - 4;
+        if (f >= 2 * Y0 && f <= 2 * Y1) {
+            const C* R = wL[f & 1];
+            const rsrc_t rc = line_rsrc(bc, (long)(f / 2 - 1) * nc, nc, true);
+#pragma unroll
+            for (int q = 0; q < MC; ++q) {
+                const int c = cq[q];
+                const C xs = C(0.5) * R[c] + C(0.25) * (R[c - 1] + R[c + 1]);
+                if ((f & 1) == 0) {
+                    if (f > 2 * Y0) {
+                        acc[q] += C(0.25) * xs;
+                        bstore<false>(static_cast<S>(acc[q]), rc, cgb[q]);
+                    }
+                    acc[q] = C(0.25) * xs;
+                } else {
+                    acc[q] += C(0.5) * xs;
+                }
+            }
+        }
+        // u of row s+1 for the next step's neighbours; shift the histories
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            uL[(s + 1) & 1][li[m]] = up1[m];
+            um2[m] = um1[m];
+            um1[m] = u0[m];
+            u0[m] = up1[m];
+            up1[m] = cvt<C>(ru[k % RS][m]);
+            b3[m] = b2[m];
+            b2[m] = b1[m];
+            b1[m] = b0[m];
+            r3[m] = r2[m];
+            r2[m] = r1[m];
+            r1[m] = r0[m];
+            v2[m] = v1[m];
+            v1[m] = v0[m];
+        }
+    };
+    march<UN>(s0, s1, step);
+    if (NORM) {
+        const double sm = block_sum<NT>(nacc, red);
+        if (t == 0) partials[(long)blockIdx.y * gridDim.x + blockIdx.x] = sm;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Coarse tail: every level from nt interior nodes per direction down to 3,
 // the exact solve on the 3^d grid and back up, in one workgroup of 1024
 // threads with all level arrays in LDS, as a V(1,1) cycle or (WC) wvisits
@@ -2552,6 +2773,58 @@ hipError_t zsr_impl(const Sweep& s, hipStream_t st) {
         ZSR(16, 16, 512);
 #undef ZSR
     return hipGetLastError();
+}
+
+template <typename S, typename C, int TX, int NT, int PD, int UN, bool NTS>
+hipError_t launch_sr2d(const Sweep& s, bool norm, int want, int minc, hipStream_t st,
+                       int* nparts) {
+    const int n = s.n, nc = (n + 1) / 2 - 1;
+    const int tx = cdiv(n, TX);
+    const int yc = pick_chunk(nc, tx, want, minc);
+    const int nch = cdiv(nc, yc);
+    dim3 grid(tx * nch, s.batch);
+    if (nparts) *nparts = grid.x * grid.y;
+    if (norm && (long)grid.x * grid.y > s.partials_cap) return hipErrorInvalidValue;
+    const S* u = static_cast<const S*>(s.u);
+    const S* b = static_cast<const S*>(s.b);
+    S* out = static_cast<S*>(s.out);
+    S* bc = static_cast<S*>(s.out_c);
+    const C sA = C(s.sA), sW = C(s.sW), c0 = C(s.c[0]), c1 = C(s.c[1]), c2 = C(s.c[2]);
+#define SR2(NM)                                                                              \
+    hipLaunchKernelGGL((k_sr2d<S, C, TX, NT, PD, UN, NTS, NM>), grid, dim3(NT), 0, st, u, b,  \
+                       out, bc, n, nc, tx, yc, nch, sA, sW, c0, c1, c2, s.partials)
+    if (norm) SR2(true);
+    else SR2(false);
+#undef SR2
+    return hipGetLastError();
+}
+
+template <typename S, typename C>
+hipError_t sr_impl(const Sweep& s, bool norm, hipStream_t st, int* nparts) {
+    const int n = s.n, nc = (n + 1) / 2 - 1;
+    if (nc < 1 || !s.out_c || !s.u) return hipErrorInvalidValue;
+    if (s.d != 2) return hipErrorInvalidValue;
+    // shapes measured on MI355X in FP64 (n = 4095: 90 us against 127 us for
+    // the separate smoother and restriction; 1024-wide strips with two
+    // columns per lane beat 512- and 256-wide ones by 8-10%; n = 2047: 25
+    // against 35 us; n = 1023: 15 against 16 us)
+    if (n >= 3000) return launch_sr2d<S, C, 1024, 576, 2, 6, true>(s, norm, 256, 16, st, nparts);
+    if (n >= 1500) return launch_sr2d<S, C, 1024, 576, 2, 6, false>(s, norm, 512, 8, st, nparts);
+    if (n >= 700) return launch_sr2d<S, C, 256, 320, 2, 6, false>(s, norm, 1024, 4, st, nparts);
+    return launch_sr2d<S, C, 128, 192, 2, 6, false>(s, norm, 1024, 2, st, nparts);
+}
+
+hipError_t launch_smooth_restrict(Prec p, bool norm, const Sweep& s, hipStream_t st,
+                                  int* nparts) {
+    switch (p) {
+        case P64: return sr_impl<double, double>(s, norm, st, nparts);
+        case P32:
+            if (norm) return hipErrorInvalidValue;
+            return sr_impl<float, float>(s, false, st, nparts);
+        default:
+            if (norm) return hipErrorInvalidValue;
+            return sr_impl<_Float16, float>(s, false, st, nparts);
+    }
 }
 
 hipError_t launch_zero_smooth_restrict(Prec p, const Sweep& s, hipStream_t st) {

@@ -143,6 +143,47 @@ def test_zero_smooth_restrict_parity(d, N, level, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32_ir", "fp16_ir"])
+@pytest.mark.parametrize("N,level,batch", [(n, 0, 1) for n in CASES_2D] +
+                         [(1024, 1, 1), (2048, 0, 1), (4096, 0, 1), (64, 0, 3), (8, 0, 2)])
+def test_smooth_restrict_parity(N, level, batch, prec):
+    # the fused 2D pre-smoother + restriction: out = u + M (b - A u) and
+    # bc = R (b - A out), against the oracle's smoother, residual and
+    # restriction (strips of 128 / 256 columns with ragged last strips and
+    # row chunks; several batch entries)
+    need_gpu()
+    d = 2
+    Nl = N >> level
+    rng = np.random.default_rng(400 + N + level + batch)
+    shp, shc = (Nl - 1,) * d, (Nl // 2 - 1,) * d
+    c = _coeffs(d)
+    sig = _sigma(prec, Nl)
+    us = _roundtrip(_rand(rng, (batch,) + shp), prec)
+    b = _roundtrip(_rand(rng, (batch,) + shp, 1.0 if prec != "fp64" else Nl * Nl), prec)
+    say("smooth-restrict", N, level, batch, prec)
+    with make_mg(N, d, c, batch=batch) as mg:
+        out = torch.empty((batch,) + shp, dtype=_tdt(prec), device="cuda")
+        bc = torch.empty((batch,) + shc, dtype=_tdt(prec), device="cuda")
+        mg.sweep_smooth_restrict(level, prec, dev(us, _tdt(prec)), dev(b, _tdt(prec)), out, bc)
+        torch.cuda.synchronize()
+        got, got_c = host(out), host(bc)
+    h2 = 1.0 / (Nl * Nl)
+    for e in range(batch):
+        v_true = O.smooth(d, Nl, c, us[e] / sig, b[e])
+        want = v_true * sig
+        want_c = O.restrict(d, Nl, O.residual(d, Nl, v_true, b[e]))
+        tol = _tol(prec, np.abs(us[e]).max(), h2 * sig * np.abs(b[e]).max(),
+                   out_mag=np.abs(want).max())
+        # the second residual sees the stored new iterate: its rounding
+        # (half an ulp of S) passes through A (weights summing to 8 / h^2)
+        tol_c = _tol(prec, np.abs(b[e]).max(), 4 * d * Nl * Nl / sig * np.abs(want).max(),
+                     out_mag=np.abs(want_c).max())
+        if prec == "fp16_ir":
+            tol_c += 4 * d * Nl * Nl / sig * EPS16 * np.abs(want).max()
+        assert np.max(np.abs(got[e] - want)) <= tol, e
+        assert np.max(np.abs(got_c[e] - want_c)) <= tol_c, e
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_ir", "fp16_ir"])
 @pytest.mark.parametrize("d,N", [(2, n) for n in CASES_2D] + [(3, n) for n in CASES_3D])
 def test_prolong_parity(d, N, prec):
     need_gpu()
