@@ -6,9 +6,9 @@ two fixed-size Poisson workloads (2D N=4096, 4095^2 unknowns, M9 smoother;
 with inputs resident in HBM.  The headline value is fine-grid unknowns per
 second per V-cycle over the pair: sum(unknowns x cycles) / sum(solve time).
 
-Also reported: per-workload rates, the roofline of the dominant kernel (the
-fine-level fused residual + smoother sweep, timed live with HIP events on the
-launch stream), per-level kernel times and GB/s (extra solves after the timed
+Also reported: per-workload rates, the roofline of the dominant kernel (of
+the fine level's two kernels, the one with the larger total time, timed live
+with HIP events on the launch stream), per-level kernel times and GB/s (extra solves after the timed
 region, every launch timed), the time to 1e-10 of the 3D N=512 noisy problem in FP64 and
 with FP32 / FP16 V-cycles inside FP64 refinement, and the CPU oracle timed on
 a bounded sample of the same workloads (single thread).
@@ -28,14 +28,20 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# algorithmic bytes per fine point of the two fine-level smoother sweeps in
-# FP64: read u and b, write the new iterate; the post-smoother also reads the
-# coarse correction once per coarse node (8 / 2^d bytes per fine point)
-SWEEP_KINDS = ("smooth", "smooth_correct")  # timed when the library times them
+# algorithmic bytes per fine point of the two fine-level kernels in FP64:
+# read u and b, write the new iterate, and once per coarse node (8 / 2^d
+# bytes per fine point) write the coarse right-hand side (the pre-smoother
+# fused with the restriction) or read the coarse correction (the
+# post-smoother)
+SWEEP_KINDS = ("smooth_restrict", "smooth_correct")  # timed when the library times them
+SWEEP_NAMES = {"smooth_restrict": "fine-level fused residual + SPAI pre-smoother + "
+                                  "residual + full-weighting restriction",
+               "smooth_correct": "fine-level fused residual + SPAI post-smoother with the "
+                                 "coarse correction"}
 
 
 def sweep_bytes_per_pt(kind, d):
-    return 24.0 + (8.0 / 2 ** d if kind == "smooth_correct" else 0.0)
+    return 24.0 + 8.0 / 2 ** d
 
 
 # HBM traffic of these sweeps, per launch, from rocprofv3 --pmc runs of this
@@ -46,14 +52,14 @@ def sweep_bytes_per_pt(kind, d):
 # commands are in profiles/hbm_counters_fp64_sweeps.md.  Valid for the
 # kernels and launch shapes they were taken on; set to None when those change.
 PMC = {
-    ("poisson3d_n256", "smooth"): (138206, 143941),
-    ("poisson3d_n256", "smooth_correct"): (149163, 145213),
-    ("poisson2d_n4096", "smooth"): (144189, 136375),
-    ("poisson2d_n4096", "smooth_correct"): (164218, 135209),
+    ("poisson3d_n256", "smooth_restrict"): (142673, 147213),
+    ("poisson3d_n256", "smooth_correct"): (149171, 144051),
+    ("poisson2d_n4096", "smooth_restrict"): (143194, 165822),
+    ("poisson2d_n4096", "smooth_correct"): (164105, 135206),
 }
 PMC_COPY = {  # copy bytes, FETCH_SIZE KiB, WRITE_SIZE KiB of the same run
-    "poisson3d_n256": (255 ** 3 * 8, 64788, 129542),
-    "poisson2d_n4096": (4095 ** 2 * 8, 65521, 131008),
+    "poisson3d_n256": (255 ** 3 * 8, 64792, 129542),
+    "poisson2d_n4096": (4095 ** 2 * 8, 65525, 131008),
 }
 
 
@@ -228,10 +234,7 @@ def main():
         "per_workload": details,
         "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": gbs / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": ("fine-level fused residual + SPAI post-smoother with the "
-                                "coarse correction" if dom[1] == "smooth_correct" else
-                                "fine-level fused residual + SPAI pre-smoother")
-                     + f" ({dom[0]})",
+                     "kernel": SWEEP_NAMES[dom[1]] + f" ({dom[0]})",
                      "avg_launch_us": avg_us,
                      "algorithmic_bytes_per_launch": byt,
                      "traffic_GBps": traffic / (avg_us * 1e-6) / 1e9 if traffic else None},

@@ -64,8 +64,8 @@ extern "C" {
                                4..64 in 2D, 4..16 in 3D) solved by the
                                single-workgroup LDS tail kernel; 0 = default:
                                64 in 2D (32 for W(1,0) cycles), 16 in 3D      */
-#define MG_OPT_TIMING 5     /* 0 off; 1 time the fine-level post-smoother
-                               (with the fused correction) with HIP events;
+#define MG_OPT_TIMING 5     /* 0 off; 1 time the fine level's fused
+                               pre-smoother + restriction with HIP events;
                                2 time every kernel of every level              */
 #define MG_OPT_INNER_CYCLES 6 /* low-precision V-cycles per FP64 refinement
                                step, 1..16; 0 = default (6 for FP32, 2 for
@@ -108,7 +108,7 @@ extern "C" {
 #define MG_TIME_ZERO_SMOOTH_RESTRICT 8  /* zero-guess pre-smoothing fused with
                                            the restriction                    */
 #define MG_TIME_SMOOTH_RESTRICT 9  /* pre-smoothing from a nonzero iterate
-                                      fused with the restriction (2D)         */
+                                      fused with the restriction              */
 
 typedef struct mg_ctx* mg_handle_t;
 
@@ -195,13 +195,12 @@ int mg_sweep_zero_restrict(mg_handle_t h, int level, int prec, const void* b, vo
                            void* stream);
 
 /* Pre-smoothing from an iterate u fused with the restriction on level
- * `level` of a 2D hierarchy, in storage precision `prec` (as mg_sweep): out
- * = u + M (b - A u) on the level and bc = R (b - A out) on level+1, in one
- * kernel (the kernel mg_solve and mg_vcycle use for the finest level's
- * pre-smoothing in 2D; Section 4, V(1,1) cycle).  u, b, out: the level's
- * shape, out must not alias u or b; bc: level+1's shape.  Errors: MG_EINVAL
- * for a null handle or pointer, a bad precision, no coarser level or a 3D
- * hierarchy. */
+ * `level`, in storage precision `prec` (as mg_sweep): out = u + M (b - A u)
+ * on the level and bc = R (b - A out) on level+1, in one kernel (the kernel
+ * mg_solve and mg_vcycle use for the finest level's pre-smoothing; Section
+ * 4, V(1,1) cycle).  u, b, out: the level's shape, out must not alias u or
+ * b; bc: level+1's shape.  Errors: MG_EINVAL for a null handle or pointer, a
+ * bad precision, or no coarser level. */
 int mg_sweep_smooth_restrict(mg_handle_t h, int level, int prec, const void* u, const void* b,
                              void* out, void* bc, void* stream);
 

@@ -274,9 +274,10 @@ int realloc_all(mg_ctx* h) {
 
 bool timed(const mg_ctx* h, int kind, int level) {
     if (h->timing == 2) return true;
-    // mode 1: the fine-level post-smoother with the fused correction (the
-    // longest-running kernel of a cycle), one event pair per cycle
-    return h->timing == 1 && level == 0 && kind == MG_TIME_SMOOTH_CORRECT;
+    // mode 1: the longest-running kernel of a cycle, the fine level's
+    // pre-smoother fused with the restriction (one event pair per cycle; a
+    // second pair for the post-smoother costs about 8 us per 3D cycle)
+    return h->timing == 1 && level == 0 && kind == MG_TIME_SMOOTH_RESTRICT;
 }
 
 int time_begin(mg_ctx* h, int kind, int level, hipStream_t st, TimedLaunch* tl) {
@@ -375,8 +376,10 @@ bool fuse_zero_restrict(const mg_ctx* h, int l) { return h->d == 2 || level_n(h,
 
 // Where the pre-smoother from a nonzero iterate (the finest level of every
 // cycle, the second coarse visit of a W(1,0) cycle) and the restriction run
-// as one kernel: 2D, every level.
-bool fuse_smooth_restrict(const mg_ctx* h, int) { return h->d == 2; }
+// as one kernel: 2D, every level (88 against 136 us at n = 4095); 3D grids
+// of 200 or more nodes per direction (108 against 138 us at n = 255; on
+// smaller grids the ring-3 halo of its tiles costs what the fusion saves).
+bool fuse_smooth_restrict(const mg_ctx* h, int l) { return h->d == 2 || level_n(h, l) >= 200; }
 
 // Which part of a cycle to enqueue: all of it, only the pre-smoother (with
 // its norm), or everything after the pre-smoother (tmp holds its output).
@@ -761,7 +764,6 @@ int mg_sweep_smooth_restrict(mg_handle_t h, int level, int prec, const void* u, 
     if (prec < MG_PREC_FP64 || prec > MG_PREC_FP16_IR) return fail(MG_EINVAL, "bad precision");
     if (level < 0 || level >= h->L - 1) return fail(MG_EINVAL, "bad level (no coarser level)");
     if (!u || !b || !out || !bc) return fail(MG_EINVAL, "null field pointer");
-    if (h->d != 2) return fail(MG_EINVAL, "the fused pre-smoother + restriction is 2D only");
     const Prec p = prec == MG_PREC_FP64 ? P64 : (prec == MG_PREC_FP32_IR ? P32 : P16);
     Hier H;
     H.p = p;

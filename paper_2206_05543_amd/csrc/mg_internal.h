@@ -55,7 +55,7 @@ hipError_t launch_restrict(Prec p, const Sweep& s, hipStream_t st);
 // zero-guess pre-smoother fused with the restriction (2D): out = sW K b on
 // the fine grid, out_c = R (b - sA L out) on the coarse grid (u, ec ignored)
 hipError_t launch_zero_smooth_restrict(Prec p, const Sweep& s, hipStream_t st);
-// pre-smoother fused with the restriction (2D, nonzero iterate): out = u +
+// pre-smoother fused with the restriction (nonzero iterate): out = u +
 // sW K (b - sA L u) on the fine grid, out_c = R (b - sA L out); the norm
 // variant (FP64 only) writes per-block sums of (b - sA L u)^2 to partials
 hipError_t launch_smooth_restrict(Prec p, bool norm, const Sweep& s, hipStream_t st,

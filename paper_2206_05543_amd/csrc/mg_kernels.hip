@@ -1595,14 +1595,18 @@ k_sr2d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out,
         cgb[q] = ok ? (unsigned)((x0 / 2 + i) * (int)sizeof(S)) : kOob;
     }
 
+    // rows any output depends on: u up to 2 Y1 + 3, b up to 2 Y1 + 2; the
+    // whole unrolled groups and the prefetch run past them, and rows
+    // outside these ranges read as zero without touching memory
+    const int ulast = min(n - 1, 2 * Y1 + 3), blast = min(n - 1, 2 * Y1 + 2);
     S ru[RS][M], rb[RS][M];
     auto issue_u = [&](int p, int k) {
-        const rsrc_t r = line_rsrc(u, (long)p * n, n, p >= 0 && p < n);
+        const rsrc_t r = line_rsrc(u, (long)p * n, n, p >= 0 && p <= ulast);
 #pragma unroll
         for (int m = 0; m < M; ++m) ru[k][m] = bload<S>(r, gb[m]);
     };
     auto issue_b = [&](int p, int k) {
-        const rsrc_t r = line_rsrc(b, (long)p * n, n, p >= 0 && p < n);
+        const rsrc_t r = line_rsrc(b, (long)p * n, n, p >= 0 && p <= blast);
 #pragma unroll
         for (int m = 0; m < M; ++m) rb[k][m] = bload<S>(r, gb[m]);
     };
@@ -1729,6 +1733,235 @@ k_sr2d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out,
             b2[m] = b1[m];
             b1[m] = b0[m];
             r3[m] = r2[m];
+            r2[m] = r1[m];
+            r1[m] = r0[m];
+            v2[m] = v1[m];
+            v1[m] = v0[m];
+        }
+    };
+    march<UN>(s0, s1, step);
+    if (NORM) {
+        const double sm = block_sum<NT>(nacc, red);
+        if (t == 0) partials[(long)blockIdx.y * gridDim.x + blockIdx.x] = sm;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Pre-smoothing fused with the restriction (3D, any iterate):
+// out = u + sW K_c (b - sA L u) and bc = R (b - sA L out).  A workgroup owns
+// a TX x TY tile of fine columns and marches over planes; every lane keeps
+// its points of the tile plus a ring of 3 (u there; the residual is valid on
+// the ring of 2, the new iterate on the ring of 1, the second residual on
+// the tile plus the row and column after it, where the coarse nodes'
+// stencils reach).  The 7-point M and A couple planes only through the same
+// column, so the stages lag by one plane each: at step s the residual of
+// plane s, the new iterate of plane s-1, the second residual of plane s-2
+// and the restriction of plane s-3, with one barrier per plane (in-plane
+// neighbours from LDS, the planes above and below from registers).
+// Residuals and iterates outside the grid are zero; the new iterate enters
+// the second residual as stored.  The norm variant sums (b - sA L u)^2 over
+// the owned nodes.
+// ---------------------------------------------------------------------------
+template <typename S, typename C, int TX, int TY, int NT, int PD, int UN, bool NTS, bool NORM>
+__global__ void __launch_bounds__(NT)
+k_sr3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out,
+       S* __restrict__ bc, int n, int nc, int tiles_x, int tiles_y, int zchunk, int nchunks,
+       C sA, C sW, C c0, C c1, double* __restrict__ partials) {
+    constexpr int WX = TX + 7, WY = TY + 7, NW = WX * WY;  // x0-3 .. x0+TX+3
+    constexpr int M = (NW + NT - 1) / NT;
+    constexpr int WP = WX + 1, LSZ = NW + 2 * WP;          // guard rows of neighbours
+    constexpr int HX = TX / 2, HY = TY / 2, NCC = HX * HY;  // coarse columns per tile
+    constexpr int MC = (NCC + NT - 1) / NT;
+    constexpr int RS = PD + 1;
+    static_assert(TX % 2 == 0 && TY % 2 == 0, "even tiles");
+    static_assert(UN % RS == 0, "unroll covers the prefetch ring");
+    __shared__ C uL[2][LSZ];
+    __shared__ C rL[2][LSZ];
+    __shared__ C vL[2][LSZ];
+    __shared__ C wL[2][LSZ];
+    __shared__ double red[NT / 64];
+
+    const int total = tiles_x * tiles_y * nchunks;
+    const int lg = xcd_remap(blockIdx.x, total);
+    const int tx = lg % tiles_x, ty = (lg / tiles_x) % tiles_y,
+              ch = lg / (tiles_x * tiles_y);
+    const long plane = (long)n * n, cplane = (long)nc * nc;
+    u += (long)blockIdx.y * plane * n;
+    b += (long)blockIdx.y * plane * n;
+    out += (long)blockIdx.y * plane * n;
+    bc += (long)blockIdx.y * cplane * nc;
+    const int x0 = tx * TX, y0 = ty * TY;
+    const int Z0 = ch * zchunk, Z1 = min(Z0 + zchunk, nc);
+    // fine planes owned: [2 Z0, 2 Z1), the last chunk up to n
+    const int o0 = 2 * Z0, o1 = Z1 == nc ? n : 2 * Z1;
+    const int t = threadIdx.x;
+
+    int li[M];
+    unsigned gb[M];
+    bool col[M], own[M], wr[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const int i = t + m * NT;
+        wr[m] = i < NW;
+        const int lx = i % WX, ly = i / WX;
+        const int gx = x0 - 3 + lx, gy = y0 - 3 + ly;
+        col[m] = wr[m] && gx >= 0 && gx < n && gy >= 0 && gy < n;
+        own[m] = col[m] && gx >= x0 && gx < x0 + TX && gy >= y0 && gy < y0 + TY;
+        li[m] = wr[m] ? WP + i : WP;  // idle lanes read a valid slot, write nothing
+        gb[m] = col[m] ? (unsigned)((gy * n + gx) * (int)sizeof(S)) : kOob;
+    }
+    // coarse column (x0/2 + i, y0/2 + j) sits over window point (2i+4, 2j+4)
+    int cq[MC];
+    unsigned cgb[MC];
+#pragma unroll
+    for (int q = 0; q < MC; ++q) {
+        const int k = t + q * NT;
+        const int i = k % HX, j = k / HX;
+        const bool ok = k < NCC && x0 / 2 + i < nc && y0 / 2 + j < nc;
+        cq[q] = k < NCC ? WP + (2 * j + 4) * WX + 2 * i + 4 : WP + WX + 1;
+        cgb[q] = ok ? (unsigned)(((y0 / 2 + j) * nc + x0 / 2 + i) * (int)sizeof(S)) : kOob;
+    }
+
+    // planes any output depends on: u up to 2 Z1 + 3, b up to 2 Z1 + 2 (as
+    // in 2D, later planes read as zero without touching memory)
+    const int ulast = min(n - 1, 2 * Z1 + 3), blast = min(n - 1, 2 * Z1 + 2);
+    S ru[RS][M], rb[RS][M];
+    auto issue_u = [&](int p, int k) {
+        const rsrc_t r = line_rsrc(u, (long)p * plane, plane, p >= 0 && p <= ulast);
+#pragma unroll
+        for (int m = 0; m < M; ++m) ru[k][m] = bload<S>(r, gb[m]);
+    };
+    auto issue_b = [&](int p, int k) {
+        const rsrc_t r = line_rsrc(b, (long)p * plane, plane, p >= 0 && p <= blast);
+#pragma unroll
+        for (int m = 0; m < M; ++m) rb[k][m] = bload<S>(r, gb[m]);
+    };
+
+    // on entry to step s: u planes s-1..s+1, b planes s-1, s-2, residual
+    // planes s-1, s-2 and new iterate planes s-2, s-3 at this lane's points
+    C um1[M], u0[M], up1[M], b1[M], b2[M], r1[M], r2[M], v1[M], v2[M];
+    C acc[MC];
+    double nacc = 0.0;
+    const int s0 = 2 * Z0 - 2, s1 = 2 * Z1 + 3;
+    {
+        S pu[3][M];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const int p = s0 - 1 + q;
+            const rsrc_t r = line_rsrc(u, (long)p * plane, plane, p >= 0 && p < n);
+#pragma unroll
+            for (int m = 0; m < M; ++m) pu[q][m] = bload<S>(r, gb[m]);
+        }
+#pragma unroll
+        for (int q = 0; q < PD; ++q) {
+            issue_u(s0 + 2 + q, q);
+            issue_b(s0 + q, q);
+        }
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            um1[m] = cvt<C>(pu[0][m]);
+            u0[m] = cvt<C>(pu[1][m]);
+            up1[m] = cvt<C>(pu[2][m]);
+            b1[m] = b2[m] = r1[m] = r2[m] = v1[m] = v2[m] = C(0);
+            if (wr[m]) uL[s0 & 1][li[m]] = u0[m];
+        }
+#pragma unroll
+        for (int q = 0; q < MC; ++q) acc[q] = C(0);
+        // the planes a first step reads before any step wrote them
+        for (int i = t; i < LSZ; i += NT) {
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                rL[j][i] = C(0);
+                vL[j][i] = C(0);
+                wL[j][i] = C(0);
+            }
+        }
+    }
+
+    auto step = [&](int s, auto kc) {
+        constexpr int k = decltype(kc)::k;  // (s - s0) % UN
+        __syncthreads();
+        issue_u(s + 2 + PD, (k + PD) % RS);
+        issue_b(s + PD, (k + PD) % RS);
+        // residual of plane s
+        const bool sin = s >= 0 && s < n;
+        const bool sown = s >= o0 && s < o1;
+        C r0[M], b0[M];
+        {
+            const C* U = uL[s & 1];
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                const int q = li[m];
+                b0[m] = cvt<C>(rb[k % RS][m]);
+                const C lap = C(6) * u0[m] - U[q - 1] - U[q + 1] - U[q - WX] - U[q + WX] -
+                              um1[m] - up1[m];
+                const C r = (sin && col[m]) ? b0[m] - sA * lap : C(0);
+                r0[m] = r;
+                if (wr[m]) rL[s & 1][q] = r;
+                if (NORM) nacc += (sown && own[m]) ? (double)r * (double)r : 0.0;
+            }
+        }
+        // new iterate of plane s-1 (residual planes s-2, s-1, s)
+        const int p = s - 1;
+        const bool pin = p >= 0 && p < n;
+        C v0[M];
+        {
+            const C* R = rL[(s + 1) & 1];  // plane s - 1
+            const rsrc_t ro = line_rsrc(out, (long)p * plane, plane, p >= o0 && p < o1);
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                const int q = li[m];
+                const C nbs = R[q - 1] + R[q + 1] + R[q - WX] + R[q + WX] + r2[m] + r0[m];
+                const C v = um1[m] + sW * (c0 * r1[m] + c1 * nbs);
+                const S vs = static_cast<S>(v);
+                bstore<NTS>(vs, ro, own[m] ? gb[m] : kOob);
+                v0[m] = (pin && col[m]) ? cvt<C>(vs) : C(0);
+                if (wr[m]) vL[p & 1][q] = v0[m];
+            }
+        }
+        // residual of plane s-2 at the new iterate (planes s-3, s-2, s-1)
+        {
+            const C* V = vL[s & 1];  // plane s - 2
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                const int q = li[m];
+                const C lap = C(6) * v1[m] - V[q - 1] - V[q + 1] - V[q - WX] - V[q + WX] -
+                              v2[m] - v0[m];
+                if (wr[m]) wL[s & 1][q] = b2[m] - sA * lap;
+            }
+        }
+        // restriction of plane f = s-3 (written by the previous step)
+        const int f = s - 3;
+        if (f >= 2 * Z0 && f <= 2 * Z1) {
+            const C* R = wL[f & 1];
+            const rsrc_t rc = line_rsrc(bc, (long)(f / 2 - 1) * cplane, cplane, true);
+#pragma unroll
+            for (int q = 0; q < MC; ++q) {
+                const int c = cq[q];
+                const C xs = C(0.25) * R[c] +
+                             C(0.125) * (R[c - 1] + R[c + 1] + R[c - WX] + R[c + WX]) +
+                             C(0.0625) * (R[c - WX - 1] + R[c - WX + 1] + R[c + WX - 1] +
+                                          R[c + WX + 1]);
+                if ((f & 1) == 0) {
+                    if (f > 2 * Z0) {
+                        acc[q] += C(0.25) * xs;
+                        bstore<false>(static_cast<S>(acc[q]), rc, cgb[q]);
+                    }
+                    acc[q] = C(0.25) * xs;
+                } else {
+                    acc[q] += C(0.5) * xs;
+                }
+            }
+        }
+        // u of plane s+1 for the next step's neighbours; shift the histories
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            if (wr[m]) uL[(s + 1) & 1][li[m]] = up1[m];
+            um1[m] = u0[m];
+            u0[m] = up1[m];
+            up1[m] = cvt<C>(ru[k % RS][m]);
+            b2[m] = b1[m];
+            b1[m] = b0[m];
             r2[m] = r1[m];
             r1[m] = r0[m];
             v2[m] = v1[m];
@@ -2799,11 +3032,55 @@ hipError_t launch_sr2d(const Sweep& s, bool norm, int want, int minc, hipStream_
     return hipGetLastError();
 }
 
+template <typename S, typename C, int TX, int TY, int NT, int PD, int UN, bool NTS>
+hipError_t launch_sr3d(const Sweep& s, bool norm, int want, int minc, hipStream_t st,
+                       int* nparts) {
+    const int n = s.n, nc = (n + 1) / 2 - 1;
+    const int tx = cdiv(n, TX), ty = cdiv(n, TY);
+    const int zc = pick_chunk(nc, tx * ty, want, minc);
+    const int nch = cdiv(nc, zc);
+    dim3 grid(tx * ty * nch, s.batch);
+    if (nparts) *nparts = grid.x * grid.y;
+    if (norm && (long)grid.x * grid.y > s.partials_cap) return hipErrorInvalidValue;
+    const S* u = static_cast<const S*>(s.u);
+    const S* b = static_cast<const S*>(s.b);
+    S* out = static_cast<S*>(s.out);
+    S* bc = static_cast<S*>(s.out_c);
+    const C sA = C(s.sA), sW = C(s.sW), c0 = C(s.c[0]), c1 = C(s.c[1]);
+#define SR3(NM)                                                                             \
+    hipLaunchKernelGGL((k_sr3d<S, C, TX, TY, NT, PD, UN, NTS, NM>), grid, dim3(NT), 0, st,     \
+                       u, b, out, bc, n, nc, tx, ty, zc, nch, sA, sW, c0, c1, s.partials)
+    if (norm) SR3(true);
+    else SR3(false);
+#undef SR3
+    return hipGetLastError();
+}
+
 template <typename S, typename C>
 hipError_t sr_impl(const Sweep& s, bool norm, hipStream_t st, int* nparts) {
     const int n = s.n, nc = (n + 1) / 2 - 1;
     if (nc < 1 || !s.out_c || !s.u) return hipErrorInvalidValue;
-    if (s.d != 2) return hipErrorInvalidValue;
+    if (s.d == 3) {
+        // buffer offsets are 32-bit byte offsets within one plane
+        if ((long)n * n * (long)sizeof(S) > 0x7fffffffL) return hipErrorInvalidValue;
+        // shapes measured on MI355X in FP64: 32x32 tiles (ring 3: 1.49x the
+        // tile's points) with two points per lane; n = 255: 106 us against
+        // 128 us for the separate smoother and restriction, n = 511: 758
+        // against 1058 us.  64x16 tiles were 3-4% slower, non-temporal
+        // stores 4-5% slower, one u and one residual plane in LDS (two
+        // workgroups per CU, a second barrier per plane) 2-3% slower.  Below
+        // 200 nodes the fused kernel is not faster than the two sweeps (22-33
+        // against 24 us at n = 127); the cycle uses it from 200 up.
+        // FP32 / FP16 storage: 64x32 tiles on 1024 threads (4- and 2-byte
+        // rows need longer row segments; n = 511: 448 / 346 us against 566 /
+        // 406 us for the separate sweeps, where 32x32 tiles take 486 / 477)
+        if constexpr (sizeof(S) < 8) {
+            return launch_sr3d<S, C, 64, 32, 1024, 2, 6, false>(s, norm, n >= 200 ? 256 : 512,
+                                                                4, st, nparts);
+        }
+        if (n >= 200) return launch_sr3d<S, C, 32, 32, 768, 2, 6, false>(s, norm, 256, 8, st, nparts);
+        return launch_sr3d<S, C, 32, 32, 768, 1, 2, false>(s, norm, 512, 4, st, nparts);
+    }
     // shapes measured on MI355X in FP64 (n = 4095: 90 us against 127 us for
     // the separate smoother and restriction; 1024-wide strips with two
     // columns per lane beat 512- and 256-wide ones by 8-10%; n = 2047: 25

@@ -143,15 +143,18 @@ def test_zero_smooth_restrict_parity(d, N, level, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32_ir", "fp16_ir"])
-@pytest.mark.parametrize("N,level,batch", [(n, 0, 1) for n in CASES_2D] +
-                         [(1024, 1, 1), (2048, 0, 1), (4096, 0, 1), (64, 0, 3), (8, 0, 2)])
-def test_smooth_restrict_parity(N, level, batch, prec):
-    # the fused 2D pre-smoother + restriction: out = u + M (b - A u) and
+@pytest.mark.parametrize("d,N,level,batch", [(2, n, 0, 1) for n in CASES_2D] +
+                         [(2, 1024, 1, 1), (2, 2048, 0, 1), (2, 4096, 0, 1), (2, 64, 0, 3),
+                          (2, 8, 0, 2)] +
+                         [(3, n, 0, 1) for n in CASES_3D + [256]] +
+                         [(3, 256, 1, 1), (3, 32, 0, 2), (3, 8, 0, 3)])
+def test_smooth_restrict_parity(d, N, level, batch, prec):
+    # the fused pre-smoother + restriction: out = u + M (b - A u) and
     # bc = R (b - A out), against the oracle's smoother, residual and
-    # restriction (strips of 128 / 256 columns with ragged last strips and
-    # row chunks; several batch entries)
+    # restriction (2D strips, 3D tiles, both with ragged last tiles and
+    # chunks along the march; the large-grid shapes at 2D N >= 2048 and 3D
+    # N = 256; several batch entries; the smallest grid with a coarse level)
     need_gpu()
-    d = 2
     Nl = N >> level
     rng = np.random.default_rng(400 + N + level + batch)
     shp, shc = (Nl - 1,) * d, (Nl // 2 - 1,) * d
@@ -174,7 +177,7 @@ def test_smooth_restrict_parity(N, level, batch, prec):
         tol = _tol(prec, np.abs(us[e]).max(), h2 * sig * np.abs(b[e]).max(),
                    out_mag=np.abs(want).max())
         # the second residual sees the stored new iterate: its rounding
-        # (half an ulp of S) passes through A (weights summing to 8 / h^2)
+        # (half an ulp of S) passes through A (weights summing to 4d / h^2)
         tol_c = _tol(prec, np.abs(b[e]).max(), 4 * d * Nl * Nl / sig * np.abs(want).max(),
                      out_mag=np.abs(want_c).max())
         if prec == "fp16_ir":
