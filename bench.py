@@ -33,15 +33,21 @@ HBM_PEAK_GBS = 8000.0
 # bytes per fine point) write the coarse right-hand side (the pre-smoother
 # fused with the restriction) or read the coarse correction (the
 # post-smoother)
-SWEEP_KINDS = ("smooth_restrict", "smooth_correct")  # timed when the library times them
+SWEEP_KINDS = ("smooth_restrict", "post_pre_restrict", "smooth_correct")  # timed if timed
 SWEEP_NAMES = {"smooth_restrict": "fine-level fused residual + SPAI pre-smoother + "
                                   "residual + full-weighting restriction",
+               "post_pre_restrict": "fine-level fused coarse correction + SPAI post-smoother + "
+                                    "next cycle's SPAI pre-smoother + residual + "
+                                    "full-weighting restriction",
                "smooth_correct": "fine-level fused residual + SPAI post-smoother with the "
                                  "coarse correction"}
 
 
 def sweep_bytes_per_pt(kind, d):
-    return 24.0 + 8.0 / 2 ** d
+    c = 8.0 / 2 ** d
+    # the chained kernel reads u1, b and the coarse correction and writes
+    # u_{k+1}, the next u1 and the coarse right-hand side
+    return 32.0 + 2 * c if kind == "post_pre_restrict" else 24.0 + c
 
 
 # HBM traffic of these sweeps, per launch, from rocprofv3 --pmc runs of this
@@ -75,14 +81,15 @@ WORKLOADS = {"poisson2d_n4096": (2, 4096), "poisson3d_n256": (3, 256)}
 
 # algorithmic FP64 bytes per fine point of a level, per timed kernel kind
 # (the tail is reported by time only)
-LEVEL_KINDS = ("smooth", "smooth_zero", "restrict", "smooth_restrict", "zero_smooth_restrict",
-               "smooth_correct", "prolong", "tail")
+LEVEL_KINDS = ("smooth", "smooth_zero", "restrict", "smooth_restrict", "post_pre_restrict",
+               "zero_smooth_restrict", "smooth_correct", "prolong", "tail")
 
 
 def level_bytes_per_pt(kind, d):
     c = 8.0 / 2 ** d  # one coarse value per 2^d fine points
     return {"smooth": 24.0, "smooth_zero": 16.0, "restrict": 16.0 + c,
-            "smooth_restrict": 24.0 + c, "zero_smooth_restrict": 16.0 + c,
+            "smooth_restrict": 24.0 + c, "post_pre_restrict": 32.0 + 2 * c,
+            "zero_smooth_restrict": 16.0 + c,
             "smooth_correct": 24.0 + c,
             "prolong": 16.0 + c}.get(kind)
 

@@ -109,6 +109,9 @@ extern "C" {
                                            the restriction                    */
 #define MG_TIME_SMOOTH_RESTRICT 9  /* pre-smoothing from a nonzero iterate
                                       fused with the restriction              */
+#define MG_TIME_POST_PRE_RESTRICT 10  /* post-smoothing of one cycle fused
+                                         with the next one's pre-smoothing
+                                         and restriction (2D solves)      */
 
 typedef struct mg_ctx* mg_handle_t;
 
@@ -203,6 +206,20 @@ int mg_sweep_zero_restrict(mg_handle_t h, int level, int prec, const void* b, vo
  * bad precision, or no coarser level. */
 int mg_sweep_smooth_restrict(mg_handle_t h, int level, int prec, const void* u, const void* b,
                              void* out, void* bc, void* stream);
+
+/* The sweeps between two V(1,1) cycles as one kernel, on level `level` of
+ * a 2D hierarchy in storage precision `prec` (as mg_sweep): with w = u + P ec
+ * (u: the pre-smoothed iterate of cycle k, ec: its coarse-grid correction on
+ * level+1), out = w + M (b - A w) is u_{k+1} (post-smoothing), out_t = out +
+ * M (b - A out) the pre-smoothed iterate of cycle k+1 and bc = R (b - A
+ * out_t) its coarse right-hand side on level+1 (Section 4, V(1,1) cycle;
+ * mg_solve uses it between the cycles of 2D FP64 solves).  u, b, out, out_t:
+ * the level's shape, out and out_t must not alias each other, u or b; ec,
+ * bc: level+1's shape.  Errors: MG_EINVAL for a null handle or pointer, a
+ * bad precision, no coarser level or a 3D hierarchy. */
+int mg_sweep_post_pre_restrict(mg_handle_t h, int level, int prec, const void* u,
+                               const void* ec, const void* b, void* out, void* out_t, void* bc,
+                               void* stream);
 
 /* Fused post-smoothing sweep with the coarse-grid correction: with
  * v = u + P ec (ec on level + 1; in the scaled low-precision storage the

@@ -21,7 +21,7 @@ PREC = {"fp64": 0, "fp32_ir": 1, "fp16_ir": 2}
 OP = {"smooth": 0, "smooth_zero": 1, "restrict": 2, "prolong_add": 3}
 TIME = {"smooth": 0, "smooth_zero": 1, "restrict": 2, "prolong": 3, "tail": 4,
         "ir_step": 5, "residual": 6, "smooth_correct": 7, "zero_smooth_restrict": 8,
-        "smooth_restrict": 9}
+        "smooth_restrict": 9, "post_pre_restrict": 10}
 STORAGE = {0: torch.float64, 1: torch.float32, 2: torch.float16}
 
 _lib = None
@@ -60,6 +60,7 @@ def lib():
         L.mg_sweep_correct.argtypes = [vp, i, i, vp, vp, vp, vp, vp]
         L.mg_sweep_zero_restrict.argtypes = [vp, i, i, vp, vp, vp, vp]
         L.mg_sweep_smooth_restrict.argtypes = [vp, i, i, vp, vp, vp, vp, vp]
+        L.mg_sweep_post_pre_restrict.argtypes = [vp, i, i, vp, vp, vp, vp, vp, vp, vp]
         L.mg_residual_norm.argtypes = [vp, vp, vp, dp, vp]
         L.mg_get_timing.argtypes = [vp, i, i, dp, ctypes.POINTER(i)]
         L.mg_reset_timing.argtypes = [vp]
@@ -218,6 +219,15 @@ class Multigrid:
             self._field(b, level, dt, "b"), self._field(out, level, dt, "out"),
             self._field(bc, level + 1, dt, "bc"), _stream()))
         return out, bc
+
+    def sweep_post_pre_restrict(self, level, prec, u, ec, b, out, out_t, bc):
+        dt = STORAGE[PREC[prec]]
+        _check(lib().mg_sweep_post_pre_restrict(
+            self._h, level, PREC[prec], self._field(u, level, dt, "u"),
+            self._field(ec, level + 1, dt, "ec"), self._field(b, level, dt, "b"),
+            self._field(out, level, dt, "out"), self._field(out_t, level, dt, "out_t"),
+            self._field(bc, level + 1, dt, "bc"), _stream()))
+        return out, out_t, bc
 
     def set_inner_cycles(self, m):
         self.set_option(OPT_INNER_CYCLES, m)

@@ -38,7 +38,7 @@ int fail(int code, const std::string& msg) {
     } while (0)
 
 constexpr int kMaxLevels = 20;
-constexpr int kTimeKinds = 10;
+constexpr int kTimeKinds = 11;
 constexpr long kPartialCap = 1 << 17;  // per batch entry
 
 struct Hier {
@@ -275,9 +275,11 @@ int realloc_all(mg_ctx* h) {
 bool timed(const mg_ctx* h, int kind, int level) {
     if (h->timing == 2) return true;
     // mode 1: the longest-running kernel of a cycle, the fine level's
-    // pre-smoother fused with the restriction (one event pair per cycle; a
-    // second pair for the post-smoother costs about 8 us per 3D cycle)
-    return h->timing == 1 && level == 0 && kind == MG_TIME_SMOOTH_RESTRICT;
+    // pre-smoother fused with the restriction (and, in chained 2D solves,
+    // with the previous cycle's post-smoother): one event pair per cycle; a
+    // second pair for the post-smoother costs about 8 us per 3D cycle
+    return h->timing == 1 && level == 0 &&
+           (kind == MG_TIME_SMOOTH_RESTRICT || kind == MG_TIME_POST_PRE_RESTRICT);
 }
 
 int time_begin(mg_ctx* h, int kind, int level, hipStream_t st, TimedLaunch* tl) {
@@ -779,6 +781,34 @@ int mg_sweep_smooth_restrict(mg_handle_t h, int level, int prec, const void* u, 
     return MG_OK;
 }
 
+int mg_sweep_post_pre_restrict(mg_handle_t h, int level, int prec, const void* u,
+                               const void* ec, const void* b, void* out, void* out_t, void* bc,
+                               void* stream) {
+    if (check_handle(h)) return MG_EINVAL;
+    if (prec < MG_PREC_FP64 || prec > MG_PREC_FP16_IR) return fail(MG_EINVAL, "bad precision");
+    if (level < 0 || level >= h->L - 1) return fail(MG_EINVAL, "bad level (no coarser level)");
+    if (!u || !ec || !b || !out || !out_t || !bc) return fail(MG_EINVAL, "null field pointer");
+    if (h->d != 2) return fail(MG_EINVAL, "the fused post- and pre-smoother is 2D only");
+    const Prec p = prec == MG_PREC_FP64 ? P64 : (prec == MG_PREC_FP32_IR ? P32 : P16);
+    Hier H;
+    H.p = p;
+    H.scaled = p != P64;
+    Sweep s = make_sweep(h, H, level);
+    double sA, sW, pf;
+    level_scales(h, H, level, &sA, &sW, &pf);
+    s.u = u;
+    s.ec = ec;
+    s.pf = pf;
+    s.b = b;
+    s.out = out;
+    s.out_t = out_t;
+    s.out_c = bc;
+    const hipError_t err =
+        launch_post_pre_restrict(p, false, s, (hipStream_t)stream, nullptr);
+    if (err != hipSuccess) return fail(MG_EHIP, std::string("launch: ") + hipGetErrorString(err));
+    return MG_OK;
+}
+
 int mg_sweep_correct(mg_handle_t h, int level, int prec, const void* u, const void* ec,
                      const void* b, void* out, void* stream) {
     if (check_handle(h)) return MG_EINVAL;
@@ -844,8 +874,131 @@ int mg_residual_norm(mg_handle_t h, const double* b, const double* u, double* no
     return MG_OK;
 }
 
+// FP64 V(1,1) solves in 2D run chained: the post-smoother of cycle k and the
+// pre-smoother and restriction of cycle k + 1 are one kernel (it also yields
+// ||r_{k+1}|| and writes u_{k+1} straight into the caller's buffer), so a
+// cycle is that kernel plus the coarse levels.  Same arithmetic per cycle
+// as the separate kernels; the answer is always in u, so neither ping-pong
+// nor an in-place cycle is needed.
+bool chain_2d(const mg_ctx* h) {
+    return h->d == 2 && h->L >= 2 && h->cycle_kind == MG_CYCLE_V11;
+}
+
+static int solve64_chain(mg_ctx* h, const double* b, double* u, double tol, mg_stats* st_out,
+                         hipStream_t st) {
+    Hier& H = h->h64;
+    double* tcur = static_cast<double*>(H.t[0]);
+    double* tnext = h->ualt;  // free: the iterate never ping-pongs here
+    HIPCHK(hipEventRecord(h->ev0, st));
+    std::vector<double> hist;
+    double r0 = 0.0, rk = 0.0;
+    int k = 0, code = MG_OK, run = 0;
+    hipEvent_t evn;
+    HIPCHK(hipEventCreateWithFlags(&evn, hipEventDisableTiming));
+    auto done = [&](int rc) {
+        (void)hipEventDestroy(evn);
+        return rc;
+    };
+    Sweep s = make_sweep(h, H, 0);
+    double sA, sW, pf;
+    level_scales(h, H, 0, &sA, &sW, &pf);
+    s.partials = h->psum;
+    s.partials_cap = kPartialCap * h->batch;
+    s.b = b;
+    s.out_c = H.b[1];
+    int nparts = 0, rc;
+    auto pend = [&](int slot) {
+        h->pend.count = nparts;
+        h->pend.with_max = false;
+        h->pend.slot = slot;
+        h->pend.ready = evn;
+    };
+    // the coarse part of a cycle (its first restriction-type kernel reduces
+    // the pending norm), or only the norm's reduction
+    auto coarse = [&]() {
+        const int r = cycle(h, H, 1, nullptr, H.b[1], H.e[1], H.t[1], NormReq(), st);
+        if (r) return r;
+        return flush_pending_norm(h, st);
+    };
+    // cycle 0: pre-smoother and restriction, with ||r_0||
+    s.u = u;
+    s.out = tcur;
+    rc = run_timed(h, MG_TIME_SMOOTH_RESTRICT, 0, st,
+                   [&] { return launch_smooth_restrict(P64, true, s, st, &nparts); });
+    if (rc) return done(rc);
+    pend(0);
+    run = 1;
+    bool gate = false;
+    rc = coarse();
+    if (rc) return done(rc);
+    for (k = 0;; ++k) {
+        // u_k is in u; the pre-smoothed iterate of cycle k in tcur, its
+        // coarse problem enqueued unless gated
+        hipError_t e = hipEventSynchronize(evn);
+        if (e != hipSuccess)
+            return done(fail(MG_EHIP, std::string("hipEventSynchronize: ") + hipGetErrorString(e)));
+        const double nk = h->hnorm[2 * k];
+        if (!std::isfinite(nk)) {
+            code = MG_ENONFINITE;
+            rk = nk;
+            break;
+        }
+        if (k == 0) r0 = nk;
+        hist.push_back(nk);
+        rk = nk;
+        if (nk <= tol * r0) break;
+        if (k >= h->max_cycles) {
+            code = MG_ENOCONV;
+            break;
+        }
+        if (gate) {
+            rc = cycle(h, H, 1, nullptr, H.b[1], H.e[1], H.t[1], NormReq(), st);
+            if (rc) return done(rc);
+        }
+        // post-smoother of cycle k with the coarse correction, then the
+        // pre-smoother and restriction of cycle k + 1, with ||r_{k+1}||
+        s.u = tcur;
+        s.ec = H.e[1];
+        s.pf = pf;
+        s.out = u;
+        s.out_t = tnext;
+        rc = run_timed(h, MG_TIME_POST_PRE_RESTRICT, 0, st,
+                       [&] { return launch_post_pre_restrict(P64, true, s, st, &nparts); });
+        if (rc) return done(rc);
+        pend(k + 1);
+        ++run;
+        std::swap(tcur, tnext);
+        // a cycle predicted to find u_{k+1} converged waits for the norm
+        // before its coarse part
+        gate = predict_final(hist, tol, r0);
+        rc = gate ? flush_pending_norm(h, st) : coarse();
+        if (rc) return done(rc);
+    }
+    (void)hipEventDestroy(evn);
+    HIPCHK(hipEventRecord(h->ev1, st));
+    HIPCHK(hipStreamSynchronize(st));
+    rc = time_collect(h);
+    if (rc) return rc;
+    if (st_out) {
+        st_out->cycles = k;
+        st_out->cycles_run = run;
+        st_out->r0_norm = r0;
+        st_out->rk_norm = rk;
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+        st_out->elapsed_ms = ms;
+        if (st_out->res_hist)
+            for (int j = 0; j < (int)hist.size() && j < st_out->hist_cap; ++j)
+                st_out->res_hist[j] = hist[j];
+    }
+    if (code == MG_ENONFINITE) return fail(code, "residual norm is not finite");
+    if (code == MG_ENOCONV) return fail(code, "maximum number of cycles reached");
+    return MG_OK;
+}
+
 static int solve64(mg_ctx* h, const double* b, double* u, double tol, mg_stats* st_out,
                    hipStream_t st) {
+    if (chain_2d(h)) return solve64_chain(h, b, u, tol, st_out, st);
     double* X = u;
     double* Y = h->ualt;
     const size_t fine = (size_t)level_pts(h, 0) * h->batch * sizeof(double);

@@ -45,6 +45,9 @@ struct Sweep {
     // coarse right-hand side written by the fused zero-guess smoother +
     // restriction ((n+1)/2 - 1 interior nodes per direction)
     void* out_c = nullptr;
+    // the next cycle's pre-smoothed iterate, written by the fused
+    // post-smoother + pre-smoother + restriction
+    void* out_t = nullptr;
 };
 
 // Launchers return hipSuccess or the launch error.  *nparts receives the
@@ -60,6 +63,13 @@ hipError_t launch_zero_smooth_restrict(Prec p, const Sweep& s, hipStream_t st);
 // variant (FP64 only) writes per-block sums of (b - sA L u)^2 to partials
 hipError_t launch_smooth_restrict(Prec p, bool norm, const Sweep& s, hipStream_t st,
                                   int* nparts);
+// post-smoother of one V(1,1) cycle fused with the pre-smoother and the
+// restriction of the next (2D): with w = u + pf P ec (u: the pre-smoothed
+// iterate, ec: the coarse correction), out = w + sW K (b - sA L w), out_t =
+// out + sW K (b - sA L out), out_c = R (b - sA L out_t); the norm variant
+// (FP64 only) writes per-block sums of (b - sA L out)^2 to partials
+hipError_t launch_post_pre_restrict(Prec p, bool norm, const Sweep& s, hipStream_t st,
+                                    int* nparts);
 // u (fine, n interior) += pf * P ec (coarse, n/2 interior)
 hipError_t launch_prolong(Prec p, int d, int n, int batch, const void* ec,
                           void* u, double pf, hipStream_t st);

@@ -1747,6 +1747,324 @@ k_sr2d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out,
 }
 
 // ---------------------------------------------------------------------------
+// Post-smoothing of one V(1,1) cycle fused with the pre-smoothing and the
+// restriction of the next (2D): from the pre-smoothed iterate t and the
+// coarse correction ec,
+//   w  = t + pf P ec,  uo = w + sW K_c (b - sA L w)         (end of cycle k)
+//   t2 = uo + sW K_c (b - sA L uo),  bc = R (b - sA L t2)    (cycle k + 1)
+// and the norm variant sums (b - sA L uo)^2 over the owned nodes (the
+// residual of u_{k+1}).  x strips march over rows through seven stages,
+// each one or two rows behind the one it reads, with one barrier per row: at
+// step s the interpolated iterate of row s, the first residual of row s-1,
+// the new iterate of row s-3, its residual of row s-4, the next
+// pre-smoothed iterate of row s-6, its residual of row s-7 and the
+// restriction of row s-8.  u is loaded on the strip plus a ring of 5 (each
+// stage is valid one column further in).  Stored values enter later stages
+// as stored.  The coarse correction is read per lane (one or two coarse
+// values per row pair, L2 hits) two row pairs ahead.
+// ---------------------------------------------------------------------------
+template <typename S, typename C, int TX, int NT, int PD, int UN, bool NTS, bool NORM>
+__global__ void __launch_bounds__(NT)
+k_psr2d(const S* __restrict__ t, const S* __restrict__ ec, const S* __restrict__ b,
+        S* __restrict__ uo, S* __restrict__ t2, S* __restrict__ bc, int n, int nc,
+        int tiles_x, int ychunk, int nchunks, C sA, C sW, C c0, C c1, C c2, C pf,
+        double* __restrict__ partials) {
+    constexpr int W = TX + 11;            // columns x0-5 .. x0+TX+5
+    constexpr int M = (W + NT - 1) / NT;
+    constexpr int LW = W + 2 + 65;        // one guard each side, scratch for idle lanes
+    constexpr int HC = TX / 2;
+    constexpr int MC = (HC + NT - 1) / NT;
+    constexpr int RS = PD + 1;
+    static_assert(TX % 2 == 0, "even strips");
+    static_assert(UN % RS == 0 && UN % 4 == 0, "unroll covers the rings and the row pairs");
+    __shared__ C wL[2][LW];   // interpolated iterate
+    __shared__ C aL[4][LW];   // its residual
+    __shared__ C kL[2][LW];   // new iterate u_{k+1}
+    __shared__ C gL[4][LW];   // its residual
+    __shared__ C oL[2][LW];   // next pre-smoothed iterate
+    __shared__ C fL[2][LW];   // its residual
+    __shared__ double red[NT / 64];
+
+    const int total = tiles_x * nchunks;
+    const int lg = xcd_remap(blockIdx.x, total);
+    const int tx = lg % tiles_x, ch = lg / tiles_x;
+    const long area = (long)n * n;
+    t += (long)blockIdx.y * area;
+    b += (long)blockIdx.y * area;
+    uo += (long)blockIdx.y * area;
+    t2 += (long)blockIdx.y * area;
+    ec += (long)blockIdx.y * nc * nc;
+    bc += (long)blockIdx.y * nc * nc;
+    const int x0 = tx * TX;
+    const int Y0 = ch * ychunk, Y1 = min(Y0 + ychunk, nc);
+    const int o0 = 2 * Y0, o1 = Y1 == nc ? n : 2 * Y1;
+    const int th = threadIdx.x;
+    const int lane = th & 63;
+
+    int li[M];
+    unsigned gb[M], ca[M], cb[M];
+    bool col[M], own[M], odd[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const int j = th + m * NT;
+        const bool inr = j < W;
+        const int gx = x0 - 5 + j;
+        col[m] = inr && gx >= 0 && gx < n;
+        own[m] = col[m] && gx >= x0 && gx < x0 + TX;
+        li[m] = inr ? j + 1 : W + 2 + lane;
+        gb[m] = col[m] ? (unsigned)(gx * (int)sizeof(S)) : kOob;
+        // linear interpolation in x: grid coordinate g = gx + 1; even g sits
+        // on coarse node g/2 - 1, odd g between (g-1)/2 - 1 and (g+1)/2 - 1
+        const int g = gx + 1;
+        odd[m] = (g & 1) != 0;
+        const int ia = odd[m] ? (g - 1) / 2 - 1 : g / 2 - 1;
+        const int ib = odd[m] ? (g + 1) / 2 - 1 : ia;
+        ca[m] = (inr && ia >= 0 && ia < nc && g >= 0) ? (unsigned)(ia * (int)sizeof(S)) : kOob;
+        cb[m] = (inr && ib >= 0 && ib < nc && g >= 0) ? (unsigned)(ib * (int)sizeof(S)) : kOob;
+    }
+    int cq[MC];
+    unsigned cgb[MC];
+#pragma unroll
+    for (int q = 0; q < MC; ++q) {
+        const int i = th + q * NT;
+        const bool ok = i < HC && x0 / 2 + i < nc;
+        cq[q] = i < HC ? 2 * i + 7 : W + 2 + lane;  // local column 2 i + 6, guard + 1
+        cgb[q] = ok ? (unsigned)((x0 / 2 + i) * (int)sizeof(S)) : kOob;
+    }
+
+    // rows any output depends on
+    const int tlast = min(n - 1, 2 * Y1 + 5), blast = min(n - 1, 2 * Y1 + 4);
+    const int clast = min(nc - 1, Y1 + 2);
+    S rt[RS][M], rb[RS][M], rca[2][M], rcb[2][M];
+    auto issue_t = [&](int p, int k) {
+        const rsrc_t r = line_rsrc(t, (long)p * n, n, p >= 0 && p <= tlast);
+#pragma unroll
+        for (int m = 0; m < M; ++m) rt[k][m] = bload<S>(r, gb[m]);
+    };
+    auto issue_b = [&](int p, int k) {
+        const rsrc_t r = line_rsrc(b, (long)p * n, n, p >= 0 && p <= blast);
+#pragma unroll
+        for (int m = 0; m < M; ++m) rb[k][m] = bload<S>(r, gb[m]);
+    };
+    auto issue_c = [&](int Y, int k) {
+        const rsrc_t r = line_rsrc(ec, (long)Y * nc, nc, Y >= 0 && Y <= clast);
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            rca[k][m] = bload<S>(r, ca[m]);
+            rcb[k][m] = bload<S>(r, cb[m]);
+        }
+    };
+    // x-interpolated coarse value (the same sums as the interpolation operator)
+    auto qx = [&](S a, S bb, int m) -> C {
+        C q = cvt<C>(a);
+        q += odd[m] ? cvt<C>(bb) : C(0);
+        return (odd[m] ? C(0.5) : C(1)) * q;
+    };
+
+    // histories at this lane's columns, on entry to step s:
+    //   w rows s-1..s-3, first residual rows s-2..s-4, u_{k+1} rows
+    //   s-4..s-6, its residual rows s-5..s-7, t2 rows s-7, s-8, b rows
+    //   s-1..s-7, and the x-interpolated coarse row of the last even row
+    C w1[M], w2[M], w3[M], a1[M], a2[M], a3[M], k1[M], k2[M], k3[M];
+    C g1[M], g2[M], g3[M], o1v[M], o2v[M], qprev[M];
+    C bh[7][M];
+    C acc[MC];
+    double nacc = 0.0;
+    const int s0 = 2 * Y0 - 5, s1 = 2 * Y1 + 8;
+    {
+        // coarse row Y0-3 (interpolation of row s0), row Y0-2 (first even
+        // step), then the rolling prefetch
+        S pa[M], pb[M];
+        {
+            const int Y = Y0 - 3;
+            const rsrc_t r = line_rsrc(ec, (long)Y * nc, nc, Y >= 0 && Y <= clast);
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                pa[m] = bload<S>(r, ca[m]);
+                pb[m] = bload<S>(r, cb[m]);
+            }
+        }
+        issue_c(Y0 - 2, 0);
+#pragma unroll
+        for (int q = 0; q < PD; ++q) {
+            issue_t(s0 + q, q);
+            issue_b(s0 + q, q);
+        }
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            qprev[m] = qx(pa[m], pb[m], m);
+            w1[m] = w2[m] = w3[m] = a1[m] = a2[m] = a3[m] = C(0);
+            k1[m] = k2[m] = k3[m] = g1[m] = g2[m] = g3[m] = o1v[m] = o2v[m] = C(0);
+#pragma unroll
+            for (int q = 0; q < 7; ++q) bh[q][m] = C(0);
+        }
+#pragma unroll
+        for (int q = 0; q < MC; ++q) acc[q] = C(0);
+        for (int i = th; i < LW; i += NT) {
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                wL[q][i] = kL[q][i] = oL[q][i] = fL[q][i] = C(0);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) aL[q][i] = gL[q][i] = C(0);
+        }
+    }
+
+    auto step = [&](int s, auto kc) {
+        constexpr int k = decltype(kc)::k;  // (s - s0) % UN; s0 is odd
+        __syncthreads();
+        issue_t(s + PD, (k + PD) % RS);
+        issue_b(s + PD, (k + PD) % RS);
+        // odd s: coarse row (s+3)/2, consumed at the even step s+3
+        if ((k & 1) == 0) issue_c((s + 3) / 2, ((k + 2) / 2) % 2);
+        // interpolated iterate of row s
+        const bool sin = s >= 0 && s < n;
+        C w0[M];
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            C pe;
+            if ((k & 1) == 1) {  // s even: between coarse rows s/2 - 1 and s/2
+                const C qn = qx(rca[((k - 1) / 2) % 2][m], rcb[((k - 1) / 2) % 2][m], m);
+                pe = C(0.5) * (qprev[m] + qn);
+                qprev[m] = qn;
+            } else {             // s odd: on coarse row (s-1)/2
+                pe = qprev[m];
+            }
+            const C v = cvt<C>(rt[k % RS][m]) + pf * pe;
+            w0[m] = (sin && col[m]) ? v : C(0);
+            wL[s & 1][li[m]] = w0[m];
+        }
+        // first residual of row s-1
+        {
+            const bool pin = s - 1 >= 0 && s - 1 < n;
+            const C* Wr = wL[(s + 1) & 1];
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                const int q = li[m];
+                const C lap = C(4) * w1[m] - Wr[q - 1] - Wr[q + 1] - w2[m] - w0[m];
+                const C r = (pin && col[m]) ? bh[0][m] - sA * lap : C(0);
+                aL[(s + 3) & 3][q] = r;
+                a3[m] = a2[m];
+                a2[m] = a1[m];
+                a1[m] = r;  // rows s-1, s-2, s-3 after this
+            }
+        }
+        // new iterate of row s-3 (first residual rows s-4, s-3, s-2)
+        C kn[M];
+        {
+            const int p = s - 3;
+            const bool pin = p >= 0 && p < n;
+            const C* R0 = aL[(s + 0) & 3];  // row s - 4
+            const C* R1 = aL[(s + 1) & 3];  // row s - 3
+            const C* R2 = aL[(s + 2) & 3];  // row s - 2
+            const rsrc_t ro = line_rsrc(uo, (long)p * n, n, p >= o0 && p < o1);
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                const int q = li[m];
+                // a1 = row s-1 now, a2 = s-2, a3 = s-3; row s-4 from LDS
+                const C fc = R1[q - 1] + R1[q + 1] + R0[q] + a2[m];
+                const C cn = R0[q - 1] + R0[q + 1] + R2[q - 1] + R2[q + 1];
+                const C v = w3[m] + sW * (c0 * a3[m] + c1 * fc + c2 * cn);
+                const S vs = static_cast<S>(v);
+                bstore<NTS>(vs, ro, own[m] ? gb[m] : kOob);
+                kn[m] = (pin && col[m]) ? cvt<C>(vs) : C(0);
+                kL[p & 1][q] = kn[m];
+            }
+        }
+        // its residual, row s-4 (new iterate rows s-5, s-4, s-3)
+        {
+            const int p = s - 4;
+            const bool pin = p >= 0 && p < n;
+            const bool pown = p >= o0 && p < o1;
+            const C* K = kL[p & 1];
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                const int q = li[m];
+                const C lap = C(4) * k1[m] - K[q - 1] - K[q + 1] - k2[m] - kn[m];
+                const C r = (pin && col[m]) ? bh[3][m] - sA * lap : C(0);
+                gL[p & 3][q] = r;
+                if (NORM) nacc += (pown && own[m]) ? (double)r * (double)r : 0.0;
+                g3[m] = g2[m];
+                g2[m] = g1[m];
+                g1[m] = r;  // rows s-4, s-5, s-6 after this
+            }
+        }
+        // next pre-smoothed iterate of row s-6 (residual rows s-7, s-6, s-5)
+        C on[M];
+        {
+            const int p = s - 6;
+            const bool pin = p >= 0 && p < n;
+            const C* Q0 = gL[(s + 1) & 3];  // row s - 7
+            const C* Q1 = gL[(s + 2) & 3];  // row s - 6
+            const C* Q2 = gL[(s + 3) & 3];  // row s - 5
+            const rsrc_t ro = line_rsrc(t2, (long)p * n, n, p >= o0 && p < o1);
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                const int q = li[m];
+                // g1 = row s-4, g2 = s-5, g3 = s-6; row s-7 from LDS
+                const C fc = Q1[q - 1] + Q1[q + 1] + Q0[q] + g2[m];
+                const C cn = Q0[q - 1] + Q0[q + 1] + Q2[q - 1] + Q2[q + 1];
+                const C v = k3[m] + sW * (c0 * g3[m] + c1 * fc + c2 * cn);
+                const S vs = static_cast<S>(v);
+                bstore<NTS>(vs, ro, own[m] ? gb[m] : kOob);
+                on[m] = (pin && col[m]) ? cvt<C>(vs) : C(0);
+                oL[p & 1][q] = on[m];
+            }
+        }
+        // its residual, row s-7 (rows s-8, s-7, s-6)
+        {
+            const C* O = oL[(s + 1) & 1];  // row s - 7
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                const int q = li[m];
+                const C lap = C(4) * o1v[m] - O[q - 1] - O[q + 1] - o2v[m] - on[m];
+                fL[(s + 1) & 1][q] = bh[6][m] - sA * lap;
+            }
+        }
+        // restriction of row f = s-8 (written by the previous step)
+        const int f = s - 8;
+        if (f >= 2 * Y0 && f <= 2 * Y1) {
+            const C* R = fL[f & 1];
+            const rsrc_t rc = line_rsrc(bc, (long)(f / 2 - 1) * nc, nc, true);
+#pragma unroll
+            for (int q = 0; q < MC; ++q) {
+                const int c = cq[q];
+                const C xs = C(0.5) * R[c] + C(0.25) * (R[c - 1] + R[c + 1]);
+                if ((f & 1) == 0) {
+                    if (f > 2 * Y0) {
+                        acc[q] += C(0.25) * xs;
+                        bstore<false>(static_cast<S>(acc[q]), rc, cgb[q]);
+                    }
+                    acc[q] = C(0.25) * xs;
+                } else {
+                    acc[q] += C(0.5) * xs;
+                }
+            }
+        }
+        // shift the histories; b of row s enters
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            w3[m] = w2[m];
+            w2[m] = w1[m];
+            w1[m] = w0[m];
+            k3[m] = k2[m];
+            k2[m] = k1[m];
+            k1[m] = kn[m];
+            o2v[m] = o1v[m];
+            o1v[m] = on[m];
+#pragma unroll
+            for (int q = 6; q > 0; --q) bh[q][m] = bh[q - 1][m];
+            bh[0][m] = cvt<C>(rb[k % RS][m]);
+        }
+    };
+    march<UN>(s0, s1, step);
+    if (NORM) {
+        const double sm = block_sum<NT>(nacc, red);
+        if (th == 0) partials[(long)blockIdx.y * gridDim.x + blockIdx.x] = sm;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Pre-smoothing fused with the restriction (3D, any iterate):
 // out = u + sW K_c (b - sA L u) and bc = R (b - sA L out).  A workgroup owns
 // a TX x TY tile of fine columns and marches over planes; every lane keeps
@@ -3101,6 +3419,62 @@ hipError_t launch_smooth_restrict(Prec p, bool norm, const Sweep& s, hipStream_t
         default:
             if (norm) return hipErrorInvalidValue;
             return sr_impl<_Float16, float>(s, false, st, nparts);
+    }
+}
+
+template <typename S, typename C, int TX, int NT, int PD, int UN, bool NTS>
+hipError_t launch_psr2d(const Sweep& s, bool norm, int want, int minc, hipStream_t st,
+                        int* nparts) {
+    const int n = s.n, nc = (n + 1) / 2 - 1;
+    const int tx = cdiv(n, TX);
+    const int yc = pick_chunk(nc, tx, want, minc);
+    const int nch = cdiv(nc, yc);
+    dim3 grid(tx * nch, s.batch);
+    if (nparts) *nparts = grid.x * grid.y;
+    if (norm && (long)grid.x * grid.y > s.partials_cap) return hipErrorInvalidValue;
+    const S* u = static_cast<const S*>(s.u);
+    const S* ec = static_cast<const S*>(s.ec);
+    const S* b = static_cast<const S*>(s.b);
+    S* out = static_cast<S*>(s.out);
+    S* out_t = static_cast<S*>(s.out_t);
+    S* bc = static_cast<S*>(s.out_c);
+    const C sA = C(s.sA), sW = C(s.sW), c0 = C(s.c[0]), c1 = C(s.c[1]), c2 = C(s.c[2]);
+    const C pf = C(s.pf);
+#define PSR2(NM)                                                                              \
+    hipLaunchKernelGGL((k_psr2d<S, C, TX, NT, PD, UN, NTS, NM>), grid, dim3(NT), 0, st, u, ec, \
+                       b, out, out_t, bc, n, nc, tx, yc, nch, sA, sW, c0, c1, c2, pf,         \
+                       s.partials)
+    if (norm) PSR2(true);
+    else PSR2(false);
+#undef PSR2
+    return hipGetLastError();
+}
+
+template <typename S, typename C>
+hipError_t psr_impl(const Sweep& s, bool norm, hipStream_t st, int* nparts) {
+    const int n = s.n, nc = (n + 1) / 2 - 1;
+    if (nc < 1 || s.d != 2 || !s.u || !s.ec || !s.out || !s.out_t || !s.out_c)
+        return hipErrorInvalidValue;
+    // shapes measured on MI355X in FP64: 512-wide strips, one column per
+    // lane (two spill), prefetch two rows ahead; n = 4095: 139 us against
+    // 170 us for the post-smoother and the fused pre-smoother + restriction
+    // (256-wide strips 151 us, prefetch one row ahead 152-164 us); n = 2047:
+    // 47 against 50 us
+    if (n >= 1500) return launch_psr2d<S, C, 512, 576, 2, 12, true>(s, norm, 256, 16, st, nparts);
+    if (n >= 700) return launch_psr2d<S, C, 256, 320, 1, 4, false>(s, norm, 512, 4, st, nparts);
+    return launch_psr2d<S, C, 128, 192, 1, 4, false>(s, norm, 1024, 2, st, nparts);
+}
+
+hipError_t launch_post_pre_restrict(Prec p, bool norm, const Sweep& s, hipStream_t st,
+                                    int* nparts) {
+    switch (p) {
+        case P64: return psr_impl<double, double>(s, norm, st, nparts);
+        case P32:
+            if (norm) return hipErrorInvalidValue;
+            return psr_impl<float, float>(s, false, st, nparts);
+        default:
+            if (norm) return hipErrorInvalidValue;
+            return psr_impl<_Float16, float>(s, false, st, nparts);
     }
 }
 

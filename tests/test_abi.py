@@ -96,6 +96,7 @@ def test_null_handle_is_rejected_everywhere():
         "mg_sweep_correct": (null, i(0), i(0), p, p, p, p, null),
         "mg_sweep_zero_restrict": (null, i(0), i(0), p, p, p, null),
         "mg_sweep_smooth_restrict": (null, i(0), i(0), p, p, p, p, null),
+        "mg_sweep_post_pre_restrict": (null, i(0), i(0), p, p, p, p, p, p, null),
         "mg_coarse_cycle": (null, i(0), i(0), p, p, null),
         "mg_residual_norm": (null, p, p, p, null),
         "mg_get_timing": (null, i(0), i(0), p, p),

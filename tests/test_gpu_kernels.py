@@ -187,6 +187,55 @@ def test_smooth_restrict_parity(d, N, level, batch, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32_ir", "fp16_ir"])
+@pytest.mark.parametrize("N,level,batch", [(n, 0, 1) for n in CASES_2D] +
+                         [(1024, 1, 1), (2048, 0, 1), (4096, 0, 1), (64, 0, 3), (8, 0, 2)])
+def test_post_pre_restrict_parity(N, level, batch, prec):
+    # the sweeps between two 2D V(1,1) cycles as one kernel: w = t + P ec,
+    # u_{k+1} = w + M (b - A w), t2 = u_{k+1} + M (b - A u_{k+1}) and
+    # bc = R (b - A t2), against the oracle's interpolation, smoother,
+    # residual and restriction (strips with ragged last strips and row
+    # chunks, the large-grid shape at N >= 4096, several batch entries)
+    need_gpu()
+    d = 2
+    Nl = N >> level
+    rng = np.random.default_rng(500 + N + level + batch)
+    shp, shc = (Nl - 1,) * d, (Nl // 2 - 1,) * d
+    c = _coeffs(d)
+    sig, sigc = _sigma(prec, Nl), _sigma(prec, Nl // 2)
+    ts = _roundtrip(_rand(rng, (batch,) + shp), prec)
+    ecs = _roundtrip(_rand(rng, (batch,) + shc), prec)
+    b = _roundtrip(_rand(rng, (batch,) + shp, 1.0 if prec != "fp64" else Nl * Nl), prec)
+    say("post-pre-restrict", N, level, batch, prec)
+    T = _tdt(prec)
+    with make_mg(N, d, c, batch=batch) as mg:
+        out = torch.empty((batch,) + shp, dtype=T, device="cuda")
+        out_t = torch.empty((batch,) + shp, dtype=T, device="cuda")
+        bc = torch.empty((batch,) + shc, dtype=T, device="cuda")
+        mg.sweep_post_pre_restrict(level, prec, dev(ts, T), dev(ecs, T), dev(b, T), out, out_t,
+                                   bc)
+        torch.cuda.synchronize()
+        got, got_t, got_c = host(out), host(out_t), host(bc)
+    h2 = 1.0 / (Nl * Nl)
+    for e in range(batch):
+        w = O.prolong_add(d, Nl, ecs[e] / sigc, ts[e] / sig)
+        u1 = O.smooth(d, Nl, c, w, b[e])
+        t2 = O.smooth(d, Nl, c, u1, b[e])
+        want_c = O.restrict(d, Nl, O.residual(d, Nl, t2, b[e]))
+        bmag = h2 * sig * np.abs(b[e]).max()
+        # each stage as in the single-sweep tests; the stored u_{k+1} (half
+        # an ulp of S) enters the next sweep through A (weights 4d / h^2)
+        # and K (weights below 1 in h^2 units)
+        tol1 = _tol(prec, 2 * np.abs(w).max() * sig, bmag, out_mag=np.abs(u1).max() * sig)
+        tol2 = 2 * tol1 + _tol(prec, np.abs(u1).max() * sig, bmag,
+                               out_mag=np.abs(t2).max() * sig)
+        tol_c = _tol(prec, np.abs(b[e]).max(), 4 * d * Nl * Nl / sig * np.abs(t2).max() * sig,
+                     out_mag=np.abs(want_c).max()) + 4 * d * Nl * Nl / sig * tol2
+        assert np.max(np.abs(got[e] - u1 * sig)) <= tol1, e
+        assert np.max(np.abs(got_t[e] - t2 * sig)) <= tol2, e
+        assert np.max(np.abs(got_c[e] - want_c)) <= tol_c, e
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_ir", "fp16_ir"])
 @pytest.mark.parametrize("d,N", [(2, n) for n in CASES_2D] + [(3, n) for n in CASES_3D])
 def test_prolong_parity(d, N, prec):
     need_gpu()
