@@ -58,10 +58,10 @@ def sweep_bytes_per_pt(kind, d):
 # commands are in profiles/hbm_counters_fp64_sweeps.md.  Valid for the
 # kernels and launch shapes they were taken on; set to None when those change.
 PMC = {
-    ("poisson3d_n256", "smooth_restrict"): (142673, 147213),
-    ("poisson3d_n256", "smooth_correct"): (149171, 144051),
-    ("poisson2d_n4096", "smooth_restrict"): (143194, 165822),
-    ("poisson2d_n4096", "smooth_correct"): (164105, 135206),
+    ("poisson3d_n256", "smooth_restrict"): (142850, 148637),
+    ("poisson3d_n256", "smooth_correct"): (149186, 143837),
+    ("poisson2d_n4096", "smooth_restrict"): (143204, 165370),
+    ("poisson2d_n4096", "post_pre_restrict"): (159432, 303612),
 }
 PMC_COPY = {  # copy bytes, FETCH_SIZE KiB, WRITE_SIZE KiB of the same run
     "poisson3d_n256": (255 ** 3 * 8, 64792, 129542),
