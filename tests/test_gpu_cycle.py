@@ -255,3 +255,37 @@ def test_zero_tolerance_runs_to_the_cycle_limit():
         got = host(u)
     assert st["code"] == -3 and st["cycles"] == 6
     assert np.max(np.abs(got - iters[6][0])) <= 1e-10 * np.abs(iters[6][0]).max()
+
+
+@pytest.mark.parametrize("N,batch", [(8, 1), (16, 2), (256, 1)])
+def test_chained_2d_solve_matches_oracle_and_single_cycles(N, batch):
+    # 2D solves chain the cycles (the post-smoother of one cycle and the
+    # pre-smoother and restriction of the next are one kernel); N = 8 has
+    # only the exact 3x3 solve below the finest level.  The iterate and the
+    # history match the oracle, the iterates match repeated single V-cycles
+    # of the unchained kernels (mg_vcycle), and one more cycle is started
+    # than completed
+    need_gpu()
+    d = 2
+    rng = np.random.default_rng(60 + N + batch)
+    shp = (batch,) + (N - 1,) * d
+    u0 = rng.uniform(-1, 1, shp)
+    b = rng.standard_normal(shp) * N
+    tol = 1e-9
+    iters, hist = _oracle_batched_history(d, N, _c(d), u0, b, 20)
+    k_or = next(k for k, h in enumerate(hist) if h <= tol * hist[0])
+    say("chained-solve", N, batch)
+    with make_mg(N, d, _c(d), batch=batch) as mg:
+        u = dev(u0)
+        st = mg.solve(dev(b), u, tol=tol)
+        got = host(u)
+        v = dev(u0)
+        for _ in range(k_or):
+            mg.vcycle(dev(b), v)
+        got_v = host(v)
+    assert st["code"] == 0 and st["cycles"] == k_or
+    assert st["cycles_run"] == k_or + 1
+    assert np.allclose(st["history"], hist[:k_or + 1], rtol=1e-8, atol=1e-13 * hist[0])
+    want = np.stack(iters[k_or])
+    assert np.max(np.abs(got - want)) <= 1e-10 * np.abs(want).max()
+    assert np.max(np.abs(got - got_v)) <= 1e-12 * np.abs(want).max()
