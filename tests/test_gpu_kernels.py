@@ -235,6 +235,23 @@ def test_post_pre_restrict_parity(N, level, batch, prec):
         assert np.max(np.abs(got_c[e] - want_c)) <= tol_c, e
 
 
+def test_post_pre_restrict_rejects_bad_requests():
+    # 2D only, and only where a coarser level exists; nothing is launched
+    need_gpu()
+    from paper_2206_05543_amd._lib import MGError
+    f = lambda N, d: torch.zeros((N - 1,) * d, dtype=torch.float64, device="cuda")
+    fc = lambda N, d: torch.zeros((N // 2 - 1,) * d, dtype=torch.float64, device="cuda")
+    with make_mg(16, 3, _coeffs(3)) as mg:
+        with pytest.raises(MGError, match="2D only"):
+            mg.sweep_post_pre_restrict(0, "fp64", f(16, 3), fc(16, 3), f(16, 3), f(16, 3),
+                                       f(16, 3), fc(16, 3))
+    with make_mg(8, 2, _coeffs(2)) as mg:
+        last = mg.num_levels - 1
+        with pytest.raises((MGError, ValueError)):
+            mg.sweep_post_pre_restrict(last, "fp64", f(4, 2), fc(4, 2), f(4, 2), f(4, 2),
+                                       f(4, 2), fc(4, 2))
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32_ir", "fp16_ir"])
 @pytest.mark.parametrize("d,N", [(2, n) for n in CASES_2D] + [(3, n) for n in CASES_3D])
 def test_prolong_parity(d, N, prec):
