@@ -7,8 +7,8 @@ with inputs resident in HBM.  The headline value is fine-grid unknowns per
 second per V-cycle over the pair: sum(unknowns x cycles) / sum(solve time).
 
 Also reported: per-workload rates, the roofline of the dominant kernel (of
-the fine level's two kernels, the one with the larger total time, timed live
-with HIP events on the launch stream), per-level kernel times and GB/s (extra solves after the timed
+the fine-level kernels timed live with HIP events on the launch stream, the
+one with the largest total time), per-level kernel times and GB/s (extra solves after the timed
 region, every launch timed), the time to 1e-10 of the 3D N=512 noisy problem in FP64 and
 with FP32 / FP16 V-cycles inside FP64 refinement, and the CPU oracle timed on
 a bounded sample of the same workloads (single thread).
