@@ -1,0 +1,61 @@
+"""Host-side logic of bench.py (no GPU): the algorithmic byte counts behind
+the roofline, the HBM-traffic table and its copy calibration, and the
+one-GPU contract.
+"""
+import importlib.util
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def bench():
+    spec = importlib.util.spec_from_file_location("bench_under_test",
+                                                  os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_algorithmic_bytes_per_fine_node(bench):
+    # FP64: read u and b, write the new iterate (24 B) and one coarse value
+    # per 2^d fine nodes (the coarse right-hand side or the correction); the
+    # chained 2D kernel reads u1, b, e_c and writes u, the next u1 and b_c
+    assert bench.sweep_bytes_per_pt("smooth_restrict", 2) == 26.0
+    assert bench.sweep_bytes_per_pt("smooth_restrict", 3) == 25.0
+    assert bench.sweep_bytes_per_pt("smooth_correct", 2) == 26.0
+    assert bench.sweep_bytes_per_pt("smooth_correct", 3) == 25.0
+    assert bench.sweep_bytes_per_pt("post_pre_restrict", 2) == 36.0
+    for kind in bench.SWEEP_KINDS:
+        for d in (2, 3):
+            assert bench.level_bytes_per_pt(kind, d) == bench.sweep_bytes_per_pt(kind, d)
+    # the zero-guess sweeps read no iterate
+    assert bench.level_bytes_per_pt("smooth_zero", 3) == 16.0
+    assert bench.level_bytes_per_pt("zero_smooth_restrict", 2) == 18.0
+    assert bench.level_bytes_per_pt("tail", 2) is None
+
+
+def test_counter_table_is_consistent_with_the_algorithmic_bytes(bench):
+    # the copy calibration: FETCH_SIZE counts half the copied bytes,
+    # WRITE_SIZE all of them; every measured kernel moves at least its
+    # algorithmic bytes and at most 15% more (halo re-reads)
+    for name, (cbytes, cfetch, cwrite) in bench.PMC_COPY.items():
+        assert cbytes / (cfetch * 1024.0) == pytest.approx(2.0, rel=1e-3)
+        assert cbytes / (cwrite * 1024.0) == pytest.approx(1.0, rel=1e-3)
+    for (name, kind) in bench.PMC:
+        d, N = bench.WORKLOADS[name]
+        algo = bench.sweep_bytes_per_pt(kind, d) * (N - 1) ** d
+        ratio = bench.hbm_traffic(name, kind) / algo
+        assert 1.0 <= ratio <= 1.15, (name, kind, ratio)
+    assert bench.hbm_traffic("poisson2d_n4096", "no_such_kernel") is None
+
+
+def test_more_than_one_gpu_is_refused():
+    out = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                         capture_output=True, text=True, timeout=120)
+    assert out.returncode == 2
+    assert "one GPU only" in out.stdout
