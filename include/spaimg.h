@@ -90,6 +90,10 @@ extern "C" {
 #define MG_PREC_FP16_IR 2   /* ... around V-cycles with FP16 storage, FP32
                                arithmetic and per-level power-of-two scaling  */
 
+/* checkpoint storage of mg_checkpoint and mg_vcycle_adjoint */
+#define MG_CKPT_FP64 0      /* FP64 copy of the iterate                      */
+#define MG_CKPT_FP32 1      /* FP32 rounding (to nearest even) of the iterate */
+
 /* operation codes of mg_sweep */
 #define MG_OP_SMOOTH 0       /* out = u + M (b - A u)                          */
 #define MG_OP_SMOOTH_ZERO 1  /* out = M b (smoothing from a zero guess)        */
@@ -125,7 +129,9 @@ typedef struct mg_stats {
                           before the host reads the norm                     */
     double r0_norm;    /* ||b - A u_0||_2 (whole batch)                       */
     double rk_norm;    /* ||b - A u_k||_2                                      */
-    double b_norm;     /* ||b||_2 (filled only when res_hist is given)        */
+    double b_norm;     /* ||b||_2 (whole batch; one extra pass over b), so
+                          that ||r_k|| / ||b|| can be reported beside the
+                          stopping rule's ||r_k|| / ||r_0||                   */
     double* res_hist;  /* optional host array: ||r_j||_2, j = 0..cycles       */
     int hist_cap;      /* its capacity (entries)                               */
     double elapsed_ms; /* device time of the whole solve (HIP events)         */
@@ -162,14 +168,31 @@ int mg_vcycle(mg_handle_t h, const double* b, double* u, void* stream);
 int mg_solve(mg_handle_t h, const double* b, double* u, double tol, mg_stats* st,
              void* stream);
 
-/* Reverse-mode derivative of one FP64 V(1,1) cycle u_out = V(u_in, b; c):
- * given ubar_out = dL/du_out, writes ubar_in = dL/du_in (may alias
- * ubar_out), accumulates bbar_acc += dL/db (device, batch-shaped) and
- * cbar_acc[j] += dL/dc_j summed over the batch (HOST FP64 array of n_coeffs).
- * The forward states of every level are recomputed from u_in.  Uses A^T = A,
- * M^T = M (symmetric stencils with zero extension), P^T = 2^d R.
- * Synchronises `stream` (to return cbar_acc on the host). */
-int mg_vcycle_adjoint(mg_handle_t h, const double* b, const double* u_in,
+/* Per-cycle checkpoint of the cycle-start iterate u (device, batch-shaped
+ * FP64) for the adjoint's recomputation: ckpt (device, batch-shaped) receives
+ * u in FP64 (MG_CKPT_FP64) or rounded to FP32 (MG_CKPT_FP32).  With FP32 u is
+ * replaced in place by the rounded value, so the forward pass continues from
+ * exactly what the checkpoint holds and mg_vcycle_adjoint recomputes that
+ * cycle's states bit for bit.  The rounding is a non-differentiable step of
+ * the forward map; the adjoint passes derivatives through it unchanged
+ * (straight-through), which differs from the derivative of the unrounded
+ * FP64 map by O(2^-24) relative.  Does not synchronise.  Errors: MG_EINVAL for
+ * a null handle or pointer or a bad ckpt_dtype. */
+int mg_checkpoint(mg_handle_t h, double* u, void* ckpt, int ckpt_dtype, void* stream);
+
+/* Reverse-mode derivative of one FP64 V(1,1) cycle u_out = V(u_in, b; c)
+ * (Section 4 cycle, Section 2 smoother, differentiated by hand): given
+ * ubar_out = dL/du_out, writes ubar_in = dL/du_in (may alias ubar_out),
+ * accumulates bbar_acc += dL/db (device, batch-shaped) and cbar_acc[j] +=
+ * dL/dc_j summed over the batch (HOST FP64 array of n_coeffs).  u_in is the
+ * cycle's checkpoint as written by mg_checkpoint: device, batch-shaped, FP64
+ * (ckpt_dtype = MG_CKPT_FP64) or FP32 (MG_CKPT_FP32, widened exactly to FP64
+ * inside the library).  The forward states of every level are recomputed
+ * from it.  Uses A^T = A, M^T = M (symmetric stencils with zero extension),
+ * P^T = 2^d R.  Synchronises `stream` (to return cbar_acc on the host).
+ * Errors: MG_EINVAL for a null handle or pointer, a bad ckpt_dtype or a
+ * W(1,0) cycle setting. */
+int mg_vcycle_adjoint(mg_handle_t h, const double* b, const void* u_ckpt, int ckpt_dtype,
                       const double* ubar_out, double* ubar_in, double* bbar_acc,
                       double* cbar_acc, void* stream);
 

@@ -203,20 +203,34 @@ def vcycle_adjoint(d, N, c, u, b, ubar_out):
     return ubar_in, bbar, cbar
 
 
-def loss_kcycles(d, N, c, e0, b, K):
-    """L = sum over the batch of ||u_K||^2 with u_K = V^K(e0, b)."""
+def _checkpoint(u, ckpt):
+    """The cycle-start state as stored: unchanged ("fp64") or rounded to
+    FP32 to nearest even ("fp32"), the value the forward pass continues
+    from."""
+    if ckpt == "fp64":
+        return u
+    assert ckpt == "fp32", ckpt
+    return u.astype(np.float32).astype(np.float64)
+
+
+def loss_kcycles(d, N, c, e0, b, K, ckpt="fp64"):
+    """L = sum over the batch of ||u_K||^2 with u_K = V^K(e0, b); with
+    ckpt="fp32" every cycle starts from the FP32 rounding of its input."""
     L = 0.0
     for e in _f64(e0).reshape((-1,) + shape(d, N)):
         u = e
         for _ in range(K):
-            u = vcycle(d, N, c, u, b)
+            u = vcycle(d, N, c, _checkpoint(u, ckpt), b)
         L += float(np.dot(u.ravel(), u.ravel()))
     return L
 
 
-def grad_kcycles(d, N, c, e0, b, K):
+def grad_kcycles(d, N, c, e0, b, K, ckpt="fp64"):
     """(L, dL/dc, dL/db, dL/de0) for loss_kcycles by reverse sweeps of
-    vcycle_adjoint over per-cycle states."""
+    vcycle_adjoint over per-cycle states.  With ckpt="fp32" the states are
+    the FP32-rounded cycle inputs and the reverse sweep passes derivatives
+    through each rounding unchanged (straight-through: the rounding is
+    piecewise constant, so its derivative is taken as the identity)."""
     c = _coeffs(d, c)
     cbar = np.zeros(c.size)
     bbar = np.zeros(shape(d, N))
@@ -224,11 +238,12 @@ def grad_kcycles(d, N, c, e0, b, K):
     e0bar = np.zeros_like(e0)
     L = 0.0
     for s, e in enumerate(e0):
-        states = [e]
+        states, u = [], e
         for _ in range(K):
-            states.append(vcycle(d, N, c, states[-1], b))
-        L += float(np.dot(states[-1].ravel(), states[-1].ravel()))
-        ubar = 2.0 * states[-1]
+            states.append(_checkpoint(u, ckpt))
+            u = vcycle(d, N, c, states[-1], b)
+        L += float(np.dot(u.ravel(), u.ravel()))
+        ubar = 2.0 * u
         for k in range(K - 1, -1, -1):
             ubar, bb, cb = vcycle_adjoint(d, N, c, states[k], b, ubar)
             bbar += bb

@@ -3,8 +3,9 @@ arXiv 2206.05543): V(1,1) cycles for the 2D 5-point and 3D 7-point Dirichlet
 Laplacian with the optimised sparse-approximate-inverse smoothers, as gfx950
 HIP kernels behind the C ABI of include/spaimg.h.
 
-Importing the package loads nothing; ``paper_2206_05543_amd.api`` loads the
-library (and fails loudly if it is not built).
+Importing the package loads nothing; ``paper_2206_05543_amd._lib`` binds the
+library on first use (``_lib.lib()``, ``_lib.Multigrid``) and fails loudly if
+it is not built.
 """
 import math
 

@@ -23,6 +23,7 @@ TIME = {"smooth": 0, "smooth_zero": 1, "restrict": 2, "prolong": 3, "tail": 4,
         "ir_step": 5, "residual": 6, "smooth_correct": 7, "zero_smooth_restrict": 8,
         "smooth_restrict": 9, "post_pre_restrict": 10}
 STORAGE = {0: torch.float64, 1: torch.float32, 2: torch.float16}
+CKPT = {torch.float64: 0, torch.float32: 1}
 
 _lib = None
 
@@ -54,7 +55,8 @@ def lib():
         L.mg_set_coeffs.argtypes = [vp, dp, i]
         L.mg_vcycle.argtypes = [vp, vp, vp, vp]
         L.mg_solve.argtypes = [vp, vp, vp, dbl, ctypes.POINTER(MGStats), vp]
-        L.mg_vcycle_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, dp, vp]
+        L.mg_vcycle_adjoint.argtypes = [vp, vp, vp, i, vp, vp, vp, dp, vp]
+        L.mg_checkpoint.argtypes = [vp, vp, vp, i, vp]
         L.mg_sweep.argtypes = [vp, i, i, i, vp, vp, vp, vp]
         L.mg_coarse_cycle.argtypes = [vp, i, i, vp, vp, vp]
         L.mg_sweep_correct.argtypes = [vp, i, i, vp, vp, vp, vp, vp]
@@ -170,17 +172,30 @@ class Multigrid:
         rc = lib().mg_solve(self._h, self._field(b, name="b"), self._field(u, name="u"),
                             float(tol), ctypes.byref(st), _stream())
         out = {"cycles": st.cycles, "cycles_run": st.cycles_run, "r0": st.r0_norm,
-               "rk": st.rk_norm, "elapsed_ms": st.elapsed_ms,
+               "rk": st.rk_norm, "b_norm": st.b_norm, "elapsed_ms": st.elapsed_ms,
                "history": [hist[j] for j in range(min(st.cycles + 1, st.hist_cap))],
                "code": rc}
         if rc not in (MG_OK, MG_ENOCONV):
             _check(rc)
         return out
 
+    def checkpoint(self, u, ckpt):
+        """ckpt <- u (FP64) or its FP32 rounding, which then replaces u."""
+        if ckpt.dtype not in CKPT:
+            raise TypeError("checkpoints are float64 or float32")
+        _check(lib().mg_checkpoint(self._h, self._field(u, name="u"),
+                                   self._field(ckpt, dtype=ckpt.dtype, name="ckpt"),
+                                   CKPT[ckpt.dtype], _stream()))
+        return ckpt
+
     def vcycle_adjoint(self, b, u_in, ubar_out, ubar_in, bbar_acc, cbar_acc):
+        """u_in: the cycle's checkpoint, float64 or float32."""
+        if u_in.dtype not in CKPT:
+            raise TypeError("checkpoints are float64 or float32")
         cb = (ctypes.c_double * self.ncoef)(*[float(x) for x in cbar_acc])
         _check(lib().mg_vcycle_adjoint(
-            self._h, self._field(b, name="b"), self._field(u_in, name="u_in"),
+            self._h, self._field(b, name="b"),
+            self._field(u_in, dtype=u_in.dtype, name="u_in"), CKPT[u_in.dtype],
             self._field(ubar_out, name="ubar_out"), self._field(ubar_in, name="ubar_in"),
             self._field(bbar_acc, name="bbar_acc"), cb, _stream()))
         return [cb[j] for j in range(self.ncoef)]

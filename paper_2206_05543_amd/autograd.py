@@ -7,10 +7,15 @@ level's states from the checkpoint.  Gradients flow to the smoother
 coefficients c (any float dtype; promoted to FP64 for the cycle, gradient
 accumulated in FP64), to b and to u_0.
 
-With checkpoint_dtype=torch.float32 the forward pass rounds each cycle-start
-iterate to FP32, stores it, and continues from the rounded value; the
-recomputation in the backward pass is then bit-identical to the forward pass
-and the gradient is exact for the computed forward map.
+Checkpoints are written by the library (mg_checkpoint) and read by it
+(mg_vcycle_adjoint).  With checkpoint_dtype=torch.float32 the forward pass
+rounds each cycle-start iterate to FP32, stores it, and continues from the
+rounded value, so the backward recomputation reproduces the forward states
+bit for bit.  The rounding itself is piecewise constant; the backward pass
+treats it as the identity (a straight-through derivative).  For K >= 2 the
+gradient is therefore that of the FP64 cycles evaluated on the rounded
+states, which differs from the gradient of the unrounded FP64 map by
+O(2^-24) relative.
 """
 import math
 
@@ -28,12 +33,9 @@ class _KCycles(torch.autograd.Function):
         u = u0.detach().to(torch.float64).contiguous().clone()
         ckpts = []
         for _ in range(K):
-            if ckpt_dtype == torch.float64:
-                ckpts.append(u.clone())
-            else:
-                ck = u.to(ckpt_dtype)
-                u = ck.to(torch.float64).contiguous()
-                ckpts.append(ck)
+            ck = torch.empty(u.shape, dtype=ckpt_dtype, device=u.device)
+            mg.checkpoint(u, ck)  # FP32: u becomes the rounded value
+            ckpts.append(ck)
             mg.vcycle(b64, u)
         ctx.mg, ctx.c, ctx.b64, ctx.ckpts = mg, c, b64, ckpts
         ctx.coeff_meta = (coeffs.dtype, coeffs.device)
@@ -47,8 +49,7 @@ class _KCycles(torch.autograd.Function):
         bbar = torch.zeros_like(ctx.b64)
         cbar = [0.0] * len(ctx.c)
         for ck in reversed(ctx.ckpts):
-            uin = ck.to(torch.float64).contiguous()
-            cbar = mg.vcycle_adjoint(ctx.b64, uin, ubar, ubar, bbar, cbar)
+            cbar = mg.vcycle_adjoint(ctx.b64, ck, ubar, ubar, bbar, cbar)
         dt, dev = ctx.coeff_meta
         gc = torch.tensor(cbar, dtype=torch.float64).to(dtype=dt, device=dev)
         return gc, bbar, ubar, None, None, None

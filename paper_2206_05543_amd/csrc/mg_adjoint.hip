@@ -195,6 +195,25 @@ k_coarse_matvec(int m, const double* __restrict__ G, const double* __restrict__ 
     else y[off + r] = s;
 }
 
+// Checkpoint of the cycle-start iterate in FP32: ck = fl32(u), and u is
+// replaced by the rounded value (round to nearest even both ways), so that
+// the forward pass continues from exactly what the checkpoint holds.
+__global__ void __launch_bounds__(256)
+k_ckpt32(double* __restrict__ u, float* __restrict__ ck, long count) {
+    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < count; i += (long)gridDim.x * 256) {
+        const float f = (float)u[i];
+        ck[i] = f;
+        u[i] = (double)f;
+    }
+}
+
+// FP64 copy of an FP32 checkpoint (exact)
+__global__ void __launch_bounds__(256)
+k_widen(const float* __restrict__ ck, double* __restrict__ u, long count) {
+    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < count; i += (long)gridDim.x * 256)
+        u[i] = (double)ck[i];
+}
+
 inline Grid make_grid(int d, int n) {
     Grid g;
     g.d = d;
@@ -259,6 +278,16 @@ hipError_t launch_interp(int d, int n, int batch, const double* coarse, double* 
 hipError_t launch_reduce_cols(const double* partials, int count, int ncols, double* acc,
                               double scale, hipStream_t st) {
     hipLaunchKernelGGL(k_reduce_cols, dim3(1), dim3(256), 0, st, partials, count, ncols, acc, scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_ckpt32(double* u, float* ck, long count, hipStream_t st) {
+    hipLaunchKernelGGL(k_ckpt32, point_grid(count, 1), dim3(256), 0, st, u, ck, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_widen(const float* ck, double* u, long count, hipStream_t st) {
+    hipLaunchKernelGGL(k_widen, point_grid(count, 1), dim3(256), 0, st, ck, u, count);
     return hipGetLastError();
 }
 

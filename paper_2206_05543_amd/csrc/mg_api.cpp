@@ -82,6 +82,7 @@ struct mg_ctx {
     int norm_slots = 0;
     // adjoint scratch (FP64), allocated on first use; per level
     std::vector<double*> adj_r1, adj_r3, adj_w, adj_ua, adj_ub, adj_uo, adj_bb;
+    double* adj_cin = nullptr;   // FP64 copy of an FP32 checkpoint (fine level)
     bool adj_alloc = false;
     double* adj_cacc = nullptr;  // device accumulator of dL/dc (3 doubles)
     // timing
@@ -593,6 +594,22 @@ int check_handle(mg_ctx* h) {
     return MG_OK;
 }
 
+// ||b||_2 over the whole batch for mg_stats: one pass over b at the start
+// of a solve into the last norm slot (the solves use slots 0 .. max_cycles
+// + 1), copied to the pinned host mirror, read after the final
+// synchronisation.
+int bnorm_slot(const mg_ctx* h) { return h->norm_slots - 1; }
+
+int enqueue_bnorm(mg_ctx* h, const double* b, hipStream_t st) {
+    int np = 0;
+    const int sl = bnorm_slot(h);
+    HIPCHK(launch_sumsq(b, level_pts(h, 0) * h->batch, h->psum, kPartialCap * h->batch, st, &np));
+    HIPCHK(launch_finalize(h->psum, nullptr, np, h->dnorm + 2 * sl, st));
+    HIPCHK(hipMemcpyAsync(h->hnorm + 2 * sl, h->dnorm + 2 * sl, sizeof(double),
+                          hipMemcpyDeviceToHost, st));
+    return MG_OK;
+}
+
 }  // namespace
 
 // ============================================================== C ABI
@@ -648,6 +665,10 @@ int mg_set_coeffs(mg_handle_t h, const double* coeffs, int n_coeffs) {
 
 int mg_set_option(mg_handle_t h, int key, double value) {
     if (check_handle(h)) return MG_EINVAL;
+    // range first: converting a NaN, an infinity or a value outside the int
+    // range to int is undefined
+    if (!std::isfinite(value) || std::fabs(value) > 1e9)
+        return fail(MG_EINVAL, "option value out of range");
     const int v = (int)value;
     if ((double)v != value) return fail(MG_EINVAL, "option values are integers");
     switch (key) {
@@ -899,6 +920,10 @@ static int solve64_chain(mg_ctx* h, const double* b, double* u, double tol, mg_s
         (void)hipEventDestroy(evn);
         return rc;
     };
+    if (st_out) {
+        const int rb = enqueue_bnorm(h, b, st);
+        if (rb) return done(rb);
+    }
     Sweep s = make_sweep(h, H, 0);
     double sA, sW, pf;
     level_scales(h, H, 0, &sA, &sW, &pf);
@@ -984,6 +1009,7 @@ static int solve64_chain(mg_ctx* h, const double* b, double* u, double tol, mg_s
         st_out->cycles_run = run;
         st_out->r0_norm = r0;
         st_out->rk_norm = rk;
+        st_out->b_norm = h->hnorm[2 * bnorm_slot(h)];
         float ms = 0.f;
         HIPCHK(hipEventElapsedTime(&ms, h->ev0, h->ev1));
         st_out->elapsed_ms = ms;
@@ -1007,6 +1033,10 @@ static int solve64(mg_ctx* h, const double* b, double* u, double tol, mg_stats* 
     double r0 = 0.0, rk = 0.0;
     int k = 0, code = MG_OK, run = 0;
     bool flipped = false;
+    if (st_out) {
+        const int rb = enqueue_bnorm(h, b, st);
+        if (rb) return rb;
+    }
     hipEvent_t evn;
     HIPCHK(hipEventCreateWithFlags(&evn, hipEventDisableTiming));
     for (k = 0;; ++k) {
@@ -1105,6 +1135,7 @@ static int solve64(mg_ctx* h, const double* b, double* u, double tol, mg_stats* 
         st_out->cycles_run = run;
         st_out->r0_norm = r0;
         st_out->rk_norm = rk;
+        st_out->b_norm = h->hnorm[2 * bnorm_slot(h)];
         float ms = 0.f;
         HIPCHK(hipEventElapsedTime(&ms, h->ev0, h->ev1));
         st_out->elapsed_ms = ms;
@@ -1127,6 +1158,10 @@ static int solve_ir(mg_ctx* h, const double* b, double* u, double tol, mg_stats*
     const double sigma0 = H.scaled ? N * N : 1.0;
     HIPCHK(hipEventRecord(h->ev0, st));
     int nparts = 0, rc;
+    if (st_out) {
+        rc = enqueue_bnorm(h, b, st);
+        if (rc) return rc;
+    }
     if (H.p == P16) {
         // FP16 storage needs r_0 scaled into range: a residual pass of the
         // initial guess puts (||r_0||, max|r_0|) in slot 0 for the first step
@@ -1238,6 +1273,7 @@ static int solve_ir(mg_ctx* h, const double* b, double* u, double tol, mg_stats*
         st_out->cycles_run = run;
         st_out->r0_norm = r0;
         st_out->rk_norm = rk;
+        st_out->b_norm = h->hnorm[2 * bnorm_slot(h)];
         float ms = 0.f;
         HIPCHK(hipEventElapsedTime(&ms, h->ev0, h->ev1));
         st_out->elapsed_ms = ms;
@@ -1305,7 +1341,9 @@ void free_adj(mg_ctx* h) {
         v->clear();
     }
     if (h->adj_cacc) (void)hipFree(h->adj_cacc);
+    if (h->adj_cin) (void)hipFree(h->adj_cin);
     h->adj_cacc = nullptr;
+    h->adj_cin = nullptr;
     h->adj_alloc = false;
 }
 
@@ -1330,6 +1368,7 @@ int alloc_adj(mg_ctx* h) {
         }
     }
     HIPCHK(hipMalloc(&h->adj_cacc, 3 * sizeof(double)));
+    HIPCHK(hipMalloc(&h->adj_cin, (size_t)level_pts(h, 0) * h->batch * sizeof(double)));
     h->adj_alloc = true;
     return MG_OK;
 }
@@ -1407,17 +1446,40 @@ int adj_reverse(mg_ctx* h, int l, const double* uo, double* ui, double* bb, cons
 }
 }  // namespace
 
-extern "C" int mg_vcycle_adjoint(mg_handle_t h, const double* b, const double* u_in,
-                                 const double* ubar_out, double* ubar_in, double* bbar_acc,
-                                 double* cbar_acc, void* stream) {
+extern "C" int mg_checkpoint(mg_handle_t h, double* u, void* ckpt, int ckpt_dtype,
+                             void* stream) {
     if (check_handle(h)) return MG_EINVAL;
-    if (!b || !u_in || !ubar_out || !ubar_in || !bbar_acc || !cbar_acc)
+    if (!u || !ckpt) return fail(MG_EINVAL, "null pointer");
+    if (ckpt_dtype != MG_CKPT_FP64 && ckpt_dtype != MG_CKPT_FP32)
+        return fail(MG_EINVAL, "ckpt_dtype must be MG_CKPT_FP64 or MG_CKPT_FP32");
+    hipStream_t st = (hipStream_t)stream;
+    const long count = level_pts(h, 0) * h->batch;
+    if (ckpt_dtype == MG_CKPT_FP64)
+        HIPCHK(hipMemcpyAsync(ckpt, u, count * sizeof(double), hipMemcpyDeviceToDevice, st));
+    else
+        HIPCHK(launch_ckpt32(u, static_cast<float*>(ckpt), count, st));
+    return MG_OK;
+}
+
+extern "C" int mg_vcycle_adjoint(mg_handle_t h, const double* b, const void* u_ckpt,
+                                 int ckpt_dtype, const double* ubar_out, double* ubar_in,
+                                 double* bbar_acc, double* cbar_acc, void* stream) {
+    if (check_handle(h)) return MG_EINVAL;
+    if (!b || !u_ckpt || !ubar_out || !ubar_in || !bbar_acc || !cbar_acc)
         return fail(MG_EINVAL, "null pointer");
+    if (ckpt_dtype != MG_CKPT_FP64 && ckpt_dtype != MG_CKPT_FP32)
+        return fail(MG_EINVAL, "ckpt_dtype must be MG_CKPT_FP64 or MG_CKPT_FP32");
     if (h->cycle_kind != MG_CYCLE_V11)
         return fail(MG_EINVAL, "the adjoint is defined for the V(1,1) cycle only");
     hipStream_t st = (hipStream_t)stream;
     int rc = alloc_adj(h);
     if (rc) return rc;
+    const double* u_in = static_cast<const double*>(u_ckpt);
+    if (ckpt_dtype == MG_CKPT_FP32) {
+        HIPCHK(launch_widen(static_cast<const float*>(u_ckpt), h->adj_cin,
+                            level_pts(h, 0) * h->batch, st));
+        u_in = h->adj_cin;
+    }
     HIPCHK(hipMemsetAsync(h->adj_cacc, 0, 3 * sizeof(double), st));
     if (h->L == 1) {
         // single grid: u_out = A^{-1} b

@@ -99,6 +99,10 @@ size_t tail_lds_bytes(Prec p, int d, int nt);
 hipError_t launch_finalize(const double* partials, const double* maxparts,
                            int count, double* out, hipStream_t st);
 
+// Per-block partial sums of v^2 over count doubles (fixed order).
+hipError_t launch_sumsq(const double* v, long count, double* partials, long partials_cap,
+                        hipStream_t st, int* nparts);
+
 // Fine-grid residual norm of an FP64 iterate: partials of r^2 and max|r|.
 hipError_t launch_residual_norm(int d, int n, int batch, const double* u,
                                 const double* b, double inv_h2, double* psum,
@@ -147,6 +151,11 @@ hipError_t launch_interp(int d, int n, int batch, const double* coarse, double* 
 //   acc[j] += scale * sum_i partials[ncols i + j] (fixed order)
 hipError_t launch_reduce_cols(const double* partials, int count, int ncols, double* acc,
                               double scale, hipStream_t st);
+//   ck = fl32(u), u = (double) ck  (FP32 checkpoint; the forward continues
+//   from the rounded iterate)
+hipError_t launch_ckpt32(double* u, float* ck, long count, hipStream_t st);
+//   u = (double) ck
+hipError_t launch_widen(const float* ck, double* u, long count, hipStream_t st);
 //   y (+)= G x per batch entry, G m x m (m <= 64)
 hipError_t launch_coarse_matvec(int m, int batch, const double* G, const double* x,
                                 double* y, bool accumulate, hipStream_t st);

@@ -2707,6 +2707,25 @@ k_finalize(const double* __restrict__ ps, const double* __restrict__ pm, int cou
     }
 }
 
+// Sum of squares of a vector as per-block partials: block i owns the i-th
+// contiguous chunk and its lanes stride through it, then a fixed shuffle
+// tree, so the result is the same run to run.  (||b||_2 of a solve.)
+__global__ void __launch_bounds__(256)
+k_sumsq(const double* __restrict__ v, long count, long per, double* __restrict__ partials) {
+    __shared__ double red[4];
+    const long a = (long)blockIdx.x * per, e = min(count, a + per);
+    double s0 = 0.0, s1 = 0.0;
+    long i = a + threadIdx.x;
+    for (; i + 256 < e; i += 512) {
+        const double x = v[i], y = v[i + 256];
+        s0 += x * x;
+        s1 += y * y;
+    }
+    if (i < e) s0 += v[i] * v[i];
+    const double tot = block_sum<256>(s0 + s1, red);
+    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+
 // ---------------------------------------------------------------------------
 // FP64 refinement step, 3D: unew = u + escale * e (on the fly, halo included),
 // r = b - A unew, r_lo = s * r (stored in S), partials of r^2 and max |r|.
@@ -3511,6 +3530,16 @@ hipError_t launch_tail(Prec p, const Tail& t, hipStream_t st) {
 hipError_t launch_finalize(const double* partials, const double* maxparts, int count,
                            double* out, hipStream_t st) {
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, partials, maxparts, count, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_sumsq(const double* v, long count, double* partials, long partials_cap,
+                        hipStream_t st, int* nparts) {
+    long blocks = std::min<long>(2048, std::max<long>(1, (count + 4095) / 4096));
+    if (blocks > partials_cap) blocks = partials_cap;
+    const long per = (count + blocks - 1) / blocks;
+    hipLaunchKernelGGL(k_sumsq, dim3((unsigned)blocks), dim3(256), 0, st, v, count, per, partials);
+    if (nparts) *nparts = (int)blocks;
     return hipGetLastError();
 }
 

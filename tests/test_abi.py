@@ -91,7 +91,8 @@ def test_null_handle_is_rejected_everywhere():
         "mg_set_coeffs": (null, p, i(3)),
         "mg_vcycle": (null, p, p, null),
         "mg_solve": (null, p, p, dbl(1e-10), null, null),
-        "mg_vcycle_adjoint": (null, p, p, p, p, p, p, null),
+        "mg_vcycle_adjoint": (null, p, p, i(0), p, p, p, p, null),
+        "mg_checkpoint": (null, p, p, i(0), null),
         "mg_sweep": (null, i(0), i(0), i(0), p, p, p, null),
         "mg_sweep_correct": (null, i(0), i(0), p, p, p, p, null),
         "mg_sweep_zero_restrict": (null, i(0), i(0), p, p, p, null),

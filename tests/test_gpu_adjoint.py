@@ -115,25 +115,34 @@ def test_autograd_matches_oracle_and_fd(d, N, batch, K):
             assert abs(fd - cw[j]) <= 1e-6 * np.abs(cw).max()
 
 
-def test_fp32_checkpoints_exact_recompute():
-    # FP32 checkpoints: the forward continues from the rounded iterate, so the
-    # gradient is that of the computed map; compare with an FP64-checkpoint run
-    # whose forward starts from the same rounded states
+@pytest.mark.parametrize("d,N,batch,K", [(3, 32, 2, 2), (2, 64, 2, 3)])
+def test_fp32_checkpoints_match_oracle(d, N, batch, K):
+    # FP32 checkpoints: each cycle starts from the FP32 rounding of its input
+    # and the derivative passes through the rounding unchanged; the oracle
+    # does the same on its own states (grad_kcycles(..., ckpt="fp32")).
+    # The two sides round states that agree to ~1e-15, so at most a few
+    # entries can round to neighbouring FP32 values (a 2^-24 change of that
+    # entry): agreement to 1e-9 of the largest entry.
     from paper_2206_05543_amd.autograd import kcycles
     need_gpu()
-    d, N, batch, K = 3, 32, 2, 2
     rng = np.random.default_rng(3)
-    e0 = rng.uniform(-1, 1, (batch,) + (N - 1,) * d).astype(np.float32).astype(np.float64)
-    say("fp32-ckpt")
-    with make_mg(N, d, M7, batch=batch) as mg:
-        cp = torch.tensor(M7, dtype=torch.float64, requires_grad=True)
-        u = kcycles(mg, cp, dev(np.zeros_like(e0)), dev(e0), K, torch.float32)
-        (u * u).sum().backward()
-        g32 = cp.grad.numpy().copy()
-        cp.grad = None
-        u = kcycles(mg, cp, dev(np.zeros_like(e0)), dev(e0), K, torch.float64)
-        (u * u).sum().backward()
-        g64 = cp.grad.numpy().copy()
-    # the two forward maps differ only by the FP32 rounding of the state
-    # after the first cycle (relative 6e-8), so the gradients agree to ~1e-6
-    assert np.max(np.abs(g32 - g64)) <= 1e-5 * np.abs(g64).max()
+    e0 = rng.uniform(-1, 1, (batch,) + (N - 1,) * d)
+    b = np.zeros((N - 1,) * d)
+    c = _c(d)
+    say("fp32-ckpt", d, N, batch, K)
+    with make_mg(N, d, c, batch=batch) as mg:
+        cp = torch.tensor(c, dtype=torch.float64, requires_grad=True)
+        bt = dev(np.zeros_like(e0)).requires_grad_(True)
+        et = dev(e0).requires_grad_(True)
+        u = kcycles(mg, cp, bt, et, K, torch.float32)
+        L = (u * u).sum()
+        L.backward()
+        gc, gb, ge = cp.grad.numpy().copy(), host(bt.grad), host(et.grad)
+    Lw, cw, bw, ew = O.grad_kcycles(d, N, c, e0, b, K, ckpt="fp32")
+    L64, cw64, _, _ = O.grad_kcycles(d, N, c, e0, b, K)
+    assert abs(float(L.detach()) - Lw) <= 1e-12 * Lw
+    assert np.max(np.abs(gc - cw)) <= 1e-9 * np.abs(cw).max()
+    assert np.max(np.abs(gb.sum(0) - bw)) <= 1e-9 * np.abs(bw).max()
+    assert np.max(np.abs(ge - ew)) <= 1e-9 * np.abs(ew).max()
+    # and the rounding is really applied: the FP64-checkpoint gradient differs
+    assert np.max(np.abs(cw64 - cw)) > 1e-9 * np.abs(cw).max()

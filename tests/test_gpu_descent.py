@@ -14,6 +14,7 @@ rather than required to be within 1% of it.  What is required:
 import time
 
 import numpy as np
+import pytest
 
 import oracle as O
 from oracle import lfa
@@ -72,3 +73,18 @@ def test_descent_n256_patterns_agree():
     cs = list(res.values())
     for c in cs[1:]:
         assert np.max(np.abs(c - cs[0]) / np.abs(cs[0])) <= 1e-3
+    REACHED["mu"] = lfa.smoothing_factor(3, cs[0], m=128)
+
+
+REACHED = {}
+
+
+@pytest.mark.xfail(strict=True, reason=(
+    "not met: the coefficient-recovery workload asks the descent to reach a "
+    "smoothing factor within 1% of 25/73 (Theorem 3.2), but the minimiser of "
+    "the k-cycle error loss is not the minimax point of mu (it lands near "
+    "mu = 0.43, +26%); only the mu-targeted minimax search recovers 25/73"))
+def test_descent_mu_within_one_percent_of_theorem_3_2():
+    need_gpu()
+    assert "mu" in REACHED, "the n256 descent did not run"
+    assert abs(REACHED["mu"] / MU_OPT - 1) <= 0.01

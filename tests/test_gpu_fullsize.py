@@ -7,8 +7,9 @@
   loss and gradients with respect to the coefficients, b and e0 against the
   oracle's reverse sweeps, and a central difference on one coefficient.
 - Gradients, 3D N=256, two cycles: one batch entry with FP64 checkpoints
-  against the oracle; the batch of 4 with FP32 checkpoints against the sum
-  of the per-entry gradients, to the accuracy FP32 states allow.
+  against the oracle; the batch of 4 with FP32 checkpoints (the workload's
+  configuration) against the oracle's reverse sweeps over the same rounded
+  states, every entry.
 """
 import numpy as np
 import pytest
@@ -92,22 +93,26 @@ def test_gradients_3d_full_size():
     c = np.array(M7)
     # one entry, FP64 checkpoints, against the oracle
     say("fullsize-grad-3d-entry0")
-    per_entry = []
     with make_mg(256, 3, c, batch=1) as mg:
-        for s in range(e0.shape[0]):
-            L, gc, gb, ge, cp = _grads(mg, c, w["b"][None], e0[s:s + 1], K, torch.float64)
-            per_entry.append(gc)
-            if s == 0:
-                c64 = cp.detach().double().numpy()
-                Lw, cw, bw, ew = O.grad_kcycles(3, 256, c64, e0[0:1], w["b"], K)
-                assert abs(L - Lw) <= 1e-12 * Lw
-                assert np.max(np.abs(gc - cw)) <= 1e-6 * np.abs(cw).max()
-                assert np.max(np.abs(gb[0] - bw)) <= 1e-10 * np.abs(bw).max()
-                assert np.max(np.abs(ge[0] - ew[0])) <= 1e-10 * np.abs(ew).max()
-    # the batch of 4 with FP32 checkpoints (the workload's configuration)
+        L, gc, gb, ge, cp = _grads(mg, c, w["b"][None], e0[0:1], K, torch.float64)
+    c64 = cp.detach().double().numpy()
+    Lw, cw, bw, ew = O.grad_kcycles(3, 256, c64, e0[0:1], w["b"], K)
+    assert abs(L - Lw) <= 1e-12 * Lw
+    assert np.max(np.abs(gc - cw)) <= 1e-6 * np.abs(cw).max()
+    assert np.max(np.abs(gb[0] - bw)) <= 1e-10 * np.abs(bw).max()
+    assert np.max(np.abs(ge[0] - ew[0])) <= 1e-10 * np.abs(ew).max()
+    # the batch of 4 with FP32 checkpoints against the oracle's FP32-checkpoint
+    # reverse sweeps of every entry (gradient reported for FP32 parameters)
     say("fullsize-grad-3d-batch4-fp32ckpt")
     with make_mg(256, 3, c, batch=4) as mg:
         b4 = np.broadcast_to(w["b"], e0.shape).copy()
         L, gc, gb, ge, cp = _grads(mg, c, b4, e0, K, torch.float32)
-    want = np.sum(per_entry, axis=0)
-    assert np.max(np.abs(gc - want)) <= 1e-5 * np.abs(want).max()
+    Lw, cw, bw, ew = O.grad_kcycles(3, 256, c64, e0, w["b"], K, ckpt="fp32")
+    # the two sides round states that agree to ~1e-15 relative, so a few of
+    # the 6.6e7 entries can round to neighbouring FP32 values (a 2^-24
+    # change of that entry); with the FP64 operation-order differences over
+    # four entries this allows 1e-9 of the largest gradient entry
+    assert abs(L - Lw) <= 1e-12 * Lw
+    assert np.max(np.abs(gc - cw)) <= 1e-6 * np.abs(cw).max()
+    assert np.max(np.abs(gb.sum(0) - bw)) <= 1e-9 * np.abs(bw).max()
+    assert np.max(np.abs(ge - ew)) <= 1e-9 * np.abs(ew).max()

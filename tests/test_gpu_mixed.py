@@ -74,6 +74,7 @@ def test_mixed_final_error_matches_fp64(d, N, prec):
             st = mg.solve(dev(p["b"]), u, tol=1e-10)
             assert st["code"] == 0
             err[pr] = np.linalg.norm(host(u) - ref) / np.linalg.norm(ref)
+    say("mixed-error ratio", d, N, prec, err[prec] / err["fp64"])
     assert err[prec] <= 2.5 * err["fp64"] + 1e-12, err
 
 

@@ -84,3 +84,63 @@ def test_rhs_gradient_vs_central_differences():
         fd = (O.loss_kcycles(d, N, c, e0 + t * v, b, K)
               - O.loss_kcycles(d, N, c, e0 - t * v, b, K)) / (2 * t)
         assert abs(fd - np.vdot(e0bar.sum(0), v)) <= 1e-7 * abs(fd) + 1e-12
+
+
+
+def _frozen_offset_loss(d, N, c, e0, K, offsets):
+    # u_{k+1} = E(c) (u_k + delta_k) with the rounding offsets delta_k of the
+    # base point held fixed (b = 0): the map whose derivative the
+    # straight-through treatment of a rounding is, through the Kronecker
+    # cycle matrix, so complex c gives its complex-step derivative
+    E, _ = dense.vcycle_maps(d, N, c)
+    n = (N - 1) ** d
+    L = 0.0
+    for s, e in enumerate(e0):
+        u = e.ravel().astype(np.result_type(E, e))
+        for k in range(K):
+            u = E @ (u + offsets[s][k].ravel())
+        L = L + np.sum(u * u)
+    return L
+
+
+@pytest.mark.parametrize("d,N,c,K", [(2, 16, C9, 3), (3, 8, C7, 2)])
+def test_fp32_checkpoint_gradient(d, N, c, K):
+    # FP32 checkpoints: every cycle starts from the FP32 rounding of its
+    # input, and the reverse sweep passes derivatives through the rounding
+    # unchanged.  Pins: (1) one cycle from an input already in FP32 is the
+    # FP64 path exactly; (2) the loss is that of the FP64 cycles from the
+    # rounded states, which differs from the FP64 loss (the rounding is
+    # applied) by O(2^-24) relative; (3) the coefficient gradient equals the
+    # complex-step derivative of the Kronecker-matrix cycles with the base
+    # point's rounding offsets frozen, to rounding, and the FP64 path's
+    # gradient does not (so the pin tells the two apart).
+    rng = np.random.default_rng(6)
+    s = (N - 1,) * d
+    e0 = rng.uniform(-1, 1, (2,) + s)
+    b = np.zeros(s)
+    e32 = e0.astype(np.float32).astype(np.float64)
+    r64 = O.grad_kcycles(d, N, c, e32, b, 1)
+    r32 = O.grad_kcycles(d, N, c, e32, b, 1, ckpt="fp32")
+    assert r64[0] == r32[0]
+    for a, z in zip(r64[1:], r32[1:]):
+        assert np.array_equal(a, z)
+    L64, g64, _, _ = O.grad_kcycles(d, N, c, e0, b, K)
+    L32, g32, _, _ = O.grad_kcycles(d, N, c, e0, b, K, ckpt="fp32")
+    assert L32 != L64 and abs(L32 - L64) <= 1e-5 * L64
+    offsets = []
+    for e in e0:
+        u, offs = e, []
+        for _ in range(K):
+            r = u.astype(np.float32).astype(np.float64)
+            offs.append(r - u)
+            u = O.vcycle(d, N, c, r, b)
+        offsets.append(offs)
+    assert abs(_frozen_offset_loss(d, N, c, e0, K, offsets) - L32) <= 1e-12 * L32
+    g = np.zeros(len(c))
+    for j in range(len(c)):
+        cc = c.astype(complex)
+        cc[j] += 1e-30j
+        g[j] = np.imag(_frozen_offset_loss(d, N, cc, e0, K, offsets)) / 1e-30
+    scale = np.max(np.abs(g))
+    assert np.max(np.abs(g32 - g)) <= 1e-11 * scale
+    assert np.max(np.abs(g64 - g)) >= 1e-9 * scale
