@@ -139,10 +139,14 @@ def test_fp32_checkpoints_match_oracle(d, N, batch, K):
         L.backward()
         gc, gb, ge = cp.grad.numpy().copy(), host(bt.grad), host(et.grad)
     Lw, cw, bw, ew = O.grad_kcycles(d, N, c, e0, b, K, ckpt="fp32")
-    L64, cw64, _, _ = O.grad_kcycles(d, N, c, e0, b, K)
     assert abs(float(L.detach()) - Lw) <= 1e-12 * Lw
     assert np.max(np.abs(gc - cw)) <= 1e-9 * np.abs(cw).max()
     assert np.max(np.abs(gb.sum(0) - bw)) <= 1e-9 * np.abs(bw).max()
     assert np.max(np.abs(ge - ew)) <= 1e-9 * np.abs(ew).max()
-    # and the rounding is really applied: the FP64-checkpoint gradient differs
-    assert np.max(np.abs(cw64 - cw)) > 1e-9 * np.abs(cw).max()
+    # and the rounding is really applied: with FP64 checkpoints the loss and the
+    # field gradients move by more than the tolerances above (measured on these
+    # inputs: loss 5e-10 relative against the 1e-12 bound, e0-gradient 2e-8
+    # against 1e-9; the c-gradient moves by only 4e-10 in 3D, so it is not used)
+    L64, _, _, ew64 = O.grad_kcycles(d, N, c, e0, b, K)
+    assert abs(float(L.detach()) - L64) > 100 * 1e-12 * L64
+    assert np.max(np.abs(ge - ew64)) > 10 * 1e-9 * np.abs(ew).max()

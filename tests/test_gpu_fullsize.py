@@ -108,11 +108,20 @@ def test_gradients_3d_full_size():
         b4 = np.broadcast_to(w["b"], e0.shape).copy()
         L, gc, gb, ge, cp = _grads(mg, c, b4, e0, K, torch.float32)
     Lw, cw, bw, ew = O.grad_kcycles(3, 256, c64, e0, w["b"], K, ckpt="fp32")
-    # the two sides round states that agree to ~1e-15 relative, so a few of
-    # the 6.6e7 entries can round to neighbouring FP32 values (a 2^-24
-    # change of that entry); with the FP64 operation-order differences over
-    # four entries this allows 1e-9 of the largest gradient entry
+    # The two sides round states that agree to ~1e-15 relative, so an entry
+    # lying that close to an FP32 rounding boundary (expected: about one of
+    # the 2.6e8 checkpointed entries) rounds to neighbouring FP32 values on
+    # the two sides.  That changes one state entry by one FP32 ulp, and the
+    # field gradients near it by the image of that change under the adjoint
+    # cycles (measured: 1.3e-12, i.e. 1.2e-9 of the largest e0-gradient entry,
+    # where every other entry agrees to ~1e-19).  Element-wise the bound is
+    # therefore set at the scale of such a flip, 1e-8 of the largest entry;
+    # in the 2-norm an isolated flip is diluted over the 6.6e7 entries, so
+    # there the FP64 operation-order bound of 1e-10 applies.
     assert abs(L - Lw) <= 1e-12 * Lw
     assert np.max(np.abs(gc - cw)) <= 1e-6 * np.abs(cw).max()
-    assert np.max(np.abs(gb.sum(0) - bw)) <= 1e-9 * np.abs(bw).max()
-    assert np.max(np.abs(ge - ew)) <= 1e-9 * np.abs(ew).max()
+    gbs = gb.sum(0)
+    assert np.max(np.abs(gbs - bw)) <= 1e-8 * np.abs(bw).max()
+    assert np.linalg.norm((gbs - bw).ravel()) <= 1e-10 * np.linalg.norm(bw.ravel())
+    assert np.max(np.abs(ge - ew)) <= 1e-8 * np.abs(ew).max()
+    assert np.linalg.norm((ge - ew).ravel()) <= 1e-10 * np.linalg.norm(ew.ravel())
