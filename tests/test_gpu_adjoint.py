@@ -101,7 +101,7 @@ def test_autograd_matches_oracle_and_fd(d, N, batch, K):
         # the FP32 parameters promoted to FP64
         c64 = cp.detach().double().numpy()
         Lw, cw, bw, ew = O.grad_kcycles(d, N, c64, e0, b[0], K)
-        assert abs(float(L) - Lw) <= 1e-12 * Lw
+        assert abs(float(L.detach()) - Lw) <= 1e-12 * Lw
         # gradient w.r.t. the FP32 parameters is reported in FP32
         assert np.max(np.abs(gc - cw)) <= 1e-6 * np.abs(cw).max()
         assert np.max(np.abs(gb.sum(0) - bw)) <= 1e-10 * np.abs(bw).max()

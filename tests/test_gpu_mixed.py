@@ -75,7 +75,12 @@ def test_mixed_final_error_matches_fp64(d, N, prec):
             assert st["code"] == 0
             err[pr] = np.linalg.norm(host(u) - ref) / np.linalg.norm(ref)
     say("mixed-error ratio", d, N, prec, err[prec] / err["fp64"])
-    assert err[prec] <= 2.5 * err["fp64"] + 1e-12, err
+    # at least as close as the FP64 solve: the last refinement step runs its
+    # whole count of inner cycles (a contraction of ~1e-4 to 1e-6 per step)
+    # past the point where the FP64 loop stops, so the mixed result lands
+    # closer to the converged solution (measured ratios 0.01 to 0.53 on
+    # these four cases); a regression to twice the FP64 error fails here
+    assert err[prec] <= 1.0 * err["fp64"] + 1e-12, err
 
 
 @pytest.mark.parametrize("prec", ["fp32_ir", "fp16_ir"])
