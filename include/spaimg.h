@@ -155,6 +155,36 @@ int mg_set_coeffs(mg_handle_t h, const double* spai_coeffs, int n_coeffs);
  * (Section 4.) */
 int mg_vcycle(mg_handle_t h, const double* b, double* u, void* stream);
 
+/* Bytes of the static per-device workspace of mg_vcycle_noalloc (32 MiB). */
+#define MG_NOALLOC_SCRATCH_BYTES (32u << 20)
+
+/* For callers that cannot allocate device memory (work recorded under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * FP64 V(1,1) cycle of mg_vcycle -- same kernels, same launch shapes, same
+ * result -- for a problem given by the arguments of mg_setup plus `batch`
+ * (1..65535), with default options and without a handle.  u <- V(u, b) in
+ * place; b and u are caller-owned device arrays shaped as for mg_vcycle.
+ *
+ * Allocates nothing: no hipMalloc, hipFree, host heap or library allocator.
+ * Every internal buffer lives in one static array of the library
+ * (MG_NOALLOC_SCRATCH_BYTES per device, allocated when the code object is
+ * loaded and held until the process ends), so the problem's workspace,
+ * (N-1)^d + 3 sum_{l>=1} (N/2^l - 1)^d doubles per batch entry (each level
+ * buffer rounded up to 256 bytes), must fit in it: e.g. 2D N <= 1024 or 3D
+ * N <= 128 at batch 1.  The first call on a device looks up that device's
+ * copy of the array (hipGetSymbolAddress); every call then only enqueues
+ * kernels on `stream` (a stream of the current device) and returns without
+ * waiting.  The cycle writes each workspace element before reading it, so
+ * the previous call's contents never matter.  Every call on one device
+ * shares that device's array: calls whose work may overlap (two streams,
+ * two host threads) race and must be serialised by the caller.
+ *
+ * Errors: MG_EINVAL for bad N, d, coefficients, batch or null pointers, or
+ * a workspace larger than the static array (the message gives both sizes);
+ * MG_EHIP for a failed address lookup or kernel launch. */
+int mg_vcycle_noalloc(int N, int d, const double* spai_coeffs, int n_coeffs, int batch,
+                      const double* b, double* u, void* stream);
+
 /* Cycles from the initial guess in u until ||b - A u_k||_2 <= tol ||b - A
  * u_0||_2 over the whole batch (the stopping rule on the relative residual,
  * Section 4), with the precision set by MG_OPT_PRECISION.  FP64: V(1,1)

@@ -54,6 +54,7 @@ def lib():
         L.mg_set_option.argtypes = [vp, i, dbl]
         L.mg_set_coeffs.argtypes = [vp, dp, i]
         L.mg_vcycle.argtypes = [vp, vp, vp, vp]
+        L.mg_vcycle_noalloc.argtypes = [i, i, dp, i, i, vp, vp, vp]
         L.mg_solve.argtypes = [vp, vp, vp, dbl, ctypes.POINTER(MGStats), vp]
         L.mg_vcycle_adjoint.argtypes = [vp, vp, vp, i, vp, vp, vp, dp, vp]
         L.mg_checkpoint.argtypes = [vp, vp, vp, i, vp]
@@ -87,6 +88,27 @@ def _stream():
 def _dbl_array(vals):
     arr = (ctypes.c_double * len(vals))(*[float(v) for v in vals])
     return arr
+
+
+NOALLOC_SCRATCH_BYTES = 32 << 20
+
+
+def vcycle_noalloc(N, d, coeffs, b, u, batch=1):
+    """One FP64 V(1,1) cycle u <- V(u, b) without a handle (mg_vcycle_noalloc):
+    no allocation, internal buffers in the library's static workspace."""
+    n = int(N) - 1
+    for t, name in ((b, "b"), (u, "u")):
+        if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+            raise TypeError(f"{name} must be a CUDA tensor")
+        if t.dtype != torch.float64 or not t.is_contiguous():
+            raise TypeError(f"{name} must be a contiguous float64 tensor")
+        if t.numel() != int(batch) * n ** int(d):
+            raise ValueError(f"{name} has {t.numel()} elements, the problem needs "
+                             f"{int(batch) * n ** int(d)}")
+    _check(lib().mg_vcycle_noalloc(int(N), int(d), _dbl_array(coeffs), len(coeffs), int(batch),
+                                   ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(u.data_ptr()),
+                                   _stream()))
+    return u
 
 
 class Multigrid:

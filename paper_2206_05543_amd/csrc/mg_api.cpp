@@ -13,6 +13,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -44,8 +45,11 @@ constexpr long kPartialCap = 1 << 17;  // per batch entry
 struct Hier {
     Prec p = P64;
     bool scaled = false;
-    std::vector<void*> e, b, t;        // per level; FP64 level 0: only t
+    void* e[kMaxLevels] = {};          // per level; FP64 level 0: only t
+    void* b[kMaxLevels] = {};
+    void* t[kMaxLevels] = {};
     double* ginv = nullptr;            // sigma_coarsest * A_coarsest^{-1}
+    bool ginv_owned = false;           // allocated by alloc_hier
     bool allocated = false;
 };
 
@@ -148,62 +152,86 @@ void level_scales(const mg_ctx* h, const Hier& H, int l, double* sA, double* sW,
     }
 }
 
-// Inverse of the h-free Laplacian stencil matrix on the 3^d coarsest grid,
-// by Gauss-Jordan elimination with partial pivoting in FP64.
-std::vector<double> coarsest_stencil_inverse(int d) {
-    const int n = 3, m = d == 2 ? 9 : 27;
-    std::vector<double> A(m * m, 0.0), I(m * m, 0.0);
-    auto id = [&](int i, int j, int k) { return d == 2 ? i + n * j : i + n * (j + n * k); };
-    for (int k = 0; k < (d == 3 ? n : 1); ++k)
-        for (int j = 0; j < n; ++j)
-            for (int i = 0; i < n; ++i) {
-                const int p = id(i, j, k);
-                A[p * m + p] = 2.0 * d;
-                const int nb[6][3] = {{i - 1, j, k}, {i + 1, j, k}, {i, j - 1, k},
-                                      {i, j + 1, k}, {i, j, k - 1}, {i, j, k + 1}};
-                for (int q = 0; q < 2 * d; ++q) {
-                    const int a = nb[q][0], b = nb[q][1], c = nb[q][2];
-                    if (a < 0 || a >= n || b < 0 || b >= n) continue;
-                    if (d == 3 && (c < 0 || c >= n)) continue;
-                    A[p * m + id(a, b, c)] = -1.0;
-                }
-            }
-    for (int i = 0; i < m; ++i) I[i * m + i] = 1.0;
+}  // namespace
+
+// Inverse of the h-free Laplacian stencil matrix on the 3^d coarsest grid
+// (h0 = 1/4, Section 4), times `scale`, by Gauss-Jordan elimination with
+// partial pivoting in FP64.  Evaluated at compile time: the host copies it
+// into each hierarchy, and the handle-free cycle reads the device tables
+// below, so both paths apply the same numbers.
+template <int M>
+struct StencilInverse {
+    double a[M * M];
+};
+
+constexpr double abs_cx(double x) { return x < 0 ? -x : x; }
+
+template <int D>
+constexpr StencilInverse<D == 2 ? 9 : 27> coarsest_stencil_inverse(double scale) {
+    constexpr int n = 3, m = D == 2 ? 9 : 27;
+    StencilInverse<m> A{}, I{};
+    for (int p = 0; p < m; ++p) {
+        const int i = p % n, j = (p / n) % n, k = p / (n * n);
+        A.a[p * m + p] = 2.0 * D;
+        const int nb[6][3] = {{i - 1, j, k}, {i + 1, j, k}, {i, j - 1, k},
+                              {i, j + 1, k}, {i, j, k - 1}, {i, j, k + 1}};
+        for (int q = 0; q < 2 * D; ++q) {
+            const int x = nb[q][0], y = nb[q][1], z = nb[q][2];
+            if (x < 0 || x >= n || y < 0 || y >= n || z < 0 || z >= (D == 3 ? n : 1)) continue;
+            A.a[p * m + x + n * (y + n * z)] = -1.0;
+        }
+        I.a[p * m + p] = 1.0;
+    }
     for (int c = 0; c < m; ++c) {
         int piv = c;
         for (int r = c + 1; r < m; ++r)
-            if (std::fabs(A[r * m + c]) > std::fabs(A[piv * m + c])) piv = r;
+            if (abs_cx(A.a[r * m + c]) > abs_cx(A.a[piv * m + c])) piv = r;
         for (int q = 0; q < m; ++q) {
-            std::swap(A[c * m + q], A[piv * m + q]);
-            std::swap(I[c * m + q], I[piv * m + q]);
+            double x = A.a[c * m + q];
+            A.a[c * m + q] = A.a[piv * m + q];
+            A.a[piv * m + q] = x;
+            x = I.a[c * m + q];
+            I.a[c * m + q] = I.a[piv * m + q];
+            I.a[piv * m + q] = x;
         }
-        const double dv = A[c * m + c];
+        const double dv = A.a[c * m + c];
         for (int q = 0; q < m; ++q) {
-            A[c * m + q] /= dv;
-            I[c * m + q] /= dv;
+            A.a[c * m + q] = A.a[c * m + q] / dv;
+            I.a[c * m + q] = I.a[c * m + q] / dv;
         }
         for (int r = 0; r < m; ++r) {
             if (r == c) continue;
-            const double f = A[r * m + c];
+            const double f = A.a[r * m + c];
             if (f == 0.0) continue;
             for (int q = 0; q < m; ++q) {
-                A[r * m + q] -= f * A[c * m + q];
-                I[r * m + q] -= f * I[c * m + q];
+                A.a[r * m + q] = A.a[r * m + q] - f * A.a[c * m + q];
+                I.a[r * m + q] = I.a[r * m + q] - f * I.a[c * m + q];
             }
         }
     }
+    for (int q = 0; q < m * m; ++q) I.a[q] = I.a[q] * scale;
     return I;
 }
 
+// sigma A_0^{-1} with A_0 = 16 x stencil (N = 4): 1/16 x the stencil
+// inverse for the FP64 hierarchy (sigma = 1), the stencil inverse itself for
+// the scaled ones (sigma = 16)
+constexpr StencilInverse<9> kInv2 = coarsest_stencil_inverse<2>(1.0);
+constexpr StencilInverse<27> kInv3 = coarsest_stencil_inverse<3>(1.0);
+constexpr StencilInverse<9> kInv2_64 = coarsest_stencil_inverse<2>(1.0 / 16);
+constexpr StencilInverse<27> kInv3_64 = coarsest_stencil_inverse<3>(1.0 / 16);
+
+namespace {
+
 void free_hier(Hier& H) {
-    for (auto* v : {&H.e, &H.b, &H.t})
-        for (void* p : *v)
-            if (p) (void)hipFree(p);
-    H.e.clear();
-    H.b.clear();
-    H.t.clear();
-    if (H.ginv) (void)hipFree(H.ginv);
+    for (void** v : {H.e, H.b, H.t})
+        for (int l = 0; l < kMaxLevels; ++l) {
+            if (v[l]) (void)hipFree(v[l]);
+            v[l] = nullptr;
+        }
+    if (H.ginv && H.ginv_owned) (void)hipFree(H.ginv);
     H.ginv = nullptr;
+    H.ginv_owned = false;
     H.allocated = false;
 }
 
@@ -211,9 +239,6 @@ int alloc_hier(mg_ctx* h, Hier& H, Prec p) {
     free_hier(H);
     H.p = p;
     H.scaled = p != P64;
-    H.e.assign(h->L, nullptr);
-    H.b.assign(h->L, nullptr);
-    H.t.assign(h->L, nullptr);
     const size_t es = prec_bytes(p);
     for (int l = 0; l < h->L; ++l) {
         const size_t bytes = (size_t)level_pts(h, l) * h->batch * es;
@@ -227,11 +252,12 @@ int alloc_hier(mg_ctx* h, Hier& H, Prec p) {
     }
     // exact coarsest solve: sigma * A^{-1}; A = N^2 * stencil (N = 4); in the
     // scaled hierarchy sigma = N^2, so sigma A^{-1} = stencil^{-1}
-    std::vector<double> G = coarsest_stencil_inverse(h->d);
-    if (!H.scaled)
-        for (double& g : G) g /= 16.0;
-    HIPCHK(hipMalloc(&H.ginv, G.size() * sizeof(double)));
-    HIPCHK(hipMemcpy(H.ginv, G.data(), G.size() * sizeof(double), hipMemcpyHostToDevice));
+    const double* G = h->d == 2 ? (H.scaled ? kInv2.a : kInv2_64.a)
+                                : (H.scaled ? kInv3.a : kInv3_64.a);
+    const size_t gbytes = (h->d == 2 ? 81 : 729) * sizeof(double);
+    HIPCHK(hipMalloc(&H.ginv, gbytes));
+    H.ginv_owned = true;
+    HIPCHK(hipMemcpy(H.ginv, G, gbytes, hipMemcpyHostToDevice));
     H.allocated = true;
     return MG_OK;
 }
@@ -610,6 +636,106 @@ int enqueue_bnorm(mg_ctx* h, const double* b, hipStream_t st) {
     return MG_OK;
 }
 
+// Checks the problem arguments of mg_setup and mg_vcycle_noalloc.
+int check_problem(int N, int d, const double* coeffs, int n_coeffs) {
+    if (d != 2 && d != 3) return fail(MG_EINVAL, "d must be 2 or 3");
+    if (N < 4 || (N & (N - 1)) != 0) return fail(MG_EINVAL, "N must be a power of two >= 4");
+    if ((d == 2 && N > 65536) || (d == 3 && N > 2048)) return fail(MG_EINVAL, "N too large");
+    const int nc = d == 2 ? 3 : 2;
+    if (!coeffs || n_coeffs != nc)
+        return fail(MG_EINVAL, d == 2 ? "2D takes 3 coefficients" : "3D takes 2 coefficients");
+    for (int j = 0; j < nc; ++j)
+        if (!std::isfinite(coeffs[j])) return fail(MG_EINVAL, "coefficients must be finite");
+    return MG_OK;
+}
+
+// Problem fields of a context (arguments already checked); the level count
+// of N <= 65536 stays below kMaxLevels.
+void init_problem(mg_ctx* h, int N, int d, const double* coeffs) {
+    h->N = N;
+    h->d = d;
+    h->ncoef = d == 2 ? 3 : 2;
+    for (int j = 0; j < h->ncoef; ++j) h->c[j] = coeffs[j];
+    h->L = 0;
+    for (int M = N; M >= 4; M /= 2) h->L++;
+}
+
+// ---- the handle-free cycle on a static workspace -------------------------
+
+constexpr size_t kScratchBytes = MG_NOALLOC_SCRATCH_BYTES;
+constexpr int kMaxDevices = 64;
+
+// Per-device addresses of the static arrays below, looked up once per device
+// with that device current (host code never passes the arrays' own names,
+// which are host-side stand-ins).
+struct StaticDevice {
+    bool ready = false;
+    unsigned char* scratch = nullptr;
+    double* inv2 = nullptr;  // A_0^{-1} of the FP64 hierarchy, 2D (9 x 9)
+    double* inv3 = nullptr;  // 3D (27 x 27)
+};
+StaticDevice g_static[kMaxDevices];
+std::mutex g_static_mu;
+
+}  // namespace
+
+// The workspace of mg_vcycle_noalloc: every internal buffer of its cycle
+// (the pre-smoothed fine iterate, and the correction, right-hand side and
+// pre-smoothed iterate of every coarser level) is carved from this array.
+// Each device holds its own copy from module load until the process ends.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+// The coarsest-grid inverses of the FP64 hierarchy, initialised in the code
+// object.  Not const: the device compiler drops a const variable that no
+// device code reads, and the runtime then cannot resolve the host's lookup.
+static __device__ StencilInverse<9> g_inv2_64 = kInv2_64;
+static __device__ StencilInverse<27> g_inv3_64 = kInv3_64;
+
+namespace {
+
+int static_setup(int dev, StaticDevice** out) {
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    StaticDevice& sd = g_static[dev];
+    if (!sd.ready) {
+        void* p = nullptr;
+        HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        sd.scratch = static_cast<unsigned char*>(p);
+        HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(g_inv2_64)));
+        sd.inv2 = static_cast<double*>(p);
+        HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(g_inv3_64)));
+        sd.inv3 = static_cast<double*>(p);
+        sd.ready = true;
+    }
+    *out = &sd;
+    return MG_OK;
+}
+
+// Workspace layout of the FP64 cycle: level 0 needs its pre-smoothed
+// iterate t, every coarser level e, b and t; each buffer starts on a
+// 256-byte boundary.  Returns the bytes needed; with base != nullptr also
+// points H's buffers into base.
+size_t carve_hier(const mg_ctx* h, Hier* H, unsigned char* base) {
+    size_t off = 0;
+    auto take = [&](long pts) {
+        const size_t at = off;
+        off += ((size_t)pts * h->batch * sizeof(double) + 255) / 256 * 256;
+        return base ? static_cast<void*>(base + at) : nullptr;
+    };
+    for (int l = 0; l < h->L; ++l) {
+        const long pts = level_pts(h, l);
+        if (l > 0) {
+            void* e = take(pts);
+            void* b = take(pts);
+            if (H) {
+                H->e[l] = e;
+                H->b[l] = b;
+            }
+        }
+        void* t = take(pts);
+        if (H) H->t[l] = t;
+    }
+    return off;
+}
+
 }  // namespace
 
 // ============================================================== C ABI
@@ -621,25 +747,9 @@ const char* mg_last_error(void) { return g_err.c_str(); }
 int mg_setup(int N, int d, const double* coeffs, int n_coeffs, mg_handle_t* out) {
     if (!out) return fail(MG_EINVAL, "out is NULL");
     *out = nullptr;
-    if (d != 2 && d != 3) return fail(MG_EINVAL, "d must be 2 or 3");
-    if (N < 4 || (N & (N - 1)) != 0) return fail(MG_EINVAL, "N must be a power of two >= 4");
-    if ((d == 2 && N > 65536) || (d == 3 && N > 2048)) return fail(MG_EINVAL, "N too large");
-    const int nc = d == 2 ? 3 : 2;
-    if (!coeffs || n_coeffs != nc)
-        return fail(MG_EINVAL, d == 2 ? "2D takes 3 coefficients" : "3D takes 2 coefficients");
-    for (int j = 0; j < nc; ++j)
-        if (!std::isfinite(coeffs[j])) return fail(MG_EINVAL, "coefficients must be finite");
+    if (check_problem(N, d, coeffs, n_coeffs)) return MG_EINVAL;
     mg_ctx* h = new mg_ctx;
-    h->N = N;
-    h->d = d;
-    h->ncoef = nc;
-    for (int j = 0; j < nc; ++j) h->c[j] = coeffs[j];
-    h->L = 0;
-    for (int M = N; M >= 4; M /= 2) h->L++;
-    if (h->L > kMaxLevels) {
-        delete h;
-        return fail(MG_EINVAL, "too many levels");
-    }
+    init_problem(h, N, d, coeffs);
     int rc = realloc_all(h);
     if (rc) {
         mg_destroy(h);
@@ -725,6 +835,38 @@ int mg_vcycle(mg_handle_t h, const double* b, double* u, void* stream) {
     // and writes u, and the pre-smoother never writes u
     h->pend = mg_ctx::PendingNorm();
     return fine_cycle64(h, b, u, u, -1, st);
+}
+
+int mg_vcycle_noalloc(int N, int d, const double* coeffs, int n_coeffs, int batch,
+                      const double* b, double* u, void* stream) {
+    if (check_problem(N, d, coeffs, n_coeffs)) return MG_EINVAL;
+    if (batch < 1 || batch > 65535) return fail(MG_EINVAL, "batch must be 1..65535");
+    if (!b || !u) return fail(MG_EINVAL, "null field pointer");
+    // the context lives on the stack: its containers stay empty, timing is
+    // off and no norm is requested, so the cycle neither allocates nor
+    // synchronises
+    mg_ctx h;
+    init_problem(&h, N, d, coeffs);
+    h.batch = batch;
+    const size_t need = carve_hier(&h, nullptr, nullptr);
+    if (need > kScratchBytes)
+        return fail(MG_EINVAL, "problem needs " + std::to_string(need) +
+                                   " bytes of workspace; the static workspace holds " +
+                                   std::to_string(kScratchBytes));
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(MG_EINVAL, "device index out of range");
+    StaticDevice* sd = nullptr;
+    int rc = static_setup(dev, &sd);
+    if (rc) return rc;
+    Hier& H = h.h64;
+    H.p = P64;
+    H.scaled = false;
+    carve_hier(&h, &H, sd->scratch);
+    H.ginv = d == 2 ? sd->inv2 : sd->inv3;
+    H.ginv_owned = false;
+    H.allocated = true;
+    return fine_cycle64(&h, b, u, u, -1, (hipStream_t)stream);
 }
 
 int mg_sweep(mg_handle_t h, int op, int level, int prec, const void* u, const void* b,

@@ -2,13 +2,15 @@
 
 The shared library loads, exports every function the header declares (and
 no other mg_ symbol), and rejects bad arguments on the host before any GPU
-work: invalid sizes, dimensions and coefficients in mg_setup, and a null
-handle in every entry point that takes one, each with MG_EINVAL and a
-message from mg_last_error.
+work: invalid sizes, dimensions and coefficients in mg_setup and in the
+handle-free cycle (which also refuses workspaces beyond its static array),
+and a null handle in every entry point that takes one, each with MG_EINVAL
+and a message from mg_last_error.
 """
 import ctypes
 import os
 import re
+import struct
 import subprocess
 
 import pytest
@@ -107,5 +109,106 @@ def test_null_handle_is_rejected_everywhere():
     for name, args in calls.items():
         assert getattr(L, name)(*args) == MG_EINVAL, name
     L.mg_destroy(null)  # a no-op
-    # every entry point that can fail is covered here or in mg_setup's test
-    assert set(calls) | {"mg_setup", "mg_destroy", "mg_last_error"} == set(_declared())
+    # every entry point that can fail is covered here or in the tests of the
+    # handle-free entry points' own argument checks
+    assert set(calls) | {"mg_setup", "mg_vcycle_noalloc", "mg_destroy",
+                         "mg_last_error"} == set(_declared())
+
+
+@pytest.mark.parametrize("N,d,nc,batch,what", [
+    (64, 1, 3, 1, "d must be"), (48, 2, 3, 1, "power of two"), (64, 2, 2, 1, "coefficients"),
+    (64, 2, 3, 0, "batch"), (64, 2, 3, 65536, "batch"),
+    # workspaces beyond the 32 MiB static array: 2D N = 2048 needs 63.9 MiB,
+    # 3D N = 256 179.9 MiB, 2D N = 1024 at batch 3 47.8 MiB
+    (2048, 2, 3, 1, "workspace"), (256, 3, 2, 1, "workspace"), (1024, 2, 3, 3, "workspace")])
+def test_noalloc_cycle_rejects_bad_arguments(N, d, nc, batch, what):
+    # all of these are refused on the host, before any device call
+    L = _lib()
+    vp = ctypes.c_void_p
+    c = (ctypes.c_double * nc)(*([0.1] * nc))
+    assert L.mg_vcycle_noalloc(N, d, c, nc, batch, vp(1), vp(1), vp()) == MG_EINVAL
+    assert what in _msg(L)
+    if what == "workspace":
+        assert str(32 << 20) in _msg(L)
+
+
+def test_noalloc_cycle_rejects_null_fields_and_coefficients():
+    L = _lib()
+    vp = ctypes.c_void_p
+    c = (ctypes.c_double * 3)(0.2, 0.0, 0.0)
+    assert L.mg_vcycle_noalloc(64, 2, c, 3, 1, vp(), vp(1), vp()) == MG_EINVAL
+    assert L.mg_vcycle_noalloc(64, 2, c, 3, 1, vp(1), vp(), vp()) == MG_EINVAL
+    assert L.mg_vcycle_noalloc(64, 2, None, 3, 1, vp(1), vp(1), vp()) == MG_EINVAL
+    bad = (ctypes.c_double * 3)(0.2, float("inf"), 0.0)
+    assert L.mg_vcycle_noalloc(64, 2, bad, 3, 1, vp(1), vp(1), vp()) == MG_EINVAL
+    assert "finite" in _msg(L)
+
+
+def _workspace_bytes(N, d, batch):
+    # the layout the header states: level 0 one buffer, every coarser level
+    # three, each rounded up to 256 bytes
+    tot, l = 0, 0
+    while (N >> l) >= 4:
+        pts = ((N >> l) - 1) ** d
+        tot += (1 if l == 0 else 3) * ((pts * batch * 8 + 255) // 256 * 256)
+        l += 1
+    return tot
+
+
+def test_noalloc_workspace_limit_is_where_the_header_says():
+    # 2D N = 1024 and 3D N = 128 fit at batch 1 (the header's examples); the
+    # rejected cases above do not
+    assert _workspace_bytes(1024, 2, 1) <= 32 << 20
+    assert _workspace_bytes(128, 3, 1) <= 32 << 20
+    assert _workspace_bytes(1024, 2, 2) <= 32 << 20
+    for N, d, b in ((2048, 2, 1), (256, 3, 1), (1024, 2, 3)):
+        assert _workspace_bytes(N, d, b) > 32 << 20
+
+
+READELF = "/opt/rocm/llvm/bin/llvm-readelf"
+
+
+def _device_code_objects(path):
+    """The gfx950 code objects of a HIP shared library: its .hip_fatbin
+    section holds one clang offload bundle per translation unit (magic,
+    entry count, then per entry offset, size, triple length and triple)."""
+    data = open(path, "rb").read()
+    magic = b"__CLANG_OFFLOAD_BUNDLE__"
+    objs, at = [], data.find(magic)
+    while at >= 0:
+        (count,) = struct.unpack_from("<Q", data, at + len(magic))
+        pos = at + len(magic) + 8
+        for _ in range(count):
+            off, size, tlen = struct.unpack_from("<QQQ", data, pos)
+            triple = data[pos + 24:pos + 24 + tlen].decode()
+            pos += 24 + tlen
+            if "gfx950" in triple:
+                objs.append(data[at + off:at + off + size])
+        at = data.find(magic, at + 1)
+    return objs
+
+
+def test_device_code_defines_the_symbols_the_host_looks_up(tmp_path):
+    # the handle-free cycle looks up its workspace and the coarsest-grid
+    # inverse tables by symbol; a device variable that no device code reads
+    # must still be emitted, or the runtime cannot resolve the lookup when it
+    # loads the module.  Checked in the built library's gfx950 code objects.
+    if not os.path.exists(LIB):
+        pytest.skip("libspaimg.so is not built")
+    if not os.path.exists(READELF):
+        pytest.skip("llvm-readelf is not installed")
+    objs = _device_code_objects(LIB)
+    assert len(objs) >= 3  # one per source file
+    defined = {}
+    for k, blob in enumerate(objs):
+        f = tmp_path / f"co{k}.elf"
+        f.write_bytes(blob)
+        out = subprocess.run([READELF, "-sW", str(f)], capture_output=True, text=True,
+                             check=True).stdout
+        for ln in out.splitlines():
+            parts = ln.split()
+            if len(parts) >= 8 and parts[3] == "OBJECT" and parts[6] != "UND":
+                defined[parts[7]] = int(parts[2], 0)
+    assert defined.get("_ZL7scratch") == 32 << 20
+    assert defined.get("_ZL9g_inv2_64") == 81 * 8
+    assert defined.get("_ZL9g_inv3_64") == 729 * 8
