@@ -11,7 +11,7 @@ the fine-level kernels timed live with HIP events on the launch stream, the
 one with the largest total time), per-level kernel times and GB/s (extra solves after the timed
 region, every launch timed), the time to 1e-10 of the 3D N=512 noisy problem in FP64 and
 with FP32 / FP16 V-cycles inside FP64 refinement, and the CPU oracle timed on
-a bounded sample of the same workloads (single thread).
+a bounded sample of the same workloads (all host threads, and one thread).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
        [--no-mixed] [--workloads a,b]
@@ -261,20 +261,63 @@ def main():
     print(json.dumps(line), flush=True)
 
 
-def mixed(tol):
-    """Time to tol of the 3D N=512 noisy problem: FP64 V-cycles vs FP32 and
-    FP16 V-cycles inside FP64 refinement (same GPU, same input)."""
+def closed_form_sine_solution(N, modes, weights, device):
+    """The exact discrete solution of A_h u = sum_m w_m phi_m on the 3D grid:
+    every sine mode phi_m is an eigenvector of A_h with eigenvalue
+    4 N^2 sum_a sin^2(k_a pi / (2 N)), so u = sum_m w_m phi_m / lambda_m."""
+    import torch
+    x = torch.arange(1, N, dtype=torch.float64, device=device) / N
+    u = torch.zeros((N - 1,) * 3, dtype=torch.float64, device=device)
+    for kk, w in zip(modes, weights):
+        lam = 4.0 * N * N * sum(np.sin(int(k) * np.pi / (2 * N)) ** 2 for k in kk)
+        sx, sy, sz = (torch.sin(int(k) * np.pi * x) for k in kk)
+        u += (float(w) / lam) * sz[:, None, None] * sy[None, :, None] * sx[None, None, :]
+    return u
+
+
+def mixed_oracle_anchored(tol, N=64):
+    """The same three solves on the same recipe at 3D N=64, where the oracle
+    solves to 1e-14: each GPU result's relative error against that solution."""
     import torch
 
+    import oracle as O
+    from paper_2206_05543_amd import M7
+    from paper_2206_05543_amd._lib import Multigrid
+    from paper_2206_05543_amd.workloads import WORKLOADS, poisson_problem
+
+    kw = dict(WORKLOADS["poisson3d_n512_noisy"])
+    kw.update(N=N)
+    p = poisson_problem(**kw)
+    ref, k, _ = O.solve(3, N, np.array(M7), p["u0"], p["b"], tol=1e-14, maxc=200)
+    out = {"N": N, "oracle_cycles_to_1e-14": k}
+    for prec in ("fp64", "fp32_ir", "fp16_ir"):
+        with Multigrid(N, 3, M7, precision=prec) as mg:
+            u = torch.from_numpy(p["u0"].copy()).cuda()
+            st = mg.solve(torch.from_numpy(p["b"]).cuda(), u, tol=tol)
+        got = u.cpu().numpy()
+        out[prec] = {"code": st["code"], "cycles": st["cycles"],
+                     "rel_error_vs_oracle": float(np.linalg.norm(got - ref) / np.linalg.norm(ref))}
+    return out
+
+
+def mixed(tol):
+    """Time to tol of the 3D N=512 noisy problem: FP64 V-cycles vs FP32 and
+    FP16 V-cycles inside FP64 refinement (same GPU, same input).  Each result
+    is also measured against a tightly converged FP64 solve, against the
+    closed-form discrete solution of the sine part of b, and by the CPU
+    oracle's own residual of it."""
+    import torch
+
+    import oracle as O
     from paper_2206_05543_amd import M7
     from paper_2206_05543_amd._lib import Multigrid
     from paper_2206_05543_amd.workloads import workload
 
     print("[bench] mixed precision: generating 3D N=512 input", file=sys.stderr, flush=True)
     p = workload("poisson3d_n512_noisy")
-    b = torch.from_numpy(p["b"]).cuda()
+    b_host = p["b"]
+    b = torch.from_numpy(b_host).cuda()
     u0 = torch.from_numpy(p["u0"]).cuda()
-    del p
     out = {"workload": "poisson3d_n512_noisy", "unknowns": 511 ** 3}
     # reference solution: FP64 cycles run until the residual stops falling
     # (a 1e-10 reduction relative to the random initial guess pins the
@@ -282,9 +325,17 @@ def mixed(tol):
     mg = Multigrid(512, 3, M7, max_cycles=40)
     ref = u0.clone()
     st = mg.solve(b, ref, tol=1e-14)
-    out["reference"] = {"cycles": st["cycles"], "rel_residual": st["rk"] / st["r0"]}
+    out["reference"] = {"cycles": st["cycles"], "code": st["code"],
+                        "rel_residual": st["rk"] / st["r0"],
+                        "rel_residual_vs_b": st["rk"] / st["b_norm"]}
     ref_norm = float(ref.norm())
     mg.close()
+    # the sine part's exact discrete solution; the noise part of b (1e-3)
+    # adds A^-1 noise, which bounds how close any solution can come to it
+    ucf = closed_form_sine_solution(512, p["modes"], p["weights"], "cuda")
+    ucf_norm = float(ucf.norm())
+    out["reference"]["rel_diff_vs_closed_form_sine"] = float((ref - ucf).norm()) / ucf_norm
+    b_norm = float(np.linalg.norm(b_host))
     for prec in ("fp64", "fp32_ir", "fp16_ir"):
         mg = Multigrid(512, 3, M7, precision=prec, max_cycles=100)
         u = u0.clone()
@@ -295,14 +346,23 @@ def mixed(tol):
             st = mg.solve(b, u, tol=tol)
             times.append(st["elapsed_ms"])
         rk = mg.residual_norm(b, u)
+        uh = u.cpu().numpy()
+        r_or = O.norm2(O.residual(3, 512, uh, b_host))
+        del uh
         rec = {"time_ms": min(times), "cycles": st["cycles"], "code": st["code"],
                "rel_residual": rk / st["r0"],
-               "rel_error_vs_reference": float((u - ref).norm()) / ref_norm}
+               "oracle_rel_residual": r_or / st["r0"],
+               "oracle_residual_vs_b": r_or / b_norm,
+               "rel_error_vs_reference": float((u - ref).norm()) / ref_norm,
+               "rel_error_vs_closed_form_sine": float((u - ucf).norm()) / ucf_norm}
         out[prec] = rec
         mg.close()
         print(f"[bench] mixed {prec}: {rec}", file=sys.stderr, flush=True)
     out["speedup_fp32_ir"] = out["fp64"]["time_ms"] / out["fp32_ir"]["time_ms"]
     out["speedup_fp16_ir"] = out["fp64"]["time_ms"] / out["fp16_ir"]["time_ms"]
+    del ucf, ref, u, b, u0
+    torch.cuda.empty_cache()
+    out["oracle_anchored"] = mixed_oracle_anchored(tol)
     return out
 
 
@@ -360,30 +420,56 @@ def paper_examples(tol):
 CPU_CYCLES = 5
 
 
+def host_cpu():
+    """The host's CPU model (from /proc/cpuinfo), logical CPUs and the CPUs
+    this process may run on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(),
+            "affinity": len(os.sched_getaffinity(0))}
+
+
 def cpu_baseline():
-    """The CPU oracle (plain FP64 loops, one thread) on a bounded sample:
-    CPU_CYCLES consecutive V(1,1) cycles of each workload of the step."""
+    """The CPU oracle (plain FP64 loops) on a bounded sample: CPU_CYCLES
+    consecutive V(1,1) cycles of each workload of the step, once with the
+    OpenMP build on every thread OMP_NUM_THREADS allows (the value) and once
+    single-threaded (the checker build; bit-identical results)."""
     import oracle as O
     from paper_2206_05543_amd import M7, M9
     from paper_2206_05543_amd.workloads import workload
 
     O.lib()
-    total_uc, total_s = 0.0, 0.0
-    for name, (d, N) in WORKLOADS.items():
-        p = workload(name)
-        c = np.array(M9 if d == 2 else M7)
-        t = time.perf_counter()
-        u = p["u0"]
-        for _ in range(CPU_CYCLES):
-            u = O.vcycle(d, N, c, u, p["b"])
-        total_s += time.perf_counter() - t
-        total_uc += CPU_CYCLES * (N - 1) ** d
-        print(f"[bench] cpu oracle {name}: {time.perf_counter() - t:.1f} s", file=sys.stderr,
-              flush=True)
-    return {"value": total_uc / total_s, "unit": "unknowns/s", "cores": 1, "kind": "oracle",
+    O.lib_omp()
+    legs = {}
+    for parallel in (True, False):
+        total_uc, total_s = 0.0, 0.0
+        for name, (d, N) in WORKLOADS.items():
+            p = workload(name)
+            c = np.array(M9 if d == 2 else M7)
+            t = time.perf_counter()
+            u = p["u0"]
+            for _ in range(CPU_CYCLES):
+                u = O.vcycle(d, N, c, u, p["b"], parallel=parallel)
+            total_s += time.perf_counter() - t
+            total_uc += CPU_CYCLES * (N - 1) ** d
+            print(f"[bench] cpu oracle {name} ({O.num_threads(parallel)} threads): "
+                  f"{time.perf_counter() - t:.1f} s", file=sys.stderr, flush=True)
+        legs[parallel] = (total_uc / total_s, total_s, O.num_threads(parallel))
+    rate, secs, threads = legs[True]
+    rate1, secs1, _ = legs[False]
+    return {"value": rate, "unit": "unknowns/s", "cores": threads, "kind": "oracle",
             "sample": f"{CPU_CYCLES} consecutive V(1,1) cycles of 2D N=4096 and {CPU_CYCLES} "
-                      f"of 3D N=256 from the benchmark's initial guesses "
-                      f"({total_s:.1f} s single-threaded)"}
+                      f"of 3D N=256 from the benchmark's initial guesses ({secs:.1f} s on "
+                      f"{threads} threads; {secs1:.1f} s single-threaded)",
+            "single_thread": {"value": rate1, "cores": 1},
+            "host": host_cpu()}
 
 
 if __name__ == "__main__":

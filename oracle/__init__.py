@@ -23,14 +23,45 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 
+_OMP_PATH = os.path.join(_HERE, "liboracle_omp.so")
+_lib_omp = None
+_FLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c99", "-fPIC", "-shared"]
+
+
 def build(force=True):
-    """Compile mg_oracle.c with gcc: -O2, no FMA contraction, single thread."""
-    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c99",
-           "-fPIC", "-shared", "-o", _LIB_PATH + ".tmp", _SRC, "-lm"]
-    if force or not os.path.exists(_LIB_PATH):
-        subprocess.check_call(cmd)
-        os.replace(_LIB_PATH + ".tmp", _LIB_PATH)
+    """Compile mg_oracle.c with gcc: -O2, no FMA contraction, single thread
+    (liboracle.so, the checker), and the same source with -fopenmp
+    (liboracle_omp.so, the all-core CPU baseline; bit-identical results)."""
+    for path, extra in ((_LIB_PATH, []), (_OMP_PATH, ["-fopenmp"])):
+        if force or not os.path.exists(path) or (
+                os.path.getmtime(path) < os.path.getmtime(_SRC)):
+            subprocess.check_call(["gcc"] + _FLAGS + extra + ["-o", path + ".tmp", _SRC, "-lm"])
+            os.replace(path + ".tmp", path)
     return _LIB_PATH
+
+
+def _bind(L):
+    dp = ctypes.POINTER(ctypes.c_double)
+    i = ctypes.c_int
+    L.or_num_threads.restype = i
+    L.or_apply_A.argtypes = [i, i, dp, dp]
+    L.or_apply_K.argtypes = [i, i, i, dp, dp]
+    L.or_apply_W.argtypes = [i, i, dp, dp, dp]
+    L.or_residual.argtypes = [i, i, dp, dp, dp]
+    L.or_smooth.argtypes = [i, i, dp, dp, dp, dp]
+    L.or_restrict.argtypes = [i, i, dp, dp]
+    L.or_prolong_add.argtypes = [i, i, dp, dp]
+    L.or_restrict_T_add.argtypes = [i, i, dp, dp]
+    L.or_prolong_T_add.argtypes = [i, i, dp, dp]
+    L.or_direct_solve.argtypes = [i, i, dp, dp]
+    L.or_cycle.argtypes = [i, i, dp, i, i, i, dp, dp]
+    L.or_vcycle.argtypes = [i, i, dp, dp, dp]
+    L.or_solve.argtypes = [i, i, dp, i, i, i, dp, dp, ctypes.c_double, i, dp]
+    L.or_solve.restype = i
+    L.or_norm2.argtypes = [ctypes.c_long, dp]
+    L.or_norm2.restype = ctypes.c_double
+    L.or_vcycle_adjoint.argtypes = [i, i, dp, dp, dp, dp, dp, dp, dp]
+    return L
 
 
 def lib():
@@ -38,29 +69,20 @@ def lib():
     if _lib is None:
         if not os.path.exists(_LIB_PATH) or (
                 os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC)):
-            build()
-        L = ctypes.CDLL(_LIB_PATH)
-        dp = ctypes.POINTER(ctypes.c_double)
-        i = ctypes.c_int
-        L.or_apply_A.argtypes = [i, i, dp, dp]
-        L.or_apply_K.argtypes = [i, i, i, dp, dp]
-        L.or_apply_W.argtypes = [i, i, dp, dp, dp]
-        L.or_residual.argtypes = [i, i, dp, dp, dp]
-        L.or_smooth.argtypes = [i, i, dp, dp, dp, dp]
-        L.or_restrict.argtypes = [i, i, dp, dp]
-        L.or_prolong_add.argtypes = [i, i, dp, dp]
-        L.or_restrict_T_add.argtypes = [i, i, dp, dp]
-        L.or_prolong_T_add.argtypes = [i, i, dp, dp]
-        L.or_direct_solve.argtypes = [i, i, dp, dp]
-        L.or_cycle.argtypes = [i, i, dp, i, i, i, dp, dp]
-        L.or_vcycle.argtypes = [i, i, dp, dp, dp]
-        L.or_solve.argtypes = [i, i, dp, i, i, i, dp, dp, ctypes.c_double, i, dp]
-        L.or_solve.restype = i
-        L.or_norm2.argtypes = [ctypes.c_long, dp]
-        L.or_norm2.restype = ctypes.c_double
-        L.or_vcycle_adjoint.argtypes = [i, i, dp, dp, dp, dp, dp, dp, dp]
-        _lib = L
+            build(force=False)
+        _lib = _bind(ctypes.CDLL(_LIB_PATH))
     return _lib
+
+
+def lib_omp():
+    """The OpenMP build (threads from OMP_NUM_THREADS, else all cores)."""
+    global _lib_omp
+    if _lib_omp is None:
+        if not os.path.exists(_OMP_PATH) or (
+                os.path.getmtime(_OMP_PATH) < os.path.getmtime(_SRC)):
+            build(force=False)
+        _lib_omp = _bind(ctypes.CDLL(_OMP_PATH))
+    return _lib_omp
 
 
 def _p(a):
@@ -170,8 +192,19 @@ def cycle(d, N, c, u, b, nu1=1, nu2=1, gamma=1):
     return u
 
 
-def vcycle(d, N, c, u, b):
-    return cycle(d, N, c, u, b, 1, 1, 1)
+def vcycle(d, N, c, u, b, parallel=False):
+    """One V(1,1) cycle; parallel=True runs the OpenMP build (same result)."""
+    if not parallel:
+        return cycle(d, N, c, u, b, 1, 1, 1)
+    u, b = _f64(u).copy(), _f64(b)
+    c = _coeffs(d, c)
+    lib_omp().or_cycle(d, N, _p(c), 1, 1, 1, _p(u), _p(b))
+    return u
+
+
+def num_threads(parallel=False):
+    """Threads the oracle's loops run on (1 for the plain build)."""
+    return (lib_omp() if parallel else lib()).or_num_threads()
 
 
 def solve(d, N, c, u, b, tol=1e-10, maxc=100, nu1=1, nu2=1, gamma=1):

@@ -7,7 +7,12 @@
  * the test-suite, the smoke check and the CPU-baseline leg of the benchmark
  * may load it.  It shares no code, header, table or helper with the GPU path.
  * Built with -O2 -ffp-contract=off so that every product and sum is rounded
- * exactly as written; loops are plain and unfused.
+ * exactly as written; loops are plain and unfused.  A second build with
+ * -fopenmp (the all-core CPU baseline) splits the outer grid loops of the
+ * stencil and transfer operators and the element-wise loops across threads;
+ * every output element is still computed by one thread with the same
+ * operations, and the reductions (norms, dot products) and scatter loops
+ * stay serial, so both builds give bit-identical results.
  *
  * Grid convention (Section 1, eqs. (Ax=b) and (A_h)): the unit square/cube
  * with N intervals per direction, h = 1/N, unknowns on the n = N-1 interior
@@ -24,6 +29,19 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* threads the loops below run on: 1 in the plain build */
+int or_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 /* ------------------------------------------------------------------ grid */
 
@@ -63,6 +81,7 @@ void or_apply_A(int d, int N, const double *v, double *out)
     int n = N - 1;
     double inv_h2 = (double)N * (double)N;
     int nk = (d == 3) ? n : 1;
+#pragma omp parallel for collapse(2) schedule(static)
     for (int k = 0; k < nk; k++)
         for (int j = 0; j < n; j++)
             for (int i = 0; i < n; i++) {
@@ -87,6 +106,7 @@ void or_apply_K(int d, int N, int which, const double *v, double *out)
 {
     int n = N - 1;
     int nk = (d == 3) ? n : 1;
+#pragma omp parallel for collapse(2) schedule(static)
     for (int k = 0; k < nk; k++)
         for (int j = 0; j < n; j++)
             for (int i = 0; i < n; i++) {
@@ -123,8 +143,10 @@ void or_apply_W(int d, int N, const double *c, const double *v, double *out)
     memset(out, 0, sizeof(double) * P);
     for (int j = 0; j < ncoef(d); j++) {
         or_apply_K(d, N, j, v, t);
+#pragma omp parallel for schedule(static)
         for (long p = 0; p < P; p++) out[p] += c[j] * t[p];
     }
+#pragma omp parallel for schedule(static)
     for (long p = 0; p < P; p++) out[p] *= h2;
     free(t);
 }
@@ -134,6 +156,7 @@ void or_residual(int d, int N, const double *u, const double *b, double *r)
 {
     long P = npts(d, N);
     or_apply_A(d, N, u, r);
+#pragma omp parallel for schedule(static)
     for (long p = 0; p < P; p++) r[p] = b[p] - r[p];
 }
 
@@ -147,6 +170,7 @@ void or_smooth(int d, int N, const double *c, const double *u,
     double *w = malloc(sizeof(double) * P);
     or_residual(d, N, u, b, r);
     or_apply_W(d, N, c, r, w);
+#pragma omp parallel for schedule(static)
     for (long p = 0; p < P; p++) out[p] = u[p] + w[p];
     free(r);
     free(w);
@@ -164,6 +188,7 @@ void or_restrict(int d, int N, const double *r, double *rc)
 {
     int Nc = N / 2, nc = Nc - 1;
     int nk = (d == 3) ? nc : 1;
+#pragma omp parallel for collapse(2) schedule(static)
     for (int kc = 0; kc < nk; kc++)
         for (int jc = 0; jc < nc; jc++)
             for (int ic = 0; ic < nc; ic++) {
@@ -204,6 +229,7 @@ void or_prolong_add(int d, int N, const double *ec, double *u)
 {
     int n = N - 1, Nc = N / 2;
     int nk = (d == 3) ? n : 1;
+#pragma omp parallel for collapse(2) schedule(static)
     for (int k = 0; k < nk; k++)
         for (int j = 0; j < n; j++)
             for (int i = 0; i < n; i++) {

@@ -7,6 +7,7 @@ import os
 import subprocess
 import sys
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -59,3 +60,22 @@ def test_more_than_one_gpu_is_refused():
                          capture_output=True, text=True, timeout=120)
     assert out.returncode == 2
     assert "one GPU only" in out.stdout
+
+
+def test_closed_form_sine_solution_solves_the_sine_part(bench):
+    # the bench's error reference for the mixed-precision workload: A_h of the
+    # closed-form solution reproduces the sine-mode right-hand side (the
+    # oracle's residual, relative to b, at rounding level)
+    import oracle as O
+    from paper_2206_05543_amd.workloads import poisson_problem, sine_sum
+    N = 32
+    p = poisson_problem(3, N, seed=3, n_modes=16, kmax=12)
+    u = bench.closed_form_sine_solution(N, p["modes"], p["weights"], "cpu").numpy()
+    b = sine_sum(3, N, p["modes"], p["weights"])
+    r = O.residual(3, N, u, b)
+    assert np.linalg.norm(r) <= 1e-12 * np.linalg.norm(b)
+
+
+def test_host_cpu_fields(bench):
+    h = bench.host_cpu()
+    assert h["nproc"] >= 1 and 1 <= h["affinity"] <= h["nproc"]

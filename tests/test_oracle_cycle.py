@@ -141,3 +141,15 @@ def test_w_cycle_converges_faster_per_cycle():
     _, kv, _ = O.solve(2, 32, CJ2, p["u0"], p["b"], 1e-8, 80, 1, 1, 1)
     _, kw, _ = O.solve(2, 32, CJ2, p["u0"], p["b"], 1e-8, 80, 1, 1, 2)
     assert 0 < kw <= kv
+
+
+def test_openmp_build_is_bit_identical():
+    # the all-core build splits only loops whose outputs are independent, so
+    # its cycle equals the checker build's bit for bit
+    from paper_2206_05543_amd import M7, M9
+    rng = np.random.default_rng(17)
+    for d, N in ((2, 128), (3, 32)):
+        u = rng.uniform(-1, 1, (N - 1,) * d)
+        b = rng.standard_normal((N - 1,) * d) * N
+        c = np.array(M9 if d == 2 else M7)
+        assert np.array_equal(O.vcycle(d, N, c, u, b), O.vcycle(d, N, c, u, b, parallel=True))
