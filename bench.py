@@ -10,7 +10,8 @@ Also reported: per-workload rates, the roofline of the dominant kernel (of
 the fine-level kernels timed live with HIP events on the launch stream, the
 one with the largest total time), per-level kernel times and GB/s (extra solves after the timed
 region, every launch timed), the time to 1e-10 of the 3D N=512 noisy problem in FP64 and
-with FP32 / FP16 V-cycles inside FP64 refinement, and the CPU oracle timed on
+with FP32 / FP16 V-cycles inside FP64 refinement, forward and backward times
+of the two gradient workloads, and the CPU oracle timed on
 a bounded sample of the same workloads (all host threads, and one thread).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
@@ -137,6 +138,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-examples", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--workloads", default="poisson2d_n4096,poisson3d_n256")
     ap.add_argument("--tol", type=float, default=1e-10)
     return ap.parse_args()
@@ -254,6 +256,8 @@ def main():
 
     if not a.no_mixed:
         line["mixed_precision"] = mixed(a.tol)
+    if not a.no_adjoint:
+        line["adjoint"] = adjoint()
     if not a.no_examples:
         line["paper_examples"] = paper_examples(a.tol)
     if not a.no_cpu:
@@ -363,6 +367,74 @@ def mixed(tol):
     del ucf, ref, u, b, u0
     torch.cuda.empty_cache()
     out["oracle_anchored"] = mixed_oracle_anchored(tol)
+    return out
+
+
+# FP64 bytes per fine point that the adjoint cycle's fine-level kernels read
+# and write (mg_vcycle_adjoint: the forward recomputation smooth, residual,
+# restriction, correction and residual, then two coefficient-gradient
+# sweeps, three update sweeps, one restriction and one interpolation of the
+# reverse pass); c is one coarse value per 2^d fine points
+def adjoint_bytes_per_pt(d):
+    c = 8.0 / 2 ** d
+    forward = 24 + 24 + (16 + c) + (16 + c) + 24
+    reverse = 24 + 40 + (8 + c) + (8 + c) + 40 + 24 + 40
+    return forward + reverse
+
+
+ADJOINT_CASES = (("errors2d_n1024_b16", 2, 1024, 16, 3, "fp64"),
+                 ("errors3d_n256_b4", 3, 256, 4, 2, "fp32"))
+
+
+def adjoint(reps=3):
+    """Forward + backward of the k-cycle loss L = sum ||V^K(e0, 0; c)||^2
+    through the autograd wrapper on the two gradient workloads: 2D N=1024,
+    batch 16, K = 3, FP64 checkpoints; 3D N=256, batch 4, K = 2, FP32
+    checkpoints.  Best of `reps` after a warm-up, timed with events on the
+    current stream."""
+    import torch
+
+    from paper_2206_05543_amd import M7, M9
+    from paper_2206_05543_amd._lib import Multigrid
+    from paper_2206_05543_amd.autograd import kcycles
+    from paper_2206_05543_amd.workloads import workload
+
+    out = {}
+    for name, d, N, batch, K, ck in ADJOINT_CASES:
+        w = workload(name)
+        e0 = torch.from_numpy(w["e0"]).cuda()
+        b = torch.zeros_like(e0)
+        c0 = M9 if d == 2 else M7
+        ckd = torch.float64 if ck == "fp64" else torch.float32
+        mg = Multigrid(N, d, c0, batch=batch)
+        best_f, best_b = float("inf"), float("inf")
+        for it in range(reps + 1):
+            cp = torch.tensor(c0, dtype=torch.float32, requires_grad=True)
+            torch.cuda.synchronize()
+            e1, e2, e3 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+            e1.record()
+            u = kcycles(mg, cp, b, e0, K, ckd)
+            L = (u * u).sum()
+            e2.record()
+            L.backward()
+            e3.record()
+            torch.cuda.synchronize()
+            if it > 0:
+                best_f = min(best_f, e1.elapsed_time(e2))
+                best_b = min(best_b, e2.elapsed_time(e3))
+        mg.close()
+        pts = (N - 1) ** d * batch
+        byt = adjoint_bytes_per_pt(d) * pts * K
+        out[name] = {"d": d, "N": N, "batch": batch, "cycles": K, "checkpoints": ck,
+                     "forward_ms": best_f, "backward_ms": best_b,
+                     "backward_over_forward": best_b / best_f,
+                     "fine_unknowns_per_s_fwd_bwd": pts * K / ((best_f + best_b) * 1e-3),
+                     "adjoint_fine_bytes_per_pt_per_cycle": adjoint_bytes_per_pt(d),
+                     "adjoint_fine_GBps": byt / (best_b * 1e-3) / 1e9,
+                     "adjoint_frac_of_peak": byt / (best_b * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        print(f"[bench] adjoint {name}: {out[name]}", file=sys.stderr, flush=True)
+        del e0, b, u, L
+        torch.cuda.empty_cache()
     return out
 
 
