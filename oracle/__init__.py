@@ -103,9 +103,15 @@ def shape(d, N):
 
 
 def _coeffs(d, c):
+    """The C side's coefficient array: 3 entries in 2D (centre, faces,
+    diagonals); 4 in 3D (centre, faces, edges, corners), where 2 or 3 given
+    entries (the 7- and 19-point families) are padded with zeros."""
     c = _f64(c).ravel()
-    assert c.size == (3 if d == 2 else 2), "2D takes 3 coefficients, 3D takes 2"
-    return c
+    if d == 2:
+        assert c.size == 3, "2D takes 3 coefficients"
+        return c
+    assert c.size in (2, 3, 4), "3D takes 2, 3 or 4 coefficients"
+    return np.concatenate([c, np.zeros(4 - c.size)])
 
 
 def apply_A(d, N, u):
@@ -227,13 +233,14 @@ def vcycle_adjoint(d, N, c, u, b, ubar_out):
     """Reverse-mode derivative of one V(1,1) cycle.  Returns (ubar_in, bbar,
     cbar) for the loss gradient ubar_out = dL/du_out."""
     u, b, ubar_out = _f64(u), _f64(b), _f64(ubar_out)
+    nc = np.size(c)
     c = _coeffs(d, c)
     ubar_in = np.empty_like(u)
     bbar = np.zeros_like(u)
     cbar = np.zeros(c.size)
     lib().or_vcycle_adjoint(d, N, _p(c), _p(u), _p(b), _p(ubar_out),
                             _p(ubar_in), _p(bbar), _p(cbar))
-    return ubar_in, bbar, cbar
+    return ubar_in, bbar, cbar[:nc]
 
 
 def _checkpoint(u, ckpt):
@@ -264,6 +271,7 @@ def grad_kcycles(d, N, c, e0, b, K, ckpt="fp64"):
     the FP32-rounded cycle inputs and the reverse sweep passes derivatives
     through each rounding unchanged (straight-through: the rounding is
     piecewise constant, so its derivative is taken as the identity)."""
+    nc = np.size(c)
     c = _coeffs(d, c)
     cbar = np.zeros(c.size)
     bbar = np.zeros(shape(d, N))
@@ -282,7 +290,7 @@ def grad_kcycles(d, N, c, e0, b, K, ckpt="fp64"):
             bbar += bb
             cbar += cb
         e0bar[s] = ubar
-    return L, cbar, bbar, e0bar
+    return L, cbar[:nc], bbar, e0bar
 
 
 def descend(d, N, c0, e0, b, K, max_iter=200, rtol=1e-7, armijo=1e-4):

@@ -35,17 +35,25 @@ def A(d, N):
 
 
 def K(d, N, which):
-    """K_0 = I, K_1 = face-neighbour sum, K_2 = diagonal-neighbour sum (2D),
-    zero extension (the stencil families of Section 3)."""
+    """K_0 = I, K_1 = face-neighbour sum, K_2 = diagonal-neighbour sum (2D)
+    or edge-neighbour sum (3D), K_3 = corner-neighbour sum (3D), zero
+    extension (the stencil families of Section 3 and the 19-/27-point
+    extensions of the 3D family): the sum over the products with exactly
+    `which` shift factors S (the rest identities)."""
     n = N - 1
     I, S = np.eye(n), _tri(n, 0.0, 1.0)
     if which == 0:
         return np.eye(n ** d)
-    if which == 1:
-        return sum(_kron_all([S if a == ax else I for a in range(d)])
-                   for ax in range(d))
-    assert d == 2
-    return np.kron(S, S)
+    assert which <= d
+    out = np.zeros((n ** d, n ** d))
+    for axes in _subsets(d, which):
+        out += _kron_all([S if a in axes else I for a in range(d)])
+    return out
+
+
+def _subsets(d, k):
+    import itertools
+    return [set(s) for s in itertools.combinations(range(d), k)]
 
 
 def W(d, N, c):

@@ -23,11 +23,19 @@ def symbol_A(d, th):
 def symbol_M(d, c, th):
     """Symbol of M divided by h^2: c0 + 2 c1 sum cos th_k + 4 c2 cos th_1 cos
     th_2 (2D, the Upsilon family of Section 3.1); c0 + 2 c1 sum cos th_k (3D,
-    the T family of Section 3.2)."""
+    the T family of Section 3.2), plus 4 c2 sum_{k<l} cos th_k cos th_l for
+    the 12 edge neighbours and 8 c3 prod cos th_k for the 8 corners when c
+    has 3 or 4 entries (the 19- and 27-point extensions)."""
     cs = np.cos(th)
     s = c[0] + 2.0 * c[1] * cs.sum(axis=-1)
     if d == 2:
         s = s + 4.0 * c[2] * cs[..., 0] * cs[..., 1]
+    else:
+        if len(c) > 2:
+            s = s + 4.0 * c[2] * (cs[..., 0] * cs[..., 1] + cs[..., 0] * cs[..., 2] +
+                                  cs[..., 1] * cs[..., 2])
+        if len(c) > 3:
+            s = s + 8.0 * c[3] * cs[..., 0] * cs[..., 1] * cs[..., 2]
     return s
 
 
@@ -48,6 +56,11 @@ def product_on_high(d, c, m=2000):
     mm = c[0] + 2.0 * c[1] * x.sum(axis=-1)
     if d == 2:
         mm = mm + 4.0 * c[2] * x[:, 0] * x[:, 1]
+    else:
+        if len(c) > 2:
+            mm = mm + 4.0 * c[2] * (x[:, 0] * x[:, 1] + x[:, 0] * x[:, 2] + x[:, 1] * x[:, 2])
+        if len(c) > 3:
+            mm = mm + 8.0 * c[3] * x[:, 0] * x[:, 1] * x[:, 2]
     return a * mm
 
 

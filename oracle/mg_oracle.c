@@ -22,9 +22,13 @@
  *
  * Smoother coefficients c (Section 3): the stencil of M with h^2 taken out
  * and the damping factor omega folded in, i.e. M = h^2 * sum_j c_j K_j with
- * K_0 the identity, K_1 the sum over the 2d face neighbours and K_2 (2D only)
- * the sum over the 4 diagonal neighbours.  M acts on a residual that is zero
- * outside the interior (zero extension).
+ * K_0 the identity, K_1 the sum over the 2d face neighbours and K_2 the sum
+ * over the 4 diagonal neighbours (2D); in 3D K_2 is the sum over the 12 edge
+ * neighbours and K_3 the sum over the 8 corner neighbours, the wider
+ * 19- and 27-point stencils the closing remark of Section 3.2 mentions
+ * (c_2 = c_3 = 0 gives the 7-point family T).  c holds 3 entries in 2D and 4
+ * in 3D.  M acts on a residual that is zero outside the interior (zero
+ * extension).
  */
 #include <math.h>
 #include <stdlib.h>
@@ -99,9 +103,12 @@ void or_apply_A(int d, int N, const double *v, double *out)
 }
 
 /* out = K_which v with zero extension: K_0 = identity, K_1 = sum of the
- * face neighbours, K_2 = sum of the four diagonal neighbours (2D only).
+ * face neighbours, K_2 = sum of the four diagonal neighbours (2D) or of the
+ * twelve edge neighbours (3D: offsets with two nonzero components), K_3 =
+ * sum of the eight corner neighbours (3D only: three nonzero components).
  * These are the building blocks of the 9-point family Upsilon(alpha, beta,
- * gamma) (Section 3.1) and the 7-point family T(alpha, beta) (Section 3.2). */
+ * gamma) (Section 3.1), the 7-point family T(alpha, beta) (Section 3.2) and
+ * its 19- and 27-point extensions. */
 void or_apply_K(int d, int N, int which, const double *v, double *out)
 {
     int n = N - 1;
@@ -122,19 +129,29 @@ void or_apply_K(int d, int N, int which, const double *v, double *out)
                         s += at(v, d, N, i, j, k - 1);
                         s += at(v, d, N, i, j, k + 1);
                     }
-                } else {
+                } else if (d == 2) {
                     s += at(v, d, N, i - 1, j - 1, k);
                     s += at(v, d, N, i + 1, j - 1, k);
                     s += at(v, d, N, i - 1, j + 1, k);
                     s += at(v, d, N, i + 1, j + 1, k);
+                } else {
+                    /* every offset (a, b, c) in {-1, 0, 1}^3 with exactly
+                     * `which` nonzero components (2: edges, 3: corners) */
+                    for (int c = -1; c <= 1; c++)
+                        for (int b = -1; b <= 1; b++)
+                            for (int a = -1; a <= 1; a++)
+                                if ((a != 0) + (b != 0) + (c != 0) == which)
+                                    s += at(v, d, N, i + a, j + b, k + c);
                 }
                 out[idx(d, N, i, j, k)] = s;
             }
 }
 
-static int ncoef(int d) { return d == 2 ? 3 : 2; }
+static int ncoef(int d) { return d == 2 ? 3 : 4; }
 
-/* out = M v = h^2 * sum_j c_j K_j v (Section 3.1: Upsilon; Section 3.2: T). */
+/* out = M v = h^2 * sum_j c_j K_j v (Section 3.1: Upsilon; Section 3.2: T
+ * and its wider extensions).  A zero coefficient of the 3D edge or corner
+ * term is skipped: its term adds nothing. */
 void or_apply_W(int d, int N, const double *c, const double *v, double *out)
 {
     long P = npts(d, N);
@@ -142,6 +159,7 @@ void or_apply_W(int d, int N, const double *c, const double *v, double *out)
     double *t = malloc(sizeof(double) * P);
     memset(out, 0, sizeof(double) * P);
     for (int j = 0; j < ncoef(d); j++) {
+        if (d == 3 && j >= 2 && c[j] == 0.0) continue;
         or_apply_K(d, N, j, v, t);
 #pragma omp parallel for schedule(static)
         for (long p = 0; p < P; p++) out[p] += c[j] * t[p];

@@ -46,17 +46,19 @@ static double *field(long n, unsigned *seed)
 static int run(int d, int N)
 {
     const double c2[3] = {0.28891272760249742, 0.065661983546022137, 0.019698595063806643};
-    const double c3[2] = {16.0 / 73.0, 2.0 / 73.0};
+    /* 3D: centre, faces, edges, corners (a 27-point stencil, so that the
+     * edge and corner terms run too) */
+    const double c3[4] = {0.1966, 0.0397, 0.0115, 0.0037};
     const double *c = d == 2 ? c2 : c3;
     unsigned seed = 7u + (unsigned)(d * 100 + N);
     long P = pts(d, N), Pc = pts(d, N / 2);
     double *u = field(P, &seed), *b = field(P, &seed), *t = field(P, &seed);
     double *w = field(P, &seed), *bc = field(Pc, &seed), *ec = field(Pc, &seed);
     double *ub = field(P, &seed), *ui = field(P, &seed), *bb = field(P, &seed);
-    double cb[3] = {0, 0, 0};
+    double cb[4] = {0, 0, 0, 0};
     double hist[64];
-    for (int k = 0; k < 3; k++) {
-        or_apply_K(d, N, k < (d == 2 ? 3 : 2) ? k : 0, u, t);
+    for (int k = 0; k < (d == 2 ? 3 : 4); k++) {
+        or_apply_K(d, N, k, u, t);
     }
     or_apply_A(d, N, u, t);
     or_apply_W(d, N, c, u, t);

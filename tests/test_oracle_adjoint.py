@@ -10,9 +10,11 @@ from oracle import dense
 
 C9 = np.array([0.28891272760249742, 0.065661983546022137, 0.019698595063806643])
 C7 = np.array([16 / 73, 2 / 73])
+C27 = np.array([0.1966, 0.0397, 0.0115, 0.0037])  # 27-point 3D stencil
 
 
-@pytest.mark.parametrize("d,N,c", [(2, 16, C9), (2, 32, C9), (3, 8, C7), (3, 16, C7)])
+@pytest.mark.parametrize("d,N,c", [(2, 16, C9), (2, 32, C9), (3, 8, C7), (3, 16, C7),
+                                   (3, 8, C27)])
 def test_dot_product(d, N, c):
     # the cycle is affine in (u, b): V(u + du, b + db) - V(u, b) = E du + B db,
     # so <ubar_out, E du + B db> = <ubar_in, du> + <bbar, db>
@@ -40,7 +42,7 @@ def test_rhs_adjoint_is_forward_cycle(d, N, c):
 
 
 @pytest.mark.parametrize("d,N,c,K", [(2, 16, C9, 3), (2, 8, np.array([0.3, 0.05, 0.02]), 2),
-                                     (3, 8, C7, 2)])
+                                     (3, 8, C7, 2), (3, 8, C27, 2), (3, 8, C27[:3], 2)])
 def test_coefficient_gradient_vs_complex_step(d, N, c, K):
     rng = np.random.default_rng(3)
     e0 = rng.uniform(-1, 1, (2,) + (N - 1,) * d)

@@ -12,6 +12,7 @@ from paper_2206_05543_amd.workloads import poisson_problem, sine_sum, workload
 
 C9 = np.array([0.28891272760249742, 0.065661983546022137, 0.019698595063806643])
 C7 = np.array([16 / 73, 2 / 73])
+C27 = np.array([0.1966, 0.0397, 0.0115, 0.0037])  # 27-point 3D stencil
 CJ2 = np.array([0.2, 0.0, 0.0])
 CM5 = np.array([12 / 41, 2 / 41, 0.0])
 CJ3 = np.array([1 / 7, 0.0])
@@ -38,7 +39,8 @@ def _loop_two_grid(d, N, c, nu1, nu2):
 
 @pytest.mark.parametrize("d,N,c,nu1,nu2", [(2, 16, C9, 1, 0), (2, 16, C9, 1, 1),
                                            (2, 32, C9, 1, 1), (2, 16, CM5, 1, 1),
-                                           (3, 8, C7, 1, 1), (3, 8, CJ3, 1, 1)])
+                                           (3, 8, C7, 1, 1), (3, 8, CJ3, 1, 1),
+                                           (3, 8, C27, 1, 1)])
 def test_two_grid_spectral_radius_equals_dirichlet_lfa(d, N, c, nu1, nu2):
     E = _loop_two_grid(d, N, c, nu1, nu2)
     rho = np.max(np.abs(np.linalg.eigvals(E)))
@@ -60,7 +62,8 @@ def _loop_cycle_maps(d, N, c, gamma=1, nu1=1, nu2=1):
 
 @pytest.mark.parametrize("d,N,c,gamma,nu1,nu2", [
     (2, 16, C9, 1, 1, 1), (2, 32, C9, 1, 1, 1), (2, 16, CJ2, 2, 1, 1), (3, 8, C7, 1, 1, 1),
-    (3, 8, C7, 2, 1, 1), (2, 16, C9, 2, 1, 0), (2, 32, CM5, 2, 1, 0), (3, 8, C7, 2, 1, 0)])
+    (3, 8, C7, 2, 1, 1), (2, 16, C9, 2, 1, 0), (2, 32, CM5, 2, 1, 0), (3, 8, C7, 2, 1, 0),
+    (3, 8, C27, 1, 1, 1), (3, 8, C27[:3], 1, 1, 1)])
 def test_cycle_operator_matches_matrix_recursion(d, N, c, gamma, nu1, nu2):
     E, B = _loop_cycle_maps(d, N, c, gamma, nu1, nu2)
     Ed, Bd = dense.vcycle_maps(d, N, c, nu1, nu2, gamma)

@@ -29,11 +29,20 @@ def lam_A(N, ks):
 
 
 def sym_M_h2(d, c, N, ks):
-    # (M phi)/phi = h^2 [c0 + 2 c1 sum cos th + 4 c2 cos th1 cos th2]
+    # (M phi)/phi = h^2 [c0 + 2 c1 sum cos th + 4 c2 cos th1 cos th2] in 2D;
+    # in 3D the edge term 4 c2 sum_{a<b} cos th_a cos th_b and the corner
+    # term 8 c3 prod cos th_a (each neighbour pair of offsets +-1 along an
+    # axis contributes 2 cos th, and the neighbour sets are products)
     th = [k * np.pi / N for k in ks]
-    s = c[0] + 2 * c[1] * sum(np.cos(t) for t in th)
+    cs = [np.cos(t) for t in th]
+    s = c[0] + 2 * c[1] * sum(cs)
     if d == 2:
-        s += 4 * c[2] * np.cos(th[0]) * np.cos(th[1])
+        s += 4 * c[2] * cs[0] * cs[1]
+    else:
+        if len(c) > 2:
+            s += 4 * c[2] * (cs[0] * cs[1] + cs[0] * cs[2] + cs[1] * cs[2])
+        if len(c) > 3:
+            s += 8 * c[3] * cs[0] * cs[1] * cs[2]
     return s / (N * N)
 
 
@@ -68,8 +77,14 @@ def test_A_exact_on_quadratics(d, N):
     assert np.max(np.abs(O.apply_A(d, N, u) - f)) <= 1e-11
 
 
+C19 = np.array([0.2034, 0.0383, 0.0076])        # 19-point: centre, faces, edges
+C27 = np.array([0.1966, 0.0397, 0.0115, 0.0037])  # 27-point: + corners
+
+
 @pytest.mark.parametrize("d,N,c", [(2, 16, C9), (2, 32, np.array([0.3, -0.1, 0.07])),
-                                   (3, 8, C7), (3, 16, np.array([0.2, 0.05]))])
+                                   (3, 8, C7), (3, 16, np.array([0.2, 0.05])),
+                                   (3, 8, C19), (3, 16, C27),
+                                   (3, 8, np.array([0.1, -0.02, 0.03, -0.05]))])
 def test_smoother_sine_eigenpairs(d, N, c):
     for ks in MODES[d]:
         if max(ks) >= N:
@@ -190,3 +205,41 @@ def test_dense_matrices_match_loop_operators(d, N):
     g = rng.standard_normal((N // 2 - 1,) * d)
     assert np.allclose(dense.P(d, N) @ g.ravel(),
                        O.prolong_add(d, N, g, np.zeros_like(v)).ravel(), atol=1e-14)
+
+
+@pytest.mark.parametrize("which,count", [(2, 12), (3, 8)])
+def test_3d_edge_and_corner_sums(which, count):
+    # the loop operators against the Kronecker sums of shift matrices, and
+    # the neighbour count on a node far from the boundary
+    N = 8
+    rng = np.random.default_rng(which)
+    v = rng.standard_normal((N - 1,) * 3)
+    got = O.apply_K(3, N, which, v)
+    want = (dense.K(3, N, which) @ v.ravel()).reshape(v.shape)
+    assert np.max(np.abs(got - want)) <= 1e-14
+    one = np.zeros((N - 1,) * 3)
+    one[3, 3, 3] = 1.0
+    assert O.apply_K(3, N, which, one).sum() == count
+
+
+def test_wide_3d_smoother_high_modes_reach_searched_mu():
+    # the sine modes with some index >= N/2 are the high frequencies; the
+    # largest |S| over them tends to the searched optimum mu of the 27-point
+    # family from below, and the oracle's smoother has exactly these
+    # eigenvalues
+    from oracle import search
+    r = search.search(3, "27pt", m=24, refine_m=60)
+    c = np.asarray(r["coeffs"])
+    N = 64
+    k = np.arange(1, N)
+    x = np.cos(k * np.pi / N)
+    X = np.stack(np.meshgrid(x, x, x, indexing="ij"), -1).reshape(-1, 3)
+    K = np.stack(np.meshgrid(k, k, k, indexing="ij"), -1).reshape(-1, 3)
+    s = np.abs(1.0 - search.symbol_product(3, c, X))
+    high = np.any(K >= N // 2, axis=1)
+    assert r["mu"] - 5e-3 < s[high].max() <= r["mu"] * (1 + 1e-4)
+    for ks in [(N // 2, 1, 3), (N - 1, 5, N // 2), (2, N - 2, 40)]:
+        phi = sine(3, N, ks)
+        out = O.smooth(3, N, c, phi, np.zeros_like(phi))
+        lam = 1.0 - lam_A(N, ks) * sym_M_h2(3, c, N, ks)
+        assert np.max(np.abs(out - lam * phi)) <= 1e-12
