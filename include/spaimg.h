@@ -10,9 +10,12 @@
  * by the caller (b_i += g/h^2 at nodes next to the boundary).
  *
  * Smoother (Section 2, eq. (smoother)): u <- u + M (b - A_h u) with
- * M = h^2 (c0 K0 + c1 K1 + c2 K2), K0 = identity, K1 = sum over the 2d face
- * neighbours, K2 = sum over the 4 diagonal neighbours (2D only), applied to a
- * residual that is zero outside the grid.  The coefficients are h-free and
+ * M = h^2 (c0 K0 + c1 K1 + c2 K2 [+ c3 K3]), K0 = identity, K1 = sum over the
+ * 2d face neighbours, K2 = sum over the 4 diagonal neighbours (2D) or the 12
+ * edge neighbours (3D), K3 = sum over the 8 corner neighbours (3D), applied
+ * to a residual that is zero outside the grid.  In 3D, c2 and c3 give the
+ * wider 19- and 27-point stencils the closing remark of Section 3.2 mentions
+ * (c2 = c3 = 0: the 7-point family T).  The coefficients are h-free and
  * include the damping factor omega; the same coefficients are used on every
  * level (rediscretisation, Section 4).  The paper's smoothers:
  *   2D M9 (Theorem 3.1): omega = (309 - 12 sqrt(10))/1720, (c0, c1, c2) =
@@ -139,7 +142,10 @@ typedef struct mg_stats {
 
 /* Creates a solver for N intervals per direction (power of two, 4 <= N <=
  * 65536 in 2D, <= 2048 in 3D) in d = 2 or 3 dimensions with n_coeffs = 3
- * (2D) or 2 (3D) host FP64 coefficients (see above).  Allocates the level
+ * (2D: centre, faces, diagonals) or 2, 3 or 4 (3D: centre, faces[, edges[,
+ * corners]]) host FP64 coefficients (see above).  A 3D stencil with a
+ * nonzero edge or corner coefficient runs the wide smoother kernel and a
+ * separate restriction on every level.  Allocates the level
  * hierarchy (about (1/3 + 1/(2^d - 1)) of one fine field per batch entry plus
  * two fine FP64 fields).  *out receives the handle. */
 int mg_setup(int N, int d, const double* spai_coeffs, int n_coeffs, mg_handle_t* out);
@@ -148,7 +154,8 @@ int mg_setup(int N, int d, const double* spai_coeffs, int n_coeffs, mg_handle_t*
  * internal buffers. */
 int mg_set_option(mg_handle_t h, int key, double value);
 
-/* Replaces the smoother coefficients (host FP64, n_coeffs as in mg_setup). */
+/* Replaces the smoother coefficients (host FP64, n_coeffs equal to
+ * mg_setup's). */
 int mg_set_coeffs(mg_handle_t h, const double* spai_coeffs, int n_coeffs);
 
 /* One FP64 V(1,1) cycle for every batch entry: u <- V(u, b), in place.
@@ -214,7 +221,7 @@ int mg_checkpoint(mg_handle_t h, double* u, void* ckpt, int ckpt_dtype, void* st
  * (Section 4 cycle, Section 2 smoother, differentiated by hand): given
  * ubar_out = dL/du_out, writes ubar_in = dL/du_in (may alias ubar_out),
  * accumulates bbar_acc += dL/db (device, batch-shaped) and cbar_acc[j] +=
- * dL/dc_j summed over the batch (HOST FP64 array of n_coeffs).  u_in is the
+ * dL/dc_j summed over the batch (HOST FP64 array of mg_setup's n_coeffs).  u_in is the
  * cycle's checkpoint as written by mg_checkpoint: device, batch-shaped, FP64
  * (ckpt_dtype = MG_CKPT_FP64) or FP32 (MG_CKPT_FP32, widened exactly to FP64
  * inside the library).  The forward states of every level are recomputed
@@ -245,8 +252,8 @@ int mg_sweep(mg_handle_t h, int op, int level, int prec, const void* u, const vo
  * - A e) on level+1, in one kernel (the kernel mg_solve and mg_vcycle use
  * for zero-guess cycles; Section 4, V-cycle with a zero initial guess on the
  * coarse levels).  b, e: the level's shape; bc: level+1's shape.  Errors:
- * MG_EINVAL for a null handle or pointer, a bad precision, or no coarser
- * level. */
+ * MG_EINVAL for a null handle or pointer, a bad precision, no coarser level,
+ * or a 3D 19-/27-point stencil (this kernel carries the 7-point one). */
 int mg_sweep_zero_restrict(mg_handle_t h, int level, int prec, const void* b, void* e, void* bc,
                            void* stream);
 
@@ -256,7 +263,7 @@ int mg_sweep_zero_restrict(mg_handle_t h, int level, int prec, const void* b, vo
  * mg_solve and mg_vcycle use for the finest level's pre-smoothing; Section
  * 4, V(1,1) cycle).  u, b, out: the level's shape, out must not alias u or
  * b; bc: level+1's shape.  Errors: MG_EINVAL for a null handle or pointer, a
- * bad precision, or no coarser level. */
+ * bad precision, no coarser level, or a 3D 19-/27-point stencil. */
 int mg_sweep_smooth_restrict(mg_handle_t h, int level, int prec, const void* u, const void* b,
                              void* out, void* bc, void* stream);
 

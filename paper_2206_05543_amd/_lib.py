@@ -118,7 +118,7 @@ class Multigrid:
                  tail_N=0, timing=0, cycle="V11"):
         self.N, self.d = int(N), int(d)
         self.n = self.N - 1
-        self.ncoef = 3 if d == 2 else 2
+        self.ncoef = len(coeffs)
         h = ctypes.c_void_p()
         c = _dbl_array(coeffs)
         _check(lib().mg_setup(self.N, self.d, c, len(coeffs), ctypes.byref(h)))

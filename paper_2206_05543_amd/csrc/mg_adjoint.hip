@@ -46,9 +46,23 @@ struct Grid {
         if (d == 3) s += at(a, i, j, k - 1) + at(a, i, j, k + 1);
         return s;
     }
-    __device__ __forceinline__ double corners(const double* a, int i, int j, int k) const {
-        return at(a, i - 1, j - 1, k) + at(a, i + 1, j - 1, k) + at(a, i - 1, j + 1, k) +
-               at(a, i + 1, j + 1, k);
+    // K_2: the 4 diagonal neighbours in 2D, the 12 edge neighbours in 3D
+    __device__ __forceinline__ double diag(const double* a, int i, int j, int k) const {
+        double s = at(a, i - 1, j - 1, k) + at(a, i + 1, j - 1, k) + at(a, i - 1, j + 1, k) +
+                   at(a, i + 1, j + 1, k);
+        if (d == 3)
+            s += at(a, i - 1, j, k - 1) + at(a, i + 1, j, k - 1) + at(a, i, j - 1, k - 1) +
+                 at(a, i, j + 1, k - 1) + at(a, i - 1, j, k + 1) + at(a, i + 1, j, k + 1) +
+                 at(a, i, j - 1, k + 1) + at(a, i, j + 1, k + 1);
+        return s;
+    }
+    // K_3: the 8 corner neighbours (3D)
+    __device__ __forceinline__ double corners3(const double* a, int i, int j, int k) const {
+        double s = 0.0;
+        for (int c = -1; c <= 1; c += 2)
+            for (int b = -1; b <= 1; b += 2)
+                for (int a2 = -1; a2 <= 1; a2 += 2) s += at(a, i + a2, j + b, k + c);
+        return s;
     }
 };
 
@@ -77,34 +91,39 @@ k_residual(const double* __restrict__ u, const double* __restrict__ b, double* _
     }
 }
 
-// w = sW (c0 K0 + c1 K1 + c2 K2) ubar and per-block partial sums of
-// (K_j ubar)(p) r(p), j = 0..2, into partials[3 * block + j]
+// w = sW (c0 K0 + c1 K1 + c2 K2 + c3 K3) ubar and per-block partial sums of
+// (K_j ubar)(p) r(p), j = 0..3, into partials[4 * block + j]
 __global__ void __launch_bounds__(256)
 k_adj_applyK(const double* __restrict__ ub, const double* __restrict__ r, double* __restrict__ w,
-             double* __restrict__ partials, Grid g, double sW, double c0, double c1, double c2) {
+             double* __restrict__ partials, Grid g, double sW, double c0, double c1, double c2,
+             double c3) {
     __shared__ double red[4];
     const long off = (long)blockIdx.y * g.pts;
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
     for (long p = (long)blockIdx.x * 256 + threadIdx.x; p < g.pts; p += (long)gridDim.x * 256) {
         int i, j, k;
         g.coords(p, &i, &j, &k);
         const double k0 = ub[off + p];
         const double k1 = g.faces(ub + off, i, j, k);
-        const double k2 = g.d == 2 ? g.corners(ub + off, i, j, k) : 0.0;
-        w[off + p] = sW * (c0 * k0 + c1 * k1 + c2 * k2);
+        const double k2 = g.diag(ub + off, i, j, k);
+        const double k3 = g.d == 3 ? g.corners3(ub + off, i, j, k) : 0.0;
+        w[off + p] = sW * (c0 * k0 + c1 * k1 + c2 * k2 + c3 * k3);
         const double rv = r[off + p];
         s0 += k0 * rv;
         s1 += k1 * rv;
         s2 += k2 * rv;
+        s3 += k3 * rv;
     }
     const double t0 = block_sum256(s0, red);
     const double t1 = block_sum256(s1, red);
     const double t2 = block_sum256(s2, red);
+    const double t3 = block_sum256(s3, red);
     if (threadIdx.x == 0) {
         const long bi = (long)blockIdx.y * gridDim.x + blockIdx.x;
-        partials[3 * bi + 0] = t0;
-        partials[3 * bi + 1] = t1;
-        partials[3 * bi + 2] = t2;
+        partials[4 * bi + 0] = t0;
+        partials[4 * bi + 1] = t1;
+        partials[4 * bi + 2] = t2;
+        partials[4 * bi + 3] = t3;
     }
 }
 
@@ -243,10 +262,10 @@ hipError_t launch_adj_applyK(int d, int n, int batch, const double* ubar, const 
     const Grid g = make_grid(d, n);
     const dim3 grid = point_grid(g.pts, batch);
     const long nb = (long)grid.x * grid.y;
-    if (3 * nb > partials_cap) return hipErrorInvalidValue;
+    if (4 * nb > partials_cap) return hipErrorInvalidValue;
     if (nparts) *nparts = (int)nb;
     hipLaunchKernelGGL(k_adj_applyK, grid, dim3(256), 0, st, ubar, r, w, partials, g, sW, c[0],
-                       c[1], d == 2 ? c[2] : 0.0);
+                       c[1], c[2], d == 3 ? c[3] : 0.0);
     return hipGetLastError();
 }
 

@@ -66,7 +66,7 @@ struct mg_ctx {
     int inner = 0;   // inner cycles per refinement step, 0 = default
     int cycle_kind = MG_CYCLE_V11;
     int ncoef = 3;
-    double c[3] = {0, 0, 0};
+    double c[4] = {0, 0, 0, 0};  // centre, faces, diagonals (2D) / edges, corners (3D)
     Hier h64, hlo;
     double* ualt = nullptr;      // FP64 fine ping-pong buffer
     double* psum = nullptr;      // per-block partial sums
@@ -88,7 +88,7 @@ struct mg_ctx {
     std::vector<double*> adj_r1, adj_r3, adj_w, adj_ua, adj_ub, adj_uo, adj_bb;
     double* adj_cin = nullptr;   // FP64 copy of an FP32 checkpoint (fine level)
     bool adj_alloc = false;
-    double* adj_cacc = nullptr;  // device accumulator of dL/dc (3 doubles)
+    double* adj_cacc = nullptr;  // device accumulator of dL/dc (4 doubles)
     // timing
     int timing = 0;
     std::vector<hipEvent_t> ev_pool;
@@ -368,7 +368,7 @@ Sweep make_sweep(const mg_ctx* h, const Hier& H, int l) {
     s.batch = h->batch;
     double pf;
     level_scales(h, H, l, &s.sA, &s.sW, &pf);
-    for (int j = 0; j < 3; ++j) s.c[j] = j < h->ncoef ? h->c[j] : 0.0;
+    for (int j = 0; j < 4; ++j) s.c[j] = j < h->ncoef ? h->c[j] : 0.0;
     return s;
 }
 
@@ -381,7 +381,7 @@ int run_tail(mg_ctx* h, Hier& H, int l, const void* b, void* e, hipStream_t st,
     t.batch = h->batch;
     t.b = b;
     t.e = e;
-    for (int j = 0; j < 3; ++j) t.c[j] = j < h->ncoef ? h->c[j] : 0.0;
+    for (int j = 0; j < 4; ++j) t.c[j] = j < h->ncoef ? h->c[j] : 0.0;
     t.ginv = H.ginv;
     t.scaled = H.scaled;
     t.N_top = level_N(h, l);
@@ -394,6 +394,12 @@ struct NormReq {
     hipEvent_t ready = nullptr;     // recorded after the copy to the host
 };
 
+// A 3D hierarchy with the 19-/27-point smoother (nonzero edge or corner
+// coefficient): its sweeps use the wide variant of the smoother kernel and
+// the separate restriction (the fused smoother + restriction kernels carry
+// the 7-point stencil only).
+bool wide_3d(const mg_ctx* h) { return h->d == 3 && (h->c[2] != 0.0 || h->c[3] != 0.0); }
+
 // Where the zero-guess pre-smoother and the restriction run as one kernel:
 // 2D, every level above the tail (a tile kernel; its halo costs 1.3x the
 // reads of b); 3D grids of 200 or more nodes per direction (the
@@ -401,14 +407,18 @@ struct NormReq {
 // n = 255 in FP64, 327 against 478 us at n = 511 with FP32 storage).  On
 // smaller 3D grids its twelve-plane unroll makes short marches slower than
 // the two sweeps (12.5 against 9.6 us at n = 63).
-bool fuse_zero_restrict(const mg_ctx* h, int l) { return h->d == 2 || level_n(h, l) >= 200; }
+bool fuse_zero_restrict(const mg_ctx* h, int l) {
+    return h->d == 2 || (level_n(h, l) >= 200 && !wide_3d(h));
+}
 
 // Where the pre-smoother from a nonzero iterate (the finest level of every
 // cycle, the second coarse visit of a W(1,0) cycle) and the restriction run
 // as one kernel: 2D, every level (88 against 136 us at n = 4095); 3D grids
 // of 200 or more nodes per direction (108 against 138 us at n = 255; on
 // smaller grids the ring-3 halo of its tiles costs what the fusion saves).
-bool fuse_smooth_restrict(const mg_ctx* h, int l) { return h->d == 2 || level_n(h, l) >= 200; }
+bool fuse_smooth_restrict(const mg_ctx* h, int l) {
+    return h->d == 2 || (level_n(h, l) >= 200 && !wide_3d(h));
+}
 
 // Which part of a cycle to enqueue: all of it, only the pre-smoother (with
 // its norm), or everything after the pre-smoother (tmp holds its output).
@@ -641,20 +651,20 @@ int check_problem(int N, int d, const double* coeffs, int n_coeffs) {
     if (d != 2 && d != 3) return fail(MG_EINVAL, "d must be 2 or 3");
     if (N < 4 || (N & (N - 1)) != 0) return fail(MG_EINVAL, "N must be a power of two >= 4");
     if ((d == 2 && N > 65536) || (d == 3 && N > 2048)) return fail(MG_EINVAL, "N too large");
-    const int nc = d == 2 ? 3 : 2;
-    if (!coeffs || n_coeffs != nc)
-        return fail(MG_EINVAL, d == 2 ? "2D takes 3 coefficients" : "3D takes 2 coefficients");
-    for (int j = 0; j < nc; ++j)
+    if (!coeffs || (d == 2 && n_coeffs != 3) || (d == 3 && (n_coeffs < 2 || n_coeffs > 4)))
+        return fail(MG_EINVAL, d == 2 ? "2D takes 3 coefficients"
+                                      : "3D takes 2, 3 or 4 coefficients");
+    for (int j = 0; j < n_coeffs; ++j)
         if (!std::isfinite(coeffs[j])) return fail(MG_EINVAL, "coefficients must be finite");
     return MG_OK;
 }
 
 // Problem fields of a context (arguments already checked); the level count
 // of N <= 65536 stays below kMaxLevels.
-void init_problem(mg_ctx* h, int N, int d, const double* coeffs) {
+void init_problem(mg_ctx* h, int N, int d, const double* coeffs, int n_coeffs) {
     h->N = N;
     h->d = d;
-    h->ncoef = d == 2 ? 3 : 2;
+    h->ncoef = n_coeffs;
     for (int j = 0; j < h->ncoef; ++j) h->c[j] = coeffs[j];
     h->L = 0;
     for (int M = N; M >= 4; M /= 2) h->L++;
@@ -749,7 +759,7 @@ int mg_setup(int N, int d, const double* coeffs, int n_coeffs, mg_handle_t* out)
     *out = nullptr;
     if (check_problem(N, d, coeffs, n_coeffs)) return MG_EINVAL;
     mg_ctx* h = new mg_ctx;
-    init_problem(h, N, d, coeffs);
+    init_problem(h, N, d, coeffs, n_coeffs);
     int rc = realloc_all(h);
     if (rc) {
         mg_destroy(h);
@@ -846,7 +856,7 @@ int mg_vcycle_noalloc(int N, int d, const double* coeffs, int n_coeffs, int batc
     // off and no norm is requested, so the cycle neither allocates nor
     // synchronises
     mg_ctx h;
-    init_problem(&h, N, d, coeffs);
+    init_problem(&h, N, d, coeffs, n_coeffs);
     h.batch = batch;
     const size_t need = carve_hier(&h, nullptr, nullptr);
     if (need > kScratchBytes)
@@ -910,6 +920,9 @@ int mg_sweep_zero_restrict(mg_handle_t h, int level, int prec, const void* b, vo
     if (prec < MG_PREC_FP64 || prec > MG_PREC_FP16_IR) return fail(MG_EINVAL, "bad precision");
     if (level < 0 || level >= h->L - 1) return fail(MG_EINVAL, "bad level (no coarser level)");
     if (!b || !e || !bc) return fail(MG_EINVAL, "null field pointer");
+    if (wide_3d(h))
+        return fail(MG_EINVAL, "the fused smoother + restriction kernels take the 7-point "
+                               "3D stencil (edge and corner coefficients must be zero)");
     const Prec p = prec == MG_PREC_FP64 ? P64 : (prec == MG_PREC_FP32_IR ? P32 : P16);
     Hier H;
     H.p = p;
@@ -929,6 +942,9 @@ int mg_sweep_smooth_restrict(mg_handle_t h, int level, int prec, const void* u, 
     if (prec < MG_PREC_FP64 || prec > MG_PREC_FP16_IR) return fail(MG_EINVAL, "bad precision");
     if (level < 0 || level >= h->L - 1) return fail(MG_EINVAL, "bad level (no coarser level)");
     if (!u || !b || !out || !bc) return fail(MG_EINVAL, "null field pointer");
+    if (wide_3d(h))
+        return fail(MG_EINVAL, "the fused smoother + restriction kernels take the 7-point "
+                               "3D stencil (edge and corner coefficients must be zero)");
     const Prec p = prec == MG_PREC_FP64 ? P64 : (prec == MG_PREC_FP32_IR ? P32 : P16);
     Hier H;
     H.p = p;
@@ -1509,7 +1525,7 @@ int alloc_adj(mg_ctx* h) {
             HIPCHK(hipMalloc(&h->adj_ub[l], bytes));
         }
     }
-    HIPCHK(hipMalloc(&h->adj_cacc, 3 * sizeof(double)));
+    HIPCHK(hipMalloc(&h->adj_cacc, 4 * sizeof(double)));
     HIPCHK(hipMalloc(&h->adj_cin, (size_t)level_pts(h, 0) * h->batch * sizeof(double)));
     h->adj_alloc = true;
     return MG_OK;
@@ -1559,7 +1575,8 @@ int adj_reverse(mg_ctx* h, int l, const double* uo, double* ui, double* bb, cons
         if (ui) HIPCHK(hipMemsetAsync(ui, 0, (size_t)level_pts(h, l) * b * sizeof(double), st));
         return MG_OK;
     }
-    double c[3] = {h->c[0], h->c[1], h->ncoef == 3 ? h->c[2] : 0.0};
+    double c[4] = {h->c[0], h->c[1], h->ncoef > 2 ? h->c[2] : 0.0,
+                   h->ncoef > 3 ? h->c[3] : 0.0};
     double* w = h->adj_w[l];
     double* ua = h->adj_ua[l];
     double* ub = h->adj_ub[l];
@@ -1567,7 +1584,7 @@ int adj_reverse(mg_ctx* h, int l, const double* uo, double* ui, double* bb, cons
     int np = 0;
     // post-smoothing  u_out = u2 + M r3, r3 = b - A u2
     HIPCHK(launch_adj_applyK(d, n, b, uo, h->adj_r3[l], w, h->psum, cap, h2, c, st, &np));
-    HIPCHK(launch_reduce_cols(h->psum, np, 3, h->adj_cacc, h2, st));
+    HIPCHK(launch_reduce_cols(h->psum, np, 4, h->adj_cacc, h2, st));
     HIPCHK(launch_adj_update(d, n, b, uo, w, ua, bb, N * N, st));
     // correction u2 = u1 + P e_c: ecbar = P^T ubar2 = 2^d R ubar2
     HIPCHK(launch_fw(d, n, b, ua, h->adj_uo[l + 1], d == 2 ? 4.0 : 8.0, st));
@@ -1581,7 +1598,7 @@ int adj_reverse(mg_ctx* h, int l, const double* uo, double* ui, double* bb, cons
     HIPCHK(launch_adj_update(d, n, b, ua, w, ub, bb, N * N, st));
     // pre-smoothing  u1 = u + M r1, r1 = b - A u
     HIPCHK(launch_adj_applyK(d, n, b, ub, r1, w, h->psum, cap, h2, c, st, &np));
-    HIPCHK(launch_reduce_cols(h->psum, np, 3, h->adj_cacc, h2, st));
+    HIPCHK(launch_reduce_cols(h->psum, np, 4, h->adj_cacc, h2, st));
     if (ui) HIPCHK(launch_adj_update(d, n, b, ub, w, ui, bb, N * N, st));
     else HIPCHK(launch_adj_update(d, n, b, ub, w, ua, bb, N * N, st));
     return MG_OK;
@@ -1622,7 +1639,7 @@ extern "C" int mg_vcycle_adjoint(mg_handle_t h, const double* b, const void* u_c
                             level_pts(h, 0) * h->batch, st));
         u_in = h->adj_cin;
     }
-    HIPCHK(hipMemsetAsync(h->adj_cacc, 0, 3 * sizeof(double), st));
+    HIPCHK(hipMemsetAsync(h->adj_cacc, 0, 4 * sizeof(double), st));
     if (h->L == 1) {
         // single grid: u_out = A^{-1} b
         HIPCHK(launch_coarse_matvec(h->d == 2 ? 9 : 27, h->batch, h->h64.ginv, ubar_out, bbar_acc,
@@ -1634,8 +1651,8 @@ extern "C" int mg_vcycle_adjoint(mg_handle_t h, const double* b, const void* u_c
         rc = adj_reverse(h, 0, ubar_out, ubar_in, bbar_acc, h->adj_r1[0], st);
         if (rc) return rc;
     }
-    double hc[3];
-    HIPCHK(hipMemcpyAsync(hc, h->adj_cacc, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
+    double hc[4];
+    HIPCHK(hipMemcpyAsync(hc, h->adj_cacc, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     for (int j = 0; j < h->ncoef; ++j) cbar_acc[j] += hc[j];
     return MG_OK;

@@ -26,7 +26,8 @@ struct Sweep {
     int n = 0;                   // interior nodes per direction (fine grid)
     int batch = 1;
     double sA = 0, sW = 0;
-    double c[3] = {0, 0, 0};     // SPAI coefficients (centre, face, corner)
+    double c[4] = {0, 0, 0, 0};  // SPAI coefficients: centre, faces, then the
+                                 // diagonals (2D) or edges and corners (3D)
     double* partials = nullptr;  // per-block sum r^2 (norm variant)
     long partials_cap = 0;       // entries available in partials
     // optional fused correction: the sweep reads u + pf * P ec, where ec is a
@@ -83,7 +84,7 @@ struct Tail {
     int d = 2, nt = 0, batch = 1;
     const void* b = nullptr;
     void* e = nullptr;
-    double c[3] = {0, 0, 0};
+    double c[4] = {0, 0, 0, 0};
     const double* ginv = nullptr;  // device: sigma_0 * A_0^{-1}, (3^d)^2
     double sigma_top = 1.0;        // storage scale of the top tail level
     bool scaled = false;           // scaled hierarchy (sigma_l = 1/h_l^2)
@@ -134,8 +135,8 @@ hipError_t launch_ir_step(Prec p, const IRStep& s, hipStream_t st, int* nparts);
 //   r = b - inv_h2 L u
 hipError_t launch_residual(int d, int n, int batch, const double* u, const double* b,
                            double* r, double inv_h2, hipStream_t st);
-//   w = sW (c0 K0 + c1 K1 + c2 K2) ubar; partials[3 i + j] = block sums of
-//   (K_j ubar) r
+//   w = sW sum_j c_j K_j ubar (K_2: diagonals in 2D, edges in 3D; K_3:
+//   corners, 3D); partials[4 i + j] = block sums of (K_j ubar) r, j = 0..3
 hipError_t launch_adj_applyK(int d, int n, int batch, const double* ubar, const double* r,
                              double* w, double* partials, long partials_cap, double sW,
                              const double* c, hipStream_t st, int* nparts);

@@ -221,14 +221,20 @@ __device__ void finalize_norm(const double* ps, const double* pm, int count, dou
 // through plane buffer resources (off-grid reads are zero, off-tile stores
 // are dropped), LDS writes of lanes past the tile land in a scratch area,
 // and the residual outside the grid is cleared with a select.
+//
+// WIDE: the 19-/27-point SPAI stencils (K_c + c2 x 12 edge neighbours + c3 x
+// 8 corner neighbours), which need the in-plane neighbours of all three
+// residual planes around an output plane: the residual planes live in a
+// ring of four LDS slots and the output lags the residual by two planes, so
+// every plane a step reads was written before that step's barrier.
 // ---------------------------------------------------------------------------
 template <typename S, typename C, int TX, int TY, int NT, int PD, int UN, bool ZG, bool NORM,
-          bool PRO, bool NTS>
+          bool PRO, bool NTS, bool WIDE = false>
 __global__ void __launch_bounds__(NT)
 k_smooth3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out,
            int n, int tiles_x, int tiles_y, int zchunk, int nchunks, C sA,
            C sW, C c0, C c1, double* __restrict__ partials,
-           const S* __restrict__ ec, int nc, C pf) {
+           const S* __restrict__ ec, int nc, C pf, C c2 = C(0), C c3 = C(0)) {
     constexpr int RX = TX + 2, RY = TY + 2, NR = RX * RY;
     constexpr int UX = TX + 4, UY = TY + 4, NU = UX * UY;
     constexpr int M = (NR + NT - 1) / NT;
@@ -243,7 +249,7 @@ k_smooth3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out
     static_assert(NR2 <= NT, "one thread per ring-2 point");
     static_assert(TX % 2 == 0 && TY % 2 == 0, "even tiles");
     __shared__ C uL[2][ZG ? 1 : USZ];
-    __shared__ C rL[2][RSZ];
+    __shared__ C rL[WIDE ? 4 : 2][RSZ];
     __shared__ C cL[PRO ? MC * NT : 1];
     __shared__ double red[NT / 64];
 
@@ -388,7 +394,7 @@ k_smooth3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out
         take_raw(p, ru[sl], rr2[sl], qh, dst, rdst);
     };
 
-    C um1[M], u0[M], up1[M], rm2[M], rm1[M], r0[M];
+    C um2[M], um1[M], u0[M], up1[M], rm2[M], rm1[M], r0[M];
     C ur0 = 0, urp1 = 0;
     double nacc = 0.0;
     const int s0 = z0 - 1;
@@ -442,7 +448,7 @@ k_smooth3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out
             take_raw(s0 + 1, pu[2], pr2[2], qs[2], up1, urp1);
         }
 #pragma unroll
-        for (int m = 0; m < M; ++m) rm2[m] = rm1[m] = C(0);
+        for (int m = 0; m < M; ++m) rm2[m] = rm1[m] = um2[m] = C(0);
         if (!ZG) {
 #pragma unroll
             for (int q = 0; q < PD; ++q) issue_u(s0 + 2 + q, (2 + q) % RS);
@@ -485,21 +491,48 @@ k_smooth3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out
                 r = (pin && val[m]) ? r - sA * lap : C(0);
             }
             r0[m] = r;
-            rL[cur][RP + t + m * NT] = r;
+            rL[WIDE ? (s & 3) : cur][RP + t + m * NT] = r;
         }
-        // smoothed plane s - 1
-        const int p = s - 1;
-        if (p >= z0 && p < z1) {
-            const C* R = rL[cur ^ 1];
-            const rsrc_t ro = line_rsrc(out, (long)p * plane, plane, true);
+        if constexpr (WIDE) {
+            // smoothed plane s - 2 from residual planes s - 3, s - 2, s - 1
+            const int p = s - 2;
+            if (p >= z0 && p < z1) {
+                const C* Rm = rL[(s - 3) & 3];
+                const C* R0 = rL[(s - 2) & 3];
+                const C* Rp = rL[(s - 1) & 3];
+                const rsrc_t ro = line_rsrc(out, (long)p * plane, plane, true);
 #pragma unroll
-            for (int m = 0; m < M; ++m) {
-                const int q = RP + t + m * NT;
-                const C rc0 = rm1[m];
-                const C nbs = R[q - 1] + R[q + 1] + R[q - RX] + R[q + RX] + rm2[m] + r0[m];
-                const C v = (ZG ? C(0) : um1[m]) + sW * (c0 * rc0 + c1 * nbs);
-                bstore<NTS>(static_cast<S>(v), ro, inn[m] ? gb[m] : kOob);
-                if (NORM) nacc += inn[m] ? (double)rc0 * (double)rc0 : 0.0;
+                for (int m = 0; m < M; ++m) {
+                    const int q = RP + t + m * NT;
+                    const C rc0 = R0[q];
+                    const C fc = R0[q - 1] + R0[q + 1] + R0[q - RX] + R0[q + RX] + Rm[q] + Rp[q];
+                    const C ed = R0[q - RX - 1] + R0[q - RX + 1] + R0[q + RX - 1] +
+                                 R0[q + RX + 1] + Rm[q - 1] + Rm[q + 1] + Rm[q - RX] +
+                                 Rm[q + RX] + Rp[q - 1] + Rp[q + 1] + Rp[q - RX] + Rp[q + RX];
+                    const C cn = Rm[q - RX - 1] + Rm[q - RX + 1] + Rm[q + RX - 1] +
+                                 Rm[q + RX + 1] + Rp[q - RX - 1] + Rp[q - RX + 1] +
+                                 Rp[q + RX - 1] + Rp[q + RX + 1];
+                    const C v = (ZG ? C(0) : um2[m]) +
+                                sW * (c0 * rc0 + c1 * fc + c2 * ed + c3 * cn);
+                    bstore<NTS>(static_cast<S>(v), ro, inn[m] ? gb[m] : kOob);
+                    if (NORM) nacc += inn[m] ? (double)rc0 * (double)rc0 : 0.0;
+                }
+            }
+        } else {
+            // smoothed plane s - 1
+            const int p = s - 1;
+            if (p >= z0 && p < z1) {
+                const C* R = rL[cur ^ 1];
+                const rsrc_t ro = line_rsrc(out, (long)p * plane, plane, true);
+#pragma unroll
+                for (int m = 0; m < M; ++m) {
+                    const int q = RP + t + m * NT;
+                    const C rc0 = rm1[m];
+                    const C nbs = R[q - 1] + R[q + 1] + R[q - RX] + R[q + RX] + rm2[m] + r0[m];
+                    const C v = (ZG ? C(0) : um1[m]) + sW * (c0 * rc0 + c1 * nbs);
+                    bstore<NTS>(static_cast<S>(v), ro, inn[m] ? gb[m] : kOob);
+                    if (NORM) nacc += inn[m] ? (double)rc0 * (double)rc0 : 0.0;
+                }
             }
         }
         // v of plane s + 1 into the other LDS slot
@@ -516,6 +549,7 @@ k_smooth3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out
         }
 #pragma unroll
         for (int m = 0; m < M; ++m) {
+            if (WIDE) um2[m] = um1[m];
             um1[m] = u0[m];
             u0[m] = up1[m];
             rm2[m] = rm1[m];
@@ -525,7 +559,8 @@ k_smooth3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out
         // s odd: stage coarse plane (s+3)/2, loaded 2 CD - 1 steps ago
         if (PRO && (k & 1) == 0) c_write((((k - 2 * CD + 1 + UN) % UN) >> 1) % RCS);
     };
-    march<UR>(s0, z1, step);
+    // WIDE outputs lag one more plane: the last one, z1 - 1, at step z1 + 1
+    march<UR>(s0, WIDE ? z1 + 1 : z1, step);
     if (NORM) {
         const double sm = block_sum<NT>(nacc, red);
         if (t == 0) partials[(long)blockIdx.y * gridDim.x + blockIdx.x] = sm;
@@ -2352,7 +2387,7 @@ __host__ __device__ inline size_t tail_ginv_offset(size_t level_bytes) {
 
 template <typename S, typename C, int D, bool WC>
 __global__ void __launch_bounds__(1024)
-k_tail(const S* __restrict__ bt, S* __restrict__ et, int nt, C c0, C c1, C c2,
+k_tail(const S* __restrict__ bt, S* __restrict__ et, int nt, C c0, C c1, C c2, C c3,
        const double* __restrict__ ginv, int scaled, int Ntop, int wvisits) {
     extern __shared__ unsigned char smem_raw[];
     C* sm = reinterpret_cast<C*>(smem_raw);
@@ -2403,11 +2438,21 @@ k_tail(const S* __restrict__ bt, S* __restrict__ et, int nt, C c0, C c1, C c2,
         if (D == 3) s -= a[q - (long)P * P] + a[q + (long)P * P];
         return s;
     };
+    // the 19-/27-point 3D stencils: edge and corner terms
+    const bool wide = D == 3 && (c2 != C(0) || c3 != C(0));
     auto spai = [&](const C* a, long q, int P) -> C {
         C f = a[q - 1] + a[q + 1] + a[q - P] + a[q + P];
         if (D == 3) {
-            f += a[q - (long)P * P] + a[q + (long)P * P];
-            return c0 * a[q] + c1 * f;
+            const long P2 = (long)P * P;
+            f += a[q - P2] + a[q + P2];
+            if (!wide) return c0 * a[q] + c1 * f;
+            const C ed = a[q - P - 1] + a[q - P + 1] + a[q + P - 1] + a[q + P + 1] +
+                         a[q - P2 - 1] + a[q - P2 + 1] + a[q - P2 - P] + a[q - P2 + P] +
+                         a[q + P2 - 1] + a[q + P2 + 1] + a[q + P2 - P] + a[q + P2 + P];
+            const C cn = a[q - P2 - P - 1] + a[q - P2 - P + 1] + a[q - P2 + P - 1] +
+                         a[q - P2 + P + 1] + a[q + P2 - P - 1] + a[q + P2 - P + 1] +
+                         a[q + P2 + P - 1] + a[q + P2 + P + 1];
+            return c0 * a[q] + c1 * f + c2 * ed + c3 * cn;
         }
         const C cn = a[q - P - 1] + a[q - P + 1] + a[q + P - 1] + a[q + P + 1];
         return c0 * a[q] + c1 * f + c2 * cn;
@@ -3054,6 +3099,7 @@ hipError_t launch_smooth3d(bool zg, bool norm, const Sweep& s, int want, int min
     const S* ec = static_cast<const S*>(s.ec);
     const bool pro = ec != nullptr;
     const C sA = C(s.sA), sW = C(s.sW), c0 = C(s.c[0]), c1 = C(s.c[1]), pf = C(s.pf);
+    const C c2 = C(s.c[2]), c3 = C(s.c[3]);
     const int tx = cdiv(n, TX), ty = cdiv(n, TY);
     const int zc = even_chunk(pick_chunk(n, tx * ty, want, minc));
     const int nch = cdiv(n, zc);
@@ -3061,13 +3107,21 @@ hipError_t launch_smooth3d(bool zg, bool norm, const Sweep& s, int want, int min
     if (nparts) *nparts = grid.x * grid.y;
     if (norm && (long)grid.x * grid.y > s.partials_cap) return hipErrorInvalidValue;
     constexpr int PDC = UN % 3 == 0 ? 2 : 1;  // deeper prefetch for the fused correction
-#define L3(PD, ZG, NM, PR)                                                                     \
-    hipLaunchKernelGGL((k_smooth3d<S, C, TX, TY, NT, PD, UN, ZG, NM, PR, NTS>), grid, dim3(NT), \
-                       0, st, u, b, out, n, tx, ty, zc, nch, sA, sW, c0, c1, s.partials, ec, nc, pf)
-    if (zg) L3(1, true, false, false);
-    else if (norm) L3(1, false, true, false);
-    else if (pro) L3(PDC, false, false, true);
-    else L3(1, false, false, false);
+#define L3(PD, ZG, NM, PR, WD)                                                                 \
+    hipLaunchKernelGGL((k_smooth3d<S, C, TX, TY, NT, PD, UN, ZG, NM, PR, NTS, WD>), grid,       \
+                       dim3(NT), 0, st, u, b, out, n, tx, ty, zc, nch, sA, sW, c0, c1,         \
+                       s.partials, ec, nc, pf, c2, c3)
+    if (s.c[2] != 0.0 || s.c[3] != 0.0) {  // 19-/27-point stencil
+        if (zg) L3(1, true, false, false, true);
+        else if (norm) L3(1, false, true, false, true);
+        else if (pro) L3(PDC, false, false, true, true);
+        else L3(1, false, false, false, true);
+    } else {
+        if (zg) L3(1, true, false, false, false);
+        else if (norm) L3(1, false, true, false, false);
+        else if (pro) L3(PDC, false, false, true, false);
+        else L3(1, false, false, false, false);
+    }
 #undef L3
     return hipGetLastError();
 }
@@ -3203,11 +3257,12 @@ hipError_t tail_impl_d(const Tail& t, size_t lds, hipStream_t st) {
     if (t.wvisits > 0)
         hipLaunchKernelGGL((k_tail<S, C, D, true>), dim3(t.batch), dim3(1024), lds, st,
                            static_cast<const S*>(t.b), static_cast<S*>(t.e), t.nt, C(t.c[0]),
-                           C(t.c[1]), C(t.c[2]), t.ginv, t.scaled ? 1 : 0, t.N_top, t.wvisits);
+                           C(t.c[1]), C(t.c[2]), C(t.c[3]), t.ginv, t.scaled ? 1 : 0, t.N_top,
+                           t.wvisits);
     else
         hipLaunchKernelGGL((k_tail<S, C, D, false>), dim3(t.batch), dim3(1024), lds, st,
                            static_cast<const S*>(t.b), static_cast<S*>(t.e), t.nt, C(t.c[0]),
-                           C(t.c[1]), C(t.c[2]), t.ginv, t.scaled ? 1 : 0, t.N_top, 0);
+                           C(t.c[1]), C(t.c[2]), C(t.c[3]), t.ginv, t.scaled ? 1 : 0, t.N_top, 0);
     return hipGetLastError();
 }
 

@@ -63,7 +63,8 @@ def _msg(L):
 @pytest.mark.parametrize("N,d,nc,what", [(64, 1, 3, "d must be"), (64, 4, 3, "d must be"),
                                          (2, 2, 3, "power of two"), (48, 2, 3, "power of two"),
                                          (1 << 17, 2, 3, "too large"), (4096, 3, 2, "too large"),
-                                         (64, 2, 2, "coefficients"), (64, 3, 3, "coefficients")])
+                                         (64, 2, 2, "coefficients"), (64, 3, 1, "coefficients"),
+                                         (64, 3, 5, "coefficients")])
 def test_setup_rejects_bad_arguments(N, d, nc, what):
     L = _lib()
     h = ctypes.c_void_p(1)
