@@ -371,15 +371,19 @@ def mixed(tol):
 
 
 # FP64 bytes per fine point that the adjoint cycle's fine-level kernels read
-# and write (mg_vcycle_adjoint: the forward recomputation smooth, residual,
-# restriction, correction and residual, then two coefficient-gradient
-# sweeps, three update sweeps, one restriction and one interpolation of the
-# reverse pass); c is one coarse value per 2^d fine points
-def adjoint_bytes_per_pt(d):
+# and write (mg_vcycle_adjoint): the forward recomputation's pre-smoother +
+# restriction with the residual r1 kept (read u, b; write t, r1, b_c) and
+# post-smoother with the fused correction and r3 kept (read t, b, e_c; write
+# u_out, r3); the reverse pass's two smoothing sweeps (read ubar, r, bbar;
+# write ubar', bbar), restriction of ubar and interpolation of bbar_c (one
+# fine field each way), and the update after the interpolation (read ubar,
+# w, bbar; write ubar', bbar); FP32 checkpoints add their widening (read 4,
+# write 8).  c is one coarse value per 2^d fine points.
+def adjoint_bytes_per_pt(d, ckpt="fp64"):
     c = 8.0 / 2 ** d
-    forward = 24 + 24 + (16 + c) + (16 + c) + 24
-    reverse = 24 + 40 + (8 + c) + (8 + c) + 40 + 24 + 40
-    return forward + reverse
+    forward = (32 + c) + (32 + c)
+    reverse = 40 + (8 + c) + (8 + c) + 40 + 40
+    return forward + reverse + (12.0 if ckpt == "fp32" else 0.0)
 
 
 ADJOINT_CASES = (("errors2d_n1024_b16", 2, 1024, 16, 3, "fp64"),
@@ -424,12 +428,12 @@ def adjoint(reps=3):
                 best_b = min(best_b, e2.elapsed_time(e3))
         mg.close()
         pts = (N - 1) ** d * batch
-        byt = adjoint_bytes_per_pt(d) * pts * K
+        byt = adjoint_bytes_per_pt(d, ck) * pts * K
         out[name] = {"d": d, "N": N, "batch": batch, "cycles": K, "checkpoints": ck,
                      "forward_ms": best_f, "backward_ms": best_b,
                      "backward_over_forward": best_b / best_f,
                      "fine_unknowns_per_s_fwd_bwd": pts * K / ((best_f + best_b) * 1e-3),
-                     "adjoint_fine_bytes_per_pt_per_cycle": adjoint_bytes_per_pt(d),
+                     "adjoint_fine_bytes_per_pt_per_cycle": adjoint_bytes_per_pt(d, ck),
                      "adjoint_fine_GBps": byt / (best_b * 1e-3) / 1e9,
                      "adjoint_frac_of_peak": byt / (best_b * 1e-3) / 1e9 / HBM_PEAK_GBS}
         print(f"[bench] adjoint {name}: {out[name]}", file=sys.stderr, flush=True)

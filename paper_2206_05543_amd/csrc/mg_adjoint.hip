@@ -1,4 +1,9 @@
-// gfx950 kernels of the reverse-mode (adjoint) V(1,1) cycle, FP64.
+// gfx950 kernels of the reverse-mode (adjoint) V(1,1) cycle, FP64: the grid
+// transfers of the reverse sweep, the coefficient-gradient reduction, the
+// checkpoint conversions and the coarsest grid's matrix product.  The
+// reverse smoothing steps are marching sweeps in mg_kernels.hip
+// (launch_adj_sweep), and the forward recomputation uses the cycle's own
+// kernels with their residual side outputs.
 //
 // The forward cycle (He, Liu and Wang, arXiv 2206.05543, Section 4, with the
 // smoother of Section 2, eq. (smoother)) is linear in (u, b) and polynomial
@@ -8,9 +13,9 @@
 // M = h^2 sum_j c_j K_j, the coefficient gradient of a smoothing step
 // u_out = u + M r is dL/dc_j = h^2 <ubar_out, K_j r> = h^2 <K_j ubar_out, r>.
 //
-// These are one-node-per-thread kernels (neighbours through L1/L2): the
-// adjoint is a measured path, not a bandwidth-tuned one.  Reductions are
-// per-block partial sums in a fixed order, so gradients are deterministic.
+// The kernels here are one-node-per-thread (neighbours through L1/L2).
+// Reductions are per-block partial sums in a fixed order, so gradients are
+// deterministic.
 #include <hip/hip_runtime.h>
 
 #include "mg_internal.h"
@@ -34,112 +39,8 @@ struct Grid {
         }
         return a[(long)j * n + i];
     }
-    __device__ __forceinline__ double lap(const double* a, int i, int j, int k) const {
-        double s = 2.0 * d * at(a, i, j, k) - at(a, i - 1, j, k) - at(a, i + 1, j, k) -
-                   at(a, i, j - 1, k) - at(a, i, j + 1, k);
-        if (d == 3) s -= at(a, i, j, k - 1) + at(a, i, j, k + 1);
-        return s;
-    }
-    __device__ __forceinline__ double faces(const double* a, int i, int j, int k) const {
-        double s = at(a, i - 1, j, k) + at(a, i + 1, j, k) + at(a, i, j - 1, k) +
-                   at(a, i, j + 1, k);
-        if (d == 3) s += at(a, i, j, k - 1) + at(a, i, j, k + 1);
-        return s;
-    }
-    // K_2: the 4 diagonal neighbours in 2D, the 12 edge neighbours in 3D
-    __device__ __forceinline__ double diag(const double* a, int i, int j, int k) const {
-        double s = at(a, i - 1, j - 1, k) + at(a, i + 1, j - 1, k) + at(a, i - 1, j + 1, k) +
-                   at(a, i + 1, j + 1, k);
-        if (d == 3)
-            s += at(a, i - 1, j, k - 1) + at(a, i + 1, j, k - 1) + at(a, i, j - 1, k - 1) +
-                 at(a, i, j + 1, k - 1) + at(a, i - 1, j, k + 1) + at(a, i + 1, j, k + 1) +
-                 at(a, i, j - 1, k + 1) + at(a, i, j + 1, k + 1);
-        return s;
-    }
-    // K_3: the 8 corner neighbours (3D)
-    __device__ __forceinline__ double corners3(const double* a, int i, int j, int k) const {
-        double s = 0.0;
-        for (int c = -1; c <= 1; c += 2)
-            for (int b = -1; b <= 1; b += 2)
-                for (int a2 = -1; a2 <= 1; a2 += 2) s += at(a, i + a2, j + b, k + c);
-        return s;
-    }
 };
 
-__device__ __forceinline__ double block_sum256(double v, double* red) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    __syncthreads();
-    if (l == 0) red[w] = v;
-    __syncthreads();
-    double s = 0.0;
-    if (threadIdx.x == 0)
-        for (int i = 0; i < 4; ++i) s += red[i];
-    __syncthreads();
-    return s;
-}
-
-// r = b - inv_h2 * L u
-__global__ void __launch_bounds__(256)
-k_residual(const double* __restrict__ u, const double* __restrict__ b, double* __restrict__ r,
-           Grid g, double inv_h2) {
-    const long off = (long)blockIdx.y * g.pts;
-    for (long p = (long)blockIdx.x * 256 + threadIdx.x; p < g.pts; p += (long)gridDim.x * 256) {
-        int i, j, k;
-        g.coords(p, &i, &j, &k);
-        r[off + p] = b[off + p] - inv_h2 * g.lap(u + off, i, j, k);
-    }
-}
-
-// w = sW (c0 K0 + c1 K1 + c2 K2 + c3 K3) ubar and per-block partial sums of
-// (K_j ubar)(p) r(p), j = 0..3, into partials[4 * block + j]
-__global__ void __launch_bounds__(256)
-k_adj_applyK(const double* __restrict__ ub, const double* __restrict__ r, double* __restrict__ w,
-             double* __restrict__ partials, Grid g, double sW, double c0, double c1, double c2,
-             double c3) {
-    __shared__ double red[4];
-    const long off = (long)blockIdx.y * g.pts;
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    for (long p = (long)blockIdx.x * 256 + threadIdx.x; p < g.pts; p += (long)gridDim.x * 256) {
-        int i, j, k;
-        g.coords(p, &i, &j, &k);
-        const double k0 = ub[off + p];
-        const double k1 = g.faces(ub + off, i, j, k);
-        const double k2 = g.diag(ub + off, i, j, k);
-        const double k3 = g.d == 3 ? g.corners3(ub + off, i, j, k) : 0.0;
-        w[off + p] = sW * (c0 * k0 + c1 * k1 + c2 * k2 + c3 * k3);
-        const double rv = r[off + p];
-        s0 += k0 * rv;
-        s1 += k1 * rv;
-        s2 += k2 * rv;
-        s3 += k3 * rv;
-    }
-    const double t0 = block_sum256(s0, red);
-    const double t1 = block_sum256(s1, red);
-    const double t2 = block_sum256(s2, red);
-    const double t3 = block_sum256(s3, red);
-    if (threadIdx.x == 0) {
-        const long bi = (long)blockIdx.y * gridDim.x + blockIdx.x;
-        partials[4 * bi + 0] = t0;
-        partials[4 * bi + 1] = t1;
-        partials[4 * bi + 2] = t2;
-        partials[4 * bi + 3] = t3;
-    }
-}
-
-// ubar_new = ubar - sA L w ;  bbar += w
-__global__ void __launch_bounds__(256)
-k_adj_update(const double* __restrict__ ub, const double* __restrict__ w,
-             double* __restrict__ ub_new, double* __restrict__ bbar, Grid g, double sA) {
-    const long off = (long)blockIdx.y * g.pts;
-    for (long p = (long)blockIdx.x * 256 + threadIdx.x; p < g.pts; p += (long)gridDim.x * 256) {
-        int i, j, k;
-        g.coords(p, &i, &j, &k);
-        const double wl = w[off + p];
-        ub_new[off + p] = ub[off + p] - sA * g.lap(w + off, i, j, k);
-        bbar[off + p] += wl;
-    }
-}
 
 // coarse = scale * R fine (full weighting; scale 2^d gives P^T)
 __global__ void __launch_bounds__(256)
@@ -188,16 +89,22 @@ k_interp(const double* __restrict__ c, double* __restrict__ f, Grid gf, Grid gc,
     }
 }
 
-// acc[j] += scale * sum_i partials[ncols * i + j], fixed order
-__global__ void __launch_bounds__(256)
+// acc[j] = scale * sum_i partials[ncols * i + j], one workgroup per column,
+// fixed order (each thread a strided subset, then a fixed tree)
+__global__ void __launch_bounds__(1024)
 k_reduce_cols(const double* __restrict__ partials, int count, int ncols, double* __restrict__ acc,
               double scale) {
-    __shared__ double red[4];
-    for (int jc = 0; jc < ncols; ++jc) {
-        double s = 0.0;
-        for (int i = threadIdx.x; i < count; i += 256) s += partials[(long)ncols * i + jc];
-        const double t = block_sum256(s, red);
-        if (threadIdx.x == 0) acc[jc] += scale * t;
+    __shared__ double red[16];
+    const int jc = blockIdx.x;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < count; i += 1024) s += partials[(long)ncols * i + jc];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int i = 0; i < 16; ++i) t += red[i];
+        acc[jc] = scale * t;
     }
 }
 
@@ -249,34 +156,6 @@ inline dim3 point_grid(long pts, int batch) {
 
 }  // namespace
 
-hipError_t launch_residual(int d, int n, int batch, const double* u, const double* b, double* r,
-                           double inv_h2, hipStream_t st) {
-    const Grid g = make_grid(d, n);
-    hipLaunchKernelGGL(k_residual, point_grid(g.pts, batch), dim3(256), 0, st, u, b, r, g, inv_h2);
-    return hipGetLastError();
-}
-
-hipError_t launch_adj_applyK(int d, int n, int batch, const double* ubar, const double* r,
-                             double* w, double* partials, long partials_cap, double sW,
-                             const double* c, hipStream_t st, int* nparts) {
-    const Grid g = make_grid(d, n);
-    const dim3 grid = point_grid(g.pts, batch);
-    const long nb = (long)grid.x * grid.y;
-    if (4 * nb > partials_cap) return hipErrorInvalidValue;
-    if (nparts) *nparts = (int)nb;
-    hipLaunchKernelGGL(k_adj_applyK, grid, dim3(256), 0, st, ubar, r, w, partials, g, sW, c[0],
-                       c[1], c[2], d == 3 ? c[3] : 0.0);
-    return hipGetLastError();
-}
-
-hipError_t launch_adj_update(int d, int n, int batch, const double* ubar, const double* w,
-                             double* ubar_new, double* bbar, double sA, hipStream_t st) {
-    const Grid g = make_grid(d, n);
-    hipLaunchKernelGGL(k_adj_update, point_grid(g.pts, batch), dim3(256), 0, st, ubar, w, ubar_new,
-                       bbar, g, sA);
-    return hipGetLastError();
-}
-
 hipError_t launch_fw(int d, int n, int batch, const double* fine, double* coarse, double scale,
                      hipStream_t st) {
     const int nc = (n + 1) / 2 - 1;
@@ -296,7 +175,8 @@ hipError_t launch_interp(int d, int n, int batch, const double* coarse, double* 
 
 hipError_t launch_reduce_cols(const double* partials, int count, int ncols, double* acc,
                               double scale, hipStream_t st) {
-    hipLaunchKernelGGL(k_reduce_cols, dim3(1), dim3(256), 0, st, partials, count, ncols, acc, scale);
+    hipLaunchKernelGGL(k_reduce_cols, dim3(ncols), dim3(1024), 0, st, partials, count, ncols, acc,
+                       scale);
     return hipGetLastError();
 }
 

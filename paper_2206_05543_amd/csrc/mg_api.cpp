@@ -41,6 +41,7 @@ int fail(int code, const std::string& msg) {
 constexpr int kMaxLevels = 20;
 constexpr int kTimeKinds = 11;
 constexpr long kPartialCap = 1 << 17;  // per batch entry
+constexpr long kAdjBlocks = 8192;      // blocks per batch entry of an adjoint sweep
 
 struct Hier {
     Prec p = P64;
@@ -89,6 +90,9 @@ struct mg_ctx {
     double* adj_cin = nullptr;   // FP64 copy of an FP32 checkpoint (fine level)
     bool adj_alloc = false;
     double* adj_cacc = nullptr;  // device accumulator of dL/dc (4 doubles)
+    double* adj_part = nullptr;  // coefficient-gradient partials of one adjoint cycle
+    long adj_pcap = 0;           // its capacity (doubles)
+    long adj_poff = 0;           // next free slot
     // timing
     int timing = 0;
     std::vector<hipEvent_t> ev_pool;
@@ -1500,8 +1504,11 @@ void free_adj(mg_ctx* h) {
     }
     if (h->adj_cacc) (void)hipFree(h->adj_cacc);
     if (h->adj_cin) (void)hipFree(h->adj_cin);
+    if (h->adj_part) (void)hipFree(h->adj_part);
     h->adj_cacc = nullptr;
     h->adj_cin = nullptr;
+    h->adj_part = nullptr;
+    h->adj_pcap = 0;
     h->adj_alloc = false;
 }
 
@@ -1527,6 +1534,10 @@ int alloc_adj(mg_ctx* h) {
     }
     HIPCHK(hipMalloc(&h->adj_cacc, 4 * sizeof(double)));
     HIPCHK(hipMalloc(&h->adj_cin, (size_t)level_pts(h, 0) * h->batch * sizeof(double)));
+    // two coefficient-gradient sweeps per level above the coarsest, each at
+    // most kAdjBlocks blocks per batch entry with 4 partial sums
+    h->adj_pcap = 2L * 4 * kAdjBlocks * h->batch * (h->L > 1 ? h->L - 1 : 1);
+    HIPCHK(hipMalloc(&h->adj_part, (size_t)h->adj_pcap * sizeof(double)));
     h->adj_alloc = true;
     return MG_OK;
 }
@@ -1534,31 +1545,45 @@ int alloc_adj(mg_ctx* h) {
 // Forward recomputation of one V(1,1) cycle at level l from u_in (null: zero
 // guess), keeping what the reverse sweep needs: r1 = b - A u_in (fine
 // level; on coarse levels r1 = b), r3 = b - A u2 with u2 = u1 + P e_{l+1},
-// and the level output e_l (for the level above).
+// and the level output e_l (for the level above).  The residuals are side
+// outputs of the cycle's own fused kernels: the pre-smoother (with the
+// restriction where the cycle fuses them) writes r1, and the post-smoother
+// with the fused correction writes r3 beside e_l.
 int adj_forward(mg_ctx* h, int l, const double* u_in, const double* bl, hipStream_t st) {
     Hier& H = h->h64;
-    const int d = h->d, n = level_n(h, l);
-    const double N = level_N(h, l);
     if (l == h->L - 1) return run_tail(h, H, l, bl, H.e[l], st);
     Sweep s = make_sweep(h, H, l);
     double* t = static_cast<double*>(H.t[l]);
     s.u = u_in;
     s.b = bl;
     s.out = t;
-    HIPCHK(launch_smooth(P64, u_in == nullptr, false, s, st, nullptr));
-    if (u_in) HIPCHK(launch_residual(d, n, h->batch, u_in, bl, h->adj_r1[l], N * N, st));
-    s.u = t;
-    s.out = H.b[l + 1];
-    HIPCHK(launch_restrict(P64, s, st));
+    const bool fused = u_in ? fuse_smooth_restrict(h, l) : fuse_zero_restrict(h, l);
+    if (fused) {
+        s.out_c = H.b[l + 1];
+        s.rout = u_in ? h->adj_r1[l] : nullptr;
+        HIPCHK(u_in ? launch_smooth_restrict(P64, false, s, st, nullptr)
+                    : launch_zero_smooth_restrict(P64, s, st));
+    } else {
+        s.rout = u_in ? h->adj_r1[l] : nullptr;
+        HIPCHK(launch_smooth(P64, u_in == nullptr, false, s, st, nullptr));
+        Sweep rs = make_sweep(h, H, l);
+        rs.u = t;
+        rs.b = bl;
+        rs.out = H.b[l + 1];
+        HIPCHK(launch_restrict(P64, rs, st));
+    }
     int rc = adj_forward(h, l + 1, nullptr, static_cast<const double*>(H.b[l + 1]), st);
     if (rc) return rc;
-    HIPCHK(launch_prolong(P64, d, n, h->batch, H.e[l + 1], t, 1.0, st));
-    HIPCHK(launch_residual(d, n, h->batch, t, bl, h->adj_r3[l], N * N, st));
-    if (l > 0) {
-        s.u = t;
-        s.out = H.e[l];
-        HIPCHK(launch_smooth(P64, false, false, s, st, nullptr));
-    }
+    // post-smoothing of u2 = t + P e_{l+1}; on the fine level only r3 is
+    // needed (the cycle's output goes to scratch)
+    Sweep q = make_sweep(h, H, l);
+    q.u = t;
+    q.b = bl;
+    q.ec = H.e[l + 1];
+    q.pf = 1.0;
+    q.rout = h->adj_r3[l];
+    q.out = l > 0 ? H.e[l] : h->adj_w[0];
+    HIPCHK(launch_smooth(P64, false, false, q, st, nullptr));
     return MG_OK;
 }
 
@@ -1580,12 +1605,15 @@ int adj_reverse(mg_ctx* h, int l, const double* uo, double* ui, double* bb, cons
     double* w = h->adj_w[l];
     double* ua = h->adj_ua[l];
     double* ub = h->adj_ub[l];
-    const long cap = kPartialCap * b;
     int np = 0;
-    // post-smoothing  u_out = u2 + M r3, r3 = b - A u2
-    HIPCHK(launch_adj_applyK(d, n, b, uo, h->adj_r3[l], w, h->psum, cap, h2, c, st, &np));
-    HIPCHK(launch_reduce_cols(h->psum, np, 4, h->adj_cacc, h2, st));
-    HIPCHK(launch_adj_update(d, n, b, uo, w, ua, bb, N * N, st));
+    // post-smoothing  u_out = u2 + M r3, r3 = b - A u2: ubar2 = ubar_out -
+    // A M ubar_out, bbar += M ubar_out; its coefficient-gradient partials
+    // (scaled by h^2) go to their own slots, reduced once per adjoint call in
+    // slot order
+    HIPCHK(launch_adj_sweep(d, n, b, 0, uo, h->adj_r3[l], nullptr, ua, bb,
+                            h->adj_part + h->adj_poff, h->adj_pcap - h->adj_poff, N * N, h2, c,
+                            st, &np));
+    h->adj_poff += 4L * np;
     // correction u2 = u1 + P e_c: ecbar = P^T ubar2 = 2^d R ubar2
     HIPCHK(launch_fw(d, n, b, ua, h->adj_uo[l + 1], d == 2 ? 4.0 : 8.0, st));
     const size_t cbytes = (size_t)level_pts(h, l + 1) * b * sizeof(double);
@@ -1593,14 +1621,17 @@ int adj_reverse(mg_ctx* h, int l, const double* uo, double* ui, double* bb, cons
     int rc = adj_reverse(h, l + 1, h->adj_uo[l + 1], nullptr, h->adj_bb[l + 1],
                          static_cast<const double*>(H.b[l + 1]), st);
     if (rc) return rc;
-    // restriction b_c = R (b - A u1): rbar = R^T bcbar = 2^-d P bcbar
+    // restriction b_c = R (b - A u1): rbar = R^T bcbar = 2^-d P bcbar;
+    // ubar1 = ubar2 - A rbar, bbar += rbar
     HIPCHK(launch_interp(d, n, b, h->adj_bb[l + 1], w, d == 2 ? 0.25 : 0.125, st));
-    HIPCHK(launch_adj_update(d, n, b, ua, w, ub, bb, N * N, st));
-    // pre-smoothing  u1 = u + M r1, r1 = b - A u
-    HIPCHK(launch_adj_applyK(d, n, b, ub, r1, w, h->psum, cap, h2, c, st, &np));
-    HIPCHK(launch_reduce_cols(h->psum, np, 4, h->adj_cacc, h2, st));
-    if (ui) HIPCHK(launch_adj_update(d, n, b, ub, w, ui, bb, N * N, st));
-    else HIPCHK(launch_adj_update(d, n, b, ub, w, ua, bb, N * N, st));
+    HIPCHK(launch_adj_sweep(d, n, b, 1, ua, nullptr, w, ub, bb, nullptr, 0, N * N, h2, c, st,
+                            nullptr));
+    // pre-smoothing  u1 = u + M r1, r1 = b - A u: ubar = ubar1 - A M ubar1
+    // (discarded below the fine level: the coarse cycles start from zero)
+    HIPCHK(launch_adj_sweep(d, n, b, 0, ub, r1, nullptr, ui ? ui : ua, bb,
+                            h->adj_part + h->adj_poff, h->adj_pcap - h->adj_poff, N * N, h2, c,
+                            st, &np));
+    h->adj_poff += 4L * np;
     return MG_OK;
 }
 }  // namespace
@@ -1639,7 +1670,7 @@ extern "C" int mg_vcycle_adjoint(mg_handle_t h, const double* b, const void* u_c
                             level_pts(h, 0) * h->batch, st));
         u_in = h->adj_cin;
     }
-    HIPCHK(hipMemsetAsync(h->adj_cacc, 0, 4 * sizeof(double), st));
+    h->adj_poff = 0;
     if (h->L == 1) {
         // single grid: u_out = A^{-1} b
         HIPCHK(launch_coarse_matvec(h->d == 2 ? 9 : 27, h->batch, h->h64.ginv, ubar_out, bbar_acc,
@@ -1651,6 +1682,8 @@ extern "C" int mg_vcycle_adjoint(mg_handle_t h, const double* b, const void* u_c
         rc = adj_reverse(h, 0, ubar_out, ubar_in, bbar_acc, h->adj_r1[0], st);
         if (rc) return rc;
     }
+    // dL/dc_j = sum over every smoothing step of its scaled partials
+    HIPCHK(launch_reduce_cols(h->adj_part, (int)(h->adj_poff / 4), 4, h->adj_cacc, 1.0, st));
     double hc[4];
     HIPCHK(hipMemcpyAsync(hc, h->adj_cacc, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));

@@ -49,6 +49,10 @@ struct Sweep {
     // the next cycle's pre-smoothed iterate, written by the fused
     // post-smoother + pre-smoother + restriction
     void* out_t = nullptr;
+    // optional (FP64): the residual b - sA L v that the smoother applies K_c
+    // to, stored at every node the sweep owns (the adjoint cycle's forward
+    // recomputation keeps it)
+    void* rout = nullptr;
 };
 
 // Launchers return hipSuccess or the launch error.  *nparts receives the
@@ -132,24 +136,22 @@ struct IRStep {
 hipError_t launch_ir_step(Prec p, const IRStep& s, hipStream_t st, int* nparts);
 
 // Kernels of the reverse-mode (adjoint) cycle, FP64, whole batch.
-//   r = b - inv_h2 L u
-hipError_t launch_residual(int d, int n, int batch, const double* u, const double* b,
-                           double* r, double inv_h2, hipStream_t st);
-//   w = sW sum_j c_j K_j ubar (K_2: diagonals in 2D, edges in 3D; K_3:
-//   corners, 3D); partials[4 i + j] = block sums of (K_j ubar) r, j = 0..3
-hipError_t launch_adj_applyK(int d, int n, int batch, const double* ubar, const double* r,
-                             double* w, double* partials, long partials_cap, double sW,
-                             const double* c, hipStream_t st, int* nparts);
-//   ubar_new = ubar - sA L w; bbar += w
-hipError_t launch_adj_update(int d, int n, int batch, const double* ubar, const double* w,
-                             double* ubar_new, double* bbar, double sA, hipStream_t st);
+//   mode 0 (the reverse of a smoothing step): w = sW sum_j c_j K_j ubar (K_2:
+//   diagonals in 2D, edges in 3D; K_3: corners, 3D), partials[4 i + j] = sW x
+//   block sums of (K_j ubar) r over the owned nodes; mode 1 (the reverse of
+//   the restricted residual): w read from `w`; then ubar_new = ubar - sA L w
+//   and bbar += w.  ubar_new must not alias ubar.  *nparts = blocks.
+hipError_t launch_adj_sweep(int d, int n, int batch, int mode, const double* ubar,
+                            const double* r, const double* w, double* ubar_new, double* bbar,
+                            double* partials, long partials_cap, double sA, double sW,
+                            const double* c, hipStream_t st, int* nparts);
 //   coarse = scale * R fine (full weighting)
 hipError_t launch_fw(int d, int n, int batch, const double* fine, double* coarse,
                      double scale, hipStream_t st);
 //   fine = scale * P coarse (linear interpolation, overwrite)
 hipError_t launch_interp(int d, int n, int batch, const double* coarse, double* fine,
                          double scale, hipStream_t st);
-//   acc[j] += scale * sum_i partials[ncols i + j] (fixed order)
+//   acc[j] = scale * sum_i partials[ncols i + j] (fixed order)
 hipError_t launch_reduce_cols(const double* partials, int count, int ncols, double* acc,
                               double scale, hipStream_t st);
 //   ck = fl32(u), u = (double) ck  (FP32 checkpoint; the forward continues

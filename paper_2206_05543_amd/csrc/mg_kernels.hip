@@ -229,12 +229,13 @@ __device__ void finalize_norm(const double* ps, const double* pm, int count, dou
 // every plane a step reads was written before that step's barrier.
 // ---------------------------------------------------------------------------
 template <typename S, typename C, int TX, int TY, int NT, int PD, int UN, bool ZG, bool NORM,
-          bool PRO, bool NTS, bool WIDE = false>
+          bool PRO, bool NTS, bool WIDE = false, bool ROUT = false>
 __global__ void __launch_bounds__(NT)
 k_smooth3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out,
            int n, int tiles_x, int tiles_y, int zchunk, int nchunks, C sA,
            C sW, C c0, C c1, double* __restrict__ partials,
-           const S* __restrict__ ec, int nc, C pf, C c2 = C(0), C c3 = C(0)) {
+           const S* __restrict__ ec, int nc, C pf, C c2 = C(0), C c3 = C(0),
+           S* __restrict__ rout = nullptr) {
     constexpr int RX = TX + 2, RY = TY + 2, NR = RX * RY;
     constexpr int UX = TX + 4, UY = TY + 4, NU = UX * UY;
     constexpr int M = (NR + NT - 1) / NT;
@@ -261,6 +262,7 @@ k_smooth3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out
     const long boff = (long)blockIdx.y * plane * n;
     b += boff;
     out += boff;
+    if (ROUT) rout += boff;
     if (!ZG) u += boff;
     const int x0 = tx * TX, y0 = ty * TY;
     const int z0 = ch * zchunk, z1 = min(z0 + zchunk, n);
@@ -515,6 +517,9 @@ k_smooth3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out
                     const C v = (ZG ? C(0) : um2[m]) +
                                 sW * (c0 * rc0 + c1 * fc + c2 * ed + c3 * cn);
                     bstore<NTS>(static_cast<S>(v), ro, inn[m] ? gb[m] : kOob);
+                    if (ROUT)
+                        bstore<false>(static_cast<S>(rc0), line_rsrc(rout, (long)p * plane, plane,
+                                                                     true), inn[m] ? gb[m] : kOob);
                     if (NORM) nacc += inn[m] ? (double)rc0 * (double)rc0 : 0.0;
                 }
             }
@@ -531,6 +536,9 @@ k_smooth3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out
                     const C nbs = R[q - 1] + R[q + 1] + R[q - RX] + R[q + RX] + rm2[m] + r0[m];
                     const C v = (ZG ? C(0) : um1[m]) + sW * (c0 * rc0 + c1 * nbs);
                     bstore<NTS>(static_cast<S>(v), ro, inn[m] ? gb[m] : kOob);
+                    if (ROUT)
+                        bstore<false>(static_cast<S>(rc0), line_rsrc(rout, (long)p * plane, plane,
+                                                                     true), inn[m] ? gb[m] : kOob);
                     if (NORM) nacc += inn[m] ? (double)rc0 * (double)rc0 : 0.0;
                 }
             }
@@ -577,11 +585,12 @@ k_smooth3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out
 // LDS scratch slots for lanes past the strip, selects for off-grid points).
 // ---------------------------------------------------------------------------
 template <typename S, typename C, int TX, int NT, int PD, int UN, bool ZG, bool NORM, bool PRO,
-          bool NTS>
+          bool NTS, bool ROUT = false>
 __global__ void __launch_bounds__(NT)
 k_smooth2d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out,
            int n, int tiles_x, int ychunk, int nchunks, C sA, C sW, C c0, C c1,
-           C c2, double* __restrict__ partials, const S* __restrict__ ec, int nc, C pf) {
+           C c2, double* __restrict__ partials, const S* __restrict__ ec, int nc, C pf,
+           S* __restrict__ rout = nullptr) {
     constexpr int RX = TX + 2, UX = TX + 4;
     constexpr int M = (RX + NT - 1) / NT;
     constexpr int CX = TX / 2 + 4;
@@ -603,6 +612,7 @@ k_smooth2d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out
     const long boff = (long)blockIdx.y * area;
     b += boff;
     out += boff;
+    if (ROUT) rout += boff;
     if (!ZG) u += boff;
     const int x0 = tx * TX;
     const int y0 = ch * ychunk, y1 = min(y0 + ychunk, n);
@@ -817,6 +827,9 @@ k_smooth2d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out
                 const C cn = R0[q - 1] + R0[q + 1] + R2[q - 1] + R2[q + 1];
                 const C v = (ZG ? C(0) : um2[m]) + sW * (c0 * rcc + c1 * fc + c2 * cn);
                 bstore<NTS>(static_cast<S>(v), ro, inn[m] ? gb[m] : kOob);
+                if (ROUT)
+                    bstore<false>(static_cast<S>(rcc), line_rsrc(rout, (long)p * n, n, true),
+                                  inn[m] ? gb[m] : kOob);
                 if (NORM) nacc += inn[m] ? (double)rcc * (double)rcc : 0.0;
             }
         }
@@ -1572,11 +1585,12 @@ k_zsr2d(const S* __restrict__ b, S* __restrict__ e, S* __restrict__ bc, int n, i
 // restriction, one pass over u and b and one launch are saved for ring-3
 // halo columns (L2 hits) and three extra rows per chunk.
 // ---------------------------------------------------------------------------
-template <typename S, typename C, int TX, int NT, int PD, int UN, bool NTS, bool NORM>
+template <typename S, typename C, int TX, int NT, int PD, int UN, bool NTS, bool NORM,
+          bool ROUT = false>
 __global__ void __launch_bounds__(NT)
 k_sr2d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out,
        S* __restrict__ bc, int n, int nc, int tiles_x, int ychunk, int nchunks, C sA, C sW,
-       C c0, C c1, C c2, double* __restrict__ partials) {
+       C c0, C c1, C c2, double* __restrict__ partials, S* __restrict__ rout = nullptr) {
     constexpr int W = TX + 7;             // columns x0-3 .. x0+TX+3
     constexpr int M = (W + NT - 1) / NT;
     constexpr int LW = W + 2 + 65;        // one guard each side, scratch for idle lanes
@@ -1598,6 +1612,7 @@ k_sr2d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out,
     u += (long)blockIdx.y * area;
     b += (long)blockIdx.y * area;
     out += (long)blockIdx.y * area;
+    if (ROUT) rout += (long)blockIdx.y * area;
     bc += (long)blockIdx.y * nc * nc;
     const int x0 = tx * TX;
     const int Y0 = ch * ychunk, Y1 = min(Y0 + ychunk, nc);
@@ -1704,6 +1719,9 @@ k_sr2d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out,
             r0[m] = r;
             rL[s & 3][q] = r;
             if (NORM) nacc += (sown && own[m]) ? (double)r * (double)r : 0.0;
+            if (ROUT)
+                bstore<false>(static_cast<S>(r), line_rsrc(rout, (long)s * n, n, sown),
+                              own[m] ? gb[m] : kOob);
         }
         // new iterate of row s-2 (residual rows s-3, s-2, s-1)
         const int p = s - 2;
@@ -2115,11 +2133,12 @@ k_psr2d(const S* __restrict__ t, const S* __restrict__ ec, const S* __restrict__
 // the second residual as stored.  The norm variant sums (b - sA L u)^2 over
 // the owned nodes.
 // ---------------------------------------------------------------------------
-template <typename S, typename C, int TX, int TY, int NT, int PD, int UN, bool NTS, bool NORM>
+template <typename S, typename C, int TX, int TY, int NT, int PD, int UN, bool NTS, bool NORM,
+          bool ROUT = false>
 __global__ void __launch_bounds__(NT)
 k_sr3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out,
        S* __restrict__ bc, int n, int nc, int tiles_x, int tiles_y, int zchunk, int nchunks,
-       C sA, C sW, C c0, C c1, double* __restrict__ partials) {
+       C sA, C sW, C c0, C c1, double* __restrict__ partials, S* __restrict__ rout = nullptr) {
     constexpr int WX = TX + 7, WY = TY + 7, NW = WX * WY;  // x0-3 .. x0+TX+3
     constexpr int M = (NW + NT - 1) / NT;
     constexpr int WP = WX + 1, LSZ = NW + 2 * WP;          // guard rows of neighbours
@@ -2142,6 +2161,7 @@ k_sr3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out,
     u += (long)blockIdx.y * plane * n;
     b += (long)blockIdx.y * plane * n;
     out += (long)blockIdx.y * plane * n;
+    if (ROUT) rout += (long)blockIdx.y * plane * n;
     bc += (long)blockIdx.y * cplane * nc;
     const int x0 = tx * TX, y0 = ty * TY;
     const int Z0 = ch * zchunk, Z1 = min(Z0 + zchunk, nc);
@@ -2252,6 +2272,9 @@ k_sr3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out,
                 r0[m] = r;
                 if (wr[m]) rL[s & 1][q] = r;
                 if (NORM) nacc += (sown && own[m]) ? (double)r * (double)r : 0.0;
+                if (ROUT)
+                    bstore<false>(static_cast<S>(r), line_rsrc(rout, (long)s * plane, plane, sown),
+                                  own[m] ? gb[m] : kOob);
             }
         }
         // new iterate of plane s-1 (residual planes s-2, s-1, s)
@@ -2325,6 +2348,369 @@ k_sr3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out,
     if (NORM) {
         const double sm = block_sum<NT>(nacc, red);
         if (t == 0) partials[(long)blockIdx.y * gridDim.x + blockIdx.x] = sm;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Reverse-mode sweeps of the adjoint cycle as marches (FP64), one barrier
+// per plane (row).  MODE 0, the reverse of a smoothing step u_out = u + M r
+// (r = b - A u): w = sW K_c ubar on the tile plus a ring of 1 from ubar
+// staged in LDS on the tile plus a ring of 2, the coefficient partials
+// sW sum (K_j ubar) r over the owned nodes, then ubar_new = ubar - sA L w
+// and bbar += w at the owned nodes, one plane (row) behind.  MODE 1, the
+// reverse of the restriction of the residual: the same update with w read
+// from memory (w = 2^-d P bbar_c, from the interpolation kernel).  ubar and
+// w are zero outside the grid (zero extension).  Loads of plane (row) s+1
+// are issued during step s.
+// ---------------------------------------------------------------------------
+template <int TX, int TY, int NT, bool WIDE, int MODE>
+__global__ void __launch_bounds__(NT)
+k_adj_sweep3d(const double* __restrict__ ub, const double* __restrict__ r,
+              const double* __restrict__ wsrc, double* __restrict__ ub_new,
+              double* __restrict__ bb, double* __restrict__ partials, int n, int tiles_x,
+              int tiles_y, int zchunk, int nchunks, double sA, double sW, double c0, double c1,
+              double c2, double c3) {
+    constexpr int UX = TX + 4, UY = TY + 4, NU = UX * UY;  // ubar: tile + ring 2
+    constexpr int RX = TX + 2, RY = TY + 2, NR = RX * RY;  // w: tile + ring 1
+    constexpr int MU = (NU + NT - 1) / NT, MW = (NR + NT - 1) / NT;
+    constexpr int UP = UX + 1, USZ = UP + MU * NT + UX + 1;  // guards for neighbour reads
+    constexpr int WP = RX + 1, WSZ = WP + MW * NT + RX + 1;
+    __shared__ double uL[MODE == 0 ? 4 : 1][MODE == 0 ? USZ : 1];
+    __shared__ double wL[2][WSZ];
+    __shared__ double red[NT / 64];
+
+    const int total = tiles_x * tiles_y * nchunks;
+    const int lg = xcd_remap(blockIdx.x, total);
+    const int tx = lg % tiles_x, ty = (lg / tiles_x) % tiles_y, ch = lg / (tiles_x * tiles_y);
+    const long plane = (long)n * n;
+    const long boff = (long)blockIdx.y * plane * n;
+    ub += boff;
+    ub_new += boff;
+    bb += boff;
+    if (MODE == 0) r += boff;
+    else wsrc += boff;
+    const int x0 = tx * TX, y0 = ty * TY;
+    const int z0 = ch * zchunk, z1 = min(z0 + zchunk, n);
+    const int t = threadIdx.x;
+
+    unsigned ugb[MU];
+    int uli[MU];
+#pragma unroll
+    for (int m = 0; m < MU; ++m) {
+        const int i = t + m * NT;
+        const int gx = x0 - 2 + i % UX, gy = y0 - 2 + i / UX;
+        const bool ok = i < NU && gx >= 0 && gx < n && gy >= 0 && gy < n;
+        ugb[m] = ok ? (unsigned)((gy * n + gx) * 8) : kOob;
+        uli[m] = UP + (i < NU ? i : NU);  // idle lanes write a guard slot
+    }
+    unsigned wgb[MW];
+    int wq[MW], wuq[MW];
+    bool wval[MW], own[MW];
+#pragma unroll
+    for (int m = 0; m < MW; ++m) {
+        const int i = t + m * NT;
+        const bool in = i < NR;
+        const int lx = in ? i % RX : 0, ly = in ? i / RX : 0;  // idle lanes read a valid node
+        const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
+        wval[m] = in && gx >= 0 && gx < n && gy >= 0 && gy < n;
+        own[m] = wval[m] && lx >= 1 && lx <= TX && ly >= 1 && ly <= TY;
+        wgb[m] = wval[m] ? (unsigned)((gy * n + gx) * 8) : kOob;
+        wq[m] = WP + (in ? i : NR);
+        wuq[m] = UP + (ly + 1) * UX + lx + 1;  // the same node in the ubar window
+    }
+
+    auto ld_plane = [&](const double* f, int p, unsigned off) {
+        return bload<double>(line_rsrc(f, (long)p * plane, plane, p >= 0 && p < n), off);
+    };
+    // w of plane s at step s (s = z0-1 .. z1), outputs of plane s-1
+    const int s0 = z0 - 1, s1 = z1;
+    double pu[MU];
+    if (MODE == 0) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const int p = s0 - 1 + q;
+#pragma unroll
+            for (int m = 0; m < MU; ++m) uL[p & 3][uli[m]] = ld_plane(ub, p, ugb[m]);
+        }
+#pragma unroll
+        for (int m = 0; m < MU; ++m) pu[m] = ld_plane(ub, s0 + 2, ugb[m]);
+    }
+    // per-step loads, one step ahead: r (MODE 0) or w (MODE 1) of plane s,
+    // ubar (MODE 1) and bbar of plane s - 1
+    double nr[MW], nw[MW], nu[MW], nb[MW];
+    auto issue = [&](int s) {
+        const int p = s - 1;
+        const bool pout = p >= z0 && p < z1, sown = s >= z0 && s < z1;
+#pragma unroll
+        for (int m = 0; m < MW; ++m) {
+            nr[m] = MODE == 0 ? ld_plane(r, s, sown && own[m] ? wgb[m] : kOob) : 0.0;
+            nw[m] = MODE == 1 ? ld_plane(wsrc, s, wgb[m]) : 0.0;
+            nu[m] = MODE == 1 ? ld_plane(ub, p, pout && own[m] ? wgb[m] : kOob) : 0.0;
+            nb[m] = ld_plane(bb, p, pout && own[m] ? wgb[m] : kOob);
+        }
+    };
+    issue(s0);
+    double wm1[MW], wm2[MW];
+#pragma unroll
+    for (int m = 0; m < MW; ++m) wm1[m] = wm2[m] = 0.0;
+    for (int i = t; i < WSZ; i += NT) wL[0][i] = wL[1][i] = 0.0;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+
+    for (int s = s0; s <= s1; ++s) {
+        __syncthreads();
+        double rv[MW], ws[MW], uo[MW], bo[MW];
+#pragma unroll
+        for (int m = 0; m < MW; ++m) {
+            rv[m] = nr[m];
+            ws[m] = nw[m];
+            uo[m] = nu[m];
+            bo[m] = nb[m];
+        }
+        if (s < s1) issue(s + 1);
+        if (MODE == 0) {
+#pragma unroll
+            for (int m = 0; m < MU; ++m) uL[(s + 2) & 3][uli[m]] = pu[m];
+#pragma unroll
+            for (int m = 0; m < MU; ++m) pu[m] = ld_plane(ub, s + 3, ugb[m]);
+        }
+        const int p = s - 1;
+        const bool pout = p >= z0 && p < z1;
+        // w of plane s
+        double w0[MW];
+        const bool sin = s >= 0 && s < n, sown = s >= z0 && s < z1;
+#pragma unroll
+        for (int m = 0; m < MW; ++m) {
+            double w = 0.0;
+            if (MODE == 0) {
+                const double* Um = uL[(s + 3) & 3];  // plane s - 1
+                const double* U0 = uL[s & 3];
+                const double* Up = uL[(s + 1) & 3];
+                const int q = wuq[m];
+                const double k0 = U0[q];
+                const double k1 = U0[q - 1] + U0[q + 1] + U0[q - UX] + U0[q + UX] + Um[q] + Up[q];
+                double k2 = 0.0, k3 = 0.0;
+                if (WIDE) {
+                    k2 = U0[q - UX - 1] + U0[q - UX + 1] + U0[q + UX - 1] + U0[q + UX + 1] +
+                         Um[q - 1] + Um[q + 1] + Um[q - UX] + Um[q + UX] + Up[q - 1] + Up[q + 1] +
+                         Up[q - UX] + Up[q + UX];
+                    k3 = Um[q - UX - 1] + Um[q - UX + 1] + Um[q + UX - 1] + Um[q + UX + 1] +
+                         Up[q - UX - 1] + Up[q - UX + 1] + Up[q + UX - 1] + Up[q + UX + 1];
+                }
+                w = sW * (c0 * k0 + c1 * k1 + c2 * k2 + c3 * k3);
+                if (sown && own[m]) {
+                    a0 += k0 * rv[m];
+                    a1 += k1 * rv[m];
+                    a2 += k2 * rv[m];
+                    a3 += k3 * rv[m];
+                }
+            } else {
+                w = ws[m];
+            }
+            w0[m] = (sin && wval[m]) ? w : 0.0;
+            wL[s & 1][wq[m]] = w0[m];
+        }
+        // outputs of plane s - 1
+        if (pout) {
+            const double* W1 = wL[(s + 1) & 1];  // plane s - 1
+            const rsrc_t ro = line_rsrc(ub_new, (long)p * plane, plane, true);
+            const rsrc_t rb = line_rsrc(bb, (long)p * plane, plane, true);
+#pragma unroll
+            for (int m = 0; m < MW; ++m) {
+                const int q = wq[m];
+                const double lw = 6.0 * wm1[m] - W1[q - 1] - W1[q + 1] - W1[q - RX] - W1[q + RX] -
+                                  wm2[m] - w0[m];
+                const double u = MODE == 0 ? uL[(s + 3) & 3][wuq[m]] : uo[m];
+                bstore<false>(u - sA * lw, ro, own[m] ? wgb[m] : kOob);
+                bstore<false>(bo[m] + wm1[m], rb, own[m] ? wgb[m] : kOob);
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < MW; ++m) {
+            wm2[m] = wm1[m];
+            wm1[m] = w0[m];
+        }
+    }
+    if (MODE == 0) {
+        // fixed-order block sums of the four coefficient partials
+        const double s_0 = block_sum<NT>(a0, red);
+        __syncthreads();
+        const double s_1 = block_sum<NT>(a1, red);
+        __syncthreads();
+        const double s_2 = block_sum<NT>(a2, red);
+        __syncthreads();
+        const double s_3 = block_sum<NT>(a3, red);
+        if (t == 0) {
+            double* pp = partials + 4 * ((long)blockIdx.y * gridDim.x + blockIdx.x);
+            pp[0] = sW * s_0;
+            pp[1] = sW * s_1;
+            pp[2] = sW * s_2;
+            pp[3] = sW * s_3;
+        }
+    }
+}
+
+// 2D: x strips of TX outputs marching over rows; K_c is the 9-point stencil.
+template <int TX, int NT, int MODE>
+__global__ void __launch_bounds__(NT)
+k_adj_sweep2d(const double* __restrict__ ub, const double* __restrict__ r,
+              const double* __restrict__ wsrc, double* __restrict__ ub_new,
+              double* __restrict__ bb, double* __restrict__ partials, int n, int tiles_x,
+              int ychunk, int nchunks, double sA, double sW, double c0, double c1, double c2) {
+    constexpr int UX = TX + 4, RX = TX + 2;
+    constexpr int MU = (UX + NT - 1) / NT, MW = (RX + NT - 1) / NT;
+    constexpr int USZ = 1 + MU * NT + 1, WSZ = 1 + MW * NT + 1;
+    __shared__ double uL[MODE == 0 ? 4 : 1][MODE == 0 ? USZ : 1];
+    __shared__ double wL[2][WSZ];
+    __shared__ double red[NT / 64];
+
+    const int total = tiles_x * nchunks;
+    const int lg = xcd_remap(blockIdx.x, total);
+    const int tx = lg % tiles_x, ch = lg / tiles_x;
+    const long area = (long)n * n;
+    const long boff = (long)blockIdx.y * area;
+    ub += boff;
+    ub_new += boff;
+    bb += boff;
+    if (MODE == 0) r += boff;
+    else wsrc += boff;
+    const int x0 = tx * TX;
+    const int z0 = ch * ychunk, z1 = min(z0 + ychunk, n);
+    const int t = threadIdx.x;
+
+    unsigned ugb[MU];
+    int uli[MU];
+#pragma unroll
+    for (int m = 0; m < MU; ++m) {
+        const int i = t + m * NT;
+        const int gx = x0 - 2 + i;
+        ugb[m] = (i < UX && gx >= 0 && gx < n) ? (unsigned)(gx * 8) : kOob;
+        uli[m] = 1 + (i < UX ? i : UX);
+    }
+    unsigned wgb[MW];
+    int wq[MW], wuq[MW];
+    bool wval[MW], own[MW];
+#pragma unroll
+    for (int m = 0; m < MW; ++m) {
+        const int i = t + m * NT;
+        const bool in = i < RX;
+        const int lx = in ? i : 0;
+        const int gx = x0 - 1 + lx;
+        wval[m] = in && gx >= 0 && gx < n;
+        own[m] = wval[m] && lx >= 1 && lx <= TX;
+        wgb[m] = wval[m] ? (unsigned)(gx * 8) : kOob;
+        wq[m] = 1 + (in ? i : RX);
+        wuq[m] = 1 + lx + 1;
+    }
+    auto ld_row = [&](const double* f, int p, unsigned off) {
+        return bload<double>(line_rsrc(f, (long)p * n, n, p >= 0 && p < n), off);
+    };
+    const int s0 = z0 - 1, s1 = z1;
+    double pu[MU];
+    if (MODE == 0) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const int p = s0 - 1 + q;
+#pragma unroll
+            for (int m = 0; m < MU; ++m) uL[p & 3][uli[m]] = ld_row(ub, p, ugb[m]);
+        }
+#pragma unroll
+        for (int m = 0; m < MU; ++m) pu[m] = ld_row(ub, s0 + 2, ugb[m]);
+    }
+    double nr[MW], nw[MW], nu[MW], nb[MW];
+    auto issue = [&](int s) {
+        const int p = s - 1;
+        const bool pout = p >= z0 && p < z1, sown = s >= z0 && s < z1;
+#pragma unroll
+        for (int m = 0; m < MW; ++m) {
+            nr[m] = MODE == 0 ? ld_row(r, s, sown && own[m] ? wgb[m] : kOob) : 0.0;
+            nw[m] = MODE == 1 ? ld_row(wsrc, s, wgb[m]) : 0.0;
+            nu[m] = MODE == 1 ? ld_row(ub, p, pout && own[m] ? wgb[m] : kOob) : 0.0;
+            nb[m] = ld_row(bb, p, pout && own[m] ? wgb[m] : kOob);
+        }
+    };
+    issue(s0);
+    double wm1[MW], wm2[MW];
+#pragma unroll
+    for (int m = 0; m < MW; ++m) wm1[m] = wm2[m] = 0.0;
+    for (int i = t; i < WSZ; i += NT) wL[0][i] = wL[1][i] = 0.0;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+
+    for (int s = s0; s <= s1; ++s) {
+        __syncthreads();
+        double rv[MW], ws[MW], uo[MW], bo[MW];
+#pragma unroll
+        for (int m = 0; m < MW; ++m) {
+            rv[m] = nr[m];
+            ws[m] = nw[m];
+            uo[m] = nu[m];
+            bo[m] = nb[m];
+        }
+        if (s < s1) issue(s + 1);
+        if (MODE == 0) {
+#pragma unroll
+            for (int m = 0; m < MU; ++m) uL[(s + 2) & 3][uli[m]] = pu[m];
+#pragma unroll
+            for (int m = 0; m < MU; ++m) pu[m] = ld_row(ub, s + 3, ugb[m]);
+        }
+        const int p = s - 1;
+        const bool pout = p >= z0 && p < z1;
+        double w0[MW];
+        const bool sin = s >= 0 && s < n, sown = s >= z0 && s < z1;
+#pragma unroll
+        for (int m = 0; m < MW; ++m) {
+            double w = 0.0;
+            if (MODE == 0) {
+                const double* Um = uL[(s + 3) & 3];  // row s - 1
+                const double* U0 = uL[s & 3];
+                const double* Up = uL[(s + 1) & 3];
+                const int q = wuq[m];
+                const double k0 = U0[q];
+                const double k1 = U0[q - 1] + U0[q + 1] + Um[q] + Up[q];
+                const double k2 = Um[q - 1] + Um[q + 1] + Up[q - 1] + Up[q + 1];
+                w = sW * (c0 * k0 + c1 * k1 + c2 * k2);
+                if (sown && own[m]) {
+                    a0 += k0 * rv[m];
+                    a1 += k1 * rv[m];
+                    a2 += k2 * rv[m];
+                }
+            } else {
+                w = ws[m];
+            }
+            w0[m] = (sin && wval[m]) ? w : 0.0;
+            wL[s & 1][wq[m]] = w0[m];
+        }
+        if (pout) {
+            const double* W1 = wL[(s + 1) & 1];  // row s - 1
+            const rsrc_t ro = line_rsrc(ub_new, (long)p * n, n, true);
+            const rsrc_t rb = line_rsrc(bb, (long)p * n, n, true);
+#pragma unroll
+            for (int m = 0; m < MW; ++m) {
+                const int q = wq[m];
+                const double lw = 4.0 * wm1[m] - W1[q - 1] - W1[q + 1] - wm2[m] - w0[m];
+                const double u = MODE == 0 ? uL[(s + 3) & 3][wuq[m]] : uo[m];
+                bstore<false>(u - sA * lw, ro, own[m] ? wgb[m] : kOob);
+                bstore<false>(bo[m] + wm1[m], rb, own[m] ? wgb[m] : kOob);
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < MW; ++m) {
+            wm2[m] = wm1[m];
+            wm1[m] = w0[m];
+        }
+    }
+    if (MODE == 0) {
+        const double s_0 = block_sum<NT>(a0, red);
+        __syncthreads();
+        const double s_1 = block_sum<NT>(a1, red);
+        __syncthreads();
+        const double s_2 = block_sum<NT>(a2, red);
+        if (t == 0) {
+            double* pp = partials + 4 * ((long)blockIdx.y * gridDim.x + blockIdx.x);
+            pp[0] = sW * s_0;
+            pp[1] = sW * s_1;
+            pp[2] = sW * s_2;
+            pp[3] = 0.0;
+        }
     }
 }
 
@@ -3111,6 +3497,22 @@ hipError_t launch_smooth3d(bool zg, bool norm, const Sweep& s, int want, int min
     hipLaunchKernelGGL((k_smooth3d<S, C, TX, TY, NT, PD, UN, ZG, NM, PR, NTS, WD>), grid,       \
                        dim3(NT), 0, st, u, b, out, n, tx, ty, zc, nch, sA, sW, c0, c1,         \
                        s.partials, ec, nc, pf, c2, c3)
+#define L3R(PD, PR, WD)                                                                        \
+    hipLaunchKernelGGL((k_smooth3d<S, C, TX, TY, NT, PD, UN, false, false, PR, NTS, WD, true>), \
+                       grid, dim3(NT), 0, st, u, b, out, n, tx, ty, zc, nch, sA, sW, c0, c1,  \
+                       s.partials, ec, nc, pf, c2, c3, static_cast<S*>(s.rout))
+    if constexpr (sizeof(S) == 8) {
+        if (s.rout) {  // residual side output (from a guess, or with the correction)
+            if (zg || norm) return hipErrorInvalidValue;
+            const bool wide = s.c[2] != 0.0 || s.c[3] != 0.0;
+            if (pro && wide) L3R(PDC, true, true);
+            else if (pro) L3R(PDC, true, false);
+            else if (wide) L3R(1, false, true);
+            else L3R(1, false, false);
+            return hipGetLastError();
+        }
+    }
+#undef L3R
     if (s.c[2] != 0.0 || s.c[3] != 0.0) {  // 19-/27-point stencil
         if (zg) L3(1, true, false, false, true);
         else if (norm) L3(1, false, true, false, true);
@@ -3146,6 +3548,20 @@ hipError_t launch_smooth2d(bool zg, bool norm, const Sweep& s, int want, int min
 #define L2(ZG, NM, PR)                                                                      \
     hipLaunchKernelGGL((k_smooth2d<S, C, TX, NT, 1, UN, ZG, NM, PR, NTS>), grid, dim3(NT), 0, \
                        st, u, b, out, n, tx, yc, nch, sA, sW, c0, c1, c2, s.partials, ec, nc, pf)
+    if constexpr (sizeof(S) == 8) {
+        if (s.rout) {  // residual side output (from a guess, or with the correction)
+            if (zg || norm) return hipErrorInvalidValue;
+            if (pro)
+                hipLaunchKernelGGL((k_smooth2d<S, C, TX, NT, 1, UN, false, false, true, NTS, true>),
+                                   grid, dim3(NT), 0, st, u, b, out, n, tx, yc, nch, sA, sW, c0,
+                                   c1, c2, s.partials, ec, nc, pf, static_cast<S*>(s.rout));
+            else
+                hipLaunchKernelGGL((k_smooth2d<S, C, TX, NT, 1, UN, false, false, false, NTS, true>),
+                                   grid, dim3(NT), 0, st, u, b, out, n, tx, yc, nch, sA, sW, c0,
+                                   c1, c2, s.partials, ec, nc, pf, static_cast<S*>(s.rout));
+            return hipGetLastError();
+        }
+    }
     if (zg) L2(true, false, false);
     else if (norm) L2(false, true, false);
     else if (pro) L2(false, false, true);
@@ -3418,6 +3834,15 @@ hipError_t launch_sr2d(const Sweep& s, bool norm, int want, int minc, hipStream_
 #define SR2(NM)                                                                              \
     hipLaunchKernelGGL((k_sr2d<S, C, TX, NT, PD, UN, NTS, NM>), grid, dim3(NT), 0, st, u, b,  \
                        out, bc, n, nc, tx, yc, nch, sA, sW, c0, c1, c2, s.partials)
+    if constexpr (sizeof(S) == 8) {
+        if (s.rout) {  // residual side output
+            if (norm) return hipErrorInvalidValue;
+            hipLaunchKernelGGL((k_sr2d<S, C, TX, NT, PD, UN, NTS, false, true>), grid, dim3(NT), 0,
+                               st, u, b, out, bc, n, nc, tx, yc, nch, sA, sW, c0, c1, c2,
+                               s.partials, static_cast<S*>(s.rout));
+            return hipGetLastError();
+        }
+    }
     if (norm) SR2(true);
     else SR2(false);
 #undef SR2
@@ -3442,6 +3867,15 @@ hipError_t launch_sr3d(const Sweep& s, bool norm, int want, int minc, hipStream_
 #define SR3(NM)                                                                             \
     hipLaunchKernelGGL((k_sr3d<S, C, TX, TY, NT, PD, UN, NTS, NM>), grid, dim3(NT), 0, st,     \
                        u, b, out, bc, n, nc, tx, ty, zc, nch, sA, sW, c0, c1, s.partials)
+    if constexpr (sizeof(S) == 8) {
+        if (s.rout) {  // residual side output
+            if (norm) return hipErrorInvalidValue;
+            hipLaunchKernelGGL((k_sr3d<S, C, TX, TY, NT, PD, UN, NTS, false, true>), grid,
+                               dim3(NT), 0, st, u, b, out, bc, n, nc, tx, ty, zc, nch, sA, sW,
+                               c0, c1, s.partials, static_cast<S*>(s.rout));
+            return hipGetLastError();
+        }
+    }
     if (norm) SR3(true);
     else SR3(false);
 #undef SR3
@@ -3580,6 +4014,53 @@ hipError_t launch_tail(Prec p, const Tail& t, hipStream_t st) {
         case P32: return tail_impl<float, float>(t, st);
         default: return tail_impl<_Float16, float>(t, st);
     }
+}
+
+hipError_t launch_adj_sweep(int d, int n, int batch, int mode, const double* ubar,
+                            const double* r, const double* w, double* ubar_new, double* bbar,
+                            double* partials, long partials_cap, double sA, double sW,
+                            const double* c, hipStream_t st, int* nparts) {
+    if (mode != 0 && mode != 1) return hipErrorInvalidValue;
+    if ((long)n * n * 8 > 0x7fffffffL) return hipErrorInvalidValue;  // 32-bit plane offsets
+    dim3 grid;
+    int tx = 0, ty = 1, zc = 0, nch = 0;
+    // about 2048 marches over the whole batch, none shorter than 8 planes
+    // (rows): each march re-reads three planes of ubar and computes one
+    // plane of w more than it owns
+    const int want = std::max(64, 2048 / std::max(1, batch));
+    if (d == 3) {
+        // 32 x 16 tiles on 512 threads (ubar on 36 x 20 per plane in LDS)
+        tx = cdiv(n, 32);
+        ty = cdiv(n, 16);
+        zc = pick_chunk(n, tx * ty, want, 8);
+    } else {
+        // 256-wide strips on 320 threads
+        tx = cdiv(n, 256);
+        zc = pick_chunk(n, tx, want, 8);
+    }
+    nch = cdiv(n, zc);
+    grid = dim3(tx * ty * nch, batch);
+    if (nparts) *nparts = grid.x * grid.y;
+    if (mode == 0 && 4L * grid.x * grid.y > partials_cap) return hipErrorInvalidValue;
+    const bool wide = d == 3 && (c[2] != 0.0 || c[3] != 0.0);
+#define AS3(WD, MD)                                                                             \
+    hipLaunchKernelGGL((k_adj_sweep3d<32, 16, 512, WD, MD>), grid, dim3(512), 0, st, ubar, r, w, \
+                       ubar_new, bbar, partials, n, tx, ty, zc, nch, sA, sW, c[0], c[1], c[2],  \
+                       c[3])
+#define AS2(MD)                                                                               \
+    hipLaunchKernelGGL((k_adj_sweep2d<256, 320, MD>), grid, dim3(320), 0, st, ubar, r, w,      \
+                       ubar_new, bbar, partials, n, tx, zc, nch, sA, sW, c[0], c[1], c[2])
+    if (d == 3) {
+        if (mode == 1) AS3(false, 1);
+        else if (wide) AS3(true, 0);
+        else AS3(false, 0);
+    } else {
+        if (mode == 1) AS2(1);
+        else AS2(0);
+    }
+#undef AS3
+#undef AS2
+    return hipGetLastError();
 }
 
 hipError_t launch_finalize(const double* partials, const double* maxparts, int count,
