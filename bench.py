@@ -375,14 +375,14 @@ def mixed(tol):
 # restriction with the residual r1 kept (read u, b; write t, r1, b_c) and
 # post-smoother with the fused correction and r3 kept (read t, b, e_c; write
 # u_out, r3); the reverse pass's two smoothing sweeps (read ubar, r, bbar;
-# write ubar', bbar), restriction of ubar and interpolation of bbar_c (one
-# fine field each way), and the update after the interpolation (read ubar,
-# w, bbar; write ubar', bbar); FP32 checkpoints add their widening (read 4,
+# write ubar', bbar), the restriction of ubar (read a fine field, write a
+# coarse one) and the update with the interpolated bbar_c (read ubar, bbar,
+# bbar_c; write ubar', bbar); FP32 checkpoints add their widening (read 4,
 # write 8).  c is one coarse value per 2^d fine points.
 def adjoint_bytes_per_pt(d, ckpt="fp64"):
     c = 8.0 / 2 ** d
     forward = (32 + c) + (32 + c)
-    reverse = 40 + (8 + c) + (8 + c) + 40 + 40
+    reverse = 40 + (8 + c) + (32 + c) + 40
     return forward + reverse + (12.0 if ckpt == "fp32" else 0.0)
 
 

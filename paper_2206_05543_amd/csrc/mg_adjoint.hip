@@ -1,5 +1,5 @@
-// gfx950 kernels of the reverse-mode (adjoint) V(1,1) cycle, FP64: the grid
-// transfers of the reverse sweep, the coefficient-gradient reduction, the
+// gfx950 kernels of the reverse-mode (adjoint) V(1,1) cycle, FP64: the
+// restriction of the reverse sweep, the coefficient-gradient reduction, the
 // checkpoint conversions and the coarsest grid's matrix product.  The
 // reverse smoothing steps are marching sweeps in mg_kernels.hip
 // (launch_adj_sweep), and the forward recomputation uses the cycle's own
@@ -60,32 +60,6 @@ k_fw(const double* __restrict__ f, double* __restrict__ c, Grid gf, Grid gc, dou
                     s += wt * gf.at(f + offf, fi + ox, fj + oy, gf.d == 3 ? fk + oz : 0);
                 }
         c[offc + p] = scale * s;
-    }
-}
-
-// fine = scale * P coarse (linear interpolation; scale 2^-d gives R^T)
-__global__ void __launch_bounds__(256)
-k_interp(const double* __restrict__ c, double* __restrict__ f, Grid gf, Grid gc, double scale) {
-    const long offf = (long)blockIdx.y * gf.pts, offc = (long)blockIdx.y * gc.pts;
-    for (long p = (long)blockIdx.x * 256 + threadIdx.x; p < gf.pts; p += (long)gridDim.x * 256) {
-        int i, j, k;
-        gf.coords(p, &i, &j, &k);
-        // grid coordinate g = i + 1: even -> coarse node g/2, odd -> mean of
-        // (g-1)/2 and (g+1)/2; coarse node G has interior index G - 1
-        const int gi = i + 1, gj = j + 1, gk = k + 1;
-        const int ia = gi / 2, ib = (gi + 1) / 2, ja = gj / 2, jb = (gj + 1) / 2;
-        double s;
-        if (gf.d == 2) {
-            s = 0.25 * (gc.at(c + offc, ia - 1, ja - 1, 0) + gc.at(c + offc, ib - 1, ja - 1, 0) +
-                        gc.at(c + offc, ia - 1, jb - 1, 0) + gc.at(c + offc, ib - 1, jb - 1, 0));
-        } else {
-            const int ka = gk / 2, kb = (gk + 1) / 2;
-            s = 0.125 * (gc.at(c + offc, ia - 1, ja - 1, ka - 1) + gc.at(c + offc, ib - 1, ja - 1, ka - 1) +
-                         gc.at(c + offc, ia - 1, jb - 1, ka - 1) + gc.at(c + offc, ib - 1, jb - 1, ka - 1) +
-                         gc.at(c + offc, ia - 1, ja - 1, kb - 1) + gc.at(c + offc, ib - 1, ja - 1, kb - 1) +
-                         gc.at(c + offc, ia - 1, jb - 1, kb - 1) + gc.at(c + offc, ib - 1, jb - 1, kb - 1));
-        }
-        f[offf + p] = scale * s;
     }
 }
 
@@ -161,15 +135,6 @@ hipError_t launch_fw(int d, int n, int batch, const double* fine, double* coarse
     const int nc = (n + 1) / 2 - 1;
     const Grid gf = make_grid(d, n), gc = make_grid(d, nc);
     hipLaunchKernelGGL(k_fw, point_grid(gc.pts, batch), dim3(256), 0, st, fine, coarse, gf, gc, scale);
-    return hipGetLastError();
-}
-
-hipError_t launch_interp(int d, int n, int batch, const double* coarse, double* fine, double scale,
-                         hipStream_t st) {
-    const int nc = (n + 1) / 2 - 1;
-    const Grid gf = make_grid(d, n), gc = make_grid(d, nc);
-    hipLaunchKernelGGL(k_interp, point_grid(gf.pts, batch), dim3(256), 0, st, coarse, fine, gf, gc,
-                       scale);
     return hipGetLastError();
 }
 

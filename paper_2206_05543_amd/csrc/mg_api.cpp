@@ -1527,10 +1527,11 @@ int alloc_adj(mg_ctx* h) {
         }
         if (l < h->L - 1) {
             HIPCHK(hipMalloc(&h->adj_r3[l], bytes));
-            HIPCHK(hipMalloc(&h->adj_w[l], bytes));
             HIPCHK(hipMalloc(&h->adj_ua[l], bytes));
             HIPCHK(hipMalloc(&h->adj_ub[l], bytes));
         }
+        // the fine level's post-smoothed iterate of the recomputation (unused)
+        if (l == 0 && h->L > 1) HIPCHK(hipMalloc(&h->adj_w[l], bytes));
     }
     HIPCHK(hipMalloc(&h->adj_cacc, 4 * sizeof(double)));
     HIPCHK(hipMalloc(&h->adj_cin, (size_t)level_pts(h, 0) * h->batch * sizeof(double)));
@@ -1602,7 +1603,6 @@ int adj_reverse(mg_ctx* h, int l, const double* uo, double* ui, double* bb, cons
     }
     double c[4] = {h->c[0], h->c[1], h->ncoef > 2 ? h->c[2] : 0.0,
                    h->ncoef > 3 ? h->c[3] : 0.0};
-    double* w = h->adj_w[l];
     double* ua = h->adj_ua[l];
     double* ub = h->adj_ub[l];
     int np = 0;
@@ -1610,7 +1610,7 @@ int adj_reverse(mg_ctx* h, int l, const double* uo, double* ui, double* bb, cons
     // A M ubar_out, bbar += M ubar_out; its coefficient-gradient partials
     // (scaled by h^2) go to their own slots, reduced once per adjoint call in
     // slot order
-    HIPCHK(launch_adj_sweep(d, n, b, 0, uo, h->adj_r3[l], nullptr, ua, bb,
+    HIPCHK(launch_adj_sweep(d, n, b, 0, uo, h->adj_r3[l], nullptr, 0.0, ua, bb,
                             h->adj_part + h->adj_poff, h->adj_pcap - h->adj_poff, N * N, h2, c,
                             st, &np));
     h->adj_poff += 4L * np;
@@ -1621,14 +1621,13 @@ int adj_reverse(mg_ctx* h, int l, const double* uo, double* ui, double* bb, cons
     int rc = adj_reverse(h, l + 1, h->adj_uo[l + 1], nullptr, h->adj_bb[l + 1],
                          static_cast<const double*>(H.b[l + 1]), st);
     if (rc) return rc;
-    // restriction b_c = R (b - A u1): rbar = R^T bcbar = 2^-d P bcbar;
-    // ubar1 = ubar2 - A rbar, bbar += rbar
-    HIPCHK(launch_interp(d, n, b, h->adj_bb[l + 1], w, d == 2 ? 0.25 : 0.125, st));
-    HIPCHK(launch_adj_sweep(d, n, b, 1, ua, nullptr, w, ub, bb, nullptr, 0, N * N, h2, c, st,
-                            nullptr));
+    // restriction b_c = R (b - A u1): rbar = R^T bcbar = 2^-d P bcbar,
+    // interpolated inside the sweep; ubar1 = ubar2 - A rbar, bbar += rbar
+    HIPCHK(launch_adj_sweep(d, n, b, 1, ua, nullptr, h->adj_bb[l + 1], d == 2 ? 0.25 : 0.125, ub,
+                            bb, nullptr, 0, N * N, h2, c, st, nullptr));
     // pre-smoothing  u1 = u + M r1, r1 = b - A u: ubar = ubar1 - A M ubar1
     // (discarded below the fine level: the coarse cycles start from zero)
-    HIPCHK(launch_adj_sweep(d, n, b, 0, ub, r1, nullptr, ui ? ui : ua, bb,
+    HIPCHK(launch_adj_sweep(d, n, b, 0, ub, r1, nullptr, 0.0, ui ? ui : ua, bb,
                             h->adj_part + h->adj_poff, h->adj_pcap - h->adj_poff, N * N, h2, c,
                             st, &np));
     h->adj_poff += 4L * np;

@@ -139,18 +139,16 @@ hipError_t launch_ir_step(Prec p, const IRStep& s, hipStream_t st, int* nparts);
 //   mode 0 (the reverse of a smoothing step): w = sW sum_j c_j K_j ubar (K_2:
 //   diagonals in 2D, edges in 3D; K_3: corners, 3D), partials[4 i + j] = sW x
 //   block sums of (K_j ubar) r over the owned nodes; mode 1 (the reverse of
-//   the restricted residual): w read from `w`; then ubar_new = ubar - sA L w
-//   and bbar += w.  ubar_new must not alias ubar.  *nparts = blocks.
+//   the restricted residual): w = scale P ec (ec on the next coarser grid);
+//   then ubar_new = ubar - sA L w and bbar += w.  ubar_new must not alias
+//   ubar.  *nparts = blocks.
 hipError_t launch_adj_sweep(int d, int n, int batch, int mode, const double* ubar,
-                            const double* r, const double* w, double* ubar_new, double* bbar,
-                            double* partials, long partials_cap, double sA, double sW,
-                            const double* c, hipStream_t st, int* nparts);
+                            const double* r, const double* ec, double scale, double* ubar_new,
+                            double* bbar, double* partials, long partials_cap, double sA,
+                            double sW, const double* c, hipStream_t st, int* nparts);
 //   coarse = scale * R fine (full weighting)
 hipError_t launch_fw(int d, int n, int batch, const double* fine, double* coarse,
                      double scale, hipStream_t st);
-//   fine = scale * P coarse (linear interpolation, overwrite)
-hipError_t launch_interp(int d, int n, int batch, const double* coarse, double* fine,
-                         double scale, hipStream_t st);
 //   acc[j] = scale * sum_i partials[ncols i + j] (fixed order)
 hipError_t launch_reduce_cols(const double* partials, int count, int ncols, double* acc,
                               double scale, hipStream_t st);

@@ -2358,18 +2358,19 @@ k_sr3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out,
 // staged in LDS on the tile plus a ring of 2, the coefficient partials
 // sW sum (K_j ubar) r over the owned nodes, then ubar_new = ubar - sA L w
 // and bbar += w at the owned nodes, one plane (row) behind.  MODE 1, the
-// reverse of the restriction of the residual: the same update with w read
-// from memory (w = 2^-d P bbar_c, from the interpolation kernel).  ubar and
-// w are zero outside the grid (zero extension).  Loads of plane (row) s+1
-// are issued during step s.
+// reverse of the restriction of the residual: the same update with w =
+// scale P bbar_c, the linear interpolation of the coarse field ec (scale =
+// 2^-d gives R^T), gathered per node from L2 with the interpolation
+// operator's weights.  ubar and w are zero outside the grid (zero
+// extension).  Loads of plane (row) s+1 are issued during step s.
 // ---------------------------------------------------------------------------
 template <int TX, int TY, int NT, bool WIDE, int MODE>
 __global__ void __launch_bounds__(NT)
 k_adj_sweep3d(const double* __restrict__ ub, const double* __restrict__ r,
-              const double* __restrict__ wsrc, double* __restrict__ ub_new,
+              const double* __restrict__ ec, double* __restrict__ ub_new,
               double* __restrict__ bb, double* __restrict__ partials, int n, int tiles_x,
               int tiles_y, int zchunk, int nchunks, double sA, double sW, double c0, double c1,
-              double c2, double c3) {
+              double c2, double c3, double scale) {
     constexpr int UX = TX + 4, UY = TY + 4, NU = UX * UY;  // ubar: tile + ring 2
     constexpr int RX = TX + 2, RY = TY + 2, NR = RX * RY;  // w: tile + ring 1
     constexpr int MU = (NU + NT - 1) / NT, MW = (NR + NT - 1) / NT;
@@ -2384,11 +2385,13 @@ k_adj_sweep3d(const double* __restrict__ ub, const double* __restrict__ r,
     const int tx = lg % tiles_x, ty = (lg / tiles_x) % tiles_y, ch = lg / (tiles_x * tiles_y);
     const long plane = (long)n * n;
     const long boff = (long)blockIdx.y * plane * n;
+    const int nc = (n + 1) / 2 - 1;
+    const long cplane = (long)nc * nc;
     ub += boff;
     ub_new += boff;
     bb += boff;
     if (MODE == 0) r += boff;
-    else wsrc += boff;
+    else ec += (long)blockIdx.y * cplane * nc;
     const int x0 = tx * TX, y0 = ty * TY;
     const int z0 = ch * zchunk, z1 = min(z0 + zchunk, n);
     const int t = threadIdx.x;
@@ -2418,9 +2421,42 @@ k_adj_sweep3d(const double* __restrict__ ub, const double* __restrict__ r,
         wq[m] = WP + (in ? i : NR);
         wuq[m] = UP + (ly + 1) * UX + lx + 1;  // the same node in the ubar window
     }
+    // MODE 1: the coarse nodes of each w node's interpolation in the plane:
+    // grid coordinate g = gx + 1 lies on or between coarse nodes g/2 and
+    // (g+1)/2 (interior indices one less; 0 and nc+1 are boundary nodes)
+    unsigned cof[MW][4];
+    if (MODE == 1) {
+#pragma unroll
+        for (int m = 0; m < MW; ++m) {
+            const int i = t + m * NT;
+            const bool in = i < NR;
+            const int gx = x0 - 1 + (in ? i % RX : 0) + 1, gy = y0 - 1 + (in ? i / RX : 0) + 1;
+            const int xa = gx / 2 - 1, xb = (gx + 1) / 2 - 1, ya = gy / 2 - 1, yb = (gy + 1) / 2 - 1;
+            auto off = [&](int cx, int cy) -> unsigned {
+                return (wval[m] && cx >= 0 && cx < nc && cy >= 0 && cy < nc)
+                           ? (unsigned)((cy * nc + cx) * 8) : kOob;
+            };
+            cof[m][0] = off(xa, ya);
+            cof[m][1] = off(xb, ya);
+            cof[m][2] = off(xa, yb);
+            cof[m][3] = off(xb, yb);
+        }
+    }
 
     auto ld_plane = [&](const double* f, int p, unsigned off) {
         return bload<double>(line_rsrc(f, (long)p * plane, plane, p >= 0 && p < n), off);
+    };
+    // the eight coarse values of a w node of plane s (four per coarse plane,
+    // coarse planes (s+1)/2 - 1 and (s+2)/2 - 1, the same plane twice when s
+    // is odd), summed in the interpolation operator's order
+    auto interp = [&](int s, int m) -> double {
+        const int g = s + 1, za = g / 2 - 1, zb = (g + 1) / 2 - 1;
+        const rsrc_t ra = line_rsrc(ec, (long)za * cplane, cplane, za >= 0 && za < nc);
+        const rsrc_t rb = line_rsrc(ec, (long)zb * cplane, cplane, zb >= 0 && zb < nc);
+        return bload<double>(ra, cof[m][0]) + bload<double>(ra, cof[m][1]) +
+               bload<double>(ra, cof[m][2]) + bload<double>(ra, cof[m][3]) +
+               bload<double>(rb, cof[m][0]) + bload<double>(rb, cof[m][1]) +
+               bload<double>(rb, cof[m][2]) + bload<double>(rb, cof[m][3]);
     };
     // w of plane s at step s (s = z0-1 .. z1), outputs of plane s-1
     const int s0 = z0 - 1, s1 = z1;
@@ -2444,7 +2480,7 @@ k_adj_sweep3d(const double* __restrict__ ub, const double* __restrict__ r,
 #pragma unroll
         for (int m = 0; m < MW; ++m) {
             nr[m] = MODE == 0 ? ld_plane(r, s, sown && own[m] ? wgb[m] : kOob) : 0.0;
-            nw[m] = MODE == 1 ? ld_plane(wsrc, s, wgb[m]) : 0.0;
+            nw[m] = MODE == 1 ? interp(s, m) : 0.0;
             nu[m] = MODE == 1 ? ld_plane(ub, p, pout && own[m] ? wgb[m] : kOob) : 0.0;
             nb[m] = ld_plane(bb, p, pout && own[m] ? wgb[m] : kOob);
         }
@@ -2504,7 +2540,7 @@ k_adj_sweep3d(const double* __restrict__ ub, const double* __restrict__ r,
                     a3 += k3 * rv[m];
                 }
             } else {
-                w = ws[m];
+                w = scale * (0.125 * ws[m]);
             }
             w0[m] = (sin && wval[m]) ? w : 0.0;
             wL[s & 1][wq[m]] = w0[m];
@@ -2553,9 +2589,10 @@ k_adj_sweep3d(const double* __restrict__ ub, const double* __restrict__ r,
 template <int TX, int NT, int MODE>
 __global__ void __launch_bounds__(NT)
 k_adj_sweep2d(const double* __restrict__ ub, const double* __restrict__ r,
-              const double* __restrict__ wsrc, double* __restrict__ ub_new,
+              const double* __restrict__ ec, double* __restrict__ ub_new,
               double* __restrict__ bb, double* __restrict__ partials, int n, int tiles_x,
-              int ychunk, int nchunks, double sA, double sW, double c0, double c1, double c2) {
+              int ychunk, int nchunks, double sA, double sW, double c0, double c1, double c2,
+              double scale) {
     constexpr int UX = TX + 4, RX = TX + 2;
     constexpr int MU = (UX + NT - 1) / NT, MW = (RX + NT - 1) / NT;
     constexpr int USZ = 1 + MU * NT + 1, WSZ = 1 + MW * NT + 1;
@@ -2568,11 +2605,12 @@ k_adj_sweep2d(const double* __restrict__ ub, const double* __restrict__ r,
     const int tx = lg % tiles_x, ch = lg / tiles_x;
     const long area = (long)n * n;
     const long boff = (long)blockIdx.y * area;
+    const int nc = (n + 1) / 2 - 1;
     ub += boff;
     ub_new += boff;
     bb += boff;
     if (MODE == 0) r += boff;
-    else wsrc += boff;
+    else ec += (long)blockIdx.y * nc * nc;
     const int x0 = tx * TX;
     const int z0 = ch * ychunk, z1 = min(z0 + ychunk, n);
     const int t = threadIdx.x;
@@ -2601,8 +2639,29 @@ k_adj_sweep2d(const double* __restrict__ ub, const double* __restrict__ r,
         wq[m] = 1 + (in ? i : RX);
         wuq[m] = 1 + lx + 1;
     }
+    // MODE 1: the coarse columns of each w node's interpolation
+    unsigned cof[MW][2];
+    if (MODE == 1) {
+#pragma unroll
+        for (int m = 0; m < MW; ++m) {
+            const int i = t + m * NT;
+            const int g = x0 - 1 + (i < RX ? i : 0) + 1;
+            const int xa = g / 2 - 1, xb = (g + 1) / 2 - 1;
+            cof[m][0] = (wval[m] && xa >= 0 && xa < nc) ? (unsigned)(xa * 8) : kOob;
+            cof[m][1] = (wval[m] && xb >= 0 && xb < nc) ? (unsigned)(xb * 8) : kOob;
+        }
+    }
     auto ld_row = [&](const double* f, int p, unsigned off) {
         return bload<double>(line_rsrc(f, (long)p * n, n, p >= 0 && p < n), off);
+    };
+    // the four coarse values of a w node of row s, in the interpolation
+    // operator's order
+    auto interp = [&](int s, int m) -> double {
+        const int g = s + 1, ya = g / 2 - 1, yb = (g + 1) / 2 - 1;
+        const rsrc_t ra = line_rsrc(ec, (long)ya * nc, nc, ya >= 0 && ya < nc);
+        const rsrc_t rb = line_rsrc(ec, (long)yb * nc, nc, yb >= 0 && yb < nc);
+        return bload<double>(ra, cof[m][0]) + bload<double>(ra, cof[m][1]) +
+               bload<double>(rb, cof[m][0]) + bload<double>(rb, cof[m][1]);
     };
     const int s0 = z0 - 1, s1 = z1;
     double pu[MU];
@@ -2623,7 +2682,7 @@ k_adj_sweep2d(const double* __restrict__ ub, const double* __restrict__ r,
 #pragma unroll
         for (int m = 0; m < MW; ++m) {
             nr[m] = MODE == 0 ? ld_row(r, s, sown && own[m] ? wgb[m] : kOob) : 0.0;
-            nw[m] = MODE == 1 ? ld_row(wsrc, s, wgb[m]) : 0.0;
+            nw[m] = MODE == 1 ? interp(s, m) : 0.0;
             nu[m] = MODE == 1 ? ld_row(ub, p, pout && own[m] ? wgb[m] : kOob) : 0.0;
             nb[m] = ld_row(bb, p, pout && own[m] ? wgb[m] : kOob);
         }
@@ -2674,7 +2733,7 @@ k_adj_sweep2d(const double* __restrict__ ub, const double* __restrict__ r,
                     a2 += k2 * rv[m];
                 }
             } else {
-                w = ws[m];
+                w = scale * (0.25 * ws[m]);
             }
             w0[m] = (sin && wval[m]) ? w : 0.0;
             wL[s & 1][wq[m]] = w0[m];
@@ -4017,9 +4076,9 @@ hipError_t launch_tail(Prec p, const Tail& t, hipStream_t st) {
 }
 
 hipError_t launch_adj_sweep(int d, int n, int batch, int mode, const double* ubar,
-                            const double* r, const double* w, double* ubar_new, double* bbar,
-                            double* partials, long partials_cap, double sA, double sW,
-                            const double* c, hipStream_t st, int* nparts) {
+                            const double* r, const double* ec, double scale, double* ubar_new,
+                            double* bbar, double* partials, long partials_cap, double sA,
+                            double sW, const double* c, hipStream_t st, int* nparts) {
     if (mode != 0 && mode != 1) return hipErrorInvalidValue;
     if ((long)n * n * 8 > 0x7fffffffL) return hipErrorInvalidValue;  // 32-bit plane offsets
     dim3 grid;
@@ -4044,12 +4103,12 @@ hipError_t launch_adj_sweep(int d, int n, int batch, int mode, const double* uba
     if (mode == 0 && 4L * grid.x * grid.y > partials_cap) return hipErrorInvalidValue;
     const bool wide = d == 3 && (c[2] != 0.0 || c[3] != 0.0);
 #define AS3(WD, MD)                                                                             \
-    hipLaunchKernelGGL((k_adj_sweep3d<32, 16, 512, WD, MD>), grid, dim3(512), 0, st, ubar, r, w, \
-                       ubar_new, bbar, partials, n, tx, ty, zc, nch, sA, sW, c[0], c[1], c[2],  \
-                       c[3])
+    hipLaunchKernelGGL((k_adj_sweep3d<32, 16, 512, WD, MD>), grid, dim3(512), 0, st, ubar, r, ec, \
+                       ubar_new, bbar, partials, n, tx, ty, zc, nch, sA, sW, c[0], c[1], c[2], \
+                       c[3], scale)
 #define AS2(MD)                                                                               \
-    hipLaunchKernelGGL((k_adj_sweep2d<256, 320, MD>), grid, dim3(320), 0, st, ubar, r, w,      \
-                       ubar_new, bbar, partials, n, tx, zc, nch, sA, sW, c[0], c[1], c[2])
+    hipLaunchKernelGGL((k_adj_sweep2d<256, 320, MD>), grid, dim3(320), 0, st, ubar, r, ec,     \
+                       ubar_new, bbar, partials, n, tx, zc, nch, sA, sW, c[0], c[1], c[2], scale)
     if (d == 3) {
         if (mode == 1) AS3(false, 1);
         else if (wide) AS3(true, 0);
