@@ -2360,9 +2360,10 @@ k_sr3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out,
 // and bbar += w at the owned nodes, one plane (row) behind.  MODE 1, the
 // reverse of the restriction of the residual: the same update with w =
 // scale P bbar_c, the linear interpolation of the coarse field ec (scale =
-// 2^-d gives R^T), gathered per node from L2 with the interpolation
-// operator's weights.  ubar and w are zero outside the grid (zero
-// extension).  Loads of plane (row) s+1 are issued during step s.
+// 2^-d gives R^T), gathered from L2 once per coarse plane (row) and node
+// column and combined with the interpolation operator's weights.  ubar and
+// w are zero outside the grid (zero extension).  Loads of plane (row) s+1
+// are issued during step s.
 // ---------------------------------------------------------------------------
 template <int TX, int TY, int NT, bool WIDE, int MODE>
 __global__ void __launch_bounds__(NT)
@@ -2446,17 +2447,16 @@ k_adj_sweep3d(const double* __restrict__ ub, const double* __restrict__ r,
     auto ld_plane = [&](const double* f, int p, unsigned off) {
         return bload<double>(line_rsrc(f, (long)p * plane, plane, p >= 0 && p < n), off);
     };
-    // the eight coarse values of a w node of plane s (four per coarse plane,
-    // coarse planes (s+1)/2 - 1 and (s+2)/2 - 1, the same plane twice when s
-    // is odd), summed in the interpolation operator's order
-    auto interp = [&](int s, int m) -> double {
-        const int g = s + 1, za = g / 2 - 1, zb = (g + 1) / 2 - 1;
-        const rsrc_t ra = line_rsrc(ec, (long)za * cplane, cplane, za >= 0 && za < nc);
-        const rsrc_t rb = line_rsrc(ec, (long)zb * cplane, cplane, zb >= 0 && zb < nc);
-        return bload<double>(ra, cof[m][0]) + bload<double>(ra, cof[m][1]) +
-               bload<double>(ra, cof[m][2]) + bload<double>(ra, cof[m][3]) +
-               bload<double>(rb, cof[m][0]) + bload<double>(rb, cof[m][1]) +
-               bload<double>(rb, cof[m][2]) + bload<double>(rb, cof[m][3]);
+    // the in-plane part of a w node's interpolation: the four coarse values
+    // of coarse plane k around it (a node on a coarse line counts its value
+    // twice).  Fine plane s (grid coordinate s + 1) lies between coarse
+    // planes s/2 - 1 and s/2 when s is even and on plane (s - 1)/2 when s is
+    // odd (counted twice), so each coarse plane is gathered once, at the even
+    // step that first needs it, and serves three fine planes.
+    auto bilin = [&](int k, int m) -> double {
+        const rsrc_t rk = line_rsrc(ec, (long)k * cplane, cplane, k >= 0 && k < nc);
+        return bload<double>(rk, cof[m][0]) + bload<double>(rk, cof[m][1]) +
+               bload<double>(rk, cof[m][2]) + bload<double>(rk, cof[m][3]);
     };
     // w of plane s at step s (s = z0-1 .. z1), outputs of plane s-1
     const int s0 = z0 - 1, s1 = z1;
@@ -2471,8 +2471,9 @@ k_adj_sweep3d(const double* __restrict__ ub, const double* __restrict__ r,
 #pragma unroll
         for (int m = 0; m < MU; ++m) pu[m] = ld_plane(ub, s0 + 2, ugb[m]);
     }
-    // per-step loads, one step ahead: r (MODE 0) or w (MODE 1) of plane s,
-    // ubar (MODE 1) and bbar of plane s - 1
+    // per-step loads, one step ahead: r (MODE 0) of plane s, or (MODE 1) at
+    // even s the in-plane interpolation of coarse plane s/2; ubar (MODE 1)
+    // and bbar of plane s - 1
     double nr[MW], nw[MW], nu[MW], nb[MW];
     auto issue = [&](int s) {
         const int p = s - 1;
@@ -2480,11 +2481,21 @@ k_adj_sweep3d(const double* __restrict__ ub, const double* __restrict__ r,
 #pragma unroll
         for (int m = 0; m < MW; ++m) {
             nr[m] = MODE == 0 ? ld_plane(r, s, sown && own[m] ? wgb[m] : kOob) : 0.0;
-            nw[m] = MODE == 1 ? interp(s, m) : 0.0;
+            if (MODE == 1 && (s & 1) == 0) nw[m] = bilin(s >> 1, m);
             nu[m] = MODE == 1 ? ld_plane(ub, p, pout && own[m] ? wgb[m] : kOob) : 0.0;
             nb[m] = ld_plane(bb, p, pout && own[m] ? wgb[m] : kOob);
         }
     };
+    // MODE 1: in-plane interpolations of the coarse planes below and above
+    // (or on) the current fine plane; before the first step, the coarse
+    // plane the first step needs besides the one it gathers itself
+    double bpre[MW], bcur[MW];
+#pragma unroll
+    for (int m = 0; m < MW; ++m) {
+        bpre[m] = 0.0;
+        nw[m] = 0.0;
+        bcur[m] = MODE == 1 ? bilin((s0 & 1) ? (s0 >> 1) : (s0 >> 1) - 1, m) : 0.0;
+    }
     issue(s0);
     double wm1[MW], wm2[MW];
 #pragma unroll
@@ -2498,7 +2509,15 @@ k_adj_sweep3d(const double* __restrict__ ub, const double* __restrict__ r,
 #pragma unroll
         for (int m = 0; m < MW; ++m) {
             rv[m] = nr[m];
-            ws[m] = nw[m];
+            if (MODE == 1) {
+                if ((s & 1) == 0) {
+                    bpre[m] = bcur[m];
+                    bcur[m] = nw[m];
+                    ws[m] = bpre[m] + bcur[m];
+                } else {
+                    ws[m] = bcur[m] + bcur[m];
+                }
+            }
             uo[m] = nu[m];
             bo[m] = nb[m];
         }
@@ -2654,14 +2673,12 @@ k_adj_sweep2d(const double* __restrict__ ub, const double* __restrict__ r,
     auto ld_row = [&](const double* f, int p, unsigned off) {
         return bload<double>(line_rsrc(f, (long)p * n, n, p >= 0 && p < n), off);
     };
-    // the four coarse values of a w node of row s, in the interpolation
-    // operator's order
-    auto interp = [&](int s, int m) -> double {
-        const int g = s + 1, ya = g / 2 - 1, yb = (g + 1) / 2 - 1;
-        const rsrc_t ra = line_rsrc(ec, (long)ya * nc, nc, ya >= 0 && ya < nc);
-        const rsrc_t rb = line_rsrc(ec, (long)yb * nc, nc, yb >= 0 && yb < nc);
-        return bload<double>(ra, cof[m][0]) + bload<double>(ra, cof[m][1]) +
-               bload<double>(rb, cof[m][0]) + bload<double>(rb, cof[m][1]);
+    // the x part of a w node's interpolation: the two coarse values of
+    // coarse row k around it; each coarse row is gathered once, at the even
+    // step that first needs it, and serves three fine rows (as in 3D)
+    auto lin = [&](int k, int m) -> double {
+        const rsrc_t rk = line_rsrc(ec, (long)k * nc, nc, k >= 0 && k < nc);
+        return bload<double>(rk, cof[m][0]) + bload<double>(rk, cof[m][1]);
     };
     const int s0 = z0 - 1, s1 = z1;
     double pu[MU];
@@ -2682,11 +2699,18 @@ k_adj_sweep2d(const double* __restrict__ ub, const double* __restrict__ r,
 #pragma unroll
         for (int m = 0; m < MW; ++m) {
             nr[m] = MODE == 0 ? ld_row(r, s, sown && own[m] ? wgb[m] : kOob) : 0.0;
-            nw[m] = MODE == 1 ? interp(s, m) : 0.0;
+            if (MODE == 1 && (s & 1) == 0) nw[m] = lin(s >> 1, m);
             nu[m] = MODE == 1 ? ld_row(ub, p, pout && own[m] ? wgb[m] : kOob) : 0.0;
             nb[m] = ld_row(bb, p, pout && own[m] ? wgb[m] : kOob);
         }
     };
+    double bpre[MW], bcur[MW];
+#pragma unroll
+    for (int m = 0; m < MW; ++m) {
+        bpre[m] = 0.0;
+        nw[m] = 0.0;
+        bcur[m] = MODE == 1 ? lin((s0 & 1) ? (s0 >> 1) : (s0 >> 1) - 1, m) : 0.0;
+    }
     issue(s0);
     double wm1[MW], wm2[MW];
 #pragma unroll
@@ -2700,7 +2724,15 @@ k_adj_sweep2d(const double* __restrict__ ub, const double* __restrict__ r,
 #pragma unroll
         for (int m = 0; m < MW; ++m) {
             rv[m] = nr[m];
-            ws[m] = nw[m];
+            if (MODE == 1) {
+                if ((s & 1) == 0) {
+                    bpre[m] = bcur[m];
+                    bcur[m] = nw[m];
+                    ws[m] = bpre[m] + bcur[m];
+                } else {
+                    ws[m] = bcur[m] + bcur[m];
+                }
+            }
             uo[m] = nu[m];
             bo[m] = nb[m];
         }
