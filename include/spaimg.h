@@ -69,7 +69,10 @@ extern "C" {
                                64 in 2D (32 for W(1,0) cycles), 16 in 3D      */
 #define MG_OPT_TIMING 5     /* 0 off; 1 time the fine level's fused
                                pre-smoother + restriction with HIP events;
-                               2 time every kernel of every level              */
+                               2 time every kernel of every level; 3 as 1,
+                               but only the second such launch of each
+                               mg_solve / mg_vcycle call (an event after a
+                               large kernel idles the GPU ~5 us)              */
 #define MG_OPT_INNER_CYCLES 6 /* low-precision V-cycles per FP64 refinement
                                step, 1..16; 0 = default (6 for FP32, 2 for
                                FP16)                                          */
@@ -199,7 +202,9 @@ int mg_vcycle_noalloc(int N, int d, const double* spai_coeffs, int n_coeffs, int
  * computes r = b - A u in FP64, scales it by a power of two s (so that
  * max |s r| < 1), runs MG_OPT_INNER_CYCLES low-precision V(1,1) cycles on
  * A e = s r (the first from zero) and updates u += e / s in FP64;
- * st->cycles counts refinement steps.  Synchronises `stream`.  Returns
+ * st->cycles counts refinement steps.  Synchronises `stream`; the calling
+ * thread busy-waits on one pinned host slot per cycle for the norm, which
+ * the GPU writes as soon as it is reduced (no event per cycle).  Returns
  * MG_ENOCONV (u = last iterate, st filled) if MG_OPT_MAX_CYCLES is reached,
  * MG_ENONFINITE if a norm is not finite.  st may be NULL. */
 int mg_solve(mg_handle_t h, const double* b, double* u, double tol, mg_stats* st,

@@ -74,7 +74,7 @@ struct mg_ctx {
     double* pmax = nullptr;      // per-block partial maxima
     double* dnorm = nullptr;     // device norms: 2 per slot (norm, max)
     double* dscale = nullptr;    // refinement scales per step
-    double* hnorm = nullptr;     // pinned host mirror of dnorm
+    double* hnorm = nullptr;     // coherent pinned host mirror of dnorm
     double* hnorm_dev = nullptr; // its device address
     // partial sums of a finished sweep waiting to be reduced: by the next
     // restriction of cycle() (block 0 of that launch), else by k_finalize
@@ -82,7 +82,6 @@ struct mg_ctx {
         int count = 0;           // partials in psum (0 = nothing pending)
         bool with_max = false;   // also reduce pmax into dnorm[2 slot + 1]
         int slot = -1;
-        hipEvent_t ready = nullptr;  // recorded once the host mirror is written
     } pend;
     int norm_slots = 0;
     // adjoint scratch (FP64), allocated on first use; per level
@@ -95,6 +94,7 @@ struct mg_ctx {
     long adj_poff = 0;           // next free slot
     // timing
     int timing = 0;
+    int call_fused = 0;          // fused fine-level launches of this call (mode 3)
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
     std::vector<TimedLaunch> pending;
@@ -281,7 +281,9 @@ int alloc_common(mg_ctx* h) {
     h->norm_slots = h->max_cycles + 4;
     HIPCHK(hipMalloc(&h->dnorm, 2 * h->norm_slots * sizeof(double)));
     HIPCHK(hipMalloc(&h->dscale, h->norm_slots * sizeof(double)));
-    HIPCHK(hipHostMalloc(&h->hnorm, 2 * h->norm_slots * sizeof(double), hipHostMallocDefault));
+    // coherent: the kernels' system-scope stores of norms reach the host
+    // directly, and the solve loops poll the slots (wait_norm)
+    HIPCHK(hipHostMalloc(&h->hnorm, 2 * h->norm_slots * sizeof(double), hipHostMallocCoherent));
     HIPCHK(hipHostGetDevicePointer(reinterpret_cast<void**>(&h->hnorm_dev), h->hnorm, 0));
     return MG_OK;
 }
@@ -303,14 +305,20 @@ int realloc_all(mg_ctx* h) {
 
 // ---- timing -------------------------------------------------------------
 
-bool timed(const mg_ctx* h, int kind, int level) {
+bool timed(mg_ctx* h, int kind, int level) {
     if (h->timing == 2) return true;
     // mode 1: the longest-running kernel of a cycle, the fine level's
     // pre-smoother fused with the restriction (and, in chained 2D solves,
-    // with the previous cycle's post-smoother): one event pair per cycle; a
-    // second pair for the post-smoother costs about 8 us per 3D cycle
-    return h->timing == 1 && level == 0 &&
-           (kind == MG_TIME_SMOOTH_RESTRICT || kind == MG_TIME_POST_PRE_RESTRICT);
+    // with the previous cycle's post-smoother): one event pair per cycle.
+    // Mode 3: one of them per call, the second (the first runs right after
+    // the caller wrote u, a cache state no later cycle sees).  An event
+    // recorded after a large kernel idles the GPU for ~5 us while the
+    // caches are written back, so mode 1 costs ~4% of a solve, mode 3 ~0.4%.
+    const bool fused = level == 0 && (kind == MG_TIME_SMOOTH_RESTRICT ||
+                                      kind == MG_TIME_POST_PRE_RESTRICT);
+    if (!fused) return false;
+    if (h->timing == 1) return true;
+    return h->timing == 3 && h->call_fused++ == 1;
 }
 
 int time_begin(mg_ctx* h, int kind, int level, hipStream_t st, TimedLaunch* tl) {
@@ -395,7 +403,6 @@ int run_tail(mg_ctx* h, Hier& H, int l, const void* b, void* e, hipStream_t st,
 // Where the pre-smoother's residual norm goes (fine FP64 level only).
 struct NormReq {
     int slot = -1;                  // dnorm slot, -1 = none
-    hipEvent_t ready = nullptr;     // recorded after the copy to the host
 };
 
 // A 3D hierarchy with the 19-/27-point smoother (nonzero edge or corner
@@ -488,10 +495,8 @@ int cycle(mg_ctx* h, Hier& H, int l, const void* u_in, const void* b, void* out,
                                         static_cast<const double*>(u_in),
                                         static_cast<const double*>(b), (double)h->N * h->N,
                                         h->psum, h->pmax, kPartialCap * h->batch, st, &nparts));
-            HIPCHK(launch_finalize(h->psum, nullptr, nparts, h->dnorm + 2 * nr.slot, st));
-            HIPCHK(hipMemcpyAsync(h->hnorm + 2 * nr.slot, h->dnorm + 2 * nr.slot,
-                                  sizeof(double), hipMemcpyDeviceToHost, st));
-            if (nr.ready) HIPCHK(hipEventRecord(nr.ready, st));
+            HIPCHK(launch_finalize(h->psum, nullptr, nparts, h->dnorm + 2 * nr.slot, st,
+                                   h->hnorm_dev + 2 * nr.slot));
         }
         return run_tail(h, H, l, b, out, st, wcycle ? 1 : 0);
     }
@@ -521,7 +526,6 @@ int cycle(mg_ctx* h, Hier& H, int l, const void* u_in, const void* b, void* out,
         rc = run_timed(h, MG_TIME_ZERO_SMOOTH_RESTRICT, l, st,
                        [&] { return launch_zero_smooth_restrict(H.p, s, st); });
         if (rc) return rc;
-        if (pz.count > 0 && pz.ready) HIPCHK(hipEventRecord(pz.ready, st));
         s.out_c = nullptr;
         s.fin_ps = s.fin_pm = nullptr;
         s.fin_count = 0;
@@ -541,7 +545,6 @@ int cycle(mg_ctx* h, Hier& H, int l, const void* u_in, const void* b, void* out,
                 h->pend.count = nparts;
                 h->pend.with_max = false;
                 h->pend.slot = nr.slot;
-                h->pend.ready = nr.ready;
             }
             s.out_c = nullptr;
             if (part == kPreOnly) return MG_OK;
@@ -557,7 +560,6 @@ int cycle(mg_ctx* h, Hier& H, int l, const void* u_in, const void* b, void* out,
             h->pend.count = nparts;
             h->pend.with_max = false;
             h->pend.slot = nr.slot;
-            h->pend.ready = nr.ready;
         }
         if (part == kPreOnly) return MG_OK;
     }
@@ -576,7 +578,6 @@ int cycle(mg_ctx* h, Hier& H, int l, const void* u_in, const void* b, void* out,
     }
     rc = run_timed(h, MG_TIME_RESTRICT, l, st, [&] { return launch_restrict(H.p, s, st); });
     if (rc) return rc;
-    if (pn.count > 0 && pn.ready) HIPCHK(hipEventRecord(pn.ready, st));
     s.fin_ps = s.fin_pm = nullptr;
     s.fin_count = 0;
     s.fin_dev = s.fin_host = nullptr;
@@ -590,22 +591,17 @@ int flush_pending_norm(mg_ctx* h, hipStream_t st) {
     if (pn.count == 0) return MG_OK;
     h->pend = mg_ctx::PendingNorm();
     HIPCHK(launch_finalize(h->psum, pn.with_max ? h->pmax : nullptr, pn.count,
-                           h->dnorm + 2 * pn.slot, st));
-    HIPCHK(hipMemcpyAsync(h->hnorm + 2 * pn.slot, h->dnorm + 2 * pn.slot, sizeof(double),
-                          hipMemcpyDeviceToHost, st));
-    if (pn.ready) HIPCHK(hipEventRecord(pn.ready, st));
+                           h->dnorm + 2 * pn.slot, st, h->hnorm_dev + 2 * pn.slot));
     return MG_OK;
 }
 
 // One FP64 V(1,1) cycle on the finest grid: u_out = V(u_in, b).  With
 // norm_slot >= 0 the pre-smoother also produces ||b - A u_in||_2 into
-// dnorm[2 slot] and starts its copy to the pinned host mirror.
+// dnorm[2 slot] and the host mirror (arm the slot first to poll it).
 int fine_cycle64(mg_ctx* h, const double* b, const double* u_in, double* u_out,
-                 int norm_slot, hipStream_t st, hipEvent_t norm_ready = nullptr,
-                 CyclePart part = kWhole) {
+                 int norm_slot, hipStream_t st, CyclePart part = kWhole) {
     NormReq nr;
     nr.slot = norm_slot;
-    nr.ready = norm_ready;
     const int rc = cycle(h, h->h64, 0, u_in, b, u_out, h->h64.t[0], nr, st, part);
     if (rc) return rc;
     return flush_pending_norm(h, st);
@@ -644,10 +640,45 @@ int enqueue_bnorm(mg_ctx* h, const double* b, hipStream_t st) {
     int np = 0;
     const int sl = bnorm_slot(h);
     HIPCHK(launch_sumsq(b, level_pts(h, 0) * h->batch, h->psum, kPartialCap * h->batch, st, &np));
-    HIPCHK(launch_finalize(h->psum, nullptr, np, h->dnorm + 2 * sl, st));
-    HIPCHK(hipMemcpyAsync(h->hnorm + 2 * sl, h->dnorm + 2 * sl, sizeof(double),
-                          hipMemcpyDeviceToHost, st));
+    HIPCHK(launch_finalize(h->psum, nullptr, np, h->dnorm + 2 * sl, st, h->hnorm_dev + 2 * sl));
     return MG_OK;
+}
+
+// Host hand-off of the per-cycle norms: the kernel that reduces a norm
+// stores it into the coherent host mirror with a system-scope store, so the
+// host reads it as soon as that workgroup has run, with no event (an event
+// after a large kernel idles the GPU ~5 us while the caches are written
+// back).  A slot is armed with a value no norm takes before the work that
+// fills it is enqueued; wait_norm polls it and, should the stream drain or
+// fail first, stops with an error instead of spinning on.
+constexpr double kNormPending = -1.0;
+
+void arm_norm(mg_ctx* h, int slot) {
+    reinterpret_cast<volatile double*>(h->hnorm)[2 * slot] = kNormPending;
+}
+
+int wait_norm(mg_ctx* h, int slot, hipStream_t st, double* out) {
+    const volatile double* p = h->hnorm + 2 * slot;
+    for (long it = 1;; ++it) {
+        const double v = *p;
+        if (!(v == kNormPending)) {  // a NaN norm ends the wait as well
+            *out = v;
+            return MG_OK;
+        }
+        if ((it & 255) == 0) {
+            const hipError_t e = hipStreamQuery(st);
+            if (e == hipSuccess) {
+                const double w = *p;
+                if (w == kNormPending)
+                    return fail(MG_EHIP, "norm slot " + std::to_string(slot) +
+                                             " not written by the stream's kernels");
+                *out = w;
+                return MG_OK;
+            }
+            if (e != hipErrorNotReady)
+                return fail(MG_EHIP, std::string("hipStreamQuery: ") + hipGetErrorString(e));
+        }
+    }
 }
 
 // Checks the problem arguments of mg_setup and mg_vcycle_noalloc.
@@ -822,7 +853,7 @@ int mg_set_option(mg_handle_t h, int key, double value) {
             return MG_OK;
         }
         case MG_OPT_TIMING:
-            if (v < 0 || v > 2) return fail(MG_EINVAL, "timing must be 0, 1 or 2");
+            if (v < 0 || v > 3) return fail(MG_EINVAL, "timing must be 0, 1, 2 or 3");
             h->timing = v;
             return MG_OK;
         case MG_OPT_INNER_CYCLES:
@@ -848,6 +879,7 @@ int mg_vcycle(mg_handle_t h, const double* b, double* u, void* stream) {
     // u is updated in place: the post-smoother reads the internal iterate
     // and writes u, and the pre-smoother never writes u
     h->pend = mg_ctx::PendingNorm();
+    h->call_fused = 0;
     return fine_cycle64(h, b, u, u, -1, st);
 }
 
@@ -1076,15 +1108,9 @@ static int solve64_chain(mg_ctx* h, const double* b, double* u, double tol, mg_s
     std::vector<double> hist;
     double r0 = 0.0, rk = 0.0;
     int k = 0, code = MG_OK, run = 0;
-    hipEvent_t evn;
-    HIPCHK(hipEventCreateWithFlags(&evn, hipEventDisableTiming));
-    auto done = [&](int rc) {
-        (void)hipEventDestroy(evn);
-        return rc;
-    };
     if (st_out) {
         const int rb = enqueue_bnorm(h, b, st);
-        if (rb) return done(rb);
+        if (rb) return rb;
     }
     Sweep s = make_sweep(h, H, 0);
     double sA, sW, pf;
@@ -1098,7 +1124,6 @@ static int solve64_chain(mg_ctx* h, const double* b, double* u, double tol, mg_s
         h->pend.count = nparts;
         h->pend.with_max = false;
         h->pend.slot = slot;
-        h->pend.ready = evn;
     };
     // the coarse part of a cycle (its first restriction-type kernel reduces
     // the pending norm), or only the norm's reduction
@@ -1110,21 +1135,21 @@ static int solve64_chain(mg_ctx* h, const double* b, double* u, double tol, mg_s
     // cycle 0: pre-smoother and restriction, with ||r_0||
     s.u = u;
     s.out = tcur;
+    arm_norm(h, 0);
     rc = run_timed(h, MG_TIME_SMOOTH_RESTRICT, 0, st,
                    [&] { return launch_smooth_restrict(P64, true, s, st, &nparts); });
-    if (rc) return done(rc);
+    if (rc) return rc;
     pend(0);
     run = 1;
     bool gate = false;
     rc = coarse();
-    if (rc) return done(rc);
+    if (rc) return rc;
     for (k = 0;; ++k) {
         // u_k is in u; the pre-smoothed iterate of cycle k in tcur, its
         // coarse problem enqueued unless gated
-        hipError_t e = hipEventSynchronize(evn);
-        if (e != hipSuccess)
-            return done(fail(MG_EHIP, std::string("hipEventSynchronize: ") + hipGetErrorString(e)));
-        const double nk = h->hnorm[2 * k];
+        double nk;
+        rc = wait_norm(h, k, st, &nk);
+        if (rc) return rc;
         if (!std::isfinite(nk)) {
             code = MG_ENONFINITE;
             rk = nk;
@@ -1140,7 +1165,7 @@ static int solve64_chain(mg_ctx* h, const double* b, double* u, double tol, mg_s
         }
         if (gate) {
             rc = cycle(h, H, 1, nullptr, H.b[1], H.e[1], H.t[1], NormReq(), st);
-            if (rc) return done(rc);
+            if (rc) return rc;
         }
         // post-smoother of cycle k with the coarse correction, then the
         // pre-smoother and restriction of cycle k + 1, with ||r_{k+1}||
@@ -1149,9 +1174,10 @@ static int solve64_chain(mg_ctx* h, const double* b, double* u, double tol, mg_s
         s.pf = pf;
         s.out = u;
         s.out_t = tnext;
+        arm_norm(h, k + 1);
         rc = run_timed(h, MG_TIME_POST_PRE_RESTRICT, 0, st,
                        [&] { return launch_post_pre_restrict(P64, true, s, st, &nparts); });
-        if (rc) return done(rc);
+        if (rc) return rc;
         pend(k + 1);
         ++run;
         std::swap(tcur, tnext);
@@ -1159,9 +1185,8 @@ static int solve64_chain(mg_ctx* h, const double* b, double* u, double tol, mg_s
         // before its coarse part
         gate = predict_final(hist, tol, r0);
         rc = gate ? flush_pending_norm(h, st) : coarse();
-        if (rc) return done(rc);
+        if (rc) return rc;
     }
-    (void)hipEventDestroy(evn);
     HIPCHK(hipEventRecord(h->ev1, st));
     HIPCHK(hipStreamSynchronize(st));
     rc = time_collect(h);
@@ -1199,8 +1224,6 @@ static int solve64(mg_ctx* h, const double* b, double* u, double tol, mg_stats* 
         const int rb = enqueue_bnorm(h, b, st);
         if (rb) return rb;
     }
-    hipEvent_t evn;
-    HIPCHK(hipEventCreateWithFlags(&evn, hipEventDisableTiming));
     for (k = 0;; ++k) {
         // cycle k reads u_k from X and writes u_{k+1} to Y; its pre-smoother
         // also yields ||r_k||.  The host waits only for that norm while the
@@ -1225,29 +1248,17 @@ static int solve64(mg_ctx* h, const double* b, double* u, double tol, mg_stats* 
                 inplace = !lands_in_u;
             }
         }
-        int rc = fine_cycle64(h, b, X, inplace ? X : Y, k, st, evn,
-                              gate ? kPreOnly : kWhole);
-        if (rc) {
-            (void)hipEventDestroy(evn);
-            return rc;
-        }
+        arm_norm(h, k);
+        int rc = fine_cycle64(h, b, X, inplace ? X : Y, k, st, gate ? kPreOnly : kWhole);
+        if (rc) return rc;
         ++run;
-        hipError_t e = hipEventSynchronize(evn);
-        if (e == hipSuccess && gate) {
-            const double ng = h->hnorm[2 * k];
-            if (std::isfinite(ng) && ng > tol * r0 && k < h->max_cycles) {
-                rc = fine_cycle64(h, b, X, Y, k, st, nullptr, kRest);
-                if (rc) {
-                    (void)hipEventDestroy(evn);
-                    return rc;
-                }
-            }
+        double nk;
+        rc = wait_norm(h, k, st, &nk);
+        if (rc) return rc;
+        if (gate && std::isfinite(nk) && nk > tol * r0 && k < h->max_cycles) {
+            rc = fine_cycle64(h, b, X, Y, -1, st, kRest);
+            if (rc) return rc;
         }
-        if (e != hipSuccess) {
-            (void)hipEventDestroy(evn);
-            return fail(MG_EHIP, std::string("hipEventSynchronize: ") + hipGetErrorString(e));
-        }
-        const double nk = h->hnorm[2 * k];
         if (!std::isfinite(nk)) {
             code = MG_ENONFINITE;
             rk = nk;
@@ -1285,7 +1296,6 @@ static int solve64(mg_ctx* h, const double* b, double* u, double tol, mg_stats* 
         else
             std::swap(X, Y);
     }
-    (void)hipEventDestroy(evn);
     // u_k is in X
     if (X != u) HIPCHK(hipMemcpyAsync(u, X, fine, hipMemcpyDeviceToDevice, st));
     HIPCHK(hipEventRecord(h->ev1, st));
@@ -1343,8 +1353,6 @@ static int solve_ir(mg_ctx* h, const double* b, double* u, double tol, mg_stats*
     int k = 0, code = MG_OK, run = 0;
     double pred = -1.0;   // predicted ||r_k|| (< 0: no prediction)
     int m_prev = 0;       // inner cycles of the previous step
-    hipEvent_t evn;
-    HIPCHK(hipEventCreateWithFlags(&evn, hipEventDisableTiming));
     for (k = 0;; ++k) {
         const int slot = 1 + k;   // k <= max_cycles < norm_slots - 2
         const int pslot = k;
@@ -1365,6 +1373,7 @@ static int solve_ir(mg_ctx* h, const double* b, double* u, double tol, mg_stats*
         s.psum = h->psum;
         s.pmax = h->pmax;
         s.partials_cap = kPartialCap * h->batch;
+        arm_norm(h, slot);
         rc = run_timed(h, MG_TIME_IR_STEP, 0, st,
                        [&] { return launch_ir_step(H.p, s, st, &nparts); });
         if (rc) return rc;
@@ -1373,7 +1382,6 @@ static int solve_ir(mg_ctx* h, const double* b, double* u, double tol, mg_stats*
         h->pend.count = nparts;
         h->pend.with_max = true;
         h->pend.slot = slot;
-        h->pend.ready = evn;
         // inner low-precision cycles on A e = s r: the first from zero, the
         // others continue from the current e.  The host reads ||r_k|| while
         // the first inner cycle runs and enqueues the others only if the
@@ -1388,8 +1396,9 @@ static int solve_ir(mg_ctx* h, const double* b, double* u, double tol, mg_stats*
         rc = flush_pending_norm(h, st);
         if (rc) return rc;
         ++run;
-        HIPCHK(hipEventSynchronize(evn));
-        const double nk = h->hnorm[2 * slot];
+        double nk;
+        rc = wait_norm(h, slot, st, &nk);
+        if (rc) return rc;
         if (!std::isfinite(nk)) {
             code = MG_ENONFINITE;
             rk = nk;
@@ -1427,7 +1436,6 @@ static int solve_ir(mg_ctx* h, const double* b, double* u, double tol, mg_stats*
     if (uk != u) HIPCHK(hipMemcpyAsync(u, uk, fine, hipMemcpyDeviceToDevice, st));
     HIPCHK(hipEventRecord(h->ev1, st));
     HIPCHK(hipStreamSynchronize(st));
-    (void)hipEventDestroy(evn);
     rc = time_collect(h);
     if (rc) return rc;
     if (st_out) {
@@ -1455,6 +1463,7 @@ int mg_solve(mg_handle_t h, const double* b, double* u, double tol, mg_stats* st
     if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(MG_EINVAL, "tol must be finite and >= 0");
     hipStream_t s = (hipStream_t)stream;
     h->pend = mg_ctx::PendingNorm();  // nothing survives a failed call
+    h->call_fused = 0;
     if (h->prec == MG_PREC_FP64) return solve64(h, b, u, tol, st, s);
     return solve_ir(h, b, u, tol, st, s);
 }

@@ -100,9 +100,10 @@ hipError_t launch_tail(Prec p, const Tail& t, hipStream_t st);
 size_t tail_lds_bytes(Prec p, int d, int nt);
 
 // Deterministic norm finalisation: out[0] = sqrt(sum partials) (fixed order),
-// out[1] = max of the max-partials (if maxparts != nullptr).
+// out[1] = max of the max-partials (if maxparts != nullptr); the norm also
+// goes to `host` (device address of a coherent pinned mirror) if given.
 hipError_t launch_finalize(const double* partials, const double* maxparts,
-                           int count, double* out, hipStream_t st);
+                           int count, double* out, hipStream_t st, double* host = nullptr);
 
 // Per-block partial sums of v^2 over count doubles (fixed order).
 hipError_t launch_sumsq(const double* v, long count, double* partials, long partials_cap,

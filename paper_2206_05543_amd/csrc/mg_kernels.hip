@@ -171,6 +171,13 @@ __device__ __forceinline__ double block_max(double v, double* red) {
     return s;
 }
 
+// The host mirror of a norm lives in coherent (fine-grained) pinned memory:
+// a system-scope store reaches the host without a cache flush, and the host
+// polls the slot for it instead of waiting for the stream.
+__device__ __forceinline__ void store_host_norm(double* host, double v) {
+    __hip_atomic_store(host, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 // Norm of a finished sweep from its per-block partials, in a fixed order
 // (deterministic run to run): (sqrt(sum ps), max pm) to dev, sqrt(sum ps)
 // to the pinned host mirror `host`.  Run by one whole workgroup of the
@@ -190,10 +197,7 @@ __device__ void finalize_norm(const double* ps, const double* pm, int count, dou
         const double nrm = sqrt(tot);
         dev[0] = nrm;
         if (pm) dev[1] = tmx;
-        if (host) {
-            host[0] = nrm;
-            __threadfence_system();
-        }
+        if (host) store_host_norm(host, nrm);
     }
 }
 
@@ -3213,7 +3217,7 @@ k_tail(const S* __restrict__ bt, S* __restrict__ et, int nt, C c0, C c1, C c2, C
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256)
 k_finalize(const double* __restrict__ ps, const double* __restrict__ pm, int count,
-           double* __restrict__ out) {
+           double* __restrict__ out, double* __restrict__ host) {
     __shared__ double red[4];
     double s = 0.0, mx = 0.0;
     for (int i = threadIdx.x; i < count; i += 256) {
@@ -3224,8 +3228,10 @@ k_finalize(const double* __restrict__ ps, const double* __restrict__ pm, int cou
     __syncthreads();
     const double tmx = block_max<256>(mx, red);
     if (threadIdx.x == 0) {
-        out[0] = sqrt(tot);
+        const double nrm = sqrt(tot);
+        out[0] = nrm;
         if (pm) out[1] = tmx;
+        if (host) store_host_norm(host, nrm);
     }
 }
 
@@ -4155,8 +4161,9 @@ hipError_t launch_adj_sweep(int d, int n, int batch, int mode, const double* uba
 }
 
 hipError_t launch_finalize(const double* partials, const double* maxparts, int count,
-                           double* out, hipStream_t st) {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, partials, maxparts, count, out);
+                           double* out, hipStream_t st, double* host) {
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, partials, maxparts, count, out,
+                       host);
     return hipGetLastError();
 }
 

@@ -9,6 +9,8 @@
   handle then solves a clean problem as a fresh one does.
 - Option values that are not integers, not finite or out of range are
   rejected on the host.
+- Sampled timing (MG_OPT_TIMING = 3) times exactly one fused fine-level
+  launch per solve and leaves the solve's result bit for bit unchanged.
 - Checkpoints written by the library: FP64 copies exactly, FP32 rounds to
   nearest even and leaves the rounded value in the iterate.
 """
@@ -150,15 +152,42 @@ def test_non_finite_rhs_then_clean_solve(d, N, bad, prec):
 
 def test_option_values_are_checked():
     need_gpu()
-    from paper_2206_05543_amd._lib import OPT_BATCH, OPT_MAX_CYCLES
+    from paper_2206_05543_amd._lib import OPT_BATCH, OPT_MAX_CYCLES, OPT_TIMING
     with make_mg(16, 2, M9) as mg:
         for key, v in [(OPT_BATCH, float("nan")), (OPT_BATCH, float("inf")),
                        (OPT_MAX_CYCLES, -float("inf")), (OPT_BATCH, 1e12),
-                       (OPT_MAX_CYCLES, 2.5), (OPT_BATCH, 0.0), (999, 1.0)]:
+                       (OPT_MAX_CYCLES, 2.5), (OPT_BATCH, 0.0), (999, 1.0),
+                       (OPT_TIMING, 4.0), (OPT_TIMING, -1.0)]:
             with pytest.raises(MGError) as ei:
                 mg.set_option(key, v)
             assert ei.value.code == MG_EINVAL
         mg.set_option(OPT_MAX_CYCLES, 7.0)  # an integer-valued double is fine
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_sampled_timing(d):
+    # 2D solves chain the cycles: the one timed launch is the second fused
+    # kernel, the first chained post + pre-smoother; 3D: the second cycle's
+    # fused pre-smoother (both run on n = 255, where the 3D one is fused)
+    need_gpu()
+    N = 256
+    p = poisson_problem(d, N, seed=81, n_modes=8, kmax=N // 4)
+    say("sampled timing", d)
+    out = []
+    for timing in (0, 3):
+        with make_mg(N, d, _c(d), timing=timing) as mg:
+            for _ in range(2):
+                u = dev(p["u0"])
+                st = mg.solve(dev(p["b"]), u, tol=1e-10)
+            out.append(host(u))
+            if timing:
+                _, n_sr = mg.timing("smooth_restrict", 0)
+                _, n_ppr = mg.timing("post_pre_restrict", 0)
+                assert (n_sr, n_ppr) == ((0, 2) if d == 2 else (2, 0))
+                for lev in range(1, mg.num_levels):
+                    assert mg.timing("smooth", lev)[1] == 0
+    assert st["code"] == 0
+    assert np.array_equal(out[0], out[1])
 
 
 @pytest.mark.parametrize("d,N,batch", [(2, 64, 2), (3, 32, 1)])
