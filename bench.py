@@ -150,6 +150,8 @@ def parse():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-examples", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    # only the gradient workloads' forward/backward timing (for kernel traces)
+    ap.add_argument("--adjoint-only", action="store_true")
     ap.add_argument("--workloads", default="poisson2d_n4096,poisson3d_n256")
     ap.add_argument("--tol", type=float, default=1e-10)
     return ap.parse_args()
@@ -168,6 +170,9 @@ def main():
     from paper_2206_05543_amd.workloads import workload
 
     torch.cuda.init()
+    if a.adjoint_only:
+        print(json.dumps({"adjoint": adjoint()}), flush=True)
+        return
     stream = torch.cuda.current_stream()
     names = [w for w in a.workloads.split(",") if w]
     probs = {}

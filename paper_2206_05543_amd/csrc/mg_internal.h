@@ -6,6 +6,15 @@
 
 namespace spaimg {
 
+// Event pair in which the next kernel launched by this thread records its own
+// start and end (hipExtLaunchKernelGGL: the dispatch's timestamps, with no
+// extra command on the stream, so the interval is the kernel alone); the
+// launch consumes it.  Null events: an ordinary launch.
+struct LaunchEvents {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+LaunchEvents& launch_events();
+
 // Storage precision of a level hierarchy.  FP64 computes in double; FP32 and
 // FP16 (storage) compute in float.
 enum Prec : int { P64 = 0, P32 = 1, P16 = 2 };

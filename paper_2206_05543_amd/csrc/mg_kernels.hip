@@ -19,13 +19,35 @@
 // receives a contiguous range of tiles, so halo reloads of neighbouring
 // tiles hit the same L2.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <algorithm>
 
 #include "mg_internal.h"
 
 namespace spaimg {
+
+LaunchEvents& launch_events() {
+    static thread_local LaunchEvents ev;
+    return ev;
+}
+
 namespace {
+
+// Every kernel of this file is launched here: with the thread's pending
+// event pair (launch_events) the launch records the kernel's own start and
+// end in it, otherwise it is an ordinary launch.
+template <typename K, typename... A>
+void mg_launch(K kernel, dim3 grid, dim3 block, unsigned lds, hipStream_t st, A... args) {
+    LaunchEvents& ev = launch_events();
+    if (ev.start) {
+        const LaunchEvents e = ev;
+        ev = LaunchEvents();
+        hipExtLaunchKernelGGL(kernel, grid, block, lds, st, e.start, e.stop, 0u, args...);
+    } else {
+        hipLaunchKernelGGL(kernel, grid, block, lds, st, args...);
+    }
+}
 
 constexpr int kXCD = 8;
 
@@ -3591,11 +3613,11 @@ hipError_t launch_smooth3d(bool zg, bool norm, const Sweep& s, int want, int min
     if (norm && (long)grid.x * grid.y > s.partials_cap) return hipErrorInvalidValue;
     constexpr int PDC = UN % 3 == 0 ? 2 : 1;  // deeper prefetch for the fused correction
 #define L3(PD, ZG, NM, PR, WD)                                                                 \
-    hipLaunchKernelGGL((k_smooth3d<S, C, TX, TY, NT, PD, UN, ZG, NM, PR, NTS, WD>), grid,       \
+    mg_launch((k_smooth3d<S, C, TX, TY, NT, PD, UN, ZG, NM, PR, NTS, WD>), grid,       \
                        dim3(NT), 0, st, u, b, out, n, tx, ty, zc, nch, sA, sW, c0, c1,         \
-                       s.partials, ec, nc, pf, c2, c3)
+                       s.partials, ec, nc, pf, c2, c3, static_cast<S*>(nullptr))
 #define L3R(PD, PR, WD)                                                                        \
-    hipLaunchKernelGGL((k_smooth3d<S, C, TX, TY, NT, PD, UN, false, false, PR, NTS, WD, true>), \
+    mg_launch((k_smooth3d<S, C, TX, TY, NT, PD, UN, false, false, PR, NTS, WD, true>), \
                        grid, dim3(NT), 0, st, u, b, out, n, tx, ty, zc, nch, sA, sW, c0, c1,  \
                        s.partials, ec, nc, pf, c2, c3, static_cast<S*>(s.rout))
     if constexpr (sizeof(S) == 8) {
@@ -3643,17 +3665,18 @@ hipError_t launch_smooth2d(bool zg, bool norm, const Sweep& s, int want, int min
     if (nparts) *nparts = grid.x * grid.y;
     if (norm && (long)grid.x * grid.y > s.partials_cap) return hipErrorInvalidValue;
 #define L2(ZG, NM, PR)                                                                      \
-    hipLaunchKernelGGL((k_smooth2d<S, C, TX, NT, 1, UN, ZG, NM, PR, NTS>), grid, dim3(NT), 0, \
-                       st, u, b, out, n, tx, yc, nch, sA, sW, c0, c1, c2, s.partials, ec, nc, pf)
+    mg_launch((k_smooth2d<S, C, TX, NT, 1, UN, ZG, NM, PR, NTS>), grid, dim3(NT), 0, \
+                       st, u, b, out, n, tx, yc, nch, sA, sW, c0, c1, c2, s.partials, ec, nc, pf, \
+                       static_cast<S*>(nullptr))
     if constexpr (sizeof(S) == 8) {
         if (s.rout) {  // residual side output (from a guess, or with the correction)
             if (zg || norm) return hipErrorInvalidValue;
             if (pro)
-                hipLaunchKernelGGL((k_smooth2d<S, C, TX, NT, 1, UN, false, false, true, NTS, true>),
+                mg_launch((k_smooth2d<S, C, TX, NT, 1, UN, false, false, true, NTS, true>),
                                    grid, dim3(NT), 0, st, u, b, out, n, tx, yc, nch, sA, sW, c0,
                                    c1, c2, s.partials, ec, nc, pf, static_cast<S*>(s.rout));
             else
-                hipLaunchKernelGGL((k_smooth2d<S, C, TX, NT, 1, UN, false, false, false, NTS, true>),
+                mg_launch((k_smooth2d<S, C, TX, NT, 1, UN, false, false, false, NTS, true>),
                                    grid, dim3(NT), 0, st, u, b, out, n, tx, yc, nch, sA, sW, c0,
                                    c1, c2, s.partials, ec, nc, pf, static_cast<S*>(s.rout));
             return hipGetLastError();
@@ -3702,7 +3725,7 @@ hipError_t launch_restrict3d(const Sweep& s, int want, int minc, hipStream_t st)
     const int zc = pick_chunk(nc, tx * ty, want, minc);
     const int nch = cdiv(nc, zc);
     dim3 grid(tx * ty * nch, s.batch);
-    hipLaunchKernelGGL((k_restrict3d<S, C, TXc, TYc, NT, UN>), grid, dim3(NT), 0, st,
+    mg_launch((k_restrict3d<S, C, TXc, TYc, NT, UN>), grid, dim3(NT), 0, st,
                        static_cast<const S*>(s.u), static_cast<const S*>(s.b),
                        static_cast<S*>(s.out), n, nc, tx, ty, zc, nch, C(s.sA), s.fin_ps,
                        s.fin_pm, s.fin_count, s.fin_dev, s.fin_host);
@@ -3716,7 +3739,7 @@ hipError_t launch_restrict2d(const Sweep& s, int want, int minc, hipStream_t st)
     const int yc = pick_chunk(nc, tx, want, minc);
     const int nch = cdiv(nc, yc);
     dim3 grid(tx * nch, s.batch);
-    hipLaunchKernelGGL((k_restrict2d<S, C, TXc, NT, UN>), grid, dim3(NT), 0, st,
+    mg_launch((k_restrict2d<S, C, TXc, NT, UN>), grid, dim3(NT), 0, st,
                        static_cast<const S*>(s.u), static_cast<const S*>(s.b),
                        static_cast<S*>(s.out), n, nc, tx, yc, nch, C(s.sA), s.fin_ps,
                        s.fin_pm, s.fin_count, s.fin_dev, s.fin_host);
@@ -3744,11 +3767,11 @@ hipError_t prolong_impl(int d, int n, int batch, const void* ec, const void* in,
     const long pts = d == 3 ? (long)n * n * n : (long)n * n;
     dim3 grid(cdiv(pts, 256), batch);
     if (d == 3)
-        hipLaunchKernelGGL((k_prolong3d<S, C>), grid, dim3(256), 0, st,
+        mg_launch((k_prolong3d<S, C>), grid, dim3(256), 0, st,
                            static_cast<const S*>(ec), static_cast<const S*>(in),
                            static_cast<S*>(out), n, nc, C(pf));
     else
-        hipLaunchKernelGGL((k_prolong2d<S, C>), grid, dim3(256), 0, st,
+        mg_launch((k_prolong2d<S, C>), grid, dim3(256), 0, st,
                            static_cast<const S*>(ec), static_cast<const S*>(in),
                            static_cast<S*>(out), n, nc, C(pf));
     return hipGetLastError();
@@ -3768,12 +3791,12 @@ hipError_t tail_impl_d(const Tail& t, size_t lds, hipStream_t st) {
         attr_set = true;
     }
     if (t.wvisits > 0)
-        hipLaunchKernelGGL((k_tail<S, C, D, true>), dim3(t.batch), dim3(1024), lds, st,
+        mg_launch((k_tail<S, C, D, true>), dim3(t.batch), dim3(1024), lds, st,
                            static_cast<const S*>(t.b), static_cast<S*>(t.e), t.nt, C(t.c[0]),
                            C(t.c[1]), C(t.c[2]), C(t.c[3]), t.ginv, t.scaled ? 1 : 0, t.N_top,
                            t.wvisits);
     else
-        hipLaunchKernelGGL((k_tail<S, C, D, false>), dim3(t.batch), dim3(1024), lds, st,
+        mg_launch((k_tail<S, C, D, false>), dim3(t.batch), dim3(1024), lds, st,
                            static_cast<const S*>(t.b), static_cast<S*>(t.e), t.nt, C(t.c[0]),
                            C(t.c[1]), C(t.c[2]), C(t.c[3]), t.ginv, t.scaled ? 1 : 0, t.N_top, 0);
     return hipGetLastError();
@@ -3807,7 +3830,7 @@ hipError_t ir_impl(const IRStep& s, hipStream_t st, int* nparts) {
         dim3 grid(tx * ty * nch, s.batch);                                                     \
         if (nparts) *nparts = grid.x * grid.y;                                                 \
         if ((long)grid.x * grid.y > s.partials_cap) return hipErrorInvalidValue;               \
-        hipLaunchKernelGGL((k_ir3d<S, TX, TY, NT, UN, NTS, RES>), grid, dim3(NT), 0, st, s.u, s.unew, \
+        mg_launch((k_ir3d<S, TX, TY, NT, UN, NTS, RES>), grid, dim3(NT), 0, st, s.u, s.unew, \
                            e, s.b, rlo, n, tx, ty, zc, nch, s.inv_h2, s.sigma0, s.k, s.scales,  \
                            s.maxprev, s.psum, s.pmax);                                          \
     } while (0)
@@ -3819,7 +3842,7 @@ hipError_t ir_impl(const IRStep& s, hipStream_t st, int* nparts) {
         dim3 grid(tx * nch, s.batch);                                                          \
         if (nparts) *nparts = grid.x * grid.y;                                                 \
         if ((long)grid.x * grid.y > s.partials_cap) return hipErrorInvalidValue;               \
-        hipLaunchKernelGGL((k_ir2d<S, TX, NT, UN, NTS, RES>), grid, dim3(NT), 0, st, s.u, s.unew, e, \
+        mg_launch((k_ir2d<S, TX, NT, UN, NTS, RES>), grid, dim3(NT), 0, st, s.u, s.unew, e, \
                            s.b, rlo, n, tx, yc, nch, s.inv_h2, s.sigma0, s.k, s.scales,         \
                            s.maxprev, s.psum, s.pmax);                                          \
     } while (0)
@@ -3870,7 +3893,7 @@ hipError_t launch_zrestrict3d(const Sweep& s, int want, int minc, hipStream_t st
     const int tx = cdiv(nc, TXc), ty = cdiv(nc, TYc);
     const int zc = pick_chunk(nc, tx * ty, want, minc);
     const int nch = cdiv(nc, zc);
-    hipLaunchKernelGGL((k_zrestrict3d<S, C, TXc, TYc, NT, 12>), dim3(tx * ty * nch, s.batch),
+    mg_launch((k_zrestrict3d<S, C, TXc, TYc, NT, 12>), dim3(tx * ty * nch, s.batch),
                        dim3(NT), 0, st, static_cast<const S*>(s.b), static_cast<S*>(s.out),
                        static_cast<S*>(s.out_c), n, nc, tx, ty, zc, nch, C(s.sA), C(s.sW),
                        C(s.c[0]), C(s.c[1]), s.fin_ps, s.fin_pm, s.fin_count, s.fin_dev,
@@ -3901,7 +3924,7 @@ hipError_t zsr_impl(const Sweep& s, hipStream_t st) {
 #define ZSR(CX, CY, NT)                                                                         \
     do {                                                                                       \
         const int tx = cdiv(nc, CX), ty = cdiv(nc, CY);                                        \
-        hipLaunchKernelGGL((k_zsr2d<S, C, CX, CY, NT>), dim3(tx * ty, s.batch), dim3(NT), 0,   \
+        mg_launch((k_zsr2d<S, C, CX, CY, NT>), dim3(tx * ty, s.batch), dim3(NT), 0,   \
                            st, b, e, bc, n, nc, tx, ty, sA, sW, c0, c1, c2, s.fin_ps,          \
                            s.fin_pm, s.fin_count, s.fin_dev, s.fin_host);                      \
     } while (0)
@@ -3929,12 +3952,13 @@ hipError_t launch_sr2d(const Sweep& s, bool norm, int want, int minc, hipStream_
     S* bc = static_cast<S*>(s.out_c);
     const C sA = C(s.sA), sW = C(s.sW), c0 = C(s.c[0]), c1 = C(s.c[1]), c2 = C(s.c[2]);
 #define SR2(NM)                                                                              \
-    hipLaunchKernelGGL((k_sr2d<S, C, TX, NT, PD, UN, NTS, NM>), grid, dim3(NT), 0, st, u, b,  \
-                       out, bc, n, nc, tx, yc, nch, sA, sW, c0, c1, c2, s.partials)
+    mg_launch((k_sr2d<S, C, TX, NT, PD, UN, NTS, NM>), grid, dim3(NT), 0, st, u, b,  \
+                       out, bc, n, nc, tx, yc, nch, sA, sW, c0, c1, c2, s.partials,          \
+                       static_cast<S*>(nullptr))
     if constexpr (sizeof(S) == 8) {
         if (s.rout) {  // residual side output
             if (norm) return hipErrorInvalidValue;
-            hipLaunchKernelGGL((k_sr2d<S, C, TX, NT, PD, UN, NTS, false, true>), grid, dim3(NT), 0,
+            mg_launch((k_sr2d<S, C, TX, NT, PD, UN, NTS, false, true>), grid, dim3(NT), 0,
                                st, u, b, out, bc, n, nc, tx, yc, nch, sA, sW, c0, c1, c2,
                                s.partials, static_cast<S*>(s.rout));
             return hipGetLastError();
@@ -3962,12 +3986,13 @@ hipError_t launch_sr3d(const Sweep& s, bool norm, int want, int minc, hipStream_
     S* bc = static_cast<S*>(s.out_c);
     const C sA = C(s.sA), sW = C(s.sW), c0 = C(s.c[0]), c1 = C(s.c[1]);
 #define SR3(NM)                                                                             \
-    hipLaunchKernelGGL((k_sr3d<S, C, TX, TY, NT, PD, UN, NTS, NM>), grid, dim3(NT), 0, st,     \
-                       u, b, out, bc, n, nc, tx, ty, zc, nch, sA, sW, c0, c1, s.partials)
+    mg_launch((k_sr3d<S, C, TX, TY, NT, PD, UN, NTS, NM>), grid, dim3(NT), 0, st,     \
+                       u, b, out, bc, n, nc, tx, ty, zc, nch, sA, sW, c0, c1, s.partials,   \
+                       static_cast<S*>(nullptr))
     if constexpr (sizeof(S) == 8) {
         if (s.rout) {  // residual side output
             if (norm) return hipErrorInvalidValue;
-            hipLaunchKernelGGL((k_sr3d<S, C, TX, TY, NT, PD, UN, NTS, false, true>), grid,
+            mg_launch((k_sr3d<S, C, TX, TY, NT, PD, UN, NTS, false, true>), grid,
                                dim3(NT), 0, st, u, b, out, bc, n, nc, tx, ty, zc, nch, sA, sW,
                                c0, c1, s.partials, static_cast<S*>(s.rout));
             return hipGetLastError();
@@ -4046,7 +4071,7 @@ hipError_t launch_psr2d(const Sweep& s, bool norm, int want, int minc, hipStream
     const C sA = C(s.sA), sW = C(s.sW), c0 = C(s.c[0]), c1 = C(s.c[1]), c2 = C(s.c[2]);
     const C pf = C(s.pf);
 #define PSR2(NM)                                                                              \
-    hipLaunchKernelGGL((k_psr2d<S, C, TX, NT, PD, UN, NTS, NM>), grid, dim3(NT), 0, st, u, ec, \
+    mg_launch((k_psr2d<S, C, TX, NT, PD, UN, NTS, NM>), grid, dim3(NT), 0, st, u, ec, \
                        b, out, out_t, bc, n, nc, tx, yc, nch, sA, sW, c0, c1, c2, pf,         \
                        s.partials)
     if (norm) PSR2(true);
@@ -4141,11 +4166,11 @@ hipError_t launch_adj_sweep(int d, int n, int batch, int mode, const double* uba
     if (mode == 0 && 4L * grid.x * grid.y > partials_cap) return hipErrorInvalidValue;
     const bool wide = d == 3 && (c[2] != 0.0 || c[3] != 0.0);
 #define AS3(WD, MD)                                                                             \
-    hipLaunchKernelGGL((k_adj_sweep3d<32, 16, 512, WD, MD>), grid, dim3(512), 0, st, ubar, r, ec, \
+    mg_launch((k_adj_sweep3d<32, 16, 512, WD, MD>), grid, dim3(512), 0, st, ubar, r, ec, \
                        ubar_new, bbar, partials, n, tx, ty, zc, nch, sA, sW, c[0], c[1], c[2], \
                        c[3], scale)
 #define AS2(MD)                                                                               \
-    hipLaunchKernelGGL((k_adj_sweep2d<256, 320, MD>), grid, dim3(320), 0, st, ubar, r, ec,     \
+    mg_launch((k_adj_sweep2d<256, 320, MD>), grid, dim3(320), 0, st, ubar, r, ec,     \
                        ubar_new, bbar, partials, n, tx, zc, nch, sA, sW, c[0], c[1], c[2], scale)
     if (d == 3) {
         if (mode == 1) AS3(false, 1);
@@ -4162,7 +4187,7 @@ hipError_t launch_adj_sweep(int d, int n, int batch, int mode, const double* uba
 
 hipError_t launch_finalize(const double* partials, const double* maxparts, int count,
                            double* out, hipStream_t st, double* host) {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, partials, maxparts, count, out,
+    mg_launch(k_finalize, dim3(1), dim3(256), 0, st, partials, maxparts, count, out,
                        host);
     return hipGetLastError();
 }
@@ -4172,7 +4197,7 @@ hipError_t launch_sumsq(const double* v, long count, double* partials, long part
     long blocks = std::min<long>(2048, std::max<long>(1, (count + 4095) / 4096));
     if (blocks > partials_cap) blocks = partials_cap;
     const long per = (count + blocks - 1) / blocks;
-    hipLaunchKernelGGL(k_sumsq, dim3((unsigned)blocks), dim3(256), 0, st, v, count, per, partials);
+    mg_launch(k_sumsq, dim3((unsigned)blocks), dim3(256), 0, st, v, count, per, partials);
     if (nparts) *nparts = (int)blocks;
     return hipGetLastError();
 }
