@@ -3703,7 +3703,17 @@ hipError_t smooth_impl(bool zg, bool norm, const Sweep& s, hipStream_t st, int* 
     if (s.d == 3) {
         // FP32 / FP16 storage: 256x8 tiles on 1024 threads and 1024 marches
         // (4-byte and 2-byte rows need longer row segments and more waves in
-        // flight; 11% faster than 128x16 tiles measured cold at n = 511)
+        // flight; 11% faster than 128x16 tiles measured cold at n = 511).
+        // FP16 storage: 128x8 tiles on 512 threads and 512 marches, two
+        // workgroups per CU (the post-smoother with the correction at n =
+        // 511 in the refinement loop: 311 against 359 us; 64x16 on 512 352,
+        // 128x16 on 1024 345, 64x8 on 256 351 us; FP32 storage is slower on
+        // every one of these shapes than on 256x8)
+        if constexpr (sizeof(S) == 2) {
+            if (n >= 200)
+                return launch_smooth3d<S, C, 128, 8, 512, 6, true>(zg, norm, s, 512, 32, st,
+                                                                    nparts);
+        }
         if constexpr (sizeof(S) < 8) {
             if (n >= 200)
                 return launch_smooth3d<S, C, 256, 8, 1024, 6, true>(zg, norm, s, 1024, 32, st,
