@@ -399,13 +399,14 @@ def mixed(tol):
 # u_out, r3); the reverse pass's two smoothing sweeps (read ubar, r, bbar;
 # write ubar', bbar), the restriction of ubar (read a fine field, write a
 # coarse one) and the update with the interpolated bbar_c (read ubar, bbar,
-# bbar_c; write ubar', bbar); FP32 checkpoints add their widening (read 4,
-# write 8).  c is one coarse value per 2^d fine points.
+# bbar_c; write ubar', bbar); the fused pre-smoother reads an FP32
+# checkpoint as stored (4 instead of 8 bytes of u).  c is one coarse value per
+# 2^d fine points.
 def adjoint_bytes_per_pt(d, ckpt="fp64"):
     c = 8.0 / 2 ** d
     forward = (32 + c) + (32 + c)
     reverse = 40 + (8 + c) + (32 + c) + 40
-    return forward + reverse + (12.0 if ckpt == "fp32" else 0.0)
+    return forward + reverse - (4.0 if ckpt == "fp32" else 0.0)
 
 
 ADJOINT_CASES = (("errors2d_n1024_b16", 2, 1024, 16, 3, "fp64"),

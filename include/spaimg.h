@@ -228,8 +228,8 @@ int mg_checkpoint(mg_handle_t h, double* u, void* ckpt, int ckpt_dtype, void* st
  * accumulates bbar_acc += dL/db (device, batch-shaped) and cbar_acc[j] +=
  * dL/dc_j summed over the batch (HOST FP64 array of mg_setup's n_coeffs).  u_in is the
  * cycle's checkpoint as written by mg_checkpoint: device, batch-shaped, FP64
- * (ckpt_dtype = MG_CKPT_FP64) or FP32 (MG_CKPT_FP32, widened exactly to FP64
- * inside the library).  The forward states of every level are recomputed
+ * (ckpt_dtype = MG_CKPT_FP64) or FP32 (MG_CKPT_FP32, converted exactly to
+ * FP64 as the recomputation reads it).  The forward states of every level are recomputed
  * from it.  Uses A^T = A, M^T = M (symmetric stencils with zero extension),
  * P^T = 2^d R.  Synchronises `stream` (to return cbar_acc on the host).
  * Errors: MG_EINVAL for a null handle or pointer, a bad ckpt_dtype or a

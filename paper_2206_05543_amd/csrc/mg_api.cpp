@@ -1563,7 +1563,6 @@ int alloc_adj(mg_ctx* h) {
         if (l == 0 && h->L > 1) HIPCHK(hipMalloc(&h->adj_w[l], bytes));
     }
     HIPCHK(hipMalloc(&h->adj_cacc, 4 * sizeof(double)));
-    HIPCHK(hipMalloc(&h->adj_cin, (size_t)level_pts(h, 0) * h->batch * sizeof(double)));
     // two coefficient-gradient sweeps per level above the coarsest, each at
     // most kAdjBlocks blocks per batch entry with 4 partial sums
     h->adj_pcap = 2L * 4 * kAdjBlocks * h->batch * (h->L > 1 ? h->L - 1 : 1);
@@ -1578,8 +1577,10 @@ int alloc_adj(mg_ctx* h) {
 // and the level output e_l (for the level above).  The residuals are side
 // outputs of the cycle's own fused kernels: the pre-smoother (with the
 // restriction where the cycle fuses them) writes r1, and the post-smoother
-// with the fused correction writes r3 beside e_l.
-int adj_forward(mg_ctx* h, int l, const double* u_in, const double* bl, hipStream_t st) {
+// with the fused correction writes r3 beside e_l.  u_f32: u_in holds FP32
+// values (an FP32 checkpoint, read by the fused pre-smoother directly).
+int adj_forward(mg_ctx* h, int l, const void* u_in, bool u_f32, const double* bl,
+                hipStream_t st) {
     Hier& H = h->h64;
     if (l == h->L - 1) return run_tail(h, H, l, bl, H.e[l], st);
     Sweep s = make_sweep(h, H, l);
@@ -1588,9 +1589,11 @@ int adj_forward(mg_ctx* h, int l, const double* u_in, const double* bl, hipStrea
     s.b = bl;
     s.out = t;
     const bool fused = u_in ? fuse_smooth_restrict(h, l) : fuse_zero_restrict(h, l);
+    if (u_f32 && !(fused && u_in)) return fail(MG_EINVAL, "FP32 input without the fused kernel");
     if (fused) {
         s.out_c = H.b[l + 1];
         s.rout = u_in ? h->adj_r1[l] : nullptr;
+        s.u_f32 = u_f32;
         HIPCHK(u_in ? launch_smooth_restrict(P64, false, s, st, nullptr)
                     : launch_zero_smooth_restrict(P64, s, st));
     } else {
@@ -1602,7 +1605,7 @@ int adj_forward(mg_ctx* h, int l, const double* u_in, const double* bl, hipStrea
         rs.out = H.b[l + 1];
         HIPCHK(launch_restrict(P64, rs, st));
     }
-    int rc = adj_forward(h, l + 1, nullptr, static_cast<const double*>(H.b[l + 1]), st);
+    int rc = adj_forward(h, l + 1, nullptr, false, static_cast<const double*>(H.b[l + 1]), st);
     if (rc) return rc;
     // post-smoothing of u2 = t + P e_{l+1}; on the fine level only r3 is
     // needed (the cycle's output goes to scratch)
@@ -1692,11 +1695,22 @@ extern "C" int mg_vcycle_adjoint(mg_handle_t h, const double* b, const void* u_c
     hipStream_t st = (hipStream_t)stream;
     int rc = alloc_adj(h);
     if (rc) return rc;
-    const double* u_in = static_cast<const double*>(u_ckpt);
+    const void* u_in = u_ckpt;
+    bool u_f32 = false;
     if (ckpt_dtype == MG_CKPT_FP32) {
-        HIPCHK(launch_widen(static_cast<const float*>(u_ckpt), h->adj_cin,
-                            level_pts(h, 0) * h->batch, st));
-        u_in = h->adj_cin;
+        if (h->L > 1 && fuse_smooth_restrict(h, 0)) {
+            // the fused pre-smoother reads the FP32 checkpoint itself
+            u_f32 = true;
+        } else {
+            // the unfused pre-smoother reads FP64: widen into a buffer of
+            // its own (allocated on first use)
+            if (!h->adj_cin)
+                HIPCHK(hipMalloc(&h->adj_cin,
+                                 (size_t)level_pts(h, 0) * h->batch * sizeof(double)));
+            HIPCHK(launch_widen(static_cast<const float*>(u_ckpt), h->adj_cin,
+                                level_pts(h, 0) * h->batch, st));
+            u_in = h->adj_cin;
+        }
     }
     h->adj_poff = 0;
     if (h->L == 1) {
@@ -1705,7 +1719,7 @@ extern "C" int mg_vcycle_adjoint(mg_handle_t h, const double* b, const void* u_c
                                     true, st));
         HIPCHK(hipMemsetAsync(ubar_in, 0, (size_t)level_pts(h, 0) * h->batch * sizeof(double), st));
     } else {
-        rc = adj_forward(h, 0, u_in, b, st);
+        rc = adj_forward(h, 0, u_in, u_f32, b, st);
         if (rc) return rc;
         rc = adj_reverse(h, 0, ubar_out, ubar_in, bbar_acc, h->adj_r1[0], st);
         if (rc) return rc;

@@ -29,6 +29,8 @@ inline size_t prec_bytes(Prec p) { return p == P64 ? 8 : (p == P32 ? 4 : 2); }
 // hierarchies (sigma = 1/h^2, sA = sW = 1).
 struct Sweep {
     const void* u = nullptr;     // current iterate (ignored for zero guess)
+    bool u_f32 = false;          // u holds FP32 values (the FP64 fused pre-smoother
+                                 // with a residual output only: an FP32 checkpoint)
     const void* b = nullptr;     // right-hand side
     void* out = nullptr;         // output (new iterate, or coarse rhs)
     int d = 2;

@@ -1612,9 +1612,9 @@ k_zsr2d(const S* __restrict__ b, S* __restrict__ e, S* __restrict__ bc, int n, i
 // halo columns (L2 hits) and three extra rows per chunk.
 // ---------------------------------------------------------------------------
 template <typename S, typename C, int TX, int NT, int PD, int UN, bool NTS, bool NORM,
-          bool ROUT = false>
+          bool ROUT = false, typename SU = S>
 __global__ void __launch_bounds__(NT)
-k_sr2d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out,
+k_sr2d(const SU* __restrict__ u, const S* __restrict__ b, S* __restrict__ out,
        S* __restrict__ bc, int n, int nc, int tiles_x, int ychunk, int nchunks, C sA, C sW,
        C c0, C c1, C c2, double* __restrict__ partials, S* __restrict__ rout = nullptr) {
     constexpr int W = TX + 7;             // columns x0-3 .. x0+TX+3
@@ -1648,7 +1648,7 @@ k_sr2d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out,
     const int lane = t & 63;
 
     int li[M];
-    unsigned gb[M];
+    unsigned gb[M], gu[M];
     bool col[M], own[M];
 #pragma unroll
     for (int m = 0; m < M; ++m) {
@@ -1659,6 +1659,7 @@ k_sr2d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out,
         own[m] = col[m] && gx >= x0 && gx < x0 + TX;
         li[m] = inr ? j + 1 : W + 2 + lane;
         gb[m] = col[m] ? (unsigned)(gx * (int)sizeof(S)) : kOob;
+        gu[m] = col[m] ? (unsigned)(gx * (int)sizeof(SU)) : kOob;
     }
     // coarse column x0/2 + i sits over local column 2 i + 4
     int cq[MC];
@@ -1675,11 +1676,12 @@ k_sr2d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out,
     // whole unrolled groups and the prefetch run past them, and rows
     // outside these ranges read as zero without touching memory
     const int ulast = min(n - 1, 2 * Y1 + 3), blast = min(n - 1, 2 * Y1 + 2);
-    S ru[RS][M], rb[RS][M];
+    SU ru[RS][M];
+    S rb[RS][M];
     auto issue_u = [&](int p, int k) {
         const rsrc_t r = line_rsrc(u, (long)p * n, n, p >= 0 && p <= ulast);
 #pragma unroll
-        for (int m = 0; m < M; ++m) ru[k][m] = bload<S>(r, gb[m]);
+        for (int m = 0; m < M; ++m) ru[k][m] = bload<SU>(r, gu[m]);
     };
     auto issue_b = [&](int p, int k) {
         const rsrc_t r = line_rsrc(b, (long)p * n, n, p >= 0 && p <= blast);
@@ -1698,13 +1700,13 @@ k_sr2d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out,
     const int s0 = 2 * Y0 - 2, s1 = 2 * Y1 + 4;
     {
         // all prologue loads before the first wait
-        S pu[3][M];
+        SU pu[3][M];
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
             const int p = s0 - 1 + q;
             const rsrc_t r = line_rsrc(u, (long)p * n, n, p >= 0 && p < n);
 #pragma unroll
-            for (int m = 0; m < M; ++m) pu[q][m] = bload<S>(r, gb[m]);
+            for (int m = 0; m < M; ++m) pu[q][m] = bload<SU>(r, gu[m]);
         }
 #pragma unroll
         for (int q = 0; q < PD; ++q) {
@@ -2160,9 +2162,9 @@ k_psr2d(const S* __restrict__ t, const S* __restrict__ ec, const S* __restrict__
 // the owned nodes.
 // ---------------------------------------------------------------------------
 template <typename S, typename C, int TX, int TY, int NT, int PD, int UN, bool NTS, bool NORM,
-          bool ROUT = false>
+          bool ROUT = false, typename SU = S>
 __global__ void __launch_bounds__(NT)
-k_sr3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out,
+k_sr3d(const SU* __restrict__ u, const S* __restrict__ b, S* __restrict__ out,
        S* __restrict__ bc, int n, int nc, int tiles_x, int tiles_y, int zchunk, int nchunks,
        C sA, C sW, C c0, C c1, double* __restrict__ partials, S* __restrict__ rout = nullptr) {
     constexpr int WX = TX + 7, WY = TY + 7, NW = WX * WY;  // x0-3 .. x0+TX+3
@@ -2196,7 +2198,7 @@ k_sr3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out,
     const int t = threadIdx.x;
 
     int li[M];
-    unsigned gb[M];
+    unsigned gb[M], gu[M];
     bool col[M], own[M], wr[M];
 #pragma unroll
     for (int m = 0; m < M; ++m) {
@@ -2208,6 +2210,7 @@ k_sr3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out,
         own[m] = col[m] && gx >= x0 && gx < x0 + TX && gy >= y0 && gy < y0 + TY;
         li[m] = wr[m] ? WP + i : WP;  // idle lanes read a valid slot, write nothing
         gb[m] = col[m] ? (unsigned)((gy * n + gx) * (int)sizeof(S)) : kOob;
+        gu[m] = col[m] ? (unsigned)((gy * n + gx) * (int)sizeof(SU)) : kOob;
     }
     // coarse column (x0/2 + i, y0/2 + j) sits over window point (2i+4, 2j+4)
     int cq[MC];
@@ -2224,11 +2227,12 @@ k_sr3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out,
     // planes any output depends on: u up to 2 Z1 + 3, b up to 2 Z1 + 2 (as
     // in 2D, later planes read as zero without touching memory)
     const int ulast = min(n - 1, 2 * Z1 + 3), blast = min(n - 1, 2 * Z1 + 2);
-    S ru[RS][M], rb[RS][M];
+    SU ru[RS][M];
+    S rb[RS][M];
     auto issue_u = [&](int p, int k) {
         const rsrc_t r = line_rsrc(u, (long)p * plane, plane, p >= 0 && p <= ulast);
 #pragma unroll
-        for (int m = 0; m < M; ++m) ru[k][m] = bload<S>(r, gb[m]);
+        for (int m = 0; m < M; ++m) ru[k][m] = bload<SU>(r, gu[m]);
     };
     auto issue_b = [&](int p, int k) {
         const rsrc_t r = line_rsrc(b, (long)p * plane, plane, p >= 0 && p <= blast);
@@ -2243,13 +2247,13 @@ k_sr3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out,
     double nacc = 0.0;
     const int s0 = 2 * Z0 - 2, s1 = 2 * Z1 + 3;
     {
-        S pu[3][M];
+        SU pu[3][M];
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
             const int p = s0 - 1 + q;
             const rsrc_t r = line_rsrc(u, (long)p * plane, plane, p >= 0 && p < n);
 #pragma unroll
-            for (int m = 0; m < M; ++m) pu[q][m] = bload<S>(r, gb[m]);
+            for (int m = 0; m < M; ++m) pu[q][m] = bload<SU>(r, gu[m]);
         }
 #pragma unroll
         for (int q = 0; q < PD; ++q) {
@@ -3597,6 +3601,7 @@ inline int even_chunk(int c) { return c + (c & 1); }
 template <typename S, typename C, int TX, int TY, int NT, int UN, bool NTS>
 hipError_t launch_smooth3d(bool zg, bool norm, const Sweep& s, int want, int minc,
                            hipStream_t st, int* nparts) {
+    if (s.u_f32) return hipErrorInvalidValue;  // FP32 input: fused pre-smoother only
     const int n = s.n, nc = (n + 1) / 2 - 1;
     const S* u = static_cast<const S*>(s.u);
     const S* b = static_cast<const S*>(s.b);
@@ -3650,6 +3655,7 @@ hipError_t launch_smooth3d(bool zg, bool norm, const Sweep& s, int want, int min
 template <typename S, typename C, int TX, int NT, int UN, bool NTS>
 hipError_t launch_smooth2d(bool zg, bool norm, const Sweep& s, int want, int minc,
                            hipStream_t st, int* nparts) {
+    if (s.u_f32) return hipErrorInvalidValue;  // FP32 input: fused pre-smoother only
     const int n = s.n, nc = (n + 1) / 2 - 1;
     const S* u = static_cast<const S*>(s.u);
     const S* b = static_cast<const S*>(s.b);
@@ -3949,6 +3955,8 @@ hipError_t zsr_impl(const Sweep& s, hipStream_t st) {
 template <typename S, typename C, int TX, int NT, int PD, int UN, bool NTS>
 hipError_t launch_sr2d(const Sweep& s, bool norm, int want, int minc, hipStream_t st,
                        int* nparts) {
+    // an FP32 input iterate only in FP64 with the residual output
+    if (s.u_f32 && (sizeof(S) != 8 || !s.rout)) return hipErrorInvalidValue;
     const int n = s.n, nc = (n + 1) / 2 - 1;
     const int tx = cdiv(n, TX);
     const int yc = pick_chunk(nc, tx, want, minc);
@@ -3968,9 +3976,14 @@ hipError_t launch_sr2d(const Sweep& s, bool norm, int want, int minc, hipStream_
     if constexpr (sizeof(S) == 8) {
         if (s.rout) {  // residual side output
             if (norm) return hipErrorInvalidValue;
-            mg_launch((k_sr2d<S, C, TX, NT, PD, UN, NTS, false, true>), grid, dim3(NT), 0,
-                               st, u, b, out, bc, n, nc, tx, yc, nch, sA, sW, c0, c1, c2,
-                               s.partials, static_cast<S*>(s.rout));
+            if (s.u_f32)  // the iterate as stored in an FP32 checkpoint
+                mg_launch((k_sr2d<S, C, TX, NT, PD, UN, NTS, false, true, float>), grid,
+                          dim3(NT), 0, st, static_cast<const float*>(s.u), b, out, bc, n, nc,
+                          tx, yc, nch, sA, sW, c0, c1, c2, s.partials, static_cast<S*>(s.rout));
+            else
+                mg_launch((k_sr2d<S, C, TX, NT, PD, UN, NTS, false, true>), grid, dim3(NT), 0,
+                          st, u, b, out, bc, n, nc, tx, yc, nch, sA, sW, c0, c1, c2,
+                          s.partials, static_cast<S*>(s.rout));
             return hipGetLastError();
         }
     }
@@ -3983,6 +3996,8 @@ hipError_t launch_sr2d(const Sweep& s, bool norm, int want, int minc, hipStream_
 template <typename S, typename C, int TX, int TY, int NT, int PD, int UN, bool NTS>
 hipError_t launch_sr3d(const Sweep& s, bool norm, int want, int minc, hipStream_t st,
                        int* nparts) {
+    // an FP32 input iterate only in FP64 with the residual output
+    if (s.u_f32 && (sizeof(S) != 8 || !s.rout)) return hipErrorInvalidValue;
     const int n = s.n, nc = (n + 1) / 2 - 1;
     const int tx = cdiv(n, TX), ty = cdiv(n, TY);
     const int zc = pick_chunk(nc, tx * ty, want, minc);
@@ -4002,9 +4017,14 @@ hipError_t launch_sr3d(const Sweep& s, bool norm, int want, int minc, hipStream_
     if constexpr (sizeof(S) == 8) {
         if (s.rout) {  // residual side output
             if (norm) return hipErrorInvalidValue;
-            mg_launch((k_sr3d<S, C, TX, TY, NT, PD, UN, NTS, false, true>), grid,
-                               dim3(NT), 0, st, u, b, out, bc, n, nc, tx, ty, zc, nch, sA, sW,
-                               c0, c1, s.partials, static_cast<S*>(s.rout));
+            if (s.u_f32)  // the iterate as stored in an FP32 checkpoint
+                mg_launch((k_sr3d<S, C, TX, TY, NT, PD, UN, NTS, false, true, float>), grid,
+                          dim3(NT), 0, st, static_cast<const float*>(s.u), b, out, bc, n, nc,
+                          tx, ty, zc, nch, sA, sW, c0, c1, s.partials, static_cast<S*>(s.rout));
+            else
+                mg_launch((k_sr3d<S, C, TX, TY, NT, PD, UN, NTS, false, true>), grid,
+                          dim3(NT), 0, st, u, b, out, bc, n, nc, tx, ty, zc, nch, sA, sW,
+                          c0, c1, s.partials, static_cast<S*>(s.rout));
             return hipGetLastError();
         }
     }
@@ -4065,6 +4085,7 @@ hipError_t launch_smooth_restrict(Prec p, bool norm, const Sweep& s, hipStream_t
 template <typename S, typename C, int TX, int NT, int PD, int UN, bool NTS>
 hipError_t launch_psr2d(const Sweep& s, bool norm, int want, int minc, hipStream_t st,
                         int* nparts) {
+    if (s.u_f32) return hipErrorInvalidValue;
     const int n = s.n, nc = (n + 1) / 2 - 1;
     const int tx = cdiv(n, TX);
     const int yc = pick_chunk(nc, tx, want, minc);
