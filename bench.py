@@ -278,6 +278,7 @@ def main():
 
     if not a.no_mixed:
         line["mixed_precision"] = mixed(a.tol)
+        line["roofline_lowprec"] = lowprec_roofline(line["mixed_precision"])
     if not a.no_adjoint:
         line["adjoint"] = adjoint()
     if not a.no_examples:
@@ -324,6 +325,67 @@ def mixed_oracle_anchored(tol, N=64):
         out[prec] = {"code": st["code"], "cycles": st["cycles"],
                      "rel_error_vs_oracle": float(np.linalg.norm(got - ref) / np.linalg.norm(ref))}
     return out
+
+
+# the fine-level kernels of the refinement solves, and their algorithmic bytes
+# per fine node with storage of sb bytes: the pre-smoother + residual +
+# restriction (read u, b; write u1, b_c), the post-smoother with the fused
+# correction (read u1, b, e_c; write u), the zero-guess pre-smoother +
+# restriction (read b; write e, b_c) and the FP64 refinement step (read u, b
+# in FP64 and e; write u in FP64 and the scaled right-hand side; its first
+# step, with no correction yet, moves less, so its average overstates the
+# bytes slightly)
+LOWPREC_KINDS = ("smooth_restrict", "smooth_correct", "zero_smooth_restrict", "ir_step")
+LOWPREC_NAMES = {"smooth_restrict": "k_sr3d (pre-smoother + residual + restriction)",
+                 "smooth_correct": "k_smooth3d PRO (post-smoother + fused correction)",
+                 "zero_smooth_restrict": "k_zrestrict3d (zero-guess pre-smoother + restriction)",
+                 "ir_step": "k_ir3d (FP64 refinement step)"}
+STORAGE_BYTES = {"fp64": 8, "fp32_ir": 4, "fp16_ir": 2}
+
+
+def lowprec_bytes_per_pt(kind, sb):
+    return {"smooth_restrict": 3 * sb + sb / 8.0, "smooth_correct": 3 * sb + sb / 8.0,
+            "zero_smooth_restrict": 2 * sb + sb / 8.0, "ir_step": 24.0 + 2 * sb}[kind]
+
+
+def fine_kernel_rates(mg, b, u, u0, tol, sb, pts):
+    """One more solve with every launch timed (its own dispatch timestamps):
+    per fine-level kernel kind, launches per solve, average time and
+    algorithmic GB/s."""
+    from paper_2206_05543_amd._lib import OPT_TIMING
+    mg.set_option(OPT_TIMING, 2)
+    mg.reset_timing()
+    u.copy_(u0)
+    mg.solve(b, u, tol=tol)
+    mg.set_option(OPT_TIMING, 0)
+    rows = {}
+    for kind in LOWPREC_KINDS:
+        ms, cnt = mg.timing(kind, 0)
+        if not cnt:
+            continue
+        avg_us = ms / cnt * 1e3
+        gbs = lowprec_bytes_per_pt(kind, sb) * pts / (avg_us * 1e-6) / 1e9
+        rows[kind] = {"kernel": LOWPREC_NAMES[kind], "launches_per_solve": cnt,
+                      "avg_us": avg_us, "bytes_per_pt": lowprec_bytes_per_pt(kind, sb),
+                      "GBps": gbs, "frac_of_peak": gbs / HBM_PEAK_GBS}
+    return rows
+
+
+def lowprec_roofline(mixed_out):
+    """The FP16-storage solve's storage-precision sweep with the largest time
+    per solve, as a roofline entry (algorithmic bytes over its average
+    launch time)."""
+    rows = mixed_out.get("fp16_ir", {}).get("fine_kernels", {})
+    sweeps = {k: v for k, v in rows.items() if k != "ir_step"}
+    if not sweeps:
+        return None
+    kind = max(sweeps, key=lambda k: sweeps[k]["avg_us"] * sweeps[k]["launches_per_solve"])
+    r = sweeps[kind]
+    return {"bound": "hbm", "achieved": r["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": r["frac_of_peak"], "traffic": None,
+            "kernel": r["kernel"] + ", FP16 storage, FP32 arithmetic (poisson3d_n512_noisy)",
+            "avg_launch_us": r["avg_us"],
+            "algorithmic_bytes_per_launch": r["bytes_per_pt"] * 511 ** 3}
 
 
 def mixed(tol):
@@ -381,6 +443,7 @@ def mixed(tol):
                "oracle_residual_vs_b": r_or / b_norm,
                "rel_error_vs_reference": float((u - ref).norm()) / ref_norm,
                "rel_error_vs_closed_form_sine": float((u - ucf).norm()) / ucf_norm}
+        rec["fine_kernels"] = fine_kernel_rates(mg, b, u, u0, tol, STORAGE_BYTES[prec], 511 ** 3)
         out[prec] = rec
         mg.close()
         print(f"[bench] mixed {prec}: {rec}", file=sys.stderr, flush=True)

@@ -87,3 +87,23 @@ def test_adjoint_bytes_per_fine_node(bench):
     assert bench.adjoint_bytes_per_pt(2) == 64 + 4 + 80 + 40 + 4
     assert bench.adjoint_bytes_per_pt(3) == 64 + 2 + 80 + 40 + 2
     assert bench.adjoint_bytes_per_pt(3, "fp32") == bench.adjoint_bytes_per_pt(3) - 4
+
+
+def test_lowprec_bytes_and_roofline(bench):
+    # FP16 storage: 3 x 2 B + 2/8 B for the two smoothing sweeps, 2 x 2 B +
+    # 2/8 B for the zero-guess one, 24 + 2 x 2 B for the FP64 step
+    assert bench.lowprec_bytes_per_pt("smooth_restrict", 2) == 6.25
+    assert bench.lowprec_bytes_per_pt("smooth_correct", 4) == 12.5
+    assert bench.lowprec_bytes_per_pt("zero_smooth_restrict", 2) == 4.25
+    assert bench.lowprec_bytes_per_pt("ir_step", 2) == 28.0
+    rows = {"smooth_restrict": {"kernel": "a", "launches_per_solve": 6, "avg_us": 380.0,
+                                "bytes_per_pt": 6.25, "GBps": 2000.0, "frac_of_peak": 0.25},
+            "smooth_correct": {"kernel": "b", "launches_per_solve": 12, "avg_us": 310.0,
+                               "bytes_per_pt": 6.25, "GBps": 2600.0, "frac_of_peak": 0.325},
+            "ir_step": {"kernel": "c", "launches_per_solve": 7, "avg_us": 820.0,
+                        "bytes_per_pt": 28.0, "GBps": 4500.0, "frac_of_peak": 0.56}}
+    r = bench.lowprec_roofline({"fp16_ir": {"fine_kernels": rows}})
+    # the storage-precision sweep with the most time per solve (12 x 310 us)
+    assert r["frac"] == 0.325 and r["avg_launch_us"] == 310.0
+    assert r["algorithmic_bytes_per_launch"] == 6.25 * 511 ** 3
+    assert bench.lowprec_roofline({}) is None
