@@ -70,14 +70,24 @@ def sweep_bytes_per_pt(kind, d):
 # commands are in profiles/hbm_counters_fp64_sweeps.md.  Valid for the
 # kernels and launch shapes they were taken on; set to None when those change.
 PMC = {
-    ("poisson3d_n256", "smooth_restrict"): (142850, 148637),
-    ("poisson3d_n256", "smooth_correct"): (149186, 143837),
-    ("poisson2d_n4096", "smooth_restrict"): (143204, 165370),
-    ("poisson2d_n4096", "post_pre_restrict"): (159432, 303612),
+    ("poisson3d_n256", "smooth_restrict"): (142798, 148531),
+    ("poisson3d_n256", "smooth_correct"): (149147, 144367),
+    ("poisson2d_n4096", "smooth_restrict"): (143190, 167329),
+    ("poisson2d_n4096", "post_pre_restrict"): (159432, 303939),
+    # the refinement solves' fine-level sweeps at 3D N=512, per storage
+    # precision (profiles/hbm_counters_lowprec_sweeps.md)
+    ("poisson3d_n512_noisy:fp16_ir", "smooth_correct"): (292535, 343992),
+    ("poisson3d_n512_noisy:fp16_ir", "smooth_restrict"): (275681, 298520),
+    ("poisson3d_n512_noisy:fp16_ir", "zero_smooth_restrict"): (141477, 293086),
+    ("poisson3d_n512_noisy:fp32_ir", "smooth_correct"): (610356, 583930),
+    ("poisson3d_n512_noisy:fp32_ir", "smooth_restrict"): (772306, 655441),
+    ("poisson3d_n512_noisy:fp32_ir", "zero_smooth_restrict"): (282661, 586496),
 }
 PMC_COPY = {  # copy bytes, FETCH_SIZE KiB, WRITE_SIZE KiB of the same run
-    "poisson3d_n256": (255 ** 3 * 8, 64792, 129542),
-    "poisson2d_n4096": (4095 ** 2 * 8, 65525, 131008),
+    "poisson3d_n256": (255 ** 3 * 8, 64782, 129542),
+    "poisson2d_n4096": (4095 ** 2 * 8, 65516, 131008),
+    "poisson3d_n512_noisy:fp16_ir": (511 ** 3 * 8, 521234, 1042444),
+    "poisson3d_n512_noisy:fp32_ir": (511 ** 3 * 8, 521234, 1042444),
 }
 
 
@@ -382,7 +392,7 @@ def lowprec_roofline(mixed_out):
     kind = max(sweeps, key=lambda k: sweeps[k]["avg_us"] * sweeps[k]["launches_per_solve"])
     r = sweeps[kind]
     return {"bound": "hbm", "achieved": r["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": r["frac_of_peak"], "traffic": None,
+            "frac": r["frac_of_peak"], "traffic": hbm_traffic("poisson3d_n512_noisy:fp16_ir", kind),
             "kernel": r["kernel"] + ", FP16 storage, FP32 arithmetic (poisson3d_n512_noisy)",
             "avg_launch_us": r["avg_us"],
             "algorithmic_bytes_per_launch": r["bytes_per_pt"] * 511 ** 3}

@@ -48,10 +48,18 @@ def test_counter_table_is_consistent_with_the_algorithmic_bytes(bench):
         assert cbytes / (cfetch * 1024.0) == pytest.approx(2.0, rel=1e-3)
         assert cbytes / (cwrite * 1024.0) == pytest.approx(1.0, rel=1e-3)
     for (name, kind) in bench.PMC:
-        d, N = bench.WORKLOADS[name]
-        algo = bench.sweep_bytes_per_pt(kind, d) * (N - 1) ** d
+        if ":" in name:
+            # refinement sweeps at 3D N=512: the FP32 fused pre-smoother
+            # re-reads its ring-3 halo from HBM (1.35x)
+            sb = bench.STORAGE_BYTES[name.split(":")[1]]
+            algo = bench.lowprec_bytes_per_pt(kind, sb) * 511 ** 3
+            hi = 1.4
+        else:
+            d, N = bench.WORKLOADS[name]
+            algo = bench.sweep_bytes_per_pt(kind, d) * (N - 1) ** d
+            hi = 1.15
         ratio = bench.hbm_traffic(name, kind) / algo
-        assert 1.0 <= ratio <= 1.15, (name, kind, ratio)
+        assert 1.0 <= ratio <= hi, (name, kind, ratio)
     assert bench.hbm_traffic("poisson2d_n4096", "no_such_kernel") is None
 
 
