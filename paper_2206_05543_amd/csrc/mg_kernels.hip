@@ -2169,7 +2169,14 @@ k_sr3d(const SU* __restrict__ u, const S* __restrict__ b, S* __restrict__ out,
        C sA, C sW, C c0, C c1, double* __restrict__ partials, S* __restrict__ rout = nullptr) {
     constexpr int WX = TX + 7, WY = TY + 7, NW = WX * WY;  // x0-3 .. x0+TX+3
     constexpr int M = (NW + NT - 1) / NT;
-    constexpr int WP = WX + 1, LSZ = NW + 2 * WP;          // guard rows of neighbours
+    constexpr int WP = WX + 1;                             // guard row of neighbours
+    // FP64: idle lanes (past the window) write, and read around, slots of
+    // their own (SCR + lane), so that no LDS write of the march needs an exec
+    // mask (1% faster at n = 255); FP32/FP16 storage: idle lanes skip their
+    // writes (3% faster at n = 511)
+    constexpr bool SCRW = sizeof(S) == 8;
+    constexpr int SCR = NW + 2 * WP + WX + 1;
+    constexpr int LSZ = SCRW ? SCR + 64 + WX + 1 : NW + 2 * WP;
     constexpr int HX = TX / 2, HY = TY / 2, NCC = HX * HY;  // coarse columns per tile
     constexpr int MC = (NCC + NT - 1) / NT;
     constexpr int RS = PD + 1;
@@ -2208,7 +2215,7 @@ k_sr3d(const SU* __restrict__ u, const S* __restrict__ b, S* __restrict__ out,
         const int gx = x0 - 3 + lx, gy = y0 - 3 + ly;
         col[m] = wr[m] && gx >= 0 && gx < n && gy >= 0 && gy < n;
         own[m] = col[m] && gx >= x0 && gx < x0 + TX && gy >= y0 && gy < y0 + TY;
-        li[m] = wr[m] ? WP + i : WP;  // idle lanes read a valid slot, write nothing
+        li[m] = wr[m] ? WP + i : (SCRW ? SCR + (t & 63) : WP);
         gb[m] = col[m] ? (unsigned)((gy * n + gx) * (int)sizeof(S)) : kOob;
         gu[m] = col[m] ? (unsigned)((gy * n + gx) * (int)sizeof(SU)) : kOob;
     }
@@ -2266,7 +2273,7 @@ k_sr3d(const SU* __restrict__ u, const S* __restrict__ b, S* __restrict__ out,
             u0[m] = cvt<C>(pu[1][m]);
             up1[m] = cvt<C>(pu[2][m]);
             b1[m] = b2[m] = r1[m] = r2[m] = v1[m] = v2[m] = C(0);
-            if (wr[m]) uL[s0 & 1][li[m]] = u0[m];
+            if (SCRW || wr[m]) uL[s0 & 1][li[m]] = u0[m];
         }
 #pragma unroll
         for (int q = 0; q < MC; ++q) acc[q] = C(0);
@@ -2300,7 +2307,7 @@ k_sr3d(const SU* __restrict__ u, const S* __restrict__ b, S* __restrict__ out,
                               um1[m] - up1[m];
                 const C r = (sin && col[m]) ? b0[m] - sA * lap : C(0);
                 r0[m] = r;
-                if (wr[m]) rL[s & 1][q] = r;
+                if (SCRW || wr[m]) rL[s & 1][q] = r;
                 if (NORM) nacc += (sown && own[m]) ? (double)r * (double)r : 0.0;
                 if (ROUT)
                     bstore<false>(static_cast<S>(r), line_rsrc(rout, (long)s * plane, plane, sown),
@@ -2322,7 +2329,7 @@ k_sr3d(const SU* __restrict__ u, const S* __restrict__ b, S* __restrict__ out,
                 const S vs = static_cast<S>(v);
                 bstore<NTS>(vs, ro, own[m] ? gb[m] : kOob);
                 v0[m] = (pin && col[m]) ? cvt<C>(vs) : C(0);
-                if (wr[m]) vL[p & 1][q] = v0[m];
+                if (SCRW || wr[m]) vL[p & 1][q] = v0[m];
             }
         }
         // residual of plane s-2 at the new iterate (planes s-3, s-2, s-1)
@@ -2333,7 +2340,7 @@ k_sr3d(const SU* __restrict__ u, const S* __restrict__ b, S* __restrict__ out,
                 const int q = li[m];
                 const C lap = C(6) * v1[m] - V[q - 1] - V[q + 1] - V[q - WX] - V[q + WX] -
                               v2[m] - v0[m];
-                if (wr[m]) wL[s & 1][q] = b2[m] - sA * lap;
+                if (SCRW || wr[m]) wL[s & 1][q] = b2[m] - sA * lap;
             }
         }
         // restriction of plane f = s-3 (written by the previous step)
@@ -2362,7 +2369,7 @@ k_sr3d(const SU* __restrict__ u, const S* __restrict__ b, S* __restrict__ out,
         // u of plane s+1 for the next step's neighbours; shift the histories
 #pragma unroll
         for (int m = 0; m < M; ++m) {
-            if (wr[m]) uL[(s + 1) & 1][li[m]] = up1[m];
+            if (SCRW || wr[m]) uL[(s + 1) & 1][li[m]] = up1[m];
             um1[m] = u0[m];
             u0[m] = up1[m];
             up1[m] = cvt<C>(ru[k % RS][m]);
