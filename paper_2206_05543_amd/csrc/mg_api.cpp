@@ -408,7 +408,6 @@ int run_tail(mg_ctx* h, Hier& H, int l, const void* b, void* e, hipStream_t st,
     for (int j = 0; j < 4; ++j) t.c[j] = j < h->ncoef ? h->c[j] : 0.0;
     t.ginv = H.ginv;
     t.scaled = H.scaled;
-    t.N_top = level_N(h, l);
     return run_timed(h, MG_TIME_TAIL, l, st, [&] { return launch_tail(H.p, t, st); });
 }
 

@@ -103,7 +103,6 @@ struct Tail {
     const double* ginv = nullptr;  // device: sigma_0 * A_0^{-1}, (3^d)^2
     double sigma_top = 1.0;        // storage scale of the top tail level
     bool scaled = false;           // scaled hierarchy (sigma_l = 1/h_l^2)
-    int N_top = 0;                 // intervals of the top tail level
     int wvisits = 0;               // 0: V(1,1); 1 or 2: W(1,0) visits of the
                                    // top level, the first from a zero guess
 };

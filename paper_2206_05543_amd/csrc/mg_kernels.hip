@@ -2899,65 +2899,75 @@ __host__ __device__ inline size_t tail_ginv_offset(size_t level_bytes) {
     return (level_bytes + 7) & ~size_t(7);
 }
 
-template <typename S, typename C, int D, bool WC>
+// Compile-time geometry of a tail whose top level has 2^KT - 1 interior
+// nodes per direction: level l (0 = top) has 2^(KT-l) - 1, down to 3 at
+// l = KT - 2; arrays e, b, r of (n_l + 2)^D each, level after level.  With
+// every size, pitch and offset a constant, a phase is a short straight-line
+// stretch of code (the tail's phases are bound by their instruction count
+// and latency, not by LDS bandwidth).
+template <int D, int KT>
+struct TailGeo {
+    static constexpr int L = KT - 1;
+    static constexpr int n(int l) { return (1 << (KT - l)) - 1; }
+    static constexpr int P(int l) { return n(l) + 2; }
+    static constexpr long pad(int l) {
+        return D == 3 ? (long)P(l) * P(l) * P(l) : (long)P(l) * P(l);
+    }
+    static constexpr long base(int l) {
+        long b = 0;
+        for (int k = 0; k < l; ++k) b += 3 * pad(k);
+        return b;
+    }
+};
+
+template <typename S, typename C, int D, bool WC, int KT>
 __global__ void __launch_bounds__(1024)
-k_tail(const S* __restrict__ bt, S* __restrict__ et, int nt, C c0, C c1, C c2, C c3,
-       const double* __restrict__ ginv, int scaled, int Ntop, int wvisits) {
+k_tail(const S* __restrict__ bt, S* __restrict__ et, C c0, C c1, C c2, C c3,
+       const double* __restrict__ ginv, int scaled, int wvisits) {
+    using G = TailGeo<D, KT>;
+    constexpr int L = G::L, nt = G::n(0);
     extern __shared__ unsigned char smem_raw[];
     C* sm = reinterpret_cast<C*>(smem_raw);
     const int t = threadIdx.x;
-    const int L = tail_levels(nt);
-    // level l: n_l, pitch P_l = n_l + 2, arrays e, b, r of (P_l)^D each
-    long tot = 0;
-    for (int l = 0, n = nt; l < L; ++l, n = (n + 1) / 2 - 1) tot += 3 * tail_padded(D, n);
+    constexpr long tot = G::base(L);
     for (long q = t; q < tot; q += 1024) sm[q] = C(0);
     constexpr int m3 = D == 2 ? 9 : 27;
     double* gl = reinterpret_cast<double*>(smem_raw + tail_ginv_offset(tot * sizeof(C)));
     for (int q = t; q < m3 * m3; q += 1024) gl[q] = ginv[q];
-    auto base = [&](int l) -> C* {
-        C* p = sm;
-        for (int k = 0, n = nt; k < l; ++k, n = (n + 1) / 2 - 1) p += 3 * tail_padded(D, n);
-        return p;
-    };
-    auto nl = [&](int l) {
-        int n = nt;
-        for (int k = 0; k < l; ++k) n = (n + 1) / 2 - 1;
-        return n;
+    auto pidx = [&](int i, int j, int k, int P) -> int {
+        return D == 3 ? ((k + 1) * P + j + 1) * P + i + 1 : (j + 1) * P + i + 1;
     };
     __syncthreads();
     {
         const long off = (long)blockIdx.x * (D == 3 ? (long)nt * nt * nt : (long)nt * nt);
-        C* B = base(0) + tail_padded(D, nt);
-        const int P = nt + 2;
+        C* B = sm + G::pad(0);
         tail_for<D>(nt, [&](int i, int j, int k) {
             const long g = D == 3 ? ((long)k * nt + j) * nt + i : (long)j * nt + i;
-            B[D == 3 ? ((k + 1) * P + j + 1) * P + i + 1 : (j + 1) * P + i + 1] = cvt<C>(bt[off + g]);
+            B[pidx(i, j, k, G::P(0))] = cvt<C>(bt[off + g]);
         });
     }
     __syncthreads();
-    auto level_consts = [&](int l, C* sA, C* sW) {
-        if (scaled) {
-            *sA = C(1);
-            *sW = C(1);
-        } else {
-            const double N = (double)(Ntop >> l);
-            *sA = C(N * N);
-            *sW = C(1.0 / (N * N));
-        }
+    // sA = 1/(h_l^2 sigma_l), sW = h_l^2 sigma_l: N_l^2 and 1/N_l^2 (N_l =
+    // 2^(KT - l)) unscaled, 1 for the scaled low-precision hierarchies
+    auto level_consts = [&](auto lc, C* sA, C* sW) {
+        constexpr int l = decltype(lc)::k;
+        constexpr double N2 = (double)(1L << (2 * (KT - l)));
+        *sA = scaled ? C(1) : C(N2);
+        *sW = scaled ? C(1) : C(1.0 / N2);
     };
     const C pf = scaled ? C(4) : C(1);
     // stencils on a padded array at flat index q with pitches 1, P, P^2
-    auto lap = [&](const C* a, long q, int P) -> C {
+    auto lap = [&](const C* a, int q, int P) -> C {
         C s = C(2 * D) * a[q] - a[q - 1] - a[q + 1] - a[q - P] - a[q + P];
-        if (D == 3) s -= a[q - (long)P * P] + a[q + (long)P * P];
+        if (D == 3) s -= a[q - P * P] + a[q + P * P];
         return s;
     };
     // the 19-/27-point 3D stencils: edge and corner terms
     const bool wide = D == 3 && (c2 != C(0) || c3 != C(0));
-    auto spai = [&](const C* a, long q, int P) -> C {
+    auto spai = [&](const C* a, int q, int P) -> C {
         C f = a[q - 1] + a[q + 1] + a[q - P] + a[q + P];
         if (D == 3) {
-            const long P2 = (long)P * P;
+            const int P2 = P * P;
             f += a[q - P2] + a[q + P2];
             if (!wide) return c0 * a[q] + c1 * f;
             const C ed = a[q - P - 1] + a[q - P + 1] + a[q + P - 1] + a[q + P + 1] +
@@ -2971,9 +2981,6 @@ k_tail(const S* __restrict__ bt, S* __restrict__ et, int nt, C c0, C c1, C c2, C
         const C cn = a[q - P - 1] + a[q - P + 1] + a[q + P - 1] + a[q + P + 1];
         return c0 * a[q] + c1 * f + c2 * cn;
     };
-    auto pidx = [&](int i, int j, int k, int P) -> long {
-        return D == 3 ? ((long)(k + 1) * P + j + 1) * P + i + 1 : (long)(j + 1) * P + i + 1;
-    };
     // runs f over the nodes of an n-grid, then a workgroup barrier
     auto nodes = [&](int n, auto&& f) {
         tail_for<D>(n, f);
@@ -2981,58 +2988,58 @@ k_tail(const S* __restrict__ bt, S* __restrict__ et, int nt, C c0, C c1, C c2, C
     };
     // ---- phases on level l (each ends with a barrier)
     // zero-guess pre-smoothing: E = sW K B
-    auto smooth_zero = [&](int l) {
-        const int n = nl(l), P = n + 2;
-        C* E = base(l);
-        const C* B = E + tail_padded(D, n);
+    auto smooth_zero = [&](auto lc) {
+        constexpr int l = decltype(lc)::k, n = G::n(l), P = G::P(l);
+        C* E = sm + G::base(l);
+        const C* B = E + G::pad(l);
         C sA, sW;
-        level_consts(l, &sA, &sW);
+        level_consts(lc, &sA, &sW);
         nodes(n, [&](int i, int j, int k) {
-            const long q = pidx(i, j, k, P);
+            const int q = pidx(i, j, k, P);
             E[q] = sW * spai(B, q, P);
         });
     };
     // R = B - sA A E
-    auto residual = [&](int l) {
-        const int n = nl(l), P = n + 2;
-        const C* E = base(l);
-        const C* B = E + tail_padded(D, n);
-        C* R = const_cast<C*>(B) + tail_padded(D, n);
+    auto residual = [&](auto lc) {
+        constexpr int l = decltype(lc)::k, n = G::n(l), P = G::P(l);
+        const C* E = sm + G::base(l);
+        const C* B = E + G::pad(l);
+        C* R = sm + G::base(l) + 2 * G::pad(l);
         C sA, sW;
-        level_consts(l, &sA, &sW);
+        level_consts(lc, &sA, &sW);
         nodes(n, [&](int i, int j, int k) {
-            const long q = pidx(i, j, k, P);
+            const int q = pidx(i, j, k, P);
             R[q] = B[q] - sA * lap(E, q, P);
         });
     };
     // E += sW K R (after residual)
-    auto update = [&](int l) {
-        const int n = nl(l), P = n + 2;
-        C* E = base(l);
-        const C* R = E + 2 * tail_padded(D, n);
+    auto update = [&](auto lc) {
+        constexpr int l = decltype(lc)::k, n = G::n(l), P = G::P(l);
+        C* E = sm + G::base(l);
+        const C* R = E + 2 * G::pad(l);
         C sA, sW;
-        level_consts(l, &sA, &sW);
+        level_consts(lc, &sA, &sW);
         nodes(n, [&](int i, int j, int k) {
-            const long q = pidx(i, j, k, P);
+            const int q = pidx(i, j, k, P);
             E[q] += sW * spai(R, q, P);
         });
     };
     // B_{l+1} = full weighting of R_l
-    auto restrict_r = [&](int l) {
-        const int n = nl(l), P = n + 2, nc = nl(l + 1), Pc = nc + 2;
-        const C* R = base(l) + 2 * tail_padded(D, n);
-        C* Bc = base(l + 1) + tail_padded(D, nc);
+    auto restrict_r = [&](auto lc) {
+        constexpr int l = decltype(lc)::k, P = G::P(l), nc = G::n(l + 1), Pc = G::P(l + 1);
+        const C* R = sm + G::base(l) + 2 * G::pad(l);
+        C* Bc = sm + G::base(l + 1) + G::pad(l + 1);
         nodes(nc, [&](int i, int j, int k) {
-            const long q = pidx(2 * i + 1, 2 * j + 1, D == 3 ? 2 * k + 1 : 0, P);
+            const int q = pidx(2 * i + 1, 2 * j + 1, D == 3 ? 2 * k + 1 : 0, P);
             C s;
             if (D == 2) {
                 s = C(0.25) * R[q] + C(0.125) * (R[q - 1] + R[q + 1] + R[q - P] + R[q + P]) +
                     C(0.0625) * (R[q - P - 1] + R[q - P + 1] + R[q + P - 1] + R[q + P + 1]);
             } else {
-                const long P2 = (long)P * P;
+                constexpr int P2 = P * P;
                 s = C(0);
                 for (int oz = -1; oz <= 1; ++oz) {
-                    const long qz = q + oz * P2;
+                    const int qz = q + oz * P2;
                     const C pl = C(0.25) * R[qz] +
                                  C(0.125) * (R[qz - 1] + R[qz + 1] + R[qz - P] + R[qz + P]) +
                                  C(0.0625) * (R[qz - P - 1] + R[qz - P + 1] + R[qz + P - 1] +
@@ -3045,9 +3052,9 @@ k_tail(const S* __restrict__ bt, S* __restrict__ et, int nt, C c0, C c1, C c2, C
     };
     // exact solve on the 3^d grid (level L-1) with the FP64 inverse
     auto exact = [&]() {
-        const int m = D == 2 ? 9 : 27, P = 5;
-        C* E = base(L - 1);
-        const C* B = E + tail_padded(D, 3);
+        constexpr int m = D == 2 ? 9 : 27, P = 5;
+        C* E = sm + G::base(L - 1);
+        const C* B = E + G::pad(L - 1);
         if (t < m) {
             const int i = t % 3, j = (t / 3) % 3, k = t / 9;
             double s = 0.0;
@@ -3063,10 +3070,10 @@ k_tail(const S* __restrict__ bt, S* __restrict__ et, int nt, C c0, C c1, C c2, C
     // coordinate i+1, takes the coarse node (i+1)/2 if even, the mean of
     // (i/2, i/2+1) if odd; in padded coarse coordinates the coarse node G
     // sits at index G, and the ring supplies the zero boundary values)
-    auto correct = [&](int l) {
-        const int n = nl(l), P = n + 2, nc = nl(l + 1), Pc = nc + 2;
-        C* E = base(l);
-        const C* Ec = base(l + 1);
+    auto correct = [&](auto lc) {
+        constexpr int l = decltype(lc)::k, n = G::n(l), P = G::P(l), Pc = G::P(l + 1);
+        C* E = sm + G::base(l);
+        const C* Ec = sm + G::base(l + 1);
         nodes(n, [&](int i, int j, int k) {
             const int gi = i + 1, gj = j + 1, gk = k + 1;
             const int ia = gi >> 1, ib = (gi + 1) >> 1;
@@ -3077,7 +3084,7 @@ k_tail(const S* __restrict__ bt, S* __restrict__ et, int nt, C c0, C c1, C c2, C
                                Ec[jb * Pc + ib]);
             } else {
                 const int ka = gk >> 1, kb = (gk + 1) >> 1;
-                const long P2 = (long)Pc * Pc;
+                constexpr int P2 = Pc * Pc;
                 v = C(0.125) * (Ec[ka * P2 + ja * Pc + ia] + Ec[ka * P2 + ja * Pc + ib] +
                                 Ec[ka * P2 + jb * Pc + ia] + Ec[ka * P2 + jb * Pc + ib] +
                                 Ec[kb * P2 + ja * Pc + ia] + Ec[kb * P2 + ja * Pc + ib] +
@@ -3088,159 +3095,58 @@ k_tail(const S* __restrict__ bt, S* __restrict__ et, int nt, C c0, C c1, C c2, C
     };
 
     if constexpr (!WC) {
-        // V(1,1) from a zero guess, written out level by level
-        for (int l = 0; l + 1 < L; ++l) {
-            const int n = nl(l), P = n + 2, nc = nl(l + 1), Pc = nc + 2;
-            C* E = base(l);
-            C* B = E + tail_padded(D, n);
-            C* R = B + tail_padded(D, n);
-            C* Bc = base(l + 1) + tail_padded(D, nc);
-            C sA, sW;
-            level_consts(l, &sA, &sW);
-            tail_for<D>(n, [&](int i, int j, int k) {
-                const long q = pidx(i, j, k, P);
-                E[q] = sW * spai(B, q, P);
-            });
-            __syncthreads();
-            tail_for<D>(n, [&](int i, int j, int k) {
-                const long q = pidx(i, j, k, P);
-                R[q] = B[q] - sA * lap(E, q, P);
-            });
-            __syncthreads();
-            tail_for<D>(nc, [&](int i, int j, int k) {
-                const long q = pidx(2 * i + 1, 2 * j + 1, D == 3 ? 2 * k + 1 : 0, P);
-                C s;
-                if (D == 2) {
-                    s = C(0.25) * R[q] + C(0.125) * (R[q - 1] + R[q + 1] + R[q - P] + R[q + P]) +
-                        C(0.0625) * (R[q - P - 1] + R[q - P + 1] + R[q + P - 1] + R[q + P + 1]);
-                } else {
-                    const long P2 = (long)P * P;
-                    s = C(0);
-                    for (int oz = -1; oz <= 1; ++oz) {
-                        const long qz = q + oz * P2;
-                        const C pl = C(0.25) * R[qz] +
-                                     C(0.125) * (R[qz - 1] + R[qz + 1] + R[qz - P] + R[qz + P]) +
-                                     C(0.0625) * (R[qz - P - 1] + R[qz - P + 1] + R[qz + P - 1] +
-                                                  R[qz + P + 1]);
-                        s += (oz == 0 ? C(0.5) : C(0.25)) * pl;
-                    }
-                }
-                Bc[pidx(i, j, k, Pc)] = s;
-            });
-            __syncthreads();
-        }
-        {
-            const int m = D == 2 ? 9 : 27, P = 5;
-            C* E = base(L - 1);
-            C* B = E + tail_padded(D, 3);
-            if (t < m) {
-                const int i = t % 3, j = (t / 3) % 3, k = t / 9;
-                double s = 0.0;
-                for (int q = 0; q < m; ++q) {
-                    const int qi = q % 3, qj = (q / 3) % 3, qk = q / 9;
-                    s += gl[t * m + q] * (double)B[pidx(qi, qj, qk, P)];
-                }
-                E[pidx(i, j, k, P)] = C(s);
+        // V(1,1) from a zero guess: down through the levels, the exact solve,
+        // back up, as compile-time recursion
+        auto visit = [&](auto self, auto lc) -> void {
+            constexpr int l = decltype(lc)::k;
+            if constexpr (l == L - 1) {
+                exact();
+            } else {
+                smooth_zero(lc);
+                residual(lc);
+                restrict_r(lc);
+                self(self, Par<l + 1>{});
+                correct(lc);
+                residual(lc);
+                update(lc);
             }
-            __syncthreads();
-        }
-        for (int l = L - 2; l >= 0; --l) {
-            const int n = nl(l), P = n + 2, nc = nl(l + 1), Pc = nc + 2;
-            C* E = base(l);
-            C* B = E + tail_padded(D, n);
-            C* R = B + tail_padded(D, n);
-            const C* Ec = base(l + 1);
-            C sA, sW;
-            level_consts(l, &sA, &sW);
-            // linear interpolation: fine node i (grid coordinate i+1) takes the
-            // coarse node (i+1)/2 if even, the mean of (i/2, i/2+1) if odd; in
-            // padded coarse coordinates the coarse node G sits at index G, and
-            // the ring supplies the zero boundary values
-            tail_for<D>(n, [&](int i, int j, int k) {
-                const int gi = i + 1, gj = j + 1, gk = k + 1;
-                const int ia = gi >> 1, ib = (gi + 1) >> 1;
-                const int ja = gj >> 1, jb = (gj + 1) >> 1;
-                C v;
-                if (D == 2) {
-                    v = C(0.25) * (Ec[ja * Pc + ia] + Ec[ja * Pc + ib] + Ec[jb * Pc + ia] +
-                                   Ec[jb * Pc + ib]);
-                } else {
-                    const int ka = gk >> 1, kb = (gk + 1) >> 1;
-                    const long P2 = (long)Pc * Pc;
-                    v = C(0.125) * (Ec[ka * P2 + ja * Pc + ia] + Ec[ka * P2 + ja * Pc + ib] +
-                                    Ec[ka * P2 + jb * Pc + ia] + Ec[ka * P2 + jb * Pc + ib] +
-                                    Ec[kb * P2 + ja * Pc + ia] + Ec[kb * P2 + ja * Pc + ib] +
-                                    Ec[kb * P2 + jb * Pc + ia] + Ec[kb * P2 + jb * Pc + ib]);
-                }
-                E[pidx(i, j, k, P)] += pf * v;
-            });
-            __syncthreads();
-            tail_for<D>(n, [&](int i, int j, int k) {
-                const long q = pidx(i, j, k, P);
-                R[q] = B[q] - sA * lap(E, q, P);
-            });
-            __syncthreads();
-            tail_for<D>(n, [&](int i, int j, int k) {
-                const long q = pidx(i, j, k, P);
-                E[q] += sW * spai(R, q, P);
-            });
-            __syncthreads();
-        }
+        };
+        visit(visit, Par<0>{});
     } else {
         // W(1,0): each visit of level l < L-1 pre-smooths (from zero on a
         // level's first visit, from its current E on the second), restricts,
-        // visits level l+1 twice and adds the interpolated correction.  The
-        // recursion runs as a loop over a level index with one pending-visit
-        // bit per level; all control is uniform across the workgroup.  A
+        // visits level l+1 twice and adds the interpolated correction.  A
         // second visit of the 3^d grid repeats an exact solve of unchanged
-        // data and is skipped.  The top level is visited wvisits times.
-        unsigned pending = wvisits > 1 ? 1u : 0u;
-        int l = 0;
-        bool zero = true;
-        for (;;) {
-            while (l + 1 < L) {
-                if (zero) {
-                    smooth_zero(l);
+        // data and is skipped.  The top level is visited wvisits times.  The
+        // visit order is compile-time recursion; `first` is uniform.
+        auto visit = [&](auto self, auto lc, bool first) -> void {
+            constexpr int l = decltype(lc)::k;
+            if constexpr (l == L - 1) {
+                if (first) exact();
+            } else {
+                if (first) {
+                    smooth_zero(lc);
                 } else {
-                    residual(l);
-                    update(l);
+                    residual(lc);
+                    update(lc);
                 }
-                residual(l);
-                restrict_r(l);
-                ++l;
-                zero = true;
-                pending |= 1u << l;
+                residual(lc);
+                restrict_r(lc);
+                self(self, Par<l + 1>{}, true);
+                self(self, Par<l + 1>{}, false);
+                correct(lc);
             }
-            exact();
-            // a visit of level l has finished: revisit it, or close the
-            // parent's visit with the correction and go up
-            bool done = false;
-            for (;;) {
-                const unsigned bit = 1u << l;
-                if ((pending & bit) && l + 1 < L) {
-                    pending &= ~bit;
-                    zero = false;
-                    break;
-                }
-                pending &= ~bit;
-                if (l == 0) {
-                    done = true;
-                    break;
-                }
-                correct(l - 1);
-                --l;
-            }
-            if (done) break;
-        }
+        };
+        visit(visit, Par<0>{}, true);
+        if (wvisits > 1) visit(visit, Par<0>{}, false);
     }
     __syncthreads();
     {
         const long off = (long)blockIdx.x * (D == 3 ? (long)nt * nt * nt : (long)nt * nt);
-        const C* E = base(0);
-        const int P = nt + 2;
+        const C* E = sm;
         tail_for<D>(nt, [&](int i, int j, int k) {
             const long g = D == 3 ? ((long)k * nt + j) * nt + i : (long)j * nt + i;
-            et[off + g] = static_cast<S>(E[pidx(i, j, k, P)]);
+            et[off + g] = static_cast<S>(E[pidx(i, j, k, G::P(0))]);
         });
     }
 }
@@ -3800,29 +3706,43 @@ hipError_t prolong_impl(int d, int n, int batch, const void* ec, const void* in,
     return hipGetLastError();
 }
 
-template <typename S, typename C, int D>
-hipError_t tail_impl_d(const Tail& t, size_t lds, hipStream_t st) {
-    static bool attr_set = false;
+template <typename S, typename C, int D, bool WC, int KT>
+hipError_t tail_launch(const Tail& t, size_t lds, hipStream_t st) {
+    static bool attr_set = false;  // the dynamic LDS limit, once per instantiation
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_tail<S, C, D, false>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           160 * 1024);
-        if (e == hipSuccess)
-            e = hipFuncSetAttribute((const void*)k_tail<S, C, D, true>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        const hipError_t e = hipFuncSetAttribute((const void*)k_tail<S, C, D, WC, KT>,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 160 * 1024);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    if (t.wvisits > 0)
-        mg_launch((k_tail<S, C, D, true>), dim3(t.batch), dim3(1024), lds, st,
-                           static_cast<const S*>(t.b), static_cast<S*>(t.e), t.nt, C(t.c[0]),
-                           C(t.c[1]), C(t.c[2]), C(t.c[3]), t.ginv, t.scaled ? 1 : 0, t.N_top,
-                           t.wvisits);
-    else
-        mg_launch((k_tail<S, C, D, false>), dim3(t.batch), dim3(1024), lds, st,
-                           static_cast<const S*>(t.b), static_cast<S*>(t.e), t.nt, C(t.c[0]),
-                           C(t.c[1]), C(t.c[2]), C(t.c[3]), t.ginv, t.scaled ? 1 : 0, t.N_top, 0);
+    mg_launch((k_tail<S, C, D, WC, KT>), dim3(t.batch), dim3(1024), lds, st,
+              static_cast<const S*>(t.b), static_cast<S*>(t.e), C(t.c[0]), C(t.c[1]),
+              C(t.c[2]), C(t.c[3]), t.ginv, t.scaled ? 1 : 0, WC ? t.wvisits : 0);
     return hipGetLastError();
+}
+
+// the top tail level has nt = 2^KT - 1 nodes per direction (3 .. 63 in 2D,
+// 3 .. 15 in 3D), a compile-time parameter of the kernel
+template <typename S, typename C, int D, bool WC>
+hipError_t tail_impl_w(const Tail& t, size_t lds, hipStream_t st) {
+    switch (t.nt) {
+        case 3: return tail_launch<S, C, D, WC, 2>(t, lds, st);
+        case 7: return tail_launch<S, C, D, WC, 3>(t, lds, st);
+        case 15: return tail_launch<S, C, D, WC, 4>(t, lds, st);
+        default: break;
+    }
+    if constexpr (D == 2) {
+        if (t.nt == 31) return tail_launch<S, C, D, WC, 5>(t, lds, st);
+        if (t.nt == 63) return tail_launch<S, C, D, WC, 6>(t, lds, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename S, typename C, int D>
+hipError_t tail_impl_d(const Tail& t, size_t lds, hipStream_t st) {
+    return t.wvisits > 0 ? tail_impl_w<S, C, D, true>(t, lds, st)
+                         : tail_impl_w<S, C, D, false>(t, lds, st);
 }
 
 template <typename S, typename C>
