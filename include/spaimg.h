@@ -66,7 +66,7 @@ extern "C" {
 #define MG_OPT_TAIL_N 4     /* largest coarse grid (intervals, power of two,
                                4..64 in 2D, 4..16 in 3D) solved by the
                                single-workgroup LDS tail kernel; 0 = default:
-                               64 in 2D (32 for W(1,0) cycles), 16 in 3D      */
+                               64 in 2D, 16 in 3D                             */
 #define MG_OPT_TIMING 5     /* 0 off; 1 time the fine level's fused
                                pre-smoother + restriction with HIP events;
                                2 time every kernel of every level; 3 as 1,

@@ -114,14 +114,14 @@ long level_pts(const mg_ctx* h, int l) {
 int level_n(const mg_ctx* h, int l) { return (h->N >> l) - 1; }
 int level_N(const mg_ctx* h, int l) { return h->N >> l; }
 
-// largest grid of the LDS tail (intervals): 64^2 / 16^3 for V-cycles.  A
-// 2D W(1,0) cycle enters the tail once per visit of the level above it, and
-// a 64^2 tail runs its top level twice in a row inside one workgroup; a 32^2
-// tail with the 64^2 level launched across the chip is faster (about 7% of
-// a 2D N=4096 W solve, measured).
+// largest grid of the LDS tail (intervals): 64^2 / 16^3 for V(1,1) and
+// W(1,0) cycles.  Measured on a 2D N=4096 W(1,0) solve: a 64^2 tail (its
+// top level visited twice inside the workgroup) 30.0 ms, 32^2 with the 64^2
+// level launched across the chip 33.4 ms, 16^2 43.1 ms; 3D N=256: 16^3
+// 14.6 ms against 17.7 ms for 8^3.
 int default_tail_N(int d, int cycle_kind) {
-    if (d == 2) return cycle_kind == MG_CYCLE_W10 ? 32 : 64;
-    return 16;
+    (void)cycle_kind;
+    return d == 2 ? 64 : 16;
 }
 
 // low-precision V-cycles per FP64 refinement step.  FP32: six reach about

@@ -117,6 +117,33 @@ __device__ __forceinline__ rsrc_t line_rsrc(const S* base, long first, long len,
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<S*>(in ? base + first : base), 0,
                                              in ? (int)(len * (long)sizeof(S)) : 0, kRsrcWord3);
 }
+// A window of lines [first, first + count) of one field under a single
+// buffer resource, built once per workgroup: a line is then addressed by a
+// 32-bit offset (one scalar multiply) instead of a resource of its own (a
+// 64-bit address, two selects and the descriptor words per line and field).
+// A line outside the caller's range gets offset kOobLine: added to an
+// in-line offset (below one line's bytes) or to kOob it stays at or above
+// num_records and below 2^32, so it reads zero and drops stores like an
+// empty line; kOob added to an in-range line's offset does the same.  The
+// host keeps count * line bytes <= kWinMax.
+constexpr unsigned kOobLine = 0x7FF00000u;
+constexpr long kWinMax = kOobLine;
+template <typename S>
+struct Win {
+    rsrc_t r;
+    int first;
+    int lb;  // line bytes
+    __device__ __forceinline__ Win(const S* base, long len, int first_, int count)
+        : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<S*>(base + (long)first_ * len), 0,
+                                              count > 0 ? (int)(count * len * (long)sizeof(S)) : 0,
+                                              kRsrcWord3)),
+          first(first_), lb((int)(len * (long)sizeof(S))) {}
+    // line p's offset; `in` must imply first <= p < first + count
+    __device__ __forceinline__ unsigned at(int p, bool in) const {
+        return in ? (unsigned)((p - first) * lb) : kOobLine;
+    }
+};
+
 template <typename S>
 __device__ __forceinline__ S bload(rsrc_t r, unsigned off);
 template <>
@@ -357,10 +384,19 @@ k_smooth3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out
             cgb[j] = ok ? (unsigned)((gy * nc + gx) * (int)sizeof(S)) : kOob;
         }
     }
+    // planes any output depends on: v up to z1 + 1, b up to z1, coarse
+    // planes up to (z1 + 1) / 2 (later planes read as zero); one window of
+    // fine planes z0 - 2 .. ulast serves every fine field
+    const int ulast = min(n - 1, z1 + 1), blast = min(n - 1, z1);
+    const int clast = min(nc - 1, z1 / 2 + 1), cf0 = max(0, z0 / 2 - 2);
+    const int f0 = max(0, z0 - 2), fcnt = ulast - f0 + 1;
+    const Win<S> wu(ZG ? b : u, plane, f0, fcnt), wb(b, plane, f0, fcnt);
+    const Win<S> wo(out, plane, f0, fcnt), wro(ROUT ? rout : out, plane, f0, fcnt);
+    const Win<S> wec(PRO ? ec : b, cplane, cf0, clast - cf0 + 1);
     auto c_issue = [&](int Z, int sl) {
-        const rsrc_t r = line_rsrc(ec, (long)Z * cplane, cplane, Z >= 0 && Z < nc);
+        const unsigned o = wec.at(Z, Z >= 0 && Z <= clast);
 #pragma unroll
-        for (int j = 0; j < MC; ++j) rc[sl][j] = bload<S>(r, cgb[j]);
+        for (int j = 0; j < MC; ++j) rc[sl][j] = bload<S>(wec.r, o + cgb[j]);
     };
     auto c_write = [&](int sl) {
 #pragma unroll
@@ -389,15 +425,15 @@ k_smooth3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out
     static_assert(UN % RS == 0 && UN % 2 == 0, "unroll covers the prefetch ring and parity");
     S ru[RS][M], rb[RS][M], rr2[RS];
     auto issue_u = [&](int p, int k) {
-        const rsrc_t r = line_rsrc(u, (long)p * plane, plane, p >= 0 && p < n);
+        const unsigned o = wu.at(p, p >= 0 && p <= ulast);
 #pragma unroll
-        for (int m = 0; m < M; ++m) ru[k][m] = bload<S>(r, gb[m]);
-        rr2[k] = bload<S>(r, r2b);
+        for (int m = 0; m < M; ++m) ru[k][m] = bload<S>(wu.r, o + gb[m]);
+        rr2[k] = bload<S>(wu.r, o + r2b);
     };
     auto issue_b = [&](int p, int k) {
-        const rsrc_t r = line_rsrc(b, (long)p * plane, plane, p >= 0 && p < n);
+        const unsigned o = wb.at(p, p >= 0 && p <= blast);
 #pragma unroll
-        for (int m = 0; m < M; ++m) rb[k][m] = bload<S>(r, gb[m]);
+        for (int m = 0; m < M; ++m) rb[k][m] = bload<S>(wb.r, o + gb[m]);
     };
     // consume raw plane p: v = u + pf * P ec; qh holds the bilinear coarse
     // values of plane p/2 when p is even
@@ -439,10 +475,10 @@ k_smooth3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out
 #pragma unroll
             for (int q = 0; q < 3; ++q) {
                 const int p = s0 - 1 + q;
-                const rsrc_t r = line_rsrc(u, (long)p * plane, plane, p >= 0 && p < n);
+                const unsigned o = wu.at(p, p >= 0 && p <= ulast);
 #pragma unroll
-                for (int m = 0; m < M; ++m) pu[q][m] = bload<S>(r, gb[m]);
-                pr2[q] = bload<S>(r, r2b);
+                for (int m = 0; m < M; ++m) pu[q][m] = bload<S>(wu.r, o + gb[m]);
+                pr2[q] = bload<S>(wu.r, o + r2b);
             }
         }
         C qs[3][M + 1];
@@ -452,9 +488,9 @@ k_smooth3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out
 #pragma unroll
             for (int q = 0; q < 3; ++q) {
                 const int Z = Zb - 1 + q;
-                const rsrc_t r = line_rsrc(ec, (long)Z * cplane, cplane, Z >= 0 && Z < nc);
+                const unsigned o = wec.at(Z, Z >= 0 && Z <= clast);
 #pragma unroll
-                for (int j = 0; j < MC; ++j) pc[q][j] = bload<S>(r, cgb[j]);
+                for (int j = 0; j < MC; ++j) pc[q][j] = bload<S>(wec.r, o + cgb[j]);
             }
             C* cs = &rL[0][0];
 #pragma unroll
@@ -528,7 +564,7 @@ k_smooth3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out
                 const C* Rm = rL[(s - 3) & 3];
                 const C* R0 = rL[(s - 2) & 3];
                 const C* Rp = rL[(s - 1) & 3];
-                const rsrc_t ro = line_rsrc(out, (long)p * plane, plane, true);
+                const unsigned ro = wo.at(p, true);
 #pragma unroll
                 for (int m = 0; m < M; ++m) {
                     const int q = RP + t + m * NT;
@@ -542,10 +578,9 @@ k_smooth3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out
                                  Rp[q + RX - 1] + Rp[q + RX + 1];
                     const C v = (ZG ? C(0) : um2[m]) +
                                 sW * (c0 * rc0 + c1 * fc + c2 * ed + c3 * cn);
-                    bstore<NTS>(static_cast<S>(v), ro, inn[m] ? gb[m] : kOob);
+                    bstore<NTS>(static_cast<S>(v), wo.r, ro + (inn[m] ? gb[m] : kOob));
                     if (ROUT)
-                        bstore<false>(static_cast<S>(rc0), line_rsrc(rout, (long)p * plane, plane,
-                                                                     true), inn[m] ? gb[m] : kOob);
+                        bstore<false>(static_cast<S>(rc0), wro.r, ro + (inn[m] ? gb[m] : kOob));
                     if (NORM) nacc += inn[m] ? (double)rc0 * (double)rc0 : 0.0;
                 }
             }
@@ -554,17 +589,16 @@ k_smooth3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out
             const int p = s - 1;
             if (p >= z0 && p < z1) {
                 const C* R = rL[cur ^ 1];
-                const rsrc_t ro = line_rsrc(out, (long)p * plane, plane, true);
+                const unsigned ro = wo.at(p, true);
 #pragma unroll
                 for (int m = 0; m < M; ++m) {
                     const int q = RP + t + m * NT;
                     const C rc0 = rm1[m];
                     const C nbs = R[q - 1] + R[q + 1] + R[q - RX] + R[q + RX] + rm2[m] + r0[m];
                     const C v = (ZG ? C(0) : um1[m]) + sW * (c0 * rc0 + c1 * nbs);
-                    bstore<NTS>(static_cast<S>(v), ro, inn[m] ? gb[m] : kOob);
+                    bstore<NTS>(static_cast<S>(v), wo.r, ro + (inn[m] ? gb[m] : kOob));
                     if (ROUT)
-                        bstore<false>(static_cast<S>(rc0), line_rsrc(rout, (long)p * plane, plane,
-                                                                     true), inn[m] ? gb[m] : kOob);
+                        bstore<false>(static_cast<S>(rc0), wro.r, ro + (inn[m] ? gb[m] : kOob));
                     if (NORM) nacc += inn[m] ? (double)rc0 * (double)rc0 : 0.0;
                 }
             }
@@ -691,10 +725,19 @@ k_smooth2d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out
             cgb[j] = (i < CX && gx >= 0 && gx < nc) ? (unsigned)(gx * (int)sizeof(S)) : kOob;
         }
     }
+    // rows any output depends on: v up to y1 + 1, b up to y1, coarse rows
+    // up to (y1 + 1) / 2 (later rows read as zero); one window of fine rows
+    // y0 - 2 .. ulast serves every fine field
+    const int ulast = min(n - 1, y1 + 1), blast = min(n - 1, y1);
+    const int clast = min(nc - 1, y1 / 2 + 1), cf0 = max(0, y0 / 2 - 2);
+    const int f0 = max(0, y0 - 2), fcnt = ulast - f0 + 1;
+    const Win<S> wu(ZG ? b : u, n, f0, fcnt), wb(b, n, f0, fcnt);
+    const Win<S> wo(out, n, f0, fcnt), wro(ROUT ? rout : out, n, f0, fcnt);
+    const Win<S> wec(PRO ? ec : b, nc, cf0, clast - cf0 + 1);
     auto c_issue = [&](int Y, int sl) {
-        const rsrc_t r = line_rsrc(ec, (long)Y * nc, nc, Y >= 0 && Y < nc);
+        const unsigned o = wec.at(Y, Y >= 0 && Y <= clast);
 #pragma unroll
-        for (int j = 0; j < MC; ++j) rc[sl][j] = bload<S>(r, cgb[j]);
+        for (int j = 0; j < MC; ++j) rc[sl][j] = bload<S>(wec.r, o + cgb[j]);
     };
     auto c_write = [&](int sl) {
 #pragma unroll
@@ -716,15 +759,15 @@ k_smooth2d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out
     static_assert(UN % RS == 0 && UN % 2 == 0, "unroll covers the prefetch ring and parity");
     S ru[RS][M], rb[RS][M], rr2[RS];
     auto issue_u = [&](int p, int k) {
-        const rsrc_t r = line_rsrc(u, (long)p * n, n, p >= 0 && p < n);
+        const unsigned o = wu.at(p, p >= 0 && p <= ulast);
 #pragma unroll
-        for (int m = 0; m < M; ++m) ru[k][m] = bload<S>(r, gb[m]);
-        rr2[k] = bload<S>(r, r2b);
+        for (int m = 0; m < M; ++m) ru[k][m] = bload<S>(wu.r, o + gb[m]);
+        rr2[k] = bload<S>(wu.r, o + r2b);
     };
     auto issue_b = [&](int p, int k) {
-        const rsrc_t r = line_rsrc(b, (long)p * n, n, p >= 0 && p < n);
+        const unsigned o = wb.at(p, p >= 0 && p <= blast);
 #pragma unroll
-        for (int m = 0; m < M; ++m) rb[k][m] = bload<S>(r, gb[m]);
+        for (int m = 0; m < M; ++m) rb[k][m] = bload<S>(wb.r, o + gb[m]);
     };
     auto take_raw = [&](int p, const S* raw, S raw2, const C* qh, C* dst, C& rdst) {
 #pragma unroll
@@ -761,10 +804,10 @@ k_smooth2d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out
 #pragma unroll
             for (int q = 0; q < 3; ++q) {
                 const int p = s0 - 1 + q;
-                const rsrc_t r = line_rsrc(u, (long)p * n, n, p >= 0 && p < n);
+                const unsigned o = wu.at(p, p >= 0 && p <= ulast);
 #pragma unroll
-                for (int m = 0; m < M; ++m) pu[q][m] = bload<S>(r, gb[m]);
-                pr2[q] = bload<S>(r, r2b);
+                for (int m = 0; m < M; ++m) pu[q][m] = bload<S>(wu.r, o + gb[m]);
+                pr2[q] = bload<S>(wu.r, o + r2b);
             }
         }
         C qs[3][M + 1];
@@ -774,9 +817,9 @@ k_smooth2d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out
 #pragma unroll
             for (int q = 0; q < 3; ++q) {
                 const int Y = Yb - 1 + q;
-                const rsrc_t r = line_rsrc(ec, (long)Y * nc, nc, Y >= 0 && Y < nc);
+                const unsigned o = wec.at(Y, Y >= 0 && Y <= clast);
 #pragma unroll
-                for (int j = 0; j < MC; ++j) pc[q][j] = bload<S>(r, cgb[j]);
+                for (int j = 0; j < MC; ++j) pc[q][j] = bload<S>(wec.r, o + cgb[j]);
             }
             C* cs = &rL[0][0];
 #pragma unroll
@@ -844,7 +887,7 @@ k_smooth2d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out
             const C* R0 = rL[(p + 3) & 3];  // row p - 1
             const C* R1 = rL[(p + 4) & 3];  // row p
             const C* R2 = rL[(p + 5) & 3];  // row p + 1
-            const rsrc_t ro = line_rsrc(out, (long)p * n, n, true);
+            const unsigned ro = wo.at(p, true);
 #pragma unroll
             for (int m = 0; m < M; ++m) {
                 const int q = 1 + t + m * NT;
@@ -852,10 +895,9 @@ k_smooth2d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out
                 const C fc = R1[q - 1] + R1[q + 1] + R0[q] + R2[q];
                 const C cn = R0[q - 1] + R0[q + 1] + R2[q - 1] + R2[q + 1];
                 const C v = (ZG ? C(0) : um2[m]) + sW * (c0 * rcc + c1 * fc + c2 * cn);
-                bstore<NTS>(static_cast<S>(v), ro, inn[m] ? gb[m] : kOob);
+                bstore<NTS>(static_cast<S>(v), wo.r, ro + (inn[m] ? gb[m] : kOob));
                 if (ROUT)
-                    bstore<false>(static_cast<S>(rcc), line_rsrc(rout, (long)p * n, n, true),
-                                  inn[m] ? gb[m] : kOob);
+                    bstore<false>(static_cast<S>(rcc), wro.r, ro + (inn[m] ? gb[m] : kOob));
                 if (NORM) nacc += inn[m] ? (double)rcc * (double)rcc : 0.0;
             }
         }
@@ -1676,17 +1718,22 @@ k_sr2d(const SU* __restrict__ u, const S* __restrict__ b, S* __restrict__ out,
     // whole unrolled groups and the prefetch run past them, and rows
     // outside these ranges read as zero without touching memory
     const int ulast = min(n - 1, 2 * Y1 + 3), blast = min(n - 1, 2 * Y1 + 2);
+    // one window of fine rows 2 Y0 - 3 .. ulast serves every fine field
+    const int f0 = max(0, 2 * Y0 - 3), fcnt = ulast - f0 + 1;
+    const Win<SU> wu(u, n, f0, fcnt);
+    const Win<S> wb(b, n, f0, fcnt), wo(out, n, f0, fcnt);
+    const Win<S> wro(ROUT ? rout : out, n, f0, fcnt), wbc(bc, nc, Y0, Y1 - Y0);
     SU ru[RS][M];
     S rb[RS][M];
     auto issue_u = [&](int p, int k) {
-        const rsrc_t r = line_rsrc(u, (long)p * n, n, p >= 0 && p <= ulast);
+        const unsigned o = wu.at(p, p >= 0 && p <= ulast);
 #pragma unroll
-        for (int m = 0; m < M; ++m) ru[k][m] = bload<SU>(r, gu[m]);
+        for (int m = 0; m < M; ++m) ru[k][m] = bload<SU>(wu.r, o + gu[m]);
     };
     auto issue_b = [&](int p, int k) {
-        const rsrc_t r = line_rsrc(b, (long)p * n, n, p >= 0 && p <= blast);
+        const unsigned o = wb.at(p, p >= 0 && p <= blast);
 #pragma unroll
-        for (int m = 0; m < M; ++m) rb[k][m] = bload<S>(r, gb[m]);
+        for (int m = 0; m < M; ++m) rb[k][m] = bload<S>(wb.r, o + gb[m]);
     };
 
     // u rows s-2..s+1, b rows s-1..s-3, residual rows s-1..s-3 and new
@@ -1704,9 +1751,9 @@ k_sr2d(const SU* __restrict__ u, const S* __restrict__ b, S* __restrict__ out,
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
             const int p = s0 - 1 + q;
-            const rsrc_t r = line_rsrc(u, (long)p * n, n, p >= 0 && p < n);
+            const unsigned o = wu.at(p, p >= 0 && p <= ulast);
 #pragma unroll
-            for (int m = 0; m < M; ++m) pu[q][m] = bload<SU>(r, gu[m]);
+            for (int m = 0; m < M; ++m) pu[q][m] = bload<SU>(wu.r, o + gu[m]);
         }
 #pragma unroll
         for (int q = 0; q < PD; ++q) {
@@ -1748,13 +1795,13 @@ k_sr2d(const SU* __restrict__ u, const S* __restrict__ b, S* __restrict__ out,
             rL[s & 3][q] = r;
             if (NORM) nacc += (sown && own[m]) ? (double)r * (double)r : 0.0;
             if (ROUT)
-                bstore<false>(static_cast<S>(r), line_rsrc(rout, (long)s * n, n, sown),
-                              own[m] ? gb[m] : kOob);
+                bstore<false>(static_cast<S>(r), wro.r,
+                              wro.at(s, sown) + (own[m] ? gb[m] : kOob));
         }
         // new iterate of row s-2 (residual rows s-3, s-2, s-1)
         const int p = s - 2;
         const bool pin = p >= 0 && p < n;
-        const rsrc_t ro = line_rsrc(out, (long)p * n, n, p >= o0 && p < o1);
+        const unsigned ro = wo.at(p, p >= o0 && p < o1);
         C v0[M];
         {
             const C* R0 = rL[(s + 1) & 3];  // row s - 3
@@ -1767,7 +1814,7 @@ k_sr2d(const SU* __restrict__ u, const S* __restrict__ b, S* __restrict__ out,
                 const C cn = R0[q - 1] + R0[q + 1] + R2[q - 1] + R2[q + 1];
                 const C v = um2[m] + sW * (c0 * r2[m] + c1 * fc + c2 * cn);
                 const S vs = static_cast<S>(v);
-                bstore<NTS>(vs, ro, own[m] ? gb[m] : kOob);
+                bstore<NTS>(vs, wo.r, ro + (own[m] ? gb[m] : kOob));
                 v0[m] = (pin && col[m]) ? cvt<C>(vs) : C(0);
                 vL[p & 1][q] = v0[m];
             }
@@ -1786,7 +1833,7 @@ k_sr2d(const SU* __restrict__ u, const S* __restrict__ b, S* __restrict__ out,
         const int f = s - 4;
         if (f >= 2 * Y0 && f <= 2 * Y1) {
             const C* R = wL[f & 1];
-            const rsrc_t rc = line_rsrc(bc, (long)(f / 2 - 1) * nc, nc, true);
+            const unsigned rc = wbc.at(f / 2 - 1, true);
 #pragma unroll
             for (int q = 0; q < MC; ++q) {
                 const int c = cq[q];
@@ -1794,7 +1841,7 @@ k_sr2d(const SU* __restrict__ u, const S* __restrict__ b, S* __restrict__ out,
                 if ((f & 1) == 0) {
                     if (f > 2 * Y0) {
                         acc[q] += C(0.25) * xs;
-                        bstore<false>(static_cast<S>(acc[q]), rc, cgb[q]);
+                        bstore<false>(static_cast<S>(acc[q]), wbc.r, rc + cgb[q]);
                     }
                     acc[q] = C(0.25) * xs;
                 } else {
@@ -1913,26 +1960,32 @@ k_psr2d(const S* __restrict__ t, const S* __restrict__ ec, const S* __restrict__
         cgb[q] = ok ? (unsigned)((x0 / 2 + i) * (int)sizeof(S)) : kOob;
     }
 
-    // rows any output depends on
+    // rows any output depends on, and the windows holding them: fine rows
+    // 2 Y0 - 5 .. tlast (every row read or written), coarse correction rows
+    // Y0 - 3 .. clast, coarse right-hand side rows Y0 .. Y1 - 1
     const int tlast = min(n - 1, 2 * Y1 + 5), blast = min(n - 1, 2 * Y1 + 4);
     const int clast = min(nc - 1, Y1 + 2);
+    const int f0 = max(0, 2 * Y0 - 5), c0r = max(0, Y0 - 3);
+    const Win<S> wt(t, n, f0, tlast - f0 + 1), wb(b, n, f0, tlast - f0 + 1);
+    const Win<S> wuo(uo, n, f0, tlast - f0 + 1), wt2(t2, n, f0, tlast - f0 + 1);
+    const Win<S> wec(ec, nc, c0r, clast - c0r + 1), wbc(bc, nc, Y0, Y1 - Y0);
     S rt[RS][M], rb[RS][M], rca[2][M], rcb[2][M];
     auto issue_t = [&](int p, int k) {
-        const rsrc_t r = line_rsrc(t, (long)p * n, n, p >= 0 && p <= tlast);
+        const unsigned o = wt.at(p, p >= 0 && p <= tlast);
 #pragma unroll
-        for (int m = 0; m < M; ++m) rt[k][m] = bload<S>(r, gb[m]);
+        for (int m = 0; m < M; ++m) rt[k][m] = bload<S>(wt.r, o + gb[m]);
     };
     auto issue_b = [&](int p, int k) {
-        const rsrc_t r = line_rsrc(b, (long)p * n, n, p >= 0 && p <= blast);
+        const unsigned o = wb.at(p, p >= 0 && p <= blast);
 #pragma unroll
-        for (int m = 0; m < M; ++m) rb[k][m] = bload<S>(r, gb[m]);
+        for (int m = 0; m < M; ++m) rb[k][m] = bload<S>(wb.r, o + gb[m]);
     };
     auto issue_c = [&](int Y, int k) {
-        const rsrc_t r = line_rsrc(ec, (long)Y * nc, nc, Y >= 0 && Y <= clast);
+        const unsigned o = wec.at(Y, Y >= 0 && Y <= clast);
 #pragma unroll
         for (int m = 0; m < M; ++m) {
-            rca[k][m] = bload<S>(r, ca[m]);
-            rcb[k][m] = bload<S>(r, cb[m]);
+            rca[k][m] = bload<S>(wec.r, o + ca[m]);
+            rcb[k][m] = bload<S>(wec.r, o + cb[m]);
         }
     };
     // x-interpolated coarse value (the same sums as the interpolation operator)
@@ -1958,11 +2011,11 @@ k_psr2d(const S* __restrict__ t, const S* __restrict__ ec, const S* __restrict__
         S pa[M], pb[M];
         {
             const int Y = Y0 - 3;
-            const rsrc_t r = line_rsrc(ec, (long)Y * nc, nc, Y >= 0 && Y <= clast);
+            const unsigned o = wec.at(Y, Y >= 0 && Y <= clast);
 #pragma unroll
             for (int m = 0; m < M; ++m) {
-                pa[m] = bload<S>(r, ca[m]);
-                pb[m] = bload<S>(r, cb[m]);
+                pa[m] = bload<S>(wec.r, o + ca[m]);
+                pb[m] = bload<S>(wec.r, o + cb[m]);
             }
         }
         issue_c(Y0 - 2, 0);
@@ -2038,7 +2091,7 @@ k_psr2d(const S* __restrict__ t, const S* __restrict__ ec, const S* __restrict__
             const C* R0 = aL[(s + 0) & 3];  // row s - 4
             const C* R1 = aL[(s + 1) & 3];  // row s - 3
             const C* R2 = aL[(s + 2) & 3];  // row s - 2
-            const rsrc_t ro = line_rsrc(uo, (long)p * n, n, p >= o0 && p < o1);
+            const unsigned ro = wuo.at(p, p >= o0 && p < o1);
 #pragma unroll
             for (int m = 0; m < M; ++m) {
                 const int q = li[m];
@@ -2047,7 +2100,7 @@ k_psr2d(const S* __restrict__ t, const S* __restrict__ ec, const S* __restrict__
                 const C cn = R0[q - 1] + R0[q + 1] + R2[q - 1] + R2[q + 1];
                 const C v = w3[m] + sW * (c0 * a3[m] + c1 * fc + c2 * cn);
                 const S vs = static_cast<S>(v);
-                bstore<NTS>(vs, ro, own[m] ? gb[m] : kOob);
+                bstore<NTS>(vs, wuo.r, ro + (own[m] ? gb[m] : kOob));
                 kn[m] = (pin && col[m]) ? cvt<C>(vs) : C(0);
                 kL[p & 1][q] = kn[m];
             }
@@ -2078,7 +2131,7 @@ k_psr2d(const S* __restrict__ t, const S* __restrict__ ec, const S* __restrict__
             const C* Q0 = gL[(s + 1) & 3];  // row s - 7
             const C* Q1 = gL[(s + 2) & 3];  // row s - 6
             const C* Q2 = gL[(s + 3) & 3];  // row s - 5
-            const rsrc_t ro = line_rsrc(t2, (long)p * n, n, p >= o0 && p < o1);
+            const unsigned ro = wt2.at(p, p >= o0 && p < o1);
 #pragma unroll
             for (int m = 0; m < M; ++m) {
                 const int q = li[m];
@@ -2087,7 +2140,7 @@ k_psr2d(const S* __restrict__ t, const S* __restrict__ ec, const S* __restrict__
                 const C cn = Q0[q - 1] + Q0[q + 1] + Q2[q - 1] + Q2[q + 1];
                 const C v = k3[m] + sW * (c0 * g3[m] + c1 * fc + c2 * cn);
                 const S vs = static_cast<S>(v);
-                bstore<NTS>(vs, ro, own[m] ? gb[m] : kOob);
+                bstore<NTS>(vs, wt2.r, ro + (own[m] ? gb[m] : kOob));
                 on[m] = (pin && col[m]) ? cvt<C>(vs) : C(0);
                 oL[p & 1][q] = on[m];
             }
@@ -2106,7 +2159,7 @@ k_psr2d(const S* __restrict__ t, const S* __restrict__ ec, const S* __restrict__
         const int f = s - 8;
         if (f >= 2 * Y0 && f <= 2 * Y1) {
             const C* R = fL[f & 1];
-            const rsrc_t rc = line_rsrc(bc, (long)(f / 2 - 1) * nc, nc, true);
+            const unsigned rc = wbc.at(f / 2 - 1, true);
 #pragma unroll
             for (int q = 0; q < MC; ++q) {
                 const int c = cq[q];
@@ -2114,7 +2167,7 @@ k_psr2d(const S* __restrict__ t, const S* __restrict__ ec, const S* __restrict__
                 if ((f & 1) == 0) {
                     if (f > 2 * Y0) {
                         acc[q] += C(0.25) * xs;
-                        bstore<false>(static_cast<S>(acc[q]), rc, cgb[q]);
+                        bstore<false>(static_cast<S>(acc[q]), wbc.r, rc + cgb[q]);
                     }
                     acc[q] = C(0.25) * xs;
                 } else {
@@ -2232,19 +2285,24 @@ k_sr3d(const SU* __restrict__ u, const S* __restrict__ b, S* __restrict__ out,
     }
 
     // planes any output depends on: u up to 2 Z1 + 3, b up to 2 Z1 + 2 (as
-    // in 2D, later planes read as zero without touching memory)
+    // in 2D, later planes read as zero without touching memory); one window
+    // of fine planes 2 Z0 - 3 .. ulast serves every fine field
     const int ulast = min(n - 1, 2 * Z1 + 3), blast = min(n - 1, 2 * Z1 + 2);
+    const int f0 = max(0, 2 * Z0 - 3), fcnt = ulast - f0 + 1;
+    const Win<SU> wu(u, plane, f0, fcnt);
+    const Win<S> wb(b, plane, f0, fcnt), wo(out, plane, f0, fcnt);
+    const Win<S> wro(ROUT ? rout : out, plane, f0, fcnt), wbc(bc, cplane, Z0, Z1 - Z0);
     SU ru[RS][M];
     S rb[RS][M];
     auto issue_u = [&](int p, int k) {
-        const rsrc_t r = line_rsrc(u, (long)p * plane, plane, p >= 0 && p <= ulast);
+        const unsigned o = wu.at(p, p >= 0 && p <= ulast);
 #pragma unroll
-        for (int m = 0; m < M; ++m) ru[k][m] = bload<SU>(r, gu[m]);
+        for (int m = 0; m < M; ++m) ru[k][m] = bload<SU>(wu.r, o + gu[m]);
     };
     auto issue_b = [&](int p, int k) {
-        const rsrc_t r = line_rsrc(b, (long)p * plane, plane, p >= 0 && p <= blast);
+        const unsigned o = wb.at(p, p >= 0 && p <= blast);
 #pragma unroll
-        for (int m = 0; m < M; ++m) rb[k][m] = bload<S>(r, gb[m]);
+        for (int m = 0; m < M; ++m) rb[k][m] = bload<S>(wb.r, o + gb[m]);
     };
 
     // on entry to step s: u planes s-1..s+1, b planes s-1, s-2, residual
@@ -2258,9 +2316,9 @@ k_sr3d(const SU* __restrict__ u, const S* __restrict__ b, S* __restrict__ out,
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
             const int p = s0 - 1 + q;
-            const rsrc_t r = line_rsrc(u, (long)p * plane, plane, p >= 0 && p < n);
+            const unsigned o = wu.at(p, p >= 0 && p <= ulast);
 #pragma unroll
-            for (int m = 0; m < M; ++m) pu[q][m] = bload<SU>(r, gu[m]);
+            for (int m = 0; m < M; ++m) pu[q][m] = bload<SU>(wu.r, o + gu[m]);
         }
 #pragma unroll
         for (int q = 0; q < PD; ++q) {
@@ -2310,8 +2368,8 @@ k_sr3d(const SU* __restrict__ u, const S* __restrict__ b, S* __restrict__ out,
                 if (SCRW || wr[m]) rL[s & 1][q] = r;
                 if (NORM) nacc += (sown && own[m]) ? (double)r * (double)r : 0.0;
                 if (ROUT)
-                    bstore<false>(static_cast<S>(r), line_rsrc(rout, (long)s * plane, plane, sown),
-                                  own[m] ? gb[m] : kOob);
+                    bstore<false>(static_cast<S>(r), wro.r,
+                                  wro.at(s, sown) + (own[m] ? gb[m] : kOob));
             }
         }
         // new iterate of plane s-1 (residual planes s-2, s-1, s)
@@ -2320,14 +2378,14 @@ k_sr3d(const SU* __restrict__ u, const S* __restrict__ b, S* __restrict__ out,
         C v0[M];
         {
             const C* R = rL[(s + 1) & 1];  // plane s - 1
-            const rsrc_t ro = line_rsrc(out, (long)p * plane, plane, p >= o0 && p < o1);
+            const unsigned ro = wo.at(p, p >= o0 && p < o1);
 #pragma unroll
             for (int m = 0; m < M; ++m) {
                 const int q = li[m];
                 const C nbs = R[q - 1] + R[q + 1] + R[q - WX] + R[q + WX] + r2[m] + r0[m];
                 const C v = um1[m] + sW * (c0 * r1[m] + c1 * nbs);
                 const S vs = static_cast<S>(v);
-                bstore<NTS>(vs, ro, own[m] ? gb[m] : kOob);
+                bstore<NTS>(vs, wo.r, ro + (own[m] ? gb[m] : kOob));
                 v0[m] = (pin && col[m]) ? cvt<C>(vs) : C(0);
                 if (SCRW || wr[m]) vL[p & 1][q] = v0[m];
             }
@@ -2347,7 +2405,7 @@ k_sr3d(const SU* __restrict__ u, const S* __restrict__ b, S* __restrict__ out,
         const int f = s - 3;
         if (f >= 2 * Z0 && f <= 2 * Z1) {
             const C* R = wL[f & 1];
-            const rsrc_t rc = line_rsrc(bc, (long)(f / 2 - 1) * cplane, cplane, true);
+            const unsigned rc = wbc.at(f / 2 - 1, true);
 #pragma unroll
             for (int q = 0; q < MC; ++q) {
                 const int c = cq[q];
@@ -2358,7 +2416,7 @@ k_sr3d(const SU* __restrict__ u, const S* __restrict__ b, S* __restrict__ out,
                 if ((f & 1) == 0) {
                     if (f > 2 * Z0) {
                         acc[q] += C(0.25) * xs;
-                        bstore<false>(static_cast<S>(acc[q]), rc, cgb[q]);
+                        bstore<false>(static_cast<S>(acc[q]), wbc.r, rc + cgb[q]);
                     }
                     acc[q] = C(0.25) * xs;
                 } else {
@@ -3524,7 +3582,10 @@ hipError_t launch_smooth3d(bool zg, bool norm, const Sweep& s, int want, int min
     const C sA = C(s.sA), sW = C(s.sW), c0 = C(s.c[0]), c1 = C(s.c[1]), pf = C(s.pf);
     const C c2 = C(s.c[2]), c3 = C(s.c[3]);
     const int tx = cdiv(n, TX), ty = cdiv(n, TY);
-    const int zc = even_chunk(pick_chunk(n, tx * ty, want, minc));
+    // a chunk's window of zc + 4 planes stays within kWinMax bytes
+    const long zcap = min((long)n + 1, kWinMax / ((long)n * n * (long)sizeof(S)) - 4) & ~1L;
+    if (zcap < 2) return hipErrorInvalidValue;
+    const int zc = min(even_chunk(pick_chunk(n, tx * ty, want, minc)), (int)zcap);
     const int nch = cdiv(n, zc);
     dim3 grid(tx * ty * nch, s.batch);
     if (nparts) *nparts = grid.x * grid.y;
@@ -3578,7 +3639,10 @@ hipError_t launch_smooth2d(bool zg, bool norm, const Sweep& s, int want, int min
     const C sA = C(s.sA), sW = C(s.sW), c0 = C(s.c[0]), c1 = C(s.c[1]), c2 = C(s.c[2]);
     const C pf = C(s.pf);
     const int tx = cdiv(n, TX);
-    const int yc = even_chunk(pick_chunk(n, tx, want, minc));
+    // a chunk's window of yc + 4 rows stays within kWinMax bytes
+    const long ycap = min((long)n + 1, kWinMax / ((long)n * (long)sizeof(S)) - 4) & ~1L;
+    if (ycap < 2) return hipErrorInvalidValue;
+    const int yc = min(even_chunk(pick_chunk(n, tx, want, minc)), (int)ycap);
     const int nch = cdiv(n, yc);
     dim3 grid(tx * nch, s.batch);
     if (nparts) *nparts = grid.x * grid.y;
@@ -3886,7 +3950,10 @@ hipError_t launch_sr2d(const Sweep& s, bool norm, int want, int minc, hipStream_
     if (s.u_f32 && (sizeof(S) != 8 || !s.rout)) return hipErrorInvalidValue;
     const int n = s.n, nc = (n + 1) / 2 - 1;
     const int tx = cdiv(n, TX);
-    const int yc = pick_chunk(nc, tx, want, minc);
+    // a chunk's window of 2 yc + 7 rows stays within kWinMax bytes
+    const int yc = (int)min((long)pick_chunk(nc, tx, want, minc),
+                            (kWinMax / ((long)n * (long)sizeof(S)) - 7) / 2);
+    if (yc < 1) return hipErrorInvalidValue;
     const int nch = cdiv(nc, yc);
     dim3 grid(tx * nch, s.batch);
     if (nparts) *nparts = grid.x * grid.y;
@@ -3927,7 +3994,10 @@ hipError_t launch_sr3d(const Sweep& s, bool norm, int want, int minc, hipStream_
     if (s.u_f32 && (sizeof(S) != 8 || !s.rout)) return hipErrorInvalidValue;
     const int n = s.n, nc = (n + 1) / 2 - 1;
     const int tx = cdiv(n, TX), ty = cdiv(n, TY);
-    const int zc = pick_chunk(nc, tx * ty, want, minc);
+    // a chunk's window of 2 zc + 7 planes stays within kWinMax bytes
+    const int zc = (int)min((long)pick_chunk(nc, tx * ty, want, minc),
+                            (kWinMax / ((long)n * n * (long)sizeof(S)) - 7) / 2);
+    if (zc < 1) return hipErrorInvalidValue;
     const int nch = cdiv(nc, zc);
     dim3 grid(tx * ty * nch, s.batch);
     if (nparts) *nparts = grid.x * grid.y;
@@ -4015,7 +4085,10 @@ hipError_t launch_psr2d(const Sweep& s, bool norm, int want, int minc, hipStream
     if (s.u_f32) return hipErrorInvalidValue;
     const int n = s.n, nc = (n + 1) / 2 - 1;
     const int tx = cdiv(n, TX);
-    const int yc = pick_chunk(nc, tx, want, minc);
+    // a chunk's window of 2 yc + 11 fine rows stays within kWinMax bytes
+    const int yc = min(pick_chunk(nc, tx, want, minc),
+                       (int)((kWinMax / ((long)n * sizeof(S)) - 11) / 2));
+    if (yc < 1) return hipErrorInvalidValue;
     const int nch = cdiv(nc, yc);
     dim3 grid(tx * nch, s.batch);
     if (nparts) *nparts = grid.x * grid.y;
