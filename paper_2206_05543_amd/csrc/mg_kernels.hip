@@ -997,17 +997,22 @@ k_restrict3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ b
         r2l = uy * UX + ux;
         if (gx >= 0 && gx < n && gy >= 0 && gy < n) r2b = (unsigned)((gy * n + gx) * (int)sizeof(S));
     }
+    // fine planes 2 Z0 - 1 .. 2 Z1 + 1 feed the residuals of planes 2 Z0 ..
+    // 2 Z1 (later planes read as zero), in one window per field
+    const int ulast = min(n - 1, 2 * Z1 + 1), blast = min(n - 1, 2 * Z1);
+    const int w0 = max(0, 2 * Z0 - 1), wcnt = ulast - w0 + 1;
+    const Win<S> wu(u, plane, w0, wcnt), wb(b, plane, w0, wcnt), wbc(bc, cplane, Z0, Z1 - Z0);
     S ru[RS][M], rb[RS][M], rr2[RS];
     auto issue_u = [&](int p, int k) {
-        const rsrc_t r = line_rsrc(u, (long)p * plane, plane, p >= 0 && p < n);
+        const unsigned o = wu.at(p, p >= 0 && p <= ulast);
 #pragma unroll
-        for (int m = 0; m < M; ++m) ru[k][m] = bload<S>(r, gb[m]);
-        rr2[k] = bload<S>(r, r2b);
+        for (int m = 0; m < M; ++m) ru[k][m] = bload<S>(wu.r, o + gb[m]);
+        rr2[k] = bload<S>(wu.r, o + r2b);
     };
     auto issue_b = [&](int p, int k) {
-        const rsrc_t r = line_rsrc(b, (long)p * plane, plane, p >= 0 && p < n);
+        const unsigned o = wb.at(p, p >= 0 && p <= blast);
 #pragma unroll
-        for (int m = 0; m < M; ++m) rb[k][m] = bload<S>(r, gb[m]);
+        for (int m = 0; m < M; ++m) rb[k][m] = bload<S>(wb.r, o + gb[m]);
     };
     // coarse column of this thread and its window centre
     const int cx = t % TXc, cy = t / TXc;
@@ -1027,10 +1032,10 @@ k_restrict3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ b
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
             const int p = f0 - 1 + q;
-            const rsrc_t r = line_rsrc(u, (long)p * plane, plane, p >= 0 && p < n);
+            const unsigned o = wu.at(p, p >= 0 && p <= ulast);
 #pragma unroll
-            for (int m = 0; m < M; ++m) pu[q][m] = bload<S>(r, gb[m]);
-            pr2[q] = bload<S>(r, r2b);
+            for (int m = 0; m < M; ++m) pu[q][m] = bload<S>(wu.r, o + gb[m]);
+            pr2[q] = bload<S>(wu.r, o + r2b);
         }
         C dummy;
 #pragma unroll
@@ -1072,8 +1077,7 @@ k_restrict3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ b
             if ((k & 1) == 1) {  // f - f0 even
                 if (f > f0) {
                     acc += C(0.25) * xs;
-                    const rsrc_t ro = line_rsrc(bc, (long)(f / 2 - 1) * cplane, cplane, true);
-                    bstore<false>(static_cast<S>(acc), ro, cgb);
+                    bstore<false>(static_cast<S>(acc), wbc.r, wbc.at(f / 2 - 1, true) + cgb);
                 }
                 acc = C(0.25) * xs;
             } else {
@@ -1198,13 +1202,20 @@ k_zrestrict3d(const S* __restrict__ b, S* __restrict__ e, S* __restrict__ bc, in
         lbx = by * BX + bx;
         if (gx >= 0 && gx < n && gy >= 0 && gy < n) gxo = (unsigned)((gy * n + gx) * (int)sizeof(S));
     }
+    // b planes 2 Z0 - 2 .. 2 Z1 + 2 feed e up to plane 2 Z1 + 1 and the
+    // residuals up to 2 Z1 (later planes read as zero); e is stored on the
+    // owned planes 2 Z0 .. blast
+    const int blast = min(n - 1, 2 * Z1 + 2);
+    const int w0 = max(0, 2 * Z0 - 2), wcnt = blast - w0 + 1;
+    const Win<S> wb(b, plane, w0, wcnt), we(e, plane, w0, wcnt), wbc(bc, cplane, Z0, Z1 - Z0);
     S rbi[4][M], rb1[4], rbx[2];
     auto issue = [&](int p, int q4, int q2) {
-        const rsrc_t r = line_rsrc(b, (long)p * plane, plane, p >= 0 && p < n);
+        const rsrc_t r = wb.r;
+        const unsigned o = wb.at(p, p >= 0 && p <= blast);
 #pragma unroll
-        for (int m = 0; m < M; ++m) rbi[q4][m] = bload<S>(r, gi[m]);
-        rb1[q4] = bload<S>(r, g1);
-        rbx[q2] = bload<S>(r, gxo);
+        for (int m = 0; m < M; ++m) rbi[q4][m] = bload<S>(r, o + gi[m]);
+        rb1[q4] = bload<S>(r, o + g1);
+        rbx[q2] = bload<S>(r, o + gxo);
     };
     // e at the e points of plane p from the b window in slot B and b below
     // (slot dn) and above (slot up) in registers
@@ -1231,9 +1242,10 @@ k_zrestrict3d(const S* __restrict__ b, S* __restrict__ e, S* __restrict__ bc, in
     };
     auto store_e = [&](int p, const C* ei) {
         const bool pown = p >= 2 * Z0 && p < n && (p < 2 * Z1 || Z1 == nc);
-        const rsrc_t r = line_rsrc(e, (long)p * plane, plane, pown);
+        const unsigned o = we.at(p, pown);
 #pragma unroll
-        for (int m = 0; m < M; ++m) bstore<false>(static_cast<S>(ei[m]), r, own[m] ? gi[m] : kOob);
+        for (int m = 0; m < M; ++m)
+            bstore<false>(static_cast<S>(ei[m]), we.r, o + (own[m] ? gi[m] : kOob));
     };
     const int cx = t % TXc, cy = t / TXc;
     const bool cin = t < TXc * TYc;
@@ -1250,15 +1262,14 @@ k_zrestrict3d(const S* __restrict__ b, S* __restrict__ e, S* __restrict__ bc, in
         // (mod 2 for the b beyond the e points), LDS slot (p - f0) mod 3
         S tmi[2][M], tm1[2], tx0, tx1;
         {
-            const rsrc_t r0 = line_rsrc(b, (long)(f0 - 2) * plane, plane, f0 - 2 >= 0);
-            const rsrc_t r1 = line_rsrc(b, (long)(f0 - 1) * plane, plane, f0 - 1 >= 0);
+            const unsigned o0 = wb.at(f0 - 2, f0 - 2 >= 0), o1 = wb.at(f0 - 1, f0 - 1 >= 0);
 #pragma unroll
             for (int m = 0; m < M; ++m) {
-                tmi[0][m] = bload<S>(r0, gi[m]);
-                tmi[1][m] = bload<S>(r1, gi[m]);
+                tmi[0][m] = bload<S>(wb.r, o0 + gi[m]);
+                tmi[1][m] = bload<S>(wb.r, o1 + gi[m]);
             }
-            tm1[0] = bload<S>(r0, g1);
-            tm1[1] = bload<S>(r1, g1);
+            tm1[0] = bload<S>(wb.r, o0 + g1);
+            tm1[1] = bload<S>(wb.r, o1 + g1);
         }
         issue(f0, 0, 0);
         tx0 = rbx[0];
@@ -1341,8 +1352,7 @@ k_zrestrict3d(const S* __restrict__ b, S* __restrict__ e, S* __restrict__ bc, in
             if ((k & 1) == 1) {  // f - f0 even
                 if (f > f0) {
                     acc += C(0.25) * xs;
-                    const rsrc_t ro = line_rsrc(bc, (long)(f / 2 - 1) * cplane, cplane, true);
-                    bstore<false>(static_cast<S>(acc), ro, cgb);
+                    bstore<false>(static_cast<S>(acc), wbc.r, wbc.at(f / 2 - 1, true) + cgb);
                 }
                 acc = C(0.25) * xs;
             } else {
@@ -1414,17 +1424,22 @@ k_restrict2d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ b
     const int r2l = t < 2 ? (t == 0 ? 0 : UX - 1) : UD + lane;
     const unsigned r2b =
         (t < 2 && r2x >= 0 && r2x < n) ? (unsigned)(r2x * (int)sizeof(S)) : kOob;
+    // fine rows 2 Y0 - 1 .. 2 Y1 + 1 feed the residuals of rows 2 Y0 .. 2 Y1
+    // (later rows read as zero), in one window per field
+    const int ulast = min(n - 1, 2 * Y1 + 1), blast = min(n - 1, 2 * Y1);
+    const int w0 = max(0, 2 * Y0 - 1), wcnt = ulast - w0 + 1;
+    const Win<S> wu(u, n, w0, wcnt), wb(b, n, w0, wcnt), wbc(bc, nc, Y0, Y1 - Y0);
     S ru[RS][M], rb[RS][M], rr2[RS];
     auto issue_u = [&](int p, int k) {
-        const rsrc_t r = line_rsrc(u, (long)p * n, n, p >= 0 && p < n);
+        const unsigned o = wu.at(p, p >= 0 && p <= ulast);
 #pragma unroll
-        for (int m = 0; m < M; ++m) ru[k][m] = bload<S>(r, gb[m]);
-        rr2[k] = bload<S>(r, r2b);
+        for (int m = 0; m < M; ++m) ru[k][m] = bload<S>(wu.r, o + gb[m]);
+        rr2[k] = bload<S>(wu.r, o + r2b);
     };
     auto issue_b = [&](int p, int k) {
-        const rsrc_t r = line_rsrc(b, (long)p * n, n, p >= 0 && p < n);
+        const unsigned o = wb.at(p, p >= 0 && p <= blast);
 #pragma unroll
-        for (int m = 0; m < M; ++m) rb[k][m] = bload<S>(r, gb[m]);
+        for (int m = 0; m < M; ++m) rb[k][m] = bload<S>(wb.r, o + gb[m]);
     };
     const unsigned cgb =
         (t < TXc && cx0 + t < nc) ? (unsigned)((cx0 + t) * (int)sizeof(S)) : kOob;
@@ -1440,10 +1455,10 @@ k_restrict2d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ b
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
             const int p = f0 - 1 + q;
-            const rsrc_t r = line_rsrc(u, (long)p * n, n, p >= 0 && p < n);
+            const unsigned o = wu.at(p, p >= 0 && p <= ulast);
 #pragma unroll
-            for (int m = 0; m < M; ++m) pu[q][m] = bload<S>(r, gb[m]);
-            pr2[q] = bload<S>(r, r2b);
+            for (int m = 0; m < M; ++m) pu[q][m] = bload<S>(wu.r, o + gb[m]);
+            pr2[q] = bload<S>(wu.r, o + r2b);
         }
         C dummy;
 #pragma unroll
@@ -1480,8 +1495,7 @@ k_restrict2d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ b
             if ((k & 1) == 1) {  // f - f0 even
                 if (f > f0) {
                     acc += C(0.25) * xs;
-                    const rsrc_t ro = line_rsrc(bc, (long)(f / 2 - 1) * nc, nc, true);
-                    bstore<false>(static_cast<S>(acc), ro, cgb);
+                    bstore<false>(static_cast<S>(acc), wbc.r, wbc.at(f / 2 - 1, true) + cgb);
                 }
                 acc = C(0.25) * xs;
             } else {
@@ -3314,22 +3328,28 @@ k_ir3d(const double* __restrict__ u, double* __restrict__ unew, const S* __restr
         ge[m] = val ? (unsigned)(g * (int)sizeof(S)) : kOob;
         gi[m] = inn[m] ? (unsigned)(g * 8) : kOob;
     }
+    // planes z0 - 1 .. z1 of u (and e) feed the residuals of planes z0 ..
+    // z1 - 1, b up to z1 - 1 (later planes read as zero); one window per field
+    const int ulast = min(n - 1, z1), blast = z1 - 1;
+    const int w0 = max(0, z0 - 1), wcnt = ulast - w0 + 1;
+    const Win<double> wu(u, plane, w0, wcnt), wb(b, plane, w0, wcnt);
+    const Win<double> wn(RES ? u : unew, plane, w0, wcnt);
+    const Win<S> we(hase ? e : rlo, plane, w0, wcnt), wr(rlo, plane, w0, wcnt);
     double ru[RS][M], rb[RS][M];
     S re[RS][M];
     auto issue = [&](int p, int q) {
-        const bool pin = p >= 0 && p < n;
-        const rsrc_t a = line_rsrc(u, (long)p * plane, plane, pin);
-        const rsrc_t c = line_rsrc(e, (long)p * plane, plane, pin && hase);
+        const bool pin = p >= 0 && p <= ulast;
+        const unsigned oa = wu.at(p, pin), oc = we.at(p, pin && hase);
 #pragma unroll
         for (int m = 0; m < M; ++m) {
-            ru[q][m] = bload<double>(a, gu[m]);
-            re[q][m] = bload<S>(c, ge[m]);
+            ru[q][m] = bload<double>(wu.r, oa + gu[m]);
+            re[q][m] = bload<S>(we.r, oc + ge[m]);
         }
     };
     auto issue_b = [&](int p, int q) {
-        const rsrc_t a = line_rsrc(b, (long)p * plane, plane, p >= 0 && p < n);
+        const unsigned o = wb.at(p, p >= 0 && p <= blast);
 #pragma unroll
-        for (int m = 0; m < M; ++m) rb[q][m] = bload<double>(a, gi[m]);
+        for (int m = 0; m < M; ++m) rb[q][m] = bload<double>(wb.r, o + gi[m]);
     };
     auto take = [&](double* dst, const double* raw, const S* rawe) {
 #pragma unroll
@@ -3345,13 +3365,12 @@ k_ir3d(const double* __restrict__ u, double* __restrict__ unew, const S* __restr
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
             const int p = z0 - 1 + q;
-            const bool pin = p >= 0 && p < n;
-            const rsrc_t a = line_rsrc(u, (long)p * plane, plane, pin);
-            const rsrc_t c = line_rsrc(e, (long)p * plane, plane, pin && hase);
+            const bool pin = p >= 0 && p <= ulast;
+            const unsigned oa = wu.at(p, pin), oc = we.at(p, pin && hase);
 #pragma unroll
             for (int m = 0; m < M; ++m) {
-                pu[q][m] = bload<double>(a, gu[m]);
-                pe[q][m] = bload<S>(c, ge[m]);
+                pu[q][m] = bload<double>(wu.r, oa + gu[m]);
+                pe[q][m] = bload<S>(we.r, oc + ge[m]);
             }
         }
         take(um1, pu[0], pe[0]);
@@ -3369,8 +3388,7 @@ k_ir3d(const double* __restrict__ u, double* __restrict__ unew, const S* __restr
         issue_b(s + 1, (k + 1) % RS);
         if (s < z1) {
             const double* U = uL[cur];
-            const rsrc_t ow = line_rsrc(unew, (long)s * plane, plane, hase);
-            const rsrc_t orl = line_rsrc(rlo, (long)s * plane, plane, true);
+            const unsigned ow = wn.at(s, hase), orl = wr.at(s, true);
 #pragma unroll
             for (int m = 0; m < M; ++m) {
                 const int q = RP + t + m * NT;
@@ -3378,8 +3396,8 @@ k_ir3d(const double* __restrict__ u, double* __restrict__ unew, const S* __restr
                                    um1[m] - up1[m];
                 const double r = rb[k % RS][m] - inv_h2 * lap;
                 if (!RES) {
-                    bstore<NTS>(u0[m], ow, gi[m]);
-                    bstore<NTS>(static_cast<S>(s_new * r), orl, inn[m] ? ge[m] : kOob);
+                    bstore<NTS>(u0[m], wn.r, ow + gi[m]);
+                    bstore<NTS>(static_cast<S>(s_new * r), wr.r, orl + (inn[m] ? ge[m] : kOob));
                 }
                 acc += inn[m] ? r * r : 0.0;
                 mx = fmax(mx, inn[m] ? fabs(r) : 0.0);
@@ -3447,22 +3465,27 @@ k_ir2d(const double* __restrict__ u, double* __restrict__ unew, const S* __restr
         ge[m] = val ? (unsigned)(gx * (int)sizeof(S)) : kOob;
         gi[m] = inn[m] ? (unsigned)(gx * 8) : kOob;
     }
+    // rows y0 - 1 .. y1 of u (and e) feed the residuals of rows y0 .. y1 - 1,
+    // b up to y1 - 1 (later rows read as zero); one window per field
+    const int ulast = min(n - 1, y1), blast = y1 - 1;
+    const int w0 = max(0, y0 - 1), wcnt = ulast - w0 + 1;
+    const Win<double> wu(u, n, w0, wcnt), wb(b, n, w0, wcnt), wn(RES ? u : unew, n, w0, wcnt);
+    const Win<S> we(hase ? e : rlo, n, w0, wcnt), wr(rlo, n, w0, wcnt);
     double ru[RS][M], rb[RS][M];
     S re[RS][M];
     auto issue = [&](int p, int q) {
-        const bool pin = p >= 0 && p < n;
-        const rsrc_t a = line_rsrc(u, (long)p * n, n, pin);
-        const rsrc_t c = line_rsrc(e, (long)p * n, n, pin && hase);
+        const bool pin = p >= 0 && p <= ulast;
+        const unsigned oa = wu.at(p, pin), oc = we.at(p, pin && hase);
 #pragma unroll
         for (int m = 0; m < M; ++m) {
-            ru[q][m] = bload<double>(a, gu[m]);
-            re[q][m] = bload<S>(c, ge[m]);
+            ru[q][m] = bload<double>(wu.r, oa + gu[m]);
+            re[q][m] = bload<S>(we.r, oc + ge[m]);
         }
     };
     auto issue_b = [&](int p, int q) {
-        const rsrc_t a = line_rsrc(b, (long)p * n, n, p >= 0 && p < n);
+        const unsigned o = wb.at(p, p >= 0 && p <= blast);
 #pragma unroll
-        for (int m = 0; m < M; ++m) rb[q][m] = bload<double>(a, gi[m]);
+        for (int m = 0; m < M; ++m) rb[q][m] = bload<double>(wb.r, o + gi[m]);
     };
     auto take = [&](double* dst, const double* raw, const S* rawe) {
 #pragma unroll
@@ -3477,13 +3500,12 @@ k_ir2d(const double* __restrict__ u, double* __restrict__ unew, const S* __restr
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
             const int p = y0 - 1 + q;
-            const bool pin = p >= 0 && p < n;
-            const rsrc_t a = line_rsrc(u, (long)p * n, n, pin);
-            const rsrc_t c = line_rsrc(e, (long)p * n, n, pin && hase);
+            const bool pin = p >= 0 && p <= ulast;
+            const unsigned oa = wu.at(p, pin), oc = we.at(p, pin && hase);
 #pragma unroll
             for (int m = 0; m < M; ++m) {
-                pu[q][m] = bload<double>(a, gu[m]);
-                pe[q][m] = bload<S>(c, ge[m]);
+                pu[q][m] = bload<double>(wu.r, oa + gu[m]);
+                pe[q][m] = bload<S>(we.r, oc + ge[m]);
             }
         }
         take(um1, pu[0], pe[0]);
@@ -3501,16 +3523,15 @@ k_ir2d(const double* __restrict__ u, double* __restrict__ unew, const S* __restr
         issue_b(s + 1, (k + 1) % RS);
         if (s < y1) {
             const double* U = uL[cur];
-            const rsrc_t ow = line_rsrc(unew, (long)s * n, n, hase);
-            const rsrc_t orl = line_rsrc(rlo, (long)s * n, n, true);
+            const unsigned ow = wn.at(s, hase), orl = wr.at(s, true);
 #pragma unroll
             for (int m = 0; m < M; ++m) {
                 const int q = 1 + t + m * NT;
                 const double lap = 4.0 * u0[m] - U[q - 1] - U[q + 1] - um1[m] - up1[m];
                 const double r = rb[k % RS][m] - inv_h2 * lap;
                 if (!RES) {
-                    bstore<NTS>(u0[m], ow, gi[m]);
-                    bstore<NTS>(static_cast<S>(s_new * r), orl, inn[m] ? ge[m] : kOob);
+                    bstore<NTS>(u0[m], wn.r, ow + gi[m]);
+                    bstore<NTS>(static_cast<S>(s_new * r), wr.r, orl + (inn[m] ? ge[m] : kOob));
                 }
                 acc += inn[m] ? r * r : 0.0;
                 mx = fmax(mx, inn[m] ? fabs(r) : 0.0);
@@ -3553,6 +3574,13 @@ inline int pick_chunk(int n, int tiles, int want, int minc) {
 
 // the fused-correction sweep assumes every chunk starts on an even plane
 inline int even_chunk(int c) { return c + (c & 1); }
+
+// chunk c capped so that a window of per * c + extra lines of line_bytes
+// each stays within kWinMax bytes; 0 when not even one chunk line fits
+inline int win_chunk(int c, long line_bytes, int per, int extra) {
+    const long cap = (kWinMax / line_bytes - extra) / per;
+    return (int)std::max(0L, std::min((long)c, cap));
+}
 
 // Launch configurations of the marching sweeps by grid size, measured on
 // MI355X in FP64 (the same shapes serve FP32/FP16 storage unless noted).  `want` is the
@@ -3715,7 +3743,8 @@ template <typename S, typename C, int TXc, int TYc, int NT, int UN>
 hipError_t launch_restrict3d(const Sweep& s, int want, int minc, hipStream_t st) {
     const int n = s.n, nc = (n + 1) / 2 - 1;
     const int tx = cdiv(nc, TXc), ty = cdiv(nc, TYc);
-    const int zc = pick_chunk(nc, tx * ty, want, minc);
+    const int zc = win_chunk(pick_chunk(nc, tx * ty, want, minc), (long)n * n * sizeof(S), 2, 3);
+    if (zc < 1) return hipErrorInvalidValue;
     const int nch = cdiv(nc, zc);
     dim3 grid(tx * ty * nch, s.batch);
     mg_launch((k_restrict3d<S, C, TXc, TYc, NT, UN>), grid, dim3(NT), 0, st,
@@ -3729,7 +3758,8 @@ template <typename S, typename C, int TXc, int NT, int UN>
 hipError_t launch_restrict2d(const Sweep& s, int want, int minc, hipStream_t st) {
     const int n = s.n, nc = (n + 1) / 2 - 1;
     const int tx = cdiv(nc, TXc);
-    const int yc = pick_chunk(nc, tx, want, minc);
+    const int yc = win_chunk(pick_chunk(nc, tx, want, minc), (long)n * sizeof(S), 2, 3);
+    if (yc < 1) return hipErrorInvalidValue;
     const int nch = cdiv(nc, yc);
     dim3 grid(tx * nch, s.batch);
     mg_launch((k_restrict2d<S, C, TXc, NT, UN>), grid, dim3(NT), 0, st,
@@ -3832,7 +3862,8 @@ hipError_t ir_impl(const IRStep& s, hipStream_t st, int* nparts) {
 #define IR3(TX, TY, NT, UN, NTS, WANT, MINC)                                                    \
     do {                                                                                       \
         const int tx = cdiv(n, TX), ty = cdiv(n, TY);                                          \
-        const int zc = pick_chunk(n, tx * ty, WANT, MINC);                                     \
+        const int zc = win_chunk(pick_chunk(n, tx * ty, WANT, MINC), 8L * n * n, 1, 2);        \
+        if (zc < 1) return hipErrorInvalidValue;                                               \
         const int nch = cdiv(n, zc);                                                           \
         dim3 grid(tx * ty * nch, s.batch);                                                     \
         if (nparts) *nparts = grid.x * grid.y;                                                 \
@@ -3844,7 +3875,8 @@ hipError_t ir_impl(const IRStep& s, hipStream_t st, int* nparts) {
 #define IR2(TX, NT, UN, NTS, WANT, MINC)                                                        \
     do {                                                                                       \
         const int tx = cdiv(n, TX);                                                            \
-        const int yc = pick_chunk(n, tx, WANT, MINC);                                          \
+        const int yc = win_chunk(pick_chunk(n, tx, WANT, MINC), 8L * n, 1, 2);                 \
+        if (yc < 1) return hipErrorInvalidValue;                                               \
         const int nch = cdiv(n, yc);                                                           \
         dim3 grid(tx * nch, s.batch);                                                          \
         if (nparts) *nparts = grid.x * grid.y;                                                 \
@@ -3898,7 +3930,8 @@ template <typename S, typename C, int TXc, int TYc, int NT>
 hipError_t launch_zrestrict3d(const Sweep& s, int want, int minc, hipStream_t st) {
     const int n = s.n, nc = (n + 1) / 2 - 1;
     const int tx = cdiv(nc, TXc), ty = cdiv(nc, TYc);
-    const int zc = pick_chunk(nc, tx * ty, want, minc);
+    const int zc = win_chunk(pick_chunk(nc, tx * ty, want, minc), (long)n * n * sizeof(S), 2, 5);
+    if (zc < 1) return hipErrorInvalidValue;
     const int nch = cdiv(nc, zc);
     mg_launch((k_zrestrict3d<S, C, TXc, TYc, NT, 12>), dim3(tx * ty * nch, s.batch),
                        dim3(NT), 0, st, static_cast<const S*>(s.b), static_cast<S*>(s.out),
