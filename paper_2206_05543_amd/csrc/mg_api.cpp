@@ -424,13 +424,15 @@ bool wide_3d(const mg_ctx* h) { return h->d == 3 && (h->c[2] != 0.0 || h->c[3] !
 
 // Where the zero-guess pre-smoother and the restriction run as one kernel:
 // 2D, every level above the tail (a tile kernel; its halo costs 1.3x the
-// reads of b); 3D grids of 200 or more nodes per direction (the
-// restriction's march forming e from b on the fly: 87 against 111 us at
-// n = 255 in FP64, 327 against 478 us at n = 511 with FP32 storage).  On
-// smaller 3D grids its twelve-plane unroll makes short marches slower than
-// the two sweeps (12.5 against 9.6 us at n = 63).
+// reads of b); 3D with the 7-point stencil, every level: grids of 200 or
+// more nodes per direction in the restriction's march forming e from b on
+// the fly (87 against 111 us at n = 255 in FP64, 327 against 478 us at
+// n = 511 with FP32 storage), smaller ones in the 3D tile kernel (one
+// launch instead of two; the march's twelve-plane unroll made short marches
+// slower than the two sweeps, 12.5 against 9.6 us at n = 63).
 bool fuse_zero_restrict(const mg_ctx* h, int l) {
-    return h->d == 2 || (level_n(h, l) >= 200 && !wide_3d(h));
+    (void)l;
+    return h->d == 2 || !wide_3d(h);
 }
 
 // Where the pre-smoother from a nonzero iterate (the finest level of every
