@@ -1609,15 +1609,29 @@ k_zsr2d(const S* __restrict__ b, S* __restrict__ e, S* __restrict__ bc, int n, i
     const int ox1 = cx0 + CX >= nc ? n : fx0 + 2 * CX;
     const int oy1 = cy0 + CY >= nc ? n : fy0 + 2 * CY;
     const int t = threadIdx.x;
-    for (int i = t; i < BX * BY; i += NT) {
-        const int lx = i % BX, ly = i / BX;
-        const int gx = fx0 - 2 + lx, gy = fy0 - 2 + ly;
-        C v = C(0);
-        if (gx >= 0 && gx < n && gy >= 0 && gy < n) v = cvt<C>(b[(long)gy * n + gx]);
-        bL[i] = v;
+    {
+        // every load in flight before the first wait
+        constexpr int NB = (BX * BY + NT - 1) / NT;
+        S v[NB];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            const int i = t + j * NT;
+            const int lx = i % BX, ly = i / BX;
+            const int gx = fx0 - 2 + lx, gy = fy0 - 2 + ly;
+            const bool in = i < BX * BY && gx >= 0 && gx < n && gy >= 0 && gy < n;
+            v[j] = in ? b[(long)gy * n + gx] : S(0);
+        }
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            const int i = t + j * NT;
+            if (i < BX * BY) bL[i] = cvt<C>(v[j]);
+        }
     }
     __syncthreads();
-    for (int i = t; i < EX * EY; i += NT) {
+#pragma unroll
+    for (int j = 0; j < (EX * EY + NT - 1) / NT; ++j) {
+        const int i = t + j * NT;
+        if (i >= EX * EY) break;
         const int lx = i % EX, ly = i / EX;
         const int gx = fx0 - 1 + lx, gy = fy0 - 1 + ly;
         const int q = (ly + 1) * BX + lx + 1;
@@ -1630,7 +1644,10 @@ k_zsr2d(const S* __restrict__ b, S* __restrict__ e, S* __restrict__ bc, int n, i
             e[(long)gy * n + gx] = static_cast<S>(v);
     }
     __syncthreads();
-    for (int i = t; i < RX * RY; i += NT) {
+#pragma unroll
+    for (int j = 0; j < (RX * RY + NT - 1) / NT; ++j) {
+        const int i = t + j * NT;
+        if (i >= RX * RY) break;
         const int lx = i % RX, ly = i / RX;
         const int qe = (ly + 1) * EX + lx + 1, qb = (ly + 2) * BX + lx + 2;
         const C lap = C(4) * eL[qe] - eL[qe - 1] - eL[qe + 1] - eL[qe - EX] - eL[qe + EX];
