@@ -73,6 +73,9 @@ struct mg_ctx {
     double* ualt = nullptr;      // FP64 fine ping-pong buffer
     double* psum = nullptr;      // per-block partial sums
     double* pmax = nullptr;      // per-block partial maxima
+    double* psum_b = nullptr;    // per-block partial sums of b^2 (||b|| of a solve)
+    bool bnorm_req = false;      // the next fused fine pre-smoother sums b^2 too
+    int bnorm_parts = 0;         // partials it left in psum_b (0 = none)
     double* dnorm = nullptr;     // device norms: 2 per slot (norm, max)
     double* dscale = nullptr;    // refinement scales per step
     double* hnorm = nullptr;     // coherent pinned host mirror of dnorm
@@ -271,14 +274,17 @@ int alloc_common(mg_ctx* h) {
     if (h->ualt) (void)hipFree(h->ualt);
     if (h->psum) (void)hipFree(h->psum);
     if (h->pmax) (void)hipFree(h->pmax);
+    if (h->psum_b) (void)hipFree(h->psum_b);
     if (h->dnorm) (void)hipFree(h->dnorm);
     if (h->dscale) (void)hipFree(h->dscale);
     if (h->hnorm) (void)hipHostFree(h->hnorm);
-    h->ualt = h->psum = h->pmax = h->dnorm = h->dscale = h->hnorm = h->hnorm_dev = nullptr;
+    h->ualt = h->psum = h->pmax = h->psum_b = h->dnorm = h->dscale = h->hnorm = h->hnorm_dev =
+        nullptr;
     const size_t fine = (size_t)level_pts(h, 0) * h->batch * sizeof(double);
     HIPCHK(hipMalloc(&h->ualt, fine));
     HIPCHK(hipMalloc(&h->psum, kPartialCap * h->batch * sizeof(double)));
     HIPCHK(hipMalloc(&h->pmax, kPartialCap * h->batch * sizeof(double)));
+    HIPCHK(hipMalloc(&h->psum_b, kPartialCap * h->batch * sizeof(double)));
     h->norm_slots = h->max_cycles + 4;
     HIPCHK(hipMalloc(&h->dnorm, 2 * h->norm_slots * sizeof(double)));
     HIPCHK(hipMalloc(&h->dscale, h->norm_slots * sizeof(double)));
@@ -550,10 +556,17 @@ int cycle(mg_ctx* h, Hier& H, int l, const void* u_in, const void* b, void* out,
         // pending for the next restriction-type kernel (or the flush)
         if (part != kRest) {
             s.out_c = H.b[l + 1];
+            const bool bn = norm && l == 0 && h->bnorm_req;
+            if (bn) s.bparts = h->psum_b;
             rc = run_timed(h, MG_TIME_SMOOTH_RESTRICT, l, st, [&] {
                 return launch_smooth_restrict(H.p, norm, s, st, &nparts);
             });
             if (rc) return rc;
+            if (bn) {
+                h->bnorm_req = false;
+                h->bnorm_parts = nparts;
+            }
+            s.bparts = nullptr;
             if (norm) {
                 h->pend.count = nparts;
                 h->pend.with_max = false;
@@ -654,6 +667,25 @@ int enqueue_bnorm(mg_ctx* h, const double* b, hipStream_t st) {
     const int sl = bnorm_slot(h);
     HIPCHK(launch_sumsq(b, level_pts(h, 0) * h->batch, h->psum, kPartialCap * h->batch, st, &np));
     HIPCHK(launch_finalize(h->psum, nullptr, np, h->dnorm + 2 * sl, st, h->hnorm_dev + 2 * sl));
+    return MG_OK;
+}
+
+// The FP64 solves ask the first cycle's fused fine pre-smoother, which
+// reads all of b, to sum b^2 beside ||r_0||^2 (one pass over b saved);
+// the partials are reduced at the end of the solve, or b gets its own pass
+// if no such kernel took the request.
+void request_bnorm(mg_ctx* h) {
+    h->bnorm_req = true;
+    h->bnorm_parts = 0;
+}
+
+int finish_bnorm(mg_ctx* h, const double* b, hipStream_t st) {
+    h->bnorm_req = false;
+    if (h->bnorm_parts == 0) return enqueue_bnorm(h, b, st);
+    const int sl = bnorm_slot(h);
+    HIPCHK(launch_finalize(h->psum_b, nullptr, h->bnorm_parts, h->dnorm + 2 * sl, st,
+                           h->hnorm_dev + 2 * sl));
+    h->bnorm_parts = 0;
     return MG_OK;
 }
 
@@ -1129,10 +1161,8 @@ static int solve64_chain(mg_ctx* h, const double* b, double* u, double tol, mg_s
     std::vector<double> hist;
     double r0 = 0.0, rk = 0.0;
     int k = 0, code = MG_OK, run = 0;
-    if (st_out) {
-        const int rb = enqueue_bnorm(h, b, st);
-        if (rb) return rb;
-    }
+    h->bnorm_req = false;
+    if (st_out) request_bnorm(h);
     Sweep s = make_sweep(h, H, 0);
     double sA, sW, pf;
     level_scales(h, H, 0, &sA, &sW, &pf);
@@ -1156,10 +1186,16 @@ static int solve64_chain(mg_ctx* h, const double* b, double* u, double tol, mg_s
     // cycle 0: pre-smoother and restriction, with ||r_0||
     s.u = u;
     s.out = tcur;
+    s.bparts = h->bnorm_req ? h->psum_b : nullptr;
     arm_norm(h, 0);
     rc = run_timed(h, MG_TIME_SMOOTH_RESTRICT, 0, st,
                    [&] { return launch_smooth_restrict(P64, true, s, st, &nparts); });
     if (rc) return rc;
+    if (s.bparts) {
+        h->bnorm_req = false;
+        h->bnorm_parts = nparts;
+        s.bparts = nullptr;
+    }
     pend(0);
     run = 1;
     bool gate = false;
@@ -1208,6 +1244,10 @@ static int solve64_chain(mg_ctx* h, const double* b, double* u, double tol, mg_s
         rc = gate ? flush_pending_norm(h, st) : coarse();
         if (rc) return rc;
     }
+    if (st_out) {
+        rc = finish_bnorm(h, b, st);
+        if (rc) return rc;
+    }
     HIPCHK(hipEventRecord(h->ev1, st));
     HIPCHK(hipStreamSynchronize(st));
     rc = time_collect(h);
@@ -1241,10 +1281,8 @@ static int solve64(mg_ctx* h, const double* b, double* u, double tol, mg_stats* 
     double r0 = 0.0, rk = 0.0;
     int k = 0, code = MG_OK, run = 0;
     bool flipped = false;
-    if (st_out) {
-        const int rb = enqueue_bnorm(h, b, st);
-        if (rb) return rb;
-    }
+    h->bnorm_req = false;
+    if (st_out) request_bnorm(h);
     for (k = 0;; ++k) {
         // cycle k reads u_k from X and writes u_{k+1} to Y; its pre-smoother
         // also yields ||r_k||.  The host waits only for that norm while the
@@ -1319,6 +1357,10 @@ static int solve64(mg_ctx* h, const double* b, double* u, double tol, mg_stats* 
     }
     // u_k is in X
     if (X != u) HIPCHK(hipMemcpyAsync(u, X, fine, hipMemcpyDeviceToDevice, st));
+    if (st_out) {
+        const int rb = finish_bnorm(h, b, st);
+        if (rb) return rb;
+    }
     HIPCHK(hipEventRecord(h->ev1, st));
     HIPCHK(hipStreamSynchronize(st));
     int rc = time_collect(h);
@@ -1513,6 +1555,7 @@ void mg_destroy(mg_handle_t h) {
     if (h->ualt) (void)hipFree(h->ualt);
     if (h->psum) (void)hipFree(h->psum);
     if (h->pmax) (void)hipFree(h->pmax);
+    if (h->psum_b) (void)hipFree(h->psum_b);
     if (h->dnorm) (void)hipFree(h->dnorm);
     if (h->dscale) (void)hipFree(h->dscale);
     if (h->hnorm) (void)hipHostFree(h->hnorm);

@@ -40,6 +40,7 @@ struct Sweep {
     double c[4] = {0, 0, 0, 0};  // SPAI coefficients: centre, faces, then the
                                  // diagonals (2D) or edges and corners (3D)
     double* partials = nullptr;  // per-block sum r^2 (norm variant)
+    double* bparts = nullptr;    // per-block sum b^2 beside it (fused pre-smoother, FP64)
     long partials_cap = 0;       // entries available in partials
     // optional fused correction: the sweep reads u + pf * P ec, where ec is a
     // coarse-grid field ((n+1)/2 - 1 interior nodes) of the same storage type

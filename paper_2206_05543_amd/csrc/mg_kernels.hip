@@ -1796,7 +1796,8 @@ template <typename S, typename C, int TX, int NT, int PD, int UN, bool NTS, bool
 __global__ void __launch_bounds__(NT)
 k_sr2d(const SU* __restrict__ u, const S* __restrict__ b, S* __restrict__ out,
        S* __restrict__ bc, int n, int nc, int tiles_x, int ychunk, int nchunks, C sA, C sW,
-       C c0, C c1, C c2, double* __restrict__ partials, S* __restrict__ rout = nullptr) {
+       C c0, C c1, C c2, double* __restrict__ partials, S* __restrict__ rout = nullptr,
+       double* __restrict__ bparts = nullptr) {
     constexpr int W = TX + 7;             // columns x0-3 .. x0+TX+3
     constexpr int M = (W + NT - 1) / NT;
     constexpr int LW = W + 2 + 65;        // one guard each side, scratch for idle lanes
@@ -1881,7 +1882,7 @@ k_sr2d(const SU* __restrict__ u, const S* __restrict__ b, S* __restrict__ out,
     C r1[M], r2[M], r3[M];
     C v1[M], v2[M];
     C acc[MC];
-    double nacc = 0.0;
+    double nacc = 0.0, bacc = 0.0;
     const int s0 = 2 * Y0 - 2, s1 = 2 * Y1 + 4;
     {
         // all prologue loads before the first wait
@@ -1931,7 +1932,10 @@ k_sr2d(const SU* __restrict__ u, const S* __restrict__ b, S* __restrict__ out,
             const C r = (sin && col[m]) ? b0[m] - sA * lap : C(0);
             r0[m] = r;
             rL[s & 3][q] = r;
-            if (NORM) nacc += (sown && own[m]) ? (double)r * (double)r : 0.0;
+            if (NORM) {
+                nacc += (sown && own[m]) ? (double)r * (double)r : 0.0;
+                bacc += (sown && own[m]) ? (double)b0[m] * (double)b0[m] : 0.0;
+            }
             if (ROUT)
                 bstore<false>(static_cast<S>(r), wro.r,
                               wro.at(s, sown) + (own[m] ? gb[m] : kOob));
@@ -2009,6 +2013,11 @@ k_sr2d(const SU* __restrict__ u, const S* __restrict__ b, S* __restrict__ out,
     if (NORM) {
         const double sm = block_sum<NT>(nacc, red);
         if (t == 0) partials[(long)blockIdx.y * gridDim.x + blockIdx.x] = sm;
+        if (bparts) {  // sum b^2 as well (||b|| of a solve, in its first cycle)
+            __syncthreads();
+            const double sb = block_sum<NT>(bacc, red);
+            if (t == 0) bparts[(long)blockIdx.y * gridDim.x + blockIdx.x] = sb;
+        }
     }
 }
 
@@ -2357,7 +2366,8 @@ template <typename S, typename C, int TX, int TY, int NT, int PD, int UN, bool N
 __global__ void __launch_bounds__(NT)
 k_sr3d(const SU* __restrict__ u, const S* __restrict__ b, S* __restrict__ out,
        S* __restrict__ bc, int n, int nc, int tiles_x, int tiles_y, int zchunk, int nchunks,
-       C sA, C sW, C c0, C c1, double* __restrict__ partials, S* __restrict__ rout = nullptr) {
+       C sA, C sW, C c0, C c1, double* __restrict__ partials, S* __restrict__ rout = nullptr,
+       double* __restrict__ bparts = nullptr) {
     constexpr int WX = TX + 7, WY = TY + 7, NW = WX * WY;  // x0-3 .. x0+TX+3
     constexpr int M = (NW + NT - 1) / NT;
     constexpr int WP = WX + 1;                             // guard row of neighbours
@@ -2447,7 +2457,7 @@ k_sr3d(const SU* __restrict__ u, const S* __restrict__ b, S* __restrict__ out,
     // planes s-1, s-2 and new iterate planes s-2, s-3 at this lane's points
     C um1[M], u0[M], up1[M], b1[M], b2[M], r1[M], r2[M], v1[M], v2[M];
     C acc[MC];
-    double nacc = 0.0;
+    double nacc = 0.0, bacc = 0.0;
     const int s0 = 2 * Z0 - 2, s1 = 2 * Z1 + 3;
     {
         SU pu[3][M];
@@ -2504,7 +2514,10 @@ k_sr3d(const SU* __restrict__ u, const S* __restrict__ b, S* __restrict__ out,
                 const C r = (sin && col[m]) ? b0[m] - sA * lap : C(0);
                 r0[m] = r;
                 if (SCRW || wr[m]) rL[s & 1][q] = r;
-                if (NORM) nacc += (sown && own[m]) ? (double)r * (double)r : 0.0;
+                if (NORM) {
+                    nacc += (sown && own[m]) ? (double)r * (double)r : 0.0;
+                    bacc += (sown && own[m]) ? (double)b0[m] * (double)b0[m] : 0.0;
+                }
                 if (ROUT)
                     bstore<false>(static_cast<S>(r), wro.r,
                                   wro.at(s, sown) + (own[m] ? gb[m] : kOob));
@@ -2581,6 +2594,11 @@ k_sr3d(const SU* __restrict__ u, const S* __restrict__ b, S* __restrict__ out,
     if (NORM) {
         const double sm = block_sum<NT>(nacc, red);
         if (t == 0) partials[(long)blockIdx.y * gridDim.x + blockIdx.x] = sm;
+        if (bparts) {  // sum b^2 as well (||b|| of a solve, in its first cycle)
+            __syncthreads();
+            const double sb = block_sum<NT>(bacc, red);
+            if (t == 0) bparts[(long)blockIdx.y * gridDim.x + blockIdx.x] = sb;
+        }
     }
 }
 
@@ -4141,18 +4159,19 @@ hipError_t launch_sr2d(const Sweep& s, bool norm, int want, int minc, hipStream_
 #define SR2(NM)                                                                              \
     mg_launch((k_sr2d<S, C, TX, NT, PD, UN, NTS, NM>), grid, dim3(NT), 0, st, u, b,  \
                        out, bc, n, nc, tx, yc, nch, sA, sW, c0, c1, c2, s.partials,          \
-                       static_cast<S*>(nullptr))
+                       static_cast<S*>(nullptr), NM ? s.bparts : nullptr)
     if constexpr (sizeof(S) == 8) {
         if (s.rout) {  // residual side output
             if (norm) return hipErrorInvalidValue;
             if (s.u_f32)  // the iterate as stored in an FP32 checkpoint
                 mg_launch((k_sr2d<S, C, TX, NT, PD, UN, NTS, false, true, float>), grid,
                           dim3(NT), 0, st, static_cast<const float*>(s.u), b, out, bc, n, nc,
-                          tx, yc, nch, sA, sW, c0, c1, c2, s.partials, static_cast<S*>(s.rout));
+                          tx, yc, nch, sA, sW, c0, c1, c2, s.partials, static_cast<S*>(s.rout),
+                          static_cast<double*>(nullptr));
             else
                 mg_launch((k_sr2d<S, C, TX, NT, PD, UN, NTS, false, true>), grid, dim3(NT), 0,
                           st, u, b, out, bc, n, nc, tx, yc, nch, sA, sW, c0, c1, c2,
-                          s.partials, static_cast<S*>(s.rout));
+                          s.partials, static_cast<S*>(s.rout), static_cast<double*>(nullptr));
             return hipGetLastError();
         }
     }
@@ -4185,18 +4204,20 @@ hipError_t launch_sr3d(const Sweep& s, bool norm, int want, int minc, hipStream_
 #define SR3(NM)                                                                             \
     mg_launch((k_sr3d<S, C, TX, TY, NT, PD, UN, NTS, NM>), grid, dim3(NT), 0, st,     \
                        u, b, out, bc, n, nc, tx, ty, zc, nch, sA, sW, c0, c1, s.partials,   \
-                       static_cast<S*>(nullptr))
+                       static_cast<S*>(nullptr), NM ? s.bparts : nullptr)
     if constexpr (sizeof(S) == 8) {
         if (s.rout) {  // residual side output
             if (norm) return hipErrorInvalidValue;
             if (s.u_f32)  // the iterate as stored in an FP32 checkpoint
                 mg_launch((k_sr3d<S, C, TX, TY, NT, PD, UN, NTS, false, true, float>), grid,
                           dim3(NT), 0, st, static_cast<const float*>(s.u), b, out, bc, n, nc,
-                          tx, ty, zc, nch, sA, sW, c0, c1, s.partials, static_cast<S*>(s.rout));
+                          tx, ty, zc, nch, sA, sW, c0, c1, s.partials, static_cast<S*>(s.rout),
+                          static_cast<double*>(nullptr));
             else
                 mg_launch((k_sr3d<S, C, TX, TY, NT, PD, UN, NTS, false, true>), grid,
                           dim3(NT), 0, st, u, b, out, bc, n, nc, tx, ty, zc, nch, sA, sW,
-                          c0, c1, s.partials, static_cast<S*>(s.rout));
+                          c0, c1, s.partials, static_cast<S*>(s.rout),
+                          static_cast<double*>(nullptr));
             return hipGetLastError();
         }
     }
