@@ -670,10 +670,11 @@ int enqueue_bnorm(mg_ctx* h, const double* b, hipStream_t st) {
     return MG_OK;
 }
 
-// The FP64 solves ask the first cycle's fused fine pre-smoother, which
-// reads all of b, to sum b^2 beside ||r_0||^2 (one pass over b saved);
-// the partials are reduced at the end of the solve, or b gets its own pass
-// if no such kernel took the request.
+// The solves ask their first kernel that reads all of b (the first cycle's
+// fused fine pre-smoother beside ||r_0||^2; in refinement the residual pass
+// or the first step) to sum b^2 too, which saves a pass over b; the
+// partials are reduced at the end of the solve, or b gets its own pass if
+// no kernel took the request.
 void request_bnorm(mg_ctx* h) {
     h->bnorm_req = true;
     h->bnorm_parts = 0;
@@ -1393,18 +1394,23 @@ static int solve_ir(mg_ctx* h, const double* b, double* u, double tol, mg_stats*
     const double sigma0 = H.scaled ? N * N : 1.0;
     HIPCHK(hipEventRecord(h->ev0, st));
     int nparts = 0, rc;
-    if (st_out) {
-        rc = enqueue_bnorm(h, b, st);
-        if (rc) return rc;
-    }
+    // ||b|| from the solve's first pass over b (the residual pass or the
+    // first refinement step)
+    h->bnorm_req = false;
+    if (st_out) request_bnorm(h);
     if (H.p == P16) {
         // FP16 storage needs r_0 scaled into range: a residual pass of the
         // initial guess puts (||r_0||, max|r_0|) in slot 0 for the first step
+        double* bp = h->bnorm_req ? h->psum_b : nullptr;
         rc = run_timed(h, MG_TIME_RESIDUAL, 0, st, [&] {
             return launch_residual_norm(h->d, level_n(h, 0), h->batch, X, b, N * N, h->psum,
-                                        h->pmax, kPartialCap * h->batch, st, &nparts);
+                                        h->pmax, kPartialCap * h->batch, st, &nparts, bp);
         });
         if (rc) return rc;
+        if (bp) {
+            h->bnorm_req = false;
+            h->bnorm_parts = nparts;
+        }
         HIPCHK(launch_finalize(h->psum, h->pmax, nparts, h->dnorm, st));
     } else {
         // FP32 holds r_0 unscaled: max|r| = 0 in slot 0 gives the first step
@@ -1435,11 +1441,16 @@ static int solve_ir(mg_ctx* h, const double* b, double* u, double tol, mg_stats*
         s.maxprev = h->dnorm + 2 * pslot + 1;
         s.psum = h->psum;
         s.pmax = h->pmax;
+        s.bparts = h->bnorm_req ? h->psum_b : nullptr;
         s.partials_cap = kPartialCap * h->batch;
         arm_norm(h, slot);
         rc = run_timed(h, MG_TIME_IR_STEP, 0, st,
                        [&] { return launch_ir_step(H.p, s, st, &nparts); });
         if (rc) return rc;
+        if (s.bparts) {
+            h->bnorm_req = false;
+            h->bnorm_parts = nparts;
+        }
         // (norm, max) of r_k: reduced by the first restriction of the inner
         // cycle, which also writes the host mirror
         h->pend.count = nparts;
@@ -1497,6 +1508,10 @@ static int solve_ir(mg_ctx* h, const double* b, double* u, double tol, mg_stats*
     // u_k is the refinement step's output: in Y, or u_0 in X after step 0
     double* uk = k > 0 ? Y : X;
     if (uk != u) HIPCHK(hipMemcpyAsync(u, uk, fine, hipMemcpyDeviceToDevice, st));
+    if (st_out) {
+        rc = finish_bnorm(h, b, st);
+        if (rc) return rc;
+    }
     HIPCHK(hipEventRecord(h->ev1, st));
     HIPCHK(hipStreamSynchronize(st));
     rc = time_collect(h);

@@ -124,7 +124,7 @@ hipError_t launch_sumsq(const double* v, long count, double* partials, long part
 hipError_t launch_residual_norm(int d, int n, int batch, const double* u,
                                 const double* b, double inv_h2, double* psum,
                                 double* pmax, long partials_cap, hipStream_t st,
-                                int* nparts);
+                                int* nparts, double* bparts = nullptr);
 
 // One FP64 refinement step: unew = u + e_lo * scale_prev (if e_lo), the
 // residual r = b - A unew in FP64 and r_lo = s r stored in precision p,
@@ -143,6 +143,7 @@ struct IRStep {
     const double* maxprev = nullptr;  // device: max|r_{k-1}|
     double* psum = nullptr;
     double* pmax = nullptr;
+    double* bparts = nullptr;    // also partials of b^2 (||b|| of a solve)
     long partials_cap = 0;
 };
 hipError_t launch_ir_step(Prec p, const IRStep& s, hipStream_t st, int* nparts);

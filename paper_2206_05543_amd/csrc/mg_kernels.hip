@@ -3430,7 +3430,7 @@ k_ir3d(const double* __restrict__ u, double* __restrict__ unew, const S* __restr
        const double* __restrict__ b, S* __restrict__ rlo, int n, int tiles_x, int tiles_y,
        int zchunk, int nchunks, double inv_h2, double sigma0, int k,
        double* __restrict__ scales, const double* __restrict__ maxprev,
-       double* __restrict__ psum, double* __restrict__ pmax) {
+       double* __restrict__ psum, double* __restrict__ pmax, double* __restrict__ bparts) {
     constexpr int RX = TX + 2, RY = TY + 2, NR = RX * RY;
     constexpr int M = (NR + NT - 1) / NT;
     constexpr int RP = RX + 1, RSZ = RP + M * NT + RX + 1;
@@ -3498,7 +3498,7 @@ k_ir3d(const double* __restrict__ u, double* __restrict__ unew, const S* __restr
         for (int m = 0; m < M; ++m) dst[m] = raw[m] + escale * (double)rawe[m];
     };
     double um1[M], u0[M], up1[M];
-    double acc = 0.0, mx = 0.0;
+    double acc = 0.0, mx = 0.0, bacc = 0.0;  // bacc: b^2, kept only with bparts
     {
         // all prologue loads before the first wait
         issue_b(z0, 0);
@@ -3542,6 +3542,7 @@ k_ir3d(const double* __restrict__ u, double* __restrict__ unew, const S* __restr
                     bstore<NTS>(static_cast<S>(s_new * r), wr.r, orl + (inn[m] ? ge[m] : kOob));
                 }
                 acc += inn[m] ? r * r : 0.0;
+                bacc += inn[m] ? rb[k % RS][m] * rb[k % RS][m] : 0.0;
                 mx = fmax(mx, inn[m] ? fabs(r) : 0.0);
             }
         }
@@ -3563,6 +3564,11 @@ k_ir3d(const double* __restrict__ u, double* __restrict__ unew, const S* __restr
         psum[pi] = ts;
         pmax[pi] = tm;
     }
+    if (bparts) {  // sum b^2 as well (||b|| of a solve, in its first pass over b)
+        __syncthreads();
+        const double sb = block_sum<NT>(bacc, red);
+        if (t == 0) bparts[(long)blockIdx.y * gridDim.x + blockIdx.x] = sb;
+    }
 }
 
 template <typename S, int TX, int NT, int UN, bool NTS, bool RES>
@@ -3571,7 +3577,7 @@ k_ir2d(const double* __restrict__ u, double* __restrict__ unew, const S* __restr
        const double* __restrict__ b, S* __restrict__ rlo, int n, int tiles_x, int ychunk,
        int nchunks, double inv_h2, double sigma0, int k, double* __restrict__ scales,
        const double* __restrict__ maxprev, double* __restrict__ psum,
-       double* __restrict__ pmax) {
+       double* __restrict__ pmax, double* __restrict__ bparts) {
     constexpr int RX = TX + 2;
     constexpr int M = (RX + NT - 1) / NT;
     constexpr int RSZ = M * NT + 2;
@@ -3634,7 +3640,7 @@ k_ir2d(const double* __restrict__ u, double* __restrict__ unew, const S* __restr
         for (int m = 0; m < M; ++m) dst[m] = raw[m] + escale * (double)rawe[m];
     };
     double um1[M], u0[M], up1[M];
-    double acc = 0.0, mx = 0.0;
+    double acc = 0.0, mx = 0.0, bacc = 0.0;  // bacc: b^2, kept only with bparts
     {
         issue_b(y0, 0);
         double pu[3][M];
@@ -3676,6 +3682,7 @@ k_ir2d(const double* __restrict__ u, double* __restrict__ unew, const S* __restr
                     bstore<NTS>(static_cast<S>(s_new * r), wr.r, orl + (inn[m] ? ge[m] : kOob));
                 }
                 acc += inn[m] ? r * r : 0.0;
+                bacc += inn[m] ? rb[k % RS][m] * rb[k % RS][m] : 0.0;
                 mx = fmax(mx, inn[m] ? fabs(r) : 0.0);
             }
         }
@@ -3696,6 +3703,11 @@ k_ir2d(const double* __restrict__ u, double* __restrict__ unew, const S* __restr
         const long pi = (long)blockIdx.y * gridDim.x + blockIdx.x;
         psum[pi] = ts;
         pmax[pi] = tm;
+    }
+    if (bparts) {  // sum b^2 as well (||b|| of a solve, in its first pass over b)
+        __syncthreads();
+        const double sb = block_sum<NT>(bacc, red);
+        if (t == 0) bparts[(long)blockIdx.y * gridDim.x + blockIdx.x] = sb;
     }
 }
 
@@ -4012,7 +4024,7 @@ hipError_t ir_impl(const IRStep& s, hipStream_t st, int* nparts) {
         if ((long)grid.x * grid.y > s.partials_cap) return hipErrorInvalidValue;               \
         mg_launch((k_ir3d<S, TX, TY, NT, UN, NTS, RES>), grid, dim3(NT), 0, st, s.u, s.unew, \
                            e, s.b, rlo, n, tx, ty, zc, nch, s.inv_h2, s.sigma0, s.k, s.scales,  \
-                           s.maxprev, s.psum, s.pmax);                                          \
+                           s.maxprev, s.psum, s.pmax, s.bparts);                                \
     } while (0)
 #define IR2(TX, NT, UN, NTS, WANT, MINC)                                                        \
     do {                                                                                       \
@@ -4025,7 +4037,7 @@ hipError_t ir_impl(const IRStep& s, hipStream_t st, int* nparts) {
         if ((long)grid.x * grid.y > s.partials_cap) return hipErrorInvalidValue;               \
         mg_launch((k_ir2d<S, TX, NT, UN, NTS, RES>), grid, dim3(NT), 0, st, s.u, s.unew, e, \
                            s.b, rlo, n, tx, yc, nch, s.inv_h2, s.sigma0, s.k, s.scales,         \
-                           s.maxprev, s.psum, s.pmax);                                          \
+                           s.maxprev, s.psum, s.pmax, s.bparts);                                \
     } while (0)
     if (s.d == 3) {
         if (large) IR3(64, 16, 640, 6, true, 256, 32);
@@ -4431,7 +4443,7 @@ hipError_t launch_sumsq(const double* v, long count, double* partials, long part
 
 hipError_t launch_residual_norm(int d, int n, int batch, const double* u, const double* b,
                                 double inv_h2, double* psum, double* pmax, long partials_cap,
-                                hipStream_t st, int* nparts) {
+                                hipStream_t st, int* nparts, double* bparts) {
     // the marching refinement-step kernel without its stores
     IRStep s;
     s.d = d;
@@ -4442,6 +4454,7 @@ hipError_t launch_residual_norm(int d, int n, int batch, const double* u, const 
     s.inv_h2 = inv_h2;
     s.psum = psum;
     s.pmax = pmax;
+    s.bparts = bparts;
     s.partials_cap = partials_cap;
     return ir_impl<double, true>(s, st, nparts);
 }
