@@ -70,18 +70,18 @@ def sweep_bytes_per_pt(kind, d):
 # commands are in profiles/hbm_counters_fp64_sweeps.md.  Valid for the
 # kernels and launch shapes they were taken on; set to None when those change.
 PMC = {
-    ("poisson3d_n256", "smooth_restrict"): (142798, 148531),
-    ("poisson3d_n256", "smooth_correct"): (149147, 144367),
-    ("poisson2d_n4096", "smooth_restrict"): (143190, 167329),
-    ("poisson2d_n4096", "post_pre_restrict"): (159432, 303939),
+    ("poisson3d_n256", "smooth_restrict"): (142654, 146079),
+    ("poisson3d_n256", "smooth_correct"): (144893, 144825),
+    ("poisson2d_n4096", "smooth_restrict"): (143194, 165892),
+    ("poisson2d_n4096", "post_pre_restrict"): (159426, 301422),
     # the refinement solves' fine-level sweeps at 3D N=512, per storage
     # precision (profiles/hbm_counters_lowprec_sweeps.md)
-    ("poisson3d_n512_noisy:fp16_ir", "smooth_correct"): (292535, 343992),
-    ("poisson3d_n512_noisy:fp16_ir", "smooth_restrict"): (275681, 298520),
-    ("poisson3d_n512_noisy:fp16_ir", "zero_smooth_restrict"): (141477, 293086),
-    ("poisson3d_n512_noisy:fp32_ir", "smooth_correct"): (610356, 583930),
-    ("poisson3d_n512_noisy:fp32_ir", "smooth_restrict"): (772306, 655441),
-    ("poisson3d_n512_noisy:fp32_ir", "zero_smooth_restrict"): (282661, 586496),
+    ("poisson3d_n512_noisy:fp16_ir", "smooth_correct"): (290990, 333261),
+    ("poisson3d_n512_noisy:fp16_ir", "smooth_restrict"): (276448, 301305),
+    ("poisson3d_n512_noisy:fp16_ir", "zero_smooth_restrict"): (138316, 293086),
+    ("poisson3d_n512_noisy:fp32_ir", "smooth_correct"): (591048, 579097),
+    ("poisson3d_n512_noisy:fp32_ir", "smooth_restrict"): (767053, 655203),
+    ("poisson3d_n512_noisy:fp32_ir", "zero_smooth_restrict"): (276358, 586599),
 }
 PMC_COPY = {  # copy bytes, FETCH_SIZE KiB, WRITE_SIZE KiB of the same run
     "poisson3d_n256": (255 ** 3 * 8, 64782, 129542),
