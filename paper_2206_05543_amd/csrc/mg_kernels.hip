@@ -101,31 +101,24 @@ __device__ __forceinline__ void st_out(S* p, S v, bool nt) {
 
 // ---------------------------------------------------------------------------
 // Raw buffer access.  The marching kernels read and write through buffer
-// resources that cover one plane (3D) or one row (2D) of one field: a plane
-// outside the grid gets num_records = 0 and a lane outside the grid uses the
-// byte offset kOob, so both read as zero and their stores are dropped by the
-// hardware range check.  This replaces per-lane index clamps, 64-bit
-// address arithmetic and exec-mask branches by one 32-bit offset per point.
+// resources, one per field and workgroup, that cover the window of lines
+// [first, first + count) (planes in 3D, rows in 2D) the workgroup's march
+// touches.  A line is addressed by a 32-bit offset (one scalar multiply); a
+// line outside the caller's range gets the offset kOobLine and a lane
+// outside the grid the offset kOob.  kOobLine added to an in-line offset
+// (below one line's bytes) or to kOob, and kOob added to an in-range line's
+// offset, stay at or above num_records and below 2^32, so all of these read
+// as zero and their stores are dropped by the hardware range check.  This
+// replaces per-lane index clamps, 64-bit address arithmetic and exec-mask
+// branches by one 32-bit offset per point, and a resource per line and
+// field (a 64-bit address, two selects and the descriptor words) by one per
+// field.  The host keeps count * line bytes <= kWinMax.
 // ---------------------------------------------------------------------------
 using rsrc_t = __amdgpu_buffer_rsrc_t;
 constexpr unsigned kOob = 0x80000000u;
 constexpr int kRsrcWord3 = 0x00020000;  // raw (untyped) buffer, gfx9-family layout
 typedef int int2v __attribute__((ext_vector_type(2)));
 
-template <typename S>
-__device__ __forceinline__ rsrc_t line_rsrc(const S* base, long first, long len, bool in) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<S*>(in ? base + first : base), 0,
-                                             in ? (int)(len * (long)sizeof(S)) : 0, kRsrcWord3);
-}
-// A window of lines [first, first + count) of one field under a single
-// buffer resource, built once per workgroup: a line is then addressed by a
-// 32-bit offset (one scalar multiply) instead of a resource of its own (a
-// 64-bit address, two selects and the descriptor words per line and field).
-// A line outside the caller's range gets offset kOobLine: added to an
-// in-line offset (below one line's bytes) or to kOob it stays at or above
-// num_records and below 2^32, so it reads zero and drops stores like an
-// empty line; kOob added to an in-range line's offset does the same.  The
-// host keeps count * line bytes <= kWinMax.
 constexpr unsigned kOobLine = 0x7FF00000u;
 constexpr long kWinMax = kOobLine;
 template <typename S>
@@ -271,8 +264,8 @@ __device__ void finalize_norm(const double* ps, const double* pm, int count, dou
 // trilinear correction costs one coarse read per coarse node.
 //
 // Every lane executes the same instruction stream: global accesses go
-// through plane buffer resources (off-grid reads are zero, off-tile stores
-// are dropped), LDS writes of lanes past the tile land in a scratch area,
+// through the per-field plane windows (off-grid reads are zero, off-tile
+// stores are dropped), LDS writes of lanes past the tile land in a scratch area,
 // and the residual outside the grid is cleared with a select.
 //
 // WIDE: the 19-/27-point SPAI stencils (K_c + c2 x 12 edge neighbours + c3 x
@@ -641,7 +634,7 @@ k_smooth3d(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ out
 // strip plus a ring of 1; output lags by two rows because the 9-point
 // stencil needs the residual of rows p-1..p+1 at x-1..x+1 from LDS (4 row
 // slots).  PRO stages the coarse row under each even fine row in LDS.  As in
-// 3D, every lane runs the same instruction stream (row buffer resources,
+// 3D, every lane runs the same instruction stream (per-field row windows,
 // LDS scratch slots for lanes past the strip, selects for off-grid points).
 // ---------------------------------------------------------------------------
 template <typename S, typename C, int TX, int NT, int PD, int UN, bool ZG, bool NORM, bool PRO,
@@ -2810,8 +2803,16 @@ k_adj_sweep3d(const double* __restrict__ ub, const double* __restrict__ r,
         }
     }
 
-    auto ld_plane = [&](const double* f, int p, unsigned off) {
-        return bload<double>(line_rsrc(f, (long)p * plane, plane, p >= 0 && p < n), off);
+    // one buffer resource per field over the planes this march touches:
+    // ubar from z0 - 2 to z1 + 3, the other fields inside that range; the
+    // coarse planes up to z1 / 2
+    const int wf0 = max(0, z0 - 2), wfl = min(n - 1, z1 + 3), wfc = wfl - wf0 + 1;
+    const Win<double> wub(ub, plane, wf0, wfc), wrr(MODE == 0 ? r : ub, plane, wf0, wfc);
+    const Win<double> wbb(bb, plane, wf0, wfc), wun(ub_new, plane, wf0, wfc);
+    const int wc0 = max(0, ((z0 - 1) >> 1) - 1), wcl = min(nc - 1, z1 >> 1);
+    const Win<double> wec(MODE == 1 ? ec : ub, cplane, wc0, wcl - wc0 + 1);
+    auto ld_plane = [&](const Win<double>& w, int p, unsigned off) {
+        return bload<double>(w.r, w.at(p, p >= 0 && p <= wfl) + off);
     };
     // the in-plane part of a w node's interpolation: the four coarse values
     // of coarse plane k around it (a node on a coarse line counts its value
@@ -2820,9 +2821,9 @@ k_adj_sweep3d(const double* __restrict__ ub, const double* __restrict__ r,
     // odd (counted twice), so each coarse plane is gathered once, at the even
     // step that first needs it, and serves three fine planes.
     auto bilin = [&](int k, int m) -> double {
-        const rsrc_t rk = line_rsrc(ec, (long)k * cplane, cplane, k >= 0 && k < nc);
-        return bload<double>(rk, cof[m][0]) + bload<double>(rk, cof[m][1]) +
-               bload<double>(rk, cof[m][2]) + bload<double>(rk, cof[m][3]);
+        const unsigned o = wec.at(k, k >= 0 && k <= wcl);
+        return bload<double>(wec.r, o + cof[m][0]) + bload<double>(wec.r, o + cof[m][1]) +
+               bload<double>(wec.r, o + cof[m][2]) + bload<double>(wec.r, o + cof[m][3]);
     };
     // w of plane s at step s (s = z0-1 .. z1), outputs of plane s-1
     const int s0 = z0 - 1, s1 = z1;
@@ -2832,10 +2833,10 @@ k_adj_sweep3d(const double* __restrict__ ub, const double* __restrict__ r,
         for (int q = 0; q < 3; ++q) {
             const int p = s0 - 1 + q;
 #pragma unroll
-            for (int m = 0; m < MU; ++m) uL[p & 3][uli[m]] = ld_plane(ub, p, ugb[m]);
+            for (int m = 0; m < MU; ++m) uL[p & 3][uli[m]] = ld_plane(wub, p, ugb[m]);
         }
 #pragma unroll
-        for (int m = 0; m < MU; ++m) pu[m] = ld_plane(ub, s0 + 2, ugb[m]);
+        for (int m = 0; m < MU; ++m) pu[m] = ld_plane(wub, s0 + 2, ugb[m]);
     }
     // per-step loads, one step ahead: r (MODE 0) of plane s, or (MODE 1) at
     // even s the in-plane interpolation of coarse plane s/2; ubar (MODE 1)
@@ -2846,10 +2847,10 @@ k_adj_sweep3d(const double* __restrict__ ub, const double* __restrict__ r,
         const bool pout = p >= z0 && p < z1, sown = s >= z0 && s < z1;
 #pragma unroll
         for (int m = 0; m < MW; ++m) {
-            nr[m] = MODE == 0 ? ld_plane(r, s, sown && own[m] ? wgb[m] : kOob) : 0.0;
+            nr[m] = MODE == 0 ? ld_plane(wrr, s, sown && own[m] ? wgb[m] : kOob) : 0.0;
             if (MODE == 1 && (s & 1) == 0) nw[m] = bilin(s >> 1, m);
-            nu[m] = MODE == 1 ? ld_plane(ub, p, pout && own[m] ? wgb[m] : kOob) : 0.0;
-            nb[m] = ld_plane(bb, p, pout && own[m] ? wgb[m] : kOob);
+            nu[m] = MODE == 1 ? ld_plane(wub, p, pout && own[m] ? wgb[m] : kOob) : 0.0;
+            nb[m] = ld_plane(wbb, p, pout && own[m] ? wgb[m] : kOob);
         }
     };
     // MODE 1: in-plane interpolations of the coarse planes below and above
@@ -2892,7 +2893,7 @@ k_adj_sweep3d(const double* __restrict__ ub, const double* __restrict__ r,
 #pragma unroll
             for (int m = 0; m < MU; ++m) uL[(s + 2) & 3][uli[m]] = pu[m];
 #pragma unroll
-            for (int m = 0; m < MU; ++m) pu[m] = ld_plane(ub, s + 3, ugb[m]);
+            for (int m = 0; m < MU; ++m) pu[m] = ld_plane(wub, s + 3, ugb[m]);
         }
         const int p = s - 1;
         const bool pout = p >= z0 && p < z1;
@@ -2933,16 +2934,15 @@ k_adj_sweep3d(const double* __restrict__ ub, const double* __restrict__ r,
         // outputs of plane s - 1
         if (pout) {
             const double* W1 = wL[(s + 1) & 1];  // plane s - 1
-            const rsrc_t ro = line_rsrc(ub_new, (long)p * plane, plane, true);
-            const rsrc_t rb = line_rsrc(bb, (long)p * plane, plane, true);
+            const unsigned oo = wun.at(p, true);  // the same offset in wbb
 #pragma unroll
             for (int m = 0; m < MW; ++m) {
                 const int q = wq[m];
                 const double lw = 6.0 * wm1[m] - W1[q - 1] - W1[q + 1] - W1[q - RX] - W1[q + RX] -
                                   wm2[m] - w0[m];
                 const double u = MODE == 0 ? uL[(s + 3) & 3][wuq[m]] : uo[m];
-                bstore<false>(u - sA * lw, ro, own[m] ? wgb[m] : kOob);
-                bstore<false>(bo[m] + wm1[m], rb, own[m] ? wgb[m] : kOob);
+                bstore<false>(u - sA * lw, wun.r, oo + (own[m] ? wgb[m] : kOob));
+                bstore<false>(bo[m] + wm1[m], wbb.r, oo + (own[m] ? wgb[m] : kOob));
             }
         }
 #pragma unroll
@@ -3036,15 +3036,22 @@ k_adj_sweep2d(const double* __restrict__ ub, const double* __restrict__ r,
             cof[m][1] = (wval[m] && xb >= 0 && xb < nc) ? (unsigned)(xb * 8) : kOob;
         }
     }
-    auto ld_row = [&](const double* f, int p, unsigned off) {
-        return bload<double>(line_rsrc(f, (long)p * n, n, p >= 0 && p < n), off);
+    // one buffer resource per field over the rows this march touches (as
+    // in 3D)
+    const int wf0 = max(0, z0 - 2), wfl = min(n - 1, z1 + 3), wfc = wfl - wf0 + 1;
+    const Win<double> wub(ub, n, wf0, wfc), wrr(MODE == 0 ? r : ub, n, wf0, wfc);
+    const Win<double> wbb(bb, n, wf0, wfc), wun(ub_new, n, wf0, wfc);
+    const int wc0 = max(0, ((z0 - 1) >> 1) - 1), wcl = min(nc - 1, z1 >> 1);
+    const Win<double> wec(MODE == 1 ? ec : ub, nc, wc0, wcl - wc0 + 1);
+    auto ld_row = [&](const Win<double>& w, int p, unsigned off) {
+        return bload<double>(w.r, w.at(p, p >= 0 && p <= wfl) + off);
     };
     // the x part of a w node's interpolation: the two coarse values of
     // coarse row k around it; each coarse row is gathered once, at the even
     // step that first needs it, and serves three fine rows (as in 3D)
     auto lin = [&](int k, int m) -> double {
-        const rsrc_t rk = line_rsrc(ec, (long)k * nc, nc, k >= 0 && k < nc);
-        return bload<double>(rk, cof[m][0]) + bload<double>(rk, cof[m][1]);
+        const unsigned o = wec.at(k, k >= 0 && k <= wcl);
+        return bload<double>(wec.r, o + cof[m][0]) + bload<double>(wec.r, o + cof[m][1]);
     };
     const int s0 = z0 - 1, s1 = z1;
     double pu[MU];
@@ -3053,10 +3060,10 @@ k_adj_sweep2d(const double* __restrict__ ub, const double* __restrict__ r,
         for (int q = 0; q < 3; ++q) {
             const int p = s0 - 1 + q;
 #pragma unroll
-            for (int m = 0; m < MU; ++m) uL[p & 3][uli[m]] = ld_row(ub, p, ugb[m]);
+            for (int m = 0; m < MU; ++m) uL[p & 3][uli[m]] = ld_row(wub, p, ugb[m]);
         }
 #pragma unroll
-        for (int m = 0; m < MU; ++m) pu[m] = ld_row(ub, s0 + 2, ugb[m]);
+        for (int m = 0; m < MU; ++m) pu[m] = ld_row(wub, s0 + 2, ugb[m]);
     }
     double nr[MW], nw[MW], nu[MW], nb[MW];
     auto issue = [&](int s) {
@@ -3064,10 +3071,10 @@ k_adj_sweep2d(const double* __restrict__ ub, const double* __restrict__ r,
         const bool pout = p >= z0 && p < z1, sown = s >= z0 && s < z1;
 #pragma unroll
         for (int m = 0; m < MW; ++m) {
-            nr[m] = MODE == 0 ? ld_row(r, s, sown && own[m] ? wgb[m] : kOob) : 0.0;
+            nr[m] = MODE == 0 ? ld_row(wrr, s, sown && own[m] ? wgb[m] : kOob) : 0.0;
             if (MODE == 1 && (s & 1) == 0) nw[m] = lin(s >> 1, m);
-            nu[m] = MODE == 1 ? ld_row(ub, p, pout && own[m] ? wgb[m] : kOob) : 0.0;
-            nb[m] = ld_row(bb, p, pout && own[m] ? wgb[m] : kOob);
+            nu[m] = MODE == 1 ? ld_row(wub, p, pout && own[m] ? wgb[m] : kOob) : 0.0;
+            nb[m] = ld_row(wbb, p, pout && own[m] ? wgb[m] : kOob);
         }
     };
     double bpre[MW], bcur[MW];
@@ -3107,7 +3114,7 @@ k_adj_sweep2d(const double* __restrict__ ub, const double* __restrict__ r,
 #pragma unroll
             for (int m = 0; m < MU; ++m) uL[(s + 2) & 3][uli[m]] = pu[m];
 #pragma unroll
-            for (int m = 0; m < MU; ++m) pu[m] = ld_row(ub, s + 3, ugb[m]);
+            for (int m = 0; m < MU; ++m) pu[m] = ld_row(wub, s + 3, ugb[m]);
         }
         const int p = s - 1;
         const bool pout = p >= z0 && p < z1;
@@ -3138,15 +3145,14 @@ k_adj_sweep2d(const double* __restrict__ ub, const double* __restrict__ r,
         }
         if (pout) {
             const double* W1 = wL[(s + 1) & 1];  // row s - 1
-            const rsrc_t ro = line_rsrc(ub_new, (long)p * n, n, true);
-            const rsrc_t rb = line_rsrc(bb, (long)p * n, n, true);
+            const unsigned oo = wun.at(p, true);  // the same offset in wbb
 #pragma unroll
             for (int m = 0; m < MW; ++m) {
                 const int q = wq[m];
                 const double lw = 4.0 * wm1[m] - W1[q - 1] - W1[q + 1] - wm2[m] - w0[m];
                 const double u = MODE == 0 ? uL[(s + 3) & 3][wuq[m]] : uo[m];
-                bstore<false>(u - sA * lw, ro, own[m] ? wgb[m] : kOob);
-                bstore<false>(bo[m] + wm1[m], rb, own[m] ? wgb[m] : kOob);
+                bstore<false>(u - sA * lw, wun.r, oo + (own[m] ? wgb[m] : kOob));
+                bstore<false>(bo[m] + wm1[m], wbb.r, oo + (own[m] ? wgb[m] : kOob));
             }
         }
 #pragma unroll
@@ -3526,7 +3532,7 @@ k_sumsq(const double* __restrict__ v, long count, long per, double* __restrict__
 // FP64 refinement step, 3D: unew = u + escale * e (on the fly, halo included),
 // r = b - A unew, r_lo = s * r (stored in S), partials of r^2 and max |r|.
 // Without a correction (the first step) unew equals u and is not stored.
-// Same scheme as the smoothers: plane buffer resources (e reads as zero when
+// Same scheme as the smoothers: per-field plane windows (e reads as zero when
 // there is no correction yet), an unrolled marching loop over planes.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double ir_scale(const double* maxprev) {
@@ -4527,12 +4533,13 @@ hipError_t launch_adj_sweep(int d, int n, int batch, int mode, const double* uba
         // 32 x 16 tiles on 512 threads (ubar on 36 x 20 per plane in LDS)
         tx = cdiv(n, 32);
         ty = cdiv(n, 16);
-        zc = pick_chunk(n, tx * ty, want, 8);
+        zc = win_chunk(pick_chunk(n, tx * ty, want, 8), 8L * n * n, 1, 6);
     } else {
         // 256-wide strips on 320 threads
         tx = cdiv(n, 256);
-        zc = pick_chunk(n, tx, want, 8);
+        zc = win_chunk(pick_chunk(n, tx, want, 8), 8L * n, 1, 6);
     }
+    if (zc < 1) return hipErrorInvalidValue;
     nch = cdiv(n, zc);
     grid = dim3(tx * ty * nch, batch);
     if (nparts) *nparts = grid.x * grid.y;
