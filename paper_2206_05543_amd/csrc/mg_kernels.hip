@@ -3867,7 +3867,8 @@ inline int win_chunk(int c, long line_bytes, int per, int extra) {
 //                rows need long row segments)
 //                n >= 100: 64x16 / 640, 256 marches;  else 32x16 / 320, 256
 //   smoother 2D  n >= 3000: 1024-wide strips / 576 threads, unrolled 4, 256
-//                n >= 700: 512 / 320, 512 marches;  else 128 / 192, 512
+//                n >= 1500: 512 / 320, 512 marches;  n >= 700: 256 / 320, 512;
+//                else 128 / 192, 512
 //   restriction  3D n >= 200: 32x8 coarse columns / 576, unrolled 6, 256
 //                (FP32/FP16: 64x8 / 768, 512);
 //                else 32x4 / 320, 512;  2D n >= 3000: 512 / 576, unrolled 6,
@@ -4029,7 +4030,11 @@ hipError_t smooth_impl(bool zg, bool norm, const Sweep& s, hipStream_t st, int* 
         return launch_smooth3d<S, C, 32, 16, 320, 2, false>(zg, norm, s, 256, 2, st, nparts);
     }
     if (n >= 3000) return launch_smooth2d<S, C, 1024, 576, 4, true>(zg, norm, s, 256, 32, st, nparts);
-    if (n >= 700) return launch_smooth2d<S, C, 512, 320, 2, false>(zg, norm, s, 512, 2, st, nparts);
+    if (n >= 1500) return launch_smooth2d<S, C, 512, 320, 2, false>(zg, norm, s, 512, 2, st, nparts);
+    // n = 1023: 256-wide strips (the post-smoother with the correction 10.5
+    // against 11.4 us on 512-wide ones; at n = 2047 512 stays, 24.2 against
+    // 24.7 us)
+    if (n >= 700) return launch_smooth2d<S, C, 256, 320, 2, false>(zg, norm, s, 512, 2, st, nparts);
     return launch_smooth2d<S, C, 128, 192, 2, false>(zg, norm, s, 512, 2, st, nparts);
 }
 
