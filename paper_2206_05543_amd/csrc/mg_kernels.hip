@@ -3865,7 +3865,7 @@ inline int win_chunk(int c, long line_bytes, int per, int extra) {
 //   smoother 3D  n >= 200: 64x16 tiles / 640 threads, unrolled 6, 256 marches
 //                (FP32/FP16 storage: 256x8 / 1024, 1024 marches: 4- and 2-byte
 //                rows need long row segments)
-//                n >= 100: 64x16 / 640, 256 marches;  else 32x16 / 320, 256
+//                n >= 100: 32x16 / 320, 512 marches;  else 32x16 / 320, 256
 //   smoother 2D  n >= 3000: 1024-wide strips / 576 threads, unrolled 4, 256
 //                n >= 1500: 512 / 320, 512 marches;  n >= 700: 256 / 320, 512;
 //                else 128 / 192, 512
@@ -4007,7 +4007,10 @@ hipError_t smooth_impl(bool zg, bool norm, const Sweep& s, hipStream_t st, int* 
                                                                      nparts);
         }
         if (n >= 200) return launch_smooth3d<S, C, 64, 16, 640, 6, true>(zg, norm, s, 256, 32, st, nparts);
-        if (n >= 100) return launch_smooth3d<S, C, 64, 16, 640, 2, false>(zg, norm, s, 256, 2, st, nparts);
+        // n = 127 (the post-smoother with the correction): 32x16 tiles and
+        // 512 marches 16.4-16.7 us, 64x16 with 256 marches 17.3-18.1, with
+        // 512 marches 22.2, 32x32 17.3-17.6
+        if (n >= 100) return launch_smooth3d<S, C, 32, 16, 320, 2, false>(zg, norm, s, 512, 2, st, nparts);
         if (n < 50 && pro && !norm && !s.rout && !s.u_f32 && s.c[2] == 0.0 && s.c[3] == 0.0) {
             // the post-smoother with the correction as a tile kernel below 50
             // nodes per side (FP64, 3D N=256: n = 31 4.7 against 6.3 us for
